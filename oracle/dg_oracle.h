@@ -1,0 +1,60 @@
+/*
+ * dg_oracle.h -- sequential CPU oracle for the snapshot-query dynamic graph.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg do.  It shares no source with the HIP path.
+ *
+ * What it computes (plain definitions, one operation at a time):
+ *   - the graph ADT operations named in the paper's preamble
+ *     (PutV / RemoveV / GetV / PutE / RemoveE / GetE), applied in index
+ *     order -- the linearization order of a batch;
+ *   - BFS hop distances (FIFO queue), SSSP distances (binary-heap Dijkstra)
+ *     and Brandes betweenness (int64 path counts, FP64 dependencies), the
+ *     queries named BFS / SSSP / BC in the same preamble, on the current
+ *     state.
+ *
+ * Error codes are the integer values of the C boundary's call status.
+ */
+#ifndef DG_ORACLE_H
+#define DG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { uint32_t type, u, v; int32_t w; } orc_op;   /* 16 bytes */
+
+enum { ORC_ADDV = 0, ORC_REMV = 1, ORC_HASV = 2, ORC_ADDE = 3, ORC_REME = 4, ORC_HASE = 5 };
+enum {
+  ORC_OK = 0, ORC_E_INVALID_ARG = -1, ORC_E_OOM = -2, ORC_E_VERTEX_RANGE = -3,
+  ORC_E_WEIGHT_RANGE = -4, ORC_E_SOURCE_ABSENT = -6, ORC_E_OVERFLOW = -7
+};
+
+typedef struct orc_graph orc_graph;
+
+orc_graph* orc_create(uint32_t n_vertices, int undirected, int32_t w_max);
+void       orc_destroy(orc_graph* g);
+uint32_t   orc_epoch(const orc_graph* g);
+/* Apply ops[0..n) in order; results[i] = 0 false / 1 true / 2 endpoint absent.
+ * The whole batch is validated first; on error nothing changes. */
+int        orc_apply(orc_graph* g, const orc_op* ops, uint64_t n, uint8_t* results);
+int        orc_bfs(const orc_graph* g, uint32_t s, int32_t* dist);
+int        orc_sssp(const orc_graph* g, uint32_t s, int32_t* dist);
+int        orc_bc(const orc_graph* g, const uint32_t* S, uint32_t k, double* bc);
+void       orc_counts(const orc_graph* g, uint64_t* n_live_vertices, uint64_t* n_arcs);
+int        orc_alive(const orc_graph* g, uint32_t v);
+/* 1 and *w set if edge key (u, v) is present, else 0. */
+int        orc_edge(const orc_graph* g, uint32_t u, uint32_t v, int32_t* w);
+/* Writes every stored edge key (undirected: lo < = hi); returns count.
+ * Arrays must hold orc_counts' key count (n_arcs, or keys in undirected). */
+uint64_t   orc_n_keys(const orc_graph* g);
+uint64_t   orc_export(const orc_graph* g, uint32_t* u, uint32_t* v, int32_t* w);
+/* Out-degree (visible arcs) of v. */
+uint32_t   orc_out_degree(const orc_graph* g, uint32_t v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
