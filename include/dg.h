@@ -1,0 +1,204 @@
+/*
+ * dg.h -- C boundary of libdg, a snapshot-query dynamic graph for MI355X.
+ *
+ * The graph is a shared object in the sense of the paper's concurrent-graph
+ * vocabulary (preamble: linearizable shared graph with vertex-list /
+ * edge-list, non-blocking).  Its operations are the ADT calls the paper names
+ * PutV / RemoveV / GetV / PutE / RemoveE / GetE, and the snapshot queries it
+ * names BFS, SSSP and BC.  Updates arrive in batches; the ops of a batch are
+ * linearized in index order, and each non-empty batch publishes one new
+ * snapshot epoch.  A query reads exactly the graph as of one epoch.
+ *
+ * Conventions for every call:
+ *   - Return value: DG_OK (0) or a negative dg_status.  No C++ exception
+ *     crosses this boundary.  On error, dg_last_error() describes it.
+ *   - "device" pointers are HIP device memory of the GPU the graph was
+ *     created on; "host or device" pointers are classified with
+ *     hipPointerGetAttributes.  The caller owns every buffer it passes in;
+ *     the library owns the graph store and all internal scratch.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device outputs
+ *     are written asynchronously on that stream; host outputs are complete
+ *     when the call returns.
+ *   - A dg_graph is driven by one caller thread at a time.  Concurrency
+ *     between updates and queries goes through dg_query_batch (many queries
+ *     in one launch) and the dg_server_* serving loop.
+ */
+#ifndef DG_H
+#define DG_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_graph dg_graph;
+typedef uint32_t dg_epoch;      /* 0 = empty graph; epoch k = after k batches */
+typedef int32_t dg_status;
+
+#define DG_EPOCH_LATEST 0xFFFFFFFFu
+
+enum {
+  DG_OK = 0,
+  DG_E_INVALID_ARG = -1,
+  DG_E_OUT_OF_MEMORY = -2,
+  DG_E_VERTEX_RANGE = -3,   /* an id >= v_capacity in the batch: whole batch rejected */
+  DG_E_WEIGHT_RANGE = -4,   /* an AddEdge weight outside [1, w_max]: batch rejected */
+  DG_E_EPOCH_RETIRED = -5,  /* epoch older than the retained window, or not yet published */
+  DG_E_SOURCE_ABSENT = -6,  /* a query source is not a live vertex at that epoch */
+  DG_E_OVERFLOW = -7,       /* a BC shortest-path count exceeded int64 */
+  DG_E_HIP = -8,            /* a HIP runtime error; text in dg_last_error */
+  DG_E_BUSY = -9,           /* serving loop: no admission capacity right now */
+  DG_E_UNIMPLEMENTED = -10
+};
+
+/* Operation record, 16 bytes: the six ADT calls.  For vertex ops only `u` is
+ * read (the vertex); `w` is read only by AddEdge. */
+typedef struct { uint32_t type, u, v; int32_t w; } dg_op;
+enum { DG_ADD_VERTEX = 0, DG_REMOVE_VERTEX = 1, DG_CONTAINS_VERTEX = 2,
+       DG_ADD_EDGE = 3, DG_REMOVE_EDGE = 4, DG_CONTAINS_EDGE = 5 };
+/* Per-op result byte: 0 = false/absent/no change, 1 = true/done,
+ * 2 = an endpoint of an edge op is not a live vertex at that point. */
+
+#define DG_UNDIRECTED 1u
+
+typedef struct {
+  uint32_t v_capacity;         /* vertex ids are [0, v_capacity) */
+  uint32_t flags;              /* DG_UNDIRECTED: key of (u,v) is {min,max}, both arcs stored */
+  int32_t w_max;               /* AddEdge weights in [1, w_max]; (v_capacity-1)*w_max < 2^31 */
+  uint32_t max_resident_epochs;/* epochs kept queryable besides pinned ones (>= 1) */
+  uint64_t edge_capacity;      /* expected peak number of stored arcs (sizing hint) */
+  uint64_t mem_budget;         /* bytes of device memory the store may use; 0 = no limit */
+} dg_config;
+
+/* Create an empty graph (epoch 0) on the current HIP device. */
+dg_status dg_create(const dg_config* cfg, dg_graph** out);
+dg_status dg_destroy(dg_graph* g);
+/* Text of the last error on g (or of the last failed dg_create if g is NULL). */
+const char* dg_last_error(const dg_graph* g);
+dg_epoch dg_latest_epoch(const dg_graph* g);
+
+/*
+ * Apply ops[0..n) as one batch (ADT ops named in the paper's preamble,
+ * linearized in index order; a Contains is answered at its position).
+ * ops: host or device array of n dg_op.  results: host or device array of n
+ * bytes, or NULL.  On success *new_epoch = the published epoch (unchanged
+ * for n == 0).  The whole batch is validated before any op applies: on
+ * DG_E_VERTEX_RANGE / DG_E_WEIGHT_RANGE / DG_E_INVALID_ARG (unknown type)
+ * nothing changes.  The call returns after the epoch is published.
+ */
+dg_status dg_apply_batch(dg_graph* g, const dg_op* ops, uint64_t n, uint8_t* results,
+                         dg_epoch* new_epoch, void* stream);
+
+/* Single-op forms: a batch of one op.  *res receives the result byte. */
+dg_status dg_add_vertex(dg_graph* g, uint32_t v, uint8_t* res, dg_epoch* ep);
+dg_status dg_remove_vertex(dg_graph* g, uint32_t v, uint8_t* res, dg_epoch* ep);
+dg_status dg_contains_vertex(dg_graph* g, uint32_t v, uint8_t* res, dg_epoch* ep);
+dg_status dg_add_edge(dg_graph* g, uint32_t u, uint32_t v, int32_t w, uint8_t* res, dg_epoch* ep);
+dg_status dg_remove_edge(dg_graph* g, uint32_t u, uint32_t v, uint8_t* res, dg_epoch* ep);
+dg_status dg_contains_edge(dg_graph* g, uint32_t u, uint32_t v, uint8_t* res, dg_epoch* ep);
+
+/*
+ * Snapshots.  The last max_resident_epochs epochs are queryable; acquiring
+ * an epoch pins it (reference count) so it stays queryable until released.
+ * want = DG_EPOCH_LATEST pins the latest epoch.  Old versions are reclaimed
+ * only below the oldest queryable epoch.
+ */
+dg_status dg_snapshot_acquire(dg_graph* g, dg_epoch want, dg_epoch* pinned);
+dg_status dg_snapshot_release(dg_graph* g, dg_epoch e);
+/* Reclaim versions invisible to every queryable epoch and repack the slabs
+ * (stream-ordered; waits for work queued on `stream`). */
+dg_status dg_compact(dg_graph* g, void* stream);
+
+/*
+ * Snapshot queries on epoch e (DG_EPOCH_LATEST allowed).
+ * dist: device array of v_capacity int32.
+ *   dg_bfs:  dist[v] = fewest arcs on a path src -> v visible at e, -1 if none.
+ *   dg_sssp: dist[v] = least total weight of such a path, -1 if none.
+ * bc: device array of v_capacity double; srcs: host array of k distinct live
+ *   vertices.  bc[v] = sum over s in srcs (in order), s != v, of the Brandes
+ *   dependency delta_s(v) on the unweighted snapshot (int64 path counts,
+ *   FP64 dependencies; no normalisation).  DG_E_OVERFLOW if a path count
+ *   exceeds int64.
+ * The call validates the epoch and sources on the host, enqueues the work on
+ * `stream` and returns; dg_bc returns after the overflow flag is read.
+ */
+dg_status dg_bfs(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* stream);
+dg_status dg_sssp(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* stream);
+dg_status dg_bc(dg_graph* g, dg_epoch e, const uint32_t* srcs, uint32_t k, double* bc, void* stream);
+
+/*
+ * Many queries in one persistent launch.  Each query names its kind, epoch
+ * and source(s) and a caller-owned device output (int32[v_capacity] for BFS
+ * and SSSP, double[v_capacity] for BC).  per_query (host, nq entries)
+ * receives each query's status.  Outputs equal the single-query calls.
+ */
+enum { DG_Q_BFS = 0, DG_Q_SSSP = 1, DG_Q_BC = 2 };
+typedef struct {
+  uint32_t kind;
+  uint32_t src;            /* BFS / SSSP source */
+  dg_epoch epoch;
+  uint32_t k;              /* BC: number of sources */
+  const uint32_t* srcs;    /* BC: host array of k sources */
+  void* out;               /* device output */
+} dg_query;
+dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query,
+                         void* stream);
+
+/* Frontier-tile tuning.  dg_autotune times candidate shapes on the latest
+ * epoch and keeps the fastest; dg_get_tuning reports the shape in use. */
+typedef struct {
+  uint32_t tile_buckets;   /* buckets per frontier work item (1..64, power of 2) */
+  uint32_t sssp_delta;     /* delta-stepping bucket width */
+  uint32_t alpha, beta;    /* direction-switch thresholds of the BFS */
+  uint32_t batch_groups;   /* workgroups per query in the persistent launch */
+} dg_tuning;
+dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t);
+dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t);
+dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, void* stream);
+
+/* Counts on epoch e: live vertices and visible arcs. */
+dg_status dg_stats(dg_graph* g, dg_epoch e, uint64_t* n_vertices, uint64_t* n_arcs, void* stream);
+/* Visible out-degree of every vertex at epoch e (device uint32[v_capacity]). */
+dg_status dg_out_degrees(dg_graph* g, dg_epoch e, uint32_t* deg, void* stream);
+
+/*
+ * Serving loop: a host thread admits requests in arrival order, runs update
+ * batches on an update stream (each publishes the next epoch) and queries
+ * concurrently on a query stream, binding each query to the latest epoch
+ * published when it is admitted (its linearization point).  Admission
+ * reserves device memory for a request's outputs and scratch from
+ * mem_budget; requests wait while the budget is exhausted.
+ * dg_server_submit_* copy their inputs and return a ticket immediately;
+ * dg_server_poll reports whether a ticket finished, its status, bound epoch
+ * and latency; dg_server_take copies a finished query's output to a host
+ * buffer (int32[v] or double[v]) or an update's result bytes.
+ */
+typedef struct dg_server dg_server;
+typedef struct {
+  uint64_t mem_budget;     /* bytes for in-flight query outputs and scratch */
+  uint32_t max_inflight;   /* queries running at once */
+  uint32_t max_batch;      /* queries fused into one launch */
+} dg_server_config;
+typedef struct {
+  uint64_t completed, updates, queries, ops_applied;
+  double p50_ms, p99_ms;             /* all requests, arrival -> completion */
+  double p50_query_ms, p99_query_ms, p50_update_ms, p99_update_ms;
+  double wall_s;                     /* first arrival -> last completion */
+  uint64_t edges_traversed;          /* sum of TEPS numerators of finished queries */
+} dg_server_stats;
+dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** out);
+dg_status dg_server_stop(dg_server* s);
+dg_status dg_server_submit_update(dg_server* s, const dg_op* ops, uint64_t n, uint64_t* ticket);
+dg_status dg_server_submit_query(dg_server* s, uint32_t kind, const uint32_t* srcs, uint32_t k,
+                                 uint64_t* ticket);
+/* done = 1 when finished; status/epoch/latency_ms valid then. */
+dg_status dg_server_poll(dg_server* s, uint64_t ticket, int* done, dg_status* status,
+                         dg_epoch* epoch, double* latency_ms);
+dg_status dg_server_take(dg_server* s, uint64_t ticket, void* host_out, uint64_t bytes);
+dg_status dg_server_drain(dg_server* s);
+dg_status dg_server_get_stats(dg_server* s, dg_server_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

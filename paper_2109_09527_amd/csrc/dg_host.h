@@ -1,0 +1,130 @@
+// Host-side state of a graph and the entry points of each kernel family.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dg.h"
+#include "dg_internal.h"
+
+namespace dg {
+
+// ------------------------------------------------------------ primitives
+uint64_t scan_scratch_words(uint64_t n);
+void exclusive_scan_u32(uint32_t* data, uint64_t n, uint32_t* scratch, hipStream_t s);
+uint64_t sort_scratch_words(uint32_t n);
+bool radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint32_t n, int bits,
+                      uint32_t* scratch, hipStream_t s);
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+hipError_t ensure(DevBuf& b, size_t bytes);
+void release(DevBuf& b);
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+#define DG_CHECK(call)                                   \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) throw ::dg::HipError{_e, #call}; \
+  } while (0)
+
+// Device counters of one update batch (zeroed at batch start).
+struct UpdCounters {
+  uint32_t flags;
+  uint32_t nv;                  // vertex ops in the batch
+  uint32_t n_touch_f, n_touch_r;
+  uint32_t n_clear, n_vchange;
+  uint32_t pad0, pad1;
+  unsigned long long arcs_delta;  // visible arcs added minus tombstoned (two's complement)
+  unsigned long long demand_f, demand_r;
+  unsigned long long cursor0_f, cursor0_r;
+};
+constexpr uint32_t VCHANGE_INLINE = 4096;   // vertex changes copied with the counters
+
+struct UpdateScratch {
+  DevBuf keys0, keys1, vals0, vals1, sortw, vafter, vlastrem, recflags, recw;
+  DevBuf ops, results, touch, plan, clear;
+  DevBuf summary;               // UpdCounters followed by the vertex-change list
+  void* host_summary = nullptr; // pinned mirror of the first part of summary
+  uint64_t cap = 0;
+};
+
+// Per-query scratch for the plain (one query per launch) path.
+struct QueryScratch {
+  DevBuf qa, qb;                // frontier work items (u64: tile << 32 | vertex)
+  DevBuf fa, fb;                // far queues (SSSP) / vertex order (BC)
+  DevBuf bm0, bm1;              // frontier bitmaps
+  DevBuf stamp, flag8;          // SSSP dedup state
+  DevBuf sigma, delta, level;   // BC
+  DevBuf counters;
+  void* host_counters = nullptr;
+  uint64_t items_cap = 0;
+};
+
+struct Tuning {
+  uint32_t tile_buckets = 8;
+  uint32_t sssp_delta = 64;
+  uint32_t alpha = 14, beta = 24;
+  uint32_t batch_groups = 4;
+};
+
+}  // namespace dg
+
+struct dg_graph {
+  dg_config cfg{};
+  int device = 0;
+  uint32_t L = 1;               // key bits per vertex id
+  dg::Store st{};
+  dg::DevBuf fdesc, rdesc, fused, rused, fpool, rpool, cursor, alive, insf, insr;
+  uint32_t epoch = 0;           // latest published epoch
+  std::map<uint32_t, int> pins;
+  // vertex liveness history: first toggle epoch per vertex (0 = never) and
+  // later toggles for vertices that changed more than once
+  std::vector<uint32_t> vfirst;
+  std::unordered_map<uint32_t, std::vector<uint32_t>> vmore;
+  uint64_t n_live = 0;
+  std::vector<uint64_t> arcs_by_epoch{0};   // visible arcs at each epoch
+  std::vector<uint64_t> live_by_epoch{0};   // live vertices at each epoch
+  dg::UpdateScratch us;
+  dg::QueryScratch qs;
+  dg::Tuning tune;
+  std::string err;
+  std::mutex mu;                // serialises the serving loop's workers on this graph
+};
+
+namespace dg {
+// graph-level helpers (api.cpp)
+uint32_t gc_floor(const dg_graph* g);
+bool alive_at(const dg_graph* g, uint32_t v, uint32_t e);
+bool is_device_ptr(const void* p);
+hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r);
+
+// update.hip: runs one batch; returns a dg_status.
+dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* dres, hipStream_t s);
+
+// query.hip
+dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStream_t s, QueryScratch& q);
+dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStream_t s, QueryScratch& q);
+dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, double* bc, hipStream_t s,
+                 QueryScratch& q);
+dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hipStream_t s);
+void free_query_scratch(QueryScratch& q);
+
+// batch.hip
+dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query,
+                          hipStream_t s);
+void free_batch_state(dg_graph* g);
+
+}  // namespace dg

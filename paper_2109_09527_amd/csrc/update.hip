@@ -1,0 +1,563 @@
+// Batched update: one batch of ADT ops (AddVertex / RemoveVertex /
+// ContainsVertex / AddEdge / RemoveEdge / ContainsEdge) applied as if
+// linearized in index order, published as one new epoch E' = e + 1.
+//
+//   k_upd_init        zero the batch counters, snapshot the pool cursors
+//   k_prep            validate every op; sort key = [edge:1][a:L][b:L]
+//                     (vertex op: a = vertex, b = 0; edge op: (u,v), or
+//                     {min,max} when undirected); value = op index
+//   radix sort        stable, so each key's ops stay in index order
+//   k_resolve_vertex  one thread per vertex-key segment walks its ops in
+//                     order: result of each op, liveness after it, index of
+//                     the last successful RemoveVertex so far
+//   k_resolve_edge    one thread per edge-key segment: state at e from one
+//                     probe of the store, then each op in order, with the
+//                     endpoints' liveness at that index from a binary search
+//                     of the vertex timelines and the edge cleared whenever a
+//                     successful RemoveVertex of an endpoint lies between two
+//                     state points; net effect per key = tombstone the
+//                     current version and/or insert a new one
+//   k_grow_plan/exec  slabs that would pass 75% load get a new slab at <=50%
+//                     load; versions dead at or below the oldest queryable
+//                     epoch are dropped while rehashing
+//   k_clear           successful RemoveVertex of a vertex live at e:
+//                     tombstone every current arc at it and its mirror
+//   k_commit_edge     per key: tombstone (death = E') and/or insert
+//                     (birth = E'), mirrored into the reverse slab
+//   k_commit_vertex   liveness of vertices whose state changed
+// Every kernel after k_prep returns at once when the batch was rejected;
+// the commit kernels also when the growth step ran out of pool space, so
+// a rejected batch leaves the store untouched.
+#include <algorithm>
+#include <cstring>
+
+#include "dg_host.h"
+
+namespace dg {
+
+constexpr int UPD_THREADS = 256;
+
+__global__ void k_upd_init(UpdCounters* c, const unsigned long long* cursor) {
+  if (threadIdx.x == 0) {
+    UpdCounters z{};
+    z.cursor0_f = cursor[0];
+    z.cursor0_r = cursor[1];
+    *c = z;
+  }
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_prep(const dg_op* ops, uint32_t n, uint32_t V, int und,
+                                                       int32_t wmax, uint32_t L, uint64_t* keys,
+                                                       uint32_t* vals, UpdCounters* c) {
+  uint32_t i = blockIdx.x * UPD_THREADS + threadIdx.x;
+  uint32_t flags = 0;
+  bool isv = false;
+  if (i < n) {
+    dg_op op = ops[i];
+    bool edge = op.type >= DG_ADD_EDGE;
+    if (op.type > DG_CONTAINS_EDGE) flags |= F_BAD_TYPE;
+    if (op.u >= V || (edge && op.v >= V)) flags |= F_BAD_VERTEX;
+    if (op.type == DG_ADD_EDGE && (op.w < 1 || op.w > wmax)) flags |= F_BAD_WEIGHT;
+    uint64_t a = op.u, b = edge ? op.v : 0;
+    if (edge && und && a > b) {
+      uint64_t t = a;
+      a = b;
+      b = t;
+    }
+    uint64_t mask = (1ull << L) - 1;
+    keys[i] = ((uint64_t)(edge ? 1 : 0) << (2 * L)) | ((a & mask) << L) | (b & mask);
+    vals[i] = i;
+    isv = !edge;
+  }
+  unsigned long long m = __ballot(isv);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, 64);
+  if (lane_id() == 0) {
+    if (m) atomicAdd(&c->nv, (uint32_t)__popcll(m));
+    if (flags) atomicOr(&c->flags, flags);
+  }
+}
+
+struct VState {
+  uint8_t alive;
+  uint32_t lastrem;   // index of the last successful RemoveVertex, or NONE
+};
+
+// State of vertex x just before op index i: the last vertex op on x with a
+// smaller index (sorted part [0, nv) is ordered by (vertex, index)).
+__device__ inline VState vstate(const uint64_t* keys, const uint32_t* vals, uint32_t nv, uint32_t L, uint32_t x,
+                                uint32_t i, const uint8_t* alive, const uint8_t* vafter, const uint32_t* vlastrem) {
+  uint32_t lo = 0, hi = nv;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    uint32_t vx = (uint32_t)(keys[mid] >> L);
+    if (vx < x || (vx == x && vals[mid] < i)) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo > 0 && (uint32_t)(keys[lo - 1] >> L) == x) return VState{vafter[lo - 1], vlastrem[lo - 1]};
+  return VState{alive[x], NONE};
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_resolve_vertex(const uint64_t* keys, const uint32_t* vals,
+                                                                 const dg_op* ops, uint32_t n, uint32_t L,
+                                                                 const uint8_t* alive, uint8_t* results,
+                                                                 uint8_t* vafter, uint32_t* vlastrem,
+                                                                 uint32_t* clear_list, uint32_t* vchange,
+                                                                 UpdCounters* c) {
+  if (c->flags) return;
+  uint32_t nv = c->nv;
+  uint32_t k = blockIdx.x * UPD_THREADS + threadIdx.x;
+  if (k >= nv) return;
+  uint32_t x = (uint32_t)(keys[k] >> L);
+  if (k > 0 && (uint32_t)(keys[k - 1] >> L) == x) return;
+  uint8_t init = alive[x], state = init;
+  uint32_t lastrem = NONE;
+  for (uint32_t j = k; j < nv && (uint32_t)(keys[j] >> L) == x; j++) {
+    uint32_t i = vals[j];
+    uint32_t t = ops[i].type;
+    uint8_t r;
+    if (t == DG_ADD_VERTEX) {
+      r = state ? 0 : 1;
+      state = 1;
+    } else if (t == DG_REMOVE_VERTEX) {
+      r = state;
+      if (state) lastrem = i;
+      state = 0;
+    } else {
+      r = state;
+    }
+    results[i] = r;
+    vafter[j] = state;
+    vlastrem[j] = lastrem;
+  }
+  if (init && lastrem != NONE) clear_list[atomicAdd(&c->n_clear, 1u)] = x;
+  if (state != init) vchange[atomicAdd(&c->n_vchange, 1u)] = x | ((uint32_t)state << 31);
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
+    const uint64_t* keys, const uint32_t* vals, const dg_op* ops, uint32_t n, uint32_t L, Store st,
+    uint8_t* results, const uint8_t* vafter, const uint32_t* vlastrem, uint8_t* recflags, int32_t* recw,
+    uint32_t* touch_f, uint32_t* touch_r, uint32_t* insf, uint32_t* insr, UpdCounters* c) {
+  if (c->flags) return;
+  uint32_t nv = c->nv;
+  uint32_t k = nv + blockIdx.x * UPD_THREADS + threadIdx.x;
+  if (k >= n) return;
+  uint64_t key = keys[k];
+  if (k > nv && keys[k - 1] == key) {
+    recflags[k] = 0;
+    return;
+  }
+  const uint64_t mask = (1ull << L) - 1;
+  uint32_t a = (uint32_t)((key >> L) & mask), b = (uint32_t)(key & mask);
+  Slab sa = slab_of(st.fp, st.fdesc[a]);
+  SlotRef ref = find_current(sa, b);
+  bool present0 = ref.bp != nullptr;
+  int32_t w0 = present0 ? (int32_t)*slot_w(ref.bp, ref.j) : 0;
+  bool present = present0;
+  int32_t w = w0;
+  int64_t last_pt = -1;
+  for (uint32_t j = k; j < n && keys[j] == key; j++) {
+    uint32_t i = vals[j];
+    dg_op op = ops[i];
+    VState sa_ = vstate(keys, vals, nv, L, a, i, st.alive, vafter, vlastrem);
+    VState sb_ = vstate(keys, vals, nv, L, b, i, st.alive, vafter, vlastrem);
+    int64_t tc = -1;
+    if (sa_.lastrem != NONE) tc = sa_.lastrem;
+    if (sb_.lastrem != NONE && (int64_t)sb_.lastrem > tc) tc = sb_.lastrem;
+    if (tc > last_pt) present = false;   // an endpoint was removed since the last state point
+    uint8_t r;
+    if (!sa_.alive || !sb_.alive) {
+      r = 2;
+    } else if (op.type == DG_ADD_EDGE) {
+      if (present) r = 0;
+      else {
+        present = true;
+        w = op.w;
+        r = 1;
+      }
+    } else if (op.type == DG_REMOVE_EDGE) {
+      r = present ? 1 : 0;
+      present = false;
+    } else {
+      r = present ? 1 : 0;
+    }
+    results[i] = r;
+    last_pt = i;
+  }
+  VState ea = vstate(keys, vals, nv, L, a, n, st.alive, vafter, vlastrem);
+  VState eb = vstate(keys, vals, nv, L, b, n, st.alive, vafter, vlastrem);
+  int64_t tce = -1;
+  if (ea.lastrem != NONE) tce = ea.lastrem;
+  if (eb.lastrem != NONE && (int64_t)eb.lastrem > tce) tce = eb.lastrem;
+  if (tce > last_pt) present = false;
+  // an endpoint live at e and removed in this batch: its clear tombstones
+  // the version present at e
+  bool cleared = present0 && tce >= 0;
+  bool tomb = present0 && !cleared && (!present || w != w0);
+  bool ins = present && (!present0 || cleared || w != w0);
+  recflags[k] = (uint8_t)((tomb ? 1 : 0) | (ins ? 2 : 0));
+  recw[k] = w;
+  if (ins) {
+    if (atomicAdd(&insf[a], 1u) == 0) touch_f[atomicAdd(&c->n_touch_f, 1u)] = a;
+    if (!st.undirected) {
+      if (atomicAdd(&insr[b], 1u) == 0) touch_r[atomicAdd(&c->n_touch_r, 1u)] = b;
+    } else if (a != b) {
+      if (atomicAdd(&insf[b], 1u) == 0) touch_f[atomicAdd(&c->n_touch_f, 1u)] = b;
+    }
+  }
+}
+
+// One wave per touched vertex: decide whether its slab must grow.
+// plan[k] = log2(new buckets) + 1, or 0 when the slab keeps its size.
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint32_t* touch_f,
+                                                            const uint32_t* touch_r, uint32_t* plan,
+                                                            uint32_t* plan_ins, uint32_t* insf,
+                                                            uint32_t* insr, uint32_t floor_e,
+                                                            UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t nf = c->n_touch_f, nr = c->n_touch_r;
+  const uint32_t lane = lane_id();
+  const uint32_t waves = gridDim.x * (UPD_THREADS / 64);
+  for (uint32_t k = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6); k < nf + nr; k += waves) {
+    bool fwd = k < nf;
+    uint32_t x = fwd ? touch_f[k] : touch_r[k - nf];
+    uint32_t* insa = fwd ? insf : insr;
+    uint32_t* useda = fwd ? st.fused : st.rused;
+    const Pool& p = fwd ? st.fp : st.rp;
+    uint32_t ins = insa[x];
+    uint32_t used = useda[x];
+    Slab s = slab_of(p, fwd ? st.fdesc[x] : st.rdesc[x]);
+    bool grow = (uint64_t)used + ins > 12ull * s.nb;
+    uint32_t kept = 0;
+    if (grow) {
+      for (uint32_t t = lane; t < s.nb * BSLOTS; t += 64) {
+        uint32_t* bp = bucket_ptr(s, t / BSLOTS);
+        uint32_t j = t % BSLOTS;
+        uint32_t d = *slot_dst(bp, j);
+        if (d != EMPTY && *slot_death(bp, j, s.words) > floor_e) kept++;
+      }
+      kept = wave_sum_u32(kept);
+    }
+    if (lane == 0) {
+      insa[x] = 0;
+      if (!grow) {
+        useda[x] = used + ins;
+        plan[k] = 0;
+      } else {
+        uint64_t target = (uint64_t)kept + ins;
+        uint32_t lg = 0;
+        while ((8ull << lg) < target) lg++;
+        plan[k] = lg + 1;
+        plan_ins[k] = ins;
+        atomicAdd(fwd ? &c->demand_f : &c->demand_r, 1ull << lg);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint32_t* touch_f,
+                                                            const uint32_t* touch_r, const uint32_t* plan,
+                                                            const uint32_t* plan_ins, uint32_t floor_e,
+                                                            UpdCounters* c) {
+  if (c->flags) return;
+  if (c->cursor0_f + c->demand_f > st.fp.cap || (!st.undirected && c->cursor0_r + c->demand_r > st.rp.cap)) {
+    if (threadIdx.x == 0) atomicOr(&c->flags, (uint32_t)F_OOM);
+    return;
+  }
+  const uint32_t nf = c->n_touch_f, nr = c->n_touch_r;
+  __shared__ unsigned long long s_off;
+  __shared__ uint32_t s_kept;
+  for (uint32_t k = blockIdx.x; k < nf + nr; k += gridDim.x) {
+    uint32_t pl = plan[k];
+    if (pl == 0) continue;
+    bool fwd = k < nf;
+    uint32_t x = fwd ? touch_f[k] : touch_r[k - nf];
+    const Pool& p = fwd ? st.fp : st.rp;
+    uint64_t* desca = fwd ? st.fdesc : st.rdesc;
+    uint32_t lg = pl - 1, nb2 = 1u << lg;
+    if (threadIdx.x == 0) {
+      s_off = atomicAdd(&st.cursor[fwd ? 0 : 1], (unsigned long long)nb2);
+      s_kept = 0;
+    }
+    __syncthreads();
+    uint64_t off = s_off;
+    uint32_t* nbase = p.base + off * p.words;
+    for (uint64_t t = threadIdx.x; t < (uint64_t)nb2 * p.words; t += UPD_THREADS) nbase[t] = 0xFFFFFFFFu;
+    __threadfence();
+    __syncthreads();
+    Slab ns{nbase, nb2, p.words};
+    Slab os = slab_of(p, desca[x]);
+    uint32_t kept = 0;
+    for (uint32_t t = threadIdx.x; t < os.nb * BSLOTS; t += UPD_THREADS) {
+      uint32_t* bp = bucket_ptr(os, t / BSLOTS);
+      uint32_t j = t % BSLOTS;
+      uint32_t d = *slot_dst(bp, j);
+      if (d == EMPTY) continue;
+      uint64_t stamp = *slot_stamp(bp, j, os.words);
+      if ((uint32_t)(stamp >> 32) <= floor_e) continue;
+      SlotRef r = claim_slot(ns, d);
+      if (fwd) *slot_w(r.bp, r.j) = *slot_w(bp, j);
+      *slot_stamp(r.bp, r.j, ns.words) = stamp;
+      kept++;
+    }
+    if (kept) atomicAdd(&s_kept, kept);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      desca[x] = make_desc(off, lg);
+      (fwd ? st.fused : st.rused)[x] = s_kept + plan_ins[k];
+    }
+    __syncthreads();
+  }
+}
+
+// Tombstone the current version of `key` (death INF -> E).  Returns true
+// for the one thread whose compare-and-swap made the transition.
+__device__ inline bool tombstone_in(const Pool& p, uint64_t desc, uint32_t key, uint32_t E) {
+  Slab s = slab_of(p, desc);
+  SlotRef r = find_current(s, key);
+  if (!r.bp) return false;
+  return atomicCAS(slot_death(r.bp, r.j, s.words), INF_EPOCH, E) == INF_EPOCH;
+}
+
+// One workgroup per cleared vertex.  arcs_delta counts forward-pool slots
+// whose version this batch tombstoned (each exactly once, via the CAS).
+__global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t* clear_list, uint32_t E,
+                                                        UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t ncl = c->n_clear;
+  for (uint32_t k = blockIdx.x; k < ncl; k += gridDim.x) {
+    uint32_t x = clear_list[k];
+    int dropped = 0;
+    Slab fs = slab_of(st.fp, st.fdesc[x]);
+    for (uint32_t t = threadIdx.x; t < fs.nb * BSLOTS; t += UPD_THREADS) {
+      uint32_t* bp = bucket_ptr(fs, t / BSLOTS);
+      uint32_t j = t % BSLOTS;
+      uint32_t d = ld_relaxed(slot_dst(bp, j));
+      if (d == EMPTY) continue;
+      if (atomicCAS(slot_death(bp, j, fs.words), INF_EPOCH, E) != INF_EPOCH) continue;
+      dropped++;
+      if (!st.undirected) tombstone_in(st.rp, st.rdesc[d], x, E);
+      else if (d != x && tombstone_in(st.fp, st.fdesc[d], x, E)) dropped++;
+    }
+    if (!st.undirected) {
+      Slab rs = slab_of(st.rp, st.rdesc[x]);
+      for (uint32_t t = threadIdx.x; t < rs.nb * BSLOTS; t += UPD_THREADS) {
+        uint32_t* bp = bucket_ptr(rs, t / BSLOTS);
+        uint32_t j = t % BSLOTS;
+        uint32_t sv = ld_relaxed(slot_dst(bp, j));
+        if (sv == EMPTY) continue;
+        if (atomicCAS(slot_death(bp, j, rs.words), INF_EPOCH, E) != INF_EPOCH) continue;
+        if (tombstone_in(st.fp, st.fdesc[sv], x, E)) dropped++;
+      }
+    }
+    uint32_t tot = wave_sum_u32((uint32_t)dropped);
+    if (lane_id() == 0 && tot) atomicAdd(&c->arcs_delta, (unsigned long long)(-(long long)tot));
+  }
+}
+
+__device__ inline void insert_in(const Pool& p, uint64_t desc, uint32_t key, int32_t w, bool has_w, uint32_t E) {
+  Slab s = slab_of(p, desc);
+  SlotRef r = claim_slot(s, key);
+  if (!r.bp) return;   // unreachable: growth guarantees a free slot
+  if (has_w) *slot_w(r.bp, r.j) = (uint32_t)w;
+  *slot_stamp(r.bp, r.j, s.words) = (uint64_t)E | ((uint64_t)INF_EPOCH << 32);
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_commit_edge(const uint64_t* keys, uint32_t n, uint32_t L,
+                                                              Store st, const uint8_t* recflags,
+                                                              const int32_t* recw, uint32_t E,
+                                                              UpdCounters* c) {
+  if (c->flags) return;
+  uint32_t k = c->nv + blockIdx.x * UPD_THREADS + threadIdx.x;
+  uint8_t f = k < n ? recflags[k] : 0;
+  int delta = 0;
+  if (f) {
+    const uint64_t mask = (1ull << L) - 1;
+    uint64_t key = keys[k];
+    uint32_t a = (uint32_t)((key >> L) & mask), b = (uint32_t)(key & mask);
+    if (f & 1) {
+      if (tombstone_in(st.fp, st.fdesc[a], b, E)) delta--;
+      if (!st.undirected) tombstone_in(st.rp, st.rdesc[b], a, E);
+      else if (a != b && tombstone_in(st.fp, st.fdesc[b], a, E)) delta--;
+    }
+    if (f & 2) {
+      int32_t w = recw[k];
+      insert_in(st.fp, st.fdesc[a], b, w, true, E);
+      delta++;
+      if (!st.undirected) insert_in(st.rp, st.rdesc[b], a, 0, false, E);
+      else if (a != b) {
+        insert_in(st.fp, st.fdesc[b], a, w, true, E);
+        delta++;
+      }
+    }
+  }
+  // wave-aggregated count of arcs added minus arcs tombstoned
+  int tot = 0;
+  {
+    int v = delta;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    tot = v;
+  }
+  if (lane_id() == 0 && tot) atomicAdd(&c->arcs_delta, (unsigned long long)(long long)tot);
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_commit_vertex(Store st, const uint32_t* vchange, UpdCounters* c) {
+  if (c->flags) return;
+  uint32_t nvc = c->n_vchange;
+  for (uint32_t k = blockIdx.x * UPD_THREADS + threadIdx.x; k < nvc; k += gridDim.x * UPD_THREADS) {
+    uint32_t x = vchange[k];
+    st.alive[x & 0x7FFFFFFFu] = (uint8_t)(x >> 31);
+  }
+}
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t per, uint32_t cap = 1u << 20) {
+  uint64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (uint32_t)b;
+}
+
+static hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
+  UpdateScratch& u = g->us;
+  if (n <= u.cap && u.host_summary) return hipSuccess;
+  uint64_t c = std::max<uint64_t>(n, 1024);
+  hipError_t e;
+#define ENS(buf, bytes) \
+  if ((e = ensure(u.buf, (bytes))) != hipSuccess) return e;
+  ENS(keys0, c * 8) ENS(keys1, c * 8) ENS(vals0, c * 4) ENS(vals1, c * 4)
+  ENS(sortw, sort_scratch_words((uint32_t)c) * 4)
+  ENS(vafter, c) ENS(vlastrem, c * 4) ENS(recflags, c) ENS(recw, c * 4)
+  ENS(ops, c * sizeof(dg_op)) ENS(results, c) ENS(touch, c * 12) ENS(plan, c * 24) ENS(clear, c * 4)
+  ENS(summary, sizeof(UpdCounters) + c * 4)
+#undef ENS
+  if (!u.host_summary) {
+    e = hipHostMalloc(&u.host_summary, sizeof(UpdCounters) + VCHANGE_INLINE * 4, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+  }
+  u.cap = c;
+  return hipSuccess;
+}
+
+// Runs the pipeline once; *flags receives the batch flags.
+static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8_t* dres, hipStream_t s,
+                               UpdCounters* hc) {
+  UpdateScratch& u = g->us;
+  const Store& st = g->st;
+  const uint32_t L = g->L;
+  const uint32_t E = g->epoch + 1;
+  const uint32_t fl = gc_floor(g);
+  UpdCounters* c = u.summary.as<UpdCounters>();
+  uint32_t* vchange = reinterpret_cast<uint32_t*>(c + 1);
+  uint32_t* touch_f = u.touch.as<uint32_t>();
+  uint32_t* touch_r = touch_f + 2ull * n;   // undirected inserts touch both ends
+  uint32_t* plan = u.plan.as<uint32_t>();
+  uint32_t* plan_ins = plan + 3ull * n;
+  uint32_t nb = blocks_for(n, UPD_THREADS);
+
+  k_upd_init<<<1, 64, 0, s>>>(c, st.cursor);
+  k_prep<<<nb, UPD_THREADS, 0, s>>>(dops, n, st.V, st.undirected, g->cfg.w_max, L, u.keys0.as<uint64_t>(),
+                                    u.vals0.as<uint32_t>(), c);
+  bool alt = radix_sort_pairs(u.keys0.as<uint64_t>(), u.vals0.as<uint32_t>(), u.keys1.as<uint64_t>(),
+                              u.vals1.as<uint32_t>(), n, (int)(2 * L + 1), u.sortw.as<uint32_t>(), s);
+  const uint64_t* keys = alt ? u.keys1.as<uint64_t>() : u.keys0.as<uint64_t>();
+  const uint32_t* vals = alt ? u.vals1.as<uint32_t>() : u.vals0.as<uint32_t>();
+  k_resolve_vertex<<<nb, UPD_THREADS, 0, s>>>(keys, vals, dops, n, L, st.alive, dres, u.vafter.as<uint8_t>(),
+                                              u.vlastrem.as<uint32_t>(), u.clear.as<uint32_t>(), vchange, c);
+  k_resolve_edge<<<nb, UPD_THREADS, 0, s>>>(keys, vals, dops, n, L, st, dres, u.vafter.as<uint8_t>(),
+                                            u.vlastrem.as<uint32_t>(), u.recflags.as<uint8_t>(),
+                                            u.recw.as<int32_t>(), touch_f, touch_r, g->insf.as<uint32_t>(),
+                                            g->insr.as<uint32_t>(), c);
+  k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS / 64, 4096), UPD_THREADS, 0, s>>>(
+      st, touch_f, touch_r, plan, plan_ins, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
+  k_grow_exec<<<blocks_for(3ull * n, 1, 2048), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, plan, plan_ins, fl, c);
+  k_clear<<<blocks_for(n, 1, 2048), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
+  k_commit_edge<<<nb, UPD_THREADS, 0, s>>>(keys, n, L, st, u.recflags.as<uint8_t>(), u.recw.as<int32_t>(), E, c);
+  k_commit_vertex<<<blocks_for(n, UPD_THREADS, 1024), UPD_THREADS, 0, s>>>(st, vchange, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t inl = sizeof(UpdCounters) + std::min<uint64_t>(n, VCHANGE_INLINE) * 4;
+  e = hipMemcpyAsync(u.host_summary, c, inl, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::memcpy(hc, u.host_summary, sizeof(UpdCounters));
+  return hipSuccess;
+}
+
+static void record_vertex_changes(dg_graph* g, const uint32_t* list, uint32_t cnt, uint32_t E) {
+  for (uint32_t k = 0; k < cnt; k++) {
+    uint32_t x = list[k] & 0x7FFFFFFFu;
+    bool now = (list[k] >> 31) != 0;
+    if (g->vfirst[x] == 0) g->vfirst[x] = E;
+    else g->vmore[x].push_back(E);
+    g->n_live += now ? 1 : -1;
+  }
+}
+
+dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* dres, hipStream_t s) {
+  if (n == 0) return DG_OK;
+  if (n > 0xFFFFFFF0ull) {
+    g->err = "batch too large";
+    return DG_E_INVALID_ARG;
+  }
+  hipError_t e = ensure_update_scratch(g, n);
+  if (e != hipSuccess) {
+    g->err = std::string("scratch allocation: ") + hipGetErrorString(e);
+    return DG_E_OUT_OF_MEMORY;
+  }
+  uint8_t* res = dres ? dres : g->us.results.as<uint8_t>();
+  UpdCounters hc{};
+  for (int attempt = 0; attempt < 8; attempt++) {
+    e = run_pipeline(g, dops, (uint32_t)n, res, s, &hc);
+    if (e != hipSuccess) {
+      g->err = std::string("update pipeline: ") + hipGetErrorString(e);
+      return DG_E_HIP;
+    }
+    if (hc.flags & F_BAD_TYPE) {
+      g->err = "unknown op type in batch";
+      return DG_E_INVALID_ARG;
+    }
+    if (hc.flags & F_BAD_VERTEX) {
+      g->err = "vertex id out of range in batch";
+      return DG_E_VERTEX_RANGE;
+    }
+    if (hc.flags & F_BAD_WEIGHT) {
+      g->err = "AddEdge weight out of range in batch";
+      return DG_E_WEIGHT_RANGE;
+    }
+    if (!(hc.flags & F_OOM)) break;
+    // the growth step found the pools too small and nothing was committed:
+    // enlarge them and run the batch again
+    e = grow_pools(g, hc.demand_f, hc.demand_r);
+    if (e != hipSuccess) {
+      g->err = std::string("pool growth: ") + hipGetErrorString(e);
+      return DG_E_OUT_OF_MEMORY;
+    }
+    if (attempt == 7) {
+      g->err = "pool growth did not converge";
+      return DG_E_OUT_OF_MEMORY;
+    }
+  }
+  const uint32_t E = g->epoch + 1;
+  if (hc.n_vchange <= VCHANGE_INLINE) {
+    record_vertex_changes(g, reinterpret_cast<uint32_t*>(static_cast<char*>(g->us.host_summary) + sizeof(UpdCounters)),
+                          hc.n_vchange, E);
+  } else {
+    std::vector<uint32_t> lst(hc.n_vchange);
+    e = hipMemcpy(lst.data(), reinterpret_cast<uint32_t*>(g->us.summary.as<UpdCounters>() + 1),
+                  (size_t)hc.n_vchange * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g->err = std::string("vertex change readback: ") + hipGetErrorString(e);
+      return DG_E_HIP;
+    }
+    record_vertex_changes(g, lst.data(), hc.n_vchange, E);
+  }
+  g->epoch = E;
+  g->arcs_by_epoch.push_back((uint64_t)((int64_t)g->arcs_by_epoch.back() + (int64_t)hc.arcs_delta));
+  g->live_by_epoch.push_back(g->n_live);
+  return DG_OK;
+}
+
+}  // namespace dg
