@@ -156,6 +156,22 @@ dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t);
 dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t);
 dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, void* stream);
 
+/*
+ * Kernel timing.  While enabled, each launch of a kernel family is bracketed
+ * by HIP events on the stream it runs on, and the visible arcs each launch
+ * examined are counted on the device.  dg_profile_read waits for the
+ * recorded events and reports, per family: launches, summed duration and
+ * summed arcs.  Names are static strings owned by the library.
+ */
+typedef struct {
+  const char* name;
+  uint64_t launches;
+  double total_ms;
+  uint64_t arcs;
+} dg_kernel_stat;
+dg_status dg_profile_enable(dg_graph* g, int on);
+dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset);
+
 /* Counts on epoch e: live vertices and visible arcs. */
 dg_status dg_stats(dg_graph* g, dg_epoch e, uint64_t* n_vertices, uint64_t* n_arcs, void* stream);
 /* Visible out-degree of every vertex at epoch e (device uint32[v_capacity]). */

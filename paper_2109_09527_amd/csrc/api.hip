@@ -45,6 +45,48 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice;
 }
 
+static hipEvent_t prof_event(Prof& p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(dg_graph* g_, int kid_, hipStream_t s_) : g(g_), kid(kid_), s(s_) {
+  if (!g->prof.on) return;
+  a = prof_event(g->prof);
+  if (a) (void)hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = prof_event(g->prof);
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  g->prof.pending.push_back(Prof::Rec{kid, a, b});
+}
+
+void prof_arcs(dg_graph* g, int kid, uint64_t arcs) {
+  if (g->prof.on) g->prof.arcs[kid] += arcs;
+}
+
+static void prof_collect(Prof& p) {
+  for (auto& r : p.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p.ms[r.kid] += ms;
+      p.launches[r.kid]++;
+    }
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.pending.clear();
+}
+
 uint32_t gc_floor(const dg_graph* g) {
   uint32_t keep = std::max<uint32_t>(1, g->cfg.max_resident_epochs);
   uint32_t fl = g->epoch + 1 > keep ? g->epoch + 1 - keep : 0;
@@ -66,21 +108,32 @@ bool alive_at(const dg_graph* g, uint32_t v, uint32_t e) {
 uint64_t arcs_at(const dg_graph* g, uint32_t e) { return e < g->arcs_by_epoch.size() ? g->arcs_by_epoch[e] : 0; }
 uint64_t live_at(const dg_graph* g, uint32_t e) { return e < g->live_by_epoch.size() ? g->live_by_epoch[e] : 0; }
 
-static hipError_t realloc_pool(DevBuf& buf, Pool& p, uint64_t new_cap, uint64_t used_buckets) {
+static hipError_t realloc_pool(DevBuf& buf, DevBuf& sbuf, Pool& p, uint64_t new_cap, uint64_t used_buckets) {
   void* np = nullptr;
+  void* ns = nullptr;
   hipError_t e = hipMalloc(&np, new_cap * p.words * 4ull);
   if (e != hipSuccess) return e;
+  if ((e = hipMalloc(&ns, new_cap * 8ull)) != hipSuccess) {
+    hipFree(np);
+    return e;
+  }
   if (used_buckets) {
     e = hipMemcpy(np, p.base, used_buckets * p.words * 4ull, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ns, p.sum, used_buckets * 8ull, hipMemcpyDeviceToDevice);
     if (e != hipSuccess) {
       hipFree(np);
+      hipFree(ns);
       return e;
     }
   }
   hipFree(buf.p);
+  hipFree(sbuf.p);
   buf.p = np;
   buf.bytes = new_cap * p.words * 4ull;
+  sbuf.p = ns;
+  sbuf.bytes = new_cap * 8ull;
   p.base = static_cast<uint32_t*>(np);
+  p.sum = static_cast<uint32_t*>(ns);
   p.cap = new_cap;
   return hipSuccess;
 }
@@ -96,11 +149,11 @@ hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r) {
   if (e != hipSuccess) return e;
   if (cur[0] + need_f > g->st.fp.cap) {
     uint64_t nc = std::max<uint64_t>(2 * g->st.fp.cap, cur[0] + 2 * need_f + 1024);
-    if ((e = realloc_pool(g->fpool, g->st.fp, nc, cur[0])) != hipSuccess) return e;
+    if ((e = realloc_pool(g->fpool, g->fsum, g->st.fp, nc, cur[0])) != hipSuccess) return e;
   }
   if (!g->st.undirected && cur[1] + need_r > g->st.rp.cap) {
     uint64_t nc = std::max<uint64_t>(2 * g->st.rp.cap, cur[1] + 2 * need_r + 1024);
-    if ((e = realloc_pool(g->rpool, g->st.rp, nc, cur[1])) != hipSuccess) return e;
+    if ((e = realloc_pool(g->rpool, g->rsum, g->st.rp, nc, cur[1])) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -150,11 +203,11 @@ __global__ __launch_bounds__(256) void k_compact_exec(Pool op, Pool np, uint64_t
       continue;
     }
     uint64_t off = 1ull + offs[v];   // bucket 0 stays unused
-    uint32_t* nbase = np.base + off * np.words;
-    for (uint64_t t = threadIdx.x; t < (uint64_t)nb * np.words; t += 256) nbase[t] = 0xFFFFFFFFu;
+    Slab ns = slab_at(np, off, nb);
+    for (uint64_t t = threadIdx.x; t < (uint64_t)nb * np.words; t += 256) ns.base[t] = 0xFFFFFFFFu;
+    clear_summaries(ns.sum, nb, threadIdx.x, 256);
     __threadfence();
     __syncthreads();
-    Slab ns{nbase, nb, np.words};
     for (uint32_t t = threadIdx.x; t < os.nb * BSLOTS; t += 256) {
       uint32_t* bp = bucket_ptr(os, t / BSLOTS);
       uint32_t j = t % BSLOTS;
@@ -162,9 +215,10 @@ __global__ __launch_bounds__(256) void k_compact_exec(Pool op, Pool np, uint64_t
       if (d == EMPTY) continue;
       uint64_t stamp = *slot_stamp(bp, j, os.words);
       if ((uint32_t)(stamp >> 32) <= floor_e) continue;
-      SlotRef r = claim_slot(ns, d);
+      SlotRef r = claim_slot(ns, d, (uint32_t)stamp);
       if (np.words == FWD_WORDS) *slot_w(r.bp, r.j) = *slot_w(bp, j);
       *slot_stamp(r.bp, r.j, ns.words) = stamp;
+      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j);
     }
     __threadfence();
     __syncthreads();
@@ -205,23 +259,34 @@ static dg_status compact_pool(dg_graph* g, bool fwd, hipStream_t s) {
   uint64_t need = 1ull + total;
   uint64_t ncap = std::max<uint64_t>(need * 2 + 1024, std::min<uint64_t>(p.cap, need * 4 + 1024));
   void* np = nullptr;
+  void* nsum = nullptr;
   if ((e = hipMalloc(&np, ncap * p.words * 4ull)) != hipSuccess) {
     g->err = "compaction: out of device memory";
     return DG_E_OUT_OF_MEMORY;
   }
-  Pool npool{static_cast<uint32_t*>(np), ncap, p.words};
+  if ((e = hipMalloc(&nsum, ncap * 8ull)) != hipSuccess) {
+    hipFree(np);
+    g->err = "compaction: out of device memory";
+    return DG_E_OUT_OF_MEMORY;
+  }
+  Pool npool{static_cast<uint32_t*>(np), static_cast<uint32_t*>(nsum), ncap, p.words};
   k_compact_exec<<<std::min<uint32_t>(V, 16384), 256, 0, s>>>(p, npool, desc, used, V, fl, nbk.as<uint32_t>(),
                                                              offs.as<uint32_t>(), kept.as<uint32_t>());
   unsigned long long cur = need;
   hipMemcpyAsync(g->st.cursor + (fwd ? 0 : 1), &cur, 8, hipMemcpyHostToDevice, s);
   if ((e = hipStreamSynchronize(s)) != hipSuccess) {
     hipFree(np);
+    hipFree(nsum);
     g->err = std::string("compaction: ") + hipGetErrorString(e);
     return DG_E_HIP;
   }
+  DevBuf& sbuf = fwd ? g->fsum : g->rsum;
   hipFree(buf.p);
+  hipFree(sbuf.p);
   buf.p = np;
   buf.bytes = ncap * p.words * 4ull;
+  sbuf.p = nsum;
+  sbuf.bytes = ncap * 8ull;
   p = npool;
   release(nbk);
   release(kept);
@@ -289,6 +354,8 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   E(g->cursor, 16);
   E(g->fpool, fcap * FWD_WORDS * 4ull);
   E(g->rpool, rcap * REV_WORDS * 4ull);
+  E(g->fsum, fcap * 8ull);
+  E(g->rsum, rcap * 8ull);
   if (e == hipSuccess) {
     hipMemset(g->fdesc.p, 0, V * 8ull);
     hipMemset(g->rdesc.p, 0, V * 8ull);
@@ -313,8 +380,8 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   st.rdesc = g->rdesc.as<uint64_t>();
   st.fused = g->fused.as<uint32_t>();
   st.rused = g->rused.as<uint32_t>();
-  st.fp = Pool{g->fpool.as<uint32_t>(), fcap, (uint32_t)FWD_WORDS};
-  st.rp = Pool{g->rpool.as<uint32_t>(), rcap, (uint32_t)REV_WORDS};
+  st.fp = Pool{g->fpool.as<uint32_t>(), g->fsum.as<uint32_t>(), fcap, (uint32_t)FWD_WORDS};
+  st.rp = Pool{g->rpool.as<uint32_t>(), g->rsum.as<uint32_t>(), rcap, (uint32_t)REV_WORDS};
   st.cursor = g->cursor.as<unsigned long long>();
   st.alive = g->alive.as<uint8_t>();
   g->vfirst.assign(V, 0);
@@ -325,8 +392,8 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
 dg_status dg_destroy(dg_graph* g) {
   if (!g) return DG_E_INVALID_ARG;
   hipDeviceSynchronize();
-  for (DevBuf* b : {&g->fdesc, &g->rdesc, &g->fused, &g->rused, &g->fpool, &g->rpool, &g->cursor, &g->alive,
-                    &g->insf, &g->insr})
+  for (DevBuf* b : {&g->fdesc, &g->rdesc, &g->fused, &g->rused, &g->fpool, &g->rpool, &g->fsum, &g->rsum,
+                    &g->cursor, &g->alive, &g->insf, &g->insr})
     release(*b);
   UpdateScratch& u = g->us;
   for (DevBuf* b : {&u.keys0, &u.keys1, &u.vals0, &u.vals1, &u.sortw, &u.vafter, &u.vlastrem, &u.recflags,
@@ -335,6 +402,12 @@ dg_status dg_destroy(dg_graph* g) {
   if (u.host_summary) hipHostFree(u.host_summary);
   free_query_scratch(g->qs);
   free_batch_state(g);
+  for (auto& r : g->prof.pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : g->prof.pool) hipEventDestroy(e);
+  if (g->last_query) hipEventDestroy(g->last_query);
   delete g;
   return DG_OK;
 }
@@ -359,6 +432,10 @@ dg_status dg_apply_batch(dg_graph* g, const dg_op* ops, uint64_t n, uint8_t* res
       dops = g->us.ops.as<dg_op>();
     }
     bool dev_res = results && is_device_ptr(results);
+    // plain queries scan buckets without per-slot stamps when no writer
+    // runs beside them: let queued query work finish before the batch
+    if (g->last_query && (e = hipStreamWaitEvent(s, g->last_query, 0)) != hipSuccess)
+      return fail(g, DG_E_HIP, std::string("stream wait: ") + hipGetErrorString(e));
     dg_status st = apply_batch_dev(g, dops, n, dev_res ? results : nullptr, s);
     if (st != DG_OK) return st;
     if (results && !dev_res) {
@@ -440,6 +517,17 @@ dg_status dg_compact(dg_graph* g, void* stream) {
   return st;
 }
 
+static dg_status note_query(dg_graph* g, dg_status st, void* stream) {
+  if (st != DG_OK) return st;
+  if (!g->last_query && hipEventCreateWithFlags(&g->last_query, hipEventDisableTiming) != hipSuccess) {
+    g->last_query = nullptr;
+    return fail(g, DG_E_HIP, "event creation");
+  }
+  if (hipEventRecord(g->last_query, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(g, DG_E_HIP, "event record");
+  return DG_OK;
+}
+
 static dg_status check_source(dg_graph* g, uint32_t e, uint32_t src) {
   if (src >= g->cfg.v_capacity) return fail(g, DG_E_VERTEX_RANGE, "source id out of range");
   if (!alive_at(g, src, e)) return fail(g, DG_E_SOURCE_ABSENT, "source is not live at the epoch");
@@ -454,7 +542,7 @@ dg_status dg_bfs(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void* 
   dg_status st = resolve_epoch(g, want, &e);
   if (st == DG_OK) st = check_source(g, e, src);
   if (st != DG_OK) return st;
-  return bfs_dev(g, e, src, dist, static_cast<hipStream_t>(stream), g->qs);
+  return note_query(g, bfs_dev(g, e, src, dist, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
 dg_status dg_sssp(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void* stream) {
@@ -465,7 +553,7 @@ dg_status dg_sssp(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void*
   dg_status st = resolve_epoch(g, want, &e);
   if (st == DG_OK) st = check_source(g, e, src);
   if (st != DG_OK) return st;
-  return sssp_dev(g, e, src, dist, static_cast<hipStream_t>(stream), g->qs);
+  return note_query(g, sssp_dev(g, e, src, dist, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
 dg_status dg_bc(dg_graph* g, dg_epoch want, const uint32_t* srcs, uint32_t k, double* bc, void* stream) {
@@ -482,7 +570,7 @@ dg_status dg_bc(dg_graph* g, dg_epoch want, const uint32_t* srcs, uint32_t k, do
   std::sort(sorted.begin(), sorted.end());
   if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
     return fail(g, DG_E_INVALID_ARG, "repeated BC source");
-  return bc_dev(g, e, S.data(), k, bc, static_cast<hipStream_t>(stream), g->qs);
+  return note_query(g, bc_dev(g, e, S.data(), k, bc, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
@@ -504,6 +592,37 @@ dg_status dg_out_degrees(dg_graph* g, dg_epoch want, uint32_t* deg, void* stream
   dg_status st = resolve_epoch(g, want, &e);
   if (st != DG_OK) return st;
   return stats_dev(g, e, nullptr, deg, static_cast<hipStream_t>(stream));
+}
+
+dg_status dg_profile_enable(dg_graph* g, int on) {
+  if (!g) return DG_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->prof.on = on != 0;
+  return DG_OK;
+}
+
+dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
+  static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
+                                         "sssp_split", "bc_forward", "bc_backward", "query_batch"};
+  if (!g) return DG_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g->mu);
+  prof_collect(g->prof);
+  uint32_t n = 0;
+  for (int k = 0; k < KID_COUNT && n < cap; k++) {
+    if (!out) break;
+    out[n].name = names[k];
+    out[n].launches = g->prof.launches[k];
+    out[n].total_ms = g->prof.ms[k];
+    out[n].arcs = g->prof.arcs[k];
+    n++;
+  }
+  if (n_out) *n_out = out ? n : KID_COUNT;
+  if (reset) {
+    std::fill(std::begin(g->prof.launches), std::end(g->prof.launches), 0ull);
+    std::fill(std::begin(g->prof.ms), std::end(g->prof.ms), 0.0);
+    std::fill(std::begin(g->prof.arcs), std::end(g->prof.arcs), 0ull);
+  }
+  return DG_OK;
 }
 
 dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t) {

@@ -73,6 +73,31 @@ struct QueryScratch {
   uint64_t items_cap = 0;
 };
 
+// Per-kernel-family event timing (dg_profile_*).
+enum KernelId {
+  KID_UPDATE = 0,   // the whole update pipeline of one batch
+  KID_BFS_TD,
+  KID_BFS_BU,
+  KID_SSSP_RELAX,
+  KID_SSSP_SPLIT,
+  KID_BC_FWD,
+  KID_BC_BWD,
+  KID_BATCH,        // one persistent multi-query launch
+  KID_COUNT
+};
+struct Prof {
+  bool on = false;
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  uint64_t launches[KID_COUNT] = {};
+  double ms[KID_COUNT] = {};
+  uint64_t arcs[KID_COUNT] = {};
+};
+
 struct Tuning {
   uint32_t tile_buckets = 8;
   uint32_t sssp_delta = 64;
@@ -87,7 +112,7 @@ struct dg_graph {
   int device = 0;
   uint32_t L = 1;               // key bits per vertex id
   dg::Store st{};
-  dg::DevBuf fdesc, rdesc, fused, rused, fpool, rpool, cursor, alive, insf, insr;
+  dg::DevBuf fdesc, rdesc, fused, rused, fpool, rpool, fsum, rsum, cursor, alive, insf, insr;
   uint32_t epoch = 0;           // latest published epoch
   std::map<uint32_t, int> pins;
   // vertex liveness history: first toggle epoch per vertex (0 = never) and
@@ -100,6 +125,9 @@ struct dg_graph {
   dg::UpdateScratch us;
   dg::QueryScratch qs;
   dg::Tuning tune;
+  dg::Prof prof;
+  int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
+  hipEvent_t last_query = nullptr;  // end of the last plain query's work; updates wait for it
   std::string err;
   std::mutex mu;                // serialises the serving loop's workers on this graph
 };
@@ -110,6 +138,17 @@ uint32_t gc_floor(const dg_graph* g);
 bool alive_at(const dg_graph* g, uint32_t v, uint32_t e);
 bool is_device_ptr(const void* p);
 hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r);
+
+// Event bracket around one launch of a kernel family (no-op unless enabled).
+struct ProfScope {
+  dg_graph* g;
+  int kid;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(dg_graph* g_, int kid_, hipStream_t s_);
+  ~ProfScope();
+};
+void prof_arcs(dg_graph* g, int kid, uint64_t arcs);
 
 // update.hip: runs one batch; returns a dg_status.
 dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* dres, hipStream_t s);

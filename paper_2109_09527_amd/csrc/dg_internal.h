@@ -11,6 +11,11 @@
 //                          [16,32) weight
 //                          [32,64) stamp[16] as u64 = birth | death << 32
 //   rpool                reverse buckets, 48 words each: src[16], stamp[16]
+//   fsum / rsum          per-bucket summary, two u32: the largest birth of
+//                        any version in the bucket and a 16-bit mask of the
+//                        slots whose version has been tombstoned.  With no
+//                        concurrent writer, a scan at epoch e >= that birth
+//                        reads a slot's stamp only when its mask bit is set.
 //   alive[v]             liveness at the latest epoch
 // A version is visible at epoch e iff birth <= e < death; death = INF for
 // the current version.  A slot's bucket is hash(dst) mod buckets, with
@@ -37,6 +42,7 @@ enum : uint32_t { F_BAD_TYPE = 1, F_BAD_VERTEX = 2, F_BAD_WEIGHT = 4, F_OOM = 8 
 
 struct Pool {
   uint32_t* base;       // bucket b starts at base + b * words
+  uint32_t* sum;        // bucket b's summary at sum[2b] (max birth), sum[2b+1] (tomb mask)
   uint64_t cap;         // buckets
   uint32_t words;       // 64 (forward) or 48 (reverse)
 };
@@ -56,6 +62,7 @@ struct Store {
 // Slab view of one vertex in one pool.
 struct Slab {
   uint32_t* base;      // first bucket
+  uint32_t* sum;       // summary of the first bucket
   uint32_t nb;         // buckets (0 = none)
   uint32_t words;
 };
@@ -77,12 +84,18 @@ __device__ inline Slab slab_of(const Pool& p, uint64_t desc) {
   s.words = p.words;
   if (desc == 0) {
     s.base = p.base;
+    s.sum = p.sum;
     s.nb = 0;
   } else {
     s.base = p.base + (desc >> 6) * p.words;
+    s.sum = p.sum + (desc >> 6) * 2;
     s.nb = 1u << (desc & 63);
   }
   return s;
+}
+
+__device__ inline Slab slab_at(const Pool& p, uint64_t off, uint32_t nb) {
+  return Slab{p.base + off * p.words, p.sum + off * 2, nb, p.words};
 }
 
 __device__ inline uint32_t* bucket_ptr(const Slab& s, uint32_t b) { return s.base + (uint64_t)b * s.words; }
@@ -111,10 +124,11 @@ __device__ inline T ld_relaxed(const T* p) { return __hip_atomic_load(p, __ATOMI
 struct SlotRef {
   uint32_t* bp;
   int j;
+  uint32_t b;
 };
 
 __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
-  SlotRef r{nullptr, -1};
+  SlotRef r{nullptr, -1, 0};
   if (s.nb == 0) return r;
   uint32_t mask = s.nb - 1;
   uint32_t b = hmix(x) & mask;
@@ -126,7 +140,7 @@ __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
       if (d == EMPTY) { full = false; break; }
       if (d == x) {
         uint32_t death = ld_relaxed(slot_death(bp, j, s.words));
-        if (death == INF_EPOCH) { r.bp = bp; r.j = j; return r; }
+        if (death == INF_EPOCH) { r.bp = bp; r.j = j; r.b = b; return r; }
       }
     }
     if (!full) return r;
@@ -135,21 +149,49 @@ __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
   return r;
 }
 
-// Claim a free slot for key x (capacity is guaranteed by the growth step).
-__device__ inline SlotRef claim_slot(const Slab& s, uint32_t x) {
-  SlotRef r{nullptr, -1};
+// Claim a free slot for key x whose version is born at `birth` (capacity
+// is guaranteed by the growth step) and raise the bucket's largest-birth
+// summary.  Readers that trust the summary never run beside a writer, so
+// the two updates need no ordering between them.
+__device__ inline SlotRef claim_slot(const Slab& s, uint32_t x, uint32_t birth) {
+  SlotRef r{nullptr, -1, 0};
   uint32_t mask = s.nb - 1;
   uint32_t b = hmix(x) & mask;
   for (uint32_t probe = 0; probe < s.nb; probe++) {
     uint32_t* bp = bucket_ptr(s, b);
+    bool raised = false;
     for (int j = 0; j < BSLOTS; j++) {
       uint32_t* pd = slot_dst(bp, j);
       if (ld_relaxed(pd) != EMPTY) continue;
-      if (atomicCAS(pd, EMPTY, x) == EMPTY) { r.bp = bp; r.j = j; return r; }
+      if (!raised) {
+        atomicMax(&s.sum[2 * b], birth);
+        raised = true;
+      }
+      if (atomicCAS(pd, EMPTY, x) == EMPTY) { r.bp = bp; r.j = j; r.b = b; return r; }
     }
     b = (b + 1) & mask;
   }
   return r;
+}
+
+// Record in the bucket summary that slot j now carries a finite death.
+__device__ inline void mark_tomb(const Slab& s, uint32_t b, int j) { atomicOr(&s.sum[2 * b + 1], 1u << j); }
+
+// Initialise the summaries of nb fresh buckets (no version, no tombstone).
+__device__ inline void clear_summaries(uint32_t* sum, uint32_t nb, uint32_t tid, uint32_t nthreads) {
+  for (uint32_t t = tid; t < 2 * nb; t += nthreads) sum[t] = 0u;
+}
+
+// Whether slot j of bucket b (holding dst d != EMPTY) is visible at e.
+// `fast` is set when no writer can run concurrently with the reader: then
+// the stamp is read only for a tombstoned slot or when the bucket holds a
+// version born after e.
+__device__ inline bool slot_visible(const Slab& s, uint32_t* bp, uint32_t b, int j, uint32_t e, bool fast) {
+  if (fast) {
+    uint2 sm = *reinterpret_cast<const uint2*>(&s.sum[2 * b]);
+    if (sm.x <= e && !((sm.y >> j) & 1u)) return true;
+  }
+  return visible(*slot_stamp(bp, j, s.words), e);
 }
 
 // ------------------------------------------------------------ wave helpers

@@ -1,19 +1,14 @@
-// Snapshot queries on epoch e (plain form: one query, host-driven levels).
-//
-// Frontier work items are (slab descriptor, vertex, tile): a tile is up to
-// T consecutive buckets of the vertex's forward slab, so a hub's adjacency
-// spreads over many items and every item costs at most T bucket scans.  The
-// descriptor is read once when the vertex is pushed and carried in the item,
-// so all tiles of a vertex read the same slab even if a concurrent update
-// regrows it (the old slab stays intact and holds every version visible at
-// e).  A 16-lane group handles one item: lane j reads slot j of a bucket.
+// Snapshot queries on epoch e in the plain form: one query per call, the
+// host driving its levels (one launch per BFS level / SSSP pass / BC level,
+// counters read back between them).  The level steps themselves live in
+// frontier.h and are shared with the persistent multi-query engine.
 //
 //   BFS   direction-optimising (Beamer, Asanovic & Patterson, SC 2012):
-//         top-down over out-slabs with a CAS claim of dist, or bottom-up
-//         over in-slabs of unvisited vertices with a frontier bitmap and
-//         early exit; switch when the frontier's slot count exceeds the
-//         unexplored count / alpha, back when the frontier falls below
-//         live vertices / beta.  Hop distances are the same either way.
+//         top-down over out-slabs with a CAS claim of dist, or bottom-up over
+//         in-slabs of unvisited vertices with a frontier bitmap and early
+//         exit; switch when the frontier's slot count exceeds the unexplored
+//         count / alpha, back when the frontier falls below live vertices /
+//         beta.  Hop distances are the same either way.
 //   SSSP  delta-stepping in near/far form (Meyer & Sanders 2003; Davidson
 //         et al., IPDPS 2014): label-correcting relaxations with atomicMin
 //         below the threshold, far queue above it, threshold += delta when
@@ -27,28 +22,11 @@
 #include <cstring>
 
 #include "dg_host.h"
+#include "frontier.h"
 
 namespace dg {
 
-constexpr int Q_THREADS = 256;
-constexpr int Q_WAVES = Q_THREADS / 64;
-constexpr int Q_ITEMS_PER_BLOCK = Q_WAVES * 4;   // four 16-lane groups per wave
-
-struct Item {
-  uint64_t desc;
-  uint32_t v;
-  uint32_t tile;
-};
-
-struct QCounters {
-  uint32_t n_items;
-  uint32_t n_verts;
-  unsigned long long m_next;
-  uint32_t n_far;
-  int32_t far_min;
-  uint32_t overflow;
-  uint32_t n_order;
-};
+constexpr uint32_t BIG_GRID = 2048;
 
 // --------------------------------------------------------------- fills
 
@@ -65,45 +43,14 @@ static void fill(T* p, uint64_t n, T v, hipStream_t s) {
   k_fill<T><<<(uint32_t)b, 256, 0, s>>>(p, n, v);
 }
 
-// ---------------------------------------------------------- item pushes
-
-__device__ inline uint32_t tiles_of(uint64_t desc, uint32_t T) {
-  if (desc == 0) return 0;
-  uint32_t nb = 1u << (desc & 63);
-  return (nb + T - 1) / T;
-}
-
-// Every lane of the wave calls this; lanes with push=false add nothing.
-__device__ inline void push_items(bool push, uint32_t y, uint64_t desc, uint32_t T, Item* q, uint32_t* counter) {
-  uint32_t k = push ? tiles_of(desc, T) : 0;
-  uint32_t pos = wave_reserve(counter, k);
-  for (uint32_t t = 0; t < k; t++) q[pos + t] = Item{desc, y, t};
-}
-
-__device__ inline void count_verts(bool found, uint32_t used, QCounters* c) {
-  unsigned long long m = __ballot(found);
-  unsigned long long tot = wave_sum_u64(found ? used : 0);
-  if (lane_id() == 0 && m) {
-    atomicAdd(&c->n_verts, (uint32_t)__popcll(m));
-    atomicAdd(&c->m_next, tot);
-  }
-}
-
-__device__ inline bool bm_test(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
-__device__ inline void bm_set(uint32_t* bm, uint32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
-
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
-  return v;
-}
-
-// Seed a query at src: dist/level 0, items of src, bitmap bit.
+// Seed a query at src: dist/level d0, items of src, bitmap bit; counters
+// slot 0 describes the seed frontier, slot 1 is cleared.
 __global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Item* q, uint32_t* bm, uint32_t T,
                        QCounters* cnt, uint32_t* order) {
   if (threadIdx.x != 0) return;
   uint64_t desc = st.fdesc[src];
-  uint32_t k = tiles_of(desc, T);
+  TileShape ts{0, T};
+  uint32_t k = ts.tiles(desc);
   for (uint32_t t = 0; t < k; t++) q[t] = Item{desc, src, t};
   if (dist) dist[src] = d0;
   if (bm) bm[src >> 5] |= 1u << (src & 31);
@@ -115,112 +62,73 @@ __global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Item* 
   c0.n_order = 1;
   c0.far_min = DIST_INF;
   cnt[0] = c0;
-  QCounters z{};
-  z.far_min = DIST_INF;
-  cnt[1] = z;
+  zero_counters(&cnt[1]);
 }
 
-// ------------------------------------------------------------------ BFS
-
-struct LevelArgs {
-  Store st;
-  uint32_t e;
-  const Item* qin;
-  uint32_t nin;
-  Item* qout;
-  const uint32_t* bm_cur;
-  uint32_t* bm_next;
-  int32_t* dist;
-  int32_t next_level;
-  uint32_t T;
-  QCounters* cnt_out;
-  QCounters* cnt_reset;
-};
-
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    QCounters z{};
-    z.far_min = DIST_INF;
-    *a.cnt_reset = z;
-  }
-  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
-  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
-  const uint32_t nwaves = gridDim.x * Q_WAVES;
-  for (uint32_t base = gwave * 4; base < a.nin; base += nwaves * 4) {
-    uint32_t it = base + grp;
-    bool act = it < a.nin;
-    Item item = act ? a.qin[it] : Item{0, 0, 0};
-    Slab s = slab_of(a.st.fp, item.desc);
-    uint32_t b0 = item.tile * a.T;
-    uint32_t nbk = act && s.nb > b0 ? min(a.T, s.nb - b0) : 0;
-    uint32_t maxnb = wave_max_u32(nbk);
-    for (uint32_t i = 0; i < maxnb; i++) {
-      bool found = false;
-      uint32_t y = 0;
-      if (i < nbk) {
-        uint32_t* bp = bucket_ptr(s, b0 + i);
-        uint32_t d = bp[j];
-        if (d != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), a.e) && a.dist[d] < 0) {
-          if (atomicCAS(&a.dist[d], -1, a.next_level) == -1) {
-            found = true;
-            y = d;
-          }
-        }
-      }
-      uint64_t ydesc = found ? a.st.fdesc[y] : 0;
-      push_items(found, y, ydesc, a.T, a.qout, &a.cnt_out->n_items);
-      if (found) bm_set(a.bm_next, y);
-      count_verts(found, found ? a.st.fused[y] : 0, a.cnt_out);
-    }
-  }
+__device__ inline void reset_other(QCounters* c) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) zero_counters(c);
 }
 
-// Bottom-up: each 16-lane group takes one unvisited vertex and scans its
-// in-slab (the forward slab when undirected) for a parent in the frontier.
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    QCounters z{};
-    z.far_min = DIST_INF;
-    *a.cnt_reset = z;
-  }
-  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
-  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
-  const uint32_t nwaves = gridDim.x * Q_WAVES;
-  const uint32_t V = a.st.V;
-  const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
-  const uint64_t* idesc = a.st.undirected ? a.st.fdesc : a.st.rdesc;
-  for (uint32_t base = gwave * 4; base < V; base += nwaves * 4) {
-    uint32_t y = base + grp;
-    bool act = y < V && a.dist[y] < 0;
-    Slab s = slab_of(ip, act ? idesc[y] : 0);
-    uint32_t nbk = act ? s.nb : 0;
-    uint32_t maxnb = wave_max_u32(nbk);
-    bool found = false;
-    for (uint32_t i = 0; i < maxnb; i++) {
-      bool hit = false;
-      if (!found && i < nbk) {
-        uint32_t* bp = bucket_ptr(s, i);
-        uint32_t x = bp[j];
-        hit = x != EMPTY && bm_test(a.bm_cur, x) && visible(*slot_stamp(bp, j, s.words), a.e);
-      }
-      if (group16_ballot(hit)) found = true;
-      if (__ballot(!found && i + 1 < nbk) == 0) break;
-    }
-    bool lead = found && j == 0;
-    if (lead) {
-      a.dist[y] = a.next_level;
-      bm_set(a.bm_next, y);
-    }
-    uint64_t ydesc = lead ? a.st.fdesc[y] : 0;
-    push_items(lead, y, ydesc, a.T, a.qout, &a.cnt_out->n_items);
-    count_verts(lead, lead ? a.st.fused[y] : 0, a.cnt_out);
-  }
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, uint32_t nin, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  td_step(a, nin, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  bu_step(a, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a) {
+  __shared__ Shared sh;
+  stages_init(sh);
+  bu_big_step(a, a.cnt_out->n_big, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, uint32_t nin, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  relax_step(a, nin, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t nin, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  split_step(a, nin, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, uint32_t nin, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  bcfwd_step(a, nin, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bc_bwd(Store st, uint32_t e, int fast, const uint32_t* verts,
+                                                      uint32_t nv, uint32_t src, const int32_t* level, int32_t L,
+                                                      const unsigned long long* sigma, double* delta, double* bc) {
+  bcbwd_step(st, e, fast != 0, verts, nv, src, level, L, sigma, delta, bc, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_inf_to_minus1(int32_t* d, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (d[i] == DIST_INF) d[i] = -1;
+}
+
+static uint64_t items_capacity(const dg_graph* g) {
+  return (uint64_t)g->cfg.v_capacity + g->st.fp.cap / std::max<uint32_t>(1, g->tune.tile_buckets) + 1024;
 }
 
 static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
   hipError_t e;
   const uint64_t V = g->cfg.v_capacity;
-  uint64_t items = V + g->st.fp.cap / std::max<uint32_t>(1, g->tune.tile_buckets) + 1024;
+  uint64_t items = items_capacity(g);
   if ((e = ensure(q.qa, items * sizeof(Item))) != hipSuccess) return e;
   if ((e = ensure(q.qb, items * sizeof(Item))) != hipSuccess) return e;
   q.items_cap = items;
@@ -230,6 +138,11 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
   if ((e = ensure(q.counters, 4 * sizeof(QCounters))) != hipSuccess) return e;
   if (!q.host_counters) {
     if ((e = hipHostMalloc(&q.host_counters, 4 * sizeof(QCounters), hipHostMallocDefault)) != hipSuccess) return e;
+  }
+  if (!sssp && !bc) {
+    // bottom-up chunk items of long in-slabs
+    uint64_t big = V + std::max(g->st.fp.cap, g->st.rp.cap) / BU_CHUNK + 1024;
+    if ((e = ensure(q.fb, big * sizeof(Item))) != hipSuccess) return e;
   }
   if (sssp) {
     if ((e = ensure(q.fa, V * 4 + 64)) != hipSuccess) return e;
@@ -277,12 +190,14 @@ uint64_t arcs_at(const dg_graph* g, uint32_t e);
 uint64_t live_at(const dg_graph* g, uint32_t e);
 
 dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStream_t s, QueryScratch& q) {
+  const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, false, false);
   if (he != hipSuccess) return hip_fail(g, he, "bfs scratch");
   const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
   const uint64_t bmw = (V + 31) / 32 + 1;
   Item* qa = q.qa.as<Item>();
   Item* qb = q.qb.as<Item>();
+  Item* qbig = q.fb.as<Item>();
   uint32_t* bm[2] = {q.bm0.as<uint32_t>(), q.bm1.as<uint32_t>()};
   QCounters* cnt = q.counters.as<QCounters>();
   fill<int32_t>(dist, V, -1, s);
@@ -304,11 +219,18 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
     else if (bu && (uint64_t)n_verts * g->tune.beta < n_live) bu = false;
     m_u -= (int64_t)m_f;
     fill<uint32_t>(bm[nxt], bmw, 0u, s);
-    LevelArgs a{g->st, e, qin, n_items, qout, bm[cur], bm[nxt], dist, level + 1, T, cnt + nxt, cnt + cur};
-    if (bu) k_bfs_bu<<<grid_for(V, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a);
-    else k_bfs_td<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a);
+    LevelArgs a{g->st, e, fast, qin, qout, qbig, bm[cur], bm[nxt], dist, level + 1, T, cnt + nxt};
+    if (bu) {
+      ProfScope ps(g, KID_BFS_BU, s);
+      k_bfs_bu<<<grid_for(V, Q_THREADS), Q_THREADS, 0, s>>>(a, cnt + cur);
+      k_bfs_bu_big<<<BIG_GRID, Q_THREADS, 0, s>>>(a);
+    } else {
+      ProfScope ps(g, KID_BFS_TD, s);
+      k_bfs_td<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+    }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bfs level launch");
     if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
+    prof_arcs(g, bu ? KID_BFS_BU : KID_BFS_TD, hc.arcs);
     n_items = hc.n_items;
     n_verts = hc.n_verts;
     m_f = hc.m_next;
@@ -320,121 +242,8 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
 
 // ----------------------------------------------------------------- SSSP
 
-struct RelaxArgs {
-  Store st;
-  uint32_t e;
-  const Item* qin;
-  uint32_t nin;
-  Item* qout;
-  uint32_t* far_out;
-  int32_t* dist;
-  uint32_t* stamp;     // iteration stamp of the last push into the near queue
-  uint32_t* infar;
-  int32_t thr;
-  uint32_t it1;        // stamp value of the queue being filled
-  uint32_t T;
-  QCounters* cnt_out;
-  QCounters* cnt_reset;
-};
-
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    QCounters z{};
-    z.far_min = DIST_INF;
-    *a.cnt_reset = z;
-  }
-  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
-  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
-  const uint32_t nwaves = gridDim.x * Q_WAVES;
-  for (uint32_t base = gwave * 4; base < a.nin; base += nwaves * 4) {
-    uint32_t it = base + grp;
-    bool act = it < a.nin;
-    Item item = act ? a.qin[it] : Item{0, 0, 0};
-    Slab s = slab_of(a.st.fp, item.desc);
-    uint32_t b0 = item.tile * a.T;
-    uint32_t nbk = act && s.nb > b0 ? min(a.T, s.nb - b0) : 0;
-    int32_t du = act ? __hip_atomic_load(&a.dist[item.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-    uint32_t maxnb = wave_max_u32(nbk);
-    for (uint32_t i = 0; i < maxnb; i++) {
-      bool to_near = false, to_far = false;
-      uint32_t y = 0;
-      if (i < nbk) {
-        uint32_t* bp = bucket_ptr(s, b0 + i);
-        uint32_t d = bp[j];
-        if (d != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), a.e)) {
-          int32_t nd = du + (int32_t)bp[16 + j];
-          if (nd < a.dist[d]) {
-            int32_t old = atomicMin(&a.dist[d], nd);
-            if (nd < old) {
-              y = d;
-              if (nd < a.thr) to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
-              else to_far = atomicExch(&a.infar[d], 1u) == 0u;
-            }
-          }
-        }
-      }
-      uint64_t ydesc = to_near ? a.st.fdesc[y] : 0;
-      push_items(to_near, y, ydesc, a.T, a.qout, &a.cnt_out->n_items);
-      uint32_t fpos = wave_reserve(&a.cnt_out->n_far, to_far ? 1u : 0u);
-      if (to_far) a.far_out[fpos] = y;
-      count_verts(to_near, 0, a.cnt_out);
-    }
-  }
-}
-
-struct SplitArgs {
-  Store st;
-  const uint32_t* far_in;
-  uint32_t nin;
-  uint32_t* far_out;
-  Item* qout;
-  int32_t* dist;
-  uint32_t* stamp;
-  uint32_t* infar;
-  int32_t thr;
-  uint32_t it1;
-  uint32_t T;
-  QCounters* cnt_out;
-  QCounters* cnt_reset;
-};
-
-// Move far entries below the new threshold into the near queue; keep the
-// rest and report their minimum distance.
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    QCounters z{};
-    z.far_min = DIST_INF;
-    *a.cnt_reset = z;
-  }
-  for (uint32_t base = blockIdx.x * Q_THREADS; base < a.nin; base += gridDim.x * Q_THREADS) {
-    uint32_t i = base + threadIdx.x;
-    bool act = i < a.nin;
-    uint32_t v = act ? a.far_in[i] : 0;
-    int32_t dv = act ? a.dist[v] : DIST_INF;
-    bool near = act && dv < a.thr;
-    bool keep = act && !near;
-    if (near) {
-      a.infar[v] = 0u;
-      near = atomicExch(&a.stamp[v], a.it1) != a.it1;
-    }
-    uint64_t vdesc = near ? a.st.fdesc[v] : 0;
-    push_items(near, v, vdesc, a.T, a.qout, &a.cnt_out->n_items);
-    uint32_t fpos = wave_reserve(&a.cnt_out->n_far, keep ? 1u : 0u);
-    if (keep) a.far_out[fpos] = v;
-    int32_t m = keep ? dv : DIST_INF;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = min(m, (int32_t)__shfl_xor(m, o, 64));
-    if (lane_id() == 0 && m < DIST_INF) atomicMin(&a.cnt_out->far_min, m);
-    count_verts(near, 0, a.cnt_out);
-  }
-}
-
-__global__ void k_inf_to_minus1(int32_t* d, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    if (d[i] == DIST_INF) d[i] = -1;
-}
-
 dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStream_t s, QueryScratch& q) {
+  const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, true, false);
   if (he != hipSuccess) return hip_fail(g, he, "sssp scratch");
   const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
@@ -454,17 +263,20 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp seed");
   uint32_t n_near = hc.n_items, n_far = 0;
   int32_t thr = delta;
-  uint32_t it = 1;   // stamp of the queue being filled; source queue had stamp 0
+  uint32_t it = 1;   // stamp of the queue being filled; the source's queue had stamp 0
   int slot = 0;
   for (;;) {
     int nxt = slot ^ 1;
     if (n_near > 0) {
-      RelaxArgs a{g->st, e, qin, n_near, qout, fout, dist, stamp, infar, thr, it, T, cnt + nxt, cnt + slot};
-      // far entries pushed by this pass land after the current far list
-      a.far_out = fin + n_far;
-      k_sssp_relax<<<grid_for(n_near, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a);
+      // far entries found by this pass are appended after the current far list
+      RelaxArgs a{g->st, e, fast, qin, qout, fin + n_far, dist, stamp, infar, thr, it, T, cnt + nxt};
+      {
+        ProfScope ps(g, KID_SSSP_RELAX, s);
+        k_sssp_relax<<<grid_for(n_near, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_near, cnt + slot);
+      }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp relax launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp relax");
+      prof_arcs(g, KID_SSSP_RELAX, hc.arcs);
       n_near = hc.n_items;
       n_far += hc.n_far;
       std::swap(qin, qout);
@@ -479,8 +291,11 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
       thr = far_min == DIST_INF ? thr + delta
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       nxt = slot ^ 1;
-      SplitArgs a{g->st, fin, n_far, fout, qin, dist, stamp, infar, thr, it, T, cnt + nxt, cnt + slot};
-      k_sssp_split<<<grid_for(n_far, Q_THREADS), Q_THREADS, 0, s>>>(a);
+      SplitArgs a{g->st, fin, fout, qin, dist, stamp, infar, thr, it, T, cnt + nxt};
+      {
+        ProfScope ps(g, KID_SSSP_SPLIT, s);
+        k_sssp_split<<<grid_for(n_far, Q_THREADS), Q_THREADS, 0, s>>>(a, n_far, cnt + slot);
+      }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
       slot = nxt;
@@ -498,107 +313,9 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
 
 // ------------------------------------------------------------------- BC
 
-struct BcFwdArgs {
-  Store st;
-  uint32_t e;
-  const Item* qin;
-  uint32_t nin;
-  Item* qout;
-  uint32_t* order;      // vertices in discovery order
-  int32_t* level;
-  unsigned long long* sigma;
-  int32_t next_level;
-  uint32_t T;
-  QCounters* cnt_out;
-  QCounters* cnt_reset;
-  QCounters* cnt_total; // n_order running total and the overflow flag
-};
-
-__global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    QCounters z{};
-    z.far_min = DIST_INF;
-    *a.cnt_reset = z;
-  }
-  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
-  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
-  const uint32_t nwaves = gridDim.x * Q_WAVES;
-  uint32_t ovf = 0;
-  for (uint32_t base = gwave * 4; base < a.nin; base += nwaves * 4) {
-    uint32_t it = base + grp;
-    bool act = it < a.nin;
-    Item item = act ? a.qin[it] : Item{0, 0, 0};
-    Slab s = slab_of(a.st.fp, item.desc);
-    uint32_t b0 = item.tile * a.T;
-    uint32_t nbk = act && s.nb > b0 ? min(a.T, s.nb - b0) : 0;
-    unsigned long long su = act ? a.sigma[item.v] : 0;
-    uint32_t maxnb = wave_max_u32(nbk);
-    for (uint32_t i = 0; i < maxnb; i++) {
-      bool found = false;
-      uint32_t y = 0;
-      if (i < nbk) {
-        uint32_t* bp = bucket_ptr(s, b0 + i);
-        uint32_t d = bp[j];
-        if (d != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), a.e)) {
-          int32_t lv = a.level[d];
-          if (lv < 0) {
-            lv = atomicCAS(&a.level[d], -1, a.next_level);
-            if (lv == -1) {
-              found = true;
-              y = d;
-              lv = a.next_level;
-            }
-          }
-          if (lv == a.next_level) {
-            unsigned long long old = atomicAdd(&a.sigma[d], su);
-            if (old + su > 0x7FFFFFFFFFFFFFFFull || old + su < old) ovf = 1;
-          }
-        }
-      }
-      uint64_t ydesc = found ? a.st.fdesc[y] : 0;
-      push_items(found, y, ydesc, a.T, a.qout, &a.cnt_out->n_items);
-      uint32_t opos = wave_reserve(&a.cnt_total->n_order, found ? 1u : 0u);
-      if (found) a.order[opos] = y;
-      count_verts(found, 0, a.cnt_out);
-    }
-  }
-  if (ovf) atomicOr(&a.cnt_total->overflow, 1u);
-}
-
-// One wave per vertex of level L: delta[v] = sum over visible arcs v->w
-// with level[w] = L+1 of sigma[v]/sigma[w] * (1 + delta[w]); lane l reads
-// slot l%16 of bucket l/16 of each group of four buckets; the 64 partial
-// sums combine by a fixed butterfly, so the result is deterministic.
-__global__ __launch_bounds__(Q_THREADS) void k_bc_bwd(Store st, uint32_t e, const uint32_t* verts, uint32_t nv,
-                                                      uint32_t src, const int32_t* level, int32_t L,
-                                                      const unsigned long long* sigma, double* delta,
-                                                      double* bc) {
-  const uint32_t lane = lane_id();
-  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
-  const uint32_t nwaves = gridDim.x * Q_WAVES;
-  for (uint32_t k = gwave; k < nv; k += nwaves) {
-    uint32_t v = verts[k];
-    Slab s = slab_of(st.fp, st.fdesc[v]);
-    double sv = (double)sigma[v];
-    double acc = 0.0;
-    for (uint32_t b = lane >> 4; b < s.nb; b += 4) {
-      uint32_t* bp = bucket_ptr(s, b);
-      uint32_t j = lane & 15;
-      uint32_t w = bp[j];
-      if (w != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), e) && level[w] == L + 1)
-        acc += sv / (double)sigma[w] * (1.0 + delta[w]);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) {
-      delta[v] = acc;
-      if (v != src) bc[v] += acc;
-    }
-  }
-}
-
 dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, double* bc, hipStream_t s,
                  QueryScratch& q) {
+  const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, false, true);
   if (he != hipSuccess) return hip_fail(g, he, "bc scratch");
   const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
@@ -632,18 +349,22 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
     int lvl = 0;
     while (true) {
       int cur = lvl & 1, nxt = cur ^ 1;
-      BcFwdArgs a{g->st, e, qin, n_items, qout, order, level, sigma, lvl + 1, T, cnt + nxt, cnt + cur, tot};
-      if (n_items) k_bc_fwd<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a);
-      else fill<unsigned long long>(reinterpret_cast<unsigned long long*>(cnt + nxt), sizeof(QCounters) / 8, 0ull, s);
+      BcFwdArgs a{g->st, e, fast, qin, qout, order, level, sigma, lvl + 1, T, cnt + nxt, tot};
+      if (n_items) {
+        ProfScope ps(g, KID_BC_FWD, s);
+        k_bc_fwd<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+      } else {
+        fill<unsigned long long>(reinterpret_cast<unsigned long long*>(cnt + nxt), sizeof(QCounters) / 8, 0ull, s);
+      }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc fwd launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bc fwd");
+      prof_arcs(g, KID_BC_FWD, hc.arcs);
       if (hc.n_verts == 0) break;
       off.push_back(off.back() + hc.n_verts);
       n_items = hc.n_items;
       std::swap(qin, qout);
       lvl++;
     }
-    // overflow flag of the whole forward pass
     {
       QCounters ht;
       (void)hipMemcpyAsync(q.host_counters, tot, sizeof(QCounters), hipMemcpyDeviceToHost, s);
@@ -656,8 +377,9 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
     }
     for (int L = (int)off.size() - 2; L >= 0; L--) {
       uint32_t nv = off[L + 1] - off[L];
-      k_bc_bwd<<<grid_for(nv, Q_WAVES), Q_THREADS, 0, s>>>(g->st, e, order + off[L], nv, src, level, L, sigma,
-                                                           delta, bc);
+      ProfScope ps(g, KID_BC_BWD, s);
+      k_bc_bwd<<<grid_for(nv, Q_WAVES), Q_THREADS, 0, s>>>(g->st, e, fast, order + off[L], nv, src, level, L,
+                                                           sigma, delta, bc);
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc bwd launch");
   }
@@ -692,7 +414,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, uin
 dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hipStream_t s) {
   hipError_t he = ensure_query_scratch(g, g->qs, false, false);
   if (he != hipSuccess) return hip_fail(g, he, "stats scratch");
-  unsigned long long* tot = reinterpret_cast<unsigned long long*>(g->qs.counters.as<QCounters>());
+  unsigned long long* tot = reinterpret_cast<unsigned long long*>(g->qs.counters.as<QCounters>() + 3);
   fill<unsigned long long>(tot, 1, 0ull, s);
   k_degrees<<<grid_for(g->cfg.v_capacity, Q_WAVES, 8192), Q_THREADS, 0, s>>>(g->st, e, deg, tot);
   if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "stats launch");

@@ -281,11 +281,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint3
     }
     __syncthreads();
     uint64_t off = s_off;
-    uint32_t* nbase = p.base + off * p.words;
-    for (uint64_t t = threadIdx.x; t < (uint64_t)nb2 * p.words; t += UPD_THREADS) nbase[t] = 0xFFFFFFFFu;
+    Slab ns = slab_at(p, off, nb2);
+    for (uint64_t t = threadIdx.x; t < (uint64_t)nb2 * p.words; t += UPD_THREADS) ns.base[t] = 0xFFFFFFFFu;
+    clear_summaries(ns.sum, nb2, threadIdx.x, UPD_THREADS);
     __threadfence();
     __syncthreads();
-    Slab ns{nbase, nb2, p.words};
     Slab os = slab_of(p, desca[x]);
     uint32_t kept = 0;
     for (uint32_t t = threadIdx.x; t < os.nb * BSLOTS; t += UPD_THREADS) {
@@ -295,9 +295,10 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint3
       if (d == EMPTY) continue;
       uint64_t stamp = *slot_stamp(bp, j, os.words);
       if ((uint32_t)(stamp >> 32) <= floor_e) continue;
-      SlotRef r = claim_slot(ns, d);
+      SlotRef r = claim_slot(ns, d, (uint32_t)stamp);
       if (fwd) *slot_w(r.bp, r.j) = *slot_w(bp, j);
       *slot_stamp(r.bp, r.j, ns.words) = stamp;
+      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j);
       kept++;
     }
     if (kept) atomicAdd(&s_kept, kept);
@@ -317,7 +318,9 @@ __device__ inline bool tombstone_in(const Pool& p, uint64_t desc, uint32_t key, 
   Slab s = slab_of(p, desc);
   SlotRef r = find_current(s, key);
   if (!r.bp) return false;
-  return atomicCAS(slot_death(r.bp, r.j, s.words), INF_EPOCH, E) == INF_EPOCH;
+  if (atomicCAS(slot_death(r.bp, r.j, s.words), INF_EPOCH, E) != INF_EPOCH) return false;
+  mark_tomb(s, r.b, r.j);
+  return true;
 }
 
 // One workgroup per cleared vertex.  arcs_delta counts forward-pool slots
@@ -336,6 +339,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
       uint32_t d = ld_relaxed(slot_dst(bp, j));
       if (d == EMPTY) continue;
       if (atomicCAS(slot_death(bp, j, fs.words), INF_EPOCH, E) != INF_EPOCH) continue;
+      mark_tomb(fs, t / BSLOTS, j);
       dropped++;
       if (!st.undirected) tombstone_in(st.rp, st.rdesc[d], x, E);
       else if (d != x && tombstone_in(st.fp, st.fdesc[d], x, E)) dropped++;
@@ -348,6 +352,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
         uint32_t sv = ld_relaxed(slot_dst(bp, j));
         if (sv == EMPTY) continue;
         if (atomicCAS(slot_death(bp, j, rs.words), INF_EPOCH, E) != INF_EPOCH) continue;
+        mark_tomb(rs, t / BSLOTS, j);
         if (tombstone_in(st.fp, st.fdesc[sv], x, E)) dropped++;
       }
     }
@@ -358,7 +363,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
 
 __device__ inline void insert_in(const Pool& p, uint64_t desc, uint32_t key, int32_t w, bool has_w, uint32_t E) {
   Slab s = slab_of(p, desc);
-  SlotRef r = claim_slot(s, key);
+  SlotRef r = claim_slot(s, key, E);
   if (!r.bp) return;   // unreachable: growth guarantees a free slot
   if (has_w) *slot_w(r.bp, r.j) = (uint32_t)w;
   *slot_stamp(r.bp, r.j, s.words) = (uint64_t)E | ((uint64_t)INF_EPOCH << 32);
@@ -471,8 +476,8 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
                                             g->insr.as<uint32_t>(), c);
   k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS / 64, 4096), UPD_THREADS, 0, s>>>(
       st, touch_f, touch_r, plan, plan_ins, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
-  k_grow_exec<<<blocks_for(3ull * n, 1, 2048), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, plan, plan_ins, fl, c);
-  k_clear<<<blocks_for(n, 1, 2048), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
+  k_grow_exec<<<blocks_for(3ull * n, 1, 8192), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, plan, plan_ins, fl, c);
+  k_clear<<<blocks_for(n, 1, 8192), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
   k_commit_edge<<<nb, UPD_THREADS, 0, s>>>(keys, n, L, st, u.recflags.as<uint8_t>(), u.recw.as<int32_t>(), E, c);
   k_commit_vertex<<<blocks_for(n, UPD_THREADS, 1024), UPD_THREADS, 0, s>>>(st, vchange, c);
   hipError_t e = hipGetLastError();
@@ -510,7 +515,10 @@ dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* d
   uint8_t* res = dres ? dres : g->us.results.as<uint8_t>();
   UpdCounters hc{};
   for (int attempt = 0; attempt < 8; attempt++) {
-    e = run_pipeline(g, dops, (uint32_t)n, res, s, &hc);
+    {
+      ProfScope ps(g, KID_UPDATE, s);
+      e = run_pipeline(g, dops, (uint32_t)n, res, s, &hc);
+    }
     if (e != hipSuccess) {
       g->err = std::string("update pipeline: ") + hipGetErrorString(e);
       return DG_E_HIP;

@@ -84,6 +84,12 @@ _sig("dg_set_tuning", _i32, _P, ctypes.POINTER(Tuning))
 _sig("dg_autotune", _i32, _P, _u32, ctypes.POINTER(Tuning), _P)
 _sig("dg_stats", _i32, _P, _u32, ctypes.POINTER(_u64), ctypes.POINTER(_u64), _P)
 _sig("dg_out_degrees", _i32, _P, _u32, _P, _P)
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", _u64), ("total_ms", ctypes.c_double), ("arcs", _u64)]
+
+
+_sig("dg_profile_enable", _i32, _P, ctypes.c_int)
+_sig("dg_profile_read", _i32, _P, _P, _u32, ctypes.POINTER(_u32), ctypes.c_int)
 _sig("dg_server_start", _i32, _P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P))
 _sig("dg_server_stop", _i32, _P)
 _sig("dg_server_submit_update", _i32, _P, _P, _u64, ctypes.POINTER(_u64))
@@ -261,6 +267,22 @@ class Graph:
     def out_degrees(self, epoch=EPOCH_LATEST) -> torch.Tensor:
         out = torch.empty(self.n, dtype=torch.int32, device="cuda")
         self._check(lib.dg_out_degrees(self.h, epoch, _ptr(out), _stream()))
+        return out
+
+    def profile(self, on: bool):
+        self._check(lib.dg_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{family: {"launches", "total_ms", "arcs"}} for kernel families with launches."""
+        arr = (KernelStat * 16)()
+        n = _u32()
+        self._check(lib.dg_profile_read(self.h, arr, 16, ctypes.byref(n), 1 if reset else 0))
+        out = {}
+        for i in range(n.value):
+            k = arr[i]
+            if k.launches:
+                out[k.name.decode()] = {"launches": int(k.launches), "total_ms": float(k.total_ms),
+                                        "arcs": int(k.arcs)}
         return out
 
     def get_tuning(self) -> dict:
