@@ -150,7 +150,7 @@ typedef struct {
   uint32_t tile_buckets;   /* buckets per frontier work item (1..64, power of 2) */
   uint32_t sssp_delta;     /* delta-stepping bucket width */
   uint32_t alpha, beta;    /* direction-switch thresholds of the BFS */
-  uint32_t batch_groups;   /* workgroups per query in the persistent launch */
+  uint32_t batch_groups;   /* workgroups per query team in the persistent launch; 0 = automatic */
 } dg_tuning;
 dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t);
 dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t);

@@ -1,17 +1,575 @@
-// Persistent multi-query executor (filled in below the plain path).
+// Persistent multi-query engine: many BFS / SSSP / BC queries, on any mix
+// of retained epochs, in one launch.
+//
+// The grid holds only as many workgroups as can be resident at once (from
+// the occupancy API), split into teams of S workgroups.  A team takes the
+// next query from a device counter, runs it level by level with the steps
+// of frontier.h over its own scratch, separating levels with a team barrier
+// (arrival counter + generation word in global memory, an acquire fence
+// after it so no workgroup reads stale lines of another's writes), and
+// takes the next query when done.  Each query terminates on its own; no
+// barrier spans the grid.  Every spin loop is bounded: a workgroup that
+// waits too long sets an abort flag that releases every other waiter, so
+// the launch always drains.  Only one engine launch runs on a device at a
+// time (teams spin on each other, so two engines could starve each other
+// of resident workgroups).
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
 #include "dg_host.h"
+#include "frontier.h"
 
 namespace dg {
-dg_status query_batch_dev(dg_graph* g, const dg_query*, uint32_t, dg_status*, hipStream_t) {
-  g->err = "query batches are not built yet";
-  return DG_E_UNIMPLEMENTED;
+
+constexpr uint64_t SPIN_LIMIT = 1ull << 26;
+
+struct TeamSync {
+  uint32_t count, gen, q, pad[13];
+};
+
+struct Ctrl {
+  uint32_t next;
+  uint32_t abort;
+  uint32_t pad[14];
+};
+
+struct QDesc {
+  uint32_t kind, src, epoch, k;
+  const uint32_t* srcs;   // device copy of BC sources
+  void* out;
+};
+
+// Scratch of one team (device pointers into one allocation).
+struct TeamScratch {
+  Item* qa;
+  Item* qb;
+  Item* qbig;
+  uint32_t* bm[3];
+  QCounters* cnt;         // [0..2] rotating level counters, [3] BC totals
+  uint32_t* fa;
+  uint32_t* fb;
+  uint32_t* stamp;
+  uint32_t* infar;
+  unsigned long long* sigma;
+  double* delta;
+  int32_t* level;
+  uint32_t* off;          // BC: start of each level in the discovery order
+  TeamSync* sync;
+};
+
+struct BatchArgs {
+  Store st;
+  int fast;
+  uint32_t T;
+  int32_t delta;
+  uint32_t alpha, beta;
+  const QDesc* q;
+  const uint32_t* qidx;   // indices of this launch's queries (one kind)
+  uint32_t nq;
+  int32_t* status;        // per query
+  const uint64_t* arcs;   // visible arcs per epoch
+  const uint64_t* live;   // live vertices per epoch
+  const TeamScratch* teams;
+  uint32_t n_teams, team_size;
+  Ctrl* ctrl;
+};
+
+__device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctrl* ctrl, Shared& sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ab = 0;
+    if (S > 1) {
+      __threadfence();
+      uint32_t my = gen;
+      if (atomicAdd(&ts->count, 1u) == S - 1) {
+        atomicExch(&ts->count, 0u);
+        __threadfence();
+        atomicAdd(&ts->gen, 1u);
+      } else {
+        uint64_t spins = 0;
+        while (ld_relaxed(&ts->gen) == my) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > SPIN_LIMIT || ld_relaxed(&ctrl->abort)) {
+            atomicExch(&ctrl->abort, 1u);
+            ab = 1;
+            break;
+          }
+        }
+      }
+      gen = my + 1;
+    }
+    if (ld_relaxed(&ctrl->abort)) ab = 1;
+    sh.flag = ab;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return sh.flag == 0;
 }
-void free_batch_state(dg_graph*) {}
+
+// Rotating bitmap i (selected without indexing a register array).
+__device__ inline uint32_t* bm_at(const TeamScratch& ts, uint32_t i) {
+  return i == 0 ? ts.bm[0] : (i == 1 ? ts.bm[1] : ts.bm[2]);
+}
+
+template <class T>
+__device__ inline void team_fill(T* p, uint64_t n, T v, uint32_t w, uint32_t S) {
+  for (uint64_t i = (uint64_t)w * Q_THREADS + threadIdx.x; i < n; i += (uint64_t)S * Q_THREADS) p[i] = v;
+}
+
+__device__ inline QCounters read_cnt(const QCounters* c) {
+  QCounters r;
+  r.n_items = ld_relaxed(&c->n_items);
+  r.n_verts = ld_relaxed(&c->n_verts);
+  r.m_next = ld_relaxed(&c->m_next);
+  r.n_far = ld_relaxed(&c->n_far);
+  r.far_min = ld_relaxed(&c->far_min);
+  r.overflow = ld_relaxed(&c->overflow);
+  r.n_order = ld_relaxed(&c->n_order);
+  r.n_big = ld_relaxed(&c->n_big);
+  return r;
+}
+
+// Worker 0 of the team writes the seed frontier of src into q and counters
+// slot 0 (the caller has set dist/level[src] and cleared the other slots).
+__device__ inline void team_seed(const Store& st, uint32_t src, Item* q, QCounters* c0, uint32_t T, uint32_t w) {
+  if (w != 0 || threadIdx.x != 0) return;
+  uint64_t desc = st.fdesc[src];
+  TileShape ts{0, T};
+  uint32_t k = ts.tiles(desc);
+  for (uint32_t t = 0; t < k; t++) q[t] = Item{desc, src, t};
+  c0->n_items = k;
+  c0->n_verts = 1;
+  c0->m_next = st.fused[src];
+}
+
+#define BARRIER()                                          \
+  do {                                                     \
+    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh)) return false; \
+  } while (0)
+
+__device__ inline bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+                        uint32_t& gen, Shared& sh) {
+  const uint32_t V = a.st.V;
+  const uint64_t bmw = (V + 31) / 32 + 1;
+  int32_t* dist = static_cast<int32_t*>(qd.out);
+  team_fill<int32_t>(dist, V, -1, w, S);
+  team_fill<uint32_t>(ts.bm[0], bmw, 0u, w, S);
+  team_fill<uint32_t>(ts.bm[1], bmw, 0u, w, S);
+  if (w == 0 && threadIdx.x == 0)
+    for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
+  BARRIER();
+  if (w == 0 && threadIdx.x == 0) {
+    dist[qd.src] = 0;
+    ts.bm[0][qd.src >> 5] |= 1u << (qd.src & 31);
+  }
+  team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
+  BARRIER();
+  int64_t m_u = (int64_t)a.arcs[qd.epoch];
+  const uint64_t n_live = a.live[qd.epoch] ? a.live[qd.epoch] : 1;
+  bool bu = false;
+  const Item* qin = ts.qa;
+  Item* qout = ts.qb;
+  for (uint32_t level = 0;; level++) {
+    QCounters c = read_cnt(&ts.cnt[level % 3]);
+    if (c.n_verts == 0) break;
+    if (!bu && (int64_t)c.m_next * (int64_t)a.alpha > m_u) bu = true;
+    else if (bu && (uint64_t)c.n_verts * a.beta < n_live) bu = false;
+    m_u -= (int64_t)c.m_next;
+    QCounters* cout = &ts.cnt[(level + 1) % 3];
+    uint32_t* bnext = bm_at(ts, (level + 1) % 3);
+    team_fill<uint32_t>(bm_at(ts, (level + 2) % 3), bmw, 0u, w, S);
+    if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(level + 2) % 3]);
+    LevelArgs la{a.st, qd.epoch, a.fast, qin, qout, ts.qbig, bm_at(ts, level % 3), bnext, dist,
+                 (int32_t)level + 1, a.T, cout};
+    if (bu) {
+      bu_step(la, w, S, sh);
+      BARRIER();
+      bu_big_step(la, ld_relaxed(&cout->n_big), w, S, sh);
+    } else {
+      td_step(la, c.n_items, w, S, sh);
+    }
+    BARRIER();
+    const Item* t = qin;
+    qin = qout;
+    qout = const_cast<Item*>(t);
+  }
+  return true;
+}
+
+__device__ inline bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+                         uint32_t& gen, Shared& sh) {
+  const uint32_t V = a.st.V;
+  int32_t* dist = static_cast<int32_t*>(qd.out);
+  team_fill<int32_t>(dist, V, DIST_INF, w, S);
+  team_fill<uint32_t>(ts.stamp, V, 0u, w, S);
+  team_fill<uint32_t>(ts.infar, V, 0u, w, S);
+  if (w == 0 && threadIdx.x == 0)
+    for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
+  BARRIER();
+  if (w == 0 && threadIdx.x == 0) dist[qd.src] = 0;
+  team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
+  BARRIER();
+  Item* qin = ts.qa;
+  Item* qout = ts.qb;
+  uint32_t* fin = ts.fa;
+  uint32_t* fout = ts.fb;
+  uint32_t n_near = ld_relaxed(&ts.cnt[0].n_items), n_far = 0;
+  int32_t thr = a.delta;
+  uint32_t it = 1;
+  uint32_t slot = 0;   // counters slot holding the last pass's results
+  for (;;) {
+    if (n_near > 0) {
+      uint32_t nx = (slot + 1) % 3;
+      if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
+      RelaxArgs ra{a.st, qd.epoch, a.fast, qin, qout, fin + n_far, dist, ts.stamp, ts.infar, thr, it, a.T,
+                   &ts.cnt[nx]};
+      relax_step(ra, n_near, w, S, sh);
+      BARRIER();
+      QCounters c = read_cnt(&ts.cnt[nx]);
+      n_near = c.n_items;
+      n_far += c.n_far;
+      Item* t = qin;
+      qin = qout;
+      qout = t;
+      it++;
+      slot = nx;
+      continue;
+    }
+    if (n_far == 0) break;
+    int32_t far_min = DIST_INF;
+    do {
+      thr = far_min == DIST_INF ? thr + a.delta
+                                : (int32_t)min((int64_t)DIST_INF, ((int64_t)far_min / a.delta + 1) * a.delta);
+      uint32_t nx = (slot + 1) % 3;
+      if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
+      SplitArgs sa{a.st, fin, fout, qin, dist, ts.stamp, ts.infar, thr, it, a.T, &ts.cnt[nx]};
+      split_step(sa, n_far, w, S, sh);
+      BARRIER();
+      QCounters c = read_cnt(&ts.cnt[nx]);
+      uint32_t* t = fin;
+      fin = fout;
+      fout = t;
+      n_far = c.n_far;
+      n_near = c.n_items;
+      far_min = c.far_min;
+      slot = nx;
+    } while (n_near == 0 && n_far > 0);
+    it++;
+  }
+  for (uint64_t i = (uint64_t)w * Q_THREADS + threadIdx.x; i < V; i += (uint64_t)S * Q_THREADS)
+    if (dist[i] == DIST_INF) dist[i] = -1;
+  return true;
+}
+
+__device__ inline bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+                       uint32_t& gen, Shared& sh, int32_t* status) {
+  const uint32_t V = a.st.V;
+  double* bc = static_cast<double*>(qd.out);
+  team_fill<double>(bc, V, 0.0, w, S);
+  for (uint32_t si = 0; si < qd.k; si++) {
+    const uint32_t src = qd.srcs[si];
+    team_fill<int32_t>(ts.level, V, -1, w, S);
+    team_fill<unsigned long long>(ts.sigma, V, 0ull, w, S);
+    if (w == 0 && threadIdx.x == 0)
+      for (int i = 0; i < 4; i++) zero_counters(&ts.cnt[i]);
+    BARRIER();
+    if (w == 0 && threadIdx.x == 0) {
+      ts.level[src] = 0;
+      ts.sigma[src] = 1ull;
+      ts.fa[0] = src;
+      ts.cnt[3].n_order = 1;
+      ts.off[0] = 0;
+      ts.off[1] = 1;
+    }
+    team_seed(a.st, src, ts.qa, &ts.cnt[0], a.T, w);
+    BARRIER();
+    const Item* qin = ts.qa;
+    Item* qout = ts.qb;
+    uint32_t nlev = 1;   // levels discovered so far (level 0 = src)
+    for (uint32_t lvl = 0;; lvl++) {
+      QCounters c = read_cnt(&ts.cnt[lvl % 3]);
+      if (lvl > 0 && c.n_verts == 0) break;
+      QCounters* cout = &ts.cnt[(lvl + 1) % 3];
+      if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(lvl + 2) % 3]);
+      BcFwdArgs fa{a.st, qd.epoch, a.fast, qin, qout, ts.fa, ts.level, ts.sigma, (int32_t)lvl + 1, a.T, cout,
+                   &ts.cnt[3]};
+      bcfwd_step(fa, c.n_items, w, S, sh);
+      BARRIER();
+      uint32_t found = ld_relaxed(&cout->n_verts);
+      if (found == 0) break;
+      if (w == 0 && threadIdx.x == 0) ts.off[nlev + 1] = ts.off[nlev] + found;
+      nlev++;
+      const Item* t = qin;
+      qin = qout;
+      qout = const_cast<Item*>(t);
+    }
+    BARRIER();
+    if (ld_relaxed(&ts.cnt[3].overflow)) {
+      if (w == 0 && threadIdx.x == 0) *status = DG_E_OVERFLOW;
+      return true;
+    }
+    for (int L = (int)nlev - 1; L >= 0; L--) {
+      uint32_t o0 = ld_relaxed(&ts.off[L]), o1 = ld_relaxed(&ts.off[L + 1]);
+      bcbwd_step(a.st, qd.epoch, a.fast != 0, ts.fa + o0, o1 - o0, src, ts.level, L, ts.sigma, ts.delta, bc, w,
+                 S);
+      BARRIER();
+    }
+  }
+  return true;
+}
+
+// One launch serves the queries of one kind, so each kind's kernel gets its
+// own register allocation.
+template <int KIND>
+__global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
+  __shared__ Shared sh;
+  stages_init(sh);
+  const uint32_t S = a.team_size;
+  const uint32_t t = blockIdx.x / S, w = blockIdx.x % S;
+  if (t >= a.n_teams) return;
+  const TeamScratch ts = a.teams[t];
+  uint32_t gen = 0;
+  for (;;) {
+    if (w == 0 && threadIdx.x == 0) ts.sync->q = atomicAdd(&a.ctrl->next, 1u);
+    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh)) return;
+    const uint32_t k = ld_relaxed(&ts.sync->q);
+    if (k >= a.nq) return;
+    const uint32_t qi = a.qidx[k];
+    const QDesc qd = a.q[qi];
+    bool ok = true;
+    if (a.status[qi] == DG_OK) {
+      if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh);
+      else if (KIND == DG_Q_SSSP) ok = run_sssp(a, qd, ts, w, S, gen, sh);
+      else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
+    }
+    if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh)) return;
+  }
+}
+
+// ------------------------------------------------------------ host side
+
+struct BatchState {
+  DevBuf scratch, teams, qdesc, qidx, srcs, status, arcs, live, ctrl;
+  int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
+};
+
+static std::mutex g_engine_mu;   // one engine launch per process at a time
+static std::map<const dg_graph*, BatchState*> g_states;
+static std::mutex g_states_mu;
+
+static BatchState* state_of(dg_graph* g) {
+  std::lock_guard<std::mutex> lk(g_states_mu);
+  auto& p = g_states[g];
+  if (!p) p = new BatchState();
+  return p;
+}
+
+void free_batch_state(dg_graph* g) {
+  std::lock_guard<std::mutex> lk(g_states_mu);
+  auto it = g_states.find(g);
+  if (it == g_states.end()) return;
+  BatchState* b = it->second;
+  for (DevBuf* d : {&b->scratch, &b->teams, &b->qdesc, &b->qidx, &b->srcs, &b->status, &b->arcs, &b->live, &b->ctrl})
+    release(*d);
+  delete b;
+  g_states.erase(it);
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Bytes of one team's scratch and, if base is set, the pointers into it.
+static uint64_t team_layout(const dg_graph* g, char* base, TeamScratch* ts) {
+  const uint64_t V = g->cfg.v_capacity;
+  const uint64_t items = V + g->st.fp.cap / std::max<uint32_t>(1, g->tune.tile_buckets) + 1024;
+  const uint64_t big = V + std::max(g->st.fp.cap, g->st.rp.cap) / BU_CHUNK + 1024;
+  const uint64_t bmw = (V + 31) / 32 + 1;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o += align256(bytes);
+    return base ? base + at : nullptr;
+  };
+  char* p;
+  p = take(items * sizeof(Item)); if (ts) ts->qa = reinterpret_cast<Item*>(p);
+  p = take(items * sizeof(Item)); if (ts) ts->qb = reinterpret_cast<Item*>(p);
+  p = take(big * sizeof(Item)); if (ts) ts->qbig = reinterpret_cast<Item*>(p);
+  for (int i = 0; i < 3; i++) {
+    p = take(bmw * 4);
+    if (ts) ts->bm[i] = reinterpret_cast<uint32_t*>(p);
+  }
+  p = take(4 * sizeof(QCounters)); if (ts) ts->cnt = reinterpret_cast<QCounters*>(p);
+  p = take(V * 4 + 64); if (ts) ts->fa = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (ts) ts->fb = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (ts) ts->stamp = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (ts) ts->infar = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 8 + 64); if (ts) ts->sigma = reinterpret_cast<unsigned long long*>(p);
+  p = take(V * 8 + 64); if (ts) ts->delta = reinterpret_cast<double*>(p);
+  p = take(V * 4 + 64); if (ts) ts->level = reinterpret_cast<int32_t*>(p);
+  p = take((V + 2) * 4 + 64); if (ts) ts->off = reinterpret_cast<uint32_t*>(p);
+  p = take(sizeof(TeamSync)); if (ts) ts->sync = reinterpret_cast<TeamSync*>(p);
+  return o;
+}
+
+bool alive_at(const dg_graph* g, uint32_t v, uint32_t e);
+
+static dg_status bfail(dg_graph* g, dg_status st, const std::string& m) {
+  g->err = m;
+  return st;
+}
+
+static const void* kernel_of(int kind) {
+  if (kind == DG_Q_BFS) return reinterpret_cast<const void*>(&k_team<DG_Q_BFS>);
+  if (kind == DG_Q_SSSP) return reinterpret_cast<const void*>(&k_team<DG_Q_SSSP>);
+  return reinterpret_cast<const void*>(&k_team<DG_Q_BC>);
+}
+
+dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, hipStream_t s) {
+  if (nq == 0) return DG_OK;
+  if (!q || !per_query) return bfail(g, DG_E_INVALID_ARG, "null query array or status array");
+  BatchState* bs = state_of(g);
+  hipError_t e;
+  // host-side validation: kinds, outputs, epochs, sources, BC source sets
+  std::vector<QDesc> qd(nq);
+  std::vector<int32_t> st(nq, DG_OK);
+  std::vector<uint32_t> all_srcs;
+  std::vector<uint64_t> src_off(nq, 0);
+  std::vector<uint32_t> by_kind[3];
+  const uint32_t fl = gc_floor(g);
+  for (uint32_t i = 0; i < nq; i++) {
+    const dg_query& x = q[i];
+    uint32_t ep = x.epoch == DG_EPOCH_LATEST ? g->epoch : x.epoch;
+    qd[i] = QDesc{x.kind, x.src, ep, 0, nullptr, x.out};
+    if (x.kind > DG_Q_BC || !x.out || !is_device_ptr(x.out)) { st[i] = DG_E_INVALID_ARG; continue; }
+    if (ep > g->epoch || ep < fl) { st[i] = DG_E_EPOCH_RETIRED; continue; }
+    if (x.kind == DG_Q_BC) {
+      if (x.k && !x.srcs) { st[i] = DG_E_INVALID_ARG; continue; }
+      std::vector<uint32_t> S(x.srcs, x.srcs + x.k);
+      for (uint32_t v : S) {
+        if (v >= g->cfg.v_capacity) { st[i] = DG_E_VERTEX_RANGE; break; }
+        if (!alive_at(g, v, ep)) { st[i] = DG_E_SOURCE_ABSENT; break; }
+      }
+      std::vector<uint32_t> sorted = S;
+      std::sort(sorted.begin(), sorted.end());
+      if (st[i] == DG_OK && std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        st[i] = DG_E_INVALID_ARG;
+      src_off[i] = all_srcs.size();
+      all_srcs.insert(all_srcs.end(), S.begin(), S.end());
+      qd[i].k = x.k;
+    } else {
+      if (x.src >= g->cfg.v_capacity) st[i] = DG_E_VERTEX_RANGE;
+      else if (!alive_at(g, x.src, ep)) st[i] = DG_E_SOURCE_ABSENT;
+    }
+    if (st[i] == DG_OK) by_kind[x.kind].push_back(i);
+  }
+  // resident workgroups per kind's kernel
+  for (int k = 0; k < 3; k++) {
+    if (bs->grid_cap[k] || by_kind[k].empty()) continue;
+    int per_cu = 0, cus = 0, dev = 0;
+    hipGetDevice(&dev);
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_of(k), Q_THREADS, 0)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    bs->grid_cap[k] = std::max(1, per_cu * cus);
+  }
+  // teams: size from the tuning (0 = automatic), count bounded by memory
+  const uint64_t per_team = team_layout(g, nullptr, nullptr);
+  const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
+  const uint32_t max_teams = (uint32_t)std::max<uint64_t>(1, budget / per_team);
+  uint32_t S_of[3] = {1, 1, 1}, T_of[3] = {0, 0, 0}, most = 1;
+  for (int k = 0; k < 3; k++) {
+    uint32_t n = (uint32_t)by_kind[k].size();
+    if (!n) continue;
+    const uint32_t G = (uint32_t)bs->grid_cap[k];
+    uint32_t S = g->tune.batch_groups;
+    if (S == 0 || S > G) S = std::max<uint32_t>(1, G / std::min<uint32_t>(n, max_teams));
+    S_of[k] = S;
+    T_of[k] = std::max<uint32_t>(1, std::min<uint32_t>({G / S, n, max_teams}));
+    most = std::max(most, T_of[k]);
+  }
+  size_t e_cnt = g->arcs_by_epoch.size();
+  if ((e = ensure(bs->scratch, per_team * most)) != hipSuccess)
+    return bfail(g, DG_E_OUT_OF_MEMORY, "batch scratch allocation");
+  std::vector<TeamScratch> tsv(most);
+  for (uint32_t t = 0; t < most; t++) team_layout(g, bs->scratch.as<char>() + per_team * t, &tsv[t]);
+  if ((e = ensure(bs->teams, most * sizeof(TeamScratch))) != hipSuccess ||
+      (e = ensure(bs->qdesc, nq * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nq * 4)) != hipSuccess ||
+      (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
+      (e = ensure(bs->status, nq * 4)) != hipSuccess || (e = ensure(bs->arcs, e_cnt * 8)) != hipSuccess ||
+      (e = ensure(bs->live, e_cnt * 8)) != hipSuccess || (e = ensure(bs->ctrl, 3 * sizeof(Ctrl))) != hipSuccess)
+    return bfail(g, DG_E_OUT_OF_MEMORY, "batch descriptor allocation");
+  for (uint32_t i = 0; i < nq; i++)
+    if (qd[i].kind == DG_Q_BC) qd[i].srcs = bs->srcs.as<uint32_t>() + src_off[i];
+  std::vector<uint32_t> qidx;
+  uint32_t koff[3] = {0, 0, 0};
+  for (int k = 0; k < 3; k++) {
+    koff[k] = (uint32_t)qidx.size();
+    qidx.insert(qidx.end(), by_kind[k].begin(), by_kind[k].end());
+  }
+  Ctrl c0[3] = {};
+  if ((e = hipMemcpyAsync(bs->teams.p, tsv.data(), most * sizeof(TeamScratch), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->qdesc.p, qd.data(), nq * sizeof(QDesc), hipMemcpyHostToDevice, s)) ||
+      (qidx.size() && (e = hipMemcpyAsync(bs->qidx.p, qidx.data(), qidx.size() * 4, hipMemcpyHostToDevice, s))) ||
+      (all_srcs.size() &&
+       (e = hipMemcpyAsync(bs->srcs.p, all_srcs.data(), all_srcs.size() * 4, hipMemcpyHostToDevice, s))) ||
+      (e = hipMemcpyAsync(bs->status.p, st.data(), nq * 4, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->arcs.p, g->arcs_by_epoch.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->live.p, g->live_by_epoch.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->ctrl.p, c0, sizeof(c0), hipMemcpyHostToDevice, s)))
+    return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> lk(g_engine_mu);
+    for (int k = 0; k < 3; k++) {
+      if (by_kind[k].empty()) continue;
+      for (uint32_t t = 0; t < T_of[k]; t++)
+        if ((e = hipMemsetAsync(tsv[t].sync, 0, sizeof(TeamSync), s)) != hipSuccess)
+          return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+      BatchArgs a{g->st,
+                  g->concurrent_writers ? 0 : 1,
+                  g->tune.tile_buckets,
+                  (int32_t)std::max<uint32_t>(1, g->tune.sssp_delta),
+                  g->tune.alpha,
+                  g->tune.beta,
+                  bs->qdesc.as<QDesc>(),
+                  bs->qidx.as<uint32_t>() + koff[k],
+                  (uint32_t)by_kind[k].size(),
+                  bs->status.as<int32_t>(),
+                  bs->arcs.as<uint64_t>(),
+                  bs->live.as<uint64_t>(),
+                  bs->teams.as<TeamScratch>(),
+                  T_of[k],
+                  S_of[k],
+                  bs->ctrl.as<Ctrl>() + k};
+      ProfScope ps(g, KID_BATCH, s);
+      if (k == DG_Q_BFS) k_team<DG_Q_BFS><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
+      else if (k == DG_Q_SSSP) k_team<DG_Q_SSSP><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
+      else k_team<DG_Q_BC><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
+      if ((e = hipGetLastError()) != hipSuccess)
+        return bfail(g, DG_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    Ctrl cres[3];
+    if ((e = hipMemcpyAsync(st.data(), bs->status.p, nq * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(cres, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+    for (int k = 0; k < 3; k++)
+      if (cres[k].abort) return bfail(g, DG_E_HIP, "batch engine: a team barrier timed out");
+  }
+  for (uint32_t i = 0; i < nq; i++) per_query[i] = st[i];
+  return DG_OK;
+}
+
 }  // namespace dg
 
 extern "C" dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
-  return dg::query_batch_dev(g, q, nq, per_query, static_cast<hipStream_t>(stream));
+  std::lock_guard<std::mutex> lk(g->mu);
+  try {
+    return dg::query_batch_dev(g, q, nq, per_query, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    g->err = "unexpected failure in dg_query_batch";
+    return DG_E_HIP;
+  }
 }
 
 extern "C" dg_status dg_autotune(dg_graph* g, uint32_t, dg_tuning*, void*) {

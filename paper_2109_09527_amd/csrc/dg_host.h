@@ -102,7 +102,7 @@ struct Tuning {
   uint32_t tile_buckets = 8;
   uint32_t sssp_delta = 64;
   uint32_t alpha = 14, beta = 24;
-  uint32_t batch_groups = 4;
+  uint32_t batch_groups = 0;   // workgroups per query team; 0 = automatic
 };
 
 }  // namespace dg

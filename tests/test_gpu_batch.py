@@ -1,0 +1,138 @@
+"""The persistent multi-query engine (dg_query_batch) against the plain
+one-query calls and the oracle.
+
+BFS / SSSP outputs must be bit-identical to the plain path and the oracle;
+BC outputs bit-identical to the plain path (same per-vertex reduction
+order) and within 1e-9 relative of the oracle.  Queries mix kinds and
+epochs, include invalid ones, and run under several team sizes.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle  # noqa: E402
+from paper_2109_09527_amd import synth  # noqa: E402
+
+BC_RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_09527_amd import dg as m
+    return m
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def build_history(dg, scale, undirected, n_batches, seed, w_max=60):
+    gr = synth.rmat_graph(scale, 8, w_max, seed=seed, undirected=undirected,
+                          unweighted=undirected)
+    wmax = 1 if undirected else w_max
+    o = Oracle(gr.n, undirected=undirected, w_max=wmax)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=wmax, max_resident_epochs=n_batches + 2)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    epochs = [g.epoch]
+    if undirected:
+        rng = np.random.default_rng(seed)
+        batches = []
+        for b in range(n_batches):
+            pick = rng.choice(gr.m, size=min(500, gr.m), replace=False)
+            batches.append(synth.make_ops(np.full(len(pick), synth.REME), gr.u[pick], gr.v[pick]))
+    else:
+        batches = synth.update_batches(graph=gr, n_batches=n_batches, n_edge_ops=1500, w_max=wmax,
+                                       seed=seed).batches
+    srcs = synth.out_degree_sources(gr, 6, synth.rng_for(seed, 5))
+    answers = {}
+
+    def record(ep):
+        for s in srcs:
+            s = int(s)
+            answers[(ep, "bfs", s)] = o.bfs(s)
+            answers[(ep, "sssp", s)] = o.sssp(s)
+        S = [int(s) for s in srcs[:3] if o.alive(int(s))]
+        answers[(ep, "bc", tuple(S))] = o.bc(S)
+
+    record(g.epoch)
+    for b in batches:
+        o.apply(b)
+        _, ep = g.apply(b)
+        epochs.append(ep)
+        record(ep)
+    return gr, g, epochs, answers
+
+
+def check_batch(dg, g, answers, team_sizes):
+    keys = list(answers.keys())
+    n = g.n
+    for S in team_sizes:
+        g.set_tuning(batch_groups=S)
+        say("batch team size", S, "queries", len(keys) + 3)
+        queries, outs = [], []
+        for (ep, kind, src) in keys:
+            if kind == "bc":
+                out = torch.empty(n, dtype=torch.float64, device="cuda")
+                queries.append((dg.Q_BC, ep, list(src), out))
+            else:
+                out = torch.empty(n, dtype=torch.int32, device="cuda")
+                queries.append((dg.Q_BFS if kind == "bfs" else dg.Q_SSSP, ep, src, out))
+            outs.append(out)
+        # invalid ones: unpublished epoch, out-of-range source, repeated BC source
+        bad = [(dg.Q_BFS, g.epoch + 1, 0, torch.empty(n, dtype=torch.int32, device="cuda")),
+               (dg.Q_SSSP, g.epoch, n + 5, torch.empty(n, dtype=torch.int32, device="cuda")),
+               (dg.Q_BC, g.epoch, [keys[0][2], keys[0][2]], torch.empty(n, dtype=torch.float64, device="cuda"))]
+        st = g.query_batch(queries + bad)
+        torch.cuda.synchronize()
+        assert st[-3] == dg.E_EPOCH_RETIRED
+        assert st[-2] == dg.E_VERTEX_RANGE
+        assert st[-1] == dg.E_INVALID_ARG
+        for i, ((ep, kind, src), out) in enumerate(zip(keys, outs)):
+            rc_o, want = answers[(ep, kind, src)]
+            assert st[i] == rc_o, (kind, ep, src, st[i], rc_o)
+            if rc_o != 0:
+                continue
+            got = out.cpu().numpy()
+            if kind == "bc":
+                plain = g.bc(list(src), ep).cpu().numpy()
+                assert np.array_equal(got, plain), ("bc differs from plain", ep)
+                err = np.abs(got - want)
+                assert not (err > BC_RTOL * np.abs(want)).any(), ("bc vs oracle", ep)
+            else:
+                assert np.array_equal(got, want), (kind, ep, src, S)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_batch_matches_plain_and_oracle(dg, undirected):
+    gr, g, epochs, answers = build_history(dg, 11, undirected, 3, seed=7 + undirected)
+    check_batch(dg, g, answers, [0, 1, 3, 16])
+
+
+def test_batch_many_queries_many_teams(dg):
+    """Scale 13, 96 BFS/SSSP queries over 4 epochs, automatic teams."""
+    gr = synth.rmat_graph(13, 16, 255, seed=11)
+    o = Oracle(gr.n, w_max=255)
+    g = dg.Graph(gr.n, w_max=255, max_resident_epochs=8)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    wl = synth.update_batches(graph=gr, n_batches=3, n_edge_ops=4000, seed=11)
+    srcs = synth.out_degree_sources(gr, 24, synth.rng_for(11, 9))
+    answers = {}
+    for ep_i in range(4):
+        ep = g.epoch
+        for k, s in enumerate(srcs):
+            s = int(s)
+            if k % 2 == 0:
+                answers[(ep, "bfs", s)] = o.bfs(s)
+            else:
+                answers[(ep, "sssp", s)] = o.sssp(s)
+        if ep_i < 3:
+            o.apply(wl.batches[ep_i])
+            g.apply(wl.batches[ep_i])
+    say("batch many queries")
+    check_batch(dg, g, answers, [0, 2])
