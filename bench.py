@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle sample size in steps (0 = skip)")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--batch-queries", type=int, default=128,
+                    help="queries of the batched-vs-plain comparison (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -155,6 +157,10 @@ def main():
                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kp["launches"],
                     "bytes_per_launch": int(bytes_per_launch)}
 
+    batched = None
+    if args.batch_queries > 0:
+        batched = batched_vs_plain(g, wl, epochs, args.batch_queries)
+
     cpu = None
     if args.cpu_steps > 0:
         cpu = cpu_baseline(wl, W, min(args.cpu_steps, K), m_bfs, m_sssp, dist_b, dist_s)
@@ -188,9 +194,75 @@ def main():
         "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3), "arcs": v["arcs"]}
                     for k, v in prof.items()},
         "roofline": roof,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def kernel_roof(prof, name, bytes_per_arc):
+    kp = prof.get(name)
+    if not kp or not kp["launches"] or kp["total_ms"] <= 0:
+        return None
+    achieved = kp["arcs"] * bytes_per_arc / (kp["total_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "avg_launch_us": round(kp["total_ms"] / kp["launches"] * 1e3, 2), "launches": kp["launches"],
+            "bytes_per_launch": int(kp["arcs"] * bytes_per_arc / kp["launches"])}
+
+
+def batched_vs_plain(g, wl, epochs, nq):
+    """nq BFS/SSSP queries (alternating) over the last 8 retained epochs:
+    one dg_query_batch launch versus one plain call per query.  Outputs of
+    the two forms are compared element by element."""
+    import torch
+    from paper_2109_09527_amd import dg
+    n = g.n
+    eps = epochs[-8:]
+    srcs = np.concatenate([wl.bfs_src, wl.sssp_src])
+    qs = [(dg.Q_BFS if i % 2 == 0 else dg.Q_SSSP, eps[i % len(eps)], int(srcs[(i * 7) % len(srcs)]))
+          for i in range(nq)]
+    plain = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
+    batch = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
+    # warm-up of both forms on a few queries
+    g.query_batch([(k, e, s, o) for (k, e, s), o in zip(qs[:8], batch[:8])])
+    for (k, e, s), o in zip(qs[:2], plain[:2]):
+        (g.bfs if k == dg.Q_BFS else g.sssp)(s, e, o)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for (k, e, s), o in zip(qs, plain):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        (g.bfs if k == dg.Q_BFS else g.sssp)(s, e, o)
+        b.record()
+        lat.append((a, b))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_ms = [a.elapsed_time(b) for a, b in lat]
+    g.profile(True)
+    g.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.query_batch([(k, e, s, o) for (k, e, s), o in zip(qs, batch)])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    prof = g.profile_read(reset=True)
+    g.profile(False)
+    same = all(x == 0 for x in st) and all(torch.equal(a, b) for a, b in zip(plain, batch))
+    degs = {e: g.out_degrees(e).to(torch.int64) for e in set(eps)}
+    m = sum(int(degs[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, batch))
+    roof = {k: kernel_roof(prof, f"batch_{k}", BYTES_PER_ARC["sssp_relax" if k == "sssp" else "bfs_top_down"])
+            for k in ("bfs", "sssp")}
+    return {"queries": nq, "epochs": len(set(eps)), "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+            "plain_gteps": round(m / t_plain / 1e9, 4), "batched_gteps": round(m / t_batch / 1e9, 4),
+            "speedup": round(t_plain / t_batch, 2),
+            "plain_latency_ms": {"p50": round(pct(plain_ms, 50), 3), "p99": round(pct(plain_ms, 99), 3)},
+            "batched_latency_ms": {"p50": round(t_batch * 1e3, 3), "p99": round(t_batch * 1e3, 3)},
+            "outputs_equal": same,
+            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3), "arcs": v["arcs"]}
+                        for k, v in prof.items()},
+            "roofline": roof}
 
 
 def cpu_baseline(wl, W, S, m_bfs, m_sssp, dist_b, dist_s):

@@ -142,6 +142,7 @@ static hipError_t realloc_pool(DevBuf& buf, DevBuf& sbuf, Pool& p, uint64_t new_
 // kernel on every stream finishes first: offsets stay valid (the contents
 // are copied to the same offsets), only the base addresses change.
 hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r) {
+  std::lock_guard<std::mutex> lk(g->mu);
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return e;
   unsigned long long cur[2];
@@ -311,7 +312,11 @@ extern "C" {
 
 const char* dg_last_error(const dg_graph* g) { return g ? g->err.c_str() : g_create_err.c_str(); }
 
-dg_epoch dg_latest_epoch(const dg_graph* g) { return g ? g->epoch : 0; }
+dg_epoch dg_latest_epoch(const dg_graph* g) {
+  if (!g) return 0;
+  std::lock_guard<std::mutex> lk(const_cast<dg_graph*>(g)->mu);
+  return g->epoch;
+}
 
 dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   if (!cfg || !out) return fail(nullptr, DG_E_INVALID_ARG, "null argument");
@@ -419,10 +424,10 @@ dg_status dg_apply_batch(dg_graph* g, const dg_op* ops, uint64_t n, uint8_t* res
   hipStream_t s = static_cast<hipStream_t>(stream);
   try {
     if (n == 0) {
-      if (new_epoch) *new_epoch = g->epoch;
+      if (new_epoch) *new_epoch = dg_latest_epoch(g);
       return DG_OK;
     }
-    std::lock_guard<std::mutex> lk(g->mu);
+    std::lock_guard<std::mutex> lk(g->upd_mu);
     hipError_t e = hipSuccess;
     const dg_op* dops = ops;
     if (!is_device_ptr(ops)) {
@@ -443,7 +448,7 @@ dg_status dg_apply_batch(dg_graph* g, const dg_op* ops, uint64_t n, uint8_t* res
           (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(g, DG_E_HIP, std::string("results copy: ") + hipGetErrorString(e));
     }
-    if (new_epoch) *new_epoch = g->epoch;
+    if (new_epoch) *new_epoch = dg_latest_epoch(g);
     return DG_OK;
   } catch (const std::bad_alloc&) {
     return fail(g, DG_E_OUT_OF_MEMORY, "host allocation");
@@ -509,6 +514,7 @@ dg_status dg_snapshot_release(dg_graph* g, dg_epoch e) {
 
 dg_status dg_compact(dg_graph* g, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lku(g->upd_mu);
   std::lock_guard<std::mutex> lk(g->mu);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipDeviceSynchronize() != hipSuccess) return fail(g, DG_E_HIP, "compaction: device sync");
@@ -603,7 +609,8 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
 
 dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
-                                         "sssp_split", "bc_forward", "bc_backward", "query_batch"};
+                                         "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
+                                         "batch_sssp",   "batch_bc"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

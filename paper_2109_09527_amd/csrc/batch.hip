@@ -31,8 +31,17 @@ struct TeamSync {
 struct Ctrl {
   uint32_t next;
   uint32_t abort;
-  uint32_t pad[14];
+  unsigned long long arcs;   // visible arcs examined by the launch
+  uint32_t pad[12];
 };
+
+// Worker 0 adds a finished step's examined-arc count to the launch total.
+__device__ inline void add_step_arcs(Ctrl* c, const QCounters* step, uint32_t w) {
+  if (w == 0 && threadIdx.x == 0) {
+    unsigned long long n = ld_relaxed(&step->arcs);
+    if (n) atomicAdd(&c->arcs, n);
+  }
+}
 
 struct QDesc {
   uint32_t kind, src, epoch, k;
@@ -190,6 +199,7 @@ __device__ inline bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamSc
       td_step(la, c.n_items, w, S, sh);
     }
     BARRIER();
+    add_step_arcs(a.ctrl, cout, w);
     const Item* t = qin;
     qin = qout;
     qout = const_cast<Item*>(t);
@@ -226,6 +236,7 @@ __device__ inline bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamS
                    &ts.cnt[nx]};
       relax_step(ra, n_near, w, S, sh);
       BARRIER();
+      add_step_arcs(a.ctrl, &ts.cnt[nx], w);
       QCounters c = read_cnt(&ts.cnt[nx]);
       n_near = c.n_items;
       n_far += c.n_far;
@@ -296,6 +307,7 @@ __device__ inline bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScr
                    &ts.cnt[3]};
       bcfwd_step(fa, c.n_items, w, S, sh);
       BARRIER();
+      add_step_arcs(a.ctrl, cout, w);
       uint32_t found = ld_relaxed(&cout->n_verts);
       if (found == 0) break;
       if (w == 0 && threadIdx.x == 0) ts.off[nlev + 1] = ts.off[nlev] + found;
@@ -350,6 +362,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
 // ------------------------------------------------------------ host side
 
 struct BatchState {
+  std::mutex mu;                 // one batch at a time per graph (shared buffers)
   DevBuf scratch, teams, qdesc, qidx, srcs, status, arcs, live, ctrl;
   int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
 };
@@ -379,10 +392,10 @@ void free_batch_state(dg_graph* g) {
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Bytes of one team's scratch and, if base is set, the pointers into it.
-static uint64_t team_layout(const dg_graph* g, char* base, TeamScratch* ts) {
-  const uint64_t V = g->cfg.v_capacity;
-  const uint64_t items = V + g->st.fp.cap / std::max<uint32_t>(1, g->tune.tile_buckets) + 1024;
-  const uint64_t big = V + std::max(g->st.fp.cap, g->st.rp.cap) / BU_CHUNK + 1024;
+static uint64_t team_layout(const Store& st, uint32_t T, char* base, TeamScratch* ts) {
+  const uint64_t V = st.V;
+  const uint64_t items = V + st.fp.cap / std::max<uint32_t>(1, T) + 1024;
+  const uint64_t big = V + std::max(st.fp.cap, st.rp.cap) / BU_CHUNK + 1024;
   const uint64_t bmw = (V + 31) / 32 + 1;
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) {
@@ -428,40 +441,73 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   if (nq == 0) return DG_OK;
   if (!q || !per_query) return bfail(g, DG_E_INVALID_ARG, "null query array or status array");
   BatchState* bs = state_of(g);
+  std::lock_guard<std::mutex> blk(bs->mu);
   hipError_t e;
-  // host-side validation: kinds, outputs, epochs, sources, BC source sets
+  // host state is read (and the epochs in use pinned) under the graph
+  // mutex; the launch itself runs without it, beside update batches
+  Store st_;
+  Tuning tune;
+  uint32_t share = 100;
+  std::vector<uint64_t> arcs, live;
+  int fast = 1;
   std::vector<QDesc> qd(nq);
   std::vector<int32_t> st(nq, DG_OK);
   std::vector<uint32_t> all_srcs;
   std::vector<uint64_t> src_off(nq, 0);
   std::vector<uint32_t> by_kind[3];
-  const uint32_t fl = gc_floor(g);
-  for (uint32_t i = 0; i < nq; i++) {
-    const dg_query& x = q[i];
-    uint32_t ep = x.epoch == DG_EPOCH_LATEST ? g->epoch : x.epoch;
-    qd[i] = QDesc{x.kind, x.src, ep, 0, nullptr, x.out};
-    if (x.kind > DG_Q_BC || !x.out || !is_device_ptr(x.out)) { st[i] = DG_E_INVALID_ARG; continue; }
-    if (ep > g->epoch || ep < fl) { st[i] = DG_E_EPOCH_RETIRED; continue; }
-    if (x.kind == DG_Q_BC) {
-      if (x.k && !x.srcs) { st[i] = DG_E_INVALID_ARG; continue; }
-      std::vector<uint32_t> S(x.srcs, x.srcs + x.k);
-      for (uint32_t v : S) {
-        if (v >= g->cfg.v_capacity) { st[i] = DG_E_VERTEX_RANGE; break; }
-        if (!alive_at(g, v, ep)) { st[i] = DG_E_SOURCE_ABSENT; break; }
+  std::vector<uint32_t> pinned;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    st_ = g->st;
+    tune = g->tune;
+    arcs = g->arcs_by_epoch;
+    live = g->live_by_epoch;
+    fast = g->concurrent_writers ? 0 : 1;
+    share = std::max<uint32_t>(1, std::min<uint32_t>(100, g->engine_share_pct));
+    const uint32_t fl = gc_floor(g);
+    for (uint32_t i = 0; i < nq; i++) {
+      const dg_query& x = q[i];
+      uint32_t ep = x.epoch == DG_EPOCH_LATEST ? g->epoch : x.epoch;
+      qd[i] = QDesc{x.kind, x.src, ep, 0, nullptr, x.out};
+      if (x.kind > DG_Q_BC || !x.out || !is_device_ptr(x.out)) { st[i] = DG_E_INVALID_ARG; continue; }
+      if (ep > g->epoch || ep < fl) { st[i] = DG_E_EPOCH_RETIRED; continue; }
+      if (x.kind == DG_Q_BC) {
+        if (x.k && !x.srcs) { st[i] = DG_E_INVALID_ARG; continue; }
+        std::vector<uint32_t> S(x.srcs, x.srcs + x.k);
+        for (uint32_t v : S) {
+          if (v >= g->cfg.v_capacity) { st[i] = DG_E_VERTEX_RANGE; break; }
+          if (!alive_at(g, v, ep)) { st[i] = DG_E_SOURCE_ABSENT; break; }
+        }
+        std::vector<uint32_t> sorted = S;
+        std::sort(sorted.begin(), sorted.end());
+        if (st[i] == DG_OK && std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+          st[i] = DG_E_INVALID_ARG;
+        src_off[i] = all_srcs.size();
+        all_srcs.insert(all_srcs.end(), S.begin(), S.end());
+        qd[i].k = x.k;
+      } else {
+        if (x.src >= g->cfg.v_capacity) st[i] = DG_E_VERTEX_RANGE;
+        else if (!alive_at(g, x.src, ep)) st[i] = DG_E_SOURCE_ABSENT;
       }
-      std::vector<uint32_t> sorted = S;
-      std::sort(sorted.begin(), sorted.end());
-      if (st[i] == DG_OK && std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-        st[i] = DG_E_INVALID_ARG;
-      src_off[i] = all_srcs.size();
-      all_srcs.insert(all_srcs.end(), S.begin(), S.end());
-      qd[i].k = x.k;
-    } else {
-      if (x.src >= g->cfg.v_capacity) st[i] = DG_E_VERTEX_RANGE;
-      else if (!alive_at(g, x.src, ep)) st[i] = DG_E_SOURCE_ABSENT;
+      if (st[i] == DG_OK) {
+        by_kind[x.kind].push_back(i);
+        if (g->pins[ep]++ == 0) pinned.push_back(ep);
+        else pinned.push_back(ep);
+      }
     }
-    if (st[i] == DG_OK) by_kind[x.kind].push_back(i);
   }
+  // unpin on every exit path
+  struct Unpin {
+    dg_graph* g;
+    std::vector<uint32_t>& eps;
+    ~Unpin() {
+      std::lock_guard<std::mutex> lk(g->mu);
+      for (uint32_t ep : eps) {
+        auto it = g->pins.find(ep);
+        if (it != g->pins.end() && --it->second == 0) g->pins.erase(it);
+      }
+    }
+  } unpin{g, pinned};
   // resident workgroups per kind's kernel
   for (int k = 0; k < 3; k++) {
     if (bs->grid_cap[k] || by_kind[k].empty()) continue;
@@ -473,25 +519,25 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
     bs->grid_cap[k] = std::max(1, per_cu * cus);
   }
   // teams: size from the tuning (0 = automatic), count bounded by memory
-  const uint64_t per_team = team_layout(g, nullptr, nullptr);
+  const uint64_t per_team = team_layout(st_, tune.tile_buckets, nullptr, nullptr);
   const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
   const uint32_t max_teams = (uint32_t)std::max<uint64_t>(1, budget / per_team);
   uint32_t S_of[3] = {1, 1, 1}, T_of[3] = {0, 0, 0}, most = 1;
   for (int k = 0; k < 3; k++) {
     uint32_t n = (uint32_t)by_kind[k].size();
     if (!n) continue;
-    const uint32_t G = (uint32_t)bs->grid_cap[k];
-    uint32_t S = g->tune.batch_groups;
+    const uint32_t G = std::max<uint32_t>(1, (uint32_t)((uint64_t)bs->grid_cap[k] * share / 100));
+    uint32_t S = tune.batch_groups;
     if (S == 0 || S > G) S = std::max<uint32_t>(1, G / std::min<uint32_t>(n, max_teams));
     S_of[k] = S;
     T_of[k] = std::max<uint32_t>(1, std::min<uint32_t>({G / S, n, max_teams}));
     most = std::max(most, T_of[k]);
   }
-  size_t e_cnt = g->arcs_by_epoch.size();
+  size_t e_cnt = arcs.size();
   if ((e = ensure(bs->scratch, per_team * most)) != hipSuccess)
     return bfail(g, DG_E_OUT_OF_MEMORY, "batch scratch allocation");
   std::vector<TeamScratch> tsv(most);
-  for (uint32_t t = 0; t < most; t++) team_layout(g, bs->scratch.as<char>() + per_team * t, &tsv[t]);
+  for (uint32_t t = 0; t < most; t++) team_layout(st_, tune.tile_buckets, bs->scratch.as<char>() + per_team * t, &tsv[t]);
   if ((e = ensure(bs->teams, most * sizeof(TeamScratch))) != hipSuccess ||
       (e = ensure(bs->qdesc, nq * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nq * 4)) != hipSuccess ||
       (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
@@ -513,8 +559,8 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       (all_srcs.size() &&
        (e = hipMemcpyAsync(bs->srcs.p, all_srcs.data(), all_srcs.size() * 4, hipMemcpyHostToDevice, s))) ||
       (e = hipMemcpyAsync(bs->status.p, st.data(), nq * 4, hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(bs->arcs.p, g->arcs_by_epoch.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(bs->live.p, g->live_by_epoch.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->arcs.p, arcs.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->live.p, live.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(bs->ctrl.p, c0, sizeof(c0), hipMemcpyHostToDevice, s)))
     return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
   {
@@ -524,12 +570,12 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       for (uint32_t t = 0; t < T_of[k]; t++)
         if ((e = hipMemsetAsync(tsv[t].sync, 0, sizeof(TeamSync), s)) != hipSuccess)
           return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
-      BatchArgs a{g->st,
-                  g->concurrent_writers ? 0 : 1,
-                  g->tune.tile_buckets,
-                  (int32_t)std::max<uint32_t>(1, g->tune.sssp_delta),
-                  g->tune.alpha,
-                  g->tune.beta,
+      BatchArgs a{st_,
+                  fast,
+                  tune.tile_buckets,
+                  (int32_t)std::max<uint32_t>(1, tune.sssp_delta),
+                  tune.alpha,
+                  tune.beta,
                   bs->qdesc.as<QDesc>(),
                   bs->qidx.as<uint32_t>() + koff[k],
                   (uint32_t)by_kind[k].size(),
@@ -540,7 +586,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
                   T_of[k],
                   S_of[k],
                   bs->ctrl.as<Ctrl>() + k};
-      ProfScope ps(g, KID_BATCH, s);
+      ProfScope ps(g, KID_BATCH_BFS + k, s);
       if (k == DG_Q_BFS) k_team<DG_Q_BFS><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
       else if (k == DG_Q_SSSP) k_team<DG_Q_SSSP><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
       else k_team<DG_Q_BC><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
@@ -552,8 +598,13 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
         (e = hipMemcpyAsync(cres, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
-    for (int k = 0; k < 3; k++)
+    for (int k = 0; k < 3; k++) {
       if (cres[k].abort) return bfail(g, DG_E_HIP, "batch engine: a team barrier timed out");
+      if (!by_kind[k].empty()) {
+        prof_arcs(g, KID_BATCH_BFS + k, cres[k].arcs);
+        g->engine_arcs += cres[k].arcs;
+      }
+    }
   }
   for (uint32_t i = 0; i < nq; i++) per_query[i] = st[i];
   return DG_OK;
@@ -563,7 +614,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
 
 extern "C" dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
-  std::lock_guard<std::mutex> lk(g->mu);
   try {
     return dg::query_batch_dev(g, q, nq, per_query, static_cast<hipStream_t>(stream));
   } catch (...) {

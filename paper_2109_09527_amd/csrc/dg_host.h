@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -82,7 +83,9 @@ enum KernelId {
   KID_SSSP_SPLIT,
   KID_BC_FWD,
   KID_BC_BWD,
-  KID_BATCH,        // one persistent multi-query launch
+  KID_BATCH_BFS,    // one persistent multi-query launch, per query kind
+  KID_BATCH_SSSP,
+  KID_BATCH_BC,
   KID_COUNT
 };
 struct Prof {
@@ -127,9 +130,12 @@ struct dg_graph {
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
+  uint32_t engine_share_pct = 100;  // share of resident workgroup slots a batch launch may fill
+  std::atomic<uint64_t> engine_arcs{0};  // visible arcs examined by all batch launches
   hipEvent_t last_query = nullptr;  // end of the last plain query's work; updates wait for it
   std::string err;
-  std::mutex mu;                // serialises the serving loop's workers on this graph
+  std::mutex mu;                // host state: epoch, pins, history, store descriptors
+  std::mutex upd_mu;            // one update batch (or compaction) at a time
 };
 
 namespace dg {

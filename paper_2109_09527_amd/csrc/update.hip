@@ -449,10 +449,16 @@ static hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
 static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8_t* dres, hipStream_t s,
                                UpdCounters* hc) {
   UpdateScratch& u = g->us;
-  const Store& st = g->st;
+  // host state is read under the graph mutex; the GPU work runs without it
+  Store st;
+  uint32_t E, fl;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    st = g->st;
+    E = g->epoch + 1;
+    fl = gc_floor(g);
+  }
   const uint32_t L = g->L;
-  const uint32_t E = g->epoch + 1;
-  const uint32_t fl = gc_floor(g);
   UpdCounters* c = u.summary.as<UpdCounters>();
   uint32_t* vchange = reinterpret_cast<uint32_t*>(c + 1);
   uint32_t* touch_f = u.touch.as<uint32_t>();
@@ -548,14 +554,16 @@ dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* d
       return DG_E_OUT_OF_MEMORY;
     }
   }
+  std::lock_guard<std::mutex> lk(g->mu);
   const uint32_t E = g->epoch + 1;
   if (hc.n_vchange <= VCHANGE_INLINE) {
     record_vertex_changes(g, reinterpret_cast<uint32_t*>(static_cast<char*>(g->us.host_summary) + sizeof(UpdCounters)),
                           hc.n_vchange, E);
   } else {
     std::vector<uint32_t> lst(hc.n_vchange);
-    e = hipMemcpy(lst.data(), reinterpret_cast<uint32_t*>(g->us.summary.as<UpdCounters>() + 1),
-                  (size_t)hc.n_vchange * 4, hipMemcpyDeviceToHost);
+    e = hipMemcpyAsync(lst.data(), reinterpret_cast<uint32_t*>(g->us.summary.as<UpdCounters>() + 1),
+                       (size_t)hc.n_vchange * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       g->err = std::string("vertex change readback: ") + hipGetErrorString(e);
       return DG_E_HIP;
