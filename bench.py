@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle sample size in steps (0 = skip)")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch-queries", type=int, default=128,
                     help="queries of the batched-vs-plain comparison (0 = skip)")
     args = ap.parse_args()
@@ -113,6 +114,9 @@ def main():
 
     for i in range(W):
         step(i)
+    torch.cuda.synchronize()
+    tuning = g.autotune(seed=0) if not args.no_autotune else g.get_tuning()
+    print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     if not args.no_profile:
         g.profile(True)
@@ -182,7 +186,7 @@ def main():
             "workload": f"R-MAT scale {args.scale} dynamic graph: per step one batch of 65,536 edge add/remove "
                         f"(50/50) + 656 vertex add/remove, then one snapshot BFS and one delta-stepping SSSP",
             "vertices": gr.n, "loaded_edges": gr.m, "weights": "int32 U[1,255]",
-            "ops_per_batch": len(wl.batches[0]), "parallelism": "single GPU",
+            "ops_per_batch": len(wl.batches[0]), "parallelism": "single GPU", "tuning": tuning,
         },
         "updates_per_s": round(n_ops / (sum(upd_ms) / 1e3), 1),
         "query_gteps": round(m_total / q_time / 1e9, 4),

@@ -151,6 +151,7 @@ typedef struct {
   uint32_t sssp_delta;     /* delta-stepping bucket width */
   uint32_t alpha, beta;    /* direction-switch thresholds of the BFS */
   uint32_t batch_groups;   /* workgroups per query team in the persistent launch; 0 = automatic */
+  uint32_t batch_delta;    /* delta-stepping bucket width inside the persistent launch */
 } dg_tuning;
 dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t);
 dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t);

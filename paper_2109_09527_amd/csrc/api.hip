@@ -639,6 +639,7 @@ dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t) {
   t->alpha = g->tune.alpha;
   t->beta = g->tune.beta;
   t->batch_groups = g->tune.batch_groups;
+  t->batch_delta = g->tune.batch_delta;
   return DG_OK;
 }
 
@@ -646,7 +647,7 @@ dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t) {
   if (!g || !t) return DG_E_INVALID_ARG;
   uint32_t T = t->tile_buckets;
   if (T == 0 || T > 64 || (T & (T - 1))) return fail(g, DG_E_INVALID_ARG, "tile_buckets must be a power of 2 in [1, 64]");
-  if (t->sssp_delta == 0 || t->alpha == 0 || t->beta == 0)
+  if (t->sssp_delta == 0 || t->alpha == 0 || t->beta == 0 || t->batch_delta == 0)
     return fail(g, DG_E_INVALID_ARG, "tuning values must be positive");
   std::lock_guard<std::mutex> lk(g->mu);
   if (T < g->tune.tile_buckets) {
@@ -659,6 +660,7 @@ dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t) {
   g->tune.alpha = t->alpha;
   g->tune.beta = t->beta;
   g->tune.batch_groups = t->batch_groups;
+  g->tune.batch_delta = t->batch_delta;
   return DG_OK;
 }
 

@@ -1,19 +1,25 @@
 // Persistent multi-query engine: many BFS / SSSP / BC queries, on any mix
 // of retained epochs, in one launch.
 //
-// The grid holds only as many workgroups as can be resident at once (from
-// the occupancy API), split into teams of S workgroups.  A team takes the
-// next query from a device counter, runs it level by level with the steps
-// of frontier.h over its own scratch, separating levels with a team barrier
-// (arrival counter + generation word in global memory, an acquire fence
-// after it so no workgroup reads stale lines of another's writes), and
-// takes the next query when done.  Each query terminates on its own; no
-// barrier spans the grid.  Every spin loop is bounded: a workgroup that
-// waits too long sets an abort flag that releases every other waiter, so
-// the launch always drains.  Only one engine launch runs on a device at a
-// time (teams spin on each other, so two engines could starve each other
-// of resident workgroups).
+// The grid holds at most 90% of the workgroups that can be resident at once
+// (from the occupancy API).  Workgroups join teams of S in the order they
+// start running, so a team's members are resident together; a team becomes
+// active only when all S members have joined, and members still waiting
+// when the query queue runs dry leave without work (the forming / active /
+// dead state is settled by one compare-and-swap, so every member takes the
+// same decision).  An active team takes the next query from a device
+// counter, runs it level by level with the steps of frontier.h over its own
+// scratch, separating levels with a team barrier (arrival counter +
+// generation word in global memory, a release fence before it and an
+// acquire fence after it, so no workgroup reads stale lines of another's
+// writes), and takes the next query when done.  Each query terminates on
+// its own; no barrier spans the grid.  Every wait is bounded by a wall-clock
+// limit: a workgroup that waits too long sets an abort flag that releases
+// every other waiter, so the launch always drains.  Only one engine launch
+// runs on a device at a time (teams spin on each other, so two engines
+// could starve each other of resident workgroups).
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 
@@ -22,17 +28,20 @@
 
 namespace dg {
 
-constexpr uint64_t SPIN_LIMIT = 1ull << 26;
-
 struct TeamSync {
-  uint32_t count, gen, q, pad[13];
+  uint32_t count, gen, q;
+  uint32_t joined;   // members that have started
+  uint32_t state;    // 0 forming, 1 active, 2 dead
+  uint32_t pad[11];
 };
 
 struct Ctrl {
   uint32_t next;
   uint32_t abort;
+  uint32_t arrive;   // start order of the workgroups
+  uint32_t done;     // queries finished
   unsigned long long arcs;   // visible arcs examined by the launch
-  uint32_t pad[12];
+  uint32_t pad[10];
 };
 
 // Worker 0 adds a finished step's examined-arc count to the launch total.
@@ -54,7 +63,9 @@ struct TeamScratch {
   Item* qa;
   Item* qb;
   Item* qbig;
-  uint32_t* bm[3];
+  uint32_t* bm0;          // three rotating frontier bitmaps
+  uint32_t* bm1;
+  uint32_t* bm2;
   QCounters* cnt;         // [0..2] rotating level counters, [3] BC totals
   uint32_t* fa;
   uint32_t* fb;
@@ -82,9 +93,11 @@ struct BatchArgs {
   const TeamScratch* teams;
   uint32_t n_teams, team_size;
   Ctrl* ctrl;
+  uint64_t spin_ticks;    // longest wait, in wall-clock ticks
 };
 
-__device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctrl* ctrl, Shared& sh) {
+__device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctrl* ctrl, Shared& sh,
+                                    uint64_t spin_ticks) {
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ab = 0;
@@ -96,10 +109,10 @@ __device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctr
         __threadfence();
         atomicAdd(&ts->gen, 1u);
       } else {
-        uint64_t spins = 0;
+        const uint64_t t0 = wall_clock64();
         while (ld_relaxed(&ts->gen) == my) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins > SPIN_LIMIT || ld_relaxed(&ctrl->abort)) {
+          if (wall_clock64() - t0 > spin_ticks || ld_relaxed(&ctrl->abort)) {
             atomicExch(&ctrl->abort, 1u);
             ab = 1;
             break;
@@ -118,7 +131,8 @@ __device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctr
 
 // Rotating bitmap i (selected without indexing a register array).
 __device__ inline uint32_t* bm_at(const TeamScratch& ts, uint32_t i) {
-  return i == 0 ? ts.bm[0] : (i == 1 ? ts.bm[1] : ts.bm[2]);
+  uint64_t p0 = (uint64_t)ts.bm0, p1 = (uint64_t)ts.bm1, p2 = (uint64_t)ts.bm2;
+  return (uint32_t*)(i == 0 ? p0 : (i == 1 ? p1 : p2));
 }
 
 template <class T>
@@ -154,23 +168,23 @@ __device__ inline void team_seed(const Store& st, uint32_t src, Item* q, QCounte
 
 #define BARRIER()                                          \
   do {                                                     \
-    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh)) return false; \
+    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return false; \
   } while (0)
 
-__device__ inline bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+__device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
                         uint32_t& gen, Shared& sh) {
   const uint32_t V = a.st.V;
   const uint64_t bmw = (V + 31) / 32 + 1;
   int32_t* dist = static_cast<int32_t*>(qd.out);
   team_fill<int32_t>(dist, V, -1, w, S);
-  team_fill<uint32_t>(ts.bm[0], bmw, 0u, w, S);
-  team_fill<uint32_t>(ts.bm[1], bmw, 0u, w, S);
+  team_fill<uint32_t>(ts.bm0, bmw, 0u, w, S);
+  team_fill<uint32_t>(ts.bm1, bmw, 0u, w, S);
   if (w == 0 && threadIdx.x == 0)
     for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
   BARRIER();
   if (w == 0 && threadIdx.x == 0) {
     dist[qd.src] = 0;
-    ts.bm[0][qd.src >> 5] |= 1u << (qd.src & 31);
+    ts.bm0[qd.src >> 5] |= 1u << (qd.src & 31);
   }
   team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
   BARRIER();
@@ -207,7 +221,7 @@ __device__ inline bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamSc
   return true;
 }
 
-__device__ inline bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+__device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
                          uint32_t& gen, Shared& sh) {
   const uint32_t V = a.st.V;
   int32_t* dist = static_cast<int32_t*>(qd.out);
@@ -273,7 +287,7 @@ __device__ inline bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamS
   return true;
 }
 
-__device__ inline bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
+__device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
                        uint32_t& gen, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   double* bc = static_cast<double*>(qd.out);
@@ -333,18 +347,59 @@ __device__ inline bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScr
 
 // One launch serves the queries of one kind, so each kind's kernel gets its
 // own register allocation.
+// Join a team in start order; returns false when the team never becomes
+// active (queue exhausted first, or a wait timed out).
+__device__ inline bool team_join(const BatchArgs& a, TeamSync* sync, uint32_t S, Shared& sh) {
+  if (threadIdx.x == 0) {
+    uint32_t go = 0;
+    if (atomicAdd(&sync->joined, 1u) + 1 == S) {
+      go = atomicCAS(&sync->state, 0u, 1u) == 0u;
+    } else {
+      const uint64_t t0 = wall_clock64();
+      for (;;) {
+        uint32_t stt = ld_relaxed(&sync->state);
+        if (stt == 1u) { go = 1; break; }
+        if (stt == 2u) break;
+        if (ld_relaxed(&a.ctrl->next) >= a.nq || ld_relaxed(&a.ctrl->abort)) {
+          uint32_t old = atomicCAS(&sync->state, 0u, 2u);
+          if (old == 1u) { go = 1; break; }
+          break;
+        }
+        if (wall_clock64() - t0 > a.spin_ticks) {
+          // a team that cannot assemble dissolves; the host checks that
+          // every query was still served
+          uint32_t old = atomicCAS(&sync->state, 0u, 2u);
+          go = old == 1u;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    sh.flag = go;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return sh.flag != 0;
+}
+
+// One launch serves the queries of one kind, so each kind's kernel gets its
+// own register allocation.
 template <int KIND>
 __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
   __shared__ Shared sh;
   stages_init(sh);
+  if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
+  __syncthreads();
+  const uint32_t slot = sh.base;
   const uint32_t S = a.team_size;
-  const uint32_t t = blockIdx.x / S, w = blockIdx.x % S;
+  const uint32_t t = slot / S, w = slot % S;
   if (t >= a.n_teams) return;
   const TeamScratch ts = a.teams[t];
+  if (!team_join(a, ts.sync, S, sh)) return;
   uint32_t gen = 0;
   for (;;) {
     if (w == 0 && threadIdx.x == 0) ts.sync->q = atomicAdd(&a.ctrl->next, 1u);
-    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh)) return;
+    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
     const uint32_t k = ld_relaxed(&ts.sync->q);
     if (k >= a.nq) return;
     const uint32_t qi = a.qidx[k];
@@ -355,7 +410,8 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
       else if (KIND == DG_Q_SSSP) ok = run_sssp(a, qd, ts, w, S, gen, sh);
       else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
     }
-    if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh)) return;
+    if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
+    if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, 1u);
   }
 }
 
@@ -363,6 +419,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
 
 struct BatchState {
   std::mutex mu;                 // one batch at a time per graph (shared buffers)
+  uint64_t spin_ticks = 0;       // 2 s of the device wall clock
   DevBuf scratch, teams, qdesc, qidx, srcs, status, arcs, live, ctrl;
   int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
 };
@@ -407,10 +464,9 @@ static uint64_t team_layout(const Store& st, uint32_t T, char* base, TeamScratch
   p = take(items * sizeof(Item)); if (ts) ts->qa = reinterpret_cast<Item*>(p);
   p = take(items * sizeof(Item)); if (ts) ts->qb = reinterpret_cast<Item*>(p);
   p = take(big * sizeof(Item)); if (ts) ts->qbig = reinterpret_cast<Item*>(p);
-  for (int i = 0; i < 3; i++) {
-    p = take(bmw * 4);
-    if (ts) ts->bm[i] = reinterpret_cast<uint32_t*>(p);
-  }
+  p = take(bmw * 4); if (ts) ts->bm0 = reinterpret_cast<uint32_t*>(p);
+  p = take(bmw * 4); if (ts) ts->bm1 = reinterpret_cast<uint32_t*>(p);
+  p = take(bmw * 4); if (ts) ts->bm2 = reinterpret_cast<uint32_t*>(p);
   p = take(4 * sizeof(QCounters)); if (ts) ts->cnt = reinterpret_cast<QCounters*>(p);
   p = take(V * 4 + 64); if (ts) ts->fa = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (ts) ts->fb = reinterpret_cast<uint32_t*>(p);
@@ -518,6 +574,12 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       return bfail(g, DG_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
     bs->grid_cap[k] = std::max(1, per_cu * cus);
   }
+  if (!bs->spin_ticks) {
+    int khz = 0, dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    bs->spin_ticks = (uint64_t)khz * 1000ull * 2ull;
+  }
   // teams: size from the tuning (0 = automatic), count bounded by memory
   const uint64_t per_team = team_layout(st_, tune.tile_buckets, nullptr, nullptr);
   const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
@@ -526,7 +588,8 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   for (int k = 0; k < 3; k++) {
     uint32_t n = (uint32_t)by_kind[k].size();
     if (!n) continue;
-    const uint32_t G = std::max<uint32_t>(1, (uint32_t)((uint64_t)bs->grid_cap[k] * share / 100));
+    // 90% of the resident capacity (times the share a server leaves to the engine)
+    const uint32_t G = std::max<uint32_t>(1, (uint32_t)((uint64_t)bs->grid_cap[k] * 9 / 10 * share / 100));
     uint32_t S = tune.batch_groups;
     if (S == 0 || S > G) S = std::max<uint32_t>(1, G / std::min<uint32_t>(n, max_teams));
     S_of[k] = S;
@@ -573,7 +636,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       BatchArgs a{st_,
                   fast,
                   tune.tile_buckets,
-                  (int32_t)std::max<uint32_t>(1, tune.sssp_delta),
+                  (int32_t)std::max<uint32_t>(1, tune.batch_delta),
                   tune.alpha,
                   tune.beta,
                   bs->qdesc.as<QDesc>(),
@@ -585,7 +648,8 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
                   bs->teams.as<TeamScratch>(),
                   T_of[k],
                   S_of[k],
-                  bs->ctrl.as<Ctrl>() + k};
+                  bs->ctrl.as<Ctrl>() + k,
+                  bs->spin_ticks};
       ProfScope ps(g, KID_BATCH_BFS + k, s);
       if (k == DG_Q_BFS) k_team<DG_Q_BFS><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
       else if (k == DG_Q_SSSP) k_team<DG_Q_SSSP><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
@@ -600,6 +664,8 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
     for (int k = 0; k < 3; k++) {
       if (cres[k].abort) return bfail(g, DG_E_HIP, "batch engine: a team barrier timed out");
+      if (cres[k].done != by_kind[k].size())
+        return bfail(g, DG_E_HIP, "batch engine: queries left unserved (teams could not assemble)");
       if (!by_kind[k].empty()) {
         prof_arcs(g, KID_BATCH_BFS + k, cres[k].arcs);
         g->engine_arcs += cres[k].arcs;
@@ -622,8 +688,101 @@ extern "C" dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq,
   }
 }
 
-extern "C" dg_status dg_autotune(dg_graph* g, uint32_t, dg_tuning*, void*) {
+// ------------------------------------------------------------ autotuner
+// Coordinate descent over the frontier-tile shape and the traversal
+// parameters at the latest epoch: each candidate is timed on the same
+// seeded sample of sources (plain BFS for the tile size and the direction
+// thresholds, plain SSSP for delta, one engine launch of mixed queries for
+// the team size) and the fastest value is kept.  Every candidate computes
+// the same results; only the time differs.
+
+namespace dg {
+uint32_t pick_u32(uint64_t& x) {   // splitmix64 step
+  x += 0x9e3779b97f4a7c15ull;
+  uint64_t z = x;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+}  // namespace dg
+
+extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, void* stream) {
+  using namespace dg;
   if (!g) return DG_E_INVALID_ARG;
-  g->err = "autotuner is not built yet";
-  return DG_E_UNIMPLEMENTED;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t V = g->cfg.v_capacity;
+  const uint32_t e = dg_latest_epoch(g);
+  DevBuf deg, d0, d1;
+  if (ensure(deg, V * 4ull) != hipSuccess || ensure(d0, V * 4ull) != hipSuccess) return DG_E_OUT_OF_MEMORY;
+  dg_status st = dg_out_degrees(g, e, deg.as<uint32_t>(), stream);
+  if (st != DG_OK) return st;
+  std::vector<uint32_t> hd(V);
+  if (hipMemcpyAsync(hd.data(), deg.p, V * 4ull, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DG_E_HIP;
+  std::vector<uint32_t> cand;
+  for (uint32_t v = 0; v < V; v++)
+    if (hd[v]) cand.push_back(v);
+  if (cand.empty()) {
+    release(deg);
+    release(d0);
+    return dg_get_tuning(g, chosen);
+  }
+  uint64_t rs = 0x243f6a8885a308d3ull ^ seed;
+  std::vector<uint32_t> src(4);
+  for (auto& x : src) x = cand[pick_u32(rs) % cand.size()];
+  auto time_queries = [&](int kind) -> double {
+    auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t x : src) {
+      dg_status r = kind == 0 ? dg_bfs(g, e, x, d0.as<int32_t>(), stream) : dg_sssp(g, e, x, d0.as<int32_t>(), stream);
+      if (r != DG_OK) return 1e30;
+    }
+    hipStreamSynchronize(s);
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  std::vector<DevBuf> outs(32);
+  auto time_batch = [&]() -> double {
+    std::vector<dg_query> qs;
+    for (uint32_t i = 0; i < 32; i++) {
+      if (ensure(outs[i], V * 4ull) != hipSuccess) return 1e30;
+      qs.push_back(dg_query{i % 2 ? (uint32_t)DG_Q_SSSP : (uint32_t)DG_Q_BFS, src[i % src.size()], e, 0, nullptr,
+                            outs[i].p});
+    }
+    std::vector<dg_status> qst(qs.size());
+    auto t0 = std::chrono::steady_clock::now();
+    if (dg_query_batch(g, qs.data(), (uint32_t)qs.size(), qst.data(), stream) != DG_OK) return 1e30;
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  dg_tuning best;
+  dg_get_tuning(g, &best);
+  auto try_field = [&](uint32_t dg_tuning::*field, std::initializer_list<uint32_t> vals, int what) {
+    double best_t = 1e30;
+    uint32_t best_v = best.*field;
+    for (uint32_t v : vals) {
+      dg_tuning t = best;
+      t.*field = v;
+      if (dg_set_tuning(g, &t) != DG_OK) continue;
+      if (what == 2) time_batch();   // the first launch sizes its scratch
+      double dt = what == 2 ? time_batch() : time_queries(what);
+      dt = std::min(dt, what == 2 ? time_batch() : time_queries(what));
+      if (dt < best_t) {
+        best_t = dt;
+        best_v = v;
+      }
+    }
+    best.*field = best_v;
+    dg_set_tuning(g, &best);
+  };
+  time_queries(0);   // warm-up
+  try_field(&dg_tuning::tile_buckets, {2, 4, 8, 16, 32}, 0);
+  try_field(&dg_tuning::alpha, {4, 14, 40, 1000000}, 0);
+  try_field(&dg_tuning::beta, {8, 24, 64}, 0);
+  try_field(&dg_tuning::sssp_delta, {16, 32, 64, 128, 256, 512}, 1);
+  try_field(&dg_tuning::batch_delta, {8, 16, 32, 64, 128}, 2);
+  try_field(&dg_tuning::batch_groups, {0, 4, 8, 16, 32}, 2);
+  release(deg);
+  release(d0);
+  for (auto& o : outs) release(o);
+  if (chosen) *chosen = best;
+  return DG_OK;
 }

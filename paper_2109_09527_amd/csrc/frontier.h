@@ -309,7 +309,7 @@ struct LevelArgs {
   QCounters* cnt_out;
 };
 
-__device__ inline void td_step(const LevelArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers, Shared& sh) {
+__device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
   LaneCounts lc;
@@ -345,7 +345,7 @@ __device__ inline void td_step(const LevelArgs& a, uint32_t nin, uint32_t worker
 // forward slab when undirected) is scanned by the lane itself, stopping at
 // the first empty slot or at a parent in the frontier; longer in-slabs
 // become chunk items of BU_CHUNK buckets for bu_big_step.
-__device__ inline void bu_step(const LevelArgs& a, uint32_t worker, uint32_t nworkers, Shared& sh) {
+__device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const TileShape ts{0, a.T}, tbig{0, BU_CHUNK};
   const uint32_t V = a.st.V;
   const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
@@ -359,19 +359,30 @@ __device__ inline void bu_step(const LevelArgs& a, uint32_t worker, uint32_t nwo
     bool found = false;
     if (act && s.nb == 1) {
       const uint4* src4 = reinterpret_cast<const uint4*>(s.base);
-      uint4 q0 = src4[0], q1 = src4[1], q2 = src4[2], q3 = src4[3];
-      uint32_t x[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                        q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
       uint2 sm = a.fast ? *reinterpret_cast<const uint2*>(s.sum) : make_uint2(0xFFFFFFFFu, 0xFFFFu);
       bool fastb = a.fast && sm.x <= a.e;
-#pragma unroll
-      for (int j = 0; j < BSLOTS; j++) {
-        if (found || x[j] == EMPTY) break;
+      bool more = true;   // no empty slot seen yet (used slots are a prefix)
+      // four slots per 16-byte load; each slot is tested in turn until a
+      // parent is found or an empty slot ends the bucket
+      auto slot = [&](uint32_t x, int j) {
+        if (!more || found) return;
+        if (x == EMPTY) {
+          more = false;
+          return;
+        }
         bool vis = (fastb && !((sm.y >> j) & 1u)) || visible(*slot_stamp(s.base, j, s.words), a.e);
         if (vis) {
           lc.arcs++;
-          found = bm_test(a.bm_cur, x[j]);
+          found = bm_test(a.bm_cur, x);
         }
+      };
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        uint4 v = src4[q];
+        slot(v.x, 4 * q);
+        slot(v.y, 4 * q + 1);
+        slot(v.z, 4 * q + 2);
+        slot(v.w, 4 * q + 3);
       }
     }
     uint64_t yd = 0;
@@ -392,7 +403,7 @@ __device__ inline void bu_step(const LevelArgs& a, uint32_t worker, uint32_t nwo
 
 // Chunk items of multi-bucket in-slabs: 16 lanes per chunk; a chunk whose
 // vertex already has a parent is skipped, and the first finder claims it.
-__device__ inline void bu_big_step(const LevelArgs& a, uint32_t nbig, uint32_t worker, uint32_t nworkers,
+__device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, uint32_t worker, uint32_t nworkers,
                                    Shared& sh) {
   const TileShape ts{0, a.T}, tbig{0, BU_CHUNK};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
@@ -449,7 +460,7 @@ struct RelaxArgs {
   QCounters* cnt_out;
 };
 
-__device__ inline void relax_step(const RelaxArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
+__device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
@@ -503,7 +514,7 @@ struct SplitArgs {
 
 // Move far entries below the threshold into the near queue; keep the rest
 // and report their minimum distance.
-__device__ inline void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
+__device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
   const TileShape ts{0, a.T};
   LaneCounts lc;
@@ -550,7 +561,7 @@ struct BcFwdArgs {
   QCounters* cnt_total; // discovery-order length and the overflow flag
 };
 
-__device__ inline void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
+__device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
@@ -599,7 +610,7 @@ __device__ inline void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uint32_t wor
 // slot l%16 of bucket l/16 of each group of four buckets; the 64 partial
 // sums combine by a fixed butterfly, so the result is deterministic for a
 // given slab layout.
-__device__ inline void bcbwd_step(const Store& st, uint32_t e, bool fast, const uint32_t* verts, uint32_t nv,
+__device__ __forceinline__ void bcbwd_step(const Store& st, uint32_t e, bool fast, const uint32_t* verts, uint32_t nv,
                                   uint32_t src, const int32_t* level, int32_t L, const unsigned long long* sigma,
                                   double* delta, double* bc, uint32_t worker, uint32_t nworkers) {
   const uint32_t lane = lane_id();

@@ -136,3 +136,23 @@ def test_batch_many_queries_many_teams(dg):
             g.apply(wl.batches[ep_i])
     say("batch many queries")
     check_batch(dg, g, answers, [0, 2])
+
+
+def test_autotune_keeps_results(dg):
+    """The autotuner changes only speed: results after tuning equal the
+    oracle's, and the chosen shape is one of the candidates."""
+    gr = synth.rmat_graph(12, 16, 255, seed=21)
+    o = Oracle(gr.n, w_max=255)
+    g = dg.Graph(gr.n, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    say("autotune")
+    t = g.autotune(seed=1)
+    assert t["tile_buckets"] in (2, 4, 8, 16, 32)
+    assert t["sssp_delta"] in (16, 32, 64, 128, 256, 512)
+    assert t["batch_delta"] in (8, 16, 32, 64, 128)
+    assert g.get_tuning() == t
+    for s in synth.out_degree_sources(gr, 3, synth.rng_for(21, 2)):
+        s = int(s)
+        assert np.array_equal(g.bfs(s).cpu().numpy(), o.bfs(s)[1])
+        assert np.array_equal(g.sssp(s).cpu().numpy(), o.sssp(s)[1])
