@@ -75,6 +75,8 @@ struct TeamScratch {
   double* delta;
   int32_t* level;
   uint32_t* off;          // BC: start of each level in the discovery order
+  uint32_t* rlist;        // SSSP bucket record list (aliases sigma)
+  uint32_t* rstamp;       // SSSP bucket record stamps (aliases delta)
   TeamSync* sync;
 };
 
@@ -83,6 +85,7 @@ struct BatchArgs {
   int fast;
   uint32_t T;
   int32_t delta;
+  int32_t w_max;
   uint32_t alpha, beta;
   const QDesc* q;
   const uint32_t* qidx;   // indices of this launch's queries (one kind)
@@ -225,11 +228,15 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
                          uint32_t& gen, Shared& sh) {
   const uint32_t V = a.st.V;
   int32_t* dist = static_cast<int32_t*>(qd.out);
+  // with delta >= w_max every arc is light and the heavy passes vanish
+  const bool split_lh = a.delta < a.w_max;
+  uint32_t* rcount = &ts.cnt[3].n_order;
   team_fill<int32_t>(dist, V, DIST_INF, w, S);
   team_fill<uint32_t>(ts.stamp, V, 0u, w, S);
   team_fill<uint32_t>(ts.infar, V, 0u, w, S);
+  if (split_lh) team_fill<uint32_t>(ts.rstamp, V, 0u, w, S);
   if (w == 0 && threadIdx.x == 0)
-    for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
+    for (int i = 0; i < 4; i++) zero_counters(&ts.cnt[i]);
   BARRIER();
   if (w == 0 && threadIdx.x == 0) dist[qd.src] = 0;
   team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
@@ -241,25 +248,49 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
   uint32_t n_near = ld_relaxed(&ts.cnt[0].n_items), n_far = 0;
   int32_t thr = a.delta;
   uint32_t it = 1;
+  uint32_t phase = 1;  // bucket number (stamp of the recorded vertices)
   uint32_t slot = 0;   // counters slot holding the last pass's results
+  auto relax = [&](uint32_t nin, int mode) -> bool {
+    uint32_t nx = (slot + 1) % 3;
+    if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
+    RelaxArgs ra{a.st, qd.epoch, a.fast, qin, qout, fin + n_far, dist, ts.stamp, ts.infar, thr, it, a.T,
+                 &ts.cnt[nx], mode, a.delta, ts.rlist, rcount, ts.rstamp, phase};
+    relax_step(ra, nin, w, S, sh);
+    BARRIER();
+    add_step_arcs(a.ctrl, &ts.cnt[nx], w);
+    QCounters c = read_cnt(&ts.cnt[nx]);
+    n_near = c.n_items;
+    n_far += c.n_far;
+    Item* t = qin;
+    qin = qout;
+    qout = t;
+    it++;
+    slot = nx;
+    return true;
+  };
   for (;;) {
     if (n_near > 0) {
-      uint32_t nx = (slot + 1) % 3;
-      if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-      RelaxArgs ra{a.st, qd.epoch, a.fast, qin, qout, fin + n_far, dist, ts.stamp, ts.infar, thr, it, a.T,
-                   &ts.cnt[nx]};
-      relax_step(ra, n_near, w, S, sh);
-      BARRIER();
-      add_step_arcs(a.ctrl, &ts.cnt[nx], w);
-      QCounters c = read_cnt(&ts.cnt[nx]);
-      n_near = c.n_items;
-      n_far += c.n_far;
-      Item* t = qin;
-      qin = qout;
-      qout = t;
-      it++;
-      slot = nx;
+      if (!relax(n_near, split_lh ? 1 : 0)) return false;
       continue;
+    }
+    if (split_lh) {
+      // the bucket has settled: its recorded vertices relax their heavy arcs once
+      const uint32_t n_r = ld_relaxed(rcount);
+      if (n_r) {
+        uint32_t nx = (slot + 1) % 3;
+        if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
+        expand_step(a.st, ts.rlist, n_r, qin, &ts.cnt[nx], a.T, w, S, sh);
+        BARRIER();
+        if (w == 0 && threadIdx.x == 0) st_relaxed(rcount, 0u);
+        slot = nx;
+        const uint32_t n_h = ld_relaxed(&ts.cnt[nx].n_items);
+        if (n_h && !relax(n_h, 2)) return false;
+        // the reset of rcount is published by the heavy pass's barrier
+        if (!n_h) BARRIER();
+      }
+      phase++;
+      // heavy arcs leave the bucket (w > delta); should any land in it, keep going
+      if (n_near > 0) continue;
     }
     if (n_far == 0) break;
     int32_t far_min = DIST_INF;
@@ -473,7 +504,9 @@ static uint64_t team_layout(const Store& st, uint32_t T, char* base, TeamScratch
   p = take(V * 4 + 64); if (ts) ts->stamp = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (ts) ts->infar = reinterpret_cast<uint32_t*>(p);
   p = take(V * 8 + 64); if (ts) ts->sigma = reinterpret_cast<unsigned long long*>(p);
+  if (ts) ts->rlist = reinterpret_cast<uint32_t*>(p);
   p = take(V * 8 + 64); if (ts) ts->delta = reinterpret_cast<double*>(p);
+  if (ts) ts->rstamp = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (ts) ts->level = reinterpret_cast<int32_t*>(p);
   p = take((V + 2) * 4 + 64); if (ts) ts->off = reinterpret_cast<uint32_t*>(p);
   p = take(sizeof(TeamSync)); if (ts) ts->sync = reinterpret_cast<TeamSync*>(p);
@@ -637,6 +670,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
                   fast,
                   tune.tile_buckets,
                   (int32_t)std::max<uint32_t>(1, tune.batch_delta),
+                  (int32_t)g->cfg.w_max,
                   tune.alpha,
                   tune.beta,
                   bs->qdesc.as<QDesc>(),

@@ -69,6 +69,7 @@ struct QueryScratch {
   DevBuf bm0, bm1;              // frontier bitmaps
   DevBuf stamp, flag8;          // SSSP dedup state
   DevBuf sigma, delta, level;   // BC
+  DevBuf rlist, rstamp;         // SSSP: vertices of the current bucket
   DevBuf counters;
   void* host_counters = nullptr;
   uint64_t items_cap = 0;

@@ -118,6 +118,8 @@ __device__ inline bool visible(uint64_t stamp, uint32_t e) {
 // other threads' writes (slabs are written concurrently in update kernels).
 template <class T>
 __device__ inline T ld_relaxed(const T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <class T>
+__device__ inline void st_relaxed(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Find the current version (death == INF) of key `x` in slab s; returns the
 // slot pointer (bucket base, slot index) or nullptr.

@@ -458,6 +458,15 @@ struct RelaxArgs {
   uint32_t it1;        // stamp value of the queue being filled
   uint32_t T;
   QCounters* cnt_out;
+  // light/heavy split (Meyer & Sanders): mode 0 relaxes every arc; mode 1
+  // only arcs with w <= light and records each processed vertex once per
+  // bucket (rstamp == phase) in rlist; mode 2 only arcs with w > light
+  int mode;
+  int32_t light;
+  uint32_t* rlist;
+  uint32_t* rcount;
+  uint32_t* rstamp;
+  uint32_t phase;
 };
 
 __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
@@ -468,6 +477,12 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
   for (uint32_t base = worker * Q_ITEMS_PER_BLOCK; base < nin; base += nworkers * Q_ITEMS_PER_BLOCK) {
     ItemView iv = view_item(a.st.fp, a.qin, base + wave * 4 + grp, nin, ts);
     int32_t du = iv.nbk ? __hip_atomic_load(&a.dist[iv.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    if (a.mode == 1) {
+      // the first tile's item records its vertex for the bucket's heavy pass
+      bool rec = iv.nbk && iv.b0 == 0 && j == 0 && atomicExch(&a.rstamp[iv.v], a.phase) != a.phase;
+      uint32_t pos = wave_reserve(a.rcount, rec ? 1u : 0u);
+      if (rec) a.rlist[pos] = iv.v;
+    }
     uint32_t maxnb = wave_max_u32(iv.nbk);
     for (uint32_t i = 0; i < maxnb; i += 4) {
       Slots4 s4 = load4<true>(iv, i, j, a.e, a.fast);
@@ -475,7 +490,8 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
       for (int k = 0; k < 4; k++) {
         bool to_near = false, to_far = false;
         uint32_t d = s4.d[k];
-        if (s4.vis[k]) {
+        bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
+        if (s4.vis[k] && take) {
           lc.arcs++;
           int32_t nd = du + s4.w[k];
           if (nd < a.dist[d]) {
@@ -496,6 +512,22 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
     flush_u32(sh.u, a.far_out, &a.cnt_out->n_far, sh);
   }
   lc.commit(a.cnt_out);
+}
+
+// Items of every vertex in list[0..n): the recorded vertices of a settled
+// bucket, for its heavy-arc pass.
+__device__ __forceinline__ void expand_step(const Store& st, const uint32_t* list, uint32_t n, Item* qout,
+                                            QCounters* cnt_out, uint32_t T, uint32_t worker, uint32_t nworkers,
+                                            Shared& sh) {
+  const TileShape ts{0, T};
+  for (uint32_t base = worker * Q_THREADS; base < n; base += nworkers * Q_THREADS) {
+    uint32_t i = base + threadIdx.x;
+    bool act = i < n;
+    uint32_t v = act ? list[i] : 0;
+    uint64_t vd = act ? st.fdesc[v] : 0;
+    stage_item(sh.a, act && vd != 0, v, vd, qout, &cnt_out->n_items, ts);
+    flush_items(sh.a, qout, &cnt_out->n_items, ts, sh);
+  }
 }
 
 struct SplitArgs {

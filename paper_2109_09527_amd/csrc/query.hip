@@ -96,6 +96,14 @@ __global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, uint32_t 
   relax_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint32_t* list, uint32_t n, Item* qout,
+                                                            QCounters* cnt_out, uint32_t T, QCounters* reset) {
+  __shared__ Shared sh;
+  reset_other(reset);
+  stages_init(sh);
+  expand_step(st, list, n, qout, cnt_out, T, blockIdx.x, gridDim.x, sh);
+}
+
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t nin, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
@@ -149,6 +157,8 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
     if ((e = ensure(q.fb, V * 4 + 64)) != hipSuccess) return e;
     if ((e = ensure(q.stamp, V * 4 + 64)) != hipSuccess) return e;
     if ((e = ensure(q.flag8, V * 4 + 64)) != hipSuccess) return e;
+    if ((e = ensure(q.rlist, V * 4 + 64)) != hipSuccess) return e;
+    if ((e = ensure(q.rstamp, V * 4 + 64)) != hipSuccess) return e;
   }
   if (bc) {
     if ((e = ensure(q.fa, V * 4 + 64)) != hipSuccess) return e;
@@ -162,6 +172,7 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
 void free_query_scratch(QueryScratch& q) {
   release(q.qa); release(q.qb); release(q.fa); release(q.fb); release(q.bm0); release(q.bm1);
   release(q.stamp); release(q.flag8); release(q.sigma); release(q.delta); release(q.level);
+  release(q.rlist); release(q.rstamp);
   release(q.counters);
   if (q.host_counters) hipHostFree(q.host_counters);
   q.host_counters = nullptr;
@@ -173,6 +184,17 @@ static hipError_t read_counters(QueryScratch& q, int slot, QCounters* out, hipSt
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   std::memcpy(out, q.host_counters, sizeof(QCounters));
+  return hipSuccess;
+}
+
+// Counters of one slot plus the running bucket record count (slot 3), in one copy.
+static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(q.host_counters, q.counters.p, 4 * sizeof(QCounters), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  const QCounters* h = static_cast<const QCounters*>(q.host_counters);
+  std::memcpy(out, h + slot, sizeof(QCounters));
+  *rc = h[3].n_order;
   return hipSuccess;
 }
 
@@ -248,41 +270,77 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   if (he != hipSuccess) return hip_fail(g, he, "sssp scratch");
   const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
   const int32_t delta = (int32_t)std::max<uint32_t>(1, g->tune.sssp_delta);
+  // with delta >= w_max every arc is light and the heavy passes vanish
+  const bool split_lh = delta < g->cfg.w_max;
   Item* qin = q.qa.as<Item>();
   Item* qout = q.qb.as<Item>();
   uint32_t* fin = q.fa.as<uint32_t>();
   uint32_t* fout = q.fb.as<uint32_t>();
   uint32_t* stamp = q.stamp.as<uint32_t>();
   uint32_t* infar = q.flag8.as<uint32_t>();
+  uint32_t* rlist = q.rlist.as<uint32_t>();
+  uint32_t* rstamp = q.rstamp.as<uint32_t>();
   QCounters* cnt = q.counters.as<QCounters>();
+  uint32_t* rcount = &cnt[3].n_order;
   fill<int32_t>(dist, V, DIST_INF, s);
   fill<uint32_t>(stamp, V, 0u, s);
   fill<uint32_t>(infar, V, 0u, s);
+  if (split_lh) {
+    fill<uint32_t>(rstamp, V, 0u, s);
+    fill<uint32_t>(rcount, 1, 0u, s);
+  }
   k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, qin, nullptr, T, cnt, nullptr);
   QCounters hc;
   if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp seed");
   uint32_t n_near = hc.n_items, n_far = 0;
   int32_t thr = delta;
-  uint32_t it = 1;   // stamp of the queue being filled; the source's queue had stamp 0
+  uint32_t it = 1;      // stamp of the queue being filled; the source's queue had stamp 0
+  uint32_t phase = 1;   // bucket number (stamp of the recorded vertices)
+  uint32_t n_rec = 0;   // vertices recorded in the current bucket
   int slot = 0;
-  for (;;) {
+  auto relax = [&](uint32_t nin, int mode) -> hipError_t {
     int nxt = slot ^ 1;
+    // far entries found by this pass are appended after the current far list
+    RelaxArgs a{g->st, e, fast, qin, qout, fin + n_far, dist, stamp, infar, thr, it, T, cnt + nxt,
+                mode, delta, rlist, rcount, rstamp, phase};
+    {
+      ProfScope ps(g, KID_SSSP_RELAX, s);
+      k_sssp_relax<<<grid_for(nin, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, nin, cnt + slot);
+    }
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    if ((r = read_counters_rc(q, nxt, &hc, &n_rec, s)) != hipSuccess) return r;
+    prof_arcs(g, KID_SSSP_RELAX, hc.arcs);
+    n_near = hc.n_items;
+    n_far += hc.n_far;
+    std::swap(qin, qout);
+    it++;
+    slot = nxt;
+    return hipSuccess;
+  };
+  for (;;) {
     if (n_near > 0) {
-      // far entries found by this pass are appended after the current far list
-      RelaxArgs a{g->st, e, fast, qin, qout, fin + n_far, dist, stamp, infar, thr, it, T, cnt + nxt};
-      {
-        ProfScope ps(g, KID_SSSP_RELAX, s);
-        k_sssp_relax<<<grid_for(n_near, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_near, cnt + slot);
-      }
-      if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp relax launch");
-      if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp relax");
-      prof_arcs(g, KID_SSSP_RELAX, hc.arcs);
-      n_near = hc.n_items;
-      n_far += hc.n_far;
-      std::swap(qin, qout);
-      it++;
-      slot = nxt;
+      if ((he = relax(n_near, split_lh ? 1 : 0)) != hipSuccess) return hip_fail(g, he, "sssp relax");
       continue;
+    }
+    if (split_lh) {
+      // the bucket has settled: its recorded vertices relax their heavy arcs once
+      if (n_rec) {
+        const uint32_t n_r = n_rec;
+        fill<uint32_t>(rcount, 1, 0u, s);
+        n_rec = 0;
+        int nxt = slot ^ 1;
+        k_sssp_expand<<<grid_for(n_r, Q_THREADS), Q_THREADS, 0, s>>>(g->st, rlist, n_r, qin, cnt + nxt, T,
+                                                                     cnt + slot);
+        if ((he = hipGetLastError()) != hipSuccess || (he = read_counters(q, nxt, &hc, s)) != hipSuccess)
+          return hip_fail(g, he, "sssp expand");
+        slot = nxt;
+        if (hc.n_items && (he = relax(hc.n_items, 2)) != hipSuccess) return hip_fail(g, he, "sssp heavy");
+        n_rec = 0;
+      }
+      phase++;
+      // heavy arcs leave the bucket (w > delta); should any land in it, keep going
+      if (n_near > 0) continue;
     }
     if (n_far == 0) break;
     int32_t far_min = DIST_INF;
@@ -290,7 +348,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
     do {
       thr = far_min == DIST_INF ? thr + delta
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
-      nxt = slot ^ 1;
+      int nxt = slot ^ 1;
       SplitArgs a{g->st, fin, fout, qin, dist, stamp, infar, thr, it, T, cnt + nxt};
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);

@@ -252,6 +252,29 @@ def test_bulk_load_spans_many_tiles(dg):
             check_queries(g, o, g.epoch, src[:1], dg)
 
 
+def test_sssp_bucket_width_sweep(dg):
+    """Delta-stepping with bucket widths from 1 (Dijkstra-like, every arc
+    heavy but weight-1 ones) through w_max (no heavy arcs) to far above it:
+    plain and batched SSSP equal the oracle's Dijkstra at every width."""
+    gr = synth.rmat_graph(12, 16, 255, seed=7)
+    o = Oracle(gr.n, w_max=255)
+    g = dg.Graph(gr.n, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    src = [int(s) for s in synth.out_degree_sources(gr, 3, synth.rng_for(7, 3))]
+    want = {s: o.sssp(s)[1] for s in src}
+    for delta in (1, 2, 7, 64, 254, 255, 256, 100000):
+        say("sssp delta", delta)
+        g.set_tuning(sssp_delta=delta, batch_delta=min(delta, 128) if delta >= 8 else 8)
+        for s in src:
+            assert np.array_equal(g.sssp(s, g.epoch).cpu().numpy(), want[s]), (delta, s)
+        outs = [torch.empty(gr.n, dtype=torch.int32, device="cuda") for _ in src]
+        st = g.query_batch([(dg.Q_SSSP, g.epoch, s, out) for s, out in zip(src, outs)])
+        assert st == [0] * len(src)
+        for s, out in zip(src, outs):
+            assert np.array_equal(out.cpu().numpy(), want[s]), ("batched", delta, s)
+
+
 def test_bc_closed_form_and_overflow(dg):
     n = 9
     g = dg.Graph(n, undirected=True, w_max=1)
