@@ -61,6 +61,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle sample size in steps (0 = skip)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (a reference kernel for "
+                         "calibrating HBM byte counters)")
+    ap.add_argument("--tuning-file", default=None,
+                    help="JSON tuning: loaded (and the autotuner skipped) if the file exists, else written "
+                         "after autotuning, so a profiled run can replay the tuned configuration")
     ap.add_argument("--batch-queries", type=int, default=128,
                     help="queries of the batched-vs-plain comparison (0 = skip)")
     args = ap.parse_args()
@@ -112,10 +118,20 @@ def main():
         e3.record()
         return ep, (e0, e1, e2, e3)
 
+    if args.tuning_file and os.path.exists(args.tuning_file):
+        with open(args.tuning_file) as f:
+            g.set_tuning(**json.load(f))
     for i in range(W):
         step(i)
     torch.cuda.synchronize()
-    tuning = g.autotune(seed=0) if not args.no_autotune else g.get_tuning()
+    fixed_tuning = bool(args.tuning_file and os.path.exists(args.tuning_file))
+    if fixed_tuning:
+        tuning = g.get_tuning()
+    else:
+        tuning = g.autotune(seed=0) if not args.no_autotune else g.get_tuning()
+        if args.tuning_file:
+            with open(args.tuning_file, "w") as f:
+                json.dump(tuning, f)
     print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     if not args.no_profile:
@@ -202,6 +218,13 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_mib > 0:
+        n = args.copy_mib << 18   # int32 elements
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copied {args.copy_mib} MiB device to device", file=sys.stderr, flush=True)
 
 
 def kernel_roof(prof, name, bytes_per_arc):

@@ -418,7 +418,6 @@ __device__ inline bool team_join(const BatchArgs& a, TeamSync* sync, uint32_t S,
 template <int KIND>
 __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
   __shared__ Shared sh;
-  stages_init(sh);
   if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
   __syncthreads();
   const uint32_t slot = sh.base;

@@ -1,9 +1,8 @@
 // Level steps of the snapshot queries, shared by the one-query kernels
 // (query.hip) and the persistent multi-query engine (batch.hip).
 //
-// A step is executed by `nworkers` workgroups numbered `worker`; each
-// workgroup loops over its share of the step's units in workgroup-uniform
-// strides and may use the LDS block `Shared`.
+// A step is executed by `nworkers` workgroups numbered `worker`; inside a
+// step every wave works on its own and no workgroup barrier is taken.
 //
 // Frontier work items are (slab descriptor, vertex, tile): a tile is up to
 // T consecutive buckets of the vertex's forward slab, so a hub's adjacency
@@ -11,10 +10,18 @@
 // descriptor is read once when the vertex is pushed and carried in the item,
 // so all tiles of a vertex read the same slab even if a concurrent update
 // regrows it (the old slab stays intact and holds every version visible at
-// e).  A 16-lane group handles one item: lane j reads slot j of a bucket,
-// four buckets in flight at a time.  Pushes are staged in LDS and flushed
-// with one global atomic per workgroup pass; counters live in registers
-// and are added once per wave.
+// e).
+//
+// A wave takes a batch of 16 items and lays their buckets out in one flat
+// sequence; each 16-lane group handles one (item, bucket) pair at a time,
+// lane j reading slot j, and four pairs are in flight per group.  Low-degree
+// vertices (one bucket) therefore fill the wave instead of idling three
+// quarters of it, and hub tiles spread over all four groups.
+//
+// Pushes are staged in the wave's own LDS arrays with a wave-uniform count
+// and appended to the global queue with one atomic per flush; a wave
+// flushes when its stage could overflow on the next round and at the end
+// of the step.  Counters live in registers and are added once per wave.
 #pragma once
 #include "dg_internal.h"
 
@@ -22,10 +29,10 @@ namespace dg {
 
 constexpr int Q_THREADS = 256;
 constexpr int Q_WAVES = Q_THREADS / 64;
-constexpr int Q_ITEMS_PER_BLOCK = Q_WAVES * 4;   // four 16-lane groups per wave
-constexpr int STAGE = 2048;                      // staged pushes per workgroup pass
-constexpr int STAGE_BIG = 256;
-constexpr uint32_t BU_CHUNK = 8;                 // buckets per bottom-up chunk item
+constexpr int WB_ITEMS = 16;                      // frontier items per wave batch
+constexpr int Q_ITEMS_PER_BLOCK = Q_WAVES * WB_ITEMS;
+constexpr int WSTAGE = 256;                       // staged pushes per wave
+constexpr uint32_t BU_CHUNK = 8;                  // buckets per bottom-up chunk item
 
 struct Item {
   uint64_t desc;
@@ -52,6 +59,13 @@ __device__ inline void zero_counters(QCounters* c) {
   *c = z;
 }
 
+// Items per wave batch for a step over nin items run by nw waves: enough
+// that every wave gets work, at most WB_ITEMS.
+__host__ __device__ inline uint32_t wb_items(uint32_t nin, uint32_t nw) {
+  uint32_t k = nw ? (nin + nw - 1) / nw : WB_ITEMS;
+  return k < 1 ? 1 : (k > (uint32_t)WB_ITEMS ? (uint32_t)WB_ITEMS : k);
+}
+
 // Which buckets of a slab an item covers: tiles of `chunk` buckets starting
 // at bucket `first`.
 struct TileShape {
@@ -63,173 +77,21 @@ struct TileShape {
   }
 };
 
-// ------------------------------------------------------- LDS staging
-
-template <int N>
-struct ItemStageT {
-  uint32_t cnt;
-  uint32_t v[N];
-  uint64_t d[N];
-};
-template <int N>
-struct U32StageT {
-  uint32_t cnt;
-  uint32_t v[N];
-};
-
-struct Shared {
-  ItemStageT<STAGE> a;              // next-frontier items
-  union {
-    ItemStageT<STAGE_BIG> b;        // bottom-up chunk items
-    U32StageT<STAGE> u;             // far queue / discovery order
-  };
-  uint32_t wsum[Q_WAVES];
-  uint32_t base;
-  uint32_t flag;
-};
+// ------------------------------------------------------ wave helpers
 
 __device__ inline uint32_t wave_rank(unsigned long long m) {
   return (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
 }
 
-// Wave-uniform call: lanes with push append (v, desc).  Positions past the
-// stage capacity go straight to the global queue.
-template <int N>
-__device__ inline void stage_item(ItemStageT<N>& sb, bool push, uint32_t v, uint64_t desc, Item* gq,
-                                  uint32_t* gcnt, TileShape ts) {
-  unsigned long long m = __ballot(push);
-  if (m == 0) return;
-  int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(&sb.cnt, (uint32_t)__popcll(m));
-  base = __shfl(base, leader, 64);
-  uint32_t pos = base + wave_rank(m);
-  if (push) {
-    if (pos < (uint32_t)N) {
-      sb.v[pos] = v;
-      sb.d[pos] = desc;
-    } else {
-      uint32_t k = ts.tiles(desc);
-      uint32_t p = atomicAdd(gcnt, k);
-      for (uint32_t t = 0; t < k; t++) gq[p + t] = Item{desc, v, t};
-    }
-  }
-}
-
-template <int N>
-__device__ inline void stage_u32(U32StageT<N>& sb, bool push, uint32_t v, uint32_t* gq, uint32_t* gcnt) {
-  unsigned long long m = __ballot(push);
-  if (m == 0) return;
-  int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(&sb.cnt, (uint32_t)__popcll(m));
-  base = __shfl(base, leader, 64);
-  uint32_t pos = base + wave_rank(m);
-  if (push) {
-    if (pos < (uint32_t)N) sb.v[pos] = v;
-    else gq[atomicAdd(gcnt, 1u)] = v;
-  }
-}
-
-__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total, uint32_t* wsum) {
-  uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  uint32_t incl = x;
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= (uint32_t)o) incl += y;
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
   }
-  if (lane == 63) wsum[wave] = incl;
-  __syncthreads();
-  uint32_t off = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < Q_WAVES; w++) {
-    uint32_t s = wsum[w];
-    if ((uint32_t)w < wave) off += s;
-    tot += s;
-  }
-  *total = tot;
-  return off + incl - x;
+  return x;
 }
-
-// Workgroup-wide: write the staged vertices' tiles to the global queue.
-template <int N>
-__device__ inline void flush_items(ItemStageT<N>& sb, Item* gq, uint32_t* gcnt, TileShape ts, Shared& sh) {
-  constexpr int PER = (N + Q_THREADS - 1) / Q_THREADS;
-  __syncthreads();
-  uint32_t n = min(sb.cnt, (uint32_t)N);
-  if (n == 0) return;   // workgroup-uniform
-  uint32_t tl[PER];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    uint32_t e = threadIdx.x * PER + k;
-    tl[k] = e < n ? ts.tiles(sb.d[e]) : 0;
-    sum += tl[k];
-  }
-  uint32_t total;
-  uint32_t off = block_excl_scan(sum, &total, sh.wsum);
-  if (threadIdx.x == 0) {
-    sh.base = total ? atomicAdd(gcnt, total) : 0;
-    sb.cnt = 0;
-  }
-  __syncthreads();
-  uint32_t p = sh.base + off;
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    uint32_t e = threadIdx.x * PER + k;
-    if (e < n) {
-      uint64_t d = sb.d[e];
-      uint32_t v = sb.v[e];
-      for (uint32_t t = 0; t < tl[k]; t++) gq[p + t] = Item{d, v, t};
-    }
-    p += tl[k];
-  }
-  __syncthreads();
-}
-
-template <int N>
-__device__ inline void flush_u32(U32StageT<N>& sb, uint32_t* gq, uint32_t* gcnt, Shared& sh) {
-  __syncthreads();
-  uint32_t n = min(sb.cnt, (uint32_t)N);
-  if (n == 0) return;
-  if (threadIdx.x == 0) {
-    sh.base = atomicAdd(gcnt, n);
-    sb.cnt = 0;
-  }
-  __syncthreads();
-  for (uint32_t e = threadIdx.x; e < n; e += Q_THREADS) gq[sh.base + e] = sb.v[e];
-  __syncthreads();
-}
-
-__device__ inline void stages_init(Shared& sh) {
-  if (threadIdx.x == 0) {
-    sh.a.cnt = 0;
-    sh.b.cnt = 0;
-    sh.u.cnt = 0;
-  }
-  __syncthreads();
-}
-
-// Register counters, added once per wave.
-struct LaneCounts {
-  uint32_t verts = 0;
-  unsigned long long m = 0;
-  uint32_t arcs = 0;
-  __device__ void commit(QCounters* c) {
-    uint32_t v = wave_sum_u32(verts);
-    unsigned long long mm = wave_sum_u64(m);
-    unsigned long long a = wave_sum_u64(arcs);
-    if (lane_id() == 0) {
-      if (v) atomicAdd(&c->n_verts, v);
-      if (mm) atomicAdd(&c->m_next, mm);
-      if (a) atomicAdd(&c->arcs, a);
-    }
-  }
-};
-
-__device__ inline bool bm_test(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
-__device__ inline void bm_set(uint32_t* bm, uint32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
@@ -237,47 +99,226 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
-// The group's item: slab, first bucket and bucket count (0 when inactive).
-struct ItemView {
-  Slab s;
-  uint32_t b0, nbk, v;
-};
-
-__device__ inline ItemView view_item(const Pool& p, const Item* q, uint32_t idx, uint32_t n, TileShape ts) {
-  ItemView iv;
-  bool act = idx < n;
-  Item it = act ? q[idx] : Item{0, 0, 0};
-  iv.s = slab_of(p, it.desc);
-  iv.b0 = ts.first + it.tile * ts.chunk;
-  iv.nbk = act && iv.s.nb > iv.b0 ? min(ts.chunk, iv.s.nb - iv.b0) : 0;
-  iv.v = it.v;
-  return iv;
+// LDS written by some lanes of a wave is read by others after this.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Slot j of four consecutive buckets of an item (EMPTY past its end), with
-// visibility at e resolved from the bucket summaries and, where needed,
-// the stamps.
-struct Slots4 {
+// ------------------------------------------------- wave-private staging
+
+struct WaveStage {
+  uint32_t v[WSTAGE];
+  uint64_t d[WSTAGE];
+  uint32_t u[WSTAGE];
+};
+
+struct Shared {
+  WaveStage ws[Q_WAVES];
+  unsigned long long part[Q_WAVES][3];   // per-wave counter sums
+  uint32_t base;
+  uint32_t flag;
+};
+
+// A wave's item stage: LDS arrays plus a wave-uniform count.
+struct ItemQ {
+  uint32_t* v;
+  uint64_t* d;
+  uint32_t cap;
+  uint32_t n;
+};
+struct U32Q {
+  uint32_t* v;
+  uint32_t cap;
+  uint32_t n;
+};
+
+__device__ inline ItemQ item_q(WaveStage& s, uint32_t off, uint32_t cap) { return ItemQ{s.v + off, s.d + off, cap, 0}; }
+__device__ inline U32Q u32_q(WaveStage& s) { return U32Q{s.u, WSTAGE, 0}; }
+
+// Wave-uniform call: lanes with push append (v, desc).
+__device__ inline void push_item(ItemQ& q, bool push, uint32_t v, uint64_t desc) {
+  unsigned long long m = __ballot(push);
+  uint32_t pos = q.n + wave_rank(m);
+  if (push) {
+    q.v[pos] = v;
+    q.d[pos] = desc;
+  }
+  q.n += (uint32_t)__popcll(m);
+}
+
+__device__ inline void push_u32(U32Q& q, bool push, uint32_t v) {
+  unsigned long long m = __ballot(push);
+  uint32_t pos = q.n + wave_rank(m);
+  if (push) q.v[pos] = v;
+  q.n += (uint32_t)__popcll(m);
+}
+
+// Write the staged vertices' tiles to the global queue (one atomic).
+__device__ inline void flush_item_q(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts) {
+  constexpr int PER = WSTAGE / 64;
+  if (q.n == 0) return;   // wave-uniform
+  wave_lds_sync();
+  const uint32_t lane = lane_id();
+  uint32_t tl[PER];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    uint32_t e = lane * PER + k;
+    tl[k] = e < q.n ? ts.tiles(q.d[e]) : 0;
+    sum += tl[k];
+  }
+  uint32_t incl = wave_incl_scan(sum);
+  uint32_t total = __shfl(incl, 63, 64);
+  uint32_t gb = 0;
+  if (lane == 0 && total) gb = atomicAdd(gcnt, total);
+  uint32_t p = __shfl(gb, 0, 64) + incl - sum;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    uint32_t e = lane * PER + k;
+    if (e < q.n) {
+      uint64_t d = q.d[e];
+      uint32_t v = q.v[e];
+      for (uint32_t t = 0; t < tl[k]; t++) gq[p + t] = Item{d, v, t};
+    }
+    p += tl[k];
+  }
+  q.n = 0;
+  wave_lds_sync();
+}
+
+__device__ inline void flush_u32_q(U32Q& q, uint32_t* gq, uint32_t* gcnt) {
+  if (q.n == 0) return;
+  wave_lds_sync();
+  const uint32_t lane = lane_id();
+  uint32_t gb = 0;
+  if (lane == 0) gb = atomicAdd(gcnt, q.n);
+  gb = __shfl(gb, 0, 64);
+  for (uint32_t e = lane; e < q.n; e += 64) gq[gb + e] = q.v[e];
+  q.n = 0;
+  wave_lds_sync();
+}
+
+// Keep room for `next` more pushes.
+__device__ inline void room_item(ItemQ& q, uint32_t next, Item* gq, uint32_t* gcnt, TileShape ts) {
+  if (q.n + next > q.cap) flush_item_q(q, gq, gcnt, ts);
+}
+__device__ inline void room_u32(U32Q& q, uint32_t next, uint32_t* gq, uint32_t* gcnt) {
+  if (q.n + next > q.cap) flush_u32_q(q, gq, gcnt);
+}
+
+// Register counters, summed per workgroup and added with one atomic per
+// counter (workgroup-uniform call: it takes a barrier).
+struct LaneCounts {
+  uint32_t verts = 0;
+  unsigned long long m = 0;
+  uint32_t arcs = 0;
+  __device__ void commit(QCounters* c, Shared& sh) {
+    uint32_t v = wave_sum_u32(verts);
+    unsigned long long mm = wave_sum_u64(m);
+    unsigned long long a = wave_sum_u64(arcs);
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+      sh.part[wave][0] = v;
+      sh.part[wave][1] = mm;
+      sh.part[wave][2] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      unsigned long long t = 0;
+#pragma unroll
+      for (int w = 0; w < Q_WAVES; w++) t += sh.part[w][threadIdx.x];
+      if (t) {
+        if (threadIdx.x == 0) atomicAdd(&c->n_verts, (uint32_t)t);
+        else if (threadIdx.x == 1) atomicAdd(&c->m_next, t);
+        else atomicAdd(&c->arcs, t);
+      }
+    }
+    __syncthreads();
+  }
+};
+
+__device__ inline bool bm_test(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+__device__ inline void bm_set(uint32_t* bm, uint32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
+
+// ------------------------------------------------------- wave batches
+
+// Up to 16 items of a frontier queue; lane l (and l + 16, l + 32, l + 48)
+// holds item l.  Its buckets occupy flat positions [start, start + nbk) of the
+// batch, and flat position f of the item is bucket f + off of its slab.
+struct WaveBatch {
+  uint64_t desc;
+  uint32_t v, tile, nbk, start, off;
+  uint32_t total;   // buckets of the whole batch (wave-uniform)
+};
+
+__device__ inline WaveBatch wave_batch(const Item* q, uint32_t first, uint32_t wbn, uint32_t n, TileShape ts) {
+  WaveBatch wb;
+  const uint32_t l = lane_id() & (WB_ITEMS - 1);
+  const uint32_t idx = first + l;
+  Item it = l < wbn && idx < n ? q[idx] : Item{0, 0, 0};
+  uint32_t nb = it.desc ? 1u << (it.desc & 63) : 0;
+  uint32_t b0 = ts.first + it.tile * ts.chunk;
+  wb.nbk = nb > b0 ? min(ts.chunk, nb - b0) : 0;
+  uint32_t incl = wb.nbk;
+#pragma unroll
+  for (int o = 1; o < WB_ITEMS; o <<= 1) {
+    uint32_t y = __shfl_up(incl, o, WB_ITEMS);
+    if (l >= (uint32_t)o) incl += y;
+  }
+  wb.start = incl - wb.nbk;
+  wb.total = __shfl(incl, WB_ITEMS - 1, 64);
+  wb.off = b0 - wb.start;
+  wb.desc = it.desc;
+  wb.v = it.v;
+  wb.tile = it.tile;
+  return wb;
+}
+
+// Index (0..15) of the batch item owning flat position f < total.
+__device__ inline uint32_t batch_item(const WaveBatch& wb, uint32_t f) {
+  uint32_t idx = 0;
+#pragma unroll
+  for (int i = 1; i < WB_ITEMS; i++) idx += (uint32_t)__builtin_amdgcn_readlane((int)wb.start, i) <= f ? 1u : 0u;
+  return idx;
+}
+
+// Slot j of the four flat positions f0 + 4 grp + k of a batch (EMPTY past
+// its end), with visibility at e resolved from the bucket summaries and,
+// where needed, the stamps; item[k] is the owning batch item.
+struct Pairs4 {
   uint32_t d[4];
   int32_t w[4];
   bool vis[4];
+  uint32_t item[4];
 };
 
 template <bool WITH_W>
-__device__ inline Slots4 load4(const ItemView& iv, uint32_t i, uint32_t j, uint32_t e, bool fast) {
-  Slots4 r;
+__device__ inline Pairs4 load_pairs(const Pool& p, const WaveBatch& wb, uint32_t f0, uint32_t grp, uint32_t j,
+                                    uint32_t e, bool fast) {
+  Pairs4 r;
   uint2 sm[4];
+  uint32_t* bp[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
+    const uint32_t f = f0 + grp * 4 + k;
+    const uint32_t idx = batch_item(wb, f);
+    const uint64_t desc = __shfl(wb.desc, (int)idx, 64);
+    const uint32_t off = __shfl(wb.off, (int)idx, 64);
+    r.item[k] = idx;
     r.d[k] = EMPTY;
     r.w[k] = 0;
     sm[k] = make_uint2(0xFFFFFFFFu, 0xFFFFu);
-    if (i + k < iv.nbk) {
-      uint32_t b = iv.b0 + i + k;
-      uint32_t* bp = bucket_ptr(iv.s, b);
-      r.d[k] = bp[j];
-      if (WITH_W) r.w[k] = (int32_t)bp[16 + j];
-      if (fast) sm[k] = *reinterpret_cast<const uint2*>(&iv.s.sum[2 * b]);
+    bp[k] = p.base;
+    if (f < wb.total) {
+      Slab s = slab_of(p, desc);
+      const uint32_t b = f + off;
+      bp[k] = bucket_ptr(s, b);
+      r.d[k] = bp[k][j];
+      if (WITH_W) r.w[k] = (int32_t)bp[k][16 + j];
+      if (fast) sm[k] = *reinterpret_cast<const uint2*>(&s.sum[2 * b]);
     }
   }
 #pragma unroll
@@ -285,7 +326,7 @@ __device__ inline Slots4 load4(const ItemView& iv, uint32_t i, uint32_t j, uint3
     bool v = false;
     if (r.d[k] != EMPTY) {
       if (fast && sm[k].x <= e && !((sm[k].y >> j) & 1u)) v = true;
-      else v = visible(*slot_stamp(bucket_ptr(iv.s, iv.b0 + i + k), j, iv.s.words), e);
+      else v = visible(*slot_stamp(bp[k], j, p.words), e);
     }
     r.vis[k] = v;
   }
@@ -312,12 +353,14 @@ struct LevelArgs {
 __device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   LaneCounts lc;
-  for (uint32_t base = worker * Q_ITEMS_PER_BLOCK; base < nin; base += nworkers * Q_ITEMS_PER_BLOCK) {
-    ItemView iv = view_item(a.st.fp, a.qin, base + wave * 4 + grp, nin, ts);
-    uint32_t maxnb = wave_max_u32(iv.nbk);
-    for (uint32_t i = 0; i < maxnb; i += 4) {
-      Slots4 s4 = load4<false>(iv, i, j, a.e, a.fast);
+  const uint32_t wbn = wb_items(nin, nw);
+  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
+    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
+    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
+      Pairs4 s4 = load_pairs<false>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         bool found = false;
@@ -333,12 +376,13 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32
           lc.verts++;
           lc.m += a.st.fused[d];
         }
-        stage_item(sh.a, found, d, yd, a.qout, &a.cnt_out->n_items, ts);
+        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        push_item(qn, found, d, yd);
       }
     }
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
   }
-  lc.commit(a.cnt_out);
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  lc.commit(a.cnt_out, sh);
 }
 
 // Bottom-up, one unvisited vertex per lane: a one-bucket in-slab (the
@@ -350,9 +394,13 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
   const uint32_t V = a.st.V;
   const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
   const uint64_t* idesc = a.st.undirected ? a.st.fdesc : a.st.rdesc;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE / 2);
+  ItemQ qb = item_q(sh.ws[wave], WSTAGE / 2, WSTAGE / 2);
   LaneCounts lc;
-  for (uint32_t base = worker * Q_THREADS; base < V; base += nworkers * Q_THREADS) {
-    uint32_t y = base + threadIdx.x;
+  for (uint32_t base = gw * 64; base < V; base += nw * 64) {
+    uint32_t y = base + lane_id();
     bool act = y < V && a.dist[y] < 0;
     uint64_t ydesc_in = act ? idesc[y] : 0;
     Slab s = slab_of(ip, ydesc_in);
@@ -393,12 +441,31 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
       lc.verts++;
       lc.m += a.st.fused[y];
     }
-    stage_item(sh.a, found, y, yd, a.qout, &a.cnt_out->n_items, ts);
-    stage_item(sh.b, act && s.nb > 1, y, ydesc_in, a.qbig, &a.cnt_out->n_big, tbig);
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
-    flush_items(sh.b, a.qbig, &a.cnt_out->n_big, tbig, sh);
+    room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+    push_item(qn, found, y, yd);
+    room_item(qb, 64, a.qbig, &a.cnt_out->n_big, tbig);
+    push_item(qb, act && s.nb > 1, y, ydesc_in);
   }
-  lc.commit(a.cnt_out);
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_item_q(qb, a.qbig, &a.cnt_out->n_big, tbig);
+  lc.commit(a.cnt_out, sh);
+}
+
+// View of one chunk item for a 16-lane group.
+struct ItemView {
+  Slab s;
+  uint32_t b0, nbk, v;
+};
+
+__device__ inline ItemView view_item(const Pool& p, const Item* q, uint32_t idx, uint32_t n, TileShape ts) {
+  ItemView iv;
+  bool act = idx < n;
+  Item it = act ? q[idx] : Item{0, 0, 0};
+  iv.s = slab_of(p, it.desc);
+  iv.b0 = ts.first + it.tile * ts.chunk;
+  iv.nbk = act && iv.s.nb > iv.b0 ? min(ts.chunk, iv.s.nb - iv.b0) : 0;
+  iv.v = it.v;
+  return iv;
 }
 
 // Chunk items of multi-bucket in-slabs: 16 lanes per chunk; a chunk whose
@@ -407,22 +474,41 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
                                    Shared& sh) {
   const TileShape ts{0, a.T}, tbig{0, BU_CHUNK};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   LaneCounts lc;
-  for (uint32_t base = worker * Q_ITEMS_PER_BLOCK; base < nbig; base += nworkers * Q_ITEMS_PER_BLOCK) {
-    ItemView iv = view_item(ip, a.qbig, base + wave * 4 + grp, nbig, tbig);
+  for (uint32_t base = gw * 4; base < nbig; base += nw * 4) {
+    ItemView iv = view_item(ip, a.qbig, base + grp, nbig, tbig);
     uint32_t y = iv.v;
     if (iv.nbk && a.dist[y] >= 0) iv.nbk = 0;
     uint32_t maxnb = wave_max_u32(iv.nbk);
     bool found = false;
     for (uint32_t i = 0; i < maxnb; i += 4) {
-      Slots4 s4 = load4<false>(iv, i, j, a.e, a.fast);
       bool hit = false;
+      uint32_t d[4];
+      uint32_t* bp[4];
+      uint2 sm[4];
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        if (s4.vis[k]) {
+        d[k] = EMPTY;
+        bp[k] = iv.s.base;
+        sm[k] = make_uint2(0xFFFFFFFFu, 0xFFFFu);
+        if (!found && i + k < iv.nbk) {
+          const uint32_t b = iv.b0 + i + k;
+          bp[k] = bucket_ptr(iv.s, b);
+          d[k] = bp[k][j];
+          if (a.fast) sm[k] = *reinterpret_cast<const uint2*>(&iv.s.sum[2 * b]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (d[k] == EMPTY) continue;
+        bool vis = (a.fast && sm[k].x <= a.e && !((sm[k].y >> j) & 1u)) ||
+                   visible(*slot_stamp(bp[k], j, iv.s.words), a.e);
+        if (vis) {
           lc.arcs++;
-          hit |= bm_test(a.bm_cur, s4.d[k]);
+          hit |= bm_test(a.bm_cur, d[k]);
         }
       }
       if (group16_ballot(hit)) found = true;
@@ -436,10 +522,11 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
       lc.verts++;
       lc.m += a.st.fused[y];
     }
-    stage_item(sh.a, win, y, yd, a.qout, &a.cnt_out->n_items, ts);
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
+    room_item(qn, 4, a.qout, &a.cnt_out->n_items, ts);
+    push_item(qn, win, y, yd);
   }
-  lc.commit(a.cnt_out);
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  lc.commit(a.cnt_out, sh);
 }
 
 // ----------------------------------------------------------------- SSSP
@@ -473,21 +560,25 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
                                   Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
+  U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
-  for (uint32_t base = worker * Q_ITEMS_PER_BLOCK; base < nin; base += nworkers * Q_ITEMS_PER_BLOCK) {
-    ItemView iv = view_item(a.st.fp, a.qin, base + wave * 4 + grp, nin, ts);
-    int32_t du = iv.nbk ? __hip_atomic_load(&a.dist[iv.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  const uint32_t wbn = wb_items(nin, nw);
+  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
+    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
+    const int32_t du_l = wb.nbk ? __hip_atomic_load(&a.dist[wb.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (a.mode == 1) {
       // the first tile's item records its vertex for the bucket's heavy pass
-      bool rec = iv.nbk && iv.b0 == 0 && j == 0 && atomicExch(&a.rstamp[iv.v], a.phase) != a.phase;
+      bool rec = lane_id() < WB_ITEMS && wb.nbk && wb.tile == 0 && atomicExch(&a.rstamp[wb.v], a.phase) != a.phase;
       uint32_t pos = wave_reserve(a.rcount, rec ? 1u : 0u);
-      if (rec) a.rlist[pos] = iv.v;
+      if (rec) a.rlist[pos] = wb.v;
     }
-    uint32_t maxnb = wave_max_u32(iv.nbk);
-    for (uint32_t i = 0; i < maxnb; i += 4) {
-      Slots4 s4 = load4<true>(iv, i, j, a.e, a.fast);
+    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
+      Pairs4 s4 = load_pairs<true>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
+        const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
         bool to_near = false, to_far = false;
         uint32_t d = s4.d[k];
         bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
@@ -504,14 +595,16 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
         }
         uint64_t yd = to_near ? a.st.fdesc[d] : 0;
         lc.verts += to_near ? 1 : 0;
-        stage_item(sh.a, to_near, d, yd, a.qout, &a.cnt_out->n_items, ts);
-        stage_u32(sh.u, to_far, d, a.far_out, &a.cnt_out->n_far);
+        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        push_item(qn, to_near, d, yd);
+        room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
+        push_u32(qf, to_far, d);
       }
     }
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
-    flush_u32(sh.u, a.far_out, &a.cnt_out->n_far, sh);
   }
-  lc.commit(a.cnt_out);
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
+  lc.commit(a.cnt_out, sh);
 }
 
 // Items of every vertex in list[0..n): the recorded vertices of a settled
@@ -520,14 +613,18 @@ __device__ __forceinline__ void expand_step(const Store& st, const uint32_t* lis
                                             QCounters* cnt_out, uint32_t T, uint32_t worker, uint32_t nworkers,
                                             Shared& sh) {
   const TileShape ts{0, T};
-  for (uint32_t base = worker * Q_THREADS; base < n; base += nworkers * Q_THREADS) {
-    uint32_t i = base + threadIdx.x;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
+  for (uint32_t base = gw * 64; base < n; base += nw * 64) {
+    uint32_t i = base + lane_id();
     bool act = i < n;
     uint32_t v = act ? list[i] : 0;
     uint64_t vd = act ? st.fdesc[v] : 0;
-    stage_item(sh.a, act && vd != 0, v, vd, qout, &cnt_out->n_items, ts);
-    flush_items(sh.a, qout, &cnt_out->n_items, ts, sh);
+    room_item(qn, 64, qout, &cnt_out->n_items, ts);
+    push_item(qn, act && vd != 0, v, vd);
   }
+  flush_item_q(qn, qout, &cnt_out->n_items, ts);
 }
 
 struct SplitArgs {
@@ -549,10 +646,14 @@ struct SplitArgs {
 __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
   const TileShape ts{0, a.T};
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
+  U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
   int32_t mn = DIST_INF;
-  for (uint32_t base = worker * Q_THREADS; base < nin; base += nworkers * Q_THREADS) {
-    uint32_t i = base + threadIdx.x;
+  for (uint32_t base = gw * 64; base < nin; base += nw * 64) {
+    uint32_t i = base + lane_id();
     bool act = i < nin;
     uint32_t v = act ? a.far_in[i] : 0;
     int32_t dv = act ? a.dist[v] : DIST_INF;
@@ -565,15 +666,17 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uin
     if (keep) mn = min(mn, dv);
     uint64_t vd = near ? a.st.fdesc[v] : 0;
     lc.verts += near ? 1 : 0;
-    stage_item(sh.a, near, v, vd, a.qout, &a.cnt_out->n_items, ts);
-    stage_u32(sh.u, keep, v, a.far_out, &a.cnt_out->n_far);
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
-    flush_u32(sh.u, a.far_out, &a.cnt_out->n_far, sh);
+    room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+    push_item(qn, near, v, vd);
+    room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
+    push_u32(qf, keep, v);
   }
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
   if (lane_id() == 0 && mn < DIST_INF) atomicMin(&a.cnt_out->far_min, mn);
-  lc.commit(a.cnt_out);
+  lc.commit(a.cnt_out, sh);
 }
 
 // ------------------------------------------------------------------- BC
@@ -597,16 +700,20 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uin
                                   Shared& sh) {
   const TileShape ts{0, a.T};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
+  const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
+  U32Q qo = u32_q(sh.ws[wave]);
   LaneCounts lc;
   uint32_t ovf = 0;
-  for (uint32_t base = worker * Q_ITEMS_PER_BLOCK; base < nin; base += nworkers * Q_ITEMS_PER_BLOCK) {
-    ItemView iv = view_item(a.st.fp, a.qin, base + wave * 4 + grp, nin, ts);
-    unsigned long long su = iv.nbk ? a.sigma[iv.v] : 0;
-    uint32_t maxnb = wave_max_u32(iv.nbk);
-    for (uint32_t i = 0; i < maxnb; i += 4) {
-      Slots4 s4 = load4<false>(iv, i, j, a.e, a.fast);
+  const uint32_t wbn = wb_items(nin, nw);
+  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
+    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
+    const unsigned long long su_l = wb.nbk ? a.sigma[wb.v] : 0;
+    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
+      Pairs4 s4 = load_pairs<false>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
+        const unsigned long long su = __shfl(su_l, (int)s4.item[k], 64);
         bool found = false;
         uint32_t d = s4.d[k];
         if (s4.vis[k]) {
@@ -626,15 +733,17 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uin
         }
         uint64_t yd = found ? a.st.fdesc[d] : 0;
         lc.verts += found ? 1 : 0;
-        stage_item(sh.a, found, d, yd, a.qout, &a.cnt_out->n_items, ts);
-        stage_u32(sh.u, found, d, a.order, &a.cnt_total->n_order);
+        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        push_item(qn, found, d, yd);
+        room_u32(qo, 64, a.order, &a.cnt_total->n_order);
+        push_u32(qo, found, d);
       }
     }
-    flush_items(sh.a, a.qout, &a.cnt_out->n_items, ts, sh);
-    flush_u32(sh.u, a.order, &a.cnt_total->n_order, sh);
   }
+  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_u32_q(qo, a.order, &a.cnt_total->n_order);
   if (ovf) atomicOr(&a.cnt_total->overflow, 1u);
-  lc.commit(a.cnt_out);
+  lc.commit(a.cnt_out, sh);
 }
 
 // One wave per vertex of level L: delta[v] = sum over visible arcs v->w

@@ -23,6 +23,8 @@
 
 #include "dg_host.h"
 #include "frontier.h"
+#include <map>
+#include <mutex>
 
 namespace dg {
 
@@ -72,27 +74,23 @@ __device__ inline void reset_other(QCounters* c) {
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, uint32_t nin, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   td_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   bu_step(a, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a) {
   __shared__ Shared sh;
-  stages_init(sh);
   bu_big_step(a, a.cnt_out->n_big, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, uint32_t nin, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   relax_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
@@ -100,21 +98,18 @@ __global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint3
                                                             QCounters* cnt_out, uint32_t T, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   expand_step(st, list, n, qout, cnt_out, T, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t nin, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   split_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, uint32_t nin, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  stages_init(sh);
   bcfwd_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
@@ -203,6 +198,39 @@ static uint32_t grid_for(uint64_t units, uint32_t per_block, uint32_t cap = 1638
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
 }
 
+// Workgroups of `kernel` resident on the current device at once.
+static uint32_t resident(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, uint32_t> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(dev, kernel);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, Q_THREADS, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  const uint32_t r = (uint32_t)std::max(1, per_cu * cus);
+  cache[key] = r;
+  return r;
+}
+
+// Grid of an item step: enough waves, each taking wave batches of
+// wb_items(nin, resident waves) items, and never more than fit at once.
+static uint32_t items_grid(const void* kernel, uint32_t nin) {
+  const uint32_t rb = resident(kernel);
+  const uint32_t wbn = wb_items(nin, rb * Q_WAVES);
+  const uint64_t waves = ((uint64_t)nin + wbn - 1) / wbn;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((waves + Q_WAVES - 1) / Q_WAVES, rb));
+}
+
+// Grid of a step with one unit per lane, at most what fits at once.
+static uint32_t lanes_grid(const void* kernel, uint64_t n) {
+  return grid_for(n, Q_THREADS, resident(kernel));
+}
+
 static dg_status hip_fail(dg_graph* g, hipError_t e, const char* where) {
   g->err = std::string(where) + ": " + hipGetErrorString(e);
   return DG_E_HIP;
@@ -244,11 +272,11 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
     LevelArgs a{g->st, e, fast, qin, qout, qbig, bm[cur], bm[nxt], dist, level + 1, T, cnt + nxt};
     if (bu) {
       ProfScope ps(g, KID_BFS_BU, s);
-      k_bfs_bu<<<grid_for(V, Q_THREADS), Q_THREADS, 0, s>>>(a, cnt + cur);
-      k_bfs_bu_big<<<BIG_GRID, Q_THREADS, 0, s>>>(a);
+      k_bfs_bu<<<lanes_grid((const void*)k_bfs_bu, V), Q_THREADS, 0, s>>>(a, cnt + cur);
+      k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a);
     } else {
       ProfScope ps(g, KID_BFS_TD, s);
-      k_bfs_td<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+      k_bfs_td<<<items_grid((const void*)k_bfs_td, n_items), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bfs level launch");
     if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
@@ -305,7 +333,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
                 mode, delta, rlist, rcount, rstamp, phase};
     {
       ProfScope ps(g, KID_SSSP_RELAX, s);
-      k_sssp_relax<<<grid_for(nin, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, nin, cnt + slot);
+      k_sssp_relax<<<items_grid((const void*)k_sssp_relax, nin), Q_THREADS, 0, s>>>(a, nin, cnt + slot);
     }
     hipError_t r = hipGetLastError();
     if (r != hipSuccess) return r;
@@ -330,7 +358,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
         fill<uint32_t>(rcount, 1, 0u, s);
         n_rec = 0;
         int nxt = slot ^ 1;
-        k_sssp_expand<<<grid_for(n_r, Q_THREADS), Q_THREADS, 0, s>>>(g->st, rlist, n_r, qin, cnt + nxt, T,
+        k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(g->st, rlist, n_r, qin, cnt + nxt, T,
                                                                      cnt + slot);
         if ((he = hipGetLastError()) != hipSuccess || (he = read_counters(q, nxt, &hc, s)) != hipSuccess)
           return hip_fail(g, he, "sssp expand");
@@ -352,7 +380,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
       SplitArgs a{g->st, fin, fout, qin, dist, stamp, infar, thr, it, T, cnt + nxt};
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);
-        k_sssp_split<<<grid_for(n_far, Q_THREADS), Q_THREADS, 0, s>>>(a, n_far, cnt + slot);
+        k_sssp_split<<<lanes_grid((const void*)k_sssp_split, n_far), Q_THREADS, 0, s>>>(a, n_far, cnt + slot);
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
@@ -410,7 +438,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
       BcFwdArgs a{g->st, e, fast, qin, qout, order, level, sigma, lvl + 1, T, cnt + nxt, tot};
       if (n_items) {
         ProfScope ps(g, KID_BC_FWD, s);
-        k_bc_fwd<<<grid_for(n_items, Q_ITEMS_PER_BLOCK), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+        k_bc_fwd<<<items_grid((const void*)k_bc_fwd, n_items), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
       } else {
         fill<unsigned long long>(reinterpret_cast<unsigned long long*>(cnt + nxt), sizeof(QCounters) / 8, 0ull, s);
       }
