@@ -144,10 +144,11 @@ typedef struct {
 dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query,
                          void* stream);
 
-/* Frontier-tile tuning.  dg_autotune times candidate shapes on the latest
- * epoch and keeps the fastest; dg_get_tuning reports the shape in use. */
+/* Traversal tuning.  dg_autotune times candidate values on the latest epoch
+ * and keeps the fastest; dg_get_tuning reports the values in use.  None of
+ * them changes a result. */
 typedef struct {
-  uint32_t tile_buckets;   /* buckets per frontier work item (1..64, power of 2) */
+  uint32_t chunk_buckets;  /* buckets of a frontier work chunk handed to one wave: 16, 32 or 64 */
   uint32_t sssp_delta;     /* delta-stepping bucket width */
   uint32_t alpha, beta;    /* direction-switch thresholds of the BFS */
   uint32_t batch_groups;   /* workgroups per query team in the persistent launch; 0 = automatic */

@@ -634,7 +634,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
 
 dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t) {
   if (!g || !t) return DG_E_INVALID_ARG;
-  t->tile_buckets = g->tune.tile_buckets;
+  t->chunk_buckets = g->tune.chunk_buckets;
   t->sssp_delta = g->tune.sssp_delta;
   t->alpha = g->tune.alpha;
   t->beta = g->tune.beta;
@@ -645,17 +645,12 @@ dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t) {
 
 dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t) {
   if (!g || !t) return DG_E_INVALID_ARG;
-  uint32_t T = t->tile_buckets;
-  if (T == 0 || T > 64 || (T & (T - 1))) return fail(g, DG_E_INVALID_ARG, "tile_buckets must be a power of 2 in [1, 64]");
+  const uint32_t C = t->chunk_buckets;
+  if (C != 16 && C != 32 && C != 64) return fail(g, DG_E_INVALID_ARG, "chunk_buckets must be 16, 32 or 64");
   if (t->sssp_delta == 0 || t->alpha == 0 || t->beta == 0 || t->batch_delta == 0)
     return fail(g, DG_E_INVALID_ARG, "tuning values must be positive");
   std::lock_guard<std::mutex> lk(g->mu);
-  if (T < g->tune.tile_buckets) {
-    // smaller tiles need longer item queues
-    free_query_scratch(g->qs);
-    free_batch_state(g);
-  }
-  g->tune.tile_buckets = T;
+  g->tune.chunk_buckets = C;
   g->tune.sssp_delta = t->sssp_delta;
   g->tune.alpha = t->alpha;
   g->tune.beta = t->beta;

@@ -62,6 +62,10 @@ struct QDesc {
 struct TeamScratch {
   Item* qa;
   Item* qb;
+  uint32_t* cmap_a;       // chunk maps of qa / qb
+  uint32_t* cmap_b;
+  uint32_t qcap, ccap;    // their capacities
+  uint32_t lch;           // log2 of the chunk size
   Item* qbig;
   uint32_t* bm0;          // three rotating frontier bitmaps
   uint32_t* bm1;
@@ -83,7 +87,6 @@ struct TeamScratch {
 struct BatchArgs {
   Store st;
   int fast;
-  uint32_t T;
   int32_t delta;
   int32_t w_max;
   uint32_t alpha, beta;
@@ -145,7 +148,7 @@ __device__ inline void team_fill(T* p, uint64_t n, T v, uint32_t w, uint32_t S) 
 
 __device__ inline QCounters read_cnt(const QCounters* c) {
   QCounters r;
-  r.n_items = ld_relaxed(&c->n_items);
+  r.fq = ld_relaxed(&c->fq);
   r.n_verts = ld_relaxed(&c->n_verts);
   r.m_next = ld_relaxed(&c->m_next);
   r.n_far = ld_relaxed(&c->n_far);
@@ -156,15 +159,22 @@ __device__ inline QCounters read_cnt(const QCounters* c) {
   return r;
 }
 
-// Worker 0 of the team writes the seed frontier of src into q and counters
-// slot 0 (the caller has set dist/level[src] and cleared the other slots).
-__device__ inline void team_seed(const Store& st, uint32_t src, Item* q, QCounters* c0, uint32_t T, uint32_t w) {
-  if (w != 0 || threadIdx.x != 0) return;
-  uint64_t desc = st.fdesc[src];
-  TileShape ts{0, T};
-  uint32_t k = ts.tiles(desc);
-  for (uint32_t t = 0; t < k; t++) q[t] = Item{desc, src, t};
-  c0->n_items = k;
+__device__ inline Front team_front(const TeamScratch& ts, int which) {
+  return Front{which ? ts.qb : ts.qa, which ? ts.cmap_b : ts.cmap_a, ts.qcap, ts.ccap, ts.lch};
+}
+
+// Worker 0 of the team writes the seed frontier of src into queue qa, its
+// chunk map and counters slot 0 (the caller has set dist/level[src] and
+// cleared the other slots).
+__device__ inline void team_seed(const Store& st, uint32_t src, const TeamScratch& ts, QCounters* c0, uint32_t w) {
+  if (w != 0) return;
+  const uint64_t desc = st.fdesc[src];
+  const uint32_t nb = desc ? 1u << (desc & 63) : 0;
+  const uint32_t nc = (nb + (1u << ts.lch) - 1) >> ts.lch;
+  for (uint32_t c = threadIdx.x; c < nc && c < ts.ccap; c += blockDim.x) ts.cmap_a[c] = 0;
+  if (threadIdx.x != 0) return;
+  if (nb) ts.qa[0] = Item{desc, src, 0};
+  c0->fq = nb ? 1ull | ((unsigned long long)nb << 32) : 0ull;
   c0->n_verts = 1;
   c0->m_next = st.fused[src];
 }
@@ -174,8 +184,18 @@ __device__ inline void team_seed(const Store& st, uint32_t src, Item* q, QCounte
     if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return false; \
   } while (0)
 
-__device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
-                        uint32_t& gen, Shared& sh) {
+// A frontier queue ran out of room: the query fails (every member reads the
+// same counters after the barrier, so all leave together).
+#define QUEUE_CHECK(cnt)                                                          \
+  do {                                                                            \
+    if (ld_relaxed(&(cnt)->overflow) & OVF_QUEUE) {                               \
+      if (w == 0 && threadIdx.x == 0) *status = DG_E_OUT_OF_MEMORY;              \
+      return true;                                                                \
+    }                                                                             \
+  } while (0)
+
+__device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
+                                        uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   const uint64_t bmw = (V + 31) / 32 + 1;
   int32_t* dist = static_cast<int32_t*>(qd.out);
@@ -189,13 +209,11 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
     dist[qd.src] = 0;
     ts.bm0[qd.src >> 5] |= 1u << (qd.src & 31);
   }
-  team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
+  team_seed(a.st, qd.src, ts, &ts.cnt[0], w);
   BARRIER();
   int64_t m_u = (int64_t)a.arcs[qd.epoch];
   const uint64_t n_live = a.live[qd.epoch] ? a.live[qd.epoch] : 1;
   bool bu = false;
-  const Item* qin = ts.qa;
-  Item* qout = ts.qb;
   for (uint32_t level = 0;; level++) {
     QCounters c = read_cnt(&ts.cnt[level % 3]);
     if (c.n_verts == 0) break;
@@ -206,26 +224,24 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
     uint32_t* bnext = bm_at(ts, (level + 1) % 3);
     team_fill<uint32_t>(bm_at(ts, (level + 2) % 3), bmw, 0u, w, S);
     if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(level + 2) % 3]);
-    LevelArgs la{a.st, qd.epoch, a.fast, qin, qout, ts.qbig, bm_at(ts, level % 3), bnext, dist,
-                 (int32_t)level + 1, a.T, cout};
+    LevelArgs la{a.st,   qd.epoch, a.fast, team_front(ts, level & 1), team_front(ts, (level + 1) & 1), ts.qbig,
+                 bm_at(ts, level % 3), bnext, dist, (int32_t)level + 1, cout};
     if (bu) {
       bu_step(la, w, S, sh);
       BARRIER();
       bu_big_step(la, ld_relaxed(&cout->n_big), w, S, sh);
     } else {
-      td_step(la, c.n_items, w, S, sh);
+      td_step(la, c.fq, w, S, sh);
     }
     BARRIER();
     add_step_arcs(a.ctrl, cout, w);
-    const Item* t = qin;
-    qin = qout;
-    qout = const_cast<Item*>(t);
+    QUEUE_CHECK(cout);
   }
   return true;
 }
 
-__device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
-                         uint32_t& gen, Shared& sh) {
+__device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
+                                         uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   int32_t* dist = static_cast<int32_t*>(qd.out);
   // with delta >= w_max every arc is light and the heavy passes vanish
@@ -239,38 +255,43 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
     for (int i = 0; i < 4; i++) zero_counters(&ts.cnt[i]);
   BARRIER();
   if (w == 0 && threadIdx.x == 0) dist[qd.src] = 0;
-  team_seed(a.st, qd.src, ts.qa, &ts.cnt[0], a.T, w);
+  team_seed(a.st, qd.src, ts, &ts.cnt[0], w);
   BARRIER();
-  Item* qin = ts.qa;
-  Item* qout = ts.qb;
+  int qi = 0;   // queue holding the current near frontier
   uint32_t* fin = ts.fa;
   uint32_t* fout = ts.fb;
-  uint32_t n_near = ld_relaxed(&ts.cnt[0].n_items), n_far = 0;
+  unsigned long long near = ld_relaxed(&ts.cnt[0].fq);
+  uint32_t n_far = 0;
   int32_t thr = a.delta;
   uint32_t it = 1;
   uint32_t phase = 1;  // bucket number (stamp of the recorded vertices)
   uint32_t slot = 0;   // counters slot holding the last pass's results
-  auto relax = [&](uint32_t nin, int mode) -> bool {
+  bool ovf = false;
+  auto relax = [&](unsigned long long nfq, int mode) -> bool {
     uint32_t nx = (slot + 1) % 3;
     if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-    RelaxArgs ra{a.st, qd.epoch, a.fast, qin, qout, fin + n_far, dist, ts.stamp, ts.infar, thr, it, a.T,
-                 &ts.cnt[nx], mode, a.delta, ts.rlist, rcount, ts.rstamp, phase};
-    relax_step(ra, nin, w, S, sh);
+    RelaxArgs ra{a.st, qd.epoch,    a.fast, team_front(ts, qi), team_front(ts, qi ^ 1), fin + n_far,
+                 dist, ts.stamp,    ts.infar, thr,              it,                     &ts.cnt[nx],
+                 mode, a.delta,     ts.rlist, rcount,           ts.rstamp,              phase};
+    relax_step(ra, nfq, w, S, sh);
     BARRIER();
     add_step_arcs(a.ctrl, &ts.cnt[nx], w);
     QCounters c = read_cnt(&ts.cnt[nx]);
-    n_near = c.n_items;
+    ovf |= (c.overflow & OVF_QUEUE) != 0;
+    near = c.fq;
     n_far += c.n_far;
-    Item* t = qin;
-    qin = qout;
-    qout = t;
+    qi ^= 1;
     it++;
     slot = nx;
     return true;
   };
   for (;;) {
-    if (n_near > 0) {
-      if (!relax(n_near, split_lh ? 1 : 0)) return false;
+    if (ovf) {
+      if (w == 0 && threadIdx.x == 0) *status = DG_E_OUT_OF_MEMORY;
+      return true;
+    }
+    if (near) {
+      if (!relax(near, split_lh ? 1 : 0)) return false;
       continue;
     }
     if (split_lh) {
@@ -279,18 +300,19 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
       if (n_r) {
         uint32_t nx = (slot + 1) % 3;
         if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-        expand_step(a.st, ts.rlist, n_r, qin, &ts.cnt[nx], a.T, w, S, sh);
+        expand_step(a.st, ts.rlist, n_r, team_front(ts, qi), &ts.cnt[nx], w, S, sh);
         BARRIER();
         if (w == 0 && threadIdx.x == 0) st_relaxed(rcount, 0u);
         slot = nx;
-        const uint32_t n_h = ld_relaxed(&ts.cnt[nx].n_items);
-        if (n_h && !relax(n_h, 2)) return false;
+        QUEUE_CHECK(&ts.cnt[nx]);
+        const unsigned long long nh = ld_relaxed(&ts.cnt[nx].fq);
+        if (nh && !relax(nh, 2)) return false;
         // the reset of rcount is published by the heavy pass's barrier
-        if (!n_h) BARRIER();
+        if (!nh) BARRIER();
       }
       phase++;
       // heavy arcs leave the bucket (w > delta); should any land in it, keep going
-      if (n_near > 0) continue;
+      if (near) continue;
     }
     if (n_far == 0) break;
     int32_t far_min = DIST_INF;
@@ -299,7 +321,7 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
                                 : (int32_t)min((int64_t)DIST_INF, ((int64_t)far_min / a.delta + 1) * a.delta);
       uint32_t nx = (slot + 1) % 3;
       if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-      SplitArgs sa{a.st, fin, fout, qin, dist, ts.stamp, ts.infar, thr, it, a.T, &ts.cnt[nx]};
+      SplitArgs sa{a.st, fin, fout, team_front(ts, qi), dist, ts.stamp, ts.infar, thr, it, &ts.cnt[nx]};
       split_step(sa, n_far, w, S, sh);
       BARRIER();
       QCounters c = read_cnt(&ts.cnt[nx]);
@@ -307,10 +329,11 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
       fin = fout;
       fout = t;
       n_far = c.n_far;
-      n_near = c.n_items;
+      near = c.fq;
       far_min = c.far_min;
       slot = nx;
-    } while (n_near == 0 && n_far > 0);
+      QUEUE_CHECK(&ts.cnt[nx]);
+    } while (!near && n_far > 0);
     it++;
   }
   for (uint64_t i = (uint64_t)w * Q_THREADS + threadIdx.x; i < V; i += (uint64_t)S * Q_THREADS)
@@ -318,8 +341,8 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
   return true;
 }
 
-__device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w, uint32_t S,
-                       uint32_t& gen, Shared& sh, int32_t* status) {
+__device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
+                                       uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   double* bc = static_cast<double*>(qd.out);
   team_fill<double>(bc, V, 0.0, w, S);
@@ -338,31 +361,28 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
       ts.off[0] = 0;
       ts.off[1] = 1;
     }
-    team_seed(a.st, src, ts.qa, &ts.cnt[0], a.T, w);
+    team_seed(a.st, src, ts, &ts.cnt[0], w);
     BARRIER();
-    const Item* qin = ts.qa;
-    Item* qout = ts.qb;
     uint32_t nlev = 1;   // levels discovered so far (level 0 = src)
     for (uint32_t lvl = 0;; lvl++) {
       QCounters c = read_cnt(&ts.cnt[lvl % 3]);
       if (lvl > 0 && c.n_verts == 0) break;
       QCounters* cout = &ts.cnt[(lvl + 1) % 3];
       if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(lvl + 2) % 3]);
-      BcFwdArgs fa{a.st, qd.epoch, a.fast, qin, qout, ts.fa, ts.level, ts.sigma, (int32_t)lvl + 1, a.T, cout,
+      BcFwdArgs fa{a.st,     qd.epoch,  a.fast,   team_front(ts, lvl & 1), team_front(ts, (lvl + 1) & 1),
+                   ts.fa,    ts.level,  ts.sigma, (int32_t)lvl + 1,        cout,
                    &ts.cnt[3]};
-      bcfwd_step(fa, c.n_items, w, S, sh);
+      bcfwd_step(fa, c.fq, w, S, sh);
       BARRIER();
       add_step_arcs(a.ctrl, cout, w);
+      QUEUE_CHECK(cout);
       uint32_t found = ld_relaxed(&cout->n_verts);
       if (found == 0) break;
       if (w == 0 && threadIdx.x == 0) ts.off[nlev + 1] = ts.off[nlev] + found;
       nlev++;
-      const Item* t = qin;
-      qin = qout;
-      qout = const_cast<Item*>(t);
     }
     BARRIER();
-    if (ld_relaxed(&ts.cnt[3].overflow)) {
+    if (ld_relaxed(&ts.cnt[3].overflow) & OVF_SIGMA) {
       if (w == 0 && threadIdx.x == 0) *status = DG_E_OVERFLOW;
       return true;
     }
@@ -436,8 +456,8 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
     const QDesc qd = a.q[qi];
     bool ok = true;
     if (a.status[qi] == DG_OK) {
-      if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh);
-      else if (KIND == DG_Q_SSSP) ok = run_sssp(a, qd, ts, w, S, gen, sh);
+      if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);
+      else if (KIND == DG_Q_SSSP) ok = run_sssp(a, qd, ts, w, S, gen, sh, &a.status[qi]);
       else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
     }
     if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
@@ -479,9 +499,10 @@ void free_batch_state(dg_graph* g) {
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Bytes of one team's scratch and, if base is set, the pointers into it.
-static uint64_t team_layout(const Store& st, uint32_t T, char* base, TeamScratch* ts) {
+static uint64_t team_layout(const Store& st, uint32_t chunk_buckets, char* base, TeamScratch* ts) {
   const uint64_t V = st.V;
-  const uint64_t items = V + st.fp.cap / std::max<uint32_t>(1, T) + 1024;
+  const uint64_t items = V + 1024;          // a frontier holds each vertex at most once
+  const uint64_t chunks = st.fp.cap / CH_MIN + 2;
   const uint64_t big = V + std::max(st.fp.cap, st.rp.cap) / BU_CHUNK + 1024;
   const uint64_t bmw = (V + 31) / 32 + 1;
   uint64_t o = 0;
@@ -493,6 +514,13 @@ static uint64_t team_layout(const Store& st, uint32_t T, char* base, TeamScratch
   char* p;
   p = take(items * sizeof(Item)); if (ts) ts->qa = reinterpret_cast<Item*>(p);
   p = take(items * sizeof(Item)); if (ts) ts->qb = reinterpret_cast<Item*>(p);
+  p = take(chunks * 4); if (ts) ts->cmap_a = reinterpret_cast<uint32_t*>(p);
+  p = take(chunks * 4); if (ts) ts->cmap_b = reinterpret_cast<uint32_t*>(p);
+  if (ts) {
+    ts->qcap = (uint32_t)std::min<uint64_t>(items, 0xFFFFFFFFu);
+    ts->ccap = (uint32_t)std::min<uint64_t>(chunks, 0xFFFFFFFFu);
+    ts->lch = 31 - __builtin_clz(chunk_buckets);
+  }
   p = take(big * sizeof(Item)); if (ts) ts->qbig = reinterpret_cast<Item*>(p);
   p = take(bmw * 4); if (ts) ts->bm0 = reinterpret_cast<uint32_t*>(p);
   p = take(bmw * 4); if (ts) ts->bm1 = reinterpret_cast<uint32_t*>(p);
@@ -613,7 +641,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
     bs->spin_ticks = (uint64_t)khz * 1000ull * 2ull;
   }
   // teams: size from the tuning (0 = automatic), count bounded by memory
-  const uint64_t per_team = team_layout(st_, tune.tile_buckets, nullptr, nullptr);
+  const uint64_t per_team = team_layout(st_, tune.chunk_buckets, nullptr, nullptr);
   const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
   const uint32_t max_teams = (uint32_t)std::max<uint64_t>(1, budget / per_team);
   uint32_t S_of[3] = {1, 1, 1}, T_of[3] = {0, 0, 0}, most = 1;
@@ -632,7 +660,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   if ((e = ensure(bs->scratch, per_team * most)) != hipSuccess)
     return bfail(g, DG_E_OUT_OF_MEMORY, "batch scratch allocation");
   std::vector<TeamScratch> tsv(most);
-  for (uint32_t t = 0; t < most; t++) team_layout(st_, tune.tile_buckets, bs->scratch.as<char>() + per_team * t, &tsv[t]);
+  for (uint32_t t = 0; t < most; t++) team_layout(st_, tune.chunk_buckets, bs->scratch.as<char>() + per_team * t, &tsv[t]);
   if ((e = ensure(bs->teams, most * sizeof(TeamScratch))) != hipSuccess ||
       (e = ensure(bs->qdesc, nq * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nq * 4)) != hipSuccess ||
       (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
@@ -667,7 +695,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
           return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
       BatchArgs a{st_,
                   fast,
-                  tune.tile_buckets,
                   (int32_t)std::max<uint32_t>(1, tune.batch_delta),
                   (int32_t)g->cfg.w_max,
                   tune.alpha,
@@ -807,7 +834,7 @@ extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, 
     dg_set_tuning(g, &best);
   };
   time_queries(0);   // warm-up
-  try_field(&dg_tuning::tile_buckets, {2, 4, 8, 16, 32}, 0);
+  try_field(&dg_tuning::chunk_buckets, {16, 32, 64}, 0);
   try_field(&dg_tuning::alpha, {4, 14, 40, 1000000}, 0);
   try_field(&dg_tuning::beta, {8, 24, 64}, 0);
   try_field(&dg_tuning::sssp_delta, {16, 32, 64, 128, 256, 512}, 1);

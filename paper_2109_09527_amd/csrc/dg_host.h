@@ -64,7 +64,8 @@ struct UpdateScratch {
 
 // Per-query scratch for the plain (one query per launch) path.
 struct QueryScratch {
-  DevBuf qa, qb;                // frontier work items (u64: tile << 32 | vertex)
+  DevBuf qa, qb;                // frontier items
+  DevBuf cmap_a, cmap_b;        // their chunk maps
   DevBuf fa, fb;                // far queues (SSSP) / vertex order (BC)
   DevBuf bm0, bm1;              // frontier bitmaps
   DevBuf stamp, flag8;          // SSSP dedup state
@@ -72,7 +73,8 @@ struct QueryScratch {
   DevBuf rlist, rstamp;         // SSSP: vertices of the current bucket
   DevBuf counters;
   void* host_counters = nullptr;
-  uint64_t items_cap = 0;
+  uint64_t items_cap = 0, chunks_cap = 0;
+  uint32_t lch = 6;             // log2 of the chunk size in buckets
 };
 
 // Per-kernel-family event timing (dg_profile_*).
@@ -103,7 +105,7 @@ struct Prof {
 };
 
 struct Tuning {
-  uint32_t tile_buckets = 8;
+  uint32_t chunk_buckets = 64;
   uint32_t sssp_delta = 64;
   uint32_t alpha = 14, beta = 24;
   uint32_t batch_groups = 0;   // workgroups per query team; 0 = automatic

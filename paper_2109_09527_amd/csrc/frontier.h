@@ -2,26 +2,29 @@
 // (query.hip) and the persistent multi-query engine (batch.hip).
 //
 // A step is executed by `nworkers` workgroups numbered `worker`; inside a
-// step every wave works on its own and no workgroup barrier is taken.
+// step every wave works on its own, and the only workgroup barrier is the
+// one that sums the step's counters at its end.
 //
-// Frontier work items are (slab descriptor, vertex, tile): a tile is up to
-// T consecutive buckets of the vertex's forward slab, so a hub's adjacency
-// spreads over many items and every item costs at most T bucket scans.  The
-// descriptor is read once when the vertex is pushed and carried in the item,
-// so all tiles of a vertex read the same slab even if a concurrent update
-// regrows it (the old slab stays intact and holds every version visible at
-// e).
-//
-// A wave takes a batch of 16 items and lays their buckets out in one flat
-// sequence; each 16-lane group handles one (item, bucket) pair at a time,
-// lane j reading slot j, and four pairs are in flight per group.  Low-degree
-// vertices (one bucket) therefore fill the wave instead of idling three
-// quarters of it, and hub tiles spread over all four groups.
+// Frontier queues (Front) hold one item per pushed vertex: its forward-slab
+// descriptor, read once at push time and carried in the item so that a
+// concurrent regrowth cannot change the slab under a query (the old slab
+// stays intact and holds every version visible at e), and its flat start.
+// The slabs of the queue's items are laid end to end in one flat bucket
+// sequence, item by item in queue order; a flush reserves its items and
+// their buckets with one 64-bit atomic, so item order and flat order agree.
+// The flat sequence is cut into chunks of 16, 32 or 64 buckets (a tuning
+// value), and cmap[c] names the item holding the first bucket of chunk c.
+// A consuming step hands out
+// whole chunks to waves, so every wave gets the same number of buckets no
+// matter how degrees are distributed: a hub's slab spreads over many waves,
+// and runs of one-bucket vertices fill a wave's lanes.  Within a chunk, a
+// 16-lane group handles one (item, bucket) pair at a time, lane j reading
+// slot j, with four pairs in flight per group.
 //
 // Pushes are staged in the wave's own LDS arrays with a wave-uniform count
 // and appended to the global queue with one atomic per flush; a wave
 // flushes when its stage could overflow on the next round and at the end
-// of the step.  Counters live in registers and are added once per wave.
+// of the step.
 #pragma once
 #include "dg_internal.h"
 
@@ -29,41 +32,50 @@ namespace dg {
 
 constexpr int Q_THREADS = 256;
 constexpr int Q_WAVES = Q_THREADS / 64;
-constexpr int WB_ITEMS = 16;                      // frontier items per wave batch
-constexpr int Q_ITEMS_PER_BLOCK = Q_WAVES * WB_ITEMS;
+constexpr uint32_t CH_MAX = 64;                   // largest chunk (a chunk holds at most CH_MAX items)
+constexpr uint32_t CH_MIN = 16;
 constexpr int WSTAGE = 256;                       // staged pushes per wave
 constexpr uint32_t BU_CHUNK = 8;                  // buckets per bottom-up chunk item
 
 struct Item {
   uint64_t desc;
   uint32_t v;
-  uint32_t tile;
+  uint32_t aux;   // frontier queue: flat start; bottom-up chunk queue: chunk index
 };
 
-struct QCounters {
-  uint32_t n_items;
-  uint32_t n_verts;
-  unsigned long long m_next;
-  uint32_t n_far;
-  int32_t far_min;
-  uint32_t overflow;
-  uint32_t n_order;
-  unsigned long long arcs;   // visible arcs examined
-  uint32_t n_big;            // bottom-up chunk items
-  uint32_t pad;
+// A frontier queue and its chunk map, with their capacities; chunks hold
+// 1 << lch buckets (16, 32 or 64).
+struct Front {
+  Item* q;
+  uint32_t* cmap;
+  uint32_t qcap, ccap;
+  uint32_t lch;
 };
+
+enum : uint32_t { OVF_SIGMA = 1, OVF_QUEUE = 2 };
+
+struct QCounters {
+  unsigned long long fq;     // frontier items (low half) | flat buckets (high half)
+  uint32_t n_verts;
+  uint32_t n_far;
+  unsigned long long m_next;
+  int32_t far_min;
+  uint32_t overflow;         // OVF_* bits
+  uint32_t n_order;
+  uint32_t n_big;            // bottom-up chunk items
+  unsigned long long arcs;   // visible arcs examined
+};
+
+__host__ __device__ inline uint32_t fq_items(unsigned long long fq) { return (uint32_t)fq; }
+__host__ __device__ inline uint32_t fq_buckets(unsigned long long fq) { return (uint32_t)(fq >> 32); }
+__host__ __device__ inline uint32_t fq_chunks(unsigned long long fq, uint32_t lch) {
+  return (uint32_t)(((uint64_t)fq_buckets(fq) + (1u << lch) - 1) >> lch);
+}
 
 __device__ inline void zero_counters(QCounters* c) {
   QCounters z{};
   z.far_min = DIST_INF;
   *c = z;
-}
-
-// Items per wave batch for a step over nin items run by nw waves: enough
-// that every wave gets work, at most WB_ITEMS.
-__host__ __device__ inline uint32_t wb_items(uint32_t nin, uint32_t nw) {
-  uint32_t k = nw ? (nin + nw - 1) / nw : WB_ITEMS;
-  return k < 1 ? 1 : (k > (uint32_t)WB_ITEMS ? (uint32_t)WB_ITEMS : k);
 }
 
 // Which buckets of a slab an item covers: tiles of `chunk` buckets starting
@@ -93,6 +105,16 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+__device__ inline unsigned long long wave_incl_scan64(unsigned long long x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
@@ -113,6 +135,7 @@ struct WaveStage {
   uint32_t v[WSTAGE];
   uint64_t d[WSTAGE];
   uint32_t u[WSTAGE];
+  uint32_t s[WSTAGE];   // flat starts of a flush's items (chunk map)
 };
 
 struct Shared {
@@ -126,6 +149,7 @@ struct Shared {
 struct ItemQ {
   uint32_t* v;
   uint64_t* d;
+  uint32_t* s;
   uint32_t cap;
   uint32_t n;
 };
@@ -135,7 +159,9 @@ struct U32Q {
   uint32_t n;
 };
 
-__device__ inline ItemQ item_q(WaveStage& s, uint32_t off, uint32_t cap) { return ItemQ{s.v + off, s.d + off, cap, 0}; }
+__device__ inline ItemQ item_q(WaveStage& s, uint32_t off, uint32_t cap) {
+  return ItemQ{s.v + off, s.d + off, s.s + off, cap, 0};
+}
 __device__ inline U32Q u32_q(WaveStage& s) { return U32Q{s.u, WSTAGE, 0}; }
 
 // Wave-uniform call: lanes with push append (v, desc).
@@ -156,8 +182,9 @@ __device__ inline void push_u32(U32Q& q, bool push, uint32_t v) {
   q.n += (uint32_t)__popcll(m);
 }
 
-// Write the staged vertices' tiles to the global queue (one atomic).
-__device__ inline void flush_item_q(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts) {
+// Tile queue (bottom-up chunk items): write the staged vertices' tiles
+// (one atomic).
+__device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts) {
   constexpr int PER = WSTAGE / 64;
   if (q.n == 0) return;   // wave-uniform
   wave_lds_sync();
@@ -201,9 +228,72 @@ __device__ inline void flush_u32_q(U32Q& q, uint32_t* gq, uint32_t* gcnt) {
   wave_lds_sync();
 }
 
+// Frontier queue: append the staged vertices that have buckets as items,
+// reserving items and flat buckets with one atomic, and point every chunk
+// that starts inside the reserved flat range at its item.
+__device__ inline void flush_front(ItemQ& q, const Front& f, QCounters* cnt) {
+  constexpr int PER = WSTAGE / 64;
+  if (q.n == 0) return;   // wave-uniform
+  wave_lds_sync();
+  const uint32_t lane = lane_id();
+  uint32_t nb[PER];
+  uint32_t ni = 0, nbs = 0;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    uint32_t e = lane * PER + k;
+    uint64_t d = e < q.n ? q.d[e] : 0;
+    nb[k] = d ? 1u << (d & 63) : 0;
+    ni += nb[k] ? 1 : 0;
+    nbs += nb[k];
+  }
+  const unsigned long long x = (unsigned long long)ni | ((unsigned long long)nbs << 32);
+  const unsigned long long incl = wave_incl_scan64(x);
+  const unsigned long long total = __shfl(incl, 63, 64);
+  unsigned long long base = 0;
+  if (lane == 0 && total) base = atomicAdd(&cnt->fq, total);
+  base = __shfl(base, 0, 64);
+  const unsigned long long ex = incl - x;
+  const uint32_t ib = fq_items(base), bb = fq_buckets(base);
+  uint32_t io = fq_items(ex), bo = fq_buckets(ex);
+  bool ovf = false;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    if (nb[k]) {
+      const uint32_t e = lane * PER + k;
+      const uint32_t p = ib + io;
+      if (p < f.qcap) f.q[p] = Item{q.d[e], q.v[e], bb + bo};
+      else ovf = true;
+      q.s[io] = bo;
+      io++;
+      bo += nb[k];
+    }
+  }
+  wave_lds_sync();
+  const uint32_t NI = fq_items(total), B = fq_buckets(total);
+  const uint32_t ch = 1u << f.lch;
+  const uint32_t c0 = (uint32_t)(((uint64_t)bb + ch - 1) >> f.lch), c1 = (uint32_t)(((uint64_t)bb + B + ch - 1) >> f.lch);
+  for (uint32_t c = c0 + lane; c < c1; c += 64) {
+    const uint32_t rel = (c << f.lch) - bb;
+    uint32_t lo = 0, hi = NI;   // q.s[lo] <= rel < q.s[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (q.s[mid] <= rel) lo = mid;
+      else hi = mid;
+    }
+    if (c < f.ccap) f.cmap[c] = ib + lo;
+    else ovf = true;
+  }
+  if (__ballot(ovf) && lane == 0) atomicOr(&cnt->overflow, OVF_QUEUE);
+  q.n = 0;
+  wave_lds_sync();
+}
+
 // Keep room for `next` more pushes.
-__device__ inline void room_item(ItemQ& q, uint32_t next, Item* gq, uint32_t* gcnt, TileShape ts) {
-  if (q.n + next > q.cap) flush_item_q(q, gq, gcnt, ts);
+__device__ inline void room_front(ItemQ& q, uint32_t next, const Front& f, QCounters* cnt) {
+  if (q.n + next > q.cap) flush_front(q, f, cnt);
+}
+__device__ inline void room_tiles(ItemQ& q, uint32_t next, Item* gq, uint32_t* gcnt, TileShape ts) {
+  if (q.n + next > q.cap) flush_tiles(q, gq, gcnt, ts);
 }
 __device__ inline void room_u32(U32Q& q, uint32_t next, uint32_t* gq, uint32_t* gcnt) {
   if (q.n + next > q.cap) flush_u32_q(q, gq, gcnt);
@@ -243,51 +333,45 @@ struct LaneCounts {
 __device__ inline bool bm_test(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 __device__ inline void bm_set(uint32_t* bm, uint32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
-// ------------------------------------------------------- wave batches
+// ------------------------------------------------------------- chunks
 
-// Up to 16 items of a frontier queue; lane l (and l + 16, l + 32, l + 48)
-// holds item l.  Its buckets occupy flat positions [start, start + nbk) of the
-// batch, and flat position f of the item is bucket f + off of its slab.
-struct WaveBatch {
+// The items touching chunk c of a frontier: lane l holds item cmap[c] + l
+// (start = 0xFFFFFFFF past the queue's end).  At most 64 items touch a
+// chunk of at most 64 buckets, each item holding at least one bucket.
+struct ChunkView {
   uint64_t desc;
-  uint32_t v, tile, nbk, start, off;
-  uint32_t total;   // buckets of the whole batch (wave-uniform)
+  uint32_t v, start;
+  uint32_t lo, hi;   // flat range of the chunk
 };
 
-__device__ inline WaveBatch wave_batch(const Item* q, uint32_t first, uint32_t wbn, uint32_t n, TileShape ts) {
-  WaveBatch wb;
-  const uint32_t l = lane_id() & (WB_ITEMS - 1);
-  const uint32_t idx = first + l;
-  Item it = l < wbn && idx < n ? q[idx] : Item{0, 0, 0};
-  uint32_t nb = it.desc ? 1u << (it.desc & 63) : 0;
-  uint32_t b0 = ts.first + it.tile * ts.chunk;
-  wb.nbk = nb > b0 ? min(ts.chunk, nb - b0) : 0;
-  uint32_t incl = wb.nbk;
-#pragma unroll
-  for (int o = 1; o < WB_ITEMS; o <<= 1) {
-    uint32_t y = __shfl_up(incl, o, WB_ITEMS);
-    if (l >= (uint32_t)o) incl += y;
-  }
-  wb.start = incl - wb.nbk;
-  wb.total = __shfl(incl, WB_ITEMS - 1, 64);
-  wb.off = b0 - wb.start;
-  wb.desc = it.desc;
-  wb.v = it.v;
-  wb.tile = it.tile;
-  return wb;
+// Chunks and items a step may read: a producer that ran out of room has
+// flagged OVF_QUEUE, and the query fails; the clamps keep every read inside
+// the queue until then.
+__device__ inline uint32_t front_chunks(const Front& f, unsigned long long fq) { return min(fq_chunks(fq, f.lch), f.ccap); }
+__device__ inline uint32_t front_items(const Front& f, unsigned long long fq) { return min(fq_items(fq), f.qcap); }
+
+__device__ inline ChunkView chunk_view(const Front& f, uint32_t c, uint32_t nitems, uint32_t nbuckets) {
+  ChunkView cv;
+  const uint32_t i0 = f.cmap[c];
+  const uint32_t idx = i0 + lane_id();
+  Item it = idx < nitems ? f.q[idx] : Item{0, 0, 0xFFFFFFFFu};
+  cv.desc = it.desc;
+  cv.v = it.v;
+  cv.start = it.aux;
+  cv.lo = c << f.lch;
+  cv.hi = min(cv.lo + (1u << f.lch), nbuckets);
+  return cv;
 }
 
-// Index (0..15) of the batch item owning flat position f < total.
-__device__ inline uint32_t batch_item(const WaveBatch& wb, uint32_t f) {
-  uint32_t idx = 0;
-#pragma unroll
-  for (int i = 1; i < WB_ITEMS; i++) idx += (uint32_t)__builtin_amdgcn_readlane((int)wb.start, i) <= f ? 1u : 0u;
-  return idx;
-}
+// Does this lane's item start inside the chunk (each item is counted by
+// exactly one chunk this way)?
+__device__ inline bool starts_here(const ChunkView& cv) { return cv.start >= cv.lo && cv.start < cv.hi; }
+// Does this lane's item hold any bucket of the chunk?
+__device__ inline bool touches(const ChunkView& cv) { return cv.start < cv.hi; }
 
-// Slot j of the four flat positions f0 + 4 grp + k of a batch (EMPTY past
-// its end), with visibility at e resolved from the bucket summaries and,
-// where needed, the stamps; item[k] is the owning batch item.
+// Slot j of the flat positions f0 + 4 grp + k (k < 4) of a chunk (EMPTY
+// past its end), with visibility at e resolved from the bucket summaries
+// and, where needed, the stamps; item[k] is the lane holding the owner.
 struct Pairs4 {
   uint32_t d[4];
   int32_t w[4];
@@ -296,25 +380,35 @@ struct Pairs4 {
 };
 
 template <bool WITH_W>
-__device__ inline Pairs4 load_pairs(const Pool& p, const WaveBatch& wb, uint32_t f0, uint32_t grp, uint32_t j,
+__device__ inline Pairs4 load_pairs(const Pool& p, const ChunkView& cv, uint32_t f0, uint32_t grp, uint32_t j,
                                     uint32_t e, bool fast) {
   Pairs4 r;
   uint2 sm[4];
   uint32_t* bp[4];
+  // owner of f0: the last lane whose item starts at or before it (starts
+  // increase with the lane); owners of f0 + 1 .. f0 + 15 follow it
+  const unsigned long long m0 = __ballot(cv.start <= f0);
+  const uint32_t L0 = (uint32_t)__popcll(m0) - 1;
+  uint32_t nxt[15];
+#pragma unroll
+  for (int m = 1; m < 16; m++)
+    nxt[m - 1] = L0 + m < 64 ? (uint32_t)__builtin_amdgcn_readlane((int)cv.start, (int)(L0 + m)) : 0xFFFFFFFFu;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const uint32_t f = f0 + grp * 4 + k;
-    const uint32_t idx = batch_item(wb, f);
-    const uint64_t desc = __shfl(wb.desc, (int)idx, 64);
-    const uint32_t off = __shfl(wb.off, (int)idx, 64);
-    r.item[k] = idx;
+    uint32_t own = L0;
+#pragma unroll
+    for (int m = 0; m < 15; m++) own += nxt[m] <= f ? 1u : 0u;
+    const uint64_t desc = __shfl(cv.desc, (int)own, 64);
+    const uint32_t st = __shfl(cv.start, (int)own, 64);
+    r.item[k] = own;
     r.d[k] = EMPTY;
     r.w[k] = 0;
     sm[k] = make_uint2(0xFFFFFFFFu, 0xFFFFu);
     bp[k] = p.base;
-    if (f < wb.total) {
+    if (f < cv.hi) {
       Slab s = slab_of(p, desc);
-      const uint32_t b = f + off;
+      const uint32_t b = f - st;
       bp[k] = bucket_ptr(s, b);
       r.d[k] = bp[k][j];
       if (WITH_W) r.w[k] = (int32_t)bp[k][16 + j];
@@ -339,28 +433,28 @@ struct LevelArgs {
   Store st;
   uint32_t e;
   int fast;
-  const Item* qin;
-  Item* qout;
-  Item* qbig;
+  Front fin;              // current frontier (top-down)
+  Front fout;             // next frontier
+  Item* qbig;             // bottom-up chunk items of long in-slabs
   const uint32_t* bm_cur;
   uint32_t* bm_next;
   int32_t* dist;
   int32_t next_level;
-  uint32_t T;
   QCounters* cnt_out;
 };
 
-__device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers, Shared& sh) {
-  const TileShape ts{0, a.T};
+// Top-down over the chunks of the current frontier (nfq: its fq counter).
+__device__ __forceinline__ void td_step(const LevelArgs& a, unsigned long long nfq, uint32_t worker, uint32_t nworkers,
+                                        Shared& sh) {
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  const uint32_t nitems = front_items(a.fin, nfq), nb = fq_buckets(nfq), nc = front_chunks(a.fin, nfq);
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   LaneCounts lc;
-  const uint32_t wbn = wb_items(nin, nw);
-  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
-    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
-    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
-      Pairs4 s4 = load_pairs<false>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
+  for (uint32_t c = gw; c < nc; c += nw) {
+    const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
+    for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
+      Pairs4 s4 = load_pairs<false>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         bool found = false;
@@ -376,12 +470,12 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32
           lc.verts++;
           lc.m += a.st.fused[d];
         }
-        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        room_front(qn, 64, a.fout, a.cnt_out);
         push_item(qn, found, d, yd);
       }
     }
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_front(qn, a.fout, a.cnt_out);
   lc.commit(a.cnt_out, sh);
 }
 
@@ -390,7 +484,7 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, uint32_t nin, uint32
 // the first empty slot or at a parent in the frontier; longer in-slabs
 // become chunk items of BU_CHUNK buckets for bu_big_step.
 __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uint32_t nworkers, Shared& sh) {
-  const TileShape ts{0, a.T}, tbig{0, BU_CHUNK};
+  const TileShape tbig{0, BU_CHUNK};
   const uint32_t V = a.st.V;
   const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
   const uint64_t* idesc = a.st.undirected ? a.st.fdesc : a.st.rdesc;
@@ -441,13 +535,13 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
       lc.verts++;
       lc.m += a.st.fused[y];
     }
-    room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+    room_front(qn, 64, a.fout, a.cnt_out);
     push_item(qn, found, y, yd);
-    room_item(qb, 64, a.qbig, &a.cnt_out->n_big, tbig);
+    room_tiles(qb, 64, a.qbig, &a.cnt_out->n_big, tbig);
     push_item(qb, act && s.nb > 1, y, ydesc_in);
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
-  flush_item_q(qb, a.qbig, &a.cnt_out->n_big, tbig);
+  flush_front(qn, a.fout, a.cnt_out);
+  flush_tiles(qb, a.qbig, &a.cnt_out->n_big, tbig);
   lc.commit(a.cnt_out, sh);
 }
 
@@ -462,7 +556,7 @@ __device__ inline ItemView view_item(const Pool& p, const Item* q, uint32_t idx,
   bool act = idx < n;
   Item it = act ? q[idx] : Item{0, 0, 0};
   iv.s = slab_of(p, it.desc);
-  iv.b0 = ts.first + it.tile * ts.chunk;
+  iv.b0 = ts.first + it.aux * ts.chunk;
   iv.nbk = act && iv.s.nb > iv.b0 ? min(ts.chunk, iv.s.nb - iv.b0) : 0;
   iv.v = it.v;
   return iv;
@@ -472,7 +566,7 @@ __device__ inline ItemView view_item(const Pool& p, const Item* q, uint32_t idx,
 // vertex already has a parent is skipped, and the first finder claims it.
 __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, uint32_t worker, uint32_t nworkers,
                                    Shared& sh) {
-  const TileShape ts{0, a.T}, tbig{0, BU_CHUNK};
+  const TileShape tbig{0, BU_CHUNK};
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   const Pool& ip = a.st.undirected ? a.st.fp : a.st.rp;
@@ -522,10 +616,10 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
       lc.verts++;
       lc.m += a.st.fused[y];
     }
-    room_item(qn, 4, a.qout, &a.cnt_out->n_items, ts);
+    room_front(qn, 4, a.fout, a.cnt_out);
     push_item(qn, win, y, yd);
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_front(qn, a.fout, a.cnt_out);
   lc.commit(a.cnt_out, sh);
 }
 
@@ -535,15 +629,14 @@ struct RelaxArgs {
   Store st;
   uint32_t e;
   int fast;
-  const Item* qin;
-  Item* qout;
+  Front fin;
+  Front fout;
   uint32_t* far_out;
   int32_t* dist;
   uint32_t* stamp;     // iteration stamp of the last push into the near queue
   uint32_t* infar;
   int32_t thr;
   uint32_t it1;        // stamp value of the queue being filled
-  uint32_t T;
   QCounters* cnt_out;
   // light/heavy split (Meyer & Sanders): mode 0 relaxes every arc; mode 1
   // only arcs with w <= light and records each processed vertex once per
@@ -556,26 +649,27 @@ struct RelaxArgs {
   uint32_t phase;
 };
 
-__device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
-                                  Shared& sh) {
-  const TileShape ts{0, a.T};
+__device__ __forceinline__ void relax_step(const RelaxArgs& a, unsigned long long nfq, uint32_t worker,
+                                           uint32_t nworkers, Shared& sh) {
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  const uint32_t nitems = front_items(a.fin, nfq), nb = fq_buckets(nfq), nc = front_chunks(a.fin, nfq);
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
-  const uint32_t wbn = wb_items(nin, nw);
-  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
-    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
-    const int32_t du_l = wb.nbk ? __hip_atomic_load(&a.dist[wb.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  for (uint32_t c = gw; c < nc; c += nw) {
+    const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
+    const int32_t du_l =
+        touches(cv) ? __hip_atomic_load(&a.dist[cv.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (a.mode == 1) {
-      // the first tile's item records its vertex for the bucket's heavy pass
-      bool rec = lane_id() < WB_ITEMS && wb.nbk && wb.tile == 0 && atomicExch(&a.rstamp[wb.v], a.phase) != a.phase;
+      // the chunk holding a vertex's first bucket records it for the
+      // bucket's heavy pass
+      bool rec = starts_here(cv) && atomicExch(&a.rstamp[cv.v], a.phase) != a.phase;
       uint32_t pos = wave_reserve(a.rcount, rec ? 1u : 0u);
-      if (rec) a.rlist[pos] = wb.v;
+      if (rec) a.rlist[pos] = cv.v;
     }
-    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
-      Pairs4 s4 = load_pairs<true>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
+    for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
+      Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
@@ -595,24 +689,22 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, uint32_t nin, uin
         }
         uint64_t yd = to_near ? a.st.fdesc[d] : 0;
         lc.verts += to_near ? 1 : 0;
-        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        room_front(qn, 64, a.fout, a.cnt_out);
         push_item(qn, to_near, d, yd);
         room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
         push_u32(qf, to_far, d);
       }
     }
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_front(qn, a.fout, a.cnt_out);
   flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
   lc.commit(a.cnt_out, sh);
 }
 
 // Items of every vertex in list[0..n): the recorded vertices of a settled
 // bucket, for its heavy-arc pass.
-__device__ __forceinline__ void expand_step(const Store& st, const uint32_t* list, uint32_t n, Item* qout,
-                                            QCounters* cnt_out, uint32_t T, uint32_t worker, uint32_t nworkers,
-                                            Shared& sh) {
-  const TileShape ts{0, T};
+__device__ __forceinline__ void expand_step(const Store& st, const uint32_t* list, uint32_t n, const Front& fout,
+                                            QCounters* cnt_out, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
@@ -621,23 +713,22 @@ __device__ __forceinline__ void expand_step(const Store& st, const uint32_t* lis
     bool act = i < n;
     uint32_t v = act ? list[i] : 0;
     uint64_t vd = act ? st.fdesc[v] : 0;
-    room_item(qn, 64, qout, &cnt_out->n_items, ts);
+    room_front(qn, 64, fout, cnt_out);
     push_item(qn, act && vd != 0, v, vd);
   }
-  flush_item_q(qn, qout, &cnt_out->n_items, ts);
+  flush_front(qn, fout, cnt_out);
 }
 
 struct SplitArgs {
   Store st;
   const uint32_t* far_in;
   uint32_t* far_out;
-  Item* qout;
+  Front fout;
   int32_t* dist;
   uint32_t* stamp;
   uint32_t* infar;
   int32_t thr;
   uint32_t it1;
-  uint32_t T;
   QCounters* cnt_out;
 };
 
@@ -645,7 +736,6 @@ struct SplitArgs {
 // and report their minimum distance.
 __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
-  const TileShape ts{0, a.T};
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
@@ -666,12 +756,12 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uin
     if (keep) mn = min(mn, dv);
     uint64_t vd = near ? a.st.fdesc[v] : 0;
     lc.verts += near ? 1 : 0;
-    room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+    room_front(qn, 64, a.fout, a.cnt_out);
     push_item(qn, near, v, vd);
     room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
     push_u32(qf, keep, v);
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_front(qn, a.fout, a.cnt_out);
   flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
@@ -685,32 +775,30 @@ struct BcFwdArgs {
   Store st;
   uint32_t e;
   int fast;
-  const Item* qin;
-  Item* qout;
+  Front fin;
+  Front fout;
   uint32_t* order;      // vertices in discovery order
   int32_t* level;
   unsigned long long* sigma;
   int32_t next_level;
-  uint32_t T;
   QCounters* cnt_out;
   QCounters* cnt_total; // discovery-order length and the overflow flag
 };
 
-__device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
-                                  Shared& sh) {
-  const TileShape ts{0, a.T};
+__device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, unsigned long long nfq, uint32_t worker,
+                                           uint32_t nworkers, Shared& sh) {
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
+  const uint32_t nitems = front_items(a.fin, nfq), nb = fq_buckets(nfq), nc = front_chunks(a.fin, nfq);
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   U32Q qo = u32_q(sh.ws[wave]);
   LaneCounts lc;
   uint32_t ovf = 0;
-  const uint32_t wbn = wb_items(nin, nw);
-  for (uint32_t first = gw * wbn; first < nin; first += nw * wbn) {
-    const WaveBatch wb = wave_batch(a.qin, first, wbn, nin, ts);
-    const unsigned long long su_l = wb.nbk ? a.sigma[wb.v] : 0;
-    for (uint32_t f0 = 0; f0 < wb.total; f0 += 16) {
-      Pairs4 s4 = load_pairs<false>(a.st.fp, wb, f0, grp, j, a.e, a.fast);
+  for (uint32_t c = gw; c < nc; c += nw) {
+    const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
+    const unsigned long long su_l = touches(cv) ? a.sigma[cv.v] : 0;
+    for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
+      Pairs4 s4 = load_pairs<false>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const unsigned long long su = __shfl(su_l, (int)s4.item[k], 64);
@@ -733,16 +821,16 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, uint32_t nin, uin
         }
         uint64_t yd = found ? a.st.fdesc[d] : 0;
         lc.verts += found ? 1 : 0;
-        room_item(qn, 64, a.qout, &a.cnt_out->n_items, ts);
+        room_front(qn, 64, a.fout, a.cnt_out);
         push_item(qn, found, d, yd);
         room_u32(qo, 64, a.order, &a.cnt_total->n_order);
         push_u32(qo, found, d);
       }
     }
   }
-  flush_item_q(qn, a.qout, &a.cnt_out->n_items, ts);
+  flush_front(qn, a.fout, a.cnt_out);
   flush_u32_q(qo, a.order, &a.cnt_total->n_order);
-  if (ovf) atomicOr(&a.cnt_total->overflow, 1u);
+  if (ovf) atomicOr(&a.cnt_total->overflow, OVF_SIGMA);
   lc.commit(a.cnt_out, sh);
 }
 

@@ -45,20 +45,22 @@ static void fill(T* p, uint64_t n, T v, hipStream_t s) {
   k_fill<T><<<(uint32_t)b, 256, 0, s>>>(p, n, v);
 }
 
-// Seed a query at src: dist/level d0, items of src, bitmap bit; counters
-// slot 0 describes the seed frontier, slot 1 is cleared.
-__global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Item* q, uint32_t* bm, uint32_t T,
-                       QCounters* cnt, uint32_t* order) {
+// Seed a query at src: dist/level d0, the item of src and its chunk map,
+// bitmap bit; counters slot 0 describes the seed frontier, slot 1 is
+// cleared.  One wave.
+__global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Front f, uint32_t* bm, QCounters* cnt,
+                       uint32_t* order) {
+  const uint64_t desc = st.fdesc[src];
+  const uint32_t nb = desc ? 1u << (desc & 63) : 0;
+  const uint32_t nc = (nb + (1u << f.lch) - 1) >> f.lch;
+  for (uint32_t c = threadIdx.x; c < nc && c < f.ccap; c += blockDim.x) f.cmap[c] = 0;
   if (threadIdx.x != 0) return;
-  uint64_t desc = st.fdesc[src];
-  TileShape ts{0, T};
-  uint32_t k = ts.tiles(desc);
-  for (uint32_t t = 0; t < k; t++) q[t] = Item{desc, src, t};
+  if (nb) f.q[0] = Item{desc, src, 0};
   if (dist) dist[src] = d0;
   if (bm) bm[src >> 5] |= 1u << (src & 31);
   if (order) order[0] = src;
   QCounters c0{};
-  c0.n_items = k;
+  c0.fq = nb ? 1ull | ((unsigned long long)nb << 32) : 0ull;
   c0.n_verts = 1;
   c0.m_next = st.fused[src];
   c0.n_order = 1;
@@ -71,10 +73,10 @@ __device__ inline void reset_other(QCounters* c) {
   if (blockIdx.x == 0 && threadIdx.x == 0) zero_counters(c);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, uint32_t nin, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, unsigned long long nfq, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  td_step(a, nin, blockIdx.x, gridDim.x, sh);
+  td_step(a, nfq, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset) {
@@ -88,17 +90,17 @@ __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a) {
   bu_big_step(a, a.cnt_out->n_big, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, uint32_t nin, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, unsigned long long nfq, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  relax_step(a, nin, blockIdx.x, gridDim.x, sh);
+  relax_step(a, nfq, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint32_t* list, uint32_t n, Item* qout,
-                                                            QCounters* cnt_out, uint32_t T, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint32_t* list, uint32_t n, Front fout,
+                                                            QCounters* cnt_out, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  expand_step(st, list, n, qout, cnt_out, T, blockIdx.x, gridDim.x, sh);
+  expand_step(st, list, n, fout, cnt_out, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t nin, QCounters* reset) {
@@ -107,10 +109,10 @@ __global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t 
   split_step(a, nin, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, uint32_t nin, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, unsigned long long nfq, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  bcfwd_step(a, nin, blockIdx.x, gridDim.x, sh);
+  bcfwd_step(a, nfq, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_bwd(Store st, uint32_t e, int fast, const uint32_t* verts,
@@ -124,8 +126,17 @@ __global__ void k_inf_to_minus1(int32_t* d, uint32_t n) {
     if (d[i] == DIST_INF) d[i] = -1;
 }
 
-static uint64_t items_capacity(const dg_graph* g) {
-  return (uint64_t)g->cfg.v_capacity + g->st.fp.cap / std::max<uint32_t>(1, g->tune.tile_buckets) + 1024;
+// A frontier holds each vertex at most once, and its slabs are distinct
+// slabs of the forward pool.
+static uint64_t items_capacity(const dg_graph* g) { return (uint64_t)g->cfg.v_capacity + 1024; }
+static uint64_t chunks_capacity(const dg_graph* g) { return g->st.fp.cap / CH_MIN + 2; }
+static uint32_t log2_of(uint32_t x) { return 31 - __builtin_clz(x); }
+
+static Front front_of(const QueryScratch& q, int which) {
+  const DevBuf& items = which ? q.qb : q.qa;
+  const DevBuf& cmap = which ? q.cmap_b : q.cmap_a;
+  return Front{items.as<Item>(), cmap.as<uint32_t>(), (uint32_t)std::min<uint64_t>(q.items_cap, 0xFFFFFFFFu),
+               (uint32_t)std::min<uint64_t>(q.chunks_cap, 0xFFFFFFFFu), q.lch};
 }
 
 static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
@@ -135,6 +146,11 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
   if ((e = ensure(q.qa, items * sizeof(Item))) != hipSuccess) return e;
   if ((e = ensure(q.qb, items * sizeof(Item))) != hipSuccess) return e;
   q.items_cap = items;
+  const uint64_t chunks = chunks_capacity(g);
+  if ((e = ensure(q.cmap_a, chunks * 4)) != hipSuccess) return e;
+  if ((e = ensure(q.cmap_b, chunks * 4)) != hipSuccess) return e;
+  q.chunks_cap = chunks;
+  q.lch = log2_of(g->tune.chunk_buckets);
   uint64_t bmw = (V + 31) / 32 + 1;
   if ((e = ensure(q.bm0, bmw * 4)) != hipSuccess) return e;
   if ((e = ensure(q.bm1, bmw * 4)) != hipSuccess) return e;
@@ -165,7 +181,7 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
 }
 
 void free_query_scratch(QueryScratch& q) {
-  release(q.qa); release(q.qb); release(q.fa); release(q.fb); release(q.bm0); release(q.bm1);
+  release(q.qa); release(q.qb); release(q.cmap_a); release(q.cmap_b); release(q.fa); release(q.fb); release(q.bm0); release(q.bm1);
   release(q.stamp); release(q.flag8); release(q.sigma); release(q.delta); release(q.level);
   release(q.rlist); release(q.rstamp);
   release(q.counters);
@@ -217,13 +233,14 @@ static uint32_t resident(const void* kernel) {
   return r;
 }
 
-// Grid of an item step: enough waves, each taking wave batches of
-// wb_items(nin, resident waves) items, and never more than fit at once.
-static uint32_t items_grid(const void* kernel, uint32_t nin) {
-  const uint32_t rb = resident(kernel);
-  const uint32_t wbn = wb_items(nin, rb * Q_WAVES);
-  const uint64_t waves = ((uint64_t)nin + wbn - 1) / wbn;
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((waves + Q_WAVES - 1) / Q_WAVES, rb));
+// Grid of a frontier step: one wave per chunk, never more than fit at once.
+static uint32_t chunks_grid(const void* kernel, unsigned long long fq, uint32_t lch) {
+  return grid_for(fq_chunks(fq, lch), Q_WAVES, resident(kernel));
+}
+
+static dg_status queue_overflow(dg_graph* g) {
+  g->err = "frontier queue capacity exceeded";
+  return DG_E_OUT_OF_MEMORY;
 }
 
 // Grid of a step with one unit per lane, at most what fits at once.
@@ -243,48 +260,46 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
   const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, false, false);
   if (he != hipSuccess) return hip_fail(g, he, "bfs scratch");
-  const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
+  const uint32_t V = g->cfg.v_capacity;
   const uint64_t bmw = (V + 31) / 32 + 1;
-  Item* qa = q.qa.as<Item>();
-  Item* qb = q.qb.as<Item>();
+  Front fr[2] = {front_of(q, 0), front_of(q, 1)};
   Item* qbig = q.fb.as<Item>();
   uint32_t* bm[2] = {q.bm0.as<uint32_t>(), q.bm1.as<uint32_t>()};
   QCounters* cnt = q.counters.as<QCounters>();
   fill<int32_t>(dist, V, -1, s);
   fill<uint32_t>(bm[0], bmw, 0u, s);
-  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, qa, bm[0], T, cnt, nullptr);
+  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], bm[0], cnt, nullptr);
   QCounters hc;
   if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs seed");
   int64_t m_u = (int64_t)arcs_at(g, e);
   const uint64_t n_live = std::max<uint64_t>(1, live_at(g, e));
   bool bu = false;
-  uint32_t n_items = hc.n_items, n_verts = hc.n_verts;
+  unsigned long long fq = hc.fq;
+  uint32_t n_verts = hc.n_verts;
   uint64_t m_f = hc.m_next;
   int level = 0;
-  Item* qin = qa;
-  Item* qout = qb;
   while (n_verts > 0) {
     int cur = level & 1, nxt = cur ^ 1;
     if (!bu && (int64_t)m_f * (int64_t)g->tune.alpha > m_u) bu = true;
     else if (bu && (uint64_t)n_verts * g->tune.beta < n_live) bu = false;
     m_u -= (int64_t)m_f;
     fill<uint32_t>(bm[nxt], bmw, 0u, s);
-    LevelArgs a{g->st, e, fast, qin, qout, qbig, bm[cur], bm[nxt], dist, level + 1, T, cnt + nxt};
+    LevelArgs a{g->st, e, fast, fr[cur], fr[nxt], qbig, bm[cur], bm[nxt], dist, level + 1, cnt + nxt};
     if (bu) {
       ProfScope ps(g, KID_BFS_BU, s);
       k_bfs_bu<<<lanes_grid((const void*)k_bfs_bu, V), Q_THREADS, 0, s>>>(a, cnt + cur);
       k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a);
     } else {
       ProfScope ps(g, KID_BFS_TD, s);
-      k_bfs_td<<<items_grid((const void*)k_bfs_td, n_items), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+      k_bfs_td<<<chunks_grid((const void*)k_bfs_td, fq, q.lch), Q_THREADS, 0, s>>>(a, fq, cnt + cur);
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bfs level launch");
     if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
+    if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
     prof_arcs(g, bu ? KID_BFS_BU : KID_BFS_TD, hc.arcs);
-    n_items = hc.n_items;
+    fq = hc.fq;
     n_verts = hc.n_verts;
     m_f = hc.m_next;
-    std::swap(qin, qout);
     level++;
   }
   return DG_OK;
@@ -296,12 +311,12 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, true, false);
   if (he != hipSuccess) return hip_fail(g, he, "sssp scratch");
-  const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
+  const uint32_t V = g->cfg.v_capacity;
   const int32_t delta = (int32_t)std::max<uint32_t>(1, g->tune.sssp_delta);
   // with delta >= w_max every arc is light and the heavy passes vanish
   const bool split_lh = delta < g->cfg.w_max;
-  Item* qin = q.qa.as<Item>();
-  Item* qout = q.qb.as<Item>();
+  Front fr[2] = {front_of(q, 0), front_of(q, 1)};
+  int qi = 0;   // queue holding the current near frontier
   uint32_t* fin = q.fa.as<uint32_t>();
   uint32_t* fout = q.fb.as<uint32_t>();
   uint32_t* stamp = q.stamp.as<uint32_t>();
@@ -317,38 +332,42 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
     fill<uint32_t>(rstamp, V, 0u, s);
     fill<uint32_t>(rcount, 1, 0u, s);
   }
-  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, qin, nullptr, T, cnt, nullptr);
+  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], nullptr, cnt, nullptr);
   QCounters hc;
   if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp seed");
-  uint32_t n_near = hc.n_items, n_far = 0;
+  unsigned long long near = hc.fq;
+  uint32_t n_far = 0;
   int32_t thr = delta;
   uint32_t it = 1;      // stamp of the queue being filled; the source's queue had stamp 0
   uint32_t phase = 1;   // bucket number (stamp of the recorded vertices)
   uint32_t n_rec = 0;   // vertices recorded in the current bucket
   int slot = 0;
-  auto relax = [&](uint32_t nin, int mode) -> hipError_t {
+  bool ovf = false;
+  auto relax = [&](unsigned long long nfq, int mode) -> hipError_t {
     int nxt = slot ^ 1;
     // far entries found by this pass are appended after the current far list
-    RelaxArgs a{g->st, e, fast, qin, qout, fin + n_far, dist, stamp, infar, thr, it, T, cnt + nxt,
-                mode, delta, rlist, rcount, rstamp, phase};
+    RelaxArgs a{g->st, e,         fast,  fr[qi], fr[qi ^ 1], fin + n_far, dist,   stamp,  infar, thr,
+                it,    cnt + nxt, mode,  delta,  rlist,      rcount,      rstamp, phase};
     {
       ProfScope ps(g, KID_SSSP_RELAX, s);
-      k_sssp_relax<<<items_grid((const void*)k_sssp_relax, nin), Q_THREADS, 0, s>>>(a, nin, cnt + slot);
+      k_sssp_relax<<<chunks_grid((const void*)k_sssp_relax, nfq, q.lch), Q_THREADS, 0, s>>>(a, nfq, cnt + slot);
     }
     hipError_t r = hipGetLastError();
     if (r != hipSuccess) return r;
     if ((r = read_counters_rc(q, nxt, &hc, &n_rec, s)) != hipSuccess) return r;
+    ovf |= (hc.overflow & OVF_QUEUE) != 0;
     prof_arcs(g, KID_SSSP_RELAX, hc.arcs);
-    n_near = hc.n_items;
+    near = hc.fq;
     n_far += hc.n_far;
-    std::swap(qin, qout);
+    qi ^= 1;
     it++;
     slot = nxt;
     return hipSuccess;
   };
   for (;;) {
-    if (n_near > 0) {
-      if ((he = relax(n_near, split_lh ? 1 : 0)) != hipSuccess) return hip_fail(g, he, "sssp relax");
+    if (ovf) return queue_overflow(g);
+    if (near) {
+      if ((he = relax(near, split_lh ? 1 : 0)) != hipSuccess) return hip_fail(g, he, "sssp relax");
       continue;
     }
     if (split_lh) {
@@ -358,17 +377,19 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
         fill<uint32_t>(rcount, 1, 0u, s);
         n_rec = 0;
         int nxt = slot ^ 1;
-        k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(g->st, rlist, n_r, qin, cnt + nxt, T,
-                                                                     cnt + slot);
+        k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(g->st, rlist, n_r, fr[qi],
+                                                                                        cnt + nxt, cnt + slot);
         if ((he = hipGetLastError()) != hipSuccess || (he = read_counters(q, nxt, &hc, s)) != hipSuccess)
           return hip_fail(g, he, "sssp expand");
+        if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
         slot = nxt;
-        if (hc.n_items && (he = relax(hc.n_items, 2)) != hipSuccess) return hip_fail(g, he, "sssp heavy");
+        if (hc.fq && (he = relax(hc.fq, 2)) != hipSuccess) return hip_fail(g, he, "sssp heavy");
         n_rec = 0;
+        if (ovf) return queue_overflow(g);
       }
       phase++;
       // heavy arcs leave the bucket (w > delta); should any land in it, keep going
-      if (n_near > 0) continue;
+      if (near) continue;
     }
     if (n_far == 0) break;
     int32_t far_min = DIST_INF;
@@ -377,19 +398,20 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
       thr = far_min == DIST_INF ? thr + delta
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       int nxt = slot ^ 1;
-      SplitArgs a{g->st, fin, fout, qin, dist, stamp, infar, thr, it, T, cnt + nxt};
+      SplitArgs a{g->st, fin, fout, fr[qi], dist, stamp, infar, thr, it, cnt + nxt};
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);
         k_sssp_split<<<lanes_grid((const void*)k_sssp_split, n_far), Q_THREADS, 0, s>>>(a, n_far, cnt + slot);
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
+      if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
       slot = nxt;
       std::swap(fin, fout);
       n_far = hc.n_far;
-      n_near = hc.n_items;
+      near = hc.fq;
       far_min = hc.far_min;
-    } while (n_near == 0 && n_far > 0);
+    } while (!near && n_far > 0);
     it++;
   }
   k_inf_to_minus1<<<grid_for(V, 256, 4096), 256, 0, s>>>(dist, V);
@@ -404,9 +426,8 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
   const int fast = g->concurrent_writers ? 0 : 1;
   hipError_t he = ensure_query_scratch(g, q, false, true);
   if (he != hipSuccess) return hip_fail(g, he, "bc scratch");
-  const uint32_t V = g->cfg.v_capacity, T = g->tune.tile_buckets;
-  Item* qa = q.qa.as<Item>();
-  Item* qb = q.qb.as<Item>();
+  const uint32_t V = g->cfg.v_capacity;
+  Front fr[2] = {front_of(q, 0), front_of(q, 1)};
   uint32_t* order = q.fa.as<uint32_t>();
   int32_t* level = q.level.as<int32_t>();
   unsigned long long* sigma = q.sigma.as<unsigned long long>();
@@ -421,7 +442,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
     uint32_t src = srcs[si];
     fill<int32_t>(level, V, -1, s);
     fill<unsigned long long>(sigma, V, 0ull, s);
-    k_seed<<<1, 64, 0, s>>>(g->st, src, level, 0, qa, nullptr, T, cnt, order);
+    k_seed<<<1, 64, 0, s>>>(g->st, src, level, 0, fr[0], nullptr, cnt, order);
     fill<unsigned long long>(reinterpret_cast<unsigned long long*>(tot), sizeof(QCounters) / 8, 0ull, s);
     fill<unsigned long long>(sigma + src, 1, 1ull, s);
     fill<uint32_t>(&tot->n_order, 1, 1u, s);
@@ -429,26 +450,24 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
     if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "bc seed");
     off.assign(1, 0);
     off.push_back(1);
-    uint32_t n_items = hc.n_items;
-    Item* qin = qa;
-    Item* qout = qb;
+    unsigned long long fq = hc.fq;
     int lvl = 0;
     while (true) {
       int cur = lvl & 1, nxt = cur ^ 1;
-      BcFwdArgs a{g->st, e, fast, qin, qout, order, level, sigma, lvl + 1, T, cnt + nxt, tot};
-      if (n_items) {
+      BcFwdArgs a{g->st, e, fast, fr[cur], fr[nxt], order, level, sigma, lvl + 1, cnt + nxt, tot};
+      if (fq) {
         ProfScope ps(g, KID_BC_FWD, s);
-        k_bc_fwd<<<items_grid((const void*)k_bc_fwd, n_items), Q_THREADS, 0, s>>>(a, n_items, cnt + cur);
+        k_bc_fwd<<<chunks_grid((const void*)k_bc_fwd, fq, q.lch), Q_THREADS, 0, s>>>(a, fq, cnt + cur);
       } else {
         fill<unsigned long long>(reinterpret_cast<unsigned long long*>(cnt + nxt), sizeof(QCounters) / 8, 0ull, s);
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc fwd launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bc fwd");
+      if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
       prof_arcs(g, KID_BC_FWD, hc.arcs);
       if (hc.n_verts == 0) break;
       off.push_back(off.back() + hc.n_verts);
-      n_items = hc.n_items;
-      std::swap(qin, qout);
+      fq = hc.fq;
       lvl++;
     }
     {

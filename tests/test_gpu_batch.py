@@ -148,7 +148,7 @@ def test_autotune_keeps_results(dg):
     g.apply(synth.load_ops(gr))
     say("autotune")
     t = g.autotune(seed=1)
-    assert t["tile_buckets"] in (2, 4, 8, 16, 32)
+    assert t["chunk_buckets"] in (16, 32, 64)
     assert t["sssp_delta"] in (16, 32, 64, 128, 256, 512)
     assert t["batch_delta"] in (8, 16, 32, 64, 128)
     assert g.get_tuning() == t

@@ -247,8 +247,8 @@ def test_bulk_load_spans_many_tiles(dg):
         assert np.array_equal(res, r_o)
         src = synth.out_degree_sources(gr, 4, synth.rng_for(2, 3))
         check_queries(g, o, g.epoch, src, dg, bc=True)
-        for T in (1, 4, 64):
-            g.set_tuning(tile_buckets=T, sssp_delta=17 * T)
+        for T in (16, 32, 64):
+            g.set_tuning(chunk_buckets=T, sssp_delta=17 * T)
             check_queries(g, o, g.epoch, src[:1], dg)
 
 
