@@ -41,6 +41,28 @@ HBM_PEAK_GBS = 8000.0
 #   bfs_bottom_up src 4 + stamp 8 (frontier bit test stays in L2)
 BYTES_PER_ARC = {"sssp_relax": 20, "bfs_top_down": 16, "bfs_bottom_up": 12}
 METRIC = "snapshot-query GTEPS + updates/s; p50/p99 query latency, batched vs plain"
+# HBM bytes per launch measured with rocprofv3 counters, valid only while the
+# kernel's sources are unchanged (their digest is stored beside the figure).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_relax_rmat20_traffic.txt")
+
+
+def measured_traffic(kernel):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary,
+    or None when there is none or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = next(json.loads(line[5:]) for line in f if line.startswith("json:"))
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("kernel") != kernel or "sources" not in rec:
+        return None
+    from paper_2109_09527_amd.rocprof_summary import sources_digest
+    try:
+        if sources_digest([os.path.join(ROOT, p) for p in rec["sources"]]) != rec.get("sources_sha256"):
+            return None
+    except OSError:
+        return None
+    return rec["bytes_per_dispatch"]
 
 
 def pct(xs, p):
@@ -172,8 +194,9 @@ def main():
             avg_ms = kp["total_ms"] / kp["launches"]
             bytes_per_launch = kp["arcs"] * BYTES_PER_ARC[kname] / kp["launches"]
             achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+            traffic = measured_traffic("k_" + kname)
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kp["launches"],
                     "bytes_per_launch": int(bytes_per_launch)}
 

@@ -84,6 +84,9 @@ struct TeamScratch {
   TeamSync* sync;
 };
 
+// uni_scratch copies every field; a new field must be added there too.
+static_assert(sizeof(TeamScratch) == 4 * 8 + 4 * 4 + 16 * 8, "TeamScratch layout changed: update uni_scratch");
+
 struct BatchArgs {
   Store st;
   int fast;
@@ -147,15 +150,59 @@ __device__ inline void team_fill(T* p, uint64_t n, T v, uint32_t w, uint32_t S) 
 }
 
 __device__ inline QCounters read_cnt(const QCounters* c) {
+  // every lane reads the same settled counters (after a team barrier)
   QCounters r;
-  r.fq = ld_relaxed(&c->fq);
-  r.n_verts = ld_relaxed(&c->n_verts);
-  r.m_next = ld_relaxed(&c->m_next);
-  r.n_far = ld_relaxed(&c->n_far);
-  r.far_min = ld_relaxed(&c->far_min);
-  r.overflow = ld_relaxed(&c->overflow);
-  r.n_order = ld_relaxed(&c->n_order);
-  r.n_big = ld_relaxed(&c->n_big);
+  r.fq = uni(ld_relaxed(&c->fq));
+  r.n_verts = uni(ld_relaxed(&c->n_verts));
+  r.m_next = uni(ld_relaxed(&c->m_next));
+  r.n_far = uni(ld_relaxed(&c->n_far));
+  r.far_min = uni(ld_relaxed(&c->far_min));
+  r.overflow = uni(ld_relaxed(&c->overflow));
+  r.n_order = uni(ld_relaxed(&c->n_order));
+  r.n_big = uni(ld_relaxed(&c->n_big));
+  return r;
+}
+
+// A team's scratch and a query's descriptor are read by every lane from
+// the same address; these copies make that uniformity visible, so the
+// pointers live in scalar registers instead of occupying two vector
+// registers each for the whole launch.
+__device__ inline TeamScratch uni_scratch(const TeamScratch& x) {
+  TeamScratch r;
+  r.qa = uni(x.qa);
+  r.qb = uni(x.qb);
+  r.cmap_a = uni(x.cmap_a);
+  r.cmap_b = uni(x.cmap_b);
+  r.qcap = uni(x.qcap);
+  r.ccap = uni(x.ccap);
+  r.lch = uni(x.lch);
+  r.qbig = uni(x.qbig);
+  r.bm0 = uni(x.bm0);
+  r.bm1 = uni(x.bm1);
+  r.bm2 = uni(x.bm2);
+  r.cnt = uni(x.cnt);
+  r.fa = uni(x.fa);
+  r.fb = uni(x.fb);
+  r.stamp = uni(x.stamp);
+  r.infar = uni(x.infar);
+  r.sigma = uni(x.sigma);
+  r.delta = uni(x.delta);
+  r.level = uni(x.level);
+  r.off = uni(x.off);
+  r.rlist = uni(x.rlist);
+  r.rstamp = uni(x.rstamp);
+  r.sync = uni(x.sync);
+  return r;
+}
+
+__device__ inline QDesc uni_desc(const QDesc& x) {
+  QDesc r;
+  r.kind = uni(x.kind);
+  r.src = uni(x.src);
+  r.epoch = uni(x.epoch);
+  r.k = uni(x.k);
+  r.srcs = uni(x.srcs);
+  r.out = uni(x.out);
   return r;
 }
 
@@ -229,7 +276,7 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
     if (bu) {
       bu_step(la, w, S, sh);
       BARRIER();
-      bu_big_step(la, ld_relaxed(&cout->n_big), w, S, sh);
+      bu_big_step(la, uni(ld_relaxed(&cout->n_big)), w, S, sh);
     } else {
       td_step(la, c.fq, w, S, sh);
     }
@@ -260,7 +307,7 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
   int qi = 0;   // queue holding the current near frontier
   uint32_t* fin = ts.fa;
   uint32_t* fout = ts.fb;
-  unsigned long long near = ld_relaxed(&ts.cnt[0].fq);
+  unsigned long long near = uni(ld_relaxed(&ts.cnt[0].fq));
   uint32_t n_far = 0;
   int32_t thr = a.delta;
   uint32_t it = 1;
@@ -296,7 +343,7 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
     }
     if (split_lh) {
       // the bucket has settled: its recorded vertices relax their heavy arcs once
-      const uint32_t n_r = ld_relaxed(rcount);
+      const uint32_t n_r = uni(ld_relaxed(rcount));
       if (n_r) {
         uint32_t nx = (slot + 1) % 3;
         if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
@@ -305,7 +352,7 @@ __device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, co
         if (w == 0 && threadIdx.x == 0) st_relaxed(rcount, 0u);
         slot = nx;
         QUEUE_CHECK(&ts.cnt[nx]);
-        const unsigned long long nh = ld_relaxed(&ts.cnt[nx].fq);
+        const unsigned long long nh = uni(ld_relaxed(&ts.cnt[nx].fq));
         if (nh && !relax(nh, 2)) return false;
         // the reset of rcount is published by the heavy pass's barrier
         if (!nh) BARRIER();
@@ -376,7 +423,7 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
       BARRIER();
       add_step_arcs(a.ctrl, cout, w);
       QUEUE_CHECK(cout);
-      uint32_t found = ld_relaxed(&cout->n_verts);
+      uint32_t found = uni(ld_relaxed(&cout->n_verts));
       if (found == 0) break;
       if (w == 0 && threadIdx.x == 0) ts.off[nlev + 1] = ts.off[nlev] + found;
       nlev++;
@@ -387,7 +434,7 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
       return true;
     }
     for (int L = (int)nlev - 1; L >= 0; L--) {
-      uint32_t o0 = ld_relaxed(&ts.off[L]), o1 = ld_relaxed(&ts.off[L + 1]);
+      uint32_t o0 = uni(ld_relaxed(&ts.off[L])), o1 = uni(ld_relaxed(&ts.off[L + 1]));
       bcbwd_step(a.st, qd.epoch, a.fast != 0, ts.fa + o0, o1 - o0, src, ts.level, L, ts.sigma, ts.delta, bc, w,
                  S);
       BARRIER();
@@ -440,20 +487,20 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
   __shared__ Shared sh;
   if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
   __syncthreads();
-  const uint32_t slot = sh.base;
+  const uint32_t slot = uni(sh.base);
   const uint32_t S = a.team_size;
   const uint32_t t = slot / S, w = slot % S;
   if (t >= a.n_teams) return;
-  const TeamScratch ts = a.teams[t];
+  const TeamScratch ts = uni_scratch(a.teams[t]);
   if (!team_join(a, ts.sync, S, sh)) return;
   uint32_t gen = 0;
   for (;;) {
     if (w == 0 && threadIdx.x == 0) ts.sync->q = atomicAdd(&a.ctrl->next, 1u);
     if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
-    const uint32_t k = ld_relaxed(&ts.sync->q);
+    const uint32_t k = uni(ld_relaxed(&ts.sync->q));
     if (k >= a.nq) return;
-    const uint32_t qi = a.qidx[k];
-    const QDesc qd = a.q[qi];
+    const uint32_t qi = uni(a.qidx[k]);
+    const QDesc qd = uni_desc(a.q[qi]);
     bool ok = true;
     if (a.status[qi] == DG_OK) {
       if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);

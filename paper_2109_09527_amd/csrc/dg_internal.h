@@ -118,6 +118,18 @@ __device__ inline bool visible(uint64_t stamp, uint32_t e) {
 // other threads' writes (slabs are written concurrently in update kernels).
 template <class T>
 __device__ inline T ld_relaxed(const T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// A value every lane of the wave holds equally, made visibly uniform for the
+// compiler (it then lives in scalar registers, and loops and branches on it
+// are uniform).
+__device__ inline uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ inline int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline unsigned long long uni(unsigned long long x) {
+  return (unsigned long long)uni((uint32_t)x) | ((unsigned long long)uni((uint32_t)(x >> 32)) << 32);
+}
+template <class T>
+__device__ inline T* uni(T* p) {
+  return reinterpret_cast<T*>(uni(reinterpret_cast<unsigned long long>(p)));
+}
 template <class T>
 __device__ inline void st_relaxed(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 

@@ -7,11 +7,12 @@ DIR is a rocprofv3 output directory holding either a rocpd database
       per-kernel calls / total / average duration
   python -m paper_2109_09527_amd.rocprof_summary pmc DIR
       per-kernel mean of every collected counter per dispatch
-  python -m paper_2109_09527_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR KERNEL COPY_KERNEL COPY_BYTES
+  python -m paper_2109_09527_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR KERNEL COPY_KERNEL COPY_BYTES [SRC...]
       HBM bytes per dispatch of KERNEL from a FETCH_SIZE run and a WRITE_SIZE
       run, each scaled by what the same counter reads for a plain copy kernel
       (COPY_KERNEL, which reads and writes COPY_BYTES) in the same run.
-      Prints one JSON object.
+      SRC files (the kernel's sources) are fingerprinted, so a reader can
+      tell whether the kernel changed since.  Prints one JSON object.
 
 Kernel names are matched by substring; the copy's dispatch is the largest
 value among dispatches whose name contains COPY_KERNEL.
@@ -102,6 +103,16 @@ def traffic(fetch_dir, write_dir, kernel, copy_kernel, copy_bytes):
     return res
 
 
+def sources_digest(paths):
+    """sha256 over the named files' bytes, in the given order."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         rows = stats(argv[1])
@@ -112,8 +123,12 @@ def main(argv):
     elif len(argv) >= 2 and argv[0] == "pmc":
         for (name, counter), (n, mean) in sorted(pmc(argv[1]).items()):
             print(f"{name[:64]:<64} {counter:<20} {n:>6} {mean:>16.1f}")
-    elif len(argv) == 6 and argv[0] == "traffic":
-        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]))))
+    elif len(argv) >= 6 and argv[0] == "traffic":
+        res = traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]))
+        if len(argv) > 6:
+            res["sources"] = argv[6:]
+            res["sources_sha256"] = sources_digest(argv[6:])
+        print(json.dumps(res))
     else:
         print(__doc__, file=sys.stderr)
         return 2
