@@ -1,23 +1,30 @@
 // Persistent multi-query engine: many BFS / SSSP / BC queries, on any mix
-// of retained epochs, in one launch.
+// of retained epochs, one launch per query kind.
 //
-// The grid holds at most 90% of the workgroups that can be resident at once
-// (from the occupancy API).  Workgroups join teams of S in the order they
-// start running, so a team's members are resident together; a team becomes
-// active only when all S members have joined, and members still waiting
-// when the query queue runs dry leave without work (the forming / active /
-// dead state is settled by one compare-and-swap, so every member takes the
-// same decision).  An active team takes the next query from a device
-// counter, runs it level by level with the steps of frontier.h over its own
-// scratch, separating levels with a team barrier (arrival counter +
-// generation word in global memory, a release fence before it and an
-// acquire fence after it, so no workgroup reads stale lines of another's
-// writes), and takes the next query when done.  Each query terminates on
-// its own; no barrier spans the grid.  Every wait is bounded by a wall-clock
-// limit: a workgroup that waits too long sets an abort flag that releases
-// every other waiter, so the launch always drains.  Only one engine launch
-// runs on a device at a time (teams spin on each other, so two engines
-// could starve each other of resident workgroups).
+// BFS and BC run in teams.  The grid holds at most 90% of the workgroups
+// that can be resident at once (from the occupancy API).  Workgroups join
+// teams of S in the order they start running, so a team's members are
+// resident together; a team becomes active only when all S members have
+// joined, and members still waiting when the query queue runs dry leave
+// without work (the forming / active / dead state is settled by one
+// compare-and-swap, so every member takes the same decision).  An active
+// team takes the next query from a device counter, runs it level by level
+// with the steps of frontier.h over its own scratch, separating levels with
+// a team barrier (arrival counter + generation word in global memory, a
+// release fence before it and an acquire fence after it, so no workgroup
+// reads stale lines of another's writes), and takes the next query when
+// done.  Each query terminates on its own.
+//
+// SSSP runs in lockstep gangs (below): the whole grid is one team, and all
+// queries of the gang advance one delta-stepping pass at a time over their
+// combined frontiers, so the thin passes of many queries fill the GPU
+// together.
+//
+// Every wait is bounded by a wall-clock limit: a workgroup that waits too
+// long sets an abort flag that releases every other waiter, so the launch
+// always drains.  Only one engine launch runs on a device at a time
+// (workgroups spin on each other, so two engines could starve each other of
+// resident workgroups).
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -287,107 +294,6 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
   return true;
 }
 
-__device__ __forceinline__ bool run_sssp(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
-                                         uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
-  const uint32_t V = a.st.V;
-  int32_t* dist = static_cast<int32_t*>(qd.out);
-  // with delta >= w_max every arc is light and the heavy passes vanish
-  const bool split_lh = a.delta < a.w_max;
-  uint32_t* rcount = &ts.cnt[3].n_order;
-  team_fill<int32_t>(dist, V, DIST_INF, w, S);
-  team_fill<uint32_t>(ts.stamp, V, 0u, w, S);
-  team_fill<uint32_t>(ts.infar, V, 0u, w, S);
-  if (split_lh) team_fill<uint32_t>(ts.rstamp, V, 0u, w, S);
-  if (w == 0 && threadIdx.x == 0)
-    for (int i = 0; i < 4; i++) zero_counters(&ts.cnt[i]);
-  BARRIER();
-  if (w == 0 && threadIdx.x == 0) dist[qd.src] = 0;
-  team_seed(a.st, qd.src, ts, &ts.cnt[0], w);
-  BARRIER();
-  int qi = 0;   // queue holding the current near frontier
-  uint32_t* fin = ts.fa;
-  uint32_t* fout = ts.fb;
-  unsigned long long near = uni(ld_relaxed(&ts.cnt[0].fq));
-  uint32_t n_far = 0;
-  int32_t thr = a.delta;
-  uint32_t it = 1;
-  uint32_t phase = 1;  // bucket number (stamp of the recorded vertices)
-  uint32_t slot = 0;   // counters slot holding the last pass's results
-  bool ovf = false;
-  auto relax = [&](unsigned long long nfq, int mode) -> bool {
-    uint32_t nx = (slot + 1) % 3;
-    if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-    RelaxArgs ra{a.st, qd.epoch,    a.fast, team_front(ts, qi), team_front(ts, qi ^ 1), fin + n_far,
-                 dist, ts.stamp,    ts.infar, thr,              it,                     &ts.cnt[nx],
-                 mode, a.delta,     ts.rlist, rcount,           ts.rstamp,              phase};
-    relax_step(ra, nfq, w, S, sh);
-    BARRIER();
-    add_step_arcs(a.ctrl, &ts.cnt[nx], w);
-    QCounters c = read_cnt(&ts.cnt[nx]);
-    ovf |= (c.overflow & OVF_QUEUE) != 0;
-    near = c.fq;
-    n_far += c.n_far;
-    qi ^= 1;
-    it++;
-    slot = nx;
-    return true;
-  };
-  for (;;) {
-    if (ovf) {
-      if (w == 0 && threadIdx.x == 0) *status = DG_E_OUT_OF_MEMORY;
-      return true;
-    }
-    if (near) {
-      if (!relax(near, split_lh ? 1 : 0)) return false;
-      continue;
-    }
-    if (split_lh) {
-      // the bucket has settled: its recorded vertices relax their heavy arcs once
-      const uint32_t n_r = uni(ld_relaxed(rcount));
-      if (n_r) {
-        uint32_t nx = (slot + 1) % 3;
-        if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-        expand_step(a.st, ts.rlist, n_r, team_front(ts, qi), &ts.cnt[nx], w, S, sh);
-        BARRIER();
-        if (w == 0 && threadIdx.x == 0) st_relaxed(rcount, 0u);
-        slot = nx;
-        QUEUE_CHECK(&ts.cnt[nx]);
-        const unsigned long long nh = uni(ld_relaxed(&ts.cnt[nx].fq));
-        if (nh && !relax(nh, 2)) return false;
-        // the reset of rcount is published by the heavy pass's barrier
-        if (!nh) BARRIER();
-      }
-      phase++;
-      // heavy arcs leave the bucket (w > delta); should any land in it, keep going
-      if (near) continue;
-    }
-    if (n_far == 0) break;
-    int32_t far_min = DIST_INF;
-    do {
-      thr = far_min == DIST_INF ? thr + a.delta
-                                : (int32_t)min((int64_t)DIST_INF, ((int64_t)far_min / a.delta + 1) * a.delta);
-      uint32_t nx = (slot + 1) % 3;
-      if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(slot + 2) % 3]);
-      SplitArgs sa{a.st, fin, fout, team_front(ts, qi), dist, ts.stamp, ts.infar, thr, it, &ts.cnt[nx]};
-      split_step(sa, n_far, w, S, sh);
-      BARRIER();
-      QCounters c = read_cnt(&ts.cnt[nx]);
-      uint32_t* t = fin;
-      fin = fout;
-      fout = t;
-      n_far = c.n_far;
-      near = c.fq;
-      far_min = c.far_min;
-      slot = nx;
-      QUEUE_CHECK(&ts.cnt[nx]);
-    } while (!near && n_far > 0);
-    it++;
-  }
-  for (uint64_t i = (uint64_t)w * Q_THREADS + threadIdx.x; i < V; i += (uint64_t)S * Q_THREADS)
-    if (dist[i] == DIST_INF) dist[i] = -1;
-  return true;
-}
-
 __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
                                        uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
@@ -447,7 +353,8 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
 // own register allocation.
 // Join a team in start order; returns false when the team never becomes
 // active (queue exhausted first, or a wait timed out).
-__device__ inline bool team_join(const BatchArgs& a, TeamSync* sync, uint32_t S, Shared& sh) {
+__device__ inline bool team_join(Ctrl* ctrl, uint32_t nq, uint64_t spin_ticks, TeamSync* sync, uint32_t S,
+                                 Shared& sh) {
   if (threadIdx.x == 0) {
     uint32_t go = 0;
     if (atomicAdd(&sync->joined, 1u) + 1 == S) {
@@ -458,12 +365,12 @@ __device__ inline bool team_join(const BatchArgs& a, TeamSync* sync, uint32_t S,
         uint32_t stt = ld_relaxed(&sync->state);
         if (stt == 1u) { go = 1; break; }
         if (stt == 2u) break;
-        if (ld_relaxed(&a.ctrl->next) >= a.nq || ld_relaxed(&a.ctrl->abort)) {
+        if (ld_relaxed(&ctrl->next) >= nq || ld_relaxed(&ctrl->abort)) {
           uint32_t old = atomicCAS(&sync->state, 0u, 2u);
           if (old == 1u) { go = 1; break; }
           break;
         }
-        if (wall_clock64() - t0 > a.spin_ticks) {
+        if (wall_clock64() - t0 > spin_ticks) {
           // a team that cannot assemble dissolves; the host checks that
           // every query was still served
           uint32_t old = atomicCAS(&sync->state, 0u, 2u);
@@ -492,7 +399,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
   const uint32_t t = slot / S, w = slot % S;
   if (t >= a.n_teams) return;
   const TeamScratch ts = uni_scratch(a.teams[t]);
-  if (!team_join(a, ts.sync, S, sh)) return;
+  if (!team_join(a.ctrl, a.nq, a.spin_ticks, ts.sync, S, sh)) return;
   uint32_t gen = 0;
   for (;;) {
     if (w == 0 && threadIdx.x == 0) ts.sync->q = atomicAdd(&a.ctrl->next, 1u);
@@ -504,12 +411,337 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
     bool ok = true;
     if (a.status[qi] == DG_OK) {
       if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);
-      else if (KIND == DG_Q_SSSP) ok = run_sssp(a, qd, ts, w, S, gen, sh, &a.status[qi]);
       else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
     }
     if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
     if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, 1u);
   }
+}
+
+
+// ----------------------------------------------------- lockstep SSSP gang
+//
+// All SSSP queries of a gang advance together, one pass at a time, in one
+// persistent launch whose workgroups form a single team.  A pass does, for
+// every query still running, the next step of its delta-stepping (a relax
+// pass over its near frontier, light / heavy / all arcs; the item expansion
+// of a settled bucket's recorded vertices; or a split of its far list at a
+// raised threshold).  The work units of all queries (frontier chunks, blocks
+// of 64 list entries) form one index space, cut into equal contiguous
+// ranges, one per wave; a grid barrier ends the pass.  Every workgroup then
+// reads the counters of all queries and advances an identical copy of each
+// query's state machine in its LDS, so no further synchronisation is needed
+// to agree on the next pass.  Thin delta-stepping buckets of many queries
+// thus fill the GPU together, and each query's per-pass cost is one barrier
+// shared by the gang instead of one host round trip of its own.
+
+constexpr uint32_t GANG_MAX = 128;   // queries per gang launch (LDS and registers sized for 5 waves per SIMD)
+
+enum GKind : uint32_t { G_RELAX = 0, G_EXPAND = 1, G_HEAVY = 2, G_SPLIT = 3, G_DONE = 4 };
+
+// Scratch and output of one query (device pointers, fixed for the launch).
+struct GQuery {
+  uint32_t epoch;
+  int32_t* dist;
+  Item* qa;
+  Item* qb;
+  uint32_t* cmap_a;
+  uint32_t* cmap_b;
+  uint32_t* fa;
+  uint32_t* fb;
+  uint32_t* stamp;
+  uint32_t* infar;
+  uint32_t* rlist;
+  uint32_t* rstamp;
+  QCounters* cnt;   // [0..2] rotating pass counters, [3].n_order bucket record count
+};
+
+// A query's delta-stepping state, kept identically by every workgroup.
+struct GState {
+  unsigned long long near;   // fq of the near frontier
+  uint32_t kind, n_far, n_rec, it, phase, slot, qi, fsel;
+  int32_t thr, far_min;
+  uint32_t reset_rec;        // clear the bucket record count in the next plan
+};
+
+struct GangArgs {
+  Store st;
+  int fast;
+  int32_t delta;
+  int32_t w_max;
+  uint32_t qcap, ccap, lch;
+  const GQuery* q;
+  int32_t* status;
+  uint32_t nq;
+  TeamSync* sync;
+  Ctrl* ctrl;
+  uint64_t spin_ticks;
+};
+
+__device__ inline Front gang_front(const GangArgs& a, const GQuery& q, uint32_t which) {
+  return Front{which ? q.qb : q.qa, which ? q.cmap_b : q.cmap_a, a.qcap, a.ccap, a.lch};
+}
+
+__device__ inline uint32_t gang_units(const GangArgs& a, const GState& s) {
+  switch (s.kind) {
+    case G_RELAX:
+    case G_HEAVY: return min(fq_chunks(s.near, a.lch), a.ccap);
+    case G_EXPAND: return (min(s.n_rec, a.st.V) + 63) / 64;
+    case G_SPLIT: return (s.n_far + 63) / 64;
+    default: return 0;
+  }
+}
+
+// Leave the bucket: split the far list (at a threshold one delta higher),
+// or finish.
+__device__ inline void gang_to_split(GState& s, int32_t delta) {
+  if (s.n_far == 0) {
+    s.kind = G_DONE;
+    return;
+  }
+  s.kind = G_SPLIT;
+  s.far_min = DIST_INF;
+  s.thr = (int32_t)min((int64_t)DIST_INF, (int64_t)s.thr + delta);
+}
+
+// Advance query q's state after a pass, from the counters that pass wrote.
+//
+// Workgroups reach this point at different times, and workgroup 0 may
+// already be planning the next pass while others still read these
+// counters; so nothing read here is written by the next pass's plan or
+// work: the pass counters rotate over three slots, and the bucket record
+// count is cleared only in the plan of the pass after an expansion.
+__device__ inline void gang_advance(const GangArgs& a, const GQuery& q, GState& s, int32_t* status) {
+  s.reset_rec = 0;
+  if (s.kind == G_DONE) return;
+  const bool split_lh = a.delta < a.w_max;
+  const uint32_t nx = (s.slot + 1) % 3;
+  const QCounters* c = &q.cnt[nx];
+  const unsigned long long fq = ld_relaxed(&c->fq);
+  if (ld_relaxed(&c->overflow) & OVF_QUEUE) {
+    *status = DG_E_OUT_OF_MEMORY;
+    s.kind = G_DONE;
+    return;
+  }
+  switch (s.kind) {
+    case G_RELAX:
+    case G_HEAVY: {
+      const bool heavy = s.kind == G_HEAVY;
+      s.near = fq;
+      s.n_far += ld_relaxed(&c->n_far);
+      s.qi ^= 1;
+      s.it++;
+      s.slot = nx;
+      if (heavy) s.phase++;
+      else if (split_lh) s.n_rec = ld_relaxed(&q.cnt[3].n_order);
+      if (s.near) s.kind = G_RELAX;
+      else if (!heavy && split_lh && s.n_rec) s.kind = G_EXPAND;
+      else {
+        if (!heavy && split_lh) s.phase++;
+        gang_to_split(s, a.delta);
+      }
+      break;
+    }
+    case G_EXPAND:
+      s.slot = nx;
+      s.n_rec = 0;
+      s.reset_rec = 1;
+      if (fq) {
+        s.near = fq;
+        s.kind = G_HEAVY;
+      } else {
+        s.phase++;
+        gang_to_split(s, a.delta);
+      }
+      break;
+    case G_SPLIT: {
+      s.slot = nx;
+      s.fsel ^= 1;
+      s.n_far = ld_relaxed(&c->n_far);
+      s.near = fq;
+      s.far_min = ld_relaxed(&c->far_min);
+      if (s.near) {
+        s.it++;
+        s.kind = G_RELAX;
+      } else if (s.n_far) {
+        // raise the threshold until some far entry falls below it
+        s.thr = (int32_t)min((int64_t)DIST_INF, ((int64_t)s.far_min / a.delta + 1) * a.delta);
+      } else {
+        s.kind = G_DONE;
+      }
+      break;
+    }
+  }
+}
+
+// Units [j0, j1) of query qn's current step, by the calling wave.
+__device__ inline GQuery uni_gquery(const GQuery& x) {
+  GQuery r;
+  r.epoch = uni(x.epoch);
+  r.dist = uni(x.dist);
+  r.qa = uni(x.qa);
+  r.qb = uni(x.qb);
+  r.cmap_a = uni(x.cmap_a);
+  r.cmap_b = uni(x.cmap_b);
+  r.fa = uni(x.fa);
+  r.fb = uni(x.fb);
+  r.stamp = uni(x.stamp);
+  r.infar = uni(x.infar);
+  r.rlist = uni(x.rlist);
+  r.rstamp = uni(x.rstamp);
+  r.cnt = uni(x.cnt);
+  return r;
+}
+static_assert(sizeof(GQuery) == 8 + 12 * 8, "GQuery layout changed: update uni_gquery");
+
+__device__ inline GState uni_state(const GState& x) {
+  GState r;
+  r.near = uni(x.near);
+  r.kind = uni(x.kind);
+  r.n_far = uni(x.n_far);
+  r.n_rec = uni(x.n_rec);
+  r.it = uni(x.it);
+  r.phase = uni(x.phase);
+  r.slot = uni(x.slot);
+  r.qi = uni(x.qi);
+  r.fsel = uni(x.fsel);
+  r.thr = uni(x.thr);
+  r.far_min = uni(x.far_min);
+  r.reset_rec = uni(x.reset_rec);
+  return r;
+}
+static_assert(sizeof(GState) == 8 + 11 * 4 + 4, "GState layout changed: update uni_state");
+
+__device__ __forceinline__ void gang_work(const GangArgs& a, uint32_t qn, const GState& s, uint32_t j0, uint32_t j1,
+                                          Shared& sh) {
+  const GQuery q = uni_gquery(a.q[qn]);
+  const uint32_t wave = threadIdx.x >> 6;
+  const bool split_lh = a.delta < a.w_max;
+  QCounters* cout = &q.cnt[(s.slot + 1) % 3];
+  uint32_t* fin = s.fsel ? q.fb : q.fa;
+  uint32_t* fout = s.fsel ? q.fa : q.fb;
+  ItemQ qn_ = item_q(sh.ws[wave], 0, WSTAGE);
+  U32Q qf = u32_q(sh.ws[wave]);
+  LaneCounts lc;
+  if (s.kind == G_RELAX || s.kind == G_HEAVY) {
+    const int mode = s.kind == G_HEAVY ? 2 : (split_lh ? 1 : 0);
+    RelaxArgs ra{a.st,    q.epoch,           a.fast,       gang_front(a, q, s.qi), gang_front(a, q, s.qi ^ 1),
+                 fin + s.n_far, q.dist,      q.stamp,      q.infar,                s.thr,
+                 s.it,    cout,              mode,         a.delta,                q.rlist,
+                 &q.cnt[3].n_order,          q.rstamp,     s.phase};
+    const uint32_t nitems = front_items(ra.fin, s.near), nb = fq_buckets(s.near);
+    for (uint32_t c = j0; c < j1; c++) relax_chunk(ra, c, nitems, nb, qn_, qf, lc);
+    flush_front(qn_, ra.fout, cout);
+    flush_u32_q(qf, ra.far_out, &cout->n_far);
+  } else if (s.kind == G_EXPAND) {
+    const Front f = gang_front(a, q, s.qi);
+    const uint32_t n_rec = min(s.n_rec, a.st.V);
+    for (uint32_t b = j0; b < j1; b++) expand_block(a.st, q.rlist, n_rec, b * 64, f, cout, qn_);
+    flush_front(qn_, f, cout);
+  } else {
+    SplitArgs sa{a.st, fin, fout, gang_front(a, q, s.qi), q.dist, q.stamp, q.infar, s.thr, s.it, cout};
+    int32_t mn = DIST_INF;
+    for (uint32_t b = j0; b < j1; b++) split_block(sa, s.n_far, b * 64, qn_, qf, lc, mn);
+    flush_front(qn_, sa.fout, cout);
+    flush_u32_q(qf, sa.far_out, &cout->n_far);
+    commit_far_min(mn, cout);
+  }
+  const unsigned long long arcs = lc.commit_wave(cout);
+  if (lane_id() == 0 && arcs) atomicAdd(&a.ctrl->arcs, arcs);
+}
+
+__global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
+  __shared__ Shared sh;
+  __shared__ GState gs[GANG_MAX];
+  __shared__ uint32_t pre[GANG_MAX + 1];
+  if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
+  __syncthreads();
+  const uint32_t w = uni(sh.base), S = gridDim.x;
+  if (!team_join(a.ctrl, 0xFFFFFFFFu, a.spin_ticks, a.sync, S, sh)) return;
+  uint32_t gen = 0;
+  const uint32_t nq = a.nq;
+  for (uint32_t i = threadIdx.x; i < nq; i += Q_THREADS) {
+    GState s{};
+    s.near = ld_relaxed(&a.q[i].cnt[0].fq);
+    s.kind = s.near ? G_RELAX : G_DONE;
+    s.thr = a.delta;
+    s.far_min = DIST_INF;
+    s.it = 1;
+    s.phase = 1;
+    gs[i] = s;
+  }
+  const uint32_t wave = threadIdx.x >> 6, nw = S * Q_WAVES, gw = w * Q_WAVES + wave;
+  for (;;) {
+    // plan the pass: units per query and their prefix (nq <= Q_THREADS)
+    __syncthreads();
+    const uint32_t my = threadIdx.x < nq ? gang_units(a, gs[threadIdx.x]) : 0;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(my, &total, sh);
+    if (threadIdx.x < nq) pre[threadIdx.x] = ex;
+    if (threadIdx.x == 0) pre[nq] = total;
+    if (w == 0 && threadIdx.x < nq) {
+      // clear the counters the pass after this one will fill, and the
+      // bucket record count once its expansion is done
+      const GState& s = gs[threadIdx.x];
+      if (s.kind != G_DONE) zero_counters(&a.q[threadIdx.x].cnt[(s.slot + 2) % 3]);
+      if (s.reset_rec) st_relaxed(&a.q[threadIdx.x].cnt[3].n_order, 0u);
+    }
+    __syncthreads();
+    total = uni(total);
+    if (total == 0) break;
+    // this wave's contiguous share of the units
+    const uint32_t lo = (uint32_t)((uint64_t)total * gw / nw), hi = (uint32_t)((uint64_t)total * (gw + 1) / nw);
+    uint32_t u = lo;
+    while (u < hi) {
+      uint32_t l = 0, h = nq;   // pre[l] <= u < pre[h]
+      while (h - l > 1) {
+        const uint32_t m = (l + h) >> 1;
+        if (pre[m] <= u) l = m;
+        else h = m;
+      }
+      const uint32_t qn = uni(l);
+      const uint32_t p0 = uni(pre[qn]), end = min(hi, uni(pre[qn + 1]));
+      gang_work(a, qn, uni_state(gs[qn]), u - p0, end - p0, sh);
+      u = end;
+    }
+    if (!team_barrier(a.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
+    for (uint32_t i = threadIdx.x; i < nq; i += Q_THREADS) gang_advance(a, a.q[i], gs[i], &a.status[i]);
+  }
+  if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, nq);
+}
+
+// Per-query start state of a gang: grid (x: blocks over V, y: query).
+__global__ void k_gang_init(const GQuery* gq, uint32_t V, int split_lh) {
+  const GQuery q = gq[blockIdx.y];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < V; i += gridDim.x * blockDim.x) {
+    q.dist[i] = DIST_INF;
+    q.stamp[i] = 0u;
+    q.infar[i] = 0u;
+    if (split_lh) q.rstamp[i] = 0u;
+  }
+}
+
+// Seed query blockIdx.x at its source: dist 0, the source's item and chunk
+// map, counters slot 0 = the seed frontier, other slots cleared.  One wave
+// per query, after k_gang_init.
+__global__ void k_gang_seed(const GQuery* gq, const uint32_t* src, Store st, uint32_t ccap, uint32_t lch) {
+  const GQuery q = gq[blockIdx.x];
+  const uint32_t v = src[blockIdx.x];
+  const uint64_t desc = st.fdesc[v];
+  const uint32_t nb = desc ? 1u << (desc & 63) : 0;
+  const uint32_t nc = (nb + (1u << lch) - 1) >> lch;
+  for (uint32_t c = threadIdx.x; c < nc && c < ccap; c += blockDim.x) q.cmap_a[c] = 0;
+  if (threadIdx.x != 0) return;
+  if (nb) q.qa[0] = Item{desc, v, 0};
+  q.dist[v] = 0;
+  for (int i = 0; i < 4; i++) zero_counters(&q.cnt[i]);
+  q.cnt[0].fq = nb ? 1ull | ((unsigned long long)nb << 32) : 0ull;
+}
+
+__global__ void k_gang_finish(const GQuery* gq, uint32_t V) {
+  int32_t* d = gq[blockIdx.y].dist;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < V; i += gridDim.x * blockDim.x)
+    if (d[i] == DIST_INF) d[i] = -1;
 }
 
 // ------------------------------------------------------------ host side
@@ -519,6 +751,8 @@ struct BatchState {
   uint64_t spin_ticks = 0;       // 2 s of the device wall clock
   DevBuf scratch, teams, qdesc, qidx, srcs, status, arcs, live, ctrl;
   int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
+  DevBuf gang_scratch, gq, gsrc, gsync, gctrl, gstatus;
+  int gang_cap = 0;              // resident workgroups of the gang kernel
 };
 
 static std::mutex g_engine_mu;   // one engine launch per process at a time
@@ -596,8 +830,117 @@ static dg_status bfail(dg_graph* g, dg_status st, const std::string& m) {
 
 static const void* kernel_of(int kind) {
   if (kind == DG_Q_BFS) return reinterpret_cast<const void*>(&k_team<DG_Q_BFS>);
-  if (kind == DG_Q_SSSP) return reinterpret_cast<const void*>(&k_team<DG_Q_SSSP>);
   return reinterpret_cast<const void*>(&k_team<DG_Q_BC>);
+}
+
+// Bytes of one gang query's scratch and, if base is set, its pointers.
+static uint64_t gang_layout(const Store& st, char* base, GQuery* q) {
+  const uint64_t V = st.V;
+  const uint64_t items = V + 1024;
+  const uint64_t chunks = st.fp.cap / CH_MIN + 2;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o += align256(bytes);
+    return base ? base + at : nullptr;
+  };
+  char* p;
+  p = take(items * sizeof(Item)); if (q) q->qa = reinterpret_cast<Item*>(p);
+  p = take(items * sizeof(Item)); if (q) q->qb = reinterpret_cast<Item*>(p);
+  p = take(chunks * 4); if (q) q->cmap_a = reinterpret_cast<uint32_t*>(p);
+  p = take(chunks * 4); if (q) q->cmap_b = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->fa = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->fb = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->stamp = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->infar = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->rlist = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 4 + 64); if (q) q->rstamp = reinterpret_cast<uint32_t*>(p);
+  p = take(4 * sizeof(QCounters)); if (q) q->cnt = reinterpret_cast<QCounters*>(p);
+  return o;
+}
+
+// The SSSP queries idx[] of a batch, in gangs of lockstep queries.
+static dg_status run_sssp_gangs(dg_graph* g, BatchState* bs, const Store& st_, const Tuning& tune, int fast,
+                                uint32_t share, const std::vector<QDesc>& qd, const std::vector<uint32_t>& idx,
+                                std::vector<int32_t>& st, uint64_t budget, hipStream_t s) {
+  hipError_t e;
+  const uint32_t V = st_.V;
+  const int32_t delta = (int32_t)std::max<uint32_t>(1, tune.batch_delta);
+  const int split_lh = delta < g->cfg.w_max ? 1 : 0;
+  const uint64_t per_q = gang_layout(st_, nullptr, nullptr);
+  const uint32_t gang = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>({(uint64_t)GANG_MAX, budget / per_q, (uint64_t)idx.size()}));
+  if (!bs->gang_cap) {
+    int per_cu = 0, cus = 0, dev = 0;
+    hipGetDevice(&dev);
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gang_sssp, Q_THREADS, 0)) !=
+            hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    bs->gang_cap = std::max(1, per_cu * cus);
+  }
+  const uint32_t G = std::max<uint32_t>(1, (uint32_t)((uint64_t)bs->gang_cap * 9 / 10 * share / 100));
+  const uint32_t lch = 31 - __builtin_clz(tune.chunk_buckets);
+  if ((e = ensure(bs->gang_scratch, per_q * gang)) != hipSuccess ||
+      (e = ensure(bs->gq, gang * sizeof(GQuery))) != hipSuccess || (e = ensure(bs->gsrc, gang * 4)) != hipSuccess ||
+      (e = ensure(bs->gsync, sizeof(TeamSync))) != hipSuccess || (e = ensure(bs->gctrl, sizeof(Ctrl))) != hipSuccess ||
+      (e = ensure(bs->gstatus, gang * 4)) != hipSuccess)
+    return bfail(g, DG_E_OUT_OF_MEMORY, "gang scratch allocation");
+  for (size_t g0 = 0; g0 < idx.size(); g0 += gang) {
+    const uint32_t n = (uint32_t)std::min<size_t>(gang, idx.size() - g0);
+    std::vector<GQuery> gq(n);
+    std::vector<uint32_t> src(n);
+    std::vector<int32_t> gst(n, DG_OK);
+    for (uint32_t i = 0; i < n; i++) {
+      const QDesc& d = qd[idx[g0 + i]];
+      gang_layout(st_, bs->gang_scratch.as<char>() + per_q * i, &gq[i]);
+      gq[i].epoch = d.epoch;
+      gq[i].dist = static_cast<int32_t*>(d.out);
+      src[i] = d.src;
+    }
+    Ctrl c0{};
+    if ((e = hipMemcpyAsync(bs->gq.p, gq.data(), n * sizeof(GQuery), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(bs->gsrc.p, src.data(), n * 4, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(bs->gstatus.p, gst.data(), n * 4, hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(bs->gctrl.p, &c0, sizeof(c0), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemsetAsync(bs->gsync.p, 0, sizeof(TeamSync), s)))
+      return bfail(g, DG_E_HIP, std::string("gang upload: ") + hipGetErrorString(e));
+    const dim3 fill_grid(std::max<uint32_t>(1, std::min<uint32_t>((V + 255) / 256, 1024)), n);
+    k_gang_init<<<fill_grid, 256, 0, s>>>(bs->gq.as<GQuery>(), V, split_lh);
+    k_gang_seed<<<n, 64, 0, s>>>(bs->gq.as<GQuery>(), bs->gsrc.as<uint32_t>(), st_,
+                                 (uint32_t)std::min<uint64_t>(st_.fp.cap / CH_MIN + 2, 0xFFFFFFFFu), lch);
+    GangArgs a{st_,
+               fast,
+               delta,
+               (int32_t)g->cfg.w_max,
+               (uint32_t)std::min<uint64_t>((uint64_t)V + 1024, 0xFFFFFFFFu),
+               (uint32_t)std::min<uint64_t>(st_.fp.cap / CH_MIN + 2, 0xFFFFFFFFu),
+               lch,
+               bs->gq.as<GQuery>(),
+               bs->gstatus.as<int32_t>(),
+               n,
+               bs->gsync.as<TeamSync>(),
+               bs->gctrl.as<Ctrl>(),
+               bs->spin_ticks};
+    {
+      ProfScope ps(g, KID_BATCH_SSSP, s);
+      k_gang_sssp<<<G, Q_THREADS, 0, s>>>(a);
+    }
+    k_gang_finish<<<fill_grid, 256, 0, s>>>(bs->gq.as<GQuery>(), V);
+    if ((e = hipGetLastError()) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("gang launch: ") + hipGetErrorString(e));
+    Ctrl cres;
+    if ((e = hipMemcpyAsync(gst.data(), bs->gstatus.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&cres, bs->gctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("gang: ") + hipGetErrorString(e));
+    if (cres.abort) return bfail(g, DG_E_HIP, "gang engine: a barrier timed out");
+    if (cres.done != n) return bfail(g, DG_E_HIP, "gang engine: the gang could not assemble");
+    prof_arcs(g, KID_BATCH_SSSP, cres.arcs);
+    g->engine_arcs += cres.arcs;
+    for (uint32_t i = 0; i < n; i++) st[idx[g0 + i]] = gst[i];
+  }
+  return DG_OK;
 }
 
 dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, hipStream_t s) {
@@ -673,7 +1016,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   } unpin{g, pinned};
   // resident workgroups per kind's kernel
   for (int k = 0; k < 3; k++) {
-    if (bs->grid_cap[k] || by_kind[k].empty()) continue;
+    if (bs->grid_cap[k] || by_kind[k].empty() || k == DG_Q_SSSP) continue;
     int per_cu = 0, cus = 0, dev = 0;
     hipGetDevice(&dev);
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_of(k), Q_THREADS, 0)) != hipSuccess ||
@@ -694,7 +1037,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   uint32_t S_of[3] = {1, 1, 1}, T_of[3] = {0, 0, 0}, most = 1;
   for (int k = 0; k < 3; k++) {
     uint32_t n = (uint32_t)by_kind[k].size();
-    if (!n) continue;
+    if (!n || k == DG_Q_SSSP) continue;   // SSSP runs in lockstep gangs
     // 90% of the resident capacity (times the share a server leaves to the engine)
     const uint32_t G = std::max<uint32_t>(1, (uint32_t)((uint64_t)bs->grid_cap[k] * 9 / 10 * share / 100));
     uint32_t S = tune.batch_groups;
@@ -736,7 +1079,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   {
     std::lock_guard<std::mutex> lk(g_engine_mu);
     for (int k = 0; k < 3; k++) {
-      if (by_kind[k].empty()) continue;
+      if (by_kind[k].empty() || k == DG_Q_SSSP) continue;
       for (uint32_t t = 0; t < T_of[k]; t++)
         if ((e = hipMemsetAsync(tsv[t].sync, 0, sizeof(TeamSync), s)) != hipSuccess)
           return bfail(g, DG_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
@@ -759,7 +1102,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
                   bs->spin_ticks};
       ProfScope ps(g, KID_BATCH_BFS + k, s);
       if (k == DG_Q_BFS) k_team<DG_Q_BFS><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
-      else if (k == DG_Q_SSSP) k_team<DG_Q_SSSP><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
       else k_team<DG_Q_BC><<<T_of[k] * S_of[k], Q_THREADS, 0, s>>>(a);
       if ((e = hipGetLastError()) != hipSuccess)
         return bfail(g, DG_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
@@ -769,7 +1111,12 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
         (e = hipMemcpyAsync(cres, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+    if (!by_kind[DG_Q_SSSP].empty()) {
+      dg_status r = run_sssp_gangs(g, bs, st_, tune, fast, share, qd, by_kind[DG_Q_SSSP], st, budget, s);
+      if (r != DG_OK) return r;
+    }
     for (int k = 0; k < 3; k++) {
+      if (k == DG_Q_SSSP) continue;
       if (cres[k].abort) return bfail(g, DG_E_HIP, "batch engine: a team barrier timed out");
       if (cres[k].done != by_kind[k].size())
         return bfail(g, DG_E_HIP, "batch engine: queries left unserved (teams could not assemble)");

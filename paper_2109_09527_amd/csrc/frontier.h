@@ -141,9 +141,28 @@ struct WaveStage {
 struct Shared {
   WaveStage ws[Q_WAVES];
   unsigned long long part[Q_WAVES][3];   // per-wave counter sums
+  uint32_t wsum[Q_WAVES];
   uint32_t base;
   uint32_t flag;
 };
+
+// Workgroup-wide exclusive prefix sum of one value per thread (takes a
+// barrier); *total receives the sum over the workgroup.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* total, Shared& sh) {
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t incl = wave_incl_scan(x);
+  if (lane == 63) sh.wsum[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < Q_WAVES; w++) {
+    const uint32_t v = sh.wsum[w];
+    if ((uint32_t)w < wave) off += v;
+    tot += v;
+  }
+  *total = tot;
+  return off + incl - x;
+}
 
 // A wave's item stage: LDS arrays plus a wave-uniform count.
 struct ItemQ {
@@ -327,6 +346,22 @@ struct LaneCounts {
       }
     }
     __syncthreads();
+  }
+  // Wave-uniform call: add this wave's counts with atomics of lane 0;
+  // returns the wave's arc count.
+  __device__ unsigned long long commit_wave(QCounters* c) {
+    uint32_t v = wave_sum_u32(verts);
+    unsigned long long mm = wave_sum_u64(m);
+    unsigned long long a = wave_sum_u64(arcs);
+    if (lane_id() == 0) {
+      if (v) atomicAdd(&c->n_verts, v);
+      if (mm) atomicAdd(&c->m_next, mm);
+      if (a) atomicAdd(&c->arcs, a);
+    }
+    verts = 0;
+    m = 0;
+    arcs = 0;
+    return a;
   }
 };
 
@@ -649,73 +684,81 @@ struct RelaxArgs {
   uint32_t phase;
 };
 
+// One chunk of the near frontier (all lanes of the wave).
+__device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint32_t nitems, uint32_t nb, ItemQ& qn,
+                                            U32Q& qf, LaneCounts& lc) {
+  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
+  const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
+  const int32_t du_l =
+      touches(cv) ? __hip_atomic_load(&a.dist[cv.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  if (a.mode == 1) {
+    // the chunk holding a vertex's first bucket records it for the
+    // bucket's heavy pass
+    bool rec = starts_here(cv) && atomicExch(&a.rstamp[cv.v], a.phase) != a.phase;
+    uint32_t pos = wave_reserve(a.rcount, rec ? 1u : 0u);
+    if (rec) a.rlist[pos] = cv.v;
+  }
+  for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
+    Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
+      bool to_near = false, to_far = false;
+      uint32_t d = s4.d[k];
+      bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
+      if (s4.vis[k] && take) {
+        lc.arcs++;
+        int32_t nd = du + s4.w[k];
+        if (nd < a.dist[d]) {
+          int32_t old = atomicMin(&a.dist[d], nd);
+          if (nd < old) {
+            if (nd < a.thr) to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
+            else to_far = atomicExch(&a.infar[d], 1u) == 0u;
+          }
+        }
+      }
+      uint64_t yd = to_near ? a.st.fdesc[d] : 0;
+      lc.verts += to_near ? 1 : 0;
+      room_front(qn, 64, a.fout, a.cnt_out);
+      push_item(qn, to_near, d, yd);
+      room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
+      push_u32(qf, to_far, d);
+    }
+  }
+}
+
 __device__ __forceinline__ void relax_step(const RelaxArgs& a, unsigned long long nfq, uint32_t worker,
                                            uint32_t nworkers, Shared& sh) {
-  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15, wave = threadIdx.x >> 6;
+  const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   const uint32_t nitems = front_items(a.fin, nfq), nb = fq_buckets(nfq), nc = front_chunks(a.fin, nfq);
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
-  for (uint32_t c = gw; c < nc; c += nw) {
-    const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
-    const int32_t du_l =
-        touches(cv) ? __hip_atomic_load(&a.dist[cv.v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-    if (a.mode == 1) {
-      // the chunk holding a vertex's first bucket records it for the
-      // bucket's heavy pass
-      bool rec = starts_here(cv) && atomicExch(&a.rstamp[cv.v], a.phase) != a.phase;
-      uint32_t pos = wave_reserve(a.rcount, rec ? 1u : 0u);
-      if (rec) a.rlist[pos] = cv.v;
-    }
-    for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
-      Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
-        bool to_near = false, to_far = false;
-        uint32_t d = s4.d[k];
-        bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
-        if (s4.vis[k] && take) {
-          lc.arcs++;
-          int32_t nd = du + s4.w[k];
-          if (nd < a.dist[d]) {
-            int32_t old = atomicMin(&a.dist[d], nd);
-            if (nd < old) {
-              if (nd < a.thr) to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
-              else to_far = atomicExch(&a.infar[d], 1u) == 0u;
-            }
-          }
-        }
-        uint64_t yd = to_near ? a.st.fdesc[d] : 0;
-        lc.verts += to_near ? 1 : 0;
-        room_front(qn, 64, a.fout, a.cnt_out);
-        push_item(qn, to_near, d, yd);
-        room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
-        push_u32(qf, to_far, d);
-      }
-    }
-  }
+  for (uint32_t c = gw; c < nc; c += nw) relax_chunk(a, c, nitems, nb, qn, qf, lc);
   flush_front(qn, a.fout, a.cnt_out);
   flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
   lc.commit(a.cnt_out, sh);
 }
 
 // Items of every vertex in list[0..n): the recorded vertices of a settled
-// bucket, for its heavy-arc pass.
+// bucket, for its heavy-arc pass.  One block of 64 entries per call.
+__device__ __forceinline__ void expand_block(const Store& st, const uint32_t* list, uint32_t n, uint32_t base,
+                                             const Front& fout, QCounters* cnt_out, ItemQ& qn) {
+  uint32_t i = base + lane_id();
+  bool act = i < n;
+  uint32_t v = act ? list[i] : 0;
+  uint64_t vd = act ? st.fdesc[v] : 0;
+  room_front(qn, 64, fout, cnt_out);
+  push_item(qn, act && vd != 0, v, vd);
+}
+
 __device__ __forceinline__ void expand_step(const Store& st, const uint32_t* list, uint32_t n, const Front& fout,
                                             QCounters* cnt_out, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
-  for (uint32_t base = gw * 64; base < n; base += nw * 64) {
-    uint32_t i = base + lane_id();
-    bool act = i < n;
-    uint32_t v = act ? list[i] : 0;
-    uint64_t vd = act ? st.fdesc[v] : 0;
-    room_front(qn, 64, fout, cnt_out);
-    push_item(qn, act && vd != 0, v, vd);
-  }
+  for (uint32_t base = gw * 64; base < n; base += nw * 64) expand_block(st, list, n, base, fout, cnt_out, qn);
   flush_front(qn, fout, cnt_out);
 }
 
@@ -733,7 +776,35 @@ struct SplitArgs {
 };
 
 // Move far entries below the threshold into the near queue; keep the rest
-// and report their minimum distance.
+// and report their minimum distance.  One block of 64 entries per call.
+__device__ __forceinline__ void split_block(const SplitArgs& a, uint32_t nin, uint32_t base, ItemQ& qn, U32Q& qf,
+                                            LaneCounts& lc, int32_t& mn) {
+  uint32_t i = base + lane_id();
+  bool act = i < nin;
+  uint32_t v = act ? a.far_in[i] : 0;
+  int32_t dv = act ? a.dist[v] : DIST_INF;
+  bool near = act && dv < a.thr;
+  bool keep = act && !near;
+  if (near) {
+    a.infar[v] = 0u;
+    near = atomicExch(&a.stamp[v], a.it1) != a.it1;
+  }
+  if (keep) mn = min(mn, dv);
+  uint64_t vd = near ? a.st.fdesc[v] : 0;
+  lc.verts += near ? 1 : 0;
+  room_front(qn, 64, a.fout, a.cnt_out);
+  push_item(qn, near, v, vd);
+  room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
+  push_u32(qf, keep, v);
+}
+
+// The far list's minimum reaches the counters once per wave.
+__device__ inline void commit_far_min(int32_t mn, QCounters* c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
+  if (lane_id() == 0 && mn < DIST_INF) atomicMin(&c->far_min, mn);
+}
+
 __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
                                   Shared& sh) {
   const uint32_t wave = threadIdx.x >> 6;
@@ -742,30 +813,10 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uin
   U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
   int32_t mn = DIST_INF;
-  for (uint32_t base = gw * 64; base < nin; base += nw * 64) {
-    uint32_t i = base + lane_id();
-    bool act = i < nin;
-    uint32_t v = act ? a.far_in[i] : 0;
-    int32_t dv = act ? a.dist[v] : DIST_INF;
-    bool near = act && dv < a.thr;
-    bool keep = act && !near;
-    if (near) {
-      a.infar[v] = 0u;
-      near = atomicExch(&a.stamp[v], a.it1) != a.it1;
-    }
-    if (keep) mn = min(mn, dv);
-    uint64_t vd = near ? a.st.fdesc[v] : 0;
-    lc.verts += near ? 1 : 0;
-    room_front(qn, 64, a.fout, a.cnt_out);
-    push_item(qn, near, v, vd);
-    room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
-    push_u32(qf, keep, v);
-  }
+  for (uint32_t base = gw * 64; base < nin; base += nw * 64) split_block(a, nin, base, qn, qf, lc, mn);
   flush_front(qn, a.fout, a.cnt_out);
   flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
-  if (lane_id() == 0 && mn < DIST_INF) atomicMin(&a.cnt_out->far_min, mn);
+  commit_far_min(mn, a.cnt_out);
   lc.commit(a.cnt_out, sh);
 }
 

@@ -7,9 +7,11 @@ edge ops (half AddEdge, half RemoveEdge), 70% queries split 40/40/20 between
 BFS, SSSP and BC with 16 sources.  Requests are generated before the clock
 starts and submitted at their arrival times; the run then drains.
 
-Prints one JSON line: offered and achieved request rates, p50/p99 latency
-(all, queries, updates; arrival to completion), updates/s, arcs examined by
-the queries per second, and whether the offered load was sustained.
+Prints one JSON line per offered rate: offered and achieved request rates,
+p50/p99 latency (all, queries, updates; arrival to completion), updates/s,
+arcs examined by the queries per second, and whether the offered load was
+sustained.  Several rates (--rate 2000,100,25) run one after another on the
+same loaded graph, each with its own request stream and server.
 
 Usage: python -m paper_2109_09527_amd.serve_bench [--scale 22] [--rate 2000] [--duration 2]
 """
@@ -26,7 +28,7 @@ import numpy as np
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--rate", default="2000", help="offered requests/s; a comma-separated list runs each")
     ap.add_argument("--duration", type=float, default=2.0)
     ap.add_argument("--mem-gb", type=float, default=24.0)
     ap.add_argument("--max-batch", type=int, default=64)
@@ -39,11 +41,19 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.time()
     gr = synth.rmat_graph(args.scale, 16, 255, seed=args.seed)
-    reqs = synth.serving_requests(gr, rate=args.rate, duration=args.duration, seed=args.seed)
-    print(f"[serve] generated V={gr.n} m={gr.m} requests={len(reqs)} in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
     g = dg.Graph(gr.n, w_max=255, max_resident_epochs=16, edge_capacity=2 * gr.m)
     g.apply(dg.ops_to_device(synth.load_ops(gr)))
+    torch.cuda.synchronize()
+    print(f"[serve] loaded V={gr.n} m={gr.m} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    for k, rate in enumerate(float(x) for x in str(args.rate).split(",")):
+        run_rate(args, g, gr, rate, args.seed + k)
+
+
+def run_rate(args, g, gr, rate, seed):
+    import torch
+    from paper_2109_09527_amd import dg, synth
+    reqs = synth.serving_requests(gr, rate=rate, duration=args.duration, seed=seed)
+    print(f"[serve] rate {rate:g}/s: {len(reqs)} requests", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     srv = dg.Server(g, mem_budget=int(args.mem_gb * (1 << 30)), max_inflight=1024, max_batch=args.max_batch)
     tickets = []
@@ -78,10 +88,10 @@ def main():
 
     achieved = len(tickets) / st["wall_s"] if st["wall_s"] else None
     out = {
-        "workload": f"R-MAT scale {args.scale} serving: Poisson {args.rate:g}/s for {args.duration:g}s, 30% updates "
+        "workload": f"R-MAT scale {args.scale} serving: Poisson {rate:g}/s for {args.duration:g}s, 30% updates "
                     "(log-uniform 1k-256k edge ops), 70% queries (BFS 40%, SSSP 40%, BC-16 20%)",
-        "requests": len(tickets), "offered_rps": args.rate, "achieved_rps": round(achieved, 1) if achieved else None,
-        "sustained": bool(achieved and achieved >= 0.95 * args.rate),
+        "requests": len(tickets), "offered_rps": rate, "achieved_rps": round(achieved, 1) if achieved else None,
+        "sustained": bool(achieved and achieved >= 0.95 * rate),
         "wall_s": round(st["wall_s"], 3), "drain_s": round(t_all - t_submit, 3),
         "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
         "query_p50_ms": round(st["p50_query_ms"], 3), "query_p99_ms": round(st["p99_query_ms"], 3),

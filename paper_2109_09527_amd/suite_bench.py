@@ -1,0 +1,200 @@
+"""Measurements of the batched and betweenness forms at their full sizes.
+
+  python -m paper_2109_09527_amd.suite_bench batched [--queries 512]
+      R-MAT scale 21 (2,097,152 vertices, 33.5M sampled directed edges,
+      int32 weights in [1, 255]) loaded as the first snapshot, then 7 batches
+      of log-uniform [65,536, 1,048,576] edge ops (50/50 add/remove), one
+      snapshot each.  Query i is a BFS for even i and an SSSP for odd i, on
+      snapshot i mod 8.  One dg_query_batch launch runs all of them, against
+      one plain call per query; the outputs of the two are compared element
+      by element.
+
+  python -m paper_2109_09527_amd.suite_bench bc [--sources 256]
+      Undirected unweighted R-MAT scale 18 (262,144 vertices), Brandes BC from
+      256 sampled sources on the loaded snapshot, then again after a batch of
+      32,768 undirected edge deletions.  Plain dg_bc over all sources against
+      the engine with the sources split into groups of 16; the sum of the
+      groups equals the plain result within 1e-9 relative.
+
+Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
+of the edges in the traversed component (visible out-degree summed over the
+vertices reached) / wall time.  Kernel figures come from the library's
+HIP-event profile on the stream the kernels run on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+# BC: the forward arc count stands for both passes (forward 16 B + backward pull 32 B per arc)
+BYTES_PER_ARC = {"batch_bfs": 16, "batch_sssp": 20, "batch_bc": 48, "bc_forward": 48, "sssp_relax": 20,
+                 "bfs_top_down": 16, "bfs_bottom_up": 12}
+
+
+def say(*a):
+    print("[suite]", *a, file=sys.stderr, flush=True)
+
+
+def roof(prof):
+    out = {}
+    for k, v in prof.items():
+        if k in BYTES_PER_ARC and v["launches"] and v["total_ms"] > 0 and v["arcs"]:
+            gbs = v["arcs"] * BYTES_PER_ARC[k] / (v["total_ms"] / 1e3) / 1e9
+            out[k] = {"launches": v["launches"], "total_ms": round(v["total_ms"], 3), "arcs": v["arcs"],
+                      "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def reached_edges(g, dist, epoch, torch):
+    deg = g.out_degrees(epoch).to(torch.int64)
+    return int(deg[dist >= 0].sum().item())
+
+
+def batched(args):
+    import torch
+    from paper_2109_09527_amd import dg, synth
+    t0 = time.time()
+    eq = synth.epoch_queries(scale=args.scale, n_queries=args.queries, seed=0)
+    gr = eq.graph
+    say(f"generated R-MAT {args.scale}: V={gr.n} m={gr.m} in {time.time() - t0:.1f}s")
+    g = dg.Graph(gr.n, w_max=255, max_resident_epochs=8, edge_capacity=2 * gr.m)
+    g.apply(dg.ops_to_device(synth.load_ops(gr)))
+    epochs = [g.epoch]
+    sizes = []
+    for b in eq.batches:
+        _, ep = g.apply(dg.ops_to_device(b))
+        epochs.append(ep)
+        sizes.append(len(b))
+    torch.cuda.synchronize()
+    say("epochs", epochs, "batch sizes", sizes)
+    if not args.no_autotune:
+        say("tuning", g.autotune(seed=0))
+    n = gr.n
+    qs = [(dg.Q_BFS if eq.kinds[i] == 0 else dg.Q_SSSP, epochs[eq.epoch_slot[i]], int(eq.src[i]))
+          for i in range(len(eq.kinds))]
+    plain = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
+    batch = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
+    # warm-up of both forms
+    g.query_batch([(k, e, s, o) for (k, e, s), o in zip(qs[:16], batch[:16])])
+    for (k, e, s), o in zip(qs[:4], plain[:4]):
+        (g.bfs if k == dg.Q_BFS else g.sssp)(s, e, o)
+    torch.cuda.synchronize()
+    g.profile(True)
+    g.profile_read(reset=True)
+    lat = []
+    t0 = time.perf_counter()
+    for (k, e, s), o in zip(qs, plain):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        (g.bfs if k == dg.Q_BFS else g.sssp)(s, e, o)
+        b.record()
+        lat.append((a, b))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    prof_plain = g.profile_read(reset=True)
+    plain_ms = sorted(a.elapsed_time(b) for a, b in lat)
+    t0 = time.perf_counter()
+    st = g.query_batch([(k, e, s, o) for (k, e, s), o in zip(qs, batch)])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    prof_batch = g.profile_read(reset=True)
+    g.profile(False)
+    equal = all(x == 0 for x in st) and all(torch.equal(p, b) for p, b in zip(plain, batch))
+    deg = {e: g.out_degrees(e).to(torch.int64) for e in epochs}
+    m = sum(int(deg[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, plain))
+    out = {
+        "workload": f"R-MAT scale {args.scale}, 8 snapshots (7 batches of log-uniform 64k-1M edge ops), "
+                    f"{len(qs)} queries BFS/SSSP 50/50, snapshot i mod 8",
+        "vertices": n, "loaded_edges": gr.m, "batch_ops": sizes, "queries": len(qs), "tuning": g.get_tuning(),
+        "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+        "plain_gteps": round(m / t_plain / 1e9, 4), "batched_gteps": round(m / t_batch / 1e9, 4),
+        "speedup": round(t_plain / t_batch, 3),
+        "plain_latency_ms": {"p50": round(plain_ms[len(plain_ms) // 2], 3),
+                             "p99": round(plain_ms[min(len(plain_ms) - 1, int(np.ceil(0.99 * len(plain_ms))) - 1)], 3)},
+        "outputs_equal": bool(equal),
+        "kernels_plain": roof(prof_plain), "kernels_batched": roof(prof_batch),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bc(args):
+    import torch
+    from paper_2109_09527_amd import dg, synth
+    t0 = time.time()
+    wl = synth.bc_workload(scale=args.scale, n_sources=args.sources, seed=0)
+    gr = wl.graph
+    say(f"generated R-MAT {args.scale} undirected: V={gr.n} m={gr.m} in {time.time() - t0:.1f}s")
+    g = dg.Graph(gr.n, undirected=True, w_max=1, edge_capacity=4 * gr.m)
+    g.apply(dg.ops_to_device(synth.load_ops(gr)))
+    S = [int(x) for x in wl.sources]
+    groups = [S[i:i + args.group] for i in range(0, len(S), args.group)]
+    phases = []
+    for phase in range(2):
+        ep = g.epoch
+        # TEPS numerator: edges of the component reached from each source
+        deg = g.out_degrees(ep).to(torch.int64)
+        m = 0
+        for s in S:
+            m += int(deg[g.bfs(s, ep) >= 0].sum().item())
+        g.bc(S[:4], ep)   # warm-up
+        torch.cuda.synchronize()
+        g.profile(True)
+        g.profile_read(reset=True)
+        t0 = time.perf_counter()
+        ref = g.bc(S, ep)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        prof_plain = g.profile_read(reset=True)
+        outs = [torch.empty(gr.n, dtype=torch.float64, device="cuda") for _ in groups]
+        g.query_batch([(dg.Q_BC, ep, grp, o) for grp, o in zip(groups[:1], outs[:1])])   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.query_batch([(dg.Q_BC, ep, grp, o) for grp, o in zip(groups, outs)])
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        prof_batch = g.profile_read(reset=True)
+        g.profile(False)
+        tot = torch.stack(outs).sum(0)
+        err = ((tot - ref).abs() / ref.abs().clamp_min(1e-300)).max().item()
+        phases.append({
+            "epoch": ep, "sources": len(S), "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+            "plain_gteps": round(m / t_plain / 1e9, 4), "batched_gteps": round(m / t_batch / 1e9, 4),
+            "batched_groups": len(groups), "status_ok": all(x == 0 for x in st),
+            "max_rel_diff_batched_vs_plain": err,
+            "kernels_plain": roof(prof_plain), "kernels_batched": roof(prof_batch),
+        })
+        if phase == 0:
+            g.apply(dg.ops_to_device(wl.deletions))
+    out = {
+        "workload": f"undirected unweighted R-MAT scale {args.scale}, Brandes BC from {len(S)} sources "
+                    f"(int64 path counts, FP64 dependencies), before and after {len(wl.deletions)} edge deletions",
+        "vertices": gr.n, "loaded_edges": gr.m, "phases": phases,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("batched")
+    a.add_argument("--scale", type=int, default=21)
+    a.add_argument("--queries", type=int, default=512)
+    a.add_argument("--no-autotune", action="store_true")
+    b = sub.add_parser("bc")
+    b.add_argument("--scale", type=int, default=18)
+    b.add_argument("--sources", type=int, default=256)
+    b.add_argument("--group", type=int, default=16)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    (batched if args.what == "batched" else bc)(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -265,7 +265,7 @@ def test_sssp_bucket_width_sweep(dg):
     want = {s: o.sssp(s)[1] for s in src}
     for delta in (1, 2, 7, 64, 254, 255, 256, 100000):
         say("sssp delta", delta)
-        g.set_tuning(sssp_delta=delta, batch_delta=min(delta, 128) if delta >= 8 else 8)
+        g.set_tuning(sssp_delta=delta, batch_delta=delta)
         for s in src:
             assert np.array_equal(g.sssp(s, g.epoch).cpu().numpy(), want[s]), (delta, s)
         outs = [torch.empty(gr.n, dtype=torch.int32, device="cuda") for _ in src]
