@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "dg_host.h"
@@ -59,9 +60,12 @@ __device__ inline void add_step_arcs(Ctrl* c, const QCounters* step, uint32_t w)
   }
 }
 
+// One engine job: a query, or (BFS with k > 0) a group of k <= 64 BFS
+// queries on one snapshot, run as one multi-source BFS; then srcs holds
+// their sources and out points at a device array of their k outputs.
 struct QDesc {
   uint32_t kind, src, epoch, k;
-  const uint32_t* srcs;   // device copy of BC sources
+  const uint32_t* srcs;   // device copy of BC / group sources
   void* out;
 };
 
@@ -88,11 +92,12 @@ struct TeamScratch {
   uint32_t* off;          // BC: start of each level in the discovery order
   uint32_t* rlist;        // SSSP bucket record list (aliases sigma)
   uint32_t* rstamp;       // SSSP bucket record stamps (aliases delta)
+  unsigned long long* msf;   // multi-source BFS frontier masks
   TeamSync* sync;
 };
 
 // uni_scratch copies every field; a new field must be added there too.
-static_assert(sizeof(TeamScratch) == 4 * 8 + 4 * 4 + 16 * 8, "TeamScratch layout changed: update uni_scratch");
+static_assert(sizeof(TeamScratch) == 4 * 8 + 4 * 4 + 17 * 8, "TeamScratch layout changed: update uni_scratch");
 
 struct BatchArgs {
   Store st;
@@ -198,6 +203,7 @@ __device__ inline TeamScratch uni_scratch(const TeamScratch& x) {
   r.off = uni(x.off);
   r.rlist = uni(x.rlist);
   r.rstamp = uni(x.rstamp);
+  r.msf = uni(x.msf);
   r.sync = uni(x.sync);
   return r;
 }
@@ -290,6 +296,68 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
     BARRIER();
     add_step_arcs(a.ctrl, cout, w);
     QUEUE_CHECK(cout);
+  }
+  return true;
+}
+
+// A group of qd.k BFS queries on one snapshot (multi-source BFS, top-down
+// only).  vis and nxt reuse the BC arrays sigma and delta; the touched list
+// lives in fa.
+__device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
+                                          uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
+  const uint32_t V = a.st.V, k = qd.k;
+  int32_t* const* outs = static_cast<int32_t* const*>(qd.out);
+  unsigned long long* vis = ts.sigma;
+  unsigned long long* nxt = reinterpret_cast<unsigned long long*>(ts.delta);
+  unsigned long long* fr = ts.msf;
+  const uint32_t wave = threadIdx.x >> 6, gw = w * Q_WAVES + wave, nw = S * Q_WAVES;
+  team_fill<unsigned long long>(vis, V, 0ull, w, S);
+  team_fill<unsigned long long>(nxt, V, 0ull, w, S);
+  team_fill<unsigned long long>(fr, V, 0ull, w, S);
+  for (uint32_t q = 0; q < k; q++) team_fill<int32_t>(uni(outs[q]), V, -1, w, S);
+  if (w == 0 && threadIdx.x == 0)
+    for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
+  BARRIER();
+  if (w == 0 && wave == 0) {
+    // query q's bit at its source; one frontier item per distinct source
+    const uint32_t q = lane_id();
+    const uint32_t v = q < k ? qd.srcs[q] : 0;
+    bool first = false;
+    if (q < k) {
+      const unsigned long long bit = 1ull << q;
+      first = atomicOr(&vis[v], bit) == 0ull;
+      atomicOr(&fr[v], bit);
+      outs[q][v] = 0;
+    }
+    ItemQ qn = item_q(sh.ws[0], 0, WSTAGE);
+    push_item(qn, first, v, first ? a.st.fdesc[v] : 0);
+    flush_front(qn, team_front(ts, 0), &ts.cnt[0]);
+  }
+  BARRIER();
+  for (uint32_t lvl = 0;; lvl++) {
+    const QCounters c = read_cnt(&ts.cnt[lvl % 3]);
+    if (c.fq == 0) break;   // no frontier vertex has an out-slab
+    QCounters* cout = &ts.cnt[(lvl + 1) % 3];
+    if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(lvl + 2) % 3]);
+    const MsArgs ma{a.st, qd.epoch, a.fast, team_front(ts, lvl & 1), team_front(ts, (lvl + 1) & 1),
+                    fr,   vis,      nxt,    ts.fa,                   cout};
+    {
+      ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
+      U32Q qt = u32_q(sh.ws[wave]);
+      LaneCounts lc;
+      const uint32_t nitems = front_items(ma.fin, c.fq), nb = fq_buckets(c.fq), nc = front_chunks(ma.fin, c.fq);
+      for (uint32_t cc = gw; cc < nc; cc += nw) msbfs_chunk(ma, cc, nitems, nb, qn, qt, lc);
+      flush_front(qn, ma.fout, cout);
+      flush_u32_q(qt, ts.fa, &cout->n_far);
+      lc.commit(cout, sh);
+    }
+    BARRIER();
+    add_step_arcs(a.ctrl, cout, w);
+    QUEUE_CHECK(cout);
+    const uint32_t nt = uni(ld_relaxed(&cout->n_far));
+    for (uint32_t base = gw * 64; base < nt; base += nw * 64)
+      msbfs_final_block(ts.fa, nt, base, fr, vis, nxt, outs, (int32_t)lvl);
+    BARRIER();
   }
   return true;
 }
@@ -390,7 +458,7 @@ __device__ inline bool team_join(Ctrl* ctrl, uint32_t nq, uint64_t spin_ticks, T
 // One launch serves the queries of one kind, so each kind's kernel gets its
 // own register allocation.
 template <int KIND>
-__global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
+__global__ __launch_bounds__(Q_THREADS, 4) void k_team(BatchArgs a) {
   __shared__ Shared sh;
   if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
   __syncthreads();
@@ -410,7 +478,8 @@ __global__ __launch_bounds__(Q_THREADS) void k_team(BatchArgs a) {
     const QDesc qd = uni_desc(a.q[qi]);
     bool ok = true;
     if (a.status[qi] == DG_OK) {
-      if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);
+      if (KIND == DG_Q_BFS) ok = qd.k ? run_msbfs(a, qd, ts, w, S, gen, sh, &a.status[qi])
+                                      : run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);
       else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
     }
     if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
@@ -749,7 +818,7 @@ __global__ void k_gang_finish(const GQuery* gq, uint32_t V) {
 struct BatchState {
   std::mutex mu;                 // one batch at a time per graph (shared buffers)
   uint64_t spin_ticks = 0;       // 2 s of the device wall clock
-  DevBuf scratch, teams, qdesc, qidx, srcs, status, arcs, live, ctrl;
+  DevBuf scratch, teams, qdesc, qidx, srcs, outs, status, arcs, live, ctrl;
   int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
   DevBuf gang_scratch, gq, gsrc, gsync, gctrl, gstatus;
   int gang_cap = 0;              // resident workgroups of the gang kernel
@@ -817,6 +886,7 @@ static uint64_t team_layout(const Store& st, uint32_t chunk_buckets, char* base,
   if (ts) ts->rstamp = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (ts) ts->level = reinterpret_cast<int32_t*>(p);
   p = take((V + 2) * 4 + 64); if (ts) ts->off = reinterpret_cast<uint32_t*>(p);
+  p = take(V * 8 + 64); if (ts) ts->msf = reinterpret_cast<unsigned long long*>(p);
   p = take(sizeof(TeamSync)); if (ts) ts->sync = reinterpret_cast<TeamSync*>(p);
   return o;
 }
@@ -1014,6 +1084,44 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       }
     }
   } unpin{g, pinned};
+  // BFS queries on one snapshot run in groups of up to 64 as one
+  // multi-source BFS job each (appended to qd); fewer than MS_MIN stay single
+  constexpr size_t MS_MIN = 4;
+  std::vector<std::vector<uint32_t>> groups;   // member queries of each group job
+  std::vector<uint32_t> group_job;
+  std::vector<void*> all_outs;
+  std::vector<uint64_t> out_off;
+  {
+    std::map<uint32_t, std::vector<uint32_t>> by_ep;
+    for (uint32_t i : by_kind[DG_Q_BFS]) by_ep[qd[i].epoch].push_back(i);
+    std::vector<uint32_t> jobs;
+    for (auto& kv : by_ep) {
+      const std::vector<uint32_t>& v = kv.second;
+      for (size_t o = 0; o < v.size(); o += 64) {
+        const size_t n = std::min<size_t>(64, v.size() - o);
+        if (n < MS_MIN) {
+          jobs.insert(jobs.end(), v.begin() + o, v.begin() + o + n);
+          continue;
+        }
+        std::vector<uint32_t> mem(v.begin() + o, v.begin() + o + n);
+        const uint32_t j = (uint32_t)qd.size();
+        const uint32_t src0 = qd[mem[0]].src;
+        src_off.push_back(all_srcs.size());
+        out_off.push_back(all_outs.size());
+        for (uint32_t u : mem) {
+          all_srcs.push_back(qd[u].src);
+          all_outs.push_back(qd[u].out);
+        }
+        qd.push_back(QDesc{DG_Q_BFS, src0, kv.first, (uint32_t)n, nullptr, nullptr});
+        st.push_back(DG_OK);
+        groups.push_back(std::move(mem));
+        group_job.push_back(j);
+        jobs.push_back(j);
+      }
+    }
+    by_kind[DG_Q_BFS] = jobs;
+  }
+  const uint32_t nj = (uint32_t)qd.size();   // queries and group jobs
   // resident workgroups per kind's kernel
   for (int k = 0; k < 3; k++) {
     if (bs->grid_cap[k] || by_kind[k].empty() || k == DG_Q_SSSP) continue;
@@ -1052,13 +1160,19 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   std::vector<TeamScratch> tsv(most);
   for (uint32_t t = 0; t < most; t++) team_layout(st_, tune.chunk_buckets, bs->scratch.as<char>() + per_team * t, &tsv[t]);
   if ((e = ensure(bs->teams, most * sizeof(TeamScratch))) != hipSuccess ||
-      (e = ensure(bs->qdesc, nq * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nq * 4)) != hipSuccess ||
+      (e = ensure(bs->qdesc, nj * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nj * 4)) != hipSuccess ||
       (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
-      (e = ensure(bs->status, nq * 4)) != hipSuccess || (e = ensure(bs->arcs, e_cnt * 8)) != hipSuccess ||
+      (e = ensure(bs->outs, std::max<size_t>(1, all_outs.size()) * sizeof(void*))) != hipSuccess ||
+      (e = ensure(bs->status, nj * 4)) != hipSuccess || (e = ensure(bs->arcs, e_cnt * 8)) != hipSuccess ||
       (e = ensure(bs->live, e_cnt * 8)) != hipSuccess || (e = ensure(bs->ctrl, 3 * sizeof(Ctrl))) != hipSuccess)
     return bfail(g, DG_E_OUT_OF_MEMORY, "batch descriptor allocation");
   for (uint32_t i = 0; i < nq; i++)
     if (qd[i].kind == DG_Q_BC) qd[i].srcs = bs->srcs.as<uint32_t>() + src_off[i];
+  for (size_t gi = 0; gi < group_job.size(); gi++) {
+    QDesc& d = qd[group_job[gi]];
+    d.srcs = bs->srcs.as<uint32_t>() + src_off[group_job[gi]];
+    d.out = bs->outs.as<void*>() + out_off[gi];
+  }
   std::vector<uint32_t> qidx;
   uint32_t koff[3] = {0, 0, 0};
   for (int k = 0; k < 3; k++) {
@@ -1067,11 +1181,13 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   }
   Ctrl c0[3] = {};
   if ((e = hipMemcpyAsync(bs->teams.p, tsv.data(), most * sizeof(TeamScratch), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(bs->qdesc.p, qd.data(), nq * sizeof(QDesc), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->qdesc.p, qd.data(), nj * sizeof(QDesc), hipMemcpyHostToDevice, s)) ||
+      (all_outs.size() &&
+       (e = hipMemcpyAsync(bs->outs.p, all_outs.data(), all_outs.size() * sizeof(void*), hipMemcpyHostToDevice, s))) ||
       (qidx.size() && (e = hipMemcpyAsync(bs->qidx.p, qidx.data(), qidx.size() * 4, hipMemcpyHostToDevice, s))) ||
       (all_srcs.size() &&
        (e = hipMemcpyAsync(bs->srcs.p, all_srcs.data(), all_srcs.size() * 4, hipMemcpyHostToDevice, s))) ||
-      (e = hipMemcpyAsync(bs->status.p, st.data(), nq * 4, hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(bs->status.p, st.data(), nj * 4, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(bs->arcs.p, arcs.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(bs->live.p, live.data(), e_cnt * 8, hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(bs->ctrl.p, c0, sizeof(c0), hipMemcpyHostToDevice, s)))
@@ -1107,7 +1223,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
         return bfail(g, DG_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
     Ctrl cres[3];
-    if ((e = hipMemcpyAsync(st.data(), bs->status.p, nq * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(st.data(), bs->status.p, nj * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipMemcpyAsync(cres, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
@@ -1126,6 +1242,8 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       }
     }
   }
+  for (size_t gi = 0; gi < groups.size(); gi++)
+    for (uint32_t u : groups[gi]) st[u] = st[group_job[gi]];
   for (uint32_t i = 0; i < nq; i++) per_query[i] = st[i];
   return DG_OK;
 }

@@ -885,6 +885,76 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, unsigned long lon
   lc.commit(a.cnt_out, sh);
 }
 
+// ------------------------------------------------- multi-source BFS
+//
+// Up to 64 BFS queries on one snapshot share every adjacency scan: vertex v
+// keeps a 64-bit mask of the queries that have reached it (vis), of those
+// whose frontier it is in at the current level (fr), and of those that reach
+// it in the current level (nxt).  Expanding a frontier vertex u ORs
+// fr[u] & ~vis[v] into nxt[v] for each visible arc (u, v); the first
+// contribution to nxt[v] lists v as touched and queues its slab for the
+// next level.  Finalising a touched v then moves the new bits into vis and
+// fr and writes the level into the distance array of each new query.
+
+struct MsArgs {
+  Store st;
+  uint32_t e;
+  int fast;
+  Front fin;                      // vertices with a nonzero frontier mask
+  Front fout;                     // touched vertices that have an out-slab
+  const unsigned long long* fr;
+  const unsigned long long* vis;
+  unsigned long long* nxt;
+  uint32_t* touched;              // all touched vertices (count in cnt_out->n_far)
+  QCounters* cnt_out;
+};
+
+__device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_t nitems, uint32_t nb, ItemQ& qn,
+                                            U32Q& qt, LaneCounts& lc) {
+  const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
+  const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
+  const unsigned long long f_l = touches(cv) ? a.fr[cv.v] : 0ull;
+  for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
+    Pairs4 s4 = load_pairs<false>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const unsigned long long fm = __shfl(f_l, (int)s4.item[k], 64);
+      const uint32_t d = s4.d[k];
+      bool first = false;
+      if (s4.vis[k]) {
+        lc.arcs++;
+        const unsigned long long m = fm & ~a.vis[d];
+        if (m && (m & ~__hip_atomic_load(&a.nxt[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+          first = atomicOr(&a.nxt[d], m) == 0ull;
+      }
+      const uint64_t yd = first ? a.st.fdesc[d] : 0;
+      room_front(qn, 64, a.fout, a.cnt_out);
+      push_item(qn, first, d, yd);
+      room_u32(qt, 64, a.touched, &a.cnt_out->n_far);
+      push_u32(qt, first, d);
+    }
+  }
+}
+
+// Touched vertices touched[base .. base + 64) of level `lvl` (the levels
+// reached are lvl + 1); outs[q] is query q's distance array.
+__device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint32_t n, uint32_t base,
+                                                  unsigned long long* fr, unsigned long long* vis,
+                                                  unsigned long long* nxt, int32_t* const* outs, int32_t lvl) {
+  const uint32_t i = base + lane_id();
+  if (i >= n) return;
+  const uint32_t v = touched[i];
+  unsigned long long nw = nxt[v] & ~vis[v];
+  vis[v] |= nw;
+  fr[v] = nw;
+  nxt[v] = 0ull;
+  while (nw) {
+    const int b = __ffsll((long long)nw) - 1;
+    nw &= nw - 1;
+    outs[b][v] = lvl + 1;
+  }
+}
+
 // One wave per vertex of level L: delta[v] = sum over visible arcs v->w
 // with level[w] = L+1 of sigma[v]/sigma[w] * (1 + delta[w]); lane l reads
 // slot l%16 of bucket l/16 of each group of four buckets; the 64 partial
