@@ -516,8 +516,6 @@ struct GQuery {
   Item* qb;
   uint32_t* cmap_a;
   uint32_t* cmap_b;
-  uint32_t* fa;
-  uint32_t* fb;
   uint32_t* stamp;
   uint32_t* infar;
   uint32_t* rlist;
@@ -528,7 +526,7 @@ struct GQuery {
 // A query's delta-stepping state, kept identically by every workgroup.
 struct GState {
   unsigned long long near;   // fq of the near frontier
-  uint32_t kind, n_far, n_rec, it, phase, slot, qi, fsel;
+  uint32_t kind, n_far, n_rec, it, phase, slot, qi;
   int32_t thr, far_min;
   uint32_t reset_rec;        // clear the bucket record count in the next plan
 };
@@ -556,7 +554,7 @@ __device__ inline uint32_t gang_units(const GangArgs& a, const GState& s) {
     case G_RELAX:
     case G_HEAVY: return min(fq_chunks(s.near, a.lch), a.ccap);
     case G_EXPAND: return (min(s.n_rec, a.st.V) + 63) / 64;
-    case G_SPLIT: return (s.n_far + 63) / 64;
+    case G_SPLIT: return (a.st.V + 63) / 64;
     default: return 0;
   }
 }
@@ -625,7 +623,6 @@ __device__ inline void gang_advance(const GangArgs& a, const GQuery& q, GState& 
       break;
     case G_SPLIT: {
       s.slot = nx;
-      s.fsel ^= 1;
       s.n_far = ld_relaxed(&c->n_far);
       s.near = fq;
       s.far_min = ld_relaxed(&c->far_min);
@@ -652,8 +649,6 @@ __device__ inline GQuery uni_gquery(const GQuery& x) {
   r.qb = uni(x.qb);
   r.cmap_a = uni(x.cmap_a);
   r.cmap_b = uni(x.cmap_b);
-  r.fa = uni(x.fa);
-  r.fb = uni(x.fb);
   r.stamp = uni(x.stamp);
   r.infar = uni(x.infar);
   r.rlist = uni(x.rlist);
@@ -661,7 +656,7 @@ __device__ inline GQuery uni_gquery(const GQuery& x) {
   r.cnt = uni(x.cnt);
   return r;
 }
-static_assert(sizeof(GQuery) == 8 + 12 * 8, "GQuery layout changed: update uni_gquery");
+static_assert(sizeof(GQuery) == 8 + 10 * 8, "GQuery layout changed: update uni_gquery");
 
 __device__ inline GState uni_state(const GState& x) {
   GState r;
@@ -673,13 +668,12 @@ __device__ inline GState uni_state(const GState& x) {
   r.phase = uni(x.phase);
   r.slot = uni(x.slot);
   r.qi = uni(x.qi);
-  r.fsel = uni(x.fsel);
   r.thr = uni(x.thr);
   r.far_min = uni(x.far_min);
   r.reset_rec = uni(x.reset_rec);
   return r;
 }
-static_assert(sizeof(GState) == 8 + 11 * 4 + 4, "GState layout changed: update uni_state");
+static_assert(sizeof(GState) == 8 + 10 * 4, "GState layout changed: update uni_state");
 
 __device__ __forceinline__ void gang_work(const GangArgs& a, uint32_t qn, const GState& s, uint32_t j0, uint32_t j1,
                                           Shared& sh) {
@@ -687,32 +681,27 @@ __device__ __forceinline__ void gang_work(const GangArgs& a, uint32_t qn, const 
   const uint32_t wave = threadIdx.x >> 6;
   const bool split_lh = a.delta < a.w_max;
   QCounters* cout = &q.cnt[(s.slot + 1) % 3];
-  uint32_t* fin = s.fsel ? q.fb : q.fa;
-  uint32_t* fout = s.fsel ? q.fa : q.fb;
   ItemQ qn_ = item_q(sh.ws[wave], 0, WSTAGE);
-  U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
   if (s.kind == G_RELAX || s.kind == G_HEAVY) {
     const int mode = s.kind == G_HEAVY ? 2 : (split_lh ? 1 : 0);
-    RelaxArgs ra{a.st,    q.epoch,           a.fast,       gang_front(a, q, s.qi), gang_front(a, q, s.qi ^ 1),
-                 fin + s.n_far, q.dist,      q.stamp,      q.infar,                s.thr,
-                 s.it,    cout,              mode,         a.delta,                q.rlist,
-                 &q.cnt[3].n_order,          q.rstamp,     s.phase};
+    RelaxArgs ra{a.st,    q.epoch,  a.fast,           gang_front(a, q, s.qi), gang_front(a, q, s.qi ^ 1),
+                 q.dist,  q.stamp,  q.infar,          s.thr,                  s.it,
+                 cout,    mode,     a.delta,          q.rlist,                &q.cnt[3].n_order,
+                 q.rstamp, s.phase};
     const uint32_t nitems = front_items(ra.fin, s.near), nb = fq_buckets(s.near);
-    for (uint32_t c = j0; c < j1; c++) relax_chunk(ra, c, nitems, nb, qn_, qf, lc);
+    for (uint32_t c = j0; c < j1; c++) relax_chunk(ra, c, nitems, nb, qn_, lc);
     flush_front(qn_, ra.fout, cout);
-    flush_u32_q(qf, ra.far_out, &cout->n_far);
   } else if (s.kind == G_EXPAND) {
     const Front f = gang_front(a, q, s.qi);
     const uint32_t n_rec = min(s.n_rec, a.st.V);
     for (uint32_t b = j0; b < j1; b++) expand_block(a.st, q.rlist, n_rec, b * 64, f, cout, qn_);
     flush_front(qn_, f, cout);
   } else {
-    SplitArgs sa{a.st, fin, fout, gang_front(a, q, s.qi), q.dist, q.stamp, q.infar, s.thr, s.it, cout};
+    SplitArgs sa{a.st, gang_front(a, q, s.qi), q.dist, q.stamp, q.infar, s.thr, s.it, cout};
     int32_t mn = DIST_INF;
-    for (uint32_t b = j0; b < j1; b++) split_block(sa, s.n_far, b * 64, qn_, qf, lc, mn);
+    for (uint32_t b = j0; b < j1; b++) split_block(sa, b * 64, qn_, lc, mn);
     flush_front(qn_, sa.fout, cout);
-    flush_u32_q(qf, sa.far_out, &cout->n_far);
     commit_far_min(mn, cout);
   }
   const unsigned long long arcs = lc.commit_wave(cout);
@@ -919,8 +908,6 @@ static uint64_t gang_layout(const Store& st, char* base, GQuery* q) {
   p = take(items * sizeof(Item)); if (q) q->qb = reinterpret_cast<Item*>(p);
   p = take(chunks * 4); if (q) q->cmap_a = reinterpret_cast<uint32_t*>(p);
   p = take(chunks * 4); if (q) q->cmap_b = reinterpret_cast<uint32_t*>(p);
-  p = take(V * 4 + 64); if (q) q->fa = reinterpret_cast<uint32_t*>(p);
-  p = take(V * 4 + 64); if (q) q->fb = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (q) q->stamp = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (q) q->infar = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (q) q->rlist = reinterpret_cast<uint32_t*>(p);

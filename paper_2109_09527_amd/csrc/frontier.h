@@ -140,7 +140,7 @@ struct WaveStage {
 
 struct Shared {
   WaveStage ws[Q_WAVES];
-  unsigned long long part[Q_WAVES][3];   // per-wave counter sums
+  unsigned long long part[Q_WAVES][4];   // per-wave counter sums
   uint32_t wsum[Q_WAVES];
   uint32_t base;
   uint32_t flag;
@@ -324,25 +324,29 @@ struct LaneCounts {
   uint32_t verts = 0;
   unsigned long long m = 0;
   uint32_t arcs = 0;
+  uint32_t far = 0;   // SSSP: vertices flagged far
   __device__ void commit(QCounters* c, Shared& sh) {
     uint32_t v = wave_sum_u32(verts);
     unsigned long long mm = wave_sum_u64(m);
     unsigned long long a = wave_sum_u64(arcs);
+    uint32_t f = wave_sum_u32(far);
     const uint32_t wave = threadIdx.x >> 6;
     if (lane_id() == 0) {
       sh.part[wave][0] = v;
       sh.part[wave][1] = mm;
       sh.part[wave][2] = a;
+      sh.part[wave][3] = f;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 4) {
       unsigned long long t = 0;
 #pragma unroll
       for (int w = 0; w < Q_WAVES; w++) t += sh.part[w][threadIdx.x];
       if (t) {
         if (threadIdx.x == 0) atomicAdd(&c->n_verts, (uint32_t)t);
         else if (threadIdx.x == 1) atomicAdd(&c->m_next, t);
-        else atomicAdd(&c->arcs, t);
+        else if (threadIdx.x == 2) atomicAdd(&c->arcs, t);
+        else atomicAdd(&c->n_far, (uint32_t)t);
       }
     }
     __syncthreads();
@@ -353,14 +357,17 @@ struct LaneCounts {
     uint32_t v = wave_sum_u32(verts);
     unsigned long long mm = wave_sum_u64(m);
     unsigned long long a = wave_sum_u64(arcs);
+    uint32_t f = wave_sum_u32(far);
     if (lane_id() == 0) {
       if (v) atomicAdd(&c->n_verts, v);
       if (mm) atomicAdd(&c->m_next, mm);
       if (a) atomicAdd(&c->arcs, a);
+      if (f) atomicAdd(&c->n_far, f);
     }
     verts = 0;
     m = 0;
     arcs = 0;
+    far = 0;
     return a;
   }
 };
@@ -660,16 +667,21 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
 
 // ----------------------------------------------------------------- SSSP
 
+// The far set of delta-stepping is the flag array infar (no list): a relax
+// that improves a vertex to a distance at or above the threshold flags it,
+// and a split scans all vertices densely (flags and distances are read in
+// order), moving flagged vertices below the new threshold into the near
+// frontier.  A split then costs one streaming pass over V, whatever the
+// number of far vertices, instead of a random read per far entry.
 struct RelaxArgs {
   Store st;
   uint32_t e;
   int fast;
   Front fin;
   Front fout;
-  uint32_t* far_out;
   int32_t* dist;
   uint32_t* stamp;     // iteration stamp of the last push into the near queue
-  uint32_t* infar;
+  uint32_t* infar;     // far flags (new flags are counted in cnt_out->n_far)
   int32_t thr;
   uint32_t it1;        // stamp value of the queue being filled
   QCounters* cnt_out;
@@ -686,7 +698,7 @@ struct RelaxArgs {
 
 // One chunk of the near frontier (all lanes of the wave).
 __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint32_t nitems, uint32_t nb, ItemQ& qn,
-                                            U32Q& qf, LaneCounts& lc) {
+                                            LaneCounts& lc) {
   const uint32_t grp = (threadIdx.x >> 4) & 3, j = threadIdx.x & 15;
   const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
   const int32_t du_l =
@@ -703,7 +715,7 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
-      bool to_near = false, to_far = false;
+      bool to_near = false;
       uint32_t d = s4.d[k];
       bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
       if (s4.vis[k] && take) {
@@ -712,8 +724,13 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
         if (nd < a.dist[d]) {
           int32_t old = atomicMin(&a.dist[d], nd);
           if (nd < old) {
-            if (nd < a.thr) to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
-            else to_far = atomicExch(&a.infar[d], 1u) == 0u;
+            if (nd < a.thr) {
+              to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
+              // settled in this bucket: no later split needs to move it again
+              if (a.infar[d]) a.infar[d] = 0u;
+            } else if (atomicExch(&a.infar[d], 1u) == 0u) {
+              lc.far++;
+            }
           }
         }
       }
@@ -721,8 +738,6 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
       lc.verts += to_near ? 1 : 0;
       room_front(qn, 64, a.fout, a.cnt_out);
       push_item(qn, to_near, d, yd);
-      room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
-      push_u32(qf, to_far, d);
     }
   }
 }
@@ -733,11 +748,9 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, unsigned long lon
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   const uint32_t nitems = front_items(a.fin, nfq), nb = fq_buckets(nfq), nc = front_chunks(a.fin, nfq);
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
-  U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
-  for (uint32_t c = gw; c < nc; c += nw) relax_chunk(a, c, nitems, nb, qn, qf, lc);
+  for (uint32_t c = gw; c < nc; c += nw) relax_chunk(a, c, nitems, nb, qn, lc);
   flush_front(qn, a.fout, a.cnt_out);
-  flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
   lc.commit(a.cnt_out, sh);
 }
 
@@ -764,58 +777,51 @@ __device__ __forceinline__ void expand_step(const Store& st, const uint32_t* lis
 
 struct SplitArgs {
   Store st;
-  const uint32_t* far_in;
-  uint32_t* far_out;
   Front fout;
   int32_t* dist;
   uint32_t* stamp;
   uint32_t* infar;
   int32_t thr;
   uint32_t it1;
-  QCounters* cnt_out;
+  QCounters* cnt_out;   // near items; n_far = far vertices left; far_min
 };
 
-// Move far entries below the threshold into the near queue; keep the rest
-// and report their minimum distance.  One block of 64 entries per call.
-__device__ __forceinline__ void split_block(const SplitArgs& a, uint32_t nin, uint32_t base, ItemQ& qn, U32Q& qf,
-                                            LaneCounts& lc, int32_t& mn) {
-  uint32_t i = base + lane_id();
-  bool act = i < nin;
-  uint32_t v = act ? a.far_in[i] : 0;
-  int32_t dv = act ? a.dist[v] : DIST_INF;
-  bool near = act && dv < a.thr;
-  bool keep = act && !near;
+// Vertices [base, base + 64): flagged ones below the threshold move into the
+// near queue; the rest stay flagged, counted, with their minimum distance.
+__device__ __forceinline__ void split_block(const SplitArgs& a, uint32_t base, ItemQ& qn, LaneCounts& lc,
+                                            int32_t& mn) {
+  const uint32_t v = base + lane_id();
+  const bool flagged = v < a.st.V && a.infar[v] != 0u;
+  const int32_t dv = flagged ? a.dist[v] : DIST_INF;
+  bool near = flagged && dv < a.thr;
   if (near) {
     a.infar[v] = 0u;
     near = atomicExch(&a.stamp[v], a.it1) != a.it1;
+  } else if (flagged) {
+    mn = min(mn, dv);
+    lc.far++;
   }
-  if (keep) mn = min(mn, dv);
   uint64_t vd = near ? a.st.fdesc[v] : 0;
   lc.verts += near ? 1 : 0;
   room_front(qn, 64, a.fout, a.cnt_out);
   push_item(qn, near, v, vd);
-  room_u32(qf, 64, a.far_out, &a.cnt_out->n_far);
-  push_u32(qf, keep, v);
 }
 
-// The far list's minimum reaches the counters once per wave.
+// The far minimum reaches the counters once per wave.
 __device__ inline void commit_far_min(int32_t mn, QCounters* c) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
   if (lane_id() == 0 && mn < DIST_INF) atomicMin(&c->far_min, mn);
 }
 
-__device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t nin, uint32_t worker, uint32_t nworkers,
-                                  Shared& sh) {
+__device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
-  U32Q qf = u32_q(sh.ws[wave]);
   LaneCounts lc;
   int32_t mn = DIST_INF;
-  for (uint32_t base = gw * 64; base < nin; base += nw * 64) split_block(a, nin, base, qn, qf, lc, mn);
+  for (uint32_t base = gw * 64; base < a.st.V; base += nw * 64) split_block(a, base, qn, lc, mn);
   flush_front(qn, a.fout, a.cnt_out);
-  flush_u32_q(qf, a.far_out, &a.cnt_out->n_far);
   commit_far_min(mn, a.cnt_out);
   lc.commit(a.cnt_out, sh);
 }

@@ -11,8 +11,11 @@
 //         beta.  Hop distances are the same either way.
 //   SSSP  delta-stepping in near/far form (Meyer & Sanders 2003; Davidson
 //         et al., IPDPS 2014): label-correcting relaxations with atomicMin
-//         below the threshold, far queue above it, threshold += delta when
-//         the near queue drains.  Exact for every delta.
+//         below the threshold, far flags above it, threshold += delta when
+//         the near queue drains (a dense split moves flagged vertices below
+//         the new threshold into the near queue); light arcs are relaxed
+//         until a bucket settles, heavy arcs once per settled bucket.
+//         Exact for every delta.
 //   BC    Brandes (2001): level-synchronous forward BFS with int64
 //         shortest-path counts (atomic adds, overflow flagged), then
 //         dependencies pulled from successors level by level in FP64 with a
@@ -103,10 +106,10 @@ __global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint3
   expand_step(st, list, n, fout, cnt_out, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, uint32_t nin, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, QCounters* reset) {
   __shared__ Shared sh;
   reset_other(reset);
-  split_step(a, nin, blockIdx.x, gridDim.x, sh);
+  split_step(a, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, unsigned long long nfq, QCounters* reset) {
@@ -164,8 +167,6 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
     if ((e = ensure(q.fb, big * sizeof(Item))) != hipSuccess) return e;
   }
   if (sssp) {
-    if ((e = ensure(q.fa, V * 4 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.fb, V * 4 + 64)) != hipSuccess) return e;
     if ((e = ensure(q.stamp, V * 4 + 64)) != hipSuccess) return e;
     if ((e = ensure(q.flag8, V * 4 + 64)) != hipSuccess) return e;
     if ((e = ensure(q.rlist, V * 4 + 64)) != hipSuccess) return e;
@@ -317,8 +318,6 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   const bool split_lh = delta < g->cfg.w_max;
   Front fr[2] = {front_of(q, 0), front_of(q, 1)};
   int qi = 0;   // queue holding the current near frontier
-  uint32_t* fin = q.fa.as<uint32_t>();
-  uint32_t* fout = q.fb.as<uint32_t>();
   uint32_t* stamp = q.stamp.as<uint32_t>();
   uint32_t* infar = q.flag8.as<uint32_t>();
   uint32_t* rlist = q.rlist.as<uint32_t>();
@@ -346,8 +345,8 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   auto relax = [&](unsigned long long nfq, int mode) -> hipError_t {
     int nxt = slot ^ 1;
     // far entries found by this pass are appended after the current far list
-    RelaxArgs a{g->st, e,         fast,  fr[qi], fr[qi ^ 1], fin + n_far, dist,   stamp,  infar, thr,
-                it,    cnt + nxt, mode,  delta,  rlist,      rcount,      rstamp, phase};
+    RelaxArgs a{g->st, e,     fast,  fr[qi], fr[qi ^ 1], dist,  stamp,  infar, thr,
+                it,    cnt + nxt, mode, delta,  rlist,      rcount, rstamp, phase};
     {
       ProfScope ps(g, KID_SSSP_RELAX, s);
       k_sssp_relax<<<chunks_grid((const void*)k_sssp_relax, nfq, q.lch), Q_THREADS, 0, s>>>(a, nfq, cnt + slot);
@@ -398,16 +397,15 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
       thr = far_min == DIST_INF ? thr + delta
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       int nxt = slot ^ 1;
-      SplitArgs a{g->st, fin, fout, fr[qi], dist, stamp, infar, thr, it, cnt + nxt};
+      SplitArgs a{g->st, fr[qi], dist, stamp, infar, thr, it, cnt + nxt};
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);
-        k_sssp_split<<<lanes_grid((const void*)k_sssp_split, n_far), Q_THREADS, 0, s>>>(a, n_far, cnt + slot);
+        k_sssp_split<<<lanes_grid((const void*)k_sssp_split, V), Q_THREADS, 0, s>>>(a, cnt + slot);
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
       if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
       slot = nxt;
-      std::swap(fin, fout);
       n_far = hc.n_far;
       near = hc.fq;
       far_min = hc.far_min;
