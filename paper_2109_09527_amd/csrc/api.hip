@@ -113,13 +113,13 @@ static hipError_t realloc_pool(DevBuf& buf, DevBuf& sbuf, Pool& p, uint64_t new_
   void* ns = nullptr;
   hipError_t e = hipMalloc(&np, new_cap * p.words * 4ull);
   if (e != hipSuccess) return e;
-  if ((e = hipMalloc(&ns, new_cap * 8ull)) != hipSuccess) {
+  if ((e = hipMalloc(&ns, new_cap * SUM_WORDS * 4ull)) != hipSuccess) {
     hipFree(np);
     return e;
   }
   if (used_buckets) {
     e = hipMemcpy(np, p.base, used_buckets * p.words * 4ull, hipMemcpyDeviceToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ns, p.sum, used_buckets * 8ull, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ns, p.sum, used_buckets * SUM_WORDS * 4ull, hipMemcpyDeviceToDevice);
     if (e != hipSuccess) {
       hipFree(np);
       hipFree(ns);
@@ -131,7 +131,7 @@ static hipError_t realloc_pool(DevBuf& buf, DevBuf& sbuf, Pool& p, uint64_t new_
   buf.p = np;
   buf.bytes = new_cap * p.words * 4ull;
   sbuf.p = ns;
-  sbuf.bytes = new_cap * 8ull;
+  sbuf.bytes = new_cap * SUM_WORDS * 4ull;
   p.base = static_cast<uint32_t*>(np);
   p.sum = static_cast<uint32_t*>(ns);
   p.cap = new_cap;
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_compact_exec(Pool op, Pool np, uint64_t
       SlotRef r = claim_slot(ns, d, (uint32_t)stamp);
       if (np.words == FWD_WORDS) *slot_w(r.bp, r.j) = *slot_w(bp, j);
       *slot_stamp(r.bp, r.j, ns.words) = stamp;
-      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j);
+      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j, (uint32_t)(stamp >> 32));
     }
     __threadfence();
     __syncthreads();
@@ -265,7 +265,7 @@ static dg_status compact_pool(dg_graph* g, bool fwd, hipStream_t s) {
     g->err = "compaction: out of device memory";
     return DG_E_OUT_OF_MEMORY;
   }
-  if ((e = hipMalloc(&nsum, ncap * 8ull)) != hipSuccess) {
+  if ((e = hipMalloc(&nsum, ncap * SUM_WORDS * 4ull)) != hipSuccess) {
     hipFree(np);
     g->err = "compaction: out of device memory";
     return DG_E_OUT_OF_MEMORY;
@@ -287,7 +287,7 @@ static dg_status compact_pool(dg_graph* g, bool fwd, hipStream_t s) {
   buf.p = np;
   buf.bytes = ncap * p.words * 4ull;
   sbuf.p = nsum;
-  sbuf.bytes = ncap * 8ull;
+  sbuf.bytes = ncap * SUM_WORDS * 4ull;
   p = npool;
   release(nbk);
   release(kept);
@@ -359,8 +359,8 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   E(g->cursor, 16);
   E(g->fpool, fcap * FWD_WORDS * 4ull);
   E(g->rpool, rcap * REV_WORDS * 4ull);
-  E(g->fsum, fcap * 8ull);
-  E(g->rsum, rcap * 8ull);
+  E(g->fsum, fcap * SUM_WORDS * 4ull);
+  E(g->rsum, rcap * SUM_WORDS * 4ull);
   if (e == hipSuccess) {
     hipMemset(g->fdesc.p, 0, V * 8ull);
     hipMemset(g->rdesc.p, 0, V * 8ull);

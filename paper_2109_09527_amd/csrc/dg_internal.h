@@ -11,11 +11,14 @@
 //                          [16,32) weight
 //                          [32,64) stamp[16] as u64 = birth | death << 32
 //   rpool                reverse buckets, 48 words each: src[16], stamp[16]
-//   fsum / rsum          per-bucket summary, two u32: the largest birth of
-//                        any version in the bucket and a 16-bit mask of the
-//                        slots whose version has been tombstoned.  With no
-//                        concurrent writer, a scan at epoch e >= that birth
-//                        reads a slot's stamp only when its mask bit is set.
+//   fsum / rsum          per-bucket summary, four u32: the largest birth of
+//                        any version in the bucket, a 16-bit mask of the
+//                        slots whose version has been tombstoned, the
+//                        largest death among them, and a spare word.  With
+//                        no concurrent writer, a scan at epoch e >= that
+//                        birth reads no stamp at all when every tombstone
+//                        died at or before e, and otherwise only the stamps
+//                        of tombstoned slots.
 //   alive[v]             liveness at the latest epoch
 // A version is visible at epoch e iff birth <= e < death; death = INF for
 // the current version.  A slot's bucket is hash(dst) mod buckets, with
@@ -32,6 +35,7 @@ constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr uint32_t INF_EPOCH = 0xFFFFFFFFu;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int BSLOTS = 16;
+constexpr int SUM_WORDS = 4;   // bucket summary: max birth, tomb mask, max death, spare
 constexpr int FWD_WORDS = 64;
 constexpr int REV_WORDS = 48;
 constexpr uint64_t EMPTY_STAMP = ~0ull;
@@ -42,7 +46,7 @@ enum : uint32_t { F_BAD_TYPE = 1, F_BAD_VERTEX = 2, F_BAD_WEIGHT = 4, F_OOM = 8 
 
 struct Pool {
   uint32_t* base;       // bucket b starts at base + b * words
-  uint32_t* sum;        // bucket b's summary at sum[2b] (max birth), sum[2b+1] (tomb mask)
+  uint32_t* sum;        // bucket b's summary at sum[4b .. 4b+4)
   uint64_t cap;         // buckets
   uint32_t words;       // 64 (forward) or 48 (reverse)
 };
@@ -88,14 +92,14 @@ __device__ inline Slab slab_of(const Pool& p, uint64_t desc) {
     s.nb = 0;
   } else {
     s.base = p.base + (desc >> 6) * p.words;
-    s.sum = p.sum + (desc >> 6) * 2;
+    s.sum = p.sum + (desc >> 6) * SUM_WORDS;
     s.nb = 1u << (desc & 63);
   }
   return s;
 }
 
 __device__ inline Slab slab_at(const Pool& p, uint64_t off, uint32_t nb) {
-  return Slab{p.base + off * p.words, p.sum + off * 2, nb, p.words};
+  return Slab{p.base + off * p.words, p.sum + off * SUM_WORDS, nb, p.words};
 }
 
 __device__ inline uint32_t* bucket_ptr(const Slab& s, uint32_t b) { return s.base + (uint64_t)b * s.words; }
@@ -178,7 +182,7 @@ __device__ inline SlotRef claim_slot(const Slab& s, uint32_t x, uint32_t birth) 
       uint32_t* pd = slot_dst(bp, j);
       if (ld_relaxed(pd) != EMPTY) continue;
       if (!raised) {
-        atomicMax(&s.sum[2 * b], birth);
+        atomicMax(&s.sum[SUM_WORDS * b], birth);
         raised = true;
       }
       if (atomicCAS(pd, EMPTY, x) == EMPTY) { r.bp = bp; r.j = j; r.b = b; return r; }
@@ -188,12 +192,16 @@ __device__ inline SlotRef claim_slot(const Slab& s, uint32_t x, uint32_t birth) 
   return r;
 }
 
-// Record in the bucket summary that slot j now carries a finite death.
-__device__ inline void mark_tomb(const Slab& s, uint32_t b, int j) { atomicOr(&s.sum[2 * b + 1], 1u << j); }
+// Record in the bucket summary that slot j now carries the finite death
+// `death`.
+__device__ inline void mark_tomb(const Slab& s, uint32_t b, int j, uint32_t death) {
+  atomicOr(&s.sum[SUM_WORDS * b + 1], 1u << j);
+  atomicMax(&s.sum[SUM_WORDS * b + 2], death);
+}
 
 // Initialise the summaries of nb fresh buckets (no version, no tombstone).
 __device__ inline void clear_summaries(uint32_t* sum, uint32_t nb, uint32_t tid, uint32_t nthreads) {
-  for (uint32_t t = tid; t < 2 * nb; t += nthreads) sum[t] = 0u;
+  for (uint32_t t = tid; t < SUM_WORDS * nb; t += nthreads) sum[t] = 0u;
 }
 
 // Whether slot j of bucket b (holding dst d != EMPTY) is visible at e.
@@ -202,10 +210,23 @@ __device__ inline void clear_summaries(uint32_t* sum, uint32_t nb, uint32_t tid,
 // version born after e.
 __device__ inline bool slot_visible(const Slab& s, uint32_t* bp, uint32_t b, int j, uint32_t e, bool fast) {
   if (fast) {
-    uint2 sm = *reinterpret_cast<const uint2*>(&s.sum[2 * b]);
-    if (sm.x <= e && !((sm.y >> j) & 1u)) return true;
+    const uint4 sm = *reinterpret_cast<const uint4*>(&s.sum[SUM_WORDS * b]);
+    if (sm.x <= e) {
+      if (!((sm.y >> j) & 1u)) return true;   // live, born at or before e
+      if (sm.z <= e) return false;            // tombstoned at or before e
+    }
   }
   return visible(*slot_stamp(bp, j, s.words), e);
+}
+
+// The same decision from a summary already loaded (x max birth, y tomb
+// mask, z max death); `stamp` is read only when the summary cannot decide.
+__device__ inline bool visible_by_summary(uint4 sm, bool fast, int j, uint32_t e, const uint64_t* stamp) {
+  if (fast && sm.x <= e) {
+    if (!((sm.y >> j) & 1u)) return true;
+    if (sm.z <= e) return false;
+  }
+  return visible(*stamp, e);
 }
 
 // ------------------------------------------------------------ wave helpers

@@ -425,7 +425,7 @@ template <bool WITH_W>
 __device__ inline Pairs4 load_pairs(const Pool& p, const ChunkView& cv, uint32_t f0, uint32_t grp, uint32_t j,
                                     uint32_t e, bool fast) {
   Pairs4 r;
-  uint2 sm[4];
+  uint4 sm[4];
   uint32_t* bp[4];
   // owner of f0: the last lane whose item starts at or before it (starts
   // increase with the lane); owners of f0 + 1 .. f0 + 15 follow it
@@ -446,7 +446,7 @@ __device__ inline Pairs4 load_pairs(const Pool& p, const ChunkView& cv, uint32_t
     r.item[k] = own;
     r.d[k] = EMPTY;
     r.w[k] = 0;
-    sm[k] = make_uint2(0xFFFFFFFFu, 0xFFFFu);
+    sm[k] = make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
     bp[k] = p.base;
     if (f < cv.hi) {
       Slab s = slab_of(p, desc);
@@ -454,15 +454,14 @@ __device__ inline Pairs4 load_pairs(const Pool& p, const ChunkView& cv, uint32_t
       bp[k] = bucket_ptr(s, b);
       r.d[k] = bp[k][j];
       if (WITH_W) r.w[k] = (int32_t)bp[k][16 + j];
-      if (fast) sm[k] = *reinterpret_cast<const uint2*>(&s.sum[2 * b]);
+      if (fast) sm[k] = *reinterpret_cast<const uint4*>(&s.sum[SUM_WORDS * b]);
     }
   }
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     bool v = false;
     if (r.d[k] != EMPTY) {
-      if (fast && sm[k].x <= e && !((sm[k].y >> j) & 1u)) v = true;
-      else v = visible(*slot_stamp(bp[k], j, p.words), e);
+      v = visible_by_summary(sm[k], fast, j, e, slot_stamp(bp[k], j, p.words));
     }
     r.vis[k] = v;
   }
@@ -543,8 +542,8 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
     bool found = false;
     if (act && s.nb == 1) {
       const uint4* src4 = reinterpret_cast<const uint4*>(s.base);
-      uint2 sm = a.fast ? *reinterpret_cast<const uint2*>(s.sum) : make_uint2(0xFFFFFFFFu, 0xFFFFu);
-      bool fastb = a.fast && sm.x <= a.e;
+      const uint4 sm = a.fast ? *reinterpret_cast<const uint4*>(s.sum)
+                              : make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
       bool more = true;   // no empty slot seen yet (used slots are a prefix)
       // four slots per 16-byte load; each slot is tested in turn until a
       // parent is found or an empty slot ends the bucket
@@ -554,7 +553,7 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
           more = false;
           return;
         }
-        bool vis = (fastb && !((sm.y >> j) & 1u)) || visible(*slot_stamp(s.base, j, s.words), a.e);
+        bool vis = visible_by_summary(sm, a.fast, j, a.e, slot_stamp(s.base, j, s.words));
         if (vis) {
           lc.arcs++;
           found = bm_test(a.bm_cur, x);
@@ -624,24 +623,23 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
       bool hit = false;
       uint32_t d[4];
       uint32_t* bp[4];
-      uint2 sm[4];
+      uint4 sm[4];
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         d[k] = EMPTY;
         bp[k] = iv.s.base;
-        sm[k] = make_uint2(0xFFFFFFFFu, 0xFFFFu);
+        sm[k] = make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
         if (!found && i + k < iv.nbk) {
           const uint32_t b = iv.b0 + i + k;
           bp[k] = bucket_ptr(iv.s, b);
           d[k] = bp[k][j];
-          if (a.fast) sm[k] = *reinterpret_cast<const uint2*>(&iv.s.sum[2 * b]);
+          if (a.fast) sm[k] = *reinterpret_cast<const uint4*>(&iv.s.sum[SUM_WORDS * b]);
         }
       }
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         if (d[k] == EMPTY) continue;
-        bool vis = (a.fast && sm[k].x <= a.e && !((sm[k].y >> j) & 1u)) ||
-                   visible(*slot_stamp(bp[k], j, iv.s.words), a.e);
+        bool vis = visible_by_summary(sm[k], a.fast, j, a.e, slot_stamp(bp[k], j, iv.s.words));
         if (vis) {
           lc.arcs++;
           hit |= bm_test(a.bm_cur, d[k]);

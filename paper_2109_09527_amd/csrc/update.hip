@@ -298,7 +298,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint3
       SlotRef r = claim_slot(ns, d, (uint32_t)stamp);
       if (fwd) *slot_w(r.bp, r.j) = *slot_w(bp, j);
       *slot_stamp(r.bp, r.j, ns.words) = stamp;
-      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j);
+      if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j, (uint32_t)(stamp >> 32));
       kept++;
     }
     if (kept) atomicAdd(&s_kept, kept);
@@ -319,7 +319,7 @@ __device__ inline bool tombstone_in(const Pool& p, uint64_t desc, uint32_t key, 
   SlotRef r = find_current(s, key);
   if (!r.bp) return false;
   if (atomicCAS(slot_death(r.bp, r.j, s.words), INF_EPOCH, E) != INF_EPOCH) return false;
-  mark_tomb(s, r.b, r.j);
+  mark_tomb(s, r.b, r.j, E);
   return true;
 }
 
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
       uint32_t d = ld_relaxed(slot_dst(bp, j));
       if (d == EMPTY) continue;
       if (atomicCAS(slot_death(bp, j, fs.words), INF_EPOCH, E) != INF_EPOCH) continue;
-      mark_tomb(fs, t / BSLOTS, j);
+      mark_tomb(fs, t / BSLOTS, j, E);
       dropped++;
       if (!st.undirected) tombstone_in(st.rp, st.rdesc[d], x, E);
       else if (d != x && tombstone_in(st.fp, st.fdesc[d], x, E)) dropped++;
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
         uint32_t sv = ld_relaxed(slot_dst(bp, j));
         if (sv == EMPTY) continue;
         if (atomicCAS(slot_death(bp, j, rs.words), INF_EPOCH, E) != INF_EPOCH) continue;
-        mark_tomb(rs, t / BSLOTS, j);
+        mark_tomb(rs, t / BSLOTS, j, E);
         if (tombstone_in(st.fp, st.fdesc[sv], x, E)) dropped++;
       }
     }
