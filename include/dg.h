@@ -153,6 +153,7 @@ typedef struct {
   uint32_t alpha, beta;    /* direction-switch thresholds of the BFS */
   uint32_t batch_groups;   /* workgroups per query team in the persistent launch; 0 = automatic */
   uint32_t batch_delta;    /* delta-stepping bucket width inside the persistent launch */
+  uint32_t batch_gang;     /* SSSP queries advanced in lockstep by one persistent launch, 1..128; 0 = automatic */
 } dg_tuning;
 dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t);
 dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t);

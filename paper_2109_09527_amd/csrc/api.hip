@@ -640,6 +640,7 @@ dg_status dg_get_tuning(const dg_graph* g, dg_tuning* t) {
   t->beta = g->tune.beta;
   t->batch_groups = g->tune.batch_groups;
   t->batch_delta = g->tune.batch_delta;
+  t->batch_gang = g->tune.batch_gang;
   return DG_OK;
 }
 
@@ -649,6 +650,7 @@ dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t) {
   if (C != 16 && C != 32 && C != 64) return fail(g, DG_E_INVALID_ARG, "chunk_buckets must be 16, 32 or 64");
   if (t->sssp_delta == 0 || t->alpha == 0 || t->beta == 0 || t->batch_delta == 0)
     return fail(g, DG_E_INVALID_ARG, "tuning values must be positive");
+  if (t->batch_gang > 128) return fail(g, DG_E_INVALID_ARG, "batch_gang must be at most 128");
   std::lock_guard<std::mutex> lk(g->mu);
   g->tune.chunk_buckets = C;
   g->tune.sssp_delta = t->sssp_delta;
@@ -656,6 +658,7 @@ dg_status dg_set_tuning(dg_graph* g, const dg_tuning* t) {
   g->tune.beta = t->beta;
   g->tune.batch_groups = t->batch_groups;
   g->tune.batch_delta = t->batch_delta;
+  g->tune.batch_gang = t->batch_gang;
   return DG_OK;
 }
 

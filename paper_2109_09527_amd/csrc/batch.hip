@@ -36,11 +36,30 @@
 
 namespace dg {
 
+// Arrival counters of a team barrier: members arrive at one of up to
+// SYNC_FAN counters, whose last arrivals arrive at the team counter.
+constexpr uint32_t SYNC_FAN = 32;
+
+// One arrival counter and its release word, on a 128-byte line of its own.
+struct alignas(128) SyncLine {
+  uint32_t count;   // members of this group at the current barrier
+  uint32_t gen;     // barriers released
+  uint32_t pad[30];
+};
+
 struct TeamSync {
-  uint32_t count, gen, q;
+  uint32_t count;    // groups complete at the current barrier
+  uint32_t q;        // the team's current query (engine teams)
   uint32_t joined;   // members that have started
   uint32_t state;    // 0 forming, 1 active, 2 dead
-  uint32_t pad[11];
+  uint32_t pad[28];
+  SyncLine line[SYNC_FAN];
+};
+
+// A workgroup's place in its team's barrier.
+struct BarrierPos {
+  uint32_t gen;   // barriers passed
+  uint32_t w;     // index of the workgroup in its team
 };
 
 struct Ctrl {
@@ -117,36 +136,63 @@ struct BatchArgs {
   uint64_t spin_ticks;    // longest wait, in wall-clock ticks
 };
 
-__device__ inline bool team_barrier(TeamSync* ts, uint32_t S, uint32_t& gen, Ctrl* ctrl, Shared& sh,
+// Wait, bounded, until *p differs from old; a timeout or another member's
+// abort sets the launch's abort flag.
+__device__ inline bool wait_change(const uint32_t* p, uint32_t old, Ctrl* ctrl, uint64_t spin_ticks) {
+  const uint64_t t0 = wall_clock64();
+  for (uint32_t k = 1; ld_relaxed(p) == old; k++) {
+    __builtin_amdgcn_s_sleep(1);
+    if (wall_clock64() - t0 > spin_ticks || ((k & 15) == 0 && ld_relaxed(&ctrl->abort))) {
+      atomicExch(&ctrl->abort, 1u);
+      return false;
+    }
+  }
+  return true;
+}
+
+// Team barrier.  Each member writes its data back from its XCD's L2
+// (agent-scope release by one wave, after the workgroup barrier) and
+// arrives at counter w mod F; the last arrival of a counter arrives at the
+// team counter, and the last of those releases every counter's waiters.
+// After the release, one wave per workgroup invalidates its CU's L1 and its
+// XCD's L2 (agent-scope acquire); the workgroup barrier after it orders the
+// other waves behind that invalidation.  Fanning arrivals over F counters
+// keeps each counter's chain of same-address atomics short.
+// Returns false when a wait timed out or another member aborted.
+__device__ inline bool team_barrier(TeamSync* ts, uint32_t S, BarrierPos& bp, Ctrl* ctrl, Shared& sh,
                                     uint64_t spin_ticks) {
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const uint32_t my = bp.gen;
+  bp.gen = my + 1;
+  if (threadIdx.x < 64) {
     uint32_t ab = 0;
     if (S > 1) {
-      __threadfence();
-      uint32_t my = gen;
-      if (atomicAdd(&ts->count, 1u) == S - 1) {
-        atomicExch(&ts->count, 0u);
-        __threadfence();
-        atomicAdd(&ts->gen, 1u);
-      } else {
-        const uint64_t t0 = wall_clock64();
-        while (ld_relaxed(&ts->gen) == my) {
-          __builtin_amdgcn_s_sleep(2);
-          if (wall_clock64() - t0 > spin_ticks || ld_relaxed(&ctrl->abort)) {
-            atomicExch(&ctrl->abort, 1u);
-            ab = 1;
-            break;
+      const uint32_t F = S < SYNC_FAN ? S : SYNC_FAN;
+      const uint32_t grp = bp.w % F, ng = S / F + (grp < S % F ? 1u : 0u);
+      uint32_t last = 0;
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (atomicAdd(&ts->line[grp].count, 1u) == ng - 1) {
+          atomicExch(&ts->line[grp].count, 0u);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          if (atomicAdd(&ts->count, 1u) == F - 1) {
+            atomicExch(&ts->count, 0u);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            last = 1;
           }
         }
       }
-      gen = my + 1;
+      last = __shfl(last, 0);
+      if (last) {
+        for (uint32_t i = threadIdx.x; i < F; i += 64) st_relaxed(&ts->line[i].gen, my + 1);
+      } else if (threadIdx.x == 0 && !wait_change(&ts->line[grp].gen, my, ctrl, spin_ticks)) {
+        ab = 1;
+      }
     }
-    if (ld_relaxed(&ctrl->abort)) ab = 1;
-    sh.flag = ab;
+    if (threadIdx.x == 0) sh.flag = ab | ld_relaxed(&ctrl->abort);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return sh.flag == 0;
 }
 
@@ -241,7 +287,7 @@ __device__ inline void team_seed(const Store& st, uint32_t src, const TeamScratc
 
 #define BARRIER()                                          \
   do {                                                     \
-    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return false; \
+    if (!team_barrier(ts.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return false; \
   } while (0)
 
 // A frontier queue ran out of room: the query fails (every member reads the
@@ -255,7 +301,7 @@ __device__ inline void team_seed(const Store& st, uint32_t src, const TeamScratc
   } while (0)
 
 __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
-                                        uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
+                                        uint32_t S, BarrierPos& bp, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   const uint64_t bmw = (V + 31) / 32 + 1;
   int32_t* dist = static_cast<int32_t*>(qd.out);
@@ -304,7 +350,7 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
 // only).  vis and nxt reuse the BC arrays sigma and delta; the touched list
 // lives in fa.
 __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
-                                          uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
+                                          uint32_t S, BarrierPos& bp, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V, k = qd.k;
   int32_t* const* outs = static_cast<int32_t* const*>(qd.out);
   unsigned long long* vis = ts.sigma;
@@ -363,7 +409,7 @@ __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, c
 }
 
 __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
-                                       uint32_t S, uint32_t& gen, Shared& sh, int32_t* status) {
+                                       uint32_t S, BarrierPos& bp, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V;
   double* bc = static_cast<double*>(qd.out);
   team_fill<double>(bc, V, 0.0, w, S);
@@ -422,7 +468,7 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
 // Join a team in start order; returns false when the team never becomes
 // active (queue exhausted first, or a wait timed out).
 __device__ inline bool team_join(Ctrl* ctrl, uint32_t nq, uint64_t spin_ticks, TeamSync* sync, uint32_t S,
-                                 Shared& sh) {
+                                 uint32_t w, Shared& sh, BarrierPos& bp) {
   if (threadIdx.x == 0) {
     uint32_t go = 0;
     if (atomicAdd(&sync->joined, 1u) + 1 == S) {
@@ -452,6 +498,8 @@ __device__ inline bool team_join(Ctrl* ctrl, uint32_t nq, uint64_t spin_ticks, T
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  bp.gen = 0;
+  bp.w = w;
   return sh.flag != 0;
 }
 
@@ -467,22 +515,22 @@ __global__ __launch_bounds__(Q_THREADS, 4) void k_team(BatchArgs a) {
   const uint32_t t = slot / S, w = slot % S;
   if (t >= a.n_teams) return;
   const TeamScratch ts = uni_scratch(a.teams[t]);
-  if (!team_join(a.ctrl, a.nq, a.spin_ticks, ts.sync, S, sh)) return;
-  uint32_t gen = 0;
+  BarrierPos bp;
+  if (!team_join(a.ctrl, a.nq, a.spin_ticks, ts.sync, S, w, sh, bp)) return;
   for (;;) {
     if (w == 0 && threadIdx.x == 0) ts.sync->q = atomicAdd(&a.ctrl->next, 1u);
-    if (!team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
+    if (!team_barrier(ts.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return;
     const uint32_t k = uni(ld_relaxed(&ts.sync->q));
     if (k >= a.nq) return;
     const uint32_t qi = uni(a.qidx[k]);
     const QDesc qd = uni_desc(a.q[qi]);
     bool ok = true;
     if (a.status[qi] == DG_OK) {
-      if (KIND == DG_Q_BFS) ok = qd.k ? run_msbfs(a, qd, ts, w, S, gen, sh, &a.status[qi])
-                                      : run_bfs(a, qd, ts, w, S, gen, sh, &a.status[qi]);
-      else ok = run_bc(a, qd, ts, w, S, gen, sh, &a.status[qi]);
+      if (KIND == DG_Q_BFS) ok = qd.k ? run_msbfs(a, qd, ts, w, S, bp, sh, &a.status[qi])
+                                      : run_bfs(a, qd, ts, w, S, bp, sh, &a.status[qi]);
+      else ok = run_bc(a, qd, ts, w, S, bp, sh, &a.status[qi]);
     }
-    if (!ok || !team_barrier(ts.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
+    if (!ok || !team_barrier(ts.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return;
     if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, 1u);
   }
 }
@@ -715,8 +763,8 @@ __global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
   if (threadIdx.x == 0) sh.base = atomicAdd(&a.ctrl->arrive, 1u);
   __syncthreads();
   const uint32_t w = uni(sh.base), S = gridDim.x;
-  if (!team_join(a.ctrl, 0xFFFFFFFFu, a.spin_ticks, a.sync, S, sh)) return;
-  uint32_t gen = 0;
+  BarrierPos bp;
+  if (!team_join(a.ctrl, 0xFFFFFFFFu, a.spin_ticks, a.sync, S, w, sh, bp)) return;
   const uint32_t nq = a.nq;
   for (uint32_t i = threadIdx.x; i < nq; i += Q_THREADS) {
     GState s{};
@@ -762,7 +810,7 @@ __global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
       gang_work(a, qn, uni_state(gs[qn]), u - p0, end - p0, sh);
       u = end;
     }
-    if (!team_barrier(a.sync, S, gen, a.ctrl, sh, a.spin_ticks)) return;
+    if (!team_barrier(a.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return;
     for (uint32_t i = threadIdx.x; i < nq; i += Q_THREADS) gang_advance(a, a.q[i], gs[i], &a.status[i]);
   }
   if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, nq);
@@ -925,8 +973,9 @@ static dg_status run_sssp_gangs(dg_graph* g, BatchState* bs, const Store& st_, c
   const int32_t delta = (int32_t)std::max<uint32_t>(1, tune.batch_delta);
   const int split_lh = delta < g->cfg.w_max ? 1 : 0;
   const uint64_t per_q = gang_layout(st_, nullptr, nullptr);
+  const uint32_t want = tune.batch_gang ? std::min<uint32_t>(tune.batch_gang, GANG_MAX) : GANG_MAX;
   const uint32_t gang = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>({(uint64_t)GANG_MAX, budget / per_q, (uint64_t)idx.size()}));
+      1, std::min<uint64_t>({(uint64_t)want, budget / per_q, (uint64_t)idx.size()}));
   if (!bs->gang_cap) {
     int per_cu = 0, cus = 0, dev = 0;
     hipGetDevice(&dev);

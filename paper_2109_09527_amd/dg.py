@@ -36,7 +36,7 @@ class Config(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_buckets", _u32), ("sssp_delta", _u32), ("alpha", _u32), ("beta", _u32),
-                ("batch_groups", _u32), ("batch_delta", _u32)]
+                ("batch_groups", _u32), ("batch_delta", _u32), ("batch_gang", _u32)]
 
 
 class Query(ctypes.Structure):

@@ -68,12 +68,13 @@ def build_history(dg, scale, undirected, n_batches, seed, w_max=60):
     return gr, g, epochs, answers
 
 
-def check_batch(dg, g, answers, team_sizes):
+def check_batch(dg, g, answers, shapes):
+    """shapes: (workgroups per team, SSSP queries per lockstep launch)."""
     keys = list(answers.keys())
     n = g.n
-    for S in team_sizes:
-        g.set_tuning(batch_groups=S)
-        say("batch team size", S, "queries", len(keys) + 3)
+    for S, G in shapes:
+        g.set_tuning(batch_groups=S, batch_gang=G)
+        say("batch team size", S, "gang", G, "queries", len(keys) + 3)
         queries, outs = [], []
         for (ep, kind, src) in keys:
             if kind == "bc":
@@ -110,7 +111,9 @@ def check_batch(dg, g, answers, team_sizes):
 @pytest.mark.parametrize("undirected", [False, True])
 def test_batch_matches_plain_and_oracle(dg, undirected):
     gr, g, epochs, answers = build_history(dg, 11, undirected, 3, seed=7 + undirected)
-    check_batch(dg, g, answers, [0, 1, 3, 16])
+    check_batch(dg, g, answers, [(0, 0), (1, 1), (3, 2), (16, 5)])
+    with pytest.raises(dg.DGError):
+        g.set_tuning(batch_gang=129)
 
 
 def test_batch_many_queries_many_teams(dg):
@@ -135,7 +138,7 @@ def test_batch_many_queries_many_teams(dg):
             o.apply(wl.batches[ep_i])
             g.apply(wl.batches[ep_i])
     say("batch many queries")
-    check_batch(dg, g, answers, [0, 2])
+    check_batch(dg, g, answers, [(0, 0), (2, 7)])
 
 
 def test_autotune_keeps_results(dg):
