@@ -181,12 +181,17 @@ dg_status dg_stats(dg_graph* g, dg_epoch e, uint64_t* n_vertices, uint64_t* n_ar
 dg_status dg_out_degrees(dg_graph* g, dg_epoch e, uint32_t* deg, void* stream);
 
 /*
- * Serving loop: a host thread admits requests in arrival order, runs update
- * batches on an update stream (each publishes the next epoch) and queries
- * concurrently on a query stream, binding each query to the latest epoch
- * published when it is admitted (its linearization point).  Admission
- * reserves device memory for a request's outputs and scratch from
- * mem_budget; requests wait while the budget is exhausted.
+ * Serving loop: requests are admitted in arrival order.  Update batches run
+ * on an update stream (each publishes the next epoch).  Queries run on
+ * query_lanes lanes, each a host thread with a stream and an engine instance
+ * of its own: a free lane takes the queries at the head of the queue (up to
+ * max_batch, within max_inflight queries admitted across lanes) and runs
+ * them in one engine launch, binding each to the latest epoch published when
+ * it is admitted (its linearization point).  Queries that arrive while a
+ * lane is busy go to the next lane to come free, so launches overlap on the
+ * device with each other and with update batches.  Admission reserves
+ * device memory for a query's output from mem_budget; queries wait while the
+ * budget is exhausted.
  * dg_server_submit_* copy their inputs and return a ticket immediately;
  * dg_server_poll reports whether a ticket finished, its status, bound epoch
  * and latency; dg_server_take copies a finished query's output to a host
@@ -194,9 +199,10 @@ dg_status dg_out_degrees(dg_graph* g, dg_epoch e, uint32_t* deg, void* stream);
  */
 typedef struct dg_server dg_server;
 typedef struct {
-  uint64_t mem_budget;     /* bytes for in-flight query outputs and scratch */
-  uint32_t max_inflight;   /* queries running at once */
-  uint32_t max_batch;      /* queries fused into one launch */
+  uint64_t mem_budget;     /* bytes for in-flight query outputs; 0 = 8 GiB */
+  uint32_t max_inflight;   /* queries admitted and not yet finished, over all lanes; 0 = 1024 */
+  uint32_t max_batch;      /* queries fused into one launch; 0 = 64 */
+  uint32_t query_lanes;    /* engine launches in flight at once, 1..4; 0 = 1 */
 } dg_server_config;
 typedef struct {
   uint64_t completed, updates, queries, ops_applied;

@@ -850,6 +850,15 @@ __global__ void k_gang_finish(const GQuery* gq, uint32_t V) {
     if (d[i] == DIST_INF) d[i] = -1;
 }
 
+// out[v] = sum over t < k of part[t * V + v], added in t order.
+__global__ void k_bc_sum(const double* part, uint32_t k, uint64_t V, double* out) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
+    double r = 0.0;
+    for (uint32_t t = 0; t < k; t++) r += part[(uint64_t)t * V + v];
+    out[v] = r;
+  }
+}
+
 // ------------------------------------------------------------ host side
 
 struct BatchState {
@@ -859,28 +868,37 @@ struct BatchState {
   int grid_cap[3] = {0, 0, 0};   // resident workgroups of each kind's engine kernel
   DevBuf gang_scratch, gq, gsrc, gsync, gctrl, gstatus;
   int gang_cap = 0;              // resident workgroups of the gang kernel
+  DevBuf bc_part;                // per-source dependency arrays of split BC queries
 };
 
-static std::mutex g_engine_mu;   // one engine launch per process at a time
-static std::map<const dg_graph*, BatchState*> g_states;
+static std::mutex g_engine_mu;   // one engine launch enqueued per process at a time
+// Engine state per (graph, lane): each lane owns its buffers, so launches of
+// different lanes can be in flight together on different streams.
+static std::map<std::pair<const dg_graph*, uint32_t>, BatchState*> g_states;
 static std::mutex g_states_mu;
 
-static BatchState* state_of(dg_graph* g) {
+static BatchState* state_of(dg_graph* g, uint32_t lane) {
   std::lock_guard<std::mutex> lk(g_states_mu);
-  auto& p = g_states[g];
+  auto& p = g_states[{g, lane}];
   if (!p) p = new BatchState();
   return p;
 }
 
 void free_batch_state(dg_graph* g) {
   std::lock_guard<std::mutex> lk(g_states_mu);
-  auto it = g_states.find(g);
-  if (it == g_states.end()) return;
-  BatchState* b = it->second;
-  for (DevBuf* d : {&b->scratch, &b->teams, &b->qdesc, &b->qidx, &b->srcs, &b->status, &b->arcs, &b->live, &b->ctrl})
-    release(*d);
-  delete b;
-  g_states.erase(it);
+  for (auto it = g_states.begin(); it != g_states.end();) {
+    if (it->first.first != g) {
+      ++it;
+      continue;
+    }
+    BatchState* b = it->second;
+    for (DevBuf* d : {&b->scratch, &b->teams, &b->qdesc, &b->qidx, &b->srcs, &b->outs, &b->status, &b->arcs,
+                      &b->live, &b->ctrl, &b->gang_scratch, &b->gq, &b->gsrc, &b->gsync, &b->gctrl, &b->gstatus,
+                      &b->bc_part})
+      release(*d);
+    delete b;
+    it = g_states.erase(it);
+  }
 }
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -1049,10 +1067,11 @@ static dg_status run_sssp_gangs(dg_graph* g, BatchState* bs, const Store& st_, c
   return DG_OK;
 }
 
-dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, hipStream_t s) {
+dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, hipStream_t s,
+                          uint32_t lane) {
   if (nq == 0) return DG_OK;
   if (!q || !per_query) return bfail(g, DG_E_INVALID_ARG, "null query array or status array");
-  BatchState* bs = state_of(g);
+  BatchState* bs = state_of(g, lane);
   std::lock_guard<std::mutex> blk(bs->mu);
   hipError_t e;
   // host state is read (and the epochs in use pinned) under the graph
@@ -1157,7 +1176,43 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
     }
     by_kind[DG_Q_BFS] = jobs;
   }
-  const uint32_t nj = (uint32_t)qd.size();   // queries and group jobs
+  // A BC query of k > 1 sources runs as k one-source jobs, each writing its
+  // own dependency array, when those fit the engine's memory budget; a
+  // reduction then adds the k arrays in source order.  A single
+  // team would have added the same per-source terms to zero in the same
+  // order (x + 0 = x exactly where a source does not reach or is the
+  // vertex), so the sum is the same bit for bit, and the sources run on
+  // k teams at once.
+  const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
+  struct BcSplit {
+    uint32_t q, j0, k;
+    uint64_t off;   // first partial array, in doubles from the partials buffer
+  };
+  std::vector<BcSplit> splits;
+  uint64_t part_words = 0;
+  {
+    const uint64_t V = st_.V;
+    std::vector<uint32_t> jobs, whole;   // whole: multi-source queries left unsplit
+    for (uint32_t i : by_kind[DG_Q_BC]) {
+      const uint32_t k = qd[i].k;
+      if (k < 2 || (part_words + (uint64_t)k * V) * 8 > budget) {
+        (k < 2 ? jobs : whole).push_back(i);
+        continue;
+      }
+      splits.push_back(BcSplit{i, (uint32_t)qd.size(), k, part_words});
+      part_words += (uint64_t)k * V;
+      for (uint32_t t = 0; t < k; t++) {
+        jobs.push_back((uint32_t)qd.size());
+        src_off.push_back(src_off[i] + t);
+        qd.push_back(QDesc{DG_Q_BC, 0, qd[i].epoch, 1, nullptr, nullptr});
+        st.push_back(DG_OK);
+      }
+    }
+    // the longest jobs (unsplit multi-source queries) are taken first
+    whole.insert(whole.end(), jobs.begin(), jobs.end());
+    by_kind[DG_Q_BC] = whole;
+  }
+  const uint32_t nj = (uint32_t)qd.size();   // queries, group jobs and BC source jobs
   // resident workgroups per kind's kernel
   for (int k = 0; k < 3; k++) {
     if (bs->grid_cap[k] || by_kind[k].empty() || k == DG_Q_SSSP) continue;
@@ -1176,7 +1231,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   }
   // teams: size from the tuning (0 = automatic), count bounded by memory
   const uint64_t per_team = team_layout(st_, tune.chunk_buckets, nullptr, nullptr);
-  const uint64_t budget = g->cfg.mem_budget ? g->cfg.mem_budget / 4 : (16ull << 30);
   const uint32_t max_teams = (uint32_t)std::max<uint64_t>(1, budget / per_team);
   uint32_t S_of[3] = {1, 1, 1}, T_of[3] = {0, 0, 0}, most = 1;
   for (int k = 0; k < 3; k++) {
@@ -1200,10 +1254,17 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
       (e = ensure(bs->outs, std::max<size_t>(1, all_outs.size()) * sizeof(void*))) != hipSuccess ||
       (e = ensure(bs->status, nj * 4)) != hipSuccess || (e = ensure(bs->arcs, e_cnt * 8)) != hipSuccess ||
-      (e = ensure(bs->live, e_cnt * 8)) != hipSuccess || (e = ensure(bs->ctrl, 3 * sizeof(Ctrl))) != hipSuccess)
+      (e = ensure(bs->live, e_cnt * 8)) != hipSuccess || (e = ensure(bs->ctrl, 3 * sizeof(Ctrl))) != hipSuccess ||
+      (part_words && (e = ensure(bs->bc_part, part_words * 8)) != hipSuccess))
     return bfail(g, DG_E_OUT_OF_MEMORY, "batch descriptor allocation");
   for (uint32_t i = 0; i < nq; i++)
     if (qd[i].kind == DG_Q_BC) qd[i].srcs = bs->srcs.as<uint32_t>() + src_off[i];
+  for (const BcSplit& sp : splits)
+    for (uint32_t t = 0; t < sp.k; t++) {
+      QDesc& d = qd[sp.j0 + t];
+      d.srcs = bs->srcs.as<uint32_t>() + src_off[sp.j0 + t];
+      d.out = bs->bc_part.as<double>() + sp.off + (uint64_t)t * st_.V;
+    }
   for (size_t gi = 0; gi < group_job.size(); gi++) {
     QDesc& d = qd[group_job[gi]];
     d.srcs = bs->srcs.as<uint32_t>() + src_off[group_job[gi]];
@@ -1280,6 +1341,18 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   }
   for (size_t gi = 0; gi < groups.size(); gi++)
     for (uint32_t u : groups[gi]) st[u] = st[group_job[gi]];
+  if (!splits.empty()) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((st_.V + 255) / 256, 4096);
+    for (const BcSplit& sp : splits) {
+      st[sp.q] = DG_OK;
+      for (uint32_t t = 0; t < sp.k && st[sp.q] == DG_OK; t++) st[sp.q] = st[sp.j0 + t];
+      if (st[sp.q] == DG_OK)
+        k_bc_sum<<<std::max<uint32_t>(1, grid), 256, 0, s>>>(bs->bc_part.as<double>() + sp.off, sp.k, st_.V,
+                                                             static_cast<double*>(qd[sp.q].out));
+    }
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+      return bfail(g, DG_E_HIP, std::string("batch BC sum: ") + hipGetErrorString(e));
+  }
   for (uint32_t i = 0; i < nq; i++) per_query[i] = st[i];
   return DG_OK;
 }
@@ -1289,7 +1362,7 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
 extern "C" dg_status dg_query_batch(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   try {
-    return dg::query_batch_dev(g, q, nq, per_query, static_cast<hipStream_t>(stream));
+    return dg::query_batch_dev(g, q, nq, per_query, static_cast<hipStream_t>(stream), 0);
   } catch (...) {
     g->err = "unexpected failure in dg_query_batch";
     return DG_E_HIP;

@@ -173,8 +173,10 @@ dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hi
 void free_query_scratch(QueryScratch& q);
 
 // batch.hip
+// lane: engine instance (its own buffers); lanes may run at once on
+// different streams, each within its share of the resident workgroups.
 dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status* per_query,
-                          hipStream_t s);
+                          hipStream_t s, uint32_t lane);
 void free_batch_state(dg_graph* g);
 
 }  // namespace dg

@@ -3,17 +3,21 @@
 //
 //   update thread  applies update requests in arrival order on its own
 //                  stream; each publishes the next epoch.
-//   query thread   whenever the engine is free, admits waiting queries in
-//                  arrival order while their output memory fits the budget
-//                  (up to max_batch at once), binds them to the latest
-//                  published epoch (their linearization point) and runs them
-//                  in one persistent engine launch on the query stream, which
-//                  overlaps the update stream's kernels.  Queries arriving
-//                  meanwhile wait for the next admission round.
+//   query lanes    (query_lanes threads, each with a stream and an engine
+//                  instance of its own) each take, whenever it is free, the
+//                  waiting queries at the head of the queue in arrival order
+//                  while their output memory fits the budget and the
+//                  in-flight cap allows (up to max_batch at once), bind them
+//                  to the latest published epoch (their linearization point)
+//                  and run them in one persistent engine launch.  A query
+//                  arriving while a lane is busy is taken by the next lane to
+//                  come free, so the launches of different lanes overlap on
+//                  the device with each other and with the update stream.
 // While a server runs, scans read per-slot stamps (no summary fast path),
 // since update kernels may write slabs under running queries, and the
-// engine leaves part of the device's resident-workgroup capacity free for
-// the update kernels.  Latency = completion - submission, host clock.
+// engine launches share part of the device's resident-workgroup capacity
+// (the rest stays free for the update kernels).  Latency = completion -
+// submission, host clock.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -21,6 +25,7 @@
 #include <deque>
 #include <memory>
 #include <thread>
+#include <vector>
 
 #include "dg_host.h"
 
@@ -62,8 +67,11 @@ struct dg_server {
   bool stop = false;
   uint64_t mem_used = 0;
   uint32_t busy = 0;             // requests taken by a worker, not yet finished
-  std::thread tu, tq;
-  hipStream_t su = nullptr, sq = nullptr;
+  uint32_t q_running = 0;        // queries taken by a lane, not yet finished
+  std::thread tu;
+  std::vector<std::thread> tq;   // one per query lane
+  hipStream_t su = nullptr;
+  std::vector<hipStream_t> sq;   // one per query lane
   clk::time_point t0;
   std::vector<double> lat_all, lat_q, lat_u;
   uint64_t ops_applied = 0, arcs = 0, n_upd = 0, n_qry = 0;
@@ -95,6 +103,7 @@ struct dg_server {
     mem_used -= r->reserve;
     r->reserve = 0;
     busy--;
+    if (r->kind >= 0) q_running--;
     cv_done.notify_all();
     cv.notify_all();
   }
@@ -117,22 +126,23 @@ struct dg_server {
     }
   }
 
-  void query_loop() {
+  void query_loop(uint32_t lane) {
     std::vector<Req*> batch;
     std::vector<dg::DevBuf> outs;
+    hipStream_t sq_ = sq[lane];
     for (;;) {
       batch.clear();
       {
         std::unique_lock<std::mutex> lk(m);
         cv.wait(lk, [&] {
           if (stop && qq.empty()) return true;
-          return !qq.empty() && mem_used + out_bytes(qq.front()) <= cfg.mem_budget;
+          return !qq.empty() && q_running < cfg.max_inflight && mem_used + out_bytes(qq.front()) <= cfg.mem_budget;
         });
         if (qq.empty()) {
           for (auto& o : outs) dg::release(o);
           return;
         }
-        while (!qq.empty() && batch.size() < cfg.max_batch) {
+        while (!qq.empty() && batch.size() < cfg.max_batch && q_running < cfg.max_inflight) {
           Req* r = qq.front();
           uint64_t need = out_bytes(r);
           if (mem_used + need > cfg.mem_budget) break;   // arrival order: the head waits
@@ -141,6 +151,7 @@ struct dg_server {
           batch.push_back(r);
           qq.pop_front();
           busy++;
+          q_running++;
         }
       }
       // linearization point: the latest published epoch, pinned until done
@@ -159,7 +170,8 @@ struct dg_server {
                          r->kind == DG_Q_BC ? r->srcs.data() : nullptr, outs[i].p};
       }
       const uint64_t arcs0 = g->engine_arcs.load();
-      dg_status call = alloc_ok ? dg_query_batch(g, qs.data(), (uint32_t)n, st.data(), sq) : DG_E_OUT_OF_MEMORY;
+      dg_status call =
+          alloc_ok ? dg::query_batch_dev(g, qs.data(), (uint32_t)n, st.data(), sq_, 1 + lane) : DG_E_OUT_OF_MEMORY;
       {
         std::lock_guard<std::mutex> lk(m);
         arcs += g->engine_arcs.load() - arcs0;
@@ -169,8 +181,8 @@ struct dg_server {
         dg_status s = call != DG_OK ? call : st[i];
         if (s == DG_OK) {
           r->out.resize(out_bytes(r));
-          if (hipMemcpyAsync(r->out.data(), outs[i].p, r->out.size(), hipMemcpyDeviceToHost, sq) != hipSuccess ||
-              hipStreamSynchronize(sq) != hipSuccess)
+          if (hipMemcpyAsync(r->out.data(), outs[i].p, r->out.size(), hipMemcpyDeviceToHost, sq_) != hipSuccess ||
+              hipStreamSynchronize(sq_) != hipSuccess)
             s = DG_E_HIP;
         }
         finish(r, s, e_bind);
@@ -191,9 +203,22 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   s->cfg = *cfg;
   if (!s->cfg.mem_budget) s->cfg.mem_budget = 8ull << 30;
   if (!s->cfg.max_batch) s->cfg.max_batch = 64;
-  if (hipStreamCreateWithFlags(&s->su, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->sq, hipStreamNonBlocking) != hipSuccess) {
+  if (!s->cfg.max_inflight) s->cfg.max_inflight = 1024;
+  if (!s->cfg.query_lanes) s->cfg.query_lanes = 1;
+  if (s->cfg.query_lanes > 4) {
+    delete s;
+    g->err = "query_lanes must be at most 4";
+    return DG_E_INVALID_ARG;
+  }
+  bool ok = hipStreamCreateWithFlags(&s->su, hipStreamNonBlocking) == hipSuccess;
+  for (uint32_t i = 0; ok && i < s->cfg.query_lanes; i++) {
+    hipStream_t x = nullptr;
+    ok = hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+    if (ok) s->sq.push_back(x);
+  }
+  if (!ok) {
     if (s->su) hipStreamDestroy(s->su);
+    for (hipStream_t x : s->sq) hipStreamDestroy(x);
     delete s;
     g->err = "server stream creation";
     return DG_E_HIP;
@@ -201,11 +226,12 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   {
     std::lock_guard<std::mutex> lk(g->mu);
     g->concurrent_writers++;
-    g->engine_share_pct = 75;
+    // three quarters of the resident workgroups, split over the lanes
+    g->engine_share_pct = std::max<uint32_t>(1, 75 / s->cfg.query_lanes);
   }
   s->t0 = clk::now();
   s->tu = std::thread([s] { s->update_loop(); });
-  s->tq = std::thread([s] { s->query_loop(); });
+  for (uint32_t i = 0; i < s->cfg.query_lanes; i++) s->tq.emplace_back([s, i] { s->query_loop(i); });
   *out = s;
   return DG_OK;
 }
@@ -218,11 +244,13 @@ dg_status dg_server_stop(dg_server* s) {
   }
   s->cv.notify_all();
   s->tu.join();
-  s->tq.join();
+  for (auto& t : s->tq) t.join();
   hipStreamSynchronize(s->su);
-  hipStreamSynchronize(s->sq);
   hipStreamDestroy(s->su);
-  hipStreamDestroy(s->sq);
+  for (hipStream_t x : s->sq) {
+    hipStreamSynchronize(x);
+    hipStreamDestroy(x);
+  }
   {
     std::lock_guard<std::mutex> lk(s->g->mu);
     s->g->concurrent_writers--;

@@ -44,7 +44,7 @@ class Query(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32)]
+    _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32), ("query_lanes", _u32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -305,8 +305,8 @@ class Graph:
 class Server:
     """Serving loop over a Graph (dg_server_*)."""
 
-    def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32):
-        cfg = ServerConfig(mem_budget, max_inflight, max_batch)
+    def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32, query_lanes=1):
+        cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes)
         h = _P()
         rc = lib.dg_server_start(graph.h, ctypes.byref(cfg), ctypes.byref(h))
         if rc != OK:

@@ -13,7 +13,7 @@ arcs examined by the queries per second, and whether the offered load was
 sustained.  Several rates (--rate 2000,100,25) run one after another on the
 same loaded graph, each with its own request stream and server.
 
-Usage: python -m paper_2109_09527_amd.serve_bench [--scale 22] [--rate 2000] [--duration 2]
+Usage: python -m paper_2109_09527_amd.serve_bench [--scale 22] [--rate 2000] [--duration 2] [--lanes 1]
 """
 from __future__ import annotations
 
@@ -32,6 +32,7 @@ def main():
     ap.add_argument("--duration", type=float, default=2.0)
     ap.add_argument("--mem-gb", type=float, default=24.0)
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--lanes", default="1", help="query lanes (engine launches in flight); a comma-separated list runs each")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
 
@@ -45,17 +46,19 @@ def main():
     g.apply(dg.ops_to_device(synth.load_ops(gr)))
     torch.cuda.synchronize()
     print(f"[serve] loaded V={gr.n} m={gr.m} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    for k, rate in enumerate(float(x) for x in str(args.rate).split(",")):
-        run_rate(args, g, gr, rate, args.seed + k)
+    for lanes in (int(x) for x in str(args.lanes).split(",")):
+        for k, rate in enumerate(float(x) for x in str(args.rate).split(",")):
+            run_rate(args, g, gr, rate, args.seed + k, lanes)
 
 
-def run_rate(args, g, gr, rate, seed):
+def run_rate(args, g, gr, rate, seed, lanes):
     import torch
     from paper_2109_09527_amd import dg, synth
     reqs = synth.serving_requests(gr, rate=rate, duration=args.duration, seed=seed)
-    print(f"[serve] rate {rate:g}/s: {len(reqs)} requests", file=sys.stderr, flush=True)
+    print(f"[serve] rate {rate:g}/s, {lanes} lanes: {len(reqs)} requests", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    srv = dg.Server(g, mem_budget=int(args.mem_gb * (1 << 30)), max_inflight=1024, max_batch=args.max_batch)
+    srv = dg.Server(g, mem_budget=int(args.mem_gb * (1 << 30)), max_inflight=1024, max_batch=args.max_batch,
+                    query_lanes=lanes)
     tickets = []
     start = time.perf_counter()
     for r in reqs:
@@ -90,6 +93,7 @@ def run_rate(args, g, gr, rate, seed):
     out = {
         "workload": f"R-MAT scale {args.scale} serving: Poisson {rate:g}/s for {args.duration:g}s, 30% updates "
                     "(log-uniform 1k-256k edge ops), 70% queries (BFS 40%, SSSP 40%, BC-16 20%)",
+        "query_lanes": lanes, "max_batch": args.max_batch,
         "requests": len(tickets), "offered_rps": rate, "achieved_rps": round(achieved, 1) if achieved else None,
         "sustained": bool(achieved and achieved >= 0.95 * rate),
         "wall_s": round(st["wall_s"], 3), "drain_s": round(t_all - t_submit, 3),

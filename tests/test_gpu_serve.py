@@ -27,7 +27,7 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3):
+def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2):
     gr = synth.rmat_graph(11, 8, 50, seed=seed)
     g = dg.Graph(gr.n, w_max=50, max_resident_epochs=128)
     g.apply(synth.load_ops(gr))
@@ -35,7 +35,7 @@ def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3):
     wl = synth.update_batches(graph=gr, n_batches=n_req, n_edge_ops=400, w_max=50, seed=seed)
     srcs = synth.out_degree_sources(gr, 16, synth.rng_for(seed, 4))
     rng = np.random.default_rng(seed)
-    srv = dg.Server(g, mem_budget=mem_budget, max_inflight=64, max_batch=max_batch)
+    srv = dg.Server(g, mem_budget=mem_budget, max_inflight=64, max_batch=max_batch, query_lanes=query_lanes)
     log = []   # (ticket, kind, payload)
     nu = 0
     for i in range(n_req):
@@ -117,9 +117,11 @@ def check_against_oracle(dg, gr, g, e_load, wl, out):
     assert sum(1 for ep in by_epoch if ep < e_load) == 0
 
 
-def test_serving_mix_matches_oracle_and_alone(dg):
-    say("serving mix")
-    gr, g, e_load, wl, out, stats = run_mix(dg, mem_budget=1 << 30, max_batch=8)
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_serving_mix_matches_oracle_and_alone(dg, lanes):
+    """With one lane, and with three lanes whose launches overlap."""
+    say("serving mix, lanes", lanes)
+    gr, g, e_load, wl, out, stats = run_mix(dg, mem_budget=1 << 30, max_batch=8, query_lanes=lanes)
     check_against_oracle(dg, gr, g, e_load, wl, out)
     assert stats["completed"] == len(out)
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
@@ -140,3 +142,6 @@ def test_serving_admission_under_tiny_budget(dg):
         srv.submit_query(dg.Q_BC, [0])
     assert ei.value.status == dg.E_BUSY
     srv.stop()
+    with pytest.raises(dg.DGError) as ei:
+        dg.Server(g2, query_lanes=5)
+    assert ei.value.status == dg.E_INVALID_ARG
