@@ -329,11 +329,14 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
                                                         UpdCounters* c) {
   if (c->flags) return;
   const uint32_t ncl = c->n_clear;
+  // workgroups (x, y) share vertex x's slots: y strides over them, so a
+  // hub's arcs are spread over gridDim.y workgroups
+  const uint32_t t0 = blockIdx.y * UPD_THREADS + threadIdx.x, tstep = gridDim.y * UPD_THREADS;
   for (uint32_t k = blockIdx.x; k < ncl; k += gridDim.x) {
     uint32_t x = clear_list[k];
     int dropped = 0;
     Slab fs = slab_of(st.fp, st.fdesc[x]);
-    for (uint32_t t = threadIdx.x; t < fs.nb * BSLOTS; t += UPD_THREADS) {
+    for (uint32_t t = t0; t < fs.nb * BSLOTS; t += tstep) {
       uint32_t* bp = bucket_ptr(fs, t / BSLOTS);
       uint32_t j = t % BSLOTS;
       uint32_t d = ld_relaxed(slot_dst(bp, j));
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_clear(Store st, const uint32_t*
     }
     if (!st.undirected) {
       Slab rs = slab_of(st.rp, st.rdesc[x]);
-      for (uint32_t t = threadIdx.x; t < rs.nb * BSLOTS; t += UPD_THREADS) {
+      for (uint32_t t = t0; t < rs.nb * BSLOTS; t += tstep) {
         uint32_t* bp = bucket_ptr(rs, t / BSLOTS);
         uint32_t j = t % BSLOTS;
         uint32_t sv = ld_relaxed(slot_dst(bp, j));
@@ -483,7 +486,7 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
   k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS / 64, 4096), UPD_THREADS, 0, s>>>(
       st, touch_f, touch_r, plan, plan_ins, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
   k_grow_exec<<<blocks_for(3ull * n, 1, 8192), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, plan, plan_ins, fl, c);
-  k_clear<<<blocks_for(n, 1, 8192), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
+  k_clear<<<dim3(blocks_for(n, 1, 1024), 8), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
   k_commit_edge<<<nb, UPD_THREADS, 0, s>>>(keys, n, L, st, u.recflags.as<uint8_t>(), u.recw.as<int32_t>(), E, c);
   k_commit_vertex<<<blocks_for(n, UPD_THREADS, 1024), UPD_THREADS, 0, s>>>(st, vchange, c);
   hipError_t e = hipGetLastError();
