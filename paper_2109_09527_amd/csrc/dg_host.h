@@ -47,7 +47,8 @@ struct UpdCounters {
   uint32_t nv;                  // vertex ops in the batch
   uint32_t n_touch_f, n_touch_r;
   uint32_t n_clear, n_vchange;
-  uint32_t pad0, pad1;
+  uint32_t n_grow;              // slabs that grow this batch
+  uint32_t pad1;
   unsigned long long arcs_delta;  // visible arcs added minus tombstoned (two's complement)
   unsigned long long demand_f, demand_r;
   unsigned long long cursor0_f, cursor0_r;
@@ -57,6 +58,7 @@ constexpr uint32_t VCHANGE_INLINE = 4096;   // vertex changes copied with the co
 struct UpdateScratch {
   DevBuf keys0, keys1, vals0, vals1, sortw, vafter, vlastrem, recflags, recw;
   DevBuf ops, results, touch, plan, clear;
+  DevBuf grow;                  // growing slabs: touch index, new offset, kept count
   DevBuf summary;               // UpdCounters followed by the vertex-change list
   void* host_summary = nullptr; // pinned mirror of the first part of summary
   uint64_t cap = 0;

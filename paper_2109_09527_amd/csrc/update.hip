@@ -17,9 +17,13 @@
 //                     successful RemoveVertex of an endpoint lies between two
 //                     state points; net effect per key = tombstone the
 //                     current version and/or insert a new one
-//   k_grow_plan/exec  slabs that would pass 75% load get a new slab at <=50%
+//   k_grow_*          slabs that would pass 75% load get a new slab at <=50%
 //                     load; versions dead at or below the oldest queryable
-//                     epoch are dropped while rehashing
+//                     epoch are dropped while rehashing.  plan lists the
+//                     growing slabs; alloc reserves their new slabs; init
+//                     and move spread each slab's words and slots over
+//                     several workgroups (hubs included); publish swaps
+//                     the descriptors
 //   k_clear           successful RemoveVertex of a vertex live at e:
 //                     tombstone every current arc at it and its mirror
 //   k_commit_edge     per key: tombstone (death = E') and/or insert
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
 // plan[k] = log2(new buckets) + 1, or 0 when the slab keeps its size.
 __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint32_t* touch_f,
                                                             const uint32_t* touch_r, uint32_t* plan,
-                                                            uint32_t* plan_ins, uint32_t* insf,
+                                                            uint32_t* plan_ins, uint32_t* glist, uint32_t* insf,
                                                             uint32_t* insr, uint32_t floor_e,
                                                             UpdCounters* c) {
   if (c->flags) return;
@@ -250,45 +254,77 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint3
         plan[k] = lg + 1;
         plan_ins[k] = ins;
         atomicAdd(fwd ? &c->demand_f : &c->demand_r, 1ull << lg);
+        glist[atomicAdd(&c->n_grow, 1u)] = k;
       }
     }
   }
 }
 
-__global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint32_t* touch_f,
-                                                            const uint32_t* touch_r, const uint32_t* plan,
-                                                            const uint32_t* plan_ins, uint32_t floor_e,
-                                                            UpdCounters* c) {
+// Growing slab i of the batch: its touch-list entry and pool.
+struct GrowRef {
+  uint32_t k, x, lg;
+  bool fwd;
+};
+__device__ inline GrowRef grow_ref(uint32_t i, const uint32_t* glist, const uint32_t* plan, const uint32_t* touch_f,
+                                   const uint32_t* touch_r, uint32_t nf) {
+  GrowRef r;
+  r.k = glist[i];
+  r.fwd = r.k < nf;
+  r.x = r.fwd ? touch_f[r.k] : touch_r[r.k - nf];
+  r.lg = plan[r.k] - 1;
+  return r;
+}
+
+// Reserve each growing slab's new space (or flag the batch out of memory).
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_alloc(Store st, const uint32_t* glist, const uint32_t* plan,
+                                                             unsigned long long* goff, uint32_t* gkept,
+                                                             UpdCounters* c) {
   if (c->flags) return;
   if (c->cursor0_f + c->demand_f > st.fp.cap || (!st.undirected && c->cursor0_r + c->demand_r > st.rp.cap)) {
-    if (threadIdx.x == 0) atomicOr(&c->flags, (uint32_t)F_OOM);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&c->flags, (uint32_t)F_OOM);
     return;
   }
-  const uint32_t nf = c->n_touch_f, nr = c->n_touch_r;
-  __shared__ unsigned long long s_off;
-  __shared__ uint32_t s_kept;
-  for (uint32_t k = blockIdx.x; k < nf + nr; k += gridDim.x) {
-    uint32_t pl = plan[k];
-    if (pl == 0) continue;
-    bool fwd = k < nf;
-    uint32_t x = fwd ? touch_f[k] : touch_r[k - nf];
-    const Pool& p = fwd ? st.fp : st.rp;
-    uint64_t* desca = fwd ? st.fdesc : st.rdesc;
-    uint32_t lg = pl - 1, nb2 = 1u << lg;
-    if (threadIdx.x == 0) {
-      s_off = atomicAdd(&st.cursor[fwd ? 0 : 1], (unsigned long long)nb2);
-      s_kept = 0;
-    }
-    __syncthreads();
-    uint64_t off = s_off;
-    Slab ns = slab_at(p, off, nb2);
-    for (uint64_t t = threadIdx.x; t < (uint64_t)nb2 * p.words; t += UPD_THREADS) ns.base[t] = 0xFFFFFFFFu;
-    clear_summaries(ns.sum, nb2, threadIdx.x, UPD_THREADS);
-    __threadfence();
-    __syncthreads();
-    Slab os = slab_of(p, desca[x]);
+  const uint32_t ng = c->n_grow, nf = c->n_touch_f;
+  for (uint32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < ng; i += gridDim.x * UPD_THREADS) {
+    const uint32_t k = glist[i];
+    const bool fwd = k < nf;
+    goff[i] = atomicAdd(&st.cursor[fwd ? 0 : 1], 1ull << (plan[k] - 1));
+    gkept[i] = 0;
+  }
+}
+
+// Empty the new slabs: workgroups (x, y) share slab x's words.
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_init(Store st, const uint32_t* glist, const uint32_t* plan,
+                                                            const unsigned long long* goff, UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t ng = c->n_grow, nf = c->n_touch_f;
+  const uint32_t t0 = blockIdx.y * UPD_THREADS + threadIdx.x, tstep = gridDim.y * UPD_THREADS;
+  for (uint32_t i = blockIdx.x; i < ng; i += gridDim.x) {
+    const uint32_t k = glist[i];
+    const Pool& p = k < nf ? st.fp : st.rp;
+    const uint32_t nb2 = 1u << (plan[k] - 1);
+    Slab ns = slab_at(p, goff[i], nb2);
+    for (uint64_t t = t0; t < (uint64_t)nb2 * p.words; t += tstep) ns.base[t] = 0xFFFFFFFFu;
+    clear_summaries(ns.sum, nb2, t0, tstep);
+  }
+}
+
+// Rehash the versions that stay (death above the floor) into the new slabs:
+// workgroups (x, y) share slab x's old slots.
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_move(Store st, const uint32_t* touch_f, const uint32_t* touch_r,
+                                                            const uint32_t* glist, const uint32_t* plan,
+                                                            const unsigned long long* goff, uint32_t* gkept,
+                                                            uint32_t floor_e, UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t ng = c->n_grow, nf = c->n_touch_f;
+  const uint32_t t0 = blockIdx.y * UPD_THREADS + threadIdx.x, tstep = gridDim.y * UPD_THREADS;
+  for (uint32_t i = blockIdx.x; i < ng; i += gridDim.x) {
+    const GrowRef g = grow_ref(i, glist, plan, touch_f, touch_r, nf);
+    const Pool& p = g.fwd ? st.fp : st.rp;
+    Slab ns = slab_at(p, goff[i], 1u << g.lg);
+    Slab os = slab_of(p, (g.fwd ? st.fdesc : st.rdesc)[g.x]);
     uint32_t kept = 0;
-    for (uint32_t t = threadIdx.x; t < os.nb * BSLOTS; t += UPD_THREADS) {
+    for (uint32_t t = t0; t < os.nb * BSLOTS; t += tstep) {
       uint32_t* bp = bucket_ptr(os, t / BSLOTS);
       uint32_t j = t % BSLOTS;
       uint32_t d = *slot_dst(bp, j);
@@ -296,19 +332,28 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_exec(Store st, const uint3
       uint64_t stamp = *slot_stamp(bp, j, os.words);
       if ((uint32_t)(stamp >> 32) <= floor_e) continue;
       SlotRef r = claim_slot(ns, d, (uint32_t)stamp);
-      if (fwd) *slot_w(r.bp, r.j) = *slot_w(bp, j);
+      if (g.fwd) *slot_w(r.bp, r.j) = *slot_w(bp, j);
       *slot_stamp(r.bp, r.j, ns.words) = stamp;
       if ((uint32_t)(stamp >> 32) != INF_EPOCH) mark_tomb(ns, r.b, r.j, (uint32_t)(stamp >> 32));
       kept++;
     }
-    if (kept) atomicAdd(&s_kept, kept);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      desca[x] = make_desc(off, lg);
-      (fwd ? st.fused : st.rused)[x] = s_kept + plan_ins[k];
-    }
-    __syncthreads();
+    kept = wave_sum_u32(kept);
+    if (lane_id() == 0 && kept) atomicAdd(&gkept[i], kept);
+  }
+}
+
+// Point each grown vertex at its new slab.
+__global__ __launch_bounds__(UPD_THREADS) void k_grow_publish(Store st, const uint32_t* touch_f,
+                                                               const uint32_t* touch_r, const uint32_t* glist,
+                                                               const uint32_t* plan, const uint32_t* plan_ins,
+                                                               const unsigned long long* goff, const uint32_t* gkept,
+                                                               UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t ng = c->n_grow, nf = c->n_touch_f;
+  for (uint32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < ng; i += gridDim.x * UPD_THREADS) {
+    const GrowRef g = grow_ref(i, glist, plan, touch_f, touch_r, nf);
+    (g.fwd ? st.fdesc : st.rdesc)[g.x] = make_desc(goff[i], g.lg);
+    (g.fwd ? st.fused : st.rused)[g.x] = gkept[i] + plan_ins[g.k];
   }
 }
 
@@ -438,6 +483,7 @@ static hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
   ENS(sortw, sort_scratch_words((uint32_t)c) * 4)
   ENS(vafter, c) ENS(vlastrem, c * 4) ENS(recflags, c) ENS(recw, c * 4)
   ENS(ops, c * sizeof(dg_op)) ENS(results, c) ENS(touch, c * 12) ENS(plan, c * 24) ENS(clear, c * 4)
+  ENS(grow, c * 48)
   ENS(summary, sizeof(UpdCounters) + c * 4)
 #undef ENS
   if (!u.host_summary) {
@@ -468,6 +514,9 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
   uint32_t* touch_r = touch_f + 2ull * n;   // undirected inserts touch both ends
   uint32_t* plan = u.plan.as<uint32_t>();
   uint32_t* plan_ins = plan + 3ull * n;
+  unsigned long long* goff = u.grow.as<unsigned long long>();   // 3n entries each
+  uint32_t* glist = reinterpret_cast<uint32_t*>(goff + 3ull * n);
+  uint32_t* gkept = glist + 3ull * n;
   uint32_t nb = blocks_for(n, UPD_THREADS);
 
   k_upd_init<<<1, 64, 0, s>>>(c, st.cursor);
@@ -484,8 +533,13 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
                                             u.recw.as<int32_t>(), touch_f, touch_r, g->insf.as<uint32_t>(),
                                             g->insr.as<uint32_t>(), c);
   k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS / 64, 4096), UPD_THREADS, 0, s>>>(
-      st, touch_f, touch_r, plan, plan_ins, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
-  k_grow_exec<<<blocks_for(3ull * n, 1, 8192), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, plan, plan_ins, fl, c);
+      st, touch_f, touch_r, plan, plan_ins, glist, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
+  const uint32_t gx = blocks_for(3ull * n, 1, 512);
+  k_grow_alloc<<<blocks_for(3ull * n, UPD_THREADS, 64), UPD_THREADS, 0, s>>>(st, glist, plan, goff, gkept, c);
+  k_grow_init<<<dim3(gx, 8), UPD_THREADS, 0, s>>>(st, glist, plan, goff, c);
+  k_grow_move<<<dim3(gx, 8), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, glist, plan, goff, gkept, fl, c);
+  k_grow_publish<<<blocks_for(3ull * n, UPD_THREADS, 64), UPD_THREADS, 0, s>>>(st, touch_f, touch_r, glist, plan,
+                                                                             plan_ins, goff, gkept, c);
   k_clear<<<dim3(blocks_for(n, 1, 1024), 8), UPD_THREADS, 0, s>>>(st, u.clear.as<uint32_t>(), E, c);
   k_commit_edge<<<nb, UPD_THREADS, 0, s>>>(keys, n, L, st, u.recflags.as<uint8_t>(), u.recw.as<int32_t>(), E, c);
   k_commit_vertex<<<blocks_for(n, UPD_THREADS, 1024), UPD_THREADS, 0, s>>>(st, vchange, c);
