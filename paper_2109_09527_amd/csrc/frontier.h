@@ -710,6 +710,16 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
   }
   for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
     Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+    // the four targets' distances are read up front, so the loads overlap
+    // instead of each waiting behind the previous target's atomics;
+    // distances only fall, so an early read is an upper bound and the
+    // atomicMin below decides
+    int32_t cur[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
+      cur[k] = s4.vis[k] && take ? a.dist[s4.d[k]] : 0;
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
@@ -719,7 +729,7 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
       if (s4.vis[k] && take) {
         lc.arcs++;
         int32_t nd = du + s4.w[k];
-        if (nd < a.dist[d]) {
+        if (nd < cur[k]) {
           int32_t old = atomicMin(&a.dist[d], nd);
           if (nd < old) {
             if (nd < a.thr) {
