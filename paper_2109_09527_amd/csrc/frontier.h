@@ -218,18 +218,28 @@ __device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape
   }
   uint32_t incl = wave_incl_scan(sum);
   uint32_t total = __shfl(incl, 63, 64);
-  uint32_t gb = 0;
-  if (lane == 0 && total) gb = atomicAdd(gcnt, total);
-  uint32_t p = __shfl(gb, 0, 64) + incl - sum;
+  // each entry's first tile within the flush
+  uint32_t p = incl - sum;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     uint32_t e = lane * PER + k;
-    if (e < q.n) {
-      uint64_t d = q.d[e];
-      uint32_t v = q.v[e];
-      for (uint32_t t = 0; t < tl[k]; t++) gq[p + t] = Item{d, v, t};
-    }
+    if (e < q.n) q.s[e] = p;
     p += tl[k];
+  }
+  wave_lds_sync();
+  uint32_t gb = 0;
+  if (lane == 0 && total) gb = atomicAdd(gcnt, total);
+  gb = __shfl(gb, 0, 64);
+  // the wave writes the tiles together, consecutive lanes consecutive
+  // tiles: a hub's many tiles no longer fall to one lane
+  for (uint32_t i = lane; i < total; i += 64) {
+    uint32_t lo = 0, hi = q.n;   // last entry whose first tile is <= i
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (q.s[m] <= i) lo = m;
+      else hi = m;
+    }
+    gq[gb + i] = Item{q.d[lo], q.v[lo], i - q.s[lo]};
   }
   q.n = 0;
   wave_lds_sync();
