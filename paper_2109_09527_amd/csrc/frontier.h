@@ -330,11 +330,54 @@ __device__ inline void room_u32(U32Q& q, uint32_t next, uint32_t* gq, uint32_t* 
 
 // Register counters, summed per workgroup and added with one atomic per
 // counter (workgroup-uniform call: it takes a barrier).
+// Additive counts of one step, spread over N_STRIPES lines: a workgroup
+// adds to stripe blockIdx.x mod N_STRIPES instead of the step's counter
+// words, so the workgroups of a large grid do not queue on the same
+// addresses; the reader sums the stripes into the counters.
+constexpr uint32_t N_STRIPES = 16;
+struct alignas(128) CountStripe {
+  unsigned long long m, arcs;
+  uint32_t verts, far;
+  uint32_t pad[26];
+};
+
 struct LaneCounts {
   uint32_t verts = 0;
   unsigned long long m = 0;
   uint32_t arcs = 0;
   uint32_t far = 0;   // SSSP: vertices flagged far
+  // to the counters c, or to a stripe when st is set
+  __device__ void commit(QCounters* c, Shared& sh, CountStripe* st) {
+    if (!st) {
+      commit(c, sh);
+      return;
+    }
+    uint32_t v = wave_sum_u32(verts);
+    unsigned long long mm = wave_sum_u64(m);
+    unsigned long long a = wave_sum_u64(arcs);
+    uint32_t f = wave_sum_u32(far);
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+      sh.part[wave][0] = v;
+      sh.part[wave][1] = mm;
+      sh.part[wave][2] = a;
+      sh.part[wave][3] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      CountStripe* x = st + blockIdx.x % N_STRIPES;
+      unsigned long long t = 0;
+#pragma unroll
+      for (int w = 0; w < Q_WAVES; w++) t += sh.part[w][threadIdx.x];
+      if (t) {
+        if (threadIdx.x == 0) atomicAdd(&x->verts, (uint32_t)t);
+        else if (threadIdx.x == 1) atomicAdd(&x->m, t);
+        else if (threadIdx.x == 2) atomicAdd(&x->arcs, t);
+        else atomicAdd(&x->far, (uint32_t)t);
+      }
+    }
+    __syncthreads();
+  }
   __device__ void commit(QCounters* c, Shared& sh) {
     uint32_t v = wave_sum_u32(verts);
     unsigned long long mm = wave_sum_u64(m);
@@ -492,6 +535,7 @@ struct LevelArgs {
   int32_t* dist;
   int32_t next_level;
   QCounters* cnt_out;
+  CountStripe* stripes;   // additive counts of cnt_out spread (null: into cnt_out)
 };
 
 // Top-down over the chunks of the current frontier (nfq: its fq counter).
@@ -527,7 +571,7 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, unsigned long long n
     }
   }
   flush_front(qn, a.fout, a.cnt_out);
-  lc.commit(a.cnt_out, sh);
+  lc.commit(a.cnt_out, sh, a.stripes);
 }
 
 // Bottom-up, one unvisited vertex per lane: a one-bucket in-slab (the
@@ -593,7 +637,7 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
   }
   flush_front(qn, a.fout, a.cnt_out);
   flush_tiles(qb, a.qbig, &a.cnt_out->n_big, tbig);
-  lc.commit(a.cnt_out, sh);
+  lc.commit(a.cnt_out, sh, a.stripes);
 }
 
 // View of one chunk item for a 16-lane group.
@@ -670,7 +714,7 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
     push_item(qn, win, y, yd);
   }
   flush_front(qn, a.fout, a.cnt_out);
-  lc.commit(a.cnt_out, sh);
+  lc.commit(a.cnt_out, sh, a.stripes);
 }
 
 // ----------------------------------------------------------------- SSSP
@@ -702,6 +746,7 @@ struct RelaxArgs {
   uint32_t* rcount;
   uint32_t* rstamp;
   uint32_t phase;
+  CountStripe* stripes;   // additive counts of cnt_out spread (null: into cnt_out)
 };
 
 // One chunk of the near frontier (all lanes of the wave).
@@ -769,7 +814,7 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, unsigned long lon
   LaneCounts lc;
   for (uint32_t c = gw; c < nc; c += nw) relax_chunk(a, c, nitems, nb, qn, lc);
   flush_front(qn, a.fout, a.cnt_out);
-  lc.commit(a.cnt_out, sh);
+  lc.commit(a.cnt_out, sh, a.stripes);
 }
 
 // Items of every vertex in list[0..n): the recorded vertices of a settled
@@ -802,6 +847,7 @@ struct SplitArgs {
   int32_t thr;
   uint32_t it1;
   QCounters* cnt_out;   // near items; n_far = far vertices left; far_min
+  CountStripe* stripes;   // additive counts of cnt_out spread (null: into cnt_out)
 };
 
 // Vertices [base, base + 64): flagged ones below the threshold move into the
@@ -841,7 +887,7 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, 
   for (uint32_t base = gw * 64; base < a.st.V; base += nw * 64) split_block(a, base, qn, lc, mn);
   flush_front(qn, a.fout, a.cnt_out);
   commit_far_min(mn, a.cnt_out);
-  lc.commit(a.cnt_out, sh);
+  lc.commit(a.cnt_out, sh, a.stripes);
 }
 
 // ------------------------------------------------------------------- BC

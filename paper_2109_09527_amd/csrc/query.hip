@@ -76,15 +76,28 @@ __device__ inline void reset_other(QCounters* c) {
   if (blockIdx.x == 0 && threadIdx.x == 0) zero_counters(c);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, unsigned long long nfq, QCounters* reset) {
+// Clears slot c and, when st is set, its count stripes.
+__device__ inline void reset_other(QCounters* c, CountStripe* st) {
+  reset_other(c);
+  if (st && blockIdx.x == 0 && threadIdx.x < N_STRIPES) {
+    CountStripe* x = st + threadIdx.x;
+    x->m = 0;
+    x->arcs = 0;
+    x->verts = 0;
+    x->far = 0;
+  }
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, unsigned long long nfq, QCounters* reset,
+                                                       CountStripe* reset_st) {
   __shared__ Shared sh;
-  reset_other(reset);
+  reset_other(reset, reset_st);
   td_step(a, nfq, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset, CountStripe* reset_st) {
   __shared__ Shared sh;
-  reset_other(reset);
+  reset_other(reset, reset_st);
   bu_step(a, blockIdx.x, gridDim.x, sh);
 }
 
@@ -93,22 +106,24 @@ __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a) {
   bu_big_step(a, a.cnt_out->n_big, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, unsigned long long nfq, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, unsigned long long nfq, QCounters* reset,
+                                                           CountStripe* reset_st) {
   __shared__ Shared sh;
-  reset_other(reset);
+  reset_other(reset, reset_st);
   relax_step(a, nfq, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint32_t* list, uint32_t n, Front fout,
-                                                            QCounters* cnt_out, QCounters* reset) {
+                                                            QCounters* cnt_out, QCounters* reset,
+                                                            CountStripe* reset_st) {
   __shared__ Shared sh;
-  reset_other(reset);
+  reset_other(reset, reset_st);
   expand_step(st, list, n, fout, cnt_out, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, QCounters* reset) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, QCounters* reset, CountStripe* reset_st) {
   __shared__ Shared sh;
-  reset_other(reset);
+  reset_other(reset, reset_st);
   split_step(a, blockIdx.x, gridDim.x, sh);
 }
 
@@ -142,6 +157,12 @@ static Front front_of(const QueryScratch& q, int which) {
                (uint32_t)std::min<uint64_t>(q.chunks_cap, 0xFFFFFFFFu), q.lch};
 }
 
+// Layout of q.counters: four counter slots, then (from STRIPE_OFF) the
+// N_STRIPES count stripes of each slot.
+constexpr size_t STRIPE_OFF = 256;
+constexpr size_t COUNTERS_BYTES = STRIPE_OFF + 4 * N_STRIPES * sizeof(CountStripe);
+static_assert(4 * sizeof(QCounters) <= STRIPE_OFF, "counter slots overlap their stripes");
+
 static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
   hipError_t e;
   const uint64_t V = g->cfg.v_capacity;
@@ -157,9 +178,9 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
   uint64_t bmw = (V + 31) / 32 + 1;
   if ((e = ensure(q.bm0, bmw * 4)) != hipSuccess) return e;
   if ((e = ensure(q.bm1, bmw * 4)) != hipSuccess) return e;
-  if ((e = ensure(q.counters, 4 * sizeof(QCounters))) != hipSuccess) return e;
+  if ((e = ensure(q.counters, COUNTERS_BYTES)) != hipSuccess) return e;
   if (!q.host_counters) {
-    if ((e = hipHostMalloc(&q.host_counters, 4 * sizeof(QCounters), hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipHostMalloc(&q.host_counters, COUNTERS_BYTES, hipHostMallocDefault)) != hipSuccess) return e;
   }
   if (!sssp && !bc) {
     // bottom-up chunk items of long in-slabs
@@ -190,24 +211,33 @@ void free_query_scratch(QueryScratch& q) {
   q.host_counters = nullptr;
 }
 
-static hipError_t read_counters(QueryScratch& q, int slot, QCounters* out, hipStream_t s) {
-  QCounters* dc = q.counters.as<QCounters>() + slot;
-  hipError_t e = hipMemcpyAsync(q.host_counters, dc, sizeof(QCounters), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  std::memcpy(out, q.host_counters, sizeof(QCounters));
-  return hipSuccess;
+static CountStripe* stripes_of(QueryScratch& q, int slot) {
+  return reinterpret_cast<CountStripe*>(q.counters.as<char>() + STRIPE_OFF) + (size_t)slot * N_STRIPES;
 }
 
-// Counters of one slot plus the running bucket record count (slot 3), in one copy.
+// Counters of one slot with its stripes added in, plus the running bucket
+// record count (slot 3); one copy of the whole block.
 static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(q.host_counters, q.counters.p, 4 * sizeof(QCounters), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(q.host_counters, q.counters.p, COUNTERS_BYTES, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   const QCounters* h = static_cast<const QCounters*>(q.host_counters);
   std::memcpy(out, h + slot, sizeof(QCounters));
+  const CountStripe* x =
+      reinterpret_cast<const CountStripe*>(static_cast<const char*>(q.host_counters) + STRIPE_OFF) + slot * N_STRIPES;
+  for (uint32_t i = 0; i < N_STRIPES; i++) {
+    out->m_next += x[i].m;
+    out->arcs += x[i].arcs;
+    out->n_verts += x[i].verts;
+    out->n_far += x[i].far;
+  }
   *rc = h[3].n_order;
   return hipSuccess;
+}
+
+static hipError_t read_counters(QueryScratch& q, int slot, QCounters* out, hipStream_t s) {
+  uint32_t rc;
+  return read_counters_rc(q, slot, out, &rc, s);
 }
 
 static uint32_t grid_for(uint64_t units, uint32_t per_block, uint32_t cap = 16384) {
@@ -268,6 +298,7 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
   uint32_t* bm[2] = {q.bm0.as<uint32_t>(), q.bm1.as<uint32_t>()};
   QCounters* cnt = q.counters.as<QCounters>();
   fill<int32_t>(dist, V, -1, s);
+  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
   fill<uint32_t>(bm[0], bmw, 0u, s);
   k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], bm[0], cnt, nullptr);
   QCounters hc;
@@ -285,7 +316,8 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
     else if (bu && (uint64_t)n_verts * g->tune.beta < n_live) bu = false;
     m_u -= (int64_t)m_f;
     fill<uint32_t>(bm[nxt], bmw, 0u, s);
-    LevelArgs a{g->st, e, fast, fr[cur], fr[nxt], qbig, bm[cur], bm[nxt], dist, level + 1, cnt + nxt};
+    LevelArgs a{g->st, e, fast, fr[cur], fr[nxt], qbig, bm[cur], bm[nxt], dist, level + 1, cnt + nxt,
+                stripes_of(q, nxt)};
     if (bu) {
       ProfScope ps(g, KID_BFS_BU, s);
       // a quarter of the resident workgroups: each workgroup's counter
@@ -293,11 +325,12 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
       // words, and fewer workgroups over more vertices each won at R-MAT 20
       // (level time 142 -> 98 us; one eighth 93 us)
       k_bfs_bu<<<grid_for(V, Q_THREADS, std::max<uint32_t>(1, resident((const void*)k_bfs_bu) / 4)), Q_THREADS, 0, s>>>(
-          a, cnt + cur);
+          a, cnt + cur, stripes_of(q, cur));
       k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a);
     } else {
       ProfScope ps(g, KID_BFS_TD, s);
-      k_bfs_td<<<chunks_grid((const void*)k_bfs_td, fq, q.lch), Q_THREADS, 0, s>>>(a, fq, cnt + cur);
+      k_bfs_td<<<chunks_grid((const void*)k_bfs_td, fq, q.lch), Q_THREADS, 0, s>>>(a, fq, cnt + cur,
+                                                                                    stripes_of(q, cur));
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bfs level launch");
     if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
@@ -330,6 +363,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   QCounters* cnt = q.counters.as<QCounters>();
   uint32_t* rcount = &cnt[3].n_order;
   fill<int32_t>(dist, V, DIST_INF, s);
+  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
   fill<uint32_t>(stamp, V, 0u, s);
   fill<uint32_t>(infar, V, 0u, s);
   if (split_lh) {
@@ -351,10 +385,11 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
     int nxt = slot ^ 1;
     // far entries found by this pass are appended after the current far list
     RelaxArgs a{g->st, e,     fast,  fr[qi], fr[qi ^ 1], dist,  stamp,  infar, thr,
-                it,    cnt + nxt, mode, delta,  rlist,      rcount, rstamp, phase};
+                it,    cnt + nxt, mode, delta,  rlist,      rcount, rstamp, phase, stripes_of(q, nxt)};
     {
       ProfScope ps(g, KID_SSSP_RELAX, s);
-      k_sssp_relax<<<chunks_grid((const void*)k_sssp_relax, nfq, q.lch), Q_THREADS, 0, s>>>(a, nfq, cnt + slot);
+      k_sssp_relax<<<chunks_grid((const void*)k_sssp_relax, nfq, q.lch), Q_THREADS, 0, s>>>(a, nfq, cnt + slot,
+                                                                                            stripes_of(q, slot));
     }
     hipError_t r = hipGetLastError();
     if (r != hipSuccess) return r;
@@ -381,8 +416,8 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
         fill<uint32_t>(rcount, 1, 0u, s);
         n_rec = 0;
         int nxt = slot ^ 1;
-        k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(g->st, rlist, n_r, fr[qi],
-                                                                                        cnt + nxt, cnt + slot);
+        k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(
+            g->st, rlist, n_r, fr[qi], cnt + nxt, cnt + slot, stripes_of(q, slot));
         if ((he = hipGetLastError()) != hipSuccess || (he = read_counters(q, nxt, &hc, s)) != hipSuccess)
           return hip_fail(g, he, "sssp expand");
         if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
@@ -402,10 +437,11 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
       thr = far_min == DIST_INF ? thr + delta
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       int nxt = slot ^ 1;
-      SplitArgs a{g->st, fr[qi], dist, stamp, infar, thr, it, cnt + nxt};
+      SplitArgs a{g->st, fr[qi], dist, stamp, infar, thr, it, cnt + nxt, stripes_of(q, nxt)};
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);
-        k_sssp_split<<<lanes_grid((const void*)k_sssp_split, V), Q_THREADS, 0, s>>>(a, cnt + slot);
+        k_sssp_split<<<lanes_grid((const void*)k_sssp_split, V), Q_THREADS, 0, s>>>(a, cnt + slot,
+                                                                                    stripes_of(q, slot));
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
       if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
@@ -440,6 +476,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
   // and the overflow flag of the current source
   QCounters* tot = cnt + 2;
   fill<double>(bc, V, 0.0, s);
+  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
   std::vector<uint32_t> off;
   for (uint32_t si = 0; si < k; si++) {
     uint32_t src = srcs[si];
