@@ -260,12 +260,11 @@ __device__ inline void flush_u32_q(U32Q& q, uint32_t* gq, uint32_t* gcnt) {
 // Frontier queue: append the staged vertices that have buckets as items,
 // reserving items and flat buckets with one atomic, and point every chunk
 // that starts inside the reserved flat range at its item.
-__device__ inline void flush_front(ItemQ& q, const Front& f, QCounters* cnt) {
+// Staged items' reservation unit: items (low half) | buckets (high half),
+// as a wave-inclusive scan (lane 63 holds the wave total).
+__device__ inline unsigned long long front_stage_scan(const ItemQ& q, uint32_t* nb, unsigned long long* x_out) {
   constexpr int PER = WSTAGE / 64;
-  if (q.n == 0) return;   // wave-uniform
-  wave_lds_sync();
   const uint32_t lane = lane_id();
-  uint32_t nb[PER];
   uint32_t ni = 0, nbs = 0;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -276,11 +275,17 @@ __device__ inline void flush_front(ItemQ& q, const Front& f, QCounters* cnt) {
     nbs += nb[k];
   }
   const unsigned long long x = (unsigned long long)ni | ((unsigned long long)nbs << 32);
-  const unsigned long long incl = wave_incl_scan64(x);
-  const unsigned long long total = __shfl(incl, 63, 64);
-  unsigned long long base = 0;
-  if (lane == 0 && total) base = atomicAdd(&cnt->fq, total);
-  base = __shfl(base, 0, 64);
+  *x_out = x;
+  return wave_incl_scan64(x);
+}
+
+// Write the wave's staged items at base (items | buckets, already
+// reserved) and point every chunk that starts in their buckets at its item.
+__device__ inline void front_stage_write(ItemQ& q, const Front& f, QCounters* cnt, unsigned long long base,
+                                         unsigned long long total, unsigned long long incl, unsigned long long x,
+                                         const uint32_t* nb) {
+  constexpr int PER = WSTAGE / 64;
+  const uint32_t lane = lane_id();
   const unsigned long long ex = incl - x;
   const uint32_t ib = fq_items(base), bb = fq_buckets(base);
   uint32_t io = fq_items(ex), bo = fq_buckets(ex);
@@ -317,6 +322,51 @@ __device__ inline void flush_front(ItemQ& q, const Front& f, QCounters* cnt) {
   wave_lds_sync();
 }
 
+__device__ inline void flush_front(ItemQ& q, const Front& f, QCounters* cnt) {
+  constexpr int PER = WSTAGE / 64;
+  if (q.n == 0) return;   // wave-uniform
+  wave_lds_sync();
+  uint32_t nb[PER];
+  unsigned long long x;
+  const unsigned long long incl = front_stage_scan(q, nb, &x);
+  const unsigned long long total = __shfl(incl, 63, 64);
+  unsigned long long base = 0;
+  if (lane_id() == 0 && total) base = atomicAdd(&cnt->fq, total);
+  base = __shfl(base, 0, 64);
+  front_stage_write(q, f, cnt, base, total, incl, x, nb);
+}
+
+// The final flush of a step, for all waves of the workgroup at once
+// (workgroup-uniform call, two barriers): one reservation per workgroup
+// instead of one per wave, since every reservation is an atomic on the
+// same counter word.
+__device__ inline void flush_front_wg(ItemQ& q, const Front& f, QCounters* cnt, Shared& sh) {
+  constexpr int PER = WSTAGE / 64;
+  const uint32_t wave = threadIdx.x >> 6;
+  wave_lds_sync();
+  uint32_t nb[PER];
+  unsigned long long x;
+  const unsigned long long incl = front_stage_scan(q, nb, &x);
+  const unsigned long long total = __shfl(incl, 63, 64);
+  if (lane_id() == 0) sh.part[wave][0] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < Q_WAVES; w++) t += sh.part[w][0];
+    sh.part[0][1] = t ? atomicAdd(&cnt->fq, t) : 0ull;
+  }
+  __syncthreads();
+  // waves' items and buckets follow one another in wave order
+  unsigned long long base = sh.part[0][1];
+#pragma unroll
+  for (int w = 0; w < Q_WAVES; w++)
+    if ((uint32_t)w < wave) base += sh.part[w][0];
+  __syncthreads();
+  if (total) front_stage_write(q, f, cnt, base, total, incl, x, nb);
+  else q.n = 0;
+}
+
 // Keep room for `next` more pushes.
 __device__ inline void room_front(ItemQ& q, uint32_t next, const Front& f, QCounters* cnt) {
   if (q.n + next > q.cap) flush_front(q, f, cnt);
@@ -328,8 +378,6 @@ __device__ inline void room_u32(U32Q& q, uint32_t next, uint32_t* gq, uint32_t* 
   if (q.n + next > q.cap) flush_u32_q(q, gq, gcnt);
 }
 
-// Register counters, summed per workgroup and added with one atomic per
-// counter (workgroup-uniform call: it takes a barrier).
 // Additive counts of one step, spread over N_STRIPES lines: a workgroup
 // adds to stripe blockIdx.x mod N_STRIPES instead of the step's counter
 // words, so the workgroups of a large grid do not queue on the same
@@ -341,6 +389,8 @@ struct alignas(128) CountStripe {
   uint32_t pad[26];
 };
 
+// Register counters, summed per workgroup and added with one atomic per
+// counter (workgroup-uniform call: it takes a barrier).
 struct LaneCounts {
   uint32_t verts = 0;
   unsigned long long m = 0;
@@ -570,7 +620,7 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, unsigned long long n
       }
     }
   }
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
 
@@ -635,7 +685,7 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
     room_tiles(qb, 64, a.qbig, &a.cnt_out->n_big, tbig);
     push_item(qb, act && s.nb > 1, y, ydesc_in);
   }
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   flush_tiles(qb, a.qbig, &a.cnt_out->n_big, tbig);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
@@ -713,7 +763,7 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
     room_front(qn, 4, a.fout, a.cnt_out);
     push_item(qn, win, y, yd);
   }
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
 
@@ -813,7 +863,7 @@ __device__ __forceinline__ void relax_step(const RelaxArgs& a, unsigned long lon
   ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
   LaneCounts lc;
   for (uint32_t c = gw; c < nc; c += nw) relax_chunk(a, c, nitems, nb, qn, lc);
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
 
@@ -885,7 +935,7 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, 
   LaneCounts lc;
   int32_t mn = DIST_INF;
   for (uint32_t base = gw * 64; base < a.st.V; base += nw * 64) split_block(a, base, qn, lc, mn);
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   commit_far_min(mn, a.cnt_out);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
@@ -949,7 +999,7 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, unsigned long lon
       }
     }
   }
-  flush_front(qn, a.fout, a.cnt_out);
+  flush_front_wg(qn, a.fout, a.cnt_out, sh);
   flush_u32_q(qo, a.order, &a.cnt_total->n_order);
   if (ovf) atomicOr(&a.cnt_total->overflow, OVF_SIGMA);
   lc.commit(a.cnt_out, sh);
