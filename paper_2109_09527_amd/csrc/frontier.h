@@ -203,10 +203,9 @@ __device__ inline void push_u32(U32Q& q, bool push, uint32_t v) {
 
 // Tile queue (bottom-up chunk items): write the staged vertices' tiles
 // (one atomic).
-__device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts) {
+// Staged entries' tile counts and first tiles (in q.s), and the wave total.
+__device__ inline uint32_t tiles_stage_scan(ItemQ& q, TileShape ts) {
   constexpr int PER = WSTAGE / 64;
-  if (q.n == 0) return;   // wave-uniform
-  wave_lds_sync();
   const uint32_t lane = lane_id();
   uint32_t tl[PER];
   uint32_t sum = 0;
@@ -217,8 +216,6 @@ __device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape
     sum += tl[k];
   }
   uint32_t incl = wave_incl_scan(sum);
-  uint32_t total = __shfl(incl, 63, 64);
-  // each entry's first tile within the flush
   uint32_t p = incl - sum;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -227,12 +224,13 @@ __device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape
     p += tl[k];
   }
   wave_lds_sync();
-  uint32_t gb = 0;
-  if (lane == 0 && total) gb = atomicAdd(gcnt, total);
-  gb = __shfl(gb, 0, 64);
-  // the wave writes the tiles together, consecutive lanes consecutive
-  // tiles: a hub's many tiles no longer fall to one lane
-  for (uint32_t i = lane; i < total; i += 64) {
+  return __shfl(incl, 63, 64);
+}
+
+// The wave writes its tiles at gb together, consecutive lanes consecutive
+// tiles, so a hub's many tiles do not fall to one lane.
+__device__ inline void tiles_stage_write(ItemQ& q, Item* gq, uint32_t gb, uint32_t total) {
+  for (uint32_t i = lane_id(); i < total; i += 64) {
     uint32_t lo = 0, hi = q.n;   // last entry whose first tile is <= i
     while (hi - lo > 1) {
       const uint32_t m = (lo + hi) >> 1;
@@ -243,6 +241,39 @@ __device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape
   }
   q.n = 0;
   wave_lds_sync();
+}
+
+__device__ inline void flush_tiles(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts) {
+  if (q.n == 0) return;   // wave-uniform
+  wave_lds_sync();
+  const uint32_t total = tiles_stage_scan(q, ts);
+  uint32_t gb = 0;
+  if (lane_id() == 0 && total) gb = atomicAdd(gcnt, total);
+  gb = __shfl(gb, 0, 64);
+  tiles_stage_write(q, gq, gb, total);
+}
+
+// Final tile flush for all waves of the workgroup (workgroup-uniform, two
+// barriers): one reservation per workgroup.
+__device__ inline void flush_tiles_wg(ItemQ& q, Item* gq, uint32_t* gcnt, TileShape ts, Shared& sh) {
+  const uint32_t wave = threadIdx.x >> 6;
+  wave_lds_sync();
+  const uint32_t total = tiles_stage_scan(q, ts);
+  if (lane_id() == 0) sh.part[wave][0] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < Q_WAVES; w++) t += sh.part[w][0];
+    sh.part[0][1] = t ? atomicAdd(gcnt, (uint32_t)t) : 0u;
+  }
+  __syncthreads();
+  uint32_t gb = (uint32_t)sh.part[0][1];
+#pragma unroll
+  for (int w = 0; w < Q_WAVES; w++)
+    if ((uint32_t)w < wave) gb += (uint32_t)sh.part[w][0];
+  __syncthreads();
+  tiles_stage_write(q, gq, gb, total);
 }
 
 __device__ inline void flush_u32_q(U32Q& q, uint32_t* gq, uint32_t* gcnt) {
@@ -686,7 +717,7 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
     push_item(qb, act && s.nb > 1, y, ydesc_in);
   }
   flush_front_wg(qn, a.fout, a.cnt_out, sh);
-  flush_tiles(qb, a.qbig, &a.cnt_out->n_big, tbig);
+  flush_tiles_wg(qb, a.qbig, &a.cnt_out->n_big, tbig, sh);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
 

@@ -138,6 +138,18 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_vertex(const uint64_t* 
   if (state != init) vchange[atomicAdd(&c->n_vchange, 1u)] = x | ((uint32_t)state << 31);
 }
 
+// Append x to list for every lane with `want`, with one atomicAdd per wave
+// on the list's count.  Any subset of the wave's lanes may be active.
+__device__ inline void wave_append(uint32_t* list, uint32_t* count, bool want, uint32_t x) {
+  const unsigned long long m = __ballot(want);
+  if (!m) return;
+  const int lead = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if ((int)lane_id() == lead) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = __shfl(base, lead, 64);
+  if (want) list[base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull))] = x;
+}
+
 __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
     const uint64_t* keys, const uint32_t* vals, const dg_op* ops, uint32_t n, uint32_t L, Store st,
     uint8_t* results, const uint8_t* vafter, const uint32_t* vlastrem, uint8_t* recflags, int32_t* recw,
@@ -201,13 +213,16 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   bool ins = present && (!present0 || cleared || w != w0);
   recflags[k] = (uint8_t)((tomb ? 1 : 0) | (ins ? 2 : 0));
   recw[k] = w;
-  if (ins) {
-    if (atomicAdd(&insf[a], 1u) == 0) touch_f[atomicAdd(&c->n_touch_f, 1u)] = a;
-    if (!st.undirected) {
-      if (atomicAdd(&insr[b], 1u) == 0) touch_r[atomicAdd(&c->n_touch_r, 1u)] = b;
-    } else if (a != b) {
-      if (atomicAdd(&insf[b], 1u) == 0) touch_f[atomicAdd(&c->n_touch_f, 1u)] = b;
-    }
+  // count the insert at each endpoint; the first insert at a vertex lists
+  // it as touched (one list reservation per wave, not per lane)
+  const bool fa = ins && atomicAdd(&insf[a], 1u) == 0;
+  wave_append(touch_f, &c->n_touch_f, fa, a);
+  if (!st.undirected) {
+    const bool fb = ins && atomicAdd(&insr[b], 1u) == 0;
+    wave_append(touch_r, &c->n_touch_r, fb, b);
+  } else {
+    const bool fb = ins && a != b && atomicAdd(&insf[b], 1u) == 0;
+    wave_append(touch_f, &c->n_touch_f, fb, b);
   }
 }
 
