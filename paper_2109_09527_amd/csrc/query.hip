@@ -320,11 +320,11 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
                 stripes_of(q, nxt)};
     if (bu) {
       ProfScope ps(g, KID_BFS_BU, s);
-      // a quarter of the resident workgroups: each workgroup's counter
-      // commit and each wave's queue flushes are atomics on a few shared
-      // words, and fewer workgroups over more vertices each won at R-MAT 20
-      // (level time 142 -> 98 us; one eighth 93 us)
-      k_bfs_bu<<<grid_for(V, Q_THREADS, std::max<uint32_t>(1, resident((const void*)k_bfs_bu) / 4)), Q_THREADS, 0, s>>>(
+      // half the resident workgroups: each workgroup's final counter commit
+      // and queue reservations are atomics on shared words, and fewer
+      // workgroups over more vertices each won at R-MAT 20 (level time with
+      // half: 53 us; a quarter: 59; an eighth: 72)
+      k_bfs_bu<<<grid_for(V, Q_THREADS, std::max<uint32_t>(1, resident((const void*)k_bfs_bu) / 2)), Q_THREADS, 0, s>>>(
           a, cnt + cur, stripes_of(q, cur));
       k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a);
     } else {
