@@ -552,6 +552,7 @@ __global__ __launch_bounds__(Q_THREADS, 4) void k_team(BatchArgs a) {
 // thus fill the GPU together, and each query's per-pass cost is one barrier
 // shared by the gang instead of one host round trip of its own.
 
+constexpr uint32_t GANG_BLOCK = 64;   // units per round-robin block of a pass
 constexpr uint32_t GANG_MAX = 128;   // queries per gang launch (LDS and registers sized for 5 waves per SIMD)
 
 enum GKind : uint32_t { G_RELAX = 0, G_EXPAND = 1, G_HEAVY = 2, G_SPLIT = 3, G_DONE = 4 };
@@ -723,8 +724,10 @@ __device__ inline GState uni_state(const GState& x) {
 }
 static_assert(sizeof(GState) == 8 + 10 * 4, "GState layout changed: update uni_state");
 
-__device__ __forceinline__ void gang_work(const GangArgs& a, uint32_t qn, const GState& s, uint32_t j0, uint32_t j1,
-                                          Shared& sh) {
+// Returns the visible arcs the wave examined (counted into the launch
+// total once per wave, at the end of the launch).
+__device__ __forceinline__ unsigned long long gang_work(const GangArgs& a, uint32_t qn, const GState& s, uint32_t j0,
+                                                        uint32_t j1, Shared& sh) {
   const GQuery q = uni_gquery(a.q[qn]);
   const uint32_t wave = threadIdx.x >> 6;
   const bool split_lh = a.delta < a.w_max;
@@ -752,8 +755,7 @@ __device__ __forceinline__ void gang_work(const GangArgs& a, uint32_t qn, const 
     flush_front(qn_, sa.fout, cout);
     commit_far_min(mn, cout);
   }
-  const unsigned long long arcs = lc.commit_wave(cout);
-  if (lane_id() == 0 && arcs) atomicAdd(&a.ctrl->arcs, arcs);
+  return lc.commit_wave(cout);
 }
 
 __global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
@@ -777,6 +779,7 @@ __global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
     gs[i] = s;
   }
   const uint32_t wave = threadIdx.x >> 6, nw = S * Q_WAVES, gw = w * Q_WAVES + wave;
+  unsigned long long wave_arcs = 0;
   for (;;) {
     // plan the pass: units per query and their prefix (nq <= Q_THREADS)
     __syncthreads();
@@ -795,24 +798,29 @@ __global__ __launch_bounds__(Q_THREADS, 5) void k_gang_sssp(GangArgs a) {
     __syncthreads();
     total = uni(total);
     if (total == 0) break;
-    // this wave's contiguous share of the units
-    const uint32_t lo = (uint32_t)((uint64_t)total * gw / nw), hi = (uint32_t)((uint64_t)total * (gw + 1) / nw);
-    uint32_t u = lo;
-    while (u < hi) {
-      uint32_t l = 0, h = nq;   // pre[l] <= u < pre[h]
-      while (h - l > 1) {
-        const uint32_t m = (l + h) >> 1;
-        if (pre[m] <= u) l = m;
-        else h = m;
+    // blocks of GANG_BLOCK units dealt round-robin to the waves: each wave
+    // gets work of many queries, so queries in a costly phase (many
+    // improvements and pushes) do not pile onto a few waves
+    for (uint32_t b = gw; (uint64_t)b * GANG_BLOCK < total; b += nw) {
+      uint32_t u = b * GANG_BLOCK;
+      const uint32_t hi = min(total, u + GANG_BLOCK);
+      while (u < hi) {
+        uint32_t l = 0, h = nq;   // pre[l] <= u < pre[h]
+        while (h - l > 1) {
+          const uint32_t m = (l + h) >> 1;
+          if (pre[m] <= u) l = m;
+          else h = m;
+        }
+        const uint32_t qn = uni(l);
+        const uint32_t p0 = uni(pre[qn]), end = min(hi, uni(pre[qn + 1]));
+        wave_arcs += gang_work(a, qn, uni_state(gs[qn]), u - p0, end - p0, sh);
+        u = end;
       }
-      const uint32_t qn = uni(l);
-      const uint32_t p0 = uni(pre[qn]), end = min(hi, uni(pre[qn + 1]));
-      gang_work(a, qn, uni_state(gs[qn]), u - p0, end - p0, sh);
-      u = end;
     }
     if (!team_barrier(a.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return;
     for (uint32_t i = threadIdx.x; i < nq; i += Q_THREADS) gang_advance(a, a.q[i], gs[i], &a.status[i]);
   }
+  if (lane_id() == 0 && wave_arcs) atomicAdd(&a.ctrl->arcs, wave_arcs);
   if (w == 0 && threadIdx.x == 0) atomicAdd(&a.ctrl->done, nq);
 }
 
