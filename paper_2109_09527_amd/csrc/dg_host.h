@@ -75,6 +75,8 @@ struct QueryScratch {
   DevBuf rlist, rstamp;         // SSSP: vertices of the current bucket
   DevBuf counters;
   void* host_counters = nullptr;
+  void* host_pub = nullptr;     // coherent pinned block the device publishes counters into
+  uint32_t pub_seq = 0;         // sequence number of the last publication
   uint64_t items_cap = 0, chunks_cap = 0;
   uint32_t lch = 6;             // log2 of the chunk size in buckets
 };

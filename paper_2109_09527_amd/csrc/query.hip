@@ -22,6 +22,7 @@
 //         fixed lane order (no float atomics); bc[v] += delta[v] for v != s,
 //         sources in order.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "dg_host.h"
@@ -163,6 +164,45 @@ constexpr size_t STRIPE_OFF = 256;
 constexpr size_t COUNTERS_BYTES = STRIPE_OFF + 4 * N_STRIPES * sizeof(CountStripe);
 static_assert(4 * sizeof(QCounters) <= STRIPE_OFF, "counter slots overlap their stripes");
 
+// What the device publishes to the host after a step: one slot's counters
+// with its stripes added in, the running bucket record count, and the
+// sequence number that marks the publication complete.
+struct HostCounters {
+  QCounters c;
+  uint32_t rc;
+  uint32_t seq;
+};
+
+// One wave: sums slot's stripes into its counters and writes the result to
+// pinned host memory, the sequence number last (system scope), so the host
+// can wait by polling instead of synchronising the stream.
+__global__ void k_publish(const QCounters* cnt, const CountStripe* st, int slot, HostCounters* h, uint32_t seq) {
+  const uint32_t lane = threadIdx.x;
+  unsigned long long m = 0, arcs = 0;
+  uint32_t verts = 0, far = 0;
+  if (lane < N_STRIPES) {
+    const CountStripe* x = st + (size_t)slot * N_STRIPES + lane;
+    m = x->m;
+    arcs = x->arcs;
+    verts = x->verts;
+    far = x->far;
+  }
+  m = wave_sum_u64(m);
+  arcs = wave_sum_u64(arcs);
+  verts = wave_sum_u32(verts);
+  far = wave_sum_u32(far);
+  if (lane != 0) return;
+  QCounters r = cnt[slot];
+  r.m_next += m;
+  r.arcs += arcs;
+  r.n_verts += verts;
+  r.n_far += far;
+  h->c = r;
+  h->rc = cnt[3].n_order;
+  __threadfence_system();
+  __hip_atomic_store(&h->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
   hipError_t e;
   const uint64_t V = g->cfg.v_capacity;
@@ -179,6 +219,11 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
   if ((e = ensure(q.bm0, bmw * 4)) != hipSuccess) return e;
   if ((e = ensure(q.bm1, bmw * 4)) != hipSuccess) return e;
   if ((e = ensure(q.counters, COUNTERS_BYTES)) != hipSuccess) return e;
+  if (!q.host_pub) {
+    if ((e = hipHostMalloc(&q.host_pub, sizeof(HostCounters), hipHostMallocCoherent)) != hipSuccess) return e;
+    std::memset(q.host_pub, 0, sizeof(HostCounters));
+    q.pub_seq = 0;
+  }
   if (!q.host_counters) {
     if ((e = hipHostMalloc(&q.host_counters, COUNTERS_BYTES, hipHostMallocDefault)) != hipSuccess) return e;
   }
@@ -209,6 +254,8 @@ void free_query_scratch(QueryScratch& q) {
   release(q.counters);
   if (q.host_counters) hipHostFree(q.host_counters);
   q.host_counters = nullptr;
+  if (q.host_pub) hipHostFree(q.host_pub);
+  q.host_pub = nullptr;
 }
 
 static CountStripe* stripes_of(QueryScratch& q, int slot) {
@@ -216,22 +263,27 @@ static CountStripe* stripes_of(QueryScratch& q, int slot) {
 }
 
 // Counters of one slot with its stripes added in, plus the running bucket
-// record count (slot 3); one copy of the whole block.
+// record count (slot 3): a one-wave kernel publishes them to pinned host
+// memory, and the host polls for its sequence number (a stream
+// synchronisation costs more than the step it follows when steps are
+// short).  A publication not seen within two seconds falls back to
+// synchronising the stream, which reports any device error.
 static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(q.host_counters, q.counters.p, COUNTERS_BYTES, hipMemcpyDeviceToHost, s);
+  HostCounters* h = static_cast<HostCounters*>(q.host_pub);
+  const uint32_t seq = ++q.pub_seq;
+  k_publish<<<1, 64, 0, s>>>(q.counters.as<QCounters>(), stripes_of(q, 0), slot, h, seq);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  const QCounters* h = static_cast<const QCounters*>(q.host_counters);
-  std::memcpy(out, h + slot, sizeof(QCounters));
-  const CountStripe* x =
-      reinterpret_cast<const CountStripe*>(static_cast<const char*>(q.host_counters) + STRIPE_OFF) + slot * N_STRIPES;
-  for (uint32_t i = 0; i < N_STRIPES; i++) {
-    out->m_next += x[i].m;
-    out->arcs += x[i].arcs;
-    out->n_verts += x[i].verts;
-    out->n_far += x[i].far;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 1; __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq; spin++) {
+    if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (__atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
+      break;
+    }
   }
-  *rc = h[3].n_order;
+  std::memcpy(out, &h->c, sizeof(QCounters));
+  *rc = h->rc;
   return hipSuccess;
 }
 
