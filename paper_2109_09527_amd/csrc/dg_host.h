@@ -60,7 +60,8 @@ struct UpdateScratch {
   DevBuf ops, results, touch, plan, clear;
   DevBuf grow;                  // growing slabs: touch index, new offset, kept count
   DevBuf summary;               // UpdCounters followed by the vertex-change list
-  void* host_summary = nullptr; // pinned mirror of the first part of summary
+  void* host_summary = nullptr; // coherent pinned copy of the first part of summary, plus a sequence word
+  uint32_t pub_seq = 0;         // sequence number of the last publication
   uint64_t cap = 0;
 };
 

@@ -68,6 +68,32 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(uint32_t* data, uint
   }
 }
 
+// Exclusive scan of up to SCAN_SINGLE_MAX values by one workgroup: tiles in
+// order with a running carry.  For the short arrays of a batch's sort
+// passes one launch costs less than the reduce / scan / down-sweep chain.
+constexpr uint64_t SCAN_SINGLE_MAX = 32ull * SCAN_TILE;
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_single(uint32_t* data, uint64_t n) {
+  uint32_t carry = 0;
+  for (uint64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+    const uint64_t base = t0 + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+      v[i] = base + i < n ? data[base + i] : 0;
+      s += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_exclusive_scan(s, &tot) + carry;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+      if (base + i < n) data[base + i] = off;
+      off += v[i];
+    }
+    carry += tot;
+  }
+}
+
 uint64_t scan_scratch_words(uint64_t n) {
   uint64_t w = 0;
   while (n > (uint64_t)SCAN_TILE) {
@@ -81,6 +107,10 @@ void exclusive_scan_u32(uint32_t* data, uint64_t n, uint32_t* scratch, hipStream
   if (n == 0) return;
   if (n <= (uint64_t)SCAN_TILE) {
     k_scan_down<<<1, SCAN_THREADS, 0, s>>>(data, n, nullptr);
+    return;
+  }
+  if (n <= SCAN_SINGLE_MAX) {
+    k_scan_single<<<1, SCAN_THREADS, 0, s>>>(data, n);
     return;
   }
   uint64_t nblk = (n + SCAN_TILE - 1) / SCAN_TILE;

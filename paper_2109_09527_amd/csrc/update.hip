@@ -33,6 +33,7 @@
 // the commit kernels also when the growth step ran out of pool space, so
 // a rejected batch leaves the store untouched.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "dg_host.h"
@@ -502,11 +503,25 @@ static hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
   ENS(summary, sizeof(UpdCounters) + c * 4)
 #undef ENS
   if (!u.host_summary) {
-    e = hipHostMalloc(&u.host_summary, sizeof(UpdCounters) + VCHANGE_INLINE * 4, hipHostMallocDefault);
+    // counters, the inline vertex changes, then the publication's sequence word
+    e = hipHostMalloc(&u.host_summary, sizeof(UpdCounters) + VCHANGE_INLINE * 4 + 4, hipHostMallocCoherent);
+    if (e == hipSuccess) std::memset(u.host_summary, 0, sizeof(UpdCounters) + VCHANGE_INLINE * 4 + 4);
     if (e != hipSuccess) return e;
   }
   u.cap = c;
   return hipSuccess;
+}
+
+// Copies the batch counters and the first VCHANGE_INLINE vertex changes to
+// coherent pinned host memory, then (system scope, last) the sequence word.
+__global__ void k_upd_publish(const UpdCounters* c, const uint32_t* vchange, uint32_t* host, uint32_t seq) {
+  constexpr uint32_t W = sizeof(UpdCounters) / 4;
+  const uint32_t* cw = reinterpret_cast<const uint32_t*>(c);
+  const uint32_t nv = min(c->n_vchange, VCHANGE_INLINE);
+  for (uint32_t t = threadIdx.x; t < W + nv; t += blockDim.x) host[t] = t < W ? cw[t] : vchange[t - W];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(host + W + VCHANGE_INLINE, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Runs the pipeline once; *flags receives the batch flags.
@@ -560,11 +575,23 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
   k_commit_vertex<<<blocks_for(n, UPD_THREADS, 1024), UPD_THREADS, 0, s>>>(st, vchange, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  size_t inl = sizeof(UpdCounters) + std::min<uint64_t>(n, VCHANGE_INLINE) * 4;
-  e = hipMemcpyAsync(u.host_summary, c, inl, hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
+  // the device publishes the counters (and the first vertex changes) to
+  // coherent pinned memory and the host polls for the sequence word; a
+  // publication not seen within two seconds falls back to synchronising
+  // the stream, which reports any device error
+  uint32_t* hs = static_cast<uint32_t*>(u.host_summary);
+  uint32_t* seqw = hs + sizeof(UpdCounters) / 4 + VCHANGE_INLINE;
+  const uint32_t seq = ++u.pub_seq;
+  k_upd_publish<<<1, 256, 0, s>>>(c, vchange, hs, seq);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 1; __atomic_load_n(seqw, __ATOMIC_ACQUIRE) != seq; spin++) {
+    if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (__atomic_load_n(seqw, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
+      break;
+    }
+  }
   std::memcpy(hc, u.host_summary, sizeof(UpdCounters));
   return hipSuccess;
 }
