@@ -1467,7 +1467,7 @@ extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, 
   try_field(&dg_tuning::alpha, {4, 14, 40, 1000000}, 0);
   try_field(&dg_tuning::beta, {8, 24, 64}, 0);
   try_field(&dg_tuning::sssp_delta, {16, 32, 64, 128, 256, 512}, 1);
-  try_field(&dg_tuning::batch_delta, {8, 16, 32, 64, 128}, 2);
+  try_field(&dg_tuning::batch_delta, {8, 16, 32, 64, 128, 256, 512, 1024}, 2);
   try_field(&dg_tuning::batch_groups, {0, 4, 8, 16, 32}, 2);
   release(deg);
   release(d0);

@@ -114,7 +114,7 @@ struct Tuning {
   uint32_t sssp_delta = 64;
   uint32_t alpha = 14, beta = 24;
   uint32_t batch_groups = 0;   // workgroups per query team; 0 = automatic
-  uint32_t batch_delta = 32;   // delta of the SSSP queries inside a batch launch
+  uint32_t batch_delta = 512;  // delta of the SSSP queries inside a batch launch
   uint32_t batch_gang = 0;     // SSSP queries per lockstep launch; 0 = automatic
 };
 
