@@ -542,7 +542,7 @@ __global__ __launch_bounds__(Q_THREADS, 4) void k_team(BatchArgs a) {
 // persistent launch whose workgroups form a single team.  A pass does, for
 // every query still running, the next step of its delta-stepping (a relax
 // pass over its near frontier, light / heavy / all arcs; the item expansion
-// of a settled bucket's recorded vertices; or a split of its far list at a
+// of a settled bucket's recorded vertices; or a split of its far set at a
 // raised threshold).  The work units of all queries (frontier chunks, blocks
 // of 64 list entries) form one index space, cut into equal contiguous
 // ranges, one per wave; a grid barrier ends the pass.  Every workgroup then
@@ -608,7 +608,7 @@ __device__ inline uint32_t gang_units(const GangArgs& a, const GState& s) {
   }
 }
 
-// Leave the bucket: split the far list (at a threshold one delta higher),
+// Leave the bucket: split the far set (at a threshold one delta higher),
 // or finish.
 __device__ inline void gang_to_split(GState& s, int32_t delta) {
   if (s.n_far == 0) {

@@ -69,7 +69,7 @@ struct UpdateScratch {
 struct QueryScratch {
   DevBuf qa, qb;                // frontier items
   DevBuf cmap_a, cmap_b;        // their chunk maps
-  DevBuf fa, fb;                // far queues (SSSP) / vertex order (BC)
+  DevBuf fa, fb;                // BC: vertex order; bottom-up BFS: tile items
   DevBuf bm0, bm1;              // frontier bitmaps
   DevBuf stamp, flag8;          // SSSP dedup state
   DevBuf sigma, delta, level;   // BC
