@@ -435,7 +435,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   bool ovf = false;
   auto relax = [&](unsigned long long nfq, int mode) -> hipError_t {
     int nxt = slot ^ 1;
-    // vertices this pass lowers to the threshold or above are flagged far
+    // far entries found by this pass are appended after the current far list
     RelaxArgs a{g->st, e,     fast,  fr[qi], fr[qi ^ 1], dist,  stamp,  infar, thr,
                 it,    cnt + nxt, mode, delta,  rlist,      rcount, rstamp, phase, stripes_of(q, nxt)};
     {
