@@ -160,7 +160,6 @@ struct dg_server {
       const size_t n = batch.size();
       if (outs.size() < n) outs.resize(n);
       std::vector<dg_query> qs(n);
-      std::vector<dg_status> st(n, DG_OK);
       bool alloc_ok = true;
       for (size_t i = 0; i < n; i++) {
         Req* r = batch[i];
@@ -169,23 +168,40 @@ struct dg_server {
                          r->kind == DG_Q_BC ? (uint32_t)r->srcs.size() : 0u,
                          r->kind == DG_Q_BC ? r->srcs.data() : nullptr, outs[i].p};
       }
-      const uint64_t arcs0 = g->engine_arcs.load();
-      dg_status call =
-          alloc_ok ? dg::query_batch_dev(g, qs.data(), (uint32_t)n, st.data(), sq_, 1 + lane) : DG_E_OUT_OF_MEMORY;
-      {
-        std::lock_guard<std::mutex> lk(m);
-        arcs += g->engine_arcs.load() - arcs0;
-      }
-      for (size_t i = 0; i < n; i++) {
-        Req* r = batch[i];
-        dg_status s = call != DG_OK ? call : st[i];
-        if (s == DG_OK) {
-          r->out.resize(out_bytes(r));
-          if (hipMemcpyAsync(r->out.data(), outs[i].p, r->out.size(), hipMemcpyDeviceToHost, sq_) != hipSuccess ||
-              hipStreamSynchronize(sq_) != hipSuccess)
-            s = DG_E_HIP;
+      // BFS and SSSP first, BC after, on the same epoch: the short queries
+      // of a round finish without waiting for its BC sources
+      std::vector<size_t> order;
+      for (int heavy = 0; heavy < 2; heavy++)
+        for (size_t i = 0; i < n; i++)
+          if ((batch[i]->kind == DG_Q_BC) == (heavy == 1)) order.push_back(i);
+      size_t o0 = 0;
+      while (o0 < n) {
+        const bool heavy = batch[order[o0]]->kind == DG_Q_BC;
+        size_t o1 = o0;
+        while (o1 < n && (batch[order[o1]]->kind == DG_Q_BC) == heavy) o1++;
+        std::vector<dg_query> part;
+        for (size_t t = o0; t < o1; t++) part.push_back(qs[order[t]]);
+        std::vector<dg_status> pst(part.size(), DG_OK);
+        const uint64_t arcs0 = g->engine_arcs.load();
+        dg_status call = alloc_ok ? dg::query_batch_dev(g, part.data(), (uint32_t)part.size(), pst.data(), sq_, 1 + lane)
+                                  : DG_E_OUT_OF_MEMORY;
+        {
+          std::lock_guard<std::mutex> lk(m);
+          arcs += g->engine_arcs.load() - arcs0;
         }
-        finish(r, s, e_bind);
+        for (size_t t = o0; t < o1; t++) {
+          const size_t i = order[t];
+          Req* r = batch[i];
+          dg_status s = call != DG_OK ? call : pst[t - o0];
+          if (s == DG_OK) {
+            r->out.resize(out_bytes(r));
+            if (hipMemcpyAsync(r->out.data(), outs[i].p, r->out.size(), hipMemcpyDeviceToHost, sq_) != hipSuccess ||
+                hipStreamSynchronize(sq_) != hipSuccess)
+              s = DG_E_HIP;
+          }
+          finish(r, s, e_bind);
+        }
+        o0 = o1;
       }
       if (pinned) dg_snapshot_release(g, e_bind);
     }
