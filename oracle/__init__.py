@@ -64,6 +64,8 @@ def _load():
     lib.orc_export.argtypes = [P, P, P, P]
     lib.orc_out_degree.restype = u32
     lib.orc_out_degree.argtypes = [P, u32]
+    lib.orc_pagerank.restype = ctypes.c_int
+    lib.orc_pagerank.argtypes = [P, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
     return lib
 
@@ -79,6 +81,7 @@ class Oracle:
     def __init__(self, n_vertices: int, undirected: bool = False, w_max: int = 255):
         self.lib = _load()
         self.n = int(n_vertices)
+        self.undirected = bool(undirected)
         self.h = self.lib.orc_create(self.n, 1 if undirected else 0, int(w_max))
         if not self.h:
             raise ValueError("oracle: invalid configuration")
@@ -133,6 +136,15 @@ class Oracle:
 
     def out_degree(self, v: int) -> int:
         return int(self.lib.orc_out_degree(self.h, int(v)))
+
+    def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000):
+        """(status, pr[n] float64, iterations, last iteration's largest change)."""
+        out = np.zeros(self.n, dtype=np.float64)
+        it = ctypes.c_uint32()
+        ch = ctypes.c_double()
+        rc = self.lib.orc_pagerank(self.h, float(damping), float(threshold), int(max_iters), _ptr(out),
+                                   ctypes.byref(it), ctypes.byref(ch))
+        return rc, out, it.value, ch.value
 
     def edges(self):
         """All stored edge keys as (u, v, w) arrays (undirected: u <= v)."""

@@ -37,6 +37,7 @@
  */
 #include "dg_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -489,4 +490,64 @@ int orc_bc(const orc_graph* g, const uint32_t* S, uint32_t k, double* bc) {
   free(delta);
   free(order);
   return rc;
+}
+
+/* ------------------------------------------------------------- PageRank */
+
+/* Eq. (1): pr(u) = (1 - d)/n + d * sum over arcs (v, u) of pr(v)/q(v), with
+ * n the live vertices and q(v) the out-degree of v.  Iterated as the
+ * synchronous Barrier baseline (Alg. 1): every live vertex starts from 1/n in
+ * the previous-iteration array; an iteration recomputes each live vertex from
+ * the previous values alone, starting at (1 - d)/n and adding
+ * prev(v)/q(v) * d per in-arc in turn, and records the largest
+ * |prev(u) - pr(u)|; the loop continues while that change exceeds the
+ * threshold.  The change is measured afresh in every iteration.  A vertex
+ * with no out-arcs passes nothing on (Eq. (1) has no term for it).  In-arcs
+ * of u are in[u] for a directed graph and out[u] for an undirected one,
+ * whose arcs are stored in both directions. */
+int orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t max_iters, double* pr,
+                 uint32_t* iters, double* last_change) {
+  if (!(damping >= 0.0 && damping < 1.0) || !(threshold >= 0.0)) return ORC_E_INVALID_ARG;
+  const uint32_t n = g->n;
+  uint64_t live = 0;
+  for (uint32_t u = 0; u < n; u++) live += g->alive[u] ? 1 : 0;
+  for (uint32_t u = 0; u < n; u++) pr[u] = 0.0;
+  *iters = 0;
+  *last_change = 0.0;
+  if (live == 0) return ORC_OK;
+  double* prev = (double*)malloc((size_t)n * sizeof(double));
+  if (!prev) return ORC_E_OOM;
+  for (uint32_t u = 0; u < n; u++) prev[u] = g->alive[u] ? 1.0 / (double)live : 0.0;
+  const double base = (1.0 - damping) / (double)live;
+  double err = 1.0;
+  uint32_t it = 0;
+  while (err > threshold && it < max_iters) {
+    err = 0.0;
+    for (uint32_t u = 0; u < n; u++) {
+      if (!g->alive[u]) continue;
+      double x = base;
+      if (g->undirected) {
+        const arc_list* l = &g->out[u];
+        for (uint32_t j = 0; j < l->n; j++) {
+          const uint32_t v = l->a[j].v;
+          x = x + prev[v] / (double)g->out[v].n * damping;
+        }
+      } else {
+        const id_list* l = &g->in[u];
+        for (uint32_t j = 0; j < l->n; j++) {
+          const uint32_t v = l->a[j];
+          x = x + prev[v] / (double)g->out[v].n * damping;
+        }
+      }
+      pr[u] = x;
+      const double c = fabs(prev[u] - x);
+      if (c > err) err = c;
+    }
+    for (uint32_t u = 0; u < n; u++) prev[u] = pr[u];
+    it++;
+  }
+  free(prev);
+  *iters = it;
+  *last_change = err;
+  return ORC_OK;
 }

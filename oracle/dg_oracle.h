@@ -12,7 +12,9 @@
  *   - BFS hop distances (FIFO queue), SSSP distances (binary-heap Dijkstra)
  *     and Brandes betweenness (int64 path counts, FP64 dependencies), the
  *     queries named BFS / SSSP / BC in the same preamble, on the current
- *     state.
+ *     state;
+ *   - PageRank of the current state, Eq. (1) iterated as the synchronous
+ *     Barrier baseline (Alg. 1) in FP64.
  *
  * Error codes are the integer values of the C boundary's call status.
  */
@@ -53,6 +55,13 @@ uint64_t   orc_n_keys(const orc_graph* g);
 uint64_t   orc_export(const orc_graph* g, uint32_t* u, uint32_t* v, int32_t* w);
 /* Out-degree (visible arcs) of v. */
 uint32_t   orc_out_degree(const orc_graph* g, uint32_t v);
+/* PageRank (Eq. (1), Alg. 1): pr[v] for every id (0 for vertices that are not
+ * live), the iterations run and the last iteration's largest change.  Stops
+ * once that change is at most `threshold`, or after max_iters iterations.
+ * ORC_E_INVALID_ARG for a damping factor outside [0, 1) or a negative
+ * threshold. */
+int        orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t max_iters, double* pr,
+                        uint32_t* iters, double* last_change);
 
 #ifdef __cplusplus
 }
