@@ -127,6 +127,27 @@ dg_status dg_sssp(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* st
 dg_status dg_bc(dg_graph* g, dg_epoch e, const uint32_t* srcs, uint32_t k, double* bc, void* stream);
 
 /*
+ * Snapshot PageRank on epoch e: Eq. (1) of arXiv 2109.09527, iterated as its
+ * synchronous Barrier baseline (Alg. 1), in FP64.  With n the live vertices
+ * at e and q(v) the visible out-degree, every live vertex starts at 1/n, and
+ * an iteration sets pr(u) = (1 - damping)/n + damping * sum over visible arcs
+ * (v, u) of pr(v)/q(v), all from the previous iteration's values.  The loop
+ * stops after the first iteration whose largest |change| over the live
+ * vertices is at most `threshold` (the paper uses damping 0.85 and threshold
+ * 1e-16), or after max_iters iterations.  Vertices without out-arcs pass
+ * nothing on (no redistribution).
+ * pr: device array of v_capacity doubles, written for every id (0 where the
+ *   vertex is not live at e, and everywhere when no iteration runs).
+ * iterations, last_change (host, optional): iterations run and the largest
+ *   change of the last one; last_change > threshold means max_iters stopped it.
+ * DG_E_INVALID_ARG for damping outside [0, 1), a negative or NaN threshold,
+ * or pr not in device memory.  The call returns after the last iteration's
+ * change is read back; pr is then complete in stream order.
+ */
+dg_status dg_pagerank(dg_graph* g, dg_epoch e, double damping, double threshold, uint32_t max_iters, double* pr,
+                      uint32_t* iterations, double* last_change, void* stream);
+
+/*
  * Many queries in one persistent launch.  Each query names its kind, epoch
  * and source(s) and a caller-owned device output (int32[v_capacity] for BFS
  * and SSSP, double[v_capacity] for BC).  per_query (host, nq entries)

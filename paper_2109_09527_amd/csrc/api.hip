@@ -406,6 +406,7 @@ dg_status dg_destroy(dg_graph* g) {
     release(*b);
   if (u.host_summary) hipHostFree(u.host_summary);
   free_query_scratch(g->qs);
+  free_pr_scratch(g->pr);
   free_batch_state(g);
   for (auto& r : g->prof.pending) {
     hipEventDestroy(r.a);
@@ -579,6 +580,24 @@ dg_status dg_bc(dg_graph* g, dg_epoch want, const uint32_t* srcs, uint32_t k, do
   return note_query(g, bc_dev(g, e, S.data(), k, bc, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
+dg_status dg_pagerank(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters, double* pr,
+                      uint32_t* iterations, double* last_change, void* stream) {
+  if (!g || !pr) return DG_E_INVALID_ARG;
+  if (!is_device_ptr(pr)) return fail(g, DG_E_INVALID_ARG, "pr must be device memory");
+  if (!(damping >= 0.0 && damping < 1.0)) return fail(g, DG_E_INVALID_ARG, "damping must lie in [0, 1)");
+  if (!(threshold >= 0.0)) return fail(g, DG_E_INVALID_ARG, "threshold must be non-negative");
+  std::lock_guard<std::mutex> lk(g->mu);
+  uint32_t e;
+  dg_status st = resolve_epoch(g, want, &e);
+  if (st != DG_OK) return st;
+  uint32_t it = 0;
+  double ch = 0.0;
+  st = pagerank_dev(g, e, damping, threshold, max_iters, pr, &it, &ch, static_cast<hipStream_t>(stream));
+  if (iterations) *iterations = it;
+  if (last_change) *last_change = ch;
+  return note_query(g, st, stream);
+}
+
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
@@ -610,7 +629,7 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
 dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
-                                         "batch_sssp",   "batch_bc"};
+                                         "batch_sssp",   "batch_bc",     "pagerank"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

@@ -82,6 +82,12 @@ struct QueryScratch {
   uint32_t lch = 6;             // log2 of the chunk size in buckets
 };
 
+// Snapshot PageRank: the in-CSR of one call and its iteration state.
+struct PrScratch {
+  DevBuf live, dsnap, ntiles, tile_v, tcount, off, pfirst, piece_v, csr, q, contrib, part, ring, scan;
+  void* host = nullptr;   // pinned: liveness mask upload, totals and changes read back
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -94,6 +100,7 @@ enum KernelId {
   KID_BATCH_BFS,    // one persistent multi-query launch, per query kind
   KID_BATCH_SSSP,
   KID_BATCH_BC,
+  KID_PAGERANK,     // one PageRank iteration (pull and apply)
   KID_COUNT
 };
 struct Prof {
@@ -137,6 +144,7 @@ struct dg_graph {
   std::vector<uint64_t> live_by_epoch{0};   // live vertices at each epoch
   dg::UpdateScratch us;
   dg::QueryScratch qs;
+  dg::PrScratch pr;
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
@@ -176,6 +184,11 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
                  QueryScratch& q);
 dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hipStream_t s);
 void free_query_scratch(QueryScratch& q);
+
+// pagerank.hip
+dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
+                       uint32_t* iters, double* last_change, hipStream_t s);
+void free_pr_scratch(PrScratch& s);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

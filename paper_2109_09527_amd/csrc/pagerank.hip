@@ -1,0 +1,391 @@
+// Snapshot PageRank on epoch e: Eq. (1) iterated synchronously, as in the
+// Barrier baseline (Alg. 1).  Every live vertex starts at 1/n (n = live
+// vertices at e); an iteration recomputes all of them from the previous
+// values only, pr(u) = (1 - d)/n + d * sum over visible arcs (v, u) of
+// pr(v)/q(v), with q(v) the visible out-degree, and the loop ends at the
+// first iteration whose largest |change| is at most the threshold (the
+// change is measured afresh each iteration).  A vertex without out-arcs
+// passes nothing on.  FP64 throughout.
+//
+// The iterations run over a compact snapshot of the visible in-arcs at e
+// (in-CSR, sources only), built once per call:
+//   tiles   each live vertex's in-slab cut into tiles of PR_TILE buckets
+//           (64 slots, one wave step), so hub slabs spread over many waves
+//   count   visible slots per tile; an exclusive scan over the tiles gives
+//           every tile its position in the CSR (tiles of a vertex are
+//           consecutive, vertices in id order)
+//   fill    each tile's visible sources, bucket by bucket, slot by slot
+//   q(v)    out-degrees counted from the CSR's sources (integer atomics)
+// An iteration then streams 4 bytes per arc plus one random 8-byte read of
+// the source's contribution, instead of re-reading buckets and stamps.
+//
+// Per iteration, two kernels:
+//   k_pr_pull   one 16-lane group per piece (at most PR_PIECE consecutive
+//               in-arcs of one vertex): lanes sum contrib[src] over strided
+//               arcs, then a fixed shuffle tree combines them
+//   k_pr_apply  one lane per vertex: its pieces' sums in piece order, the new
+//               value, its change (maximum over the grid), and
+//               contrib = pr/q for the next iteration
+// Every summation order is fixed, so results do not vary between runs.
+//
+// Convergence stays on the device: iteration i's largest change goes into
+// slot i of a ring (atomicMax on the bit pattern, which orders non-negative
+// doubles), and both kernels of iteration i return at once when iteration
+// i - 1 stored a change within the threshold (a skipped iteration leaves 0
+// in its slot, so the skip carries on).  The host queues iterations in
+// batches, reads the batch's changes back once, and sizes the next batch
+// from the observed contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dg_host.h"
+
+namespace dg {
+
+uint64_t live_at(const dg_graph* g, uint32_t e);
+
+constexpr uint32_t PR_THREADS = 256;
+constexpr uint32_t PR_TILE = 4;          // buckets per build tile (4 x 16 slots = one wave step)
+constexpr uint32_t PR_PIECE = 256;       // in-arcs per pull piece (16 lanes x 16)
+constexpr uint32_t PR_RING = 128;        // slots of the per-iteration change ring
+constexpr uint32_t PR_BATCH_MAX = 48;    // iterations queued per host check (<= PR_RING / 2)
+
+__device__ inline uint32_t pr_lane() { return __lane_id(); }
+
+__global__ void k_pr_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Tiles of each live vertex's in-slab (entry V stays 0 for the scan).  The
+// descriptors are copied once, so that count and fill read the same slabs
+// even if a concurrent update regrows one (an old slab keeps every version
+// visible at e).
+__global__ void k_pr_ntiles(const uint64_t* desc, const uint8_t* live, uint32_t V, uint64_t* dsnap,
+                            uint32_t* ntiles) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= V; u += gridDim.x * blockDim.x) {
+    uint32_t t = 0;
+    if (u < V) {
+      const uint64_t d = live[u] ? desc[u] : 0;
+      dsnap[u] = d;
+      const uint32_t nb = d ? 1u << (d & 63) : 0;
+      t = (nb + PR_TILE - 1) / PR_TILE;
+    }
+    ntiles[u] = t;
+  }
+}
+
+// tile_v[t] = owning vertex, for the tiles tfirst[u] .. tfirst[u + 1).
+__global__ void k_pr_tile_list(const uint32_t* tfirst, uint32_t V, uint32_t* tile_v) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x)
+    for (uint32_t t = tfirst[u]; t < tfirst[u + 1]; t++) tile_v[t] = u;
+}
+
+// One wave step over tile t: lane l reads slot l & 15 of bucket
+// tfirst-relative 4 * k + (l >> 4); returns the source or EMPTY.
+__device__ inline uint32_t pr_tile_slot(const Pool& p, const uint64_t* desc, const uint32_t* tfirst,
+                                        const uint32_t* tile_v, uint32_t t, uint32_t e) {
+  const uint32_t lane = pr_lane();
+  const uint32_t u = tile_v[t];
+  const Slab s = slab_of(p, desc[u]);
+  const uint32_t b = (t - tfirst[u]) * PR_TILE + (lane >> 4);
+  const int j = (int)(lane & 15);
+  if (b >= s.nb) return EMPTY;
+  uint32_t* bp = bucket_ptr(s, b);
+  const uint32_t src = bp[j];
+  if (src == EMPTY || !visible(*slot_stamp(bp, j, s.words), e)) return EMPTY;
+  return src;
+}
+
+__global__ __launch_bounds__(PR_THREADS) void k_pr_count(Pool p, const uint64_t* desc, const uint32_t* tfirst,
+                                                         const uint32_t* tile_v, uint32_t T, uint32_t e,
+                                                         uint32_t* tcount) {
+  const uint32_t nw = gridDim.x * (PR_THREADS / 64);
+  for (uint32_t t = blockIdx.x * (PR_THREADS / 64) + (threadIdx.x >> 6); t < T; t += nw) {
+    const uint32_t src = pr_tile_slot(p, desc, tfirst, tile_v, t, e);
+    const uint32_t c = (uint32_t)__popcll(__ballot(src != EMPTY));
+    if (pr_lane() == 0) tcount[t] = c;
+  }
+}
+
+__global__ __launch_bounds__(PR_THREADS) void k_pr_fill(Pool p, const uint64_t* desc, const uint32_t* tfirst,
+                                                        const uint32_t* tile_v, uint32_t T, uint32_t e,
+                                                        const uint32_t* toff, uint32_t* csr) {
+  const uint32_t nw = gridDim.x * (PR_THREADS / 64);
+  const uint32_t lane = pr_lane();
+  for (uint32_t t = blockIdx.x * (PR_THREADS / 64) + (threadIdx.x >> 6); t < T; t += nw) {
+    const uint32_t src = pr_tile_slot(p, desc, tfirst, tile_v, t, e);
+    const unsigned long long m = __ballot(src != EMPTY);
+    const uint32_t pos = toff[t] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (src != EMPTY && pos < toff[t + 1]) csr[pos] = src;
+  }
+}
+
+// CSR start of each vertex and its pieces (entry V stays 0 for the scan).
+__global__ void k_pr_offsets(const uint32_t* tfirst, const uint32_t* toff, uint32_t V, uint32_t* off,
+                             uint32_t* npieces) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= V; u += gridDim.x * blockDim.x) {
+    off[u] = toff[tfirst[u]];
+    npieces[u] = u < V ? (toff[tfirst[u + 1]] - toff[tfirst[u]] + PR_PIECE - 1) / PR_PIECE : 0;
+  }
+}
+
+__global__ void k_pr_piece_list(const uint32_t* pfirst, uint32_t V, uint32_t* piece_v) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x)
+    for (uint32_t k = pfirst[u]; k < pfirst[u + 1]; k++) piece_v[k] = u;
+}
+
+__global__ void k_pr_clear_ring(unsigned long long* ring, uint32_t first, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) ring[(first + i) % PR_RING] = 0ull;
+}
+
+__global__ void k_pr_outdeg(const uint32_t* csr, uint64_t m, uint32_t* q) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&q[csr[i]], 1u);
+}
+
+// pr = 1/n and contrib = pr/q on live vertices, 0 elsewhere.
+__global__ void k_pr_init(const uint8_t* live, const uint32_t* q, uint32_t V, double inv_n, double* pr,
+                          double* contrib) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x) {
+    const double x = live[u] ? inv_n : 0.0;
+    pr[u] = x;
+    contrib[u] = live[u] && q[u] ? x / (double)q[u] : 0.0;
+  }
+}
+
+__device__ inline bool pr_skip(const unsigned long long* ring, uint32_t it, unsigned long long thr_bits) {
+  return it > 0 && __hip_atomic_load(&ring[(it - 1) % PR_RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                       thr_bits;
+}
+
+struct PrIter {
+  const uint32_t* csr;
+  const uint32_t* off;
+  const uint32_t* pfirst;
+  const uint32_t* piece_v;
+  const uint8_t* live;
+  const uint32_t* q;
+  double* contrib;
+  double* part;
+  double* pr;
+  unsigned long long* ring;
+  uint32_t V, P;
+  double base, d;
+  unsigned long long thr_bits;
+};
+
+__global__ __launch_bounds__(PR_THREADS) void k_pr_pull(PrIter a, uint32_t it) {
+  if (pr_skip(a.ring, it, a.thr_bits)) return;
+  const uint32_t j = threadIdx.x & 15;
+  const uint32_t ng = gridDim.x * (PR_THREADS / 16);
+  for (uint32_t p0 = blockIdx.x * (PR_THREADS / 16); p0 < a.P; p0 += ng) {
+    const uint32_t p = p0 + (threadIdx.x >> 4);   // group-uniform
+    double s = 0.0;
+    if (p < a.P) {
+      const uint32_t u = a.piece_v[p];
+      const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
+      const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
+      // four arcs per lane in flight: indices first, then their contributions
+      for (uint32_t i0 = b + j; i0 < end; i0 += 64) {
+        uint32_t src[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) src[k] = i0 + 16 * k < end ? a.csr[i0 + 16 * k] : EMPTY;
+        double c[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) c[k] = src[k] != EMPTY ? a.contrib[src[k]] : 0.0;
+        s += (c[0] + c[1]) + (c[2] + c[3]);
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    if (p < a.P && j == 0) a.part[p] = s;
+  }
+}
+
+__global__ __launch_bounds__(PR_THREADS) void k_pr_apply(PrIter a, uint32_t it) {
+  if (pr_skip(a.ring, it, a.thr_bits)) return;
+  __shared__ double wmax[PR_THREADS / 64];
+  double ch = 0.0;
+  for (uint32_t u = blockIdx.x * PR_THREADS + threadIdx.x; u < a.V; u += gridDim.x * PR_THREADS) {
+    if (!a.live[u]) continue;
+    double s = 0.0;
+    for (uint32_t k = a.pfirst[u]; k < a.pfirst[u + 1]; k++) s += a.part[k];
+    const double x = a.base + a.d * s;
+    ch = fmax(ch, fabs(a.pr[u] - x));
+    a.pr[u] = x;
+    a.contrib[u] = a.q[u] ? x / (double)a.q[u] : 0.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ch = fmax(ch, __shfl_xor(ch, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = ch;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (uint32_t w = 1; w < PR_THREADS / 64; w++) m = fmax(m, wmax[w]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    if (bits) atomicMax(&a.ring[it % PR_RING], bits);
+  }
+}
+
+static uint32_t pr_grid(uint64_t units, uint32_t per_block, uint32_t cap = 8192) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((units + per_block - 1) / per_block, cap));
+}
+
+void free_pr_scratch(PrScratch& s) {
+  release(s.live); release(s.dsnap); release(s.ntiles); release(s.tile_v); release(s.tcount); release(s.off);
+  release(s.pfirst); release(s.piece_v); release(s.csr); release(s.q); release(s.contrib);
+  release(s.part); release(s.ring); release(s.scan);
+  if (s.host) (void)hipHostFree(s.host);
+  s.host = nullptr;
+}
+
+static hipError_t pr_scan(PrScratch& s, uint32_t* data, uint64_t n, hipStream_t st) {
+  hipError_t e = ensure(s.scan, scan_scratch_words(n) * 4 + 64);
+  if (e != hipSuccess) return e;
+  exclusive_scan_u32(data, n, s.scan.as<uint32_t>(), st);
+  return hipGetLastError();
+}
+
+dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
+                       uint32_t* iters, double* last_change, hipStream_t st) {
+  PrScratch& s = g->pr;
+  const uint32_t V = g->cfg.v_capacity;
+  *iters = 0;
+  *last_change = 0.0;
+  auto fail_hip = [&](hipError_t he, const char* where) {
+    g->err = std::string("pagerank ") + where + ": " + hipGetErrorString(he);
+    return DG_E_HIP;
+  };
+  if (threshold == 0.0) threshold = 0.0;   // -0.0 would compare above every change
+  k_pr_fill_u32<<<pr_grid(2ull * V, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(pr), 2ull * V, 0u);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail_hip(he, "clear");
+  const uint64_t n_live = live_at(g, e);
+  // the loop runs while the change exceeds the threshold, from a change of 1
+  if (n_live == 0 || max_iters == 0 || !(threshold < 1.0)) return DG_OK;
+
+  // liveness at e, from the host's history
+  if (!s.host && (he = hipHostMalloc(&s.host, std::max<size_t>(V, PR_RING * 8) + 64, hipHostMallocDefault)) != hipSuccess)
+    return fail_hip(he, "host buffer");
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "sync");
+  uint8_t* hl = static_cast<uint8_t*>(s.host);
+  for (uint32_t v = 0; v < V; v++) hl[v] = g->vfirst[v] != 0 && g->vfirst[v] <= e;
+  for (const auto& kv : g->vmore) hl[kv.first] = alive_at(g, kv.first, e) ? 1 : 0;
+  if ((he = ensure(s.live, V + 64)) != hipSuccess) return fail_hip(he, "alloc");
+  if ((he = hipMemcpyAsync(s.live.p, hl, V, hipMemcpyHostToDevice, st)) != hipSuccess) return fail_hip(he, "mask");
+
+  // in-arcs: the reverse pool, or the forward one of an undirected graph
+  const bool und = g->st.undirected != 0;
+  const Pool pool = und ? g->st.fp : g->st.rp;
+  const uint64_t* desc = und ? g->st.fdesc : g->st.rdesc;
+  const uint64_t T_max = pool.cap / PR_TILE + V + 1;
+  if ((he = ensure(s.ntiles, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.dsnap, V * 8ull + 64)) != hipSuccess || (he = ensure(s.tile_v, T_max * 4)) != hipSuccess ||
+      (he = ensure(s.tcount, (T_max + 1) * 4)) != hipSuccess || (he = ensure(s.off, (V + 1ull) * 4)) != hipSuccess ||
+      (he = ensure(s.pfirst, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.q, V * 4ull + 64)) != hipSuccess ||
+      (he = ensure(s.contrib, V * 8ull + 64)) != hipSuccess || (he = ensure(s.ring, PR_RING * 8)) != hipSuccess)
+    return fail_hip(he, "alloc");
+  uint32_t* tfirst = s.ntiles.as<uint32_t>();
+  k_pr_ntiles<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(desc, s.live.as<uint8_t>(), V, s.dsnap.as<uint64_t>(), tfirst);
+  desc = s.dsnap.as<uint64_t>();
+  if ((he = pr_scan(s, tfirst, V + 1ull, st)) != hipSuccess) return fail_hip(he, "tile scan");
+  // the tile total (tfirst[V]) is needed on the host before the tile kernels
+  if ((he = hipMemcpyAsync(s.host, tfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess)
+    return fail_hip(he, "tile total");
+  uint32_t T;
+  std::memcpy(&T, s.host, 4);
+  if (T > T_max) {
+    g->err = "pagerank: tile count exceeds its bound";
+    return DG_E_HIP;
+  }
+  k_pr_tile_list<<<pr_grid(V, 256), 256, 0, st>>>(tfirst, V, s.tile_v.as<uint32_t>());
+  uint32_t* tc = s.tcount.as<uint32_t>();
+  k_pr_fill_u32<<<1, 64, 0, st>>>(tc + T, 1, 0u);
+  if (T) k_pr_count<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e, tc);
+  if ((he = pr_scan(s, tc, T + 1ull, st)) != hipSuccess) return fail_hip(he, "arc scan");
+  if ((he = hipMemcpyAsync(s.host, tc + T, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess)
+    return fail_hip(he, "arc total");
+  uint32_t m;
+  std::memcpy(&m, s.host, 4);
+  const uint64_t P_max = (uint64_t)V + m / PR_PIECE + 1;
+  if ((he = ensure(s.csr, (uint64_t)m * 4 + 64)) != hipSuccess || (he = ensure(s.piece_v, P_max * 4)) != hipSuccess ||
+      (he = ensure(s.part, P_max * 8)) != hipSuccess)
+    return fail_hip(he, "alloc");
+  if (T) k_pr_fill<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e, tc,
+                                                                    s.csr.as<uint32_t>());
+  uint32_t* pfirst = s.pfirst.as<uint32_t>();
+  k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, s.off.as<uint32_t>(), pfirst);
+  if ((he = pr_scan(s, pfirst, V + 1ull, st)) != hipSuccess) return fail_hip(he, "piece scan");
+  k_pr_piece_list<<<pr_grid(V, 256), 256, 0, st>>>(pfirst, V, s.piece_v.as<uint32_t>());
+  k_pr_fill_u32<<<pr_grid(V, 256), 256, 0, st>>>(s.q.as<uint32_t>(), V, 0u);
+  if (m) k_pr_outdeg<<<pr_grid(m, 256), 256, 0, st>>>(s.csr.as<uint32_t>(), m, s.q.as<uint32_t>());
+  k_pr_init<<<pr_grid(V, 256), 256, 0, st>>>(s.live.as<uint8_t>(), s.q.as<uint32_t>(), V, 1.0 / (double)n_live, pr,
+                                             s.contrib.as<double>());
+  k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * 2, 0u);
+  if ((he = hipMemcpyAsync(s.host, pfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess)
+    return fail_hip(he, "piece total");
+  uint32_t P;
+  std::memcpy(&P, s.host, 4);
+  if (P > P_max) {
+    g->err = "pagerank: piece count exceeds its bound";
+    return DG_E_HIP;
+  }
+
+  PrIter a{s.csr.as<uint32_t>(), s.off.as<uint32_t>(), pfirst, s.piece_v.as<uint32_t>(), s.live.as<uint8_t>(),
+           s.q.as<uint32_t>(), s.contrib.as<double>(), s.part.as<double>(), pr,
+           reinterpret_cast<unsigned long long*>(s.ring.p), V, P, (1.0 - damping) / (double)n_live, damping, 0};
+  std::memcpy(&a.thr_bits, &threshold, 8);
+  const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, 4096);
+  unsigned long long* ring = a.ring;
+  double* hc = static_cast<double*>(s.host);
+  uint32_t queued = 0, batch = 8;
+  double prev_change = 0.0;
+  for (;;) {
+    const uint32_t b = std::min(batch, max_iters - queued);
+    // clear the batch's slots (the previous batch's last slot stays readable)
+    k_pr_clear_ring<<<1, 64, 0, st>>>(ring, queued % PR_RING, b);
+    for (uint32_t i = queued; i < queued + b; i++) {
+      ProfScope ps(g, KID_PAGERANK, st);
+      k_pr_pull<<<g_pull, PR_THREADS, 0, st>>>(a, i);
+      k_pr_apply<<<g_apply, PR_THREADS, 0, st>>>(a, i);
+    }
+    if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "launch");
+    const uint32_t r0 = queued % PR_RING, n1 = std::min(b, PR_RING - r0);
+    if ((he = hipMemcpyAsync(hc, ring + r0, n1 * 8ull, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (b > n1 && (he = hipMemcpyAsync(hc + n1, ring, (b - n1) * 8ull, hipMemcpyDeviceToHost, st)) != hipSuccess))
+      return fail_hip(he, "read back");
+    if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "sync");
+    for (uint32_t i = 0; i < b; i++) {
+      const double c = hc[i];
+      if (c <= threshold) {
+        *iters = queued + i + 1;
+        *last_change = c;
+        prof_arcs(g, KID_PAGERANK, (uint64_t)m * (i + 1));
+        return DG_OK;
+      }
+    }
+    prof_arcs(g, KID_PAGERANK, (uint64_t)m * b);
+    queued += b;
+    const double last = hc[b - 1];
+    if (queued >= max_iters) {
+      *iters = queued;
+      *last_change = last;
+      return DG_OK;
+    }
+    // iterations left at the observed contraction, plus one
+    const double r = b >= 2 && hc[b - 2] > 0 ? last / hc[b - 2] : (prev_change > 0 ? last / prev_change : 0.9);
+    prev_change = last;
+    uint32_t want = PR_BATCH_MAX;
+    if (r > 0 && r < 1 && last > threshold) {
+      const double k = std::log(threshold / last) / std::log(r);
+      if (k < PR_BATCH_MAX) want = (uint32_t)std::max(1.0, std::ceil(k) + 1);
+    }
+    batch = want;
+  }
+}
+
+}  // namespace dg

@@ -78,6 +78,8 @@ _sig("dg_compact", _i32, _P, _P)
 _sig("dg_bfs", _i32, _P, _u32, _u32, _P, _P)
 _sig("dg_sssp", _i32, _P, _u32, _u32, _P, _P)
 _sig("dg_bc", _i32, _P, _u32, _P, _u32, _P, _P)
+_sig("dg_pagerank", _i32, _P, _u32, ctypes.c_double, ctypes.c_double, _u32, _P, ctypes.POINTER(_u32),
+     ctypes.POINTER(ctypes.c_double), _P)
 _sig("dg_query_batch", _i32, _P, _P, _u32, _P, _P)
 _sig("dg_get_tuning", _i32, _P, ctypes.POINTER(Tuning))
 _sig("dg_set_tuning", _i32, _P, ctypes.POINTER(Tuning))
@@ -241,6 +243,21 @@ class Graph:
         rc, out = self.try_bc(srcs, epoch, out)
         self._check(rc)
         return out
+
+    def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None):
+        """(status, pr tensor, iterations, last iteration's largest change)."""
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
+        it = _u32()
+        ch = ctypes.c_double()
+        rc = lib.dg_pagerank(self.h, epoch, float(damping), float(threshold), int(max_iters), _ptr(out),
+                             ctypes.byref(it), ctypes.byref(ch), _stream())
+        return rc, out, int(it.value), float(ch.value)
+
+    def pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None):
+        """(pr tensor, iterations, last change); raises on a failed call."""
+        rc, out, it, ch = self.try_pagerank(epoch, damping, threshold, max_iters, out)
+        self._check(rc)
+        return out, it, ch
 
     def query_batch(self, queries):
         """queries: list of (kind, epoch, src_or_srcs, out_tensor).  Returns

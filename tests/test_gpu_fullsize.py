@@ -55,6 +55,14 @@ def test_rmat20_update_batches_and_queries(dg):
             assert np.array_equal(g.sssp(s, ep).cpu().numpy(), o.sssp(s)[1])
     nv, na = g.stats()
     assert (nv, na) == o.counts()
+    # snapshot PageRank of the last epoch, whole array (tolerance as in
+    # test_gpu_pagerank: 1e-13 + 1e-12 |pr|; iteration counts within one)
+    say("rmat20 pagerank")
+    rc, want, it_o, _ = o.pagerank()
+    got, it, ch = g.pagerank(ep)
+    err = np.abs(got.cpu().numpy() - want)
+    assert np.all(err <= 1e-13 + 1e-12 * np.abs(want)), err.max()
+    assert abs(it - it_o) <= 1 and ch <= 1e-16
 
 
 @pytest.mark.timeout(600)
