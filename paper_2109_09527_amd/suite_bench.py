@@ -16,6 +16,14 @@
       the engine with the sources split into groups of 16; the sum of the
       groups equals the plain result within 1e-9 relative.
 
+  python -m paper_2109_09527_amd.suite_bench pagerank [--scale 20]
+      R-MAT scale 20 (directed, int32 weights in [1, 255], weights unused)
+      loaded as snapshot e0, then one batch of 65,536 edge ops and 656 vertex
+      ops as e1.  Snapshot PageRank (d = 0.85, threshold 1e-16) of e1 and
+      again of the pinned e0; the oracle runs the first iterations of e1 on
+      the host, and the GPU's values after the same number of iterations
+      are compared with it.
+
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
 vertices reached) / wall time.  Kernel figures come from the library's
@@ -179,6 +187,86 @@ def bc(args):
     print(json.dumps(out), flush=True)
 
 
+# PageRank: algorithmic bytes of one iteration, per visible in-arc (source
+# id 4 + its contribution 8) and per live vertex (rank read and write 16,
+# contribution write 8, out-degree 4, CSR offset 4)
+PR_BYTES_PER_ARC, PR_BYTES_PER_VERTEX = 12, 32
+
+
+def pagerank(args):
+    import torch
+    from oracle import Oracle
+    from paper_2109_09527_amd import dg, synth
+    t0 = time.time()
+    wl = synth.update_batches(scale=args.scale, n_batches=1, seed=0)
+    gr = wl.graph
+    say(f"generated R-MAT {args.scale}: V={gr.n} m={gr.m} in {time.time() - t0:.1f}s")
+    g = dg.Graph(gr.n, w_max=255, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    e0 = g.acquire()
+    g.apply(dg.ops_to_device(wl.batches[0]), torch.empty(len(wl.batches[0]), dtype=torch.uint8, device="cuda"))
+    e1 = g.epoch
+    runs = []
+    for ep in (e1, e0):
+        nv, na = g.stats(ep)
+        g.pagerank(ep)   # warm-up: sizes the scratch
+        torch.cuda.synchronize()
+        times = []
+        for rep in range(args.reps):
+            g.profile(True)
+            g.profile_read(reset=True)
+            t = time.perf_counter()
+            pr, it, ch = g.pagerank(ep)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            prof = g.profile_read(reset=True).get("pagerank", {})
+            g.profile(False)
+        t_med = sorted(times)[len(times) // 2]
+        # the few queued iterations after the stop return at once; their time stays in
+        per_iter_ms = prof["total_ms"] / max(1, it)
+        algo = PR_BYTES_PER_ARC * na + PR_BYTES_PER_VERTEX * nv
+        gbs = algo / (per_iter_ms / 1e3) / 1e9
+        runs.append({
+            "epoch": ep, "live_vertices": nv, "arcs": na, "iterations": it, "last_change": ch,
+            "seconds": round(t_med, 5), "iteration_ms": round(per_iter_ms, 4),
+            "build_and_host_ms": round(t_med * 1e3 - per_iter_ms * it, 3),
+            "arc_iterations_per_s": round(na * it / t_med / 1e9, 3),
+            "roofline": {"bound": "hbm", "kernel": "pagerank iteration (k_pr_pull + k_pr_apply)",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_iteration": algo},
+        })
+        say("pagerank", runs[-1])
+    out = {
+        "workload": f"R-MAT scale {args.scale} directed, {gr.m} loaded edges, then one batch of "
+                    f"{len(wl.batches[0])} ops; snapshot PageRank d=0.85 threshold 1e-16 (FP64, synchronous)",
+        "runs": runs,
+    }
+    if args.copy_mib > 0:
+        # a plain device copy of known size, to calibrate HBM byte counters
+        a = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+    if args.cpu_iters <= 0:
+        print(json.dumps(out), flush=True)
+        return
+    # the oracle on the same state (e1) for a bounded number of iterations
+    o = Oracle(gr.n, w_max=255)
+    o.apply(load)
+    o.apply(wl.batches[0])
+    k = args.cpu_iters
+    t = time.perf_counter()
+    _, want, it_o, _ = o.pagerank(max_iters=k)
+    t_cpu = time.perf_counter() - t
+    got, it_g, _ = g.pagerank(e1, max_iters=k)
+    err = float(np.max(np.abs(got.cpu().numpy() - want)))
+    na = runs[0]["arcs"]
+    out["cpu_baseline"] = {"value": round(na * it_o / t_cpu / 1e9, 4), "unit": "G arc-iterations/s", "cores": 1,
+                           "kind": "oracle", "sample": f"first {k} iterations on the latest snapshot"}
+    out["gpu_vs_oracle_after_k_iterations"] = {"k": k, "max_abs_diff": err, "iterations": [it_g, it_o]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -190,11 +278,16 @@ def main():
     b.add_argument("--scale", type=int, default=18)
     b.add_argument("--sources", type=int, default=256)
     b.add_argument("--group", type=int, default=16)
+    c = sub.add_parser("pagerank")
+    c.add_argument("--scale", type=int, default=20)
+    c.add_argument("--reps", type=int, default=3)
+    c.add_argument("--cpu-iters", type=int, default=20, help="oracle iterations timed on the host (0: none)")
+    c.add_argument("--copy-mib", type=int, default=0, help="one plain device copy of this many MiB at the end")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    (batched if args.what == "batched" else bc)(args)
+    {"batched": batched, "bc": bc, "pagerank": pagerank}[args.what](args)
 
 
 if __name__ == "__main__":
