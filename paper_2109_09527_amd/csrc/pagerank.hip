@@ -30,9 +30,10 @@
 //
 // Convergence stays on the device: iteration i's largest change goes into
 // slot i of a ring (atomicMax on the bit pattern, which orders non-negative
-// doubles), and both kernels of iteration i return at once when iteration
-// i - 1 stored a change within the threshold (a skipped iteration leaves 0
-// in its slot, so the skip carries on).  The host queues iterations in
+// doubles, spread over PR_STRIPES words so that the workgroups do not queue
+// on one address), and both kernels of iteration i return at once when
+// iteration i - 1 stored a change within the threshold (a skipped iteration
+// leaves 0 in its slot, so the skip carries on).  The host queues iterations in
 // batches, reads the batch's changes back once, and sizes the next batch
 // from the observed contraction.
 #include <algorithm>
@@ -49,6 +50,8 @@ constexpr uint32_t PR_THREADS = 256;
 constexpr uint32_t PR_TILE = 4;          // buckets per build tile (4 x 16 slots = one wave step)
 constexpr uint32_t PR_PIECE = 256;       // in-arcs per pull piece (16 lanes x 16)
 constexpr uint32_t PR_RING = 128;        // slots of the per-iteration change ring
+constexpr uint32_t PR_STRIPES = 64;      // words of a slot (one per lane): workgroup b raises word b mod 64
+constexpr uint32_t PR_APPLY_GRID = 1024; // apply workgroups at most (16 per word)
 constexpr uint32_t PR_BATCH_MAX = 48;    // iterations queued per host check (<= PR_RING / 2)
 
 __device__ inline uint32_t pr_lane() { return __lane_id(); }
@@ -137,7 +140,8 @@ __global__ void k_pr_piece_list(const uint32_t* pfirst, uint32_t V, uint32_t* pi
 }
 
 __global__ void k_pr_clear_ring(unsigned long long* ring, uint32_t first, uint32_t n) {
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) ring[(first + i) % PR_RING] = 0ull;
+  for (uint32_t i = threadIdx.x; i < n * PR_STRIPES; i += blockDim.x)
+    ring[((first + i / PR_STRIPES) % PR_RING) * PR_STRIPES + i % PR_STRIPES] = 0ull;
 }
 
 __global__ void k_pr_outdeg(const uint32_t* csr, uint64_t m, uint32_t* q) {
@@ -155,9 +159,18 @@ __global__ void k_pr_init(const uint8_t* live, const uint32_t* q, uint32_t V, do
   }
 }
 
+// Wave-uniform: did iteration it - 1 stop the loop?  Every wave reads the
+// slot's words (lane l the word l) and takes their maximum.
 __device__ inline bool pr_skip(const unsigned long long* ring, uint32_t it, unsigned long long thr_bits) {
-  return it > 0 && __hip_atomic_load(&ring[(it - 1) % PR_RING], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
-                       thr_bits;
+  if (it == 0) return false;
+  unsigned long long x = __hip_atomic_load(&ring[((it - 1) % PR_RING) * PR_STRIPES + pr_lane()],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x <= thr_bits;
 }
 
 struct PrIter {
@@ -225,7 +238,9 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_apply(PrIter a, uint32_t it) 
     double m = wmax[0];
     for (uint32_t w = 1; w < PR_THREADS / 64; w++) m = fmax(m, wmax[w]);
     const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
-    if (bits) atomicMax(&a.ring[it % PR_RING], bits);
+    unsigned long long* w = &a.ring[(it % PR_RING) * PR_STRIPES + blockIdx.x % PR_STRIPES];
+    // the word only grows, so a read that is not above bits is safe to skip on
+    if (bits > __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(w, bits);
   }
 }
 
@@ -267,7 +282,9 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
   if (n_live == 0 || max_iters == 0 || !(threshold < 1.0)) return DG_OK;
 
   // liveness at e, from the host's history
-  if (!s.host && (he = hipHostMalloc(&s.host, std::max<size_t>(V, PR_RING * 8) + 64, hipHostMallocDefault)) != hipSuccess)
+  if (!s.host &&
+      (he = hipHostMalloc(&s.host, std::max<size_t>(V, PR_RING * PR_STRIPES * 8) + 64, hipHostMallocDefault)) !=
+          hipSuccess)
     return fail_hip(he, "host buffer");
   if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "sync");
   uint8_t* hl = static_cast<uint8_t*>(s.host);
@@ -284,7 +301,7 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
   if ((he = ensure(s.ntiles, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.dsnap, V * 8ull + 64)) != hipSuccess || (he = ensure(s.tile_v, T_max * 4)) != hipSuccess ||
       (he = ensure(s.tcount, (T_max + 1) * 4)) != hipSuccess || (he = ensure(s.off, (V + 1ull) * 4)) != hipSuccess ||
       (he = ensure(s.pfirst, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.q, V * 4ull + 64)) != hipSuccess ||
-      (he = ensure(s.contrib, V * 8ull + 64)) != hipSuccess || (he = ensure(s.ring, PR_RING * 8)) != hipSuccess)
+      (he = ensure(s.contrib, V * 8ull + 64)) != hipSuccess || (he = ensure(s.ring, PR_RING * PR_STRIPES * 8)) != hipSuccess)
     return fail_hip(he, "alloc");
   uint32_t* tfirst = s.ntiles.as<uint32_t>();
   k_pr_ntiles<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(desc, s.live.as<uint8_t>(), V, s.dsnap.as<uint64_t>(), tfirst);
@@ -324,7 +341,7 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
   if (m) k_pr_outdeg<<<pr_grid(m, 256), 256, 0, st>>>(s.csr.as<uint32_t>(), m, s.q.as<uint32_t>());
   k_pr_init<<<pr_grid(V, 256), 256, 0, st>>>(s.live.as<uint8_t>(), s.q.as<uint32_t>(), V, 1.0 / (double)n_live, pr,
                                              s.contrib.as<double>());
-  k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * 2, 0u);
+  k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * PR_STRIPES * 2, 0u);
   if ((he = hipMemcpyAsync(s.host, pfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (he = hipStreamSynchronize(st)) != hipSuccess)
     return fail_hip(he, "piece total");
@@ -339,9 +356,10 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
            s.q.as<uint32_t>(), s.contrib.as<double>(), s.part.as<double>(), pr,
            reinterpret_cast<unsigned long long*>(s.ring.p), V, P, (1.0 - damping) / (double)n_live, damping, 0};
   std::memcpy(&a.thr_bits, &threshold, 8);
-  const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, 4096);
+  const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, PR_APPLY_GRID);
   unsigned long long* ring = a.ring;
-  double* hc = static_cast<double*>(s.host);
+  unsigned long long* hw = static_cast<unsigned long long*>(s.host);
+  double hc[PR_BATCH_MAX];
   uint32_t queued = 0, batch = 8;
   double prev_change = 0.0;
   for (;;) {
@@ -355,10 +373,17 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
     }
     if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "launch");
     const uint32_t r0 = queued % PR_RING, n1 = std::min(b, PR_RING - r0);
-    if ((he = hipMemcpyAsync(hc, ring + r0, n1 * 8ull, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (b > n1 && (he = hipMemcpyAsync(hc + n1, ring, (b - n1) * 8ull, hipMemcpyDeviceToHost, st)) != hipSuccess))
+    const size_t row = PR_STRIPES * 8ull;
+    if ((he = hipMemcpyAsync(hw, ring + r0 * PR_STRIPES, n1 * row, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (b > n1 && (he = hipMemcpyAsync(hw + n1 * PR_STRIPES, ring, (b - n1) * row, hipMemcpyDeviceToHost, st)) !=
+                       hipSuccess))
       return fail_hip(he, "read back");
     if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "sync");
+    for (uint32_t i = 0; i < b; i++) {
+      unsigned long long x = 0;
+      for (uint32_t k = 0; k < PR_STRIPES; k++) x = std::max(x, hw[i * PR_STRIPES + k]);
+      std::memcpy(&hc[i], &x, 8);
+    }
     for (uint32_t i = 0; i < b; i++) {
       const double c = hc[i];
       if (c <= threshold) {
