@@ -85,6 +85,7 @@ struct QueryScratch {
 // Snapshot PageRank: the in-CSR of one call and its iteration state.
 struct PrScratch {
   DevBuf live, dsnap, ntiles, tile_v, tcount, off, pfirst, piece_v, csr, q, contrib, part, ring, scan;
+  DevBuf sort, key0, key1, val0, val1, rank, q_r, live_r, off_r, csr_r, pr_r;   // rank order
   void* host = nullptr;   // pinned: liveness mask upload, totals and changes read back
 };
 

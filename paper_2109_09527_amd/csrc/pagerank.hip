@@ -16,8 +16,15 @@
 //           consecutive, vertices in id order)
 //   fill    each tile's visible sources, bucket by bucket, slot by slot
 //   q(v)    out-degrees counted from the CSR's sources (integer atomics)
+//   ranks   vertices renumbered by decreasing out-degree (stable radix sort,
+//           ties by id); the CSR's rows are moved to rank order and its
+//           sources mapped to ranks
 // An iteration then streams 4 bytes per arc plus one random 8-byte read of
-// the source's contribution, instead of re-reading buckets and stamps.
+// the source's contribution, instead of re-reading buckets and stamps.  In
+// rank order the most-read contributions (those of the largest
+// out-degrees) share a short prefix of the array that stays in L2, and the
+// per-vertex arrays are read and written in order; the ranks are mapped
+// back to ids once, after the last iteration.
 //
 // Per iteration, two kernels:
 //   k_pr_pull   one 16-lane group per piece (at most PR_PIECE consecutive
@@ -125,13 +132,10 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_fill(Pool p, const uint64_t* 
   }
 }
 
-// CSR start of each vertex and its pieces (entry V stays 0 for the scan).
-__global__ void k_pr_offsets(const uint32_t* tfirst, const uint32_t* toff, uint32_t V, uint32_t* off,
-                             uint32_t* npieces) {
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= V; u += gridDim.x * blockDim.x) {
+// CSR start of each vertex (id order).
+__global__ void k_pr_offsets(const uint32_t* tfirst, const uint32_t* toff, uint32_t V, uint32_t* off) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= V; u += gridDim.x * blockDim.x)
     off[u] = toff[tfirst[u]];
-    npieces[u] = u < V ? (toff[tfirst[u + 1]] - toff[tfirst[u]] + PR_PIECE - 1) / PR_PIECE : 0;
-  }
 }
 
 __global__ void k_pr_piece_list(const uint32_t* pfirst, uint32_t V, uint32_t* piece_v) {
@@ -147,6 +151,58 @@ __global__ void k_pr_clear_ring(unsigned long long* ring, uint32_t first, uint32
 __global__ void k_pr_outdeg(const uint32_t* csr, uint64_t m, uint32_t* q) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
     atomicAdd(&q[csr[i]], 1u);
+}
+
+// Sort keys: decreasing out-degree, ties kept in id order by the stable sort.
+__global__ void k_pr_sort_keys(const uint32_t* q, uint32_t V, uint64_t* key, uint32_t* val) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x) {
+    key[u] = 0xFFFFFFFFull - q[u];
+    val[u] = u;
+  }
+}
+
+// Rank-order copies of the per-vertex data; deg_r and np_r leave entry V at
+// 0 for their scans (into CSR offsets and first pieces).
+__global__ void k_pr_rank(const uint32_t* order, const uint32_t* q, const uint8_t* live, const uint32_t* off,
+                          uint32_t V, uint32_t* rank, uint32_t* q_r, uint8_t* live_r, uint32_t* deg_r,
+                          uint32_t* np_r) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= V; r += gridDim.x * blockDim.x) {
+    if (r == V) {
+      deg_r[V] = 0;
+      np_r[V] = 0;
+      continue;
+    }
+    const uint32_t u = order[r];
+    rank[u] = r;
+    q_r[r] = q[u];
+    live_r[r] = live[u];
+    const uint32_t d = off[u + 1] - off[u];
+    deg_r[r] = d;
+    np_r[r] = (d + PR_PIECE - 1) / PR_PIECE;
+  }
+}
+
+// Row moves: one 16-lane group per rank-order piece copies its arcs from the
+// id-order CSR, mapping sources to ranks.
+__global__ __launch_bounds__(PR_THREADS) void k_pr_permute(const uint32_t* order, const uint32_t* rank,
+                                                           const uint32_t* off, const uint32_t* csr,
+                                                           const uint32_t* off_r, const uint32_t* pfirst,
+                                                           const uint32_t* piece_v, uint32_t P, uint32_t* csr_r) {
+  const uint32_t j = threadIdx.x & 15;
+  const uint32_t ng = gridDim.x * (PR_THREADS / 16);
+  for (uint32_t p = blockIdx.x * (PR_THREADS / 16) + (threadIdx.x >> 4); p < P; p += ng) {
+    const uint32_t r = piece_v[p];
+    const uint32_t k = (p - pfirst[r]) * PR_PIECE;
+    const uint32_t n = min(PR_PIECE, off_r[r + 1] - off_r[r] - k);
+    const uint32_t from = off[order[r]] + k, to = off_r[r] + k;
+    for (uint32_t i = j; i < n; i += 16) csr_r[to + i] = rank[csr[from + i]];
+  }
+}
+
+// Ranks back to ids.
+__global__ void k_pr_unrank(const uint32_t* rank, const double* pr_r, uint32_t V, double* pr) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < V; u += gridDim.x * blockDim.x)
+    pr[u] = pr_r[rank[u]];
 }
 
 // pr = 1/n and contrib = pr/q on live vertices, 0 elsewhere.
@@ -251,7 +307,9 @@ static uint32_t pr_grid(uint64_t units, uint32_t per_block, uint32_t cap = 8192)
 void free_pr_scratch(PrScratch& s) {
   release(s.live); release(s.dsnap); release(s.ntiles); release(s.tile_v); release(s.tcount); release(s.off);
   release(s.pfirst); release(s.piece_v); release(s.csr); release(s.q); release(s.contrib);
-  release(s.part); release(s.ring); release(s.scan);
+  release(s.part); release(s.ring); release(s.scan); release(s.sort); release(s.key0); release(s.key1);
+  release(s.val0); release(s.val1); release(s.rank); release(s.q_r); release(s.live_r); release(s.off_r);
+  release(s.csr_r); release(s.pr_r);
   if (s.host) (void)hipHostFree(s.host);
   s.host = nullptr;
 }
@@ -333,15 +391,31 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
     return fail_hip(he, "alloc");
   if (T) k_pr_fill<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e, tc,
                                                                     s.csr.as<uint32_t>());
-  uint32_t* pfirst = s.pfirst.as<uint32_t>();
-  k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, s.off.as<uint32_t>(), pfirst);
-  if ((he = pr_scan(s, pfirst, V + 1ull, st)) != hipSuccess) return fail_hip(he, "piece scan");
-  k_pr_piece_list<<<pr_grid(V, 256), 256, 0, st>>>(pfirst, V, s.piece_v.as<uint32_t>());
+  uint32_t* off = s.off.as<uint32_t>();
+  k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, off);
   k_pr_fill_u32<<<pr_grid(V, 256), 256, 0, st>>>(s.q.as<uint32_t>(), V, 0u);
   if (m) k_pr_outdeg<<<pr_grid(m, 256), 256, 0, st>>>(s.csr.as<uint32_t>(), m, s.q.as<uint32_t>());
-  k_pr_init<<<pr_grid(V, 256), 256, 0, st>>>(s.live.as<uint8_t>(), s.q.as<uint32_t>(), V, 1.0 / (double)n_live, pr,
-                                             s.contrib.as<double>());
-  k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * PR_STRIPES * 2, 0u);
+
+  // rank order: decreasing out-degree
+  if ((he = ensure(s.key0, V * 8ull + 64)) != hipSuccess || (he = ensure(s.key1, V * 8ull + 64)) != hipSuccess ||
+      (he = ensure(s.val0, V * 4ull + 64)) != hipSuccess || (he = ensure(s.val1, V * 4ull + 64)) != hipSuccess ||
+      (he = ensure(s.sort, sort_scratch_words(V) * 4 + 64)) != hipSuccess ||
+      (he = ensure(s.rank, V * 4ull + 64)) != hipSuccess || (he = ensure(s.q_r, V * 4ull + 64)) != hipSuccess ||
+      (he = ensure(s.live_r, V + 64ull)) != hipSuccess || (he = ensure(s.off_r, (V + 1ull) * 4)) != hipSuccess ||
+      (he = ensure(s.csr_r, (uint64_t)m * 4 + 64)) != hipSuccess || (he = ensure(s.pr_r, V * 8ull + 64)) != hipSuccess)
+    return fail_hip(he, "alloc");
+  k_pr_sort_keys<<<pr_grid(V, 256), 256, 0, st>>>(s.q.as<uint32_t>(), V, s.key0.as<uint64_t>(), s.val0.as<uint32_t>());
+  const bool alt = radix_sort_pairs(s.key0.as<uint64_t>(), s.val0.as<uint32_t>(), s.key1.as<uint64_t>(),
+                                    s.val1.as<uint32_t>(), V, 32, s.sort.as<uint32_t>(), st);
+  const uint32_t* order = alt ? s.val1.as<uint32_t>() : s.val0.as<uint32_t>();
+  uint32_t* pfirst = s.pfirst.as<uint32_t>();
+  uint32_t* off_r = s.off_r.as<uint32_t>();
+  k_pr_rank<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(order, s.q.as<uint32_t>(), s.live.as<uint8_t>(), off, V,
+                                                    s.rank.as<uint32_t>(), s.q_r.as<uint32_t>(),
+                                                    s.live_r.as<uint8_t>(), off_r, pfirst);
+  if ((he = pr_scan(s, off_r, V + 1ull, st)) != hipSuccess) return fail_hip(he, "offset scan");
+  if ((he = pr_scan(s, pfirst, V + 1ull, st)) != hipSuccess) return fail_hip(he, "piece scan");
+  k_pr_piece_list<<<pr_grid(V, 256), 256, 0, st>>>(pfirst, V, s.piece_v.as<uint32_t>());
   if ((he = hipMemcpyAsync(s.host, pfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (he = hipStreamSynchronize(st)) != hipSuccess)
     return fail_hip(he, "piece total");
@@ -351,9 +425,17 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
     g->err = "pagerank: piece count exceeds its bound";
     return DG_E_HIP;
   }
+  if (P)
+    k_pr_permute<<<pr_grid(P, PR_THREADS / 16, 16384), PR_THREADS, 0, st>>>(
+        order, s.rank.as<uint32_t>(), off, s.csr.as<uint32_t>(), off_r, pfirst, s.piece_v.as<uint32_t>(), P,
+        s.csr_r.as<uint32_t>());
+  double* pr_r = s.pr_r.as<double>();
+  k_pr_init<<<pr_grid(V, 256), 256, 0, st>>>(s.live_r.as<uint8_t>(), s.q_r.as<uint32_t>(), V, 1.0 / (double)n_live,
+                                             pr_r, s.contrib.as<double>());
+  k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * PR_STRIPES * 2, 0u);
 
-  PrIter a{s.csr.as<uint32_t>(), s.off.as<uint32_t>(), pfirst, s.piece_v.as<uint32_t>(), s.live.as<uint8_t>(),
-           s.q.as<uint32_t>(), s.contrib.as<double>(), s.part.as<double>(), pr,
+  PrIter a{s.csr_r.as<uint32_t>(), off_r, pfirst, s.piece_v.as<uint32_t>(), s.live_r.as<uint8_t>(),
+           s.q_r.as<uint32_t>(), s.contrib.as<double>(), s.part.as<double>(), pr_r,
            reinterpret_cast<unsigned long long*>(s.ring.p), V, P, (1.0 - damping) / (double)n_live, damping, 0};
   std::memcpy(&a.thr_bits, &threshold, 8);
   const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, PR_APPLY_GRID);
@@ -390,16 +472,17 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
         *iters = queued + i + 1;
         *last_change = c;
         prof_arcs(g, KID_PAGERANK, (uint64_t)m * (i + 1));
-        return DG_OK;
+        break;
       }
     }
+    if (*iters) break;
     prof_arcs(g, KID_PAGERANK, (uint64_t)m * b);
     queued += b;
     const double last = hc[b - 1];
     if (queued >= max_iters) {
       *iters = queued;
       *last_change = last;
-      return DG_OK;
+      break;
     }
     // iterations left at the observed contraction, plus one
     const double r = b >= 2 && hc[b - 2] > 0 ? last / hc[b - 2] : (prev_change > 0 ? last / prev_change : 0.9);
@@ -411,6 +494,9 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
     }
     batch = want;
   }
+  k_pr_unrank<<<pr_grid(V, 256), 256, 0, st>>>(s.rank.as<uint32_t>(), pr_r, V, pr);
+  if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "unrank");
+  return DG_OK;
 }
 
 }  // namespace dg
