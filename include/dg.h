@@ -148,6 +148,21 @@ dg_status dg_pagerank(dg_graph* g, dg_epoch e, double damping, double threshold,
                       uint32_t* iterations, double* last_change, void* stream);
 
 /*
+ * The No-Sync PageRank of the same paper (Alg. 3, thread-level convergence):
+ * the same Eq. (1) with no barrier between iterations.  Workgroups own
+ * disjoint vertex ranges, update their ranks in place from whatever values
+ * the others last stored, and each keeps sweeping while the largest change
+ * any workgroup last published exceeds `threshold`, or until it has swept
+ * max_iters times.  The result differs from run to run; at the stop it lies
+ * within the convergence tolerance of the synchronous result.
+ * sweeps (host, optional): the most sweeps any workgroup ran.
+ * last_change (host, optional): the largest published change at the end.
+ * Arguments and errors as for dg_pagerank.
+ */
+dg_status dg_pagerank_nosync(dg_graph* g, dg_epoch e, double damping, double threshold, uint32_t max_iters,
+                             double* pr, uint32_t* sweeps, double* last_change, void* stream);
+
+/*
  * Many queries in one persistent launch.  Each query names its kind, epoch
  * and source(s) and a caller-owned device output (int32[v_capacity] for BFS
  * and SSSP, double[v_capacity] for BC).  per_query (host, nq entries)

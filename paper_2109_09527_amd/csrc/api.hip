@@ -580,8 +580,8 @@ dg_status dg_bc(dg_graph* g, dg_epoch want, const uint32_t* srcs, uint32_t k, do
   return note_query(g, bc_dev(g, e, S.data(), k, bc, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
-dg_status dg_pagerank(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters, double* pr,
-                      uint32_t* iterations, double* last_change, void* stream) {
+static dg_status pagerank_call(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters,
+                               double* pr, uint32_t* iterations, double* last_change, void* stream, bool nosync) {
   if (!g || !pr) return DG_E_INVALID_ARG;
   if (!is_device_ptr(pr)) return fail(g, DG_E_INVALID_ARG, "pr must be device memory");
   if (!(damping >= 0.0 && damping < 1.0)) return fail(g, DG_E_INVALID_ARG, "damping must lie in [0, 1)");
@@ -592,10 +592,20 @@ dg_status dg_pagerank(dg_graph* g, dg_epoch want, double damping, double thresho
   if (st != DG_OK) return st;
   uint32_t it = 0;
   double ch = 0.0;
-  st = pagerank_dev(g, e, damping, threshold, max_iters, pr, &it, &ch, static_cast<hipStream_t>(stream));
+  st = pagerank_dev(g, e, damping, threshold, max_iters, pr, &it, &ch, static_cast<hipStream_t>(stream), nosync);
   if (iterations) *iterations = it;
   if (last_change) *last_change = ch;
   return note_query(g, st, stream);
+}
+
+dg_status dg_pagerank(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters, double* pr,
+                      uint32_t* iterations, double* last_change, void* stream) {
+  return pagerank_call(g, want, damping, threshold, max_iters, pr, iterations, last_change, stream, false);
+}
+
+dg_status dg_pagerank_nosync(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters,
+                             double* pr, uint32_t* sweeps, double* last_change, void* stream) {
+  return pagerank_call(g, want, damping, threshold, max_iters, pr, sweeps, last_change, stream, true);
 }
 
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
@@ -629,7 +639,7 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
 dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
-                                         "batch_sssp",   "batch_bc",     "pagerank"};
+                                         "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

@@ -86,6 +86,7 @@ struct QueryScratch {
 struct PrScratch {
   DevBuf live, dsnap, ntiles, tile_v, tcount, off, pfirst, piece_v, csr, q, contrib, part, ring, scan;
   DevBuf sort, key0, key1, val0, val1, rank, q_r, live_r, off_r, csr_r, pr_r;   // rank order
+  DevBuf pb, vb, werr, sweeps;   // No-Sync: workgroup ranges, published changes, sweep counts
   void* host = nullptr;   // pinned: liveness mask upload, totals and changes read back
 };
 
@@ -102,6 +103,7 @@ enum KernelId {
   KID_BATCH_SSSP,
   KID_BATCH_BC,
   KID_PAGERANK,     // one PageRank iteration (pull and apply)
+  KID_PAGERANK_NOSYNC,  // one No-Sync PageRank launch
   KID_COUNT
 };
 struct Prof {
@@ -188,7 +190,7 @@ void free_query_scratch(QueryScratch& q);
 
 // pagerank.hip
 dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
-                       uint32_t* iters, double* last_change, hipStream_t s);
+                       uint32_t* iters, double* last_change, hipStream_t s, bool nosync);
 void free_pr_scratch(PrScratch& s);
 
 // batch.hip

@@ -43,9 +43,22 @@
 // leaves 0 in its slot, so the skip carries on).  The host queues iterations in
 // batches, reads the batch's changes back once, and sizes the next batch
 // from the observed contraction.
+//
+// The No-Sync variant (Alg. 3) drops the barrier between iterations: one
+// launch of co-resident workgroups, each owning a contiguous run of pieces
+// (balanced by arcs) and the vertices whose first piece it owns.  A
+// workgroup sweeps its pieces, then finishes its vertices in place, reading
+// whatever contributions and piece sums the other workgroups last stored
+// (coherent agent-scope loads and stores, so values cross the XCDs' L2s),
+// then publishes its largest change and reads everyone's.  It sweeps again
+// while the largest published change exceeds the threshold, at most
+// max_iters times.  No workgroup waits for another, so every workgroup ends
+// after at most max_iters sweeps whether or not all are resident.  Results
+// vary from run to run within the convergence tolerance.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "dg_host.h"
 
@@ -300,6 +313,152 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_apply(PrIter a, uint32_t it) 
   }
 }
 
+// ------------------------------------------------------------- No-Sync
+
+// Work ranges: workgroup w owns pieces [pb[w], pb[w + 1]), split evenly by
+// arcs + PR_PIECE_COST per piece, and vertices [vb[w], vb[w + 1]), those
+// whose first piece (pfirst, rank order) lies in its range; the last
+// workgroup also takes the vertices with no piece at the end.
+constexpr uint64_t PR_PIECE_COST = 32;
+
+__device__ inline uint64_t pr_piece_weight(const uint32_t* off, const uint32_t* pfirst, const uint32_t* piece_v,
+                                           uint32_t P, uint32_t m, uint32_t p) {
+  if (p >= P) return (uint64_t)m + PR_PIECE_COST * P;
+  const uint32_t u = piece_v[p];
+  return (uint64_t)off[u] + (uint64_t)(p - pfirst[u]) * PR_PIECE + PR_PIECE_COST * p;
+}
+
+__global__ void k_pr_async_bounds(const uint32_t* off, const uint32_t* pfirst, const uint32_t* piece_v, uint32_t P,
+                                  uint32_t m, uint32_t V, uint32_t G, uint32_t* pb, uint32_t* vb) {
+  const uint64_t W = (uint64_t)m + PR_PIECE_COST * P;
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w <= G; w += gridDim.x * blockDim.x) {
+    uint32_t p = P, u = V;
+    if (w == 0) {
+      p = 0;
+      u = 0;
+    } else if (w < G) {
+      const uint64_t target = W * w / G;
+      uint32_t lo = 0, hi = P;   // first p with weight >= target
+      while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (pr_piece_weight(off, pfirst, piece_v, P, m, mid) >= target) hi = mid;
+        else lo = mid + 1;
+      }
+      p = lo;
+      uint32_t a = 0, b = V;     // first u with pfirst[u] >= p
+      while (a < b) {
+        const uint32_t mid = a + (b - a) / 2;
+        if (pfirst[mid] >= p) b = mid;
+        else a = mid + 1;
+      }
+      u = a;
+    }
+    pb[w] = p;
+    vb[w] = u;
+  }
+}
+
+struct PrAsync {
+  const uint32_t* csr;
+  const uint32_t* off;
+  const uint32_t* pfirst;
+  const uint32_t* piece_v;
+  const uint8_t* live;
+  const uint32_t* q;
+  const uint32_t* pb;
+  const uint32_t* vb;
+  double* contrib;
+  double* part;
+  double* pr;
+  unsigned long long* err;   // per workgroup: its last published change (bit pattern)
+  uint32_t* sweeps;          // per workgroup: sweeps run
+  uint32_t G, max_iters;
+  double base, d;
+  unsigned long long thr_bits;
+};
+
+__device__ inline double pr_ld(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void pr_st(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(PR_THREADS) void k_pr_nosync(PrAsync a) {
+  __shared__ double wmax[PR_THREADS / 64];
+  __shared__ unsigned long long umax[PR_THREADS / 64];
+  __shared__ int stop;
+  const uint32_t w = blockIdx.x;
+  const uint32_t p0 = a.pb[w], p1 = a.pb[w + 1], r0 = a.vb[w], r1 = a.vb[w + 1];
+  const uint32_t j = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  uint32_t sweep = 0;
+  for (;;) {
+    // the workgroup's pieces (16-lane groups, group-uniform loop)
+    for (uint32_t p = p0 + grp; p < p1; p += PR_THREADS / 16) {
+      const uint32_t u = a.piece_v[p];
+      const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
+      const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
+      double s = 0.0;
+      for (uint32_t i0 = b + j; i0 < end; i0 += 64) {
+        uint32_t src[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) src[k] = i0 + 16 * k < end ? a.csr[i0 + 16 * k] : EMPTY;
+        double c[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) c[k] = src[k] != EMPTY ? pr_ld(&a.contrib[src[k]]) : 0.0;
+        s += (c[0] + c[1]) + (c[2] + c[3]);
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      if (j == 0) pr_st(&a.part[p], s);
+    }
+    __syncthreads();
+    // the workgroup's vertices, from the latest sums of their pieces
+    double ch = 0.0;
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += PR_THREADS) {
+      if (!a.live[r]) continue;
+      double s = 0.0;
+      for (uint32_t k = a.pfirst[r]; k < a.pfirst[r + 1]; k++) s += pr_ld(&a.part[k]);
+      const double x = a.base + a.d * s;
+      ch = fmax(ch, fabs(a.pr[r] - x));
+      a.pr[r] = x;
+      pr_st(&a.contrib[r], a.q[r] ? x / (double)a.q[r] : 0.0);
+    }
+    sweep++;
+    // publish this workgroup's change, then take the largest published one
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ch = fmax(ch, __shfl_xor(ch, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = ch;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = wmax[0];
+      for (uint32_t k = 1; k < PR_THREADS / 64; k++) m = fmax(m, wmax[k]);
+      __hip_atomic_store(&a.err[w], (unsigned long long)__double_as_longlong(m), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned long long mx = 0;
+    for (uint32_t t = threadIdx.x; t < a.G; t += PR_THREADS) {
+      const unsigned long long x = __hip_atomic_load(&a.err[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      mx = x > mx ? x : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63) == 0) umax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long m = umax[0];
+      for (uint32_t k = 1; k < PR_THREADS / 64; k++) m = umax[k] > m ? umax[k] : m;
+      stop = m <= a.thr_bits || sweep >= a.max_iters;
+    }
+    __syncthreads();
+    if (stop) break;
+  }
+  if (threadIdx.x == 0) a.sweeps[w] = sweep;
+}
+
 static uint32_t pr_grid(uint64_t units, uint32_t per_block, uint32_t cap = 8192) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((units + per_block - 1) / per_block, cap));
 }
@@ -309,7 +468,7 @@ void free_pr_scratch(PrScratch& s) {
   release(s.pfirst); release(s.piece_v); release(s.csr); release(s.q); release(s.contrib);
   release(s.part); release(s.ring); release(s.scan); release(s.sort); release(s.key0); release(s.key1);
   release(s.val0); release(s.val1); release(s.rank); release(s.q_r); release(s.live_r); release(s.off_r);
-  release(s.csr_r); release(s.pr_r);
+  release(s.csr_r); release(s.pr_r); release(s.pb); release(s.vb); release(s.werr); release(s.sweeps);
   if (s.host) (void)hipHostFree(s.host);
   s.host = nullptr;
 }
@@ -321,8 +480,21 @@ static hipError_t pr_scan(PrScratch& s, uint32_t* data, uint64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+static uint32_t pr_resident(const void* kernel) {
+  int per_cu = 0, cus = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, PR_THREADS, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  return (uint32_t)(per_cu * cus);
+}
+
+__global__ void k_pr_fill_u64(unsigned long long* p, uint32_t n, unsigned long long v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
 dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
-                       uint32_t* iters, double* last_change, hipStream_t st) {
+                       uint32_t* iters, double* last_change, hipStream_t st, bool nosync) {
   PrScratch& s = g->pr;
   const uint32_t V = g->cfg.v_capacity;
   *iters = 0;
@@ -439,6 +611,51 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
            reinterpret_cast<unsigned long long*>(s.ring.p), V, P, (1.0 - damping) / (double)n_live, damping, 0};
   std::memcpy(&a.thr_bits, &threshold, 8);
   const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, PR_APPLY_GRID);
+  if (nosync) {
+    // co-resident workgroups, about 64 pieces each at least
+    const uint32_t G = std::max<uint32_t>(1, std::min<uint32_t>(pr_resident((const void*)k_pr_nosync), (P + 63) / 64));
+    if ((he = ensure(s.pb, (G + 1ull) * 4)) != hipSuccess || (he = ensure(s.vb, (G + 1ull) * 4)) != hipSuccess ||
+        (he = ensure(s.werr, G * 8ull)) != hipSuccess || (he = ensure(s.sweeps, G * 4ull)) != hipSuccess)
+      return fail_hip(he, "alloc");
+    k_pr_async_bounds<<<pr_grid(G + 1ull, 256), 256, 0, st>>>(off_r, pfirst, s.piece_v.as<uint32_t>(), P, m, V, G,
+                                                              s.pb.as<uint32_t>(), s.vb.as<uint32_t>());
+    // piece sums of the starting values, so a vertex never reads an unset one
+    k_pr_pull<<<g_pull, PR_THREADS, 0, st>>>(a, 0);
+    // every workgroup's change starts at 1, as the loop's does
+    k_pr_fill_u64<<<pr_grid(G, 256), 256, 0, st>>>(s.werr.as<unsigned long long>(), G, 0x3FF0000000000000ull);
+    PrAsync x{a.csr, a.off, a.pfirst, a.piece_v, a.live, a.q, s.pb.as<uint32_t>(), s.vb.as<uint32_t>(), a.contrib,
+              a.part, pr_r, s.werr.as<unsigned long long>(), s.sweeps.as<uint32_t>(), G, max_iters, a.base, a.d,
+              a.thr_bits};
+    {
+      ProfScope ps(g, KID_PAGERANK_NOSYNC, st);
+      k_pr_nosync<<<G, PR_THREADS, 0, st>>>(x);
+    }
+    if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "nosync launch");
+    unsigned long long* hw = static_cast<unsigned long long*>(s.host);
+    std::vector<unsigned long long> errs(G);
+    std::vector<uint32_t> sw(G);
+    if ((he = hipMemcpyAsync(hw, s.werr.p, G * 8ull, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (he = hipStreamSynchronize(st)) != hipSuccess)
+      return fail_hip(he, "nosync read back");
+    std::memcpy(errs.data(), hw, G * 8ull);
+    if ((he = hipMemcpyAsync(hw, s.sweeps.p, G * 4ull, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (he = hipStreamSynchronize(st)) != hipSuccess)
+      return fail_hip(he, "nosync read back");
+    std::memcpy(sw.data(), hw, G * 4ull);
+    unsigned long long mx = 0;
+    uint64_t total = 0;
+    for (uint32_t w = 0; w < G; w++) {
+      mx = std::max(mx, errs[w]);
+      *iters = std::max(*iters, sw[w]);
+      total += sw[w];
+    }
+    std::memcpy(last_change, &mx, 8);
+    // arcs examined: every workgroup's share of the arcs times its sweeps, taken as the mean
+    prof_arcs(g, KID_PAGERANK_NOSYNC, (uint64_t)((double)m * (double)total / (double)G));
+    k_pr_unrank<<<pr_grid(V, 256), 256, 0, st>>>(s.rank.as<uint32_t>(), pr_r, V, pr);
+    if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "unrank");
+    return DG_OK;
+  }
   unsigned long long* ring = a.ring;
   unsigned long long* hw = static_cast<unsigned long long*>(s.host);
   double hc[PR_BATCH_MAX];

@@ -78,8 +78,9 @@ _sig("dg_compact", _i32, _P, _P)
 _sig("dg_bfs", _i32, _P, _u32, _u32, _P, _P)
 _sig("dg_sssp", _i32, _P, _u32, _u32, _P, _P)
 _sig("dg_bc", _i32, _P, _u32, _P, _u32, _P, _P)
-_sig("dg_pagerank", _i32, _P, _u32, ctypes.c_double, ctypes.c_double, _u32, _P, ctypes.POINTER(_u32),
-     ctypes.POINTER(ctypes.c_double), _P)
+for _n in ("dg_pagerank", "dg_pagerank_nosync"):
+    _sig(_n, _i32, _P, _u32, ctypes.c_double, ctypes.c_double, _u32, _P, ctypes.POINTER(_u32),
+         ctypes.POINTER(ctypes.c_double), _P)
 _sig("dg_query_batch", _i32, _P, _P, _u32, _P, _P)
 _sig("dg_get_tuning", _i32, _P, ctypes.POINTER(Tuning))
 _sig("dg_set_tuning", _i32, _P, ctypes.POINTER(Tuning))
@@ -244,18 +245,22 @@ class Graph:
         self._check(rc)
         return out
 
-    def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None):
-        """(status, pr tensor, iterations, last iteration's largest change)."""
+    def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
+                     nosync=False):
+        """(status, pr tensor, iterations, last iteration's largest change);
+        nosync: the barrier-free form (iterations = most sweeps of a workgroup)."""
         out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
         it = _u32()
         ch = ctypes.c_double()
-        rc = lib.dg_pagerank(self.h, epoch, float(damping), float(threshold), int(max_iters), _ptr(out),
-                             ctypes.byref(it), ctypes.byref(ch), _stream())
+        fn = lib.dg_pagerank_nosync if nosync else lib.dg_pagerank
+        rc = fn(self.h, epoch, float(damping), float(threshold), int(max_iters), _ptr(out), ctypes.byref(it),
+                ctypes.byref(ch), _stream())
         return rc, out, int(it.value), float(ch.value)
 
-    def pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None):
+    def pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
+                 nosync=False):
         """(pr tensor, iterations, last change); raises on a failed call."""
-        rc, out, it, ch = self.try_pagerank(epoch, damping, threshold, max_iters, out)
+        rc, out, it, ch = self.try_pagerank(epoch, damping, threshold, max_iters, out, nosync)
         self._check(rc)
         return out, it, ch
 

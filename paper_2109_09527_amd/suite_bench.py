@@ -22,7 +22,8 @@
       ops as e1.  Snapshot PageRank (d = 0.85, threshold 1e-16) of e1 and
       again of the pinned e0; the oracle runs the first iterations of e1 on
       the host, and the GPU's values after the same number of iterations
-      are compared with it.
+      are compared with it.  The No-Sync (barrier-free) form runs on e1 too,
+      compared with the synchronous ranks.
 
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
@@ -237,10 +238,30 @@ def pagerank(args):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_iteration": algo},
         })
         say("pagerank", runs[-1])
+    # No-Sync (barrier-free) form on e1, against the synchronous ranks
+    ref, it_ref, _ = g.pagerank(e1)
+    g.pagerank(e1, nosync=True)   # warm-up
+    torch.cuda.synchronize()
+    ns = []
+    for rep in range(args.reps):
+        g.profile(True)
+        g.profile_read(reset=True)
+        t = time.perf_counter()
+        pr, sweeps, ch = g.pagerank(e1, nosync=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        prof = g.profile_read(reset=True).get("pagerank_nosync", {})
+        g.profile(False)
+        d = (pr - ref).abs()
+        ns.append({"seconds": round(dt, 5), "kernel_ms": round(prof.get("total_ms", 0.0), 3),
+                   "most_sweeps": sweeps, "last_change": ch,
+                   "max_abs_diff_vs_synchronous": float(d.max()), "l1_diff_vs_synchronous": float(d.sum())})
+    say("pagerank nosync", ns)
     out = {
         "workload": f"R-MAT scale {args.scale} directed, {gr.m} loaded edges, then one batch of "
                     f"{len(wl.batches[0])} ops; snapshot PageRank d=0.85 threshold 1e-16 (FP64, synchronous)",
         "runs": runs,
+        "nosync": {"epoch": e1, "synchronous_iterations": it_ref, "runs": ns},
     }
     if args.copy_mib > 0:
         # a plain device copy of known size, to calibrate HBM byte counters

@@ -175,3 +175,70 @@ def test_degenerate_and_invalid(dg):
         assert rc == dg.E_INVALID_ARG, kw
     # vertex 3 is live and isolated: (1 - d)/n
     check(g, o, iters_exact=True)
+
+
+# ------------------------------------------------------------ No-Sync (Alg. 3)
+
+def check_nosync(g, o, epoch=None, **kw):
+    """No-Sync stops when every workgroup's last published change is within
+    the threshold; its ranks then meet the same tolerance against the
+    synchronous oracle's (Lemma 2 of the paper: identical within the
+    threshold at the stop)."""
+    _, want, it_o, _ = o.pagerank(**kw)
+    ep = g.epoch if epoch is None else epoch
+    got, sweeps, ch = g.pagerank(ep, nosync=True, **kw)
+    got = got.cpu().numpy()
+    thr = kw.get("threshold", 1e-16)
+    err = np.abs(got - want)
+    bad = err > max(ATOL, 12 * thr) + RTOL * np.abs(want)
+    assert not bad.any(), (np.nonzero(bad)[0][:8], got[bad][:8], want[bad][:8], err.max())
+    assert ch <= thr and sweeps >= 1, (sweeps, ch)
+    return got, sweeps, float(np.abs(got - want).sum())
+
+
+def test_nosync_closed_forms_and_cap(dg):
+    say("nosync cycle")
+    g, o = build(dg, 50, np.arange(50), (np.arange(50) + 1) % 50)
+    got, sweeps, _ = check_nosync(g, o)
+    assert np.all(np.abs(got - 1 / 50) <= 1e-18)
+    say("nosync single arc")
+    g, o = build(dg, 2, [0], [1])
+    check_nosync(g, o)
+    say("nosync sweep cap")
+    gr = synth.rmat_graph(12, 16, 255, seed=13)
+    g, o = build(dg, gr.n, gr.u, gr.v)
+    _, sweeps, ch = g.pagerank(nosync=True, max_iters=3)
+    assert sweeps <= 3 and ch > 1e-16
+    say("nosync empty")
+    g = dg.Graph(16, w_max=255)
+    pr, sweeps, _ = g.pagerank(nosync=True)
+    assert sweeps == 0 and not pr.cpu().numpy().any()
+    rc, _, _, _ = g.try_pagerank(damping=1.5, nosync=True)
+    assert rc == dg.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_nosync_rmat_matches_synchronous(dg, undirected):
+    """R-MAT scale 14 with a hub-heavy in-degree spread, after a batch of
+    removals: No-Sync equals the synchronous oracle within the tolerance,
+    on the latest and on a pinned earlier epoch, run after run."""
+    gr = synth.rmat_graph(14, 16, 255, seed=17, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    e1 = g.acquire()
+    want1 = o.pagerank()[1]
+    rng = synth.rng_for(17, 5)
+    pick = rng.choice(gr.m, 3000, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    for rep in range(2):
+        say("nosync rmat14", undirected, rep)
+        _, sweeps, l1 = check_nosync(g, o)
+        print("[nosync] sweeps", sweeps, "L1 vs synchronous", l1, flush=True)
+    got1, _, ch = g.pagerank(e1, nosync=True)
+    err = np.abs(got1.cpu().numpy() - want1)
+    assert np.all(err <= ATOL + RTOL * np.abs(want1)), err.max()
+    g.release(e1)
