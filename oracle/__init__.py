@@ -66,6 +66,8 @@ def _load():
     lib.orc_out_degree.argtypes = [P, u32]
     lib.orc_pagerank.restype = ctypes.c_int
     lib.orc_pagerank.argtypes = [P, ctypes.c_double, ctypes.c_double, u32, P, P, P]
+    lib.orc_pagerank_perforated.restype = ctypes.c_int
+    lib.orc_pagerank_perforated.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
     return lib
 
@@ -137,13 +139,18 @@ class Oracle:
     def out_degree(self, v: int) -> int:
         return int(self.lib.orc_out_degree(self.h, int(v)))
 
-    def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000):
-        """(status, pr[n] float64, iterations, last iteration's largest change)."""
+    def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000, freeze_below=None):
+        """(status, pr[n] float64, iterations, last iteration's largest change);
+        freeze_below: loop perforation (Alg. 5) below that change."""
         out = np.zeros(self.n, dtype=np.float64)
         it = ctypes.c_uint32()
         ch = ctypes.c_double()
-        rc = self.lib.orc_pagerank(self.h, float(damping), float(threshold), int(max_iters), _ptr(out),
-                                   ctypes.byref(it), ctypes.byref(ch))
+        if freeze_below is None:
+            rc = self.lib.orc_pagerank(self.h, float(damping), float(threshold), int(max_iters), _ptr(out),
+                                       ctypes.byref(it), ctypes.byref(ch))
+        else:
+            rc = self.lib.orc_pagerank_perforated(self.h, float(damping), float(threshold), float(freeze_below),
+                                                  int(max_iters), _ptr(out), ctypes.byref(it), ctypes.byref(ch))
         return rc, out, it.value, ch.value
 
     def edges(self):

@@ -507,7 +507,16 @@ int orc_bc(const orc_graph* g, const uint32_t* S, uint32_t k, double* bc) {
  * whose arcs are stored in both directions. */
 int orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t max_iters, double* pr,
                  uint32_t* iters, double* last_change) {
-  if (!(damping >= 0.0 && damping < 1.0) || !(threshold >= 0.0)) return ORC_E_INVALID_ARG;
+  return orc_pagerank_perforated(g, damping, threshold, 0.0, max_iters, pr, iters, last_change);
+}
+
+/* Loop perforation (Alg. 5): a vertex whose change in an iteration is
+ * nonzero and below freeze_below is not recomputed in later iterations and
+ * keeps its value (its change counts as 0).  freeze_below = 0 freezes
+ * nothing, which is the plain iteration above. */
+int orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
+                            uint32_t max_iters, double* pr, uint32_t* iters, double* last_change) {
+  if (!(damping >= 0.0 && damping < 1.0) || !(threshold >= 0.0) || !(freeze_below >= 0.0)) return ORC_E_INVALID_ARG;
   const uint32_t n = g->n;
   uint64_t live = 0;
   for (uint32_t u = 0; u < n; u++) live += g->alive[u] ? 1 : 0;
@@ -516,7 +525,12 @@ int orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t 
   *last_change = 0.0;
   if (live == 0) return ORC_OK;
   double* prev = (double*)malloc((size_t)n * sizeof(double));
-  if (!prev) return ORC_E_OOM;
+  uint8_t* frozen = (uint8_t*)calloc(n ? n : 1, 1);
+  if (!prev || !frozen) {
+    free(prev);
+    free(frozen);
+    return ORC_E_OOM;
+  }
   for (uint32_t u = 0; u < n; u++) prev[u] = g->alive[u] ? 1.0 / (double)live : 0.0;
   const double base = (1.0 - damping) / (double)live;
   double err = 1.0;
@@ -525,6 +539,10 @@ int orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t 
     err = 0.0;
     for (uint32_t u = 0; u < n; u++) {
       if (!g->alive[u]) continue;
+      if (frozen[u]) {
+        pr[u] = prev[u];
+        continue;
+      }
       double x = base;
       if (g->undirected) {
         const arc_list* l = &g->out[u];
@@ -542,11 +560,13 @@ int orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t 
       pr[u] = x;
       const double c = fabs(prev[u] - x);
       if (c > err) err = c;
+      if (c != 0.0 && c < freeze_below) frozen[u] = 1;
     }
     for (uint32_t u = 0; u < n; u++) prev[u] = pr[u];
     it++;
   }
   free(prev);
+  free(frozen);
   *iters = it;
   *last_change = err;
   return ORC_OK;

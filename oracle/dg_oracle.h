@@ -14,7 +14,8 @@
  *     queries named BFS / SSSP / BC in the same preamble, on the current
  *     state;
  *   - PageRank of the current state, Eq. (1) iterated as the synchronous
- *     Barrier baseline (Alg. 1) in FP64.
+ *     Barrier baseline (Alg. 1) in FP64, optionally with the loop
+ *     perforation of Alg. 5.
  *
  * Error codes are the integer values of the C boundary's call status.
  */
@@ -62,6 +63,11 @@ uint32_t   orc_out_degree(const orc_graph* g, uint32_t v);
  * threshold. */
 int        orc_pagerank(const orc_graph* g, double damping, double threshold, uint32_t max_iters, double* pr,
                         uint32_t* iters, double* last_change);
+/* The same with loop perforation (Alg. 5): a live vertex whose change in an
+ * iteration is nonzero and below freeze_below keeps its value and is not
+ * recomputed afterwards.  freeze_below = 0 is orc_pagerank. */
+int        orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
+                                   uint32_t max_iters, double* pr, uint32_t* iters, double* last_change);
 
 #ifdef __cplusplus
 }

@@ -164,3 +164,43 @@ def test_empty_and_invalid():
     assert o.pagerank(damping=1.0)[0] == E_INVALID_ARG
     assert o.pagerank(damping=-0.1)[0] == E_INVALID_ARG
     assert o.pagerank(threshold=-1.0)[0] == E_INVALID_ARG
+
+
+# ------------------------------------------------------- loop perforation (Alg. 5)
+
+def test_perforation_hand_traced():
+    # d = 1/2 on 0 -> 1, 1 -> 2, 2 -> 1, and an isolated 3 (n = 4): every
+    # value is a binary fraction, so the trace is exact.  From 1/4 each:
+    #   iteration 1: (1/8, 3/8, 1/4, 1/8)
+    #   iteration 2: (1/8, 5/16, 5/16, 1/8); vertices 1 and 2 change by 1/16
+    #   iteration 3 without perforation: (1/8, 11/32, 9/32, 1/8), on towards
+    #   the fixed point (1/8, 1/3, 7/24, 1/8).
+    # With freeze_below = 0.07 both freeze after iteration 2 (change 1/16),
+    # iteration 3 changes nothing, and the loop stops there.
+    o = load(4, [0, 1, 2], [1, 2, 1])
+    rc, pr, it, ch = o.pagerank(damping=0.5, freeze_below=0.07)
+    assert rc == OK and it == 3 and ch == 0.0
+    assert pr.tolist() == [0.125, 0.3125, 0.3125, 0.125]
+    _, pr2, it2, _ = o.pagerank(damping=0.5, max_iters=3)
+    assert pr2.tolist() == [0.125, 11 / 32, 9 / 32, 0.125]
+    _, pr3, _, _ = o.pagerank(damping=0.5)
+    assert np.max(np.abs(pr3 - [0.125, 1 / 3, 7 / 24, 0.125])) <= 1e-15
+
+
+def test_perforation_at_the_papers_scale_stays_exact():
+    """With the paper's 1e-21 against a 1e-16 threshold, perforation takes
+    no more iterations and moves no rank measurably: the ranks still equal
+    the dense solve, and freeze_below = 0 is the plain iteration exactly."""
+    for seed, und in ((1, False), (2, True)):
+        rng = synth.rng_for(seed, 91)
+        n = 40
+        us = rng.integers(0, n, 120)
+        vs = rng.integers(0, n, 120)
+        keep = us != vs
+        o = load(n, us[keep], vs[keep], und)
+        _, a, ia, _ = o.pagerank(freeze_below=1e-21)
+        _, b, ib, _ = o.pagerank()
+        _, c, ic, _ = o.pagerank(freeze_below=0.0)
+        assert ia <= ib and ic == ib and np.array_equal(b, c)
+        assert np.max(np.abs(a - dense_fixed_point(o))) <= 1e-13
+    assert load(3, [0], [1]).pagerank(freeze_below=-1.0)[0] == E_INVALID_ARG
