@@ -163,6 +163,24 @@ dg_status dg_pagerank_nosync(dg_graph* g, dg_epoch e, double damping, double thr
                              double* pr, uint32_t* sweeps, double* last_change, void* stream);
 
 /*
+ * Either form with the loop perforation of the paper's Alg. 5: a live vertex
+ * whose change in an iteration (or sweep) is nonzero and below freeze_below
+ * keeps its value and is not recomputed afterwards (the paper uses 1e-21
+ * with threshold 1e-16).  freeze_below = 0 freezes nothing: the calls above.
+ * nosync = 0 runs dg_pagerank's form, 1 dg_pagerank_nosync's.  DG_E_INVALID_ARG
+ * also for a negative or NaN freeze_below, or opts NULL.
+ */
+typedef struct {
+  double damping;
+  double threshold;
+  double freeze_below;
+  uint32_t max_iters;
+  int nosync;
+} dg_pagerank_opts;
+dg_status dg_pagerank_ex(dg_graph* g, dg_epoch e, const dg_pagerank_opts* opts, double* pr, uint32_t* iterations,
+                         double* last_change, void* stream);
+
+/*
  * Many queries in one persistent launch.  Each query names its kind, epoch
  * and source(s) and a caller-owned device output (int32[v_capacity] for BFS
  * and SSSP, double[v_capacity] for BC).  per_query (host, nq entries)

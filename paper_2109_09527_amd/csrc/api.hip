@@ -580,19 +580,21 @@ dg_status dg_bc(dg_graph* g, dg_epoch want, const uint32_t* srcs, uint32_t k, do
   return note_query(g, bc_dev(g, e, S.data(), k, bc, static_cast<hipStream_t>(stream), g->qs), stream);
 }
 
-static dg_status pagerank_call(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters,
-                               double* pr, uint32_t* iterations, double* last_change, void* stream, bool nosync) {
+static dg_status pagerank_call(dg_graph* g, dg_epoch want, const dg_pagerank_opts& o, double* pr,
+                               uint32_t* iterations, double* last_change, void* stream) {
   if (!g || !pr) return DG_E_INVALID_ARG;
   if (!is_device_ptr(pr)) return fail(g, DG_E_INVALID_ARG, "pr must be device memory");
-  if (!(damping >= 0.0 && damping < 1.0)) return fail(g, DG_E_INVALID_ARG, "damping must lie in [0, 1)");
-  if (!(threshold >= 0.0)) return fail(g, DG_E_INVALID_ARG, "threshold must be non-negative");
+  if (!(o.damping >= 0.0 && o.damping < 1.0)) return fail(g, DG_E_INVALID_ARG, "damping must lie in [0, 1)");
+  if (!(o.threshold >= 0.0)) return fail(g, DG_E_INVALID_ARG, "threshold must be non-negative");
+  if (!(o.freeze_below >= 0.0)) return fail(g, DG_E_INVALID_ARG, "freeze_below must be non-negative");
   std::lock_guard<std::mutex> lk(g->mu);
   uint32_t e;
   dg_status st = resolve_epoch(g, want, &e);
   if (st != DG_OK) return st;
   uint32_t it = 0;
   double ch = 0.0;
-  st = pagerank_dev(g, e, damping, threshold, max_iters, pr, &it, &ch, static_cast<hipStream_t>(stream), nosync);
+  st = pagerank_dev(g, e, o.damping, o.threshold, o.freeze_below, o.max_iters, pr, &it, &ch,
+                    static_cast<hipStream_t>(stream), o.nosync != 0);
   if (iterations) *iterations = it;
   if (last_change) *last_change = ch;
   return note_query(g, st, stream);
@@ -600,12 +602,20 @@ static dg_status pagerank_call(dg_graph* g, dg_epoch want, double damping, doubl
 
 dg_status dg_pagerank(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters, double* pr,
                       uint32_t* iterations, double* last_change, void* stream) {
-  return pagerank_call(g, want, damping, threshold, max_iters, pr, iterations, last_change, stream, false);
+  const dg_pagerank_opts o{damping, threshold, 0.0, max_iters, 0};
+  return pagerank_call(g, want, o, pr, iterations, last_change, stream);
 }
 
 dg_status dg_pagerank_nosync(dg_graph* g, dg_epoch want, double damping, double threshold, uint32_t max_iters,
                              double* pr, uint32_t* sweeps, double* last_change, void* stream) {
-  return pagerank_call(g, want, damping, threshold, max_iters, pr, sweeps, last_change, stream, true);
+  const dg_pagerank_opts o{damping, threshold, 0.0, max_iters, 1};
+  return pagerank_call(g, want, o, pr, sweeps, last_change, stream);
+}
+
+dg_status dg_pagerank_ex(dg_graph* g, dg_epoch want, const dg_pagerank_opts* opts, double* pr, uint32_t* iterations,
+                         double* last_change, void* stream) {
+  if (!opts) return DG_E_INVALID_ARG;
+  return pagerank_call(g, want, *opts, pr, iterations, last_change, stream);
 }
 
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {

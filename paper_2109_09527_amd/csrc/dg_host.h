@@ -87,6 +87,7 @@ struct PrScratch {
   DevBuf live, dsnap, ntiles, tile_v, tcount, off, pfirst, piece_v, csr, q, contrib, part, ring, scan;
   DevBuf sort, key0, key1, val0, val1, rank, q_r, live_r, off_r, csr_r, pr_r;   // rank order
   DevBuf pb, vb, werr, sweeps;   // No-Sync: workgroup ranges, published changes, sweep counts
+  DevBuf frozen;                  // loop perforation: vertices no longer recomputed (rank order)
   void* host = nullptr;   // pinned: liveness mask upload, totals and changes read back
 };
 
@@ -189,8 +190,9 @@ dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hi
 void free_query_scratch(QueryScratch& q);
 
 // pagerank.hip
-dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
-                       uint32_t* iters, double* last_change, hipStream_t s, bool nosync);
+dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, double freeze_below,
+                       uint32_t max_iters, double* pr, uint32_t* iters, double* last_change, hipStream_t s,
+                       bool nosync);
 void free_pr_scratch(PrScratch& s);
 
 // batch.hip

@@ -55,6 +55,10 @@
 // max_iters times.  No workgroup waits for another, so every workgroup ends
 // after at most max_iters sweeps whether or not all are resident.  Results
 // vary from run to run within the convergence tolerance.
+//
+// Loop perforation (Alg. 5), in either form: a vertex whose change is
+// nonzero and below freeze_below is frozen, keeps its value and is skipped
+// from then on (its pieces too); 0 freezes nothing.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -253,8 +257,9 @@ struct PrIter {
   double* part;
   double* pr;
   unsigned long long* ring;
+  uint8_t* frozen;       // perforation: vertices no longer recomputed
   uint32_t V, P;
-  double base, d;
+  double base, d, freeze_below;
   unsigned long long thr_bits;
 };
 
@@ -265,8 +270,8 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_pull(PrIter a, uint32_t it) {
   for (uint32_t p0 = blockIdx.x * (PR_THREADS / 16); p0 < a.P; p0 += ng) {
     const uint32_t p = p0 + (threadIdx.x >> 4);   // group-uniform
     double s = 0.0;
-    if (p < a.P) {
-      const uint32_t u = a.piece_v[p];
+    const uint32_t u = p < a.P ? a.piece_v[p] : 0;
+    if (p < a.P && !a.frozen[u]) {
       const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
       const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
       // four arcs per lane in flight: indices first, then their contributions
@@ -291,13 +296,15 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_apply(PrIter a, uint32_t it) 
   __shared__ double wmax[PR_THREADS / 64];
   double ch = 0.0;
   for (uint32_t u = blockIdx.x * PR_THREADS + threadIdx.x; u < a.V; u += gridDim.x * PR_THREADS) {
-    if (!a.live[u]) continue;
+    if (!a.live[u] || a.frozen[u]) continue;
     double s = 0.0;
     for (uint32_t k = a.pfirst[u]; k < a.pfirst[u + 1]; k++) s += a.part[k];
     const double x = a.base + a.d * s;
-    ch = fmax(ch, fabs(a.pr[u] - x));
+    const double c = fabs(a.pr[u] - x);
+    ch = fmax(ch, c);
     a.pr[u] = x;
     a.contrib[u] = a.q[u] ? x / (double)a.q[u] : 0.0;
+    if (c != 0.0 && c < a.freeze_below) a.frozen[u] = 1;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) ch = fmax(ch, __shfl_xor(ch, o, 64));
@@ -372,8 +379,9 @@ struct PrAsync {
   double* pr;
   unsigned long long* err;   // per workgroup: its last published change (bit pattern)
   uint32_t* sweeps;          // per workgroup: sweeps run
+  uint8_t* frozen;
   uint32_t G, max_iters;
-  double base, d;
+  double base, d, freeze_below;
   unsigned long long thr_bits;
 };
 
@@ -396,6 +404,7 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_nosync(PrAsync a) {
     // the workgroup's pieces (16-lane groups, group-uniform loop)
     for (uint32_t p = p0 + grp; p < p1; p += PR_THREADS / 16) {
       const uint32_t u = a.piece_v[p];
+      if (a.frozen[u]) continue;   // group-uniform
       const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
       const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
       double s = 0.0;
@@ -416,13 +425,15 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_nosync(PrAsync a) {
     // the workgroup's vertices, from the latest sums of their pieces
     double ch = 0.0;
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += PR_THREADS) {
-      if (!a.live[r]) continue;
+      if (!a.live[r] || a.frozen[r]) continue;
       double s = 0.0;
       for (uint32_t k = a.pfirst[r]; k < a.pfirst[r + 1]; k++) s += pr_ld(&a.part[k]);
       const double x = a.base + a.d * s;
-      ch = fmax(ch, fabs(a.pr[r] - x));
+      const double c = fabs(a.pr[r] - x);
+      ch = fmax(ch, c);
       a.pr[r] = x;
       pr_st(&a.contrib[r], a.q[r] ? x / (double)a.q[r] : 0.0);
+      if (c != 0.0 && c < a.freeze_below) a.frozen[r] = 1;
     }
     sweep++;
     // publish this workgroup's change, then take the largest published one
@@ -468,7 +479,7 @@ void free_pr_scratch(PrScratch& s) {
   release(s.pfirst); release(s.piece_v); release(s.csr); release(s.q); release(s.contrib);
   release(s.part); release(s.ring); release(s.scan); release(s.sort); release(s.key0); release(s.key1);
   release(s.val0); release(s.val1); release(s.rank); release(s.q_r); release(s.live_r); release(s.off_r);
-  release(s.csr_r); release(s.pr_r); release(s.pb); release(s.vb); release(s.werr); release(s.sweeps);
+  release(s.csr_r); release(s.pr_r); release(s.pb); release(s.vb); release(s.werr); release(s.sweeps); release(s.frozen);
   if (s.host) (void)hipHostFree(s.host);
   s.host = nullptr;
 }
@@ -493,8 +504,9 @@ __global__ void k_pr_fill_u64(unsigned long long* p, uint32_t n, unsigned long l
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, uint32_t max_iters, double* pr,
-                       uint32_t* iters, double* last_change, hipStream_t st, bool nosync) {
+dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold, double freeze_below,
+                       uint32_t max_iters, double* pr, uint32_t* iters, double* last_change, hipStream_t st,
+                       bool nosync) {
   PrScratch& s = g->pr;
   const uint32_t V = g->cfg.v_capacity;
   *iters = 0;
@@ -605,10 +617,26 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
   k_pr_init<<<pr_grid(V, 256), 256, 0, st>>>(s.live_r.as<uint8_t>(), s.q_r.as<uint32_t>(), V, 1.0 / (double)n_live,
                                              pr_r, s.contrib.as<double>());
   k_pr_fill_u32<<<1, 256, 0, st>>>(reinterpret_cast<uint32_t*>(s.ring.p), PR_RING * PR_STRIPES * 2, 0u);
+  if ((he = ensure(s.frozen, V + 64ull)) != hipSuccess) return fail_hip(he, "alloc");
+  k_pr_fill_u32<<<pr_grid(V / 4 + 1, 256), 256, 0, st>>>(s.frozen.as<uint32_t>(), V / 4 + 1, 0u);
 
-  PrIter a{s.csr_r.as<uint32_t>(), off_r, pfirst, s.piece_v.as<uint32_t>(), s.live_r.as<uint8_t>(),
-           s.q_r.as<uint32_t>(), s.contrib.as<double>(), s.part.as<double>(), pr_r,
-           reinterpret_cast<unsigned long long*>(s.ring.p), V, P, (1.0 - damping) / (double)n_live, damping, 0};
+  PrIter a{s.csr_r.as<uint32_t>(),
+           off_r,
+           pfirst,
+           s.piece_v.as<uint32_t>(),
+           s.live_r.as<uint8_t>(),
+           s.q_r.as<uint32_t>(),
+           s.contrib.as<double>(),
+           s.part.as<double>(),
+           pr_r,
+           reinterpret_cast<unsigned long long*>(s.ring.p),
+           s.frozen.as<uint8_t>(),
+           V,
+           P,
+           (1.0 - damping) / (double)n_live,
+           damping,
+           freeze_below,
+           0};
   std::memcpy(&a.thr_bits, &threshold, 8);
   const uint32_t g_pull = pr_grid(P, PR_THREADS / 16, 16384), g_apply = pr_grid(V, PR_THREADS, PR_APPLY_GRID);
   if (nosync) {
@@ -623,8 +651,25 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
     k_pr_pull<<<g_pull, PR_THREADS, 0, st>>>(a, 0);
     // every workgroup's change starts at 1, as the loop's does
     k_pr_fill_u64<<<pr_grid(G, 256), 256, 0, st>>>(s.werr.as<unsigned long long>(), G, 0x3FF0000000000000ull);
-    PrAsync x{a.csr, a.off, a.pfirst, a.piece_v, a.live, a.q, s.pb.as<uint32_t>(), s.vb.as<uint32_t>(), a.contrib,
-              a.part, pr_r, s.werr.as<unsigned long long>(), s.sweeps.as<uint32_t>(), G, max_iters, a.base, a.d,
+    PrAsync x{a.csr,
+              a.off,
+              a.pfirst,
+              a.piece_v,
+              a.live,
+              a.q,
+              s.pb.as<uint32_t>(),
+              s.vb.as<uint32_t>(),
+              a.contrib,
+              a.part,
+              pr_r,
+              s.werr.as<unsigned long long>(),
+              s.sweeps.as<uint32_t>(),
+              a.frozen,
+              G,
+              max_iters,
+              a.base,
+              a.d,
+              a.freeze_below,
               a.thr_bits};
     {
       ProfScope ps(g, KID_PAGERANK_NOSYNC, st);

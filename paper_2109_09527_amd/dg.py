@@ -81,6 +81,15 @@ _sig("dg_bc", _i32, _P, _u32, _P, _u32, _P, _P)
 for _n in ("dg_pagerank", "dg_pagerank_nosync"):
     _sig(_n, _i32, _P, _u32, ctypes.c_double, ctypes.c_double, _u32, _P, ctypes.POINTER(_u32),
          ctypes.POINTER(ctypes.c_double), _P)
+
+
+class PageRankOpts(ctypes.Structure):
+    _fields_ = [("damping", ctypes.c_double), ("threshold", ctypes.c_double), ("freeze_below", ctypes.c_double),
+                ("max_iters", _u32), ("nosync", ctypes.c_int)]
+
+
+_sig("dg_pagerank_ex", _i32, _P, _u32, ctypes.POINTER(PageRankOpts), _P, ctypes.POINTER(_u32),
+     ctypes.POINTER(ctypes.c_double), _P)
 _sig("dg_query_batch", _i32, _P, _P, _u32, _P, _P)
 _sig("dg_get_tuning", _i32, _P, ctypes.POINTER(Tuning))
 _sig("dg_set_tuning", _i32, _P, ctypes.POINTER(Tuning))
@@ -246,21 +255,27 @@ class Graph:
         return out
 
     def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
-                     nosync=False):
+                     nosync=False, freeze_below=None):
         """(status, pr tensor, iterations, last iteration's largest change);
-        nosync: the barrier-free form (iterations = most sweeps of a workgroup)."""
+        nosync: the barrier-free form (iterations = most sweeps of a workgroup);
+        freeze_below: loop perforation (dg_pagerank_ex)."""
         out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
         it = _u32()
         ch = ctypes.c_double()
-        fn = lib.dg_pagerank_nosync if nosync else lib.dg_pagerank
-        rc = fn(self.h, epoch, float(damping), float(threshold), int(max_iters), _ptr(out), ctypes.byref(it),
-                ctypes.byref(ch), _stream())
+        if freeze_below is None:
+            fn = lib.dg_pagerank_nosync if nosync else lib.dg_pagerank
+            rc = fn(self.h, epoch, float(damping), float(threshold), int(max_iters), _ptr(out), ctypes.byref(it),
+                    ctypes.byref(ch), _stream())
+        else:
+            o = PageRankOpts(float(damping), float(threshold), float(freeze_below), int(max_iters), int(nosync))
+            rc = lib.dg_pagerank_ex(self.h, epoch, ctypes.byref(o), _ptr(out), ctypes.byref(it), ctypes.byref(ch),
+                                    _stream())
         return rc, out, int(it.value), float(ch.value)
 
     def pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
-                 nosync=False):
+                 nosync=False, freeze_below=None):
         """(pr tensor, iterations, last change); raises on a failed call."""
-        rc, out, it, ch = self.try_pagerank(epoch, damping, threshold, max_iters, out, nosync)
+        rc, out, it, ch = self.try_pagerank(epoch, damping, threshold, max_iters, out, nosync, freeze_below)
         self._check(rc)
         return out, it, ch
 

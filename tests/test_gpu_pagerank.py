@@ -242,3 +242,38 @@ def test_nosync_rmat_matches_synchronous(dg, undirected):
     err = np.abs(got1.cpu().numpy() - want1)
     assert np.all(err <= ATOL + RTOL * np.abs(want1)), err.max()
     g.release(e1)
+
+
+# ------------------------------------------------------- loop perforation (Alg. 5)
+
+def test_perforation_hand_traced_exact(dg):
+    """The oracle's hand-traced case (d = 1/2, binary fractions throughout):
+    with freeze_below = 0.07 vertices 1 and 2 freeze after iteration 2 and
+    the loop stops after iteration 3, in both forms, bit for bit."""
+    g, o = build(dg, 4, [0, 1, 2], [1, 2, 1])
+    for nosync in (False, True):
+        say("perforation hand trace", nosync)
+        pr, it, ch = g.pagerank(damping=0.5, freeze_below=0.07, nosync=nosync)
+        assert pr.cpu().numpy().tolist() == [0.125, 0.3125, 0.3125, 0.125], nosync
+        assert it == 3 and ch == 0.0
+    rc, _, _, _ = g.try_pagerank(freeze_below=-1.0)
+    assert rc == dg.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_perforation_papers_setting(dg, undirected):
+    """freeze_below = 1e-21 with threshold 1e-16 (the paper's setting) on
+    R-MAT 13: both forms stay within the tolerance of the oracle's
+    perforated ranks, and the synchronous form takes about as many
+    iterations."""
+    gr = synth.rmat_graph(13, 16, 255, seed=19, undirected=undirected)
+    g, o = build(dg, gr.n, gr.u, gr.v, undirected)
+    say("perforation 1e-21", undirected)
+    _, want, it_o, _ = o.pagerank(freeze_below=1e-21)
+    for nosync in (False, True):
+        got, it, ch = g.pagerank(freeze_below=1e-21, nosync=nosync)
+        err = np.abs(got.cpu().numpy() - want)
+        assert np.all(err <= ATOL + RTOL * np.abs(want)), (nosync, err.max())
+        assert ch <= 1e-16
+        if not nosync:
+            assert abs(it - it_o) <= max(3, it_o // 10), (it, it_o)
