@@ -66,6 +66,8 @@ def _load():
     lib.orc_out_degree.argtypes = [P, u32]
     lib.orc_pagerank.restype = ctypes.c_int
     lib.orc_pagerank.argtypes = [P, ctypes.c_double, ctypes.c_double, u32, P, P, P]
+    lib.orc_scc.restype = ctypes.c_int
+    lib.orc_scc.argtypes = [P, P]
     lib.orc_pagerank_perforated.restype = ctypes.c_int
     lib.orc_pagerank_perforated.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
@@ -138,6 +140,13 @@ class Oracle:
 
     def out_degree(self, v: int) -> int:
         return int(self.lib.orc_out_degree(self.h, int(v)))
+
+    def scc(self):
+        """(status, comp[n] int32): smallest id of each live vertex's strongly
+        connected component, -1 for vertices that are not live."""
+        out = np.empty(self.n, dtype=np.int32)
+        rc = self.lib.orc_scc(self.h, _ptr(out))
+        return rc, out
 
     def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000, freeze_below=None):
         """(status, pr[n] float64, iterations, last iteration's largest change);

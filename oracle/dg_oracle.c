@@ -571,3 +571,79 @@ int orc_pagerank_perforated(const orc_graph* g, double damping, double threshold
   *last_change = err;
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ SCC */
+
+/* Strongly connected components of the current state (the GetSCC query
+ * named in the preamble; textbook semantics): comp[v] = the smallest id in
+ * v's component for live v, -1 for others.  Tarjan's algorithm (1972) with
+ * an explicit stack; components are found in reverse topological order and
+ * relabelled by their smallest member.  An undirected graph's components
+ * are its connected components. */
+int orc_scc(const orc_graph* g, int32_t* comp) {
+  const uint32_t n = g->n;
+  int64_t* index = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int64_t* low = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  uint8_t* on = (uint8_t*)calloc(n ? n : 1, 1);
+  uint32_t* st = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  uint32_t* cs_v = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  uint32_t* cs_j = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  if (!index || !low || !on || !st || !cs_v || !cs_j) {
+    free(index); free(low); free(on); free(st); free(cs_v); free(cs_j);
+    return ORC_E_OOM;
+  }
+  for (uint32_t v = 0; v < n; v++) {
+    index[v] = -1;
+    comp[v] = -1;
+  }
+  int64_t next = 0;
+  uint32_t sp = 0;
+  for (uint32_t r = 0; r < n; r++) {
+    if (!g->alive[r] || index[r] >= 0) continue;
+    uint32_t cp = 0;   /* call stack of (vertex, next arc) */
+    cs_v[cp] = r;
+    cs_j[cp] = 0;
+    cp++;
+    index[r] = low[r] = next++;
+    st[sp++] = r;
+    on[r] = 1;
+    while (cp) {
+      const uint32_t v = cs_v[cp - 1];
+      const arc_list* l = &g->out[v];
+      if (cs_j[cp - 1] < l->n) {
+        const uint32_t w = l->a[cs_j[cp - 1]++].v;
+        if (index[w] < 0) {
+          index[w] = low[w] = next++;
+          st[sp++] = w;
+          on[w] = 1;
+          cs_v[cp] = w;
+          cs_j[cp] = 0;
+          cp++;
+        } else if (on[w] && index[w] < low[v]) {
+          low[v] = index[w];
+        }
+        continue;
+      }
+      /* v is done: close its component if it is a root, then return */
+      if (low[v] == index[v]) {
+        uint32_t k = sp, m = v;
+        do {
+          k--;
+          if (st[k] < m) m = st[k];
+        } while (st[k] != v);
+        for (uint32_t i = k; i < sp; i++) {
+          on[st[i]] = 0;
+          comp[st[i]] = (int32_t)m;
+        }
+        sp = k;
+      }
+      cp--;
+      if (cp) {
+        const uint32_t u = cs_v[cp - 1];
+        if (low[v] < low[u]) low[u] = low[v];
+      }
+    }
+  }
+  free(index); free(low); free(on); free(st); free(cs_v); free(cs_j);
+  return ORC_OK;
+}

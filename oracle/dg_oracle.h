@@ -15,7 +15,8 @@
  *     state;
  *   - PageRank of the current state, Eq. (1) iterated as the synchronous
  *     Barrier baseline (Alg. 1) in FP64, optionally with the loop
- *     perforation of Alg. 5.
+ *     perforation of Alg. 5;
+ *   - strongly connected components (GetSCC in the preamble), by Tarjan.
  *
  * Error codes are the integer values of the C boundary's call status.
  */
@@ -66,6 +67,9 @@ int        orc_pagerank(const orc_graph* g, double damping, double threshold, ui
 /* The same with loop perforation (Alg. 5): a live vertex whose change in an
  * iteration is nonzero and below freeze_below keeps its value and is not
  * recomputed afterwards.  freeze_below = 0 is orc_pagerank. */
+/* Strongly connected components (Tarjan): comp[v] = smallest id in v's
+ * component for live v, -1 otherwise. */
+int        orc_scc(const orc_graph* g, int32_t* comp);
 int        orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
                                    uint32_t max_iters, double* pr, uint32_t* iters, double* last_change);
 

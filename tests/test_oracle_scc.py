@@ -1,0 +1,109 @@
+"""Pins for the oracle's strongly connected components (CPU only).
+
+Definition: u and v share a component iff each reaches the other (or
+u = v); the label is the smallest id in the component, -1 for vertices that
+are not live.  Checked against that definition through Warshall's closure
+on random graphs with dead vertices, against closed forms, and on a larger
+R-MAT graph against invariants: labels are fixed points at or below their
+vertex, and the condensation has no cycle.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, OK
+from paper_2109_09527_amd import synth
+from paper_2109_09527_amd.synth import REMV, make_ops
+from tests.brute import warshall
+
+
+def load(n, us, vs, undirected=False):
+    o = Oracle(n, undirected=undirected, w_max=255)
+    us = np.asarray(us, dtype=np.uint32)
+    vs = np.asarray(vs, dtype=np.uint32)
+    g = synth.Graph(n, us, vs, np.ones(len(us), np.int32), undirected)
+    rc, _ = o.apply(synth.load_ops(g))
+    assert rc == OK
+    return o
+
+
+def brute_labels(o):
+    n = o.n
+    live = np.array([o.alive(v) for v in range(n)])
+    A = np.zeros((n, n), dtype=bool)
+    us, vs, _ = o.edges()
+    A[us, vs] = True
+    if o.undirected:
+        A[vs, us] = True
+    R = warshall(A) | np.eye(n, dtype=bool)
+    same = R & R.T
+    lab = np.full(n, -1, dtype=np.int32)
+    for v in range(n):
+        if live[v]:
+            lab[v] = int(np.nonzero(same[v] & live)[0].min())
+    return lab
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_matches_reachability_definition(seed, undirected):
+    rng = synth.rng_for(seed, 92)
+    n = 40
+    m = 60 if undirected else 90
+    us = rng.integers(0, n, m)
+    vs = rng.integers(0, n, m)
+    keep = us != vs
+    o = load(n, us[keep], vs[keep], undirected)
+    dead = rng.choice(n, 4, replace=False)
+    o.apply(make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead))))
+    rc, lab = o.scc()
+    assert rc == OK
+    assert np.array_equal(lab, brute_labels(o))
+
+
+def test_closed_forms():
+    n = 30
+    cyc = load(n, np.arange(n), (np.arange(n) + 1) % n)
+    assert np.all(cyc.scc()[1] == 0)
+    path = load(n, np.arange(n - 1), np.arange(1, n))
+    assert np.array_equal(path.scc()[1], np.arange(n))
+    # two 3-cycles {0,1,2} and {3,4,5} joined by 2 -> 3, and an isolated 6
+    two = load(7, [0, 1, 2, 3, 4, 5, 2], [1, 2, 0, 4, 5, 3, 3])
+    assert two.scc()[1].tolist() == [0, 0, 0, 3, 3, 3, 6]
+    # a reverse path has its largest id first: still singletons
+    rev = load(n, np.arange(1, n), np.arange(n - 1))
+    assert np.array_equal(rev.scc()[1], np.arange(n))
+    # undirected: connected components
+    und = load(6, [0, 3], [1, 4], undirected=True)
+    assert und.scc()[1].tolist() == [0, 0, 2, 3, 3, 5]
+
+
+def test_rmat_invariants():
+    gr = synth.rmat_graph(12, 8, 255, seed=6)
+    o = load(gr.n, gr.u, gr.v)
+    rc, lab = o.scc()
+    assert rc == OK
+    assert np.all(lab <= np.arange(gr.n)) and np.array_equal(lab[lab], lab)
+    # condensation: order the components so every cross arc goes forward
+    us, vs, _ = o.edges()
+    a, b = lab[us], lab[vs]
+    cross = a != b
+    comps = np.unique(lab)
+    idx = {c: i for i, c in enumerate(comps.tolist())}
+    indeg = np.zeros(len(comps), dtype=np.int64)
+    adj = [[] for _ in comps]
+    for x, y in set(zip(a[cross].tolist(), b[cross].tolist())):
+        adj[idx[x]].append(idx[y])
+        indeg[idx[y]] += 1
+    queue = [i for i in range(len(comps)) if indeg[i] == 0]
+    seen = 0
+    while queue:
+        i = queue.pop()
+        seen += 1
+        for j in adj[i]:
+            indeg[j] -= 1
+            if indeg[j] == 0:
+                queue.append(j)
+    assert seen == len(comps)   # acyclic
+    # the graph has one large component besides many singletons
+    sizes = np.bincount(lab)
+    assert sizes.max() > gr.n // 4
