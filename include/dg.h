@@ -127,6 +127,17 @@ dg_status dg_sssp(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* st
 dg_status dg_bc(dg_graph* g, dg_epoch e, const uint32_t* srcs, uint32_t k, double* bc, void* stream);
 
 /*
+ * Strongly connected components of the snapshot at epoch e (the GetSCC query
+ * named in the preamble of arXiv 2109.09527; textbook semantics): u and v
+ * share a component iff each reaches the other.  comp: device array of
+ * v_capacity int32, comp[v] = the smallest id in v's component for a vertex
+ * live at e, -1 otherwise (an undirected graph's components are its connected
+ * components).  n_components (host, optional): the number of components.
+ * The call returns after the last round's counts are read back.
+ */
+dg_status dg_scc(dg_graph* g, dg_epoch e, int32_t* comp, uint32_t* n_components, void* stream);
+
+/*
  * Snapshot PageRank on epoch e: Eq. (1) of arXiv 2109.09527, iterated as its
  * synchronous Barrier baseline (Alg. 1), in FP64.  With n the live vertices
  * at e and q(v) the visible out-degree, every live vertex starts at 1/n, and

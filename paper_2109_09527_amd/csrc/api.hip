@@ -407,6 +407,7 @@ dg_status dg_destroy(dg_graph* g) {
   if (u.host_summary) hipHostFree(u.host_summary);
   free_query_scratch(g->qs);
   free_pr_scratch(g->pr);
+  free_scc_scratch(g->scc);
   free_batch_state(g);
   for (auto& r : g->prof.pending) {
     hipEventDestroy(r.a);
@@ -618,6 +619,16 @@ dg_status dg_pagerank_ex(dg_graph* g, dg_epoch want, const dg_pagerank_opts* opt
   return pagerank_call(g, want, *opts, pr, iterations, last_change, stream);
 }
 
+dg_status dg_scc(dg_graph* g, dg_epoch want, int32_t* comp, uint32_t* n_components, void* stream) {
+  if (!g || !comp) return DG_E_INVALID_ARG;
+  if (!is_device_ptr(comp)) return fail(g, DG_E_INVALID_ARG, "comp must be device memory");
+  std::lock_guard<std::mutex> lk(g->mu);
+  uint32_t e;
+  dg_status st = resolve_epoch(g, want, &e);
+  if (st != DG_OK) return st;
+  return note_query(g, scc_dev(g, e, comp, n_components, nullptr, static_cast<hipStream_t>(stream)), stream);
+}
+
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
@@ -649,7 +660,7 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
 dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
-                                         "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync"};
+                                         "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

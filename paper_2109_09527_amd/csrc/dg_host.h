@@ -91,6 +91,13 @@ struct PrScratch {
   void* host = nullptr;   // pinned: liveness mask upload, totals and changes read back
 };
 
+// Strongly connected components: the two snapshot CSRs, their pieces and the
+// colouring state.
+struct SccScratch {
+  DevBuf off_in, csr_in, off_out, csr_out, pf_in, pv_in, pf_out, pv_out, colour, mark, rem, flags, scan;
+  void* host = nullptr;   // pinned: counters read back
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -105,6 +112,7 @@ enum KernelId {
   KID_BATCH_BC,
   KID_PAGERANK,     // one PageRank iteration (pull and apply)
   KID_PAGERANK_NOSYNC,  // one No-Sync PageRank launch
+  KID_SCC,          // one colouring or collecting pass of the SCC query
   KID_COUNT
 };
 struct Prof {
@@ -149,6 +157,7 @@ struct dg_graph {
   dg::UpdateScratch us;
   dg::QueryScratch qs;
   dg::PrScratch pr;
+  dg::SccScratch scc;
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
@@ -194,6 +203,16 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
                        uint32_t max_iters, double* pr, uint32_t* iters, double* last_change, hipStream_t s,
                        bool nosync);
 void free_pr_scratch(PrScratch& s);
+// Snapshot helpers shared by the whole-graph queries (they use the PageRank
+// build scratch): liveness at e as a device byte mask, and the visible arcs
+// at e of the live vertices' slabs in `pool` as a CSR (off: V + 1 entries;
+// csr: the other endpoint of each arc, in slab order); m = arcs.
+hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t s);
+// scc.hip
+dg_status scc_dev(dg_graph* g, uint32_t e, int32_t* comp, uint32_t* n_comp, uint32_t* rounds, hipStream_t s);
+void free_scc_scratch(SccScratch& s);
+hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
+                        DevBuf& off, DevBuf& csr, uint32_t* m, hipStream_t s);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

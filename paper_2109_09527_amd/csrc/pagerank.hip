@@ -491,6 +491,67 @@ static hipError_t pr_scan(PrScratch& s, uint32_t* data, uint64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ snapshot build
+
+hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t st) {
+  PrScratch& s = g->pr;
+  const uint32_t V = g->cfg.v_capacity;
+  hipError_t he;
+  if (!s.host &&
+      (he = hipHostMalloc(&s.host, std::max<size_t>(V, PR_RING * PR_STRIPES * 8) + 64, hipHostMallocDefault)) !=
+          hipSuccess)
+    return he;
+  // the pinned block may still feed an earlier copy
+  if ((he = hipStreamSynchronize(st)) != hipSuccess) return he;
+  uint8_t* hl = static_cast<uint8_t*>(s.host);
+  for (uint32_t v = 0; v < V; v++) hl[v] = g->vfirst[v] != 0 && g->vfirst[v] <= e;
+  for (const auto& kv : g->vmore) hl[kv.first] = alive_at(g, kv.first, e) ? 1 : 0;
+  if ((he = ensure(live, V + 64)) != hipSuccess) return he;
+  return hipMemcpyAsync(live.p, hl, V, hipMemcpyHostToDevice, st);
+}
+
+hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
+                        DevBuf& off_buf, DevBuf& csr_buf, uint32_t* m_out, hipStream_t st) {
+  PrScratch& s = g->pr;
+  const uint32_t V = g->cfg.v_capacity;
+  hipError_t he;
+  const uint64_t T_max = pool.cap / PR_TILE + V + 1;
+  if ((he = ensure(s.ntiles, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.dsnap, V * 8ull + 64)) != hipSuccess ||
+      (he = ensure(s.tile_v, T_max * 4)) != hipSuccess || (he = ensure(s.tcount, (T_max + 1) * 4)) != hipSuccess ||
+      (he = ensure(off_buf, (V + 1ull) * 4)) != hipSuccess)
+    return he;
+  uint32_t* tfirst = s.ntiles.as<uint32_t>();
+  k_pr_ntiles<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(desc, live, V, s.dsnap.as<uint64_t>(), tfirst);
+  desc = s.dsnap.as<uint64_t>();
+  if ((he = pr_scan(s, tfirst, V + 1ull, st)) != hipSuccess) return he;
+  // the tile total (tfirst[V]) is needed on the host before the tile kernels
+  if ((he = hipMemcpyAsync(s.host, tfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess)
+    return he;
+  uint32_t T;
+  std::memcpy(&T, s.host, 4);
+  if (T > T_max) return hipErrorInvalidValue;
+  k_pr_tile_list<<<pr_grid(V, 256), 256, 0, st>>>(tfirst, V, s.tile_v.as<uint32_t>());
+  uint32_t* tc = s.tcount.as<uint32_t>();
+  k_pr_fill_u32<<<1, 64, 0, st>>>(tc + T, 1, 0u);
+  if (T)
+    k_pr_count<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e,
+                                                                   tc);
+  if ((he = pr_scan(s, tc, T + 1ull, st)) != hipSuccess) return he;
+  if ((he = hipMemcpyAsync(s.host, tc + T, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess)
+    return he;
+  uint32_t m;
+  std::memcpy(&m, s.host, 4);
+  if ((he = ensure(csr_buf, (uint64_t)m * 4 + 64)) != hipSuccess) return he;
+  if (T)
+    k_pr_fill<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e,
+                                                                  tc, csr_buf.as<uint32_t>());
+  k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, off_buf.as<uint32_t>());
+  *m_out = m;
+  return hipGetLastError();
+}
+
 static uint32_t pr_resident(const void* kernel) {
   int per_cu = 0, cus = 0, dev = 0;
   (void)hipGetDevice(&dev);
@@ -523,60 +584,20 @@ dg_status pagerank_dev(dg_graph* g, uint32_t e, double damping, double threshold
   // the loop runs while the change exceeds the threshold, from a change of 1
   if (n_live == 0 || max_iters == 0 || !(threshold < 1.0)) return DG_OK;
 
-  // liveness at e, from the host's history
-  if (!s.host &&
-      (he = hipHostMalloc(&s.host, std::max<size_t>(V, PR_RING * PR_STRIPES * 8) + 64, hipHostMallocDefault)) !=
-          hipSuccess)
-    return fail_hip(he, "host buffer");
-  if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "sync");
-  uint8_t* hl = static_cast<uint8_t*>(s.host);
-  for (uint32_t v = 0; v < V; v++) hl[v] = g->vfirst[v] != 0 && g->vfirst[v] <= e;
-  for (const auto& kv : g->vmore) hl[kv.first] = alive_at(g, kv.first, e) ? 1 : 0;
-  if ((he = ensure(s.live, V + 64)) != hipSuccess) return fail_hip(he, "alloc");
-  if ((he = hipMemcpyAsync(s.live.p, hl, V, hipMemcpyHostToDevice, st)) != hipSuccess) return fail_hip(he, "mask");
-
+  if ((he = snapshot_live(g, e, s.live, st)) != hipSuccess) return fail_hip(he, "liveness");
   // in-arcs: the reverse pool, or the forward one of an undirected graph
   const bool und = g->st.undirected != 0;
-  const Pool pool = und ? g->st.fp : g->st.rp;
-  const uint64_t* desc = und ? g->st.fdesc : g->st.rdesc;
-  const uint64_t T_max = pool.cap / PR_TILE + V + 1;
-  if ((he = ensure(s.ntiles, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.dsnap, V * 8ull + 64)) != hipSuccess || (he = ensure(s.tile_v, T_max * 4)) != hipSuccess ||
-      (he = ensure(s.tcount, (T_max + 1) * 4)) != hipSuccess || (he = ensure(s.off, (V + 1ull) * 4)) != hipSuccess ||
-      (he = ensure(s.pfirst, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.q, V * 4ull + 64)) != hipSuccess ||
+  uint32_t m = 0;
+  if ((he = snapshot_csr(g, e, und ? g->st.fp : g->st.rp, und ? g->st.fdesc : g->st.rdesc, s.live.as<uint8_t>(),
+                         s.off, s.csr, &m, st)) != hipSuccess)
+    return fail_hip(he, "snapshot");
+  if ((he = ensure(s.pfirst, (V + 1ull) * 4)) != hipSuccess || (he = ensure(s.q, V * 4ull + 64)) != hipSuccess ||
       (he = ensure(s.contrib, V * 8ull + 64)) != hipSuccess || (he = ensure(s.ring, PR_RING * PR_STRIPES * 8)) != hipSuccess)
     return fail_hip(he, "alloc");
-  uint32_t* tfirst = s.ntiles.as<uint32_t>();
-  k_pr_ntiles<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(desc, s.live.as<uint8_t>(), V, s.dsnap.as<uint64_t>(), tfirst);
-  desc = s.dsnap.as<uint64_t>();
-  if ((he = pr_scan(s, tfirst, V + 1ull, st)) != hipSuccess) return fail_hip(he, "tile scan");
-  // the tile total (tfirst[V]) is needed on the host before the tile kernels
-  if ((he = hipMemcpyAsync(s.host, tfirst + V, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-      (he = hipStreamSynchronize(st)) != hipSuccess)
-    return fail_hip(he, "tile total");
-  uint32_t T;
-  std::memcpy(&T, s.host, 4);
-  if (T > T_max) {
-    g->err = "pagerank: tile count exceeds its bound";
-    return DG_E_HIP;
-  }
-  k_pr_tile_list<<<pr_grid(V, 256), 256, 0, st>>>(tfirst, V, s.tile_v.as<uint32_t>());
-  uint32_t* tc = s.tcount.as<uint32_t>();
-  k_pr_fill_u32<<<1, 64, 0, st>>>(tc + T, 1, 0u);
-  if (T) k_pr_count<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e, tc);
-  if ((he = pr_scan(s, tc, T + 1ull, st)) != hipSuccess) return fail_hip(he, "arc scan");
-  if ((he = hipMemcpyAsync(s.host, tc + T, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-      (he = hipStreamSynchronize(st)) != hipSuccess)
-    return fail_hip(he, "arc total");
-  uint32_t m;
-  std::memcpy(&m, s.host, 4);
   const uint64_t P_max = (uint64_t)V + m / PR_PIECE + 1;
-  if ((he = ensure(s.csr, (uint64_t)m * 4 + 64)) != hipSuccess || (he = ensure(s.piece_v, P_max * 4)) != hipSuccess ||
-      (he = ensure(s.part, P_max * 8)) != hipSuccess)
+  if ((he = ensure(s.piece_v, P_max * 4)) != hipSuccess || (he = ensure(s.part, P_max * 8)) != hipSuccess)
     return fail_hip(he, "alloc");
-  if (T) k_pr_fill<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e, tc,
-                                                                    s.csr.as<uint32_t>());
   uint32_t* off = s.off.as<uint32_t>();
-  k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, off);
   k_pr_fill_u32<<<pr_grid(V, 256), 256, 0, st>>>(s.q.as<uint32_t>(), V, 0u);
   if (m) k_pr_outdeg<<<pr_grid(m, 256), 256, 0, st>>>(s.csr.as<uint32_t>(), m, s.q.as<uint32_t>());
 

@@ -83,6 +83,9 @@ for _n in ("dg_pagerank", "dg_pagerank_nosync"):
          ctypes.POINTER(ctypes.c_double), _P)
 
 
+_sig("dg_scc", _i32, _P, _u32, _P, ctypes.POINTER(_u32), _P)
+
+
 class PageRankOpts(ctypes.Structure):
     _fields_ = [("damping", ctypes.c_double), ("threshold", ctypes.c_double), ("freeze_below", ctypes.c_double),
                 ("max_iters", _u32), ("nosync", ctypes.c_int)]
@@ -253,6 +256,19 @@ class Graph:
         rc, out = self.try_bc(srcs, epoch, out)
         self._check(rc)
         return out
+
+    def try_scc(self, epoch=EPOCH_LATEST, out=None):
+        """(status, comp tensor int32, number of components)."""
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda") if out is None else out
+        nc = _u32()
+        rc = lib.dg_scc(self.h, epoch, _ptr(out), ctypes.byref(nc), _stream())
+        return rc, out, int(nc.value)
+
+    def scc(self, epoch=EPOCH_LATEST, out=None):
+        """(comp tensor, number of components); raises on a failed call."""
+        rc, out, nc = self.try_scc(epoch, out)
+        self._check(rc)
+        return out, nc
 
     def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
                      nosync=False, freeze_below=None):

@@ -1,0 +1,110 @@
+"""Parity of the snapshot SCC query (dg_scc) with the oracle's Tarjan:
+component labels (smallest member, -1 for vertices not live) must match
+bit for bit, and so must the number of components."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import Oracle  # noqa: E402
+from paper_2109_09527_amd import synth  # noqa: E402
+from paper_2109_09527_amd.synth import REME, REMV, make_ops  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_09527_amd import dg as m
+    return m
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def build(dg, n, us, vs, undirected=False):
+    us = np.asarray(us, dtype=np.uint32)
+    vs = np.asarray(vs, dtype=np.uint32)
+    gr = synth.Graph(n, us, vs, np.ones(len(us), np.int32), undirected)
+    o = Oracle(n, undirected=undirected, w_max=255)
+    g = dg.Graph(n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    return g, o
+
+
+def check(g, o, epoch=None, want=None):
+    if want is None:
+        rc, want = o.scc()
+        assert rc == 0
+    comp, nc = g.scc(g.epoch if epoch is None else epoch)
+    comp = comp.cpu().numpy()
+    assert np.array_equal(comp, want), (np.nonzero(comp != want)[0][:10])
+    assert nc == len(np.unique(want[want >= 0]))
+    return comp
+
+
+def test_closed_forms(dg):
+    n = 30
+    say("cycle")
+    g, o = build(dg, n, np.arange(n), (np.arange(n) + 1) % n)
+    assert np.all(check(g, o) == 0)
+    say("path and reverse path")
+    g, o = build(dg, n, np.arange(n - 1), np.arange(1, n))
+    check(g, o)
+    g, o = build(dg, n, np.arange(1, n), np.arange(n - 1))
+    check(g, o)
+    say("two cycles")
+    g, o = build(dg, 7, [0, 1, 2, 3, 4, 5, 2], [1, 2, 0, 4, 5, 3, 3])
+    assert check(g, o).tolist() == [0, 0, 0, 3, 3, 3, 6]
+    say("undirected")
+    g, o = build(dg, 6, [0, 3], [1, 4], undirected=True)
+    assert check(g, o).tolist() == [0, 0, 2, 3, 3, 5]
+    say("empty")
+    g = dg.Graph(8, w_max=255)
+    comp, nc = g.scc()
+    assert nc == 0 and np.all(comp.cpu().numpy() == -1)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_random_graphs_with_dead_vertices(dg, undirected):
+    for seed in range(4):
+        rng = synth.rng_for(seed, 93)
+        n = 300
+        m = 400 if undirected else 700
+        us = rng.integers(0, n, m)
+        vs = rng.integers(0, n, m)
+        keep = us != vs
+        say("random", undirected, seed)
+        g, o = build(dg, n, us[keep], vs[keep], undirected)
+        dead = rng.choice(n, 20, replace=False)
+        ops = make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead)))
+        o.apply(ops)
+        g.apply(ops)
+        check(g, o)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_rmat_snapshots(dg, undirected):
+    """R-MAT scale 14 (a giant component among many small ones, hubs with
+    hundreds of buckets): the load epoch, pinned, and the epoch after edge
+    removals, read afterwards."""
+    gr = synth.rmat_graph(14, 8, 255, seed=23, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    e1 = g.acquire()
+    want1 = o.scc()[1]
+    rng = synth.rng_for(23, 5)
+    pick = rng.choice(gr.m, gr.m // 4, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    say("rmat14 latest", undirected)
+    check(g, o)
+    say("rmat14 earlier", undirected)
+    check(g, o, epoch=e1, want=want1)
+    g.release(e1)
