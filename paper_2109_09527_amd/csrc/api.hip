@@ -433,7 +433,9 @@ dg_status dg_apply_batch(dg_graph* g, const dg_op* ops, uint64_t n, uint8_t* res
     hipError_t e = hipSuccess;
     const dg_op* dops = ops;
     if (!is_device_ptr(ops)) {
-      if ((e = ensure(g->us.ops, n * sizeof(dg_op))) != hipSuccess) return fail(g, DG_E_OUT_OF_MEMORY, "ops staging");
+      // size all of the batch scratch first: growing it later would replace
+      // the staging buffer under the copy
+      if ((e = ensure_update_scratch(g, n)) != hipSuccess) return fail(g, DG_E_OUT_OF_MEMORY, "ops staging");
       if ((e = hipMemcpyAsync(g->us.ops.p, ops, n * sizeof(dg_op), hipMemcpyHostToDevice, s)) != hipSuccess)
         return fail(g, DG_E_HIP, std::string("ops copy: ") + hipGetErrorString(e));
       dops = g->us.ops.as<dg_op>();

@@ -187,6 +187,9 @@ struct ProfScope {
 };
 void prof_arcs(dg_graph* g, int kid, uint64_t arcs);
 
+// update.hip: sizes the batch scratch (us.*) for n ops; callers that stage
+// ops into us.ops do so after this, since growing it replaces the buffer.
+hipError_t ensure_update_scratch(dg_graph* g, uint64_t n);
 // update.hip: runs one batch; returns a dg_status.
 dg_status apply_batch_dev(dg_graph* g, const dg_op* dops, uint64_t n, uint8_t* dres, hipStream_t s);
 

@@ -488,7 +488,7 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t per, uint32_t cap = 1u <<
   return (uint32_t)b;
 }
 
-static hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
+hipError_t ensure_update_scratch(dg_graph* g, uint64_t n) {
   UpdateScratch& u = g->us;
   if (n <= u.cap && u.host_summary) return hipSuccess;
   uint64_t c = std::max<uint64_t>(n, 1024);

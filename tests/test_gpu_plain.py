@@ -109,8 +109,9 @@ def test_random_batches_all_sizes(dg, seed, undirected):
     g = dg.Graph(n, undirected=undirected, w_max=50)
     say("random batches", seed, undirected)
     load = make_ops([ADDV] * n, np.arange(n), np.zeros(n), np.zeros(n))
-    o.apply(load)
-    g.apply(load)
+    _, r_o = o.apply(load)
+    res, _ = g.apply(load)
+    assert np.array_equal(res, r_o)
     mix = [0.06, 0.04, 0.05, 0.45, 0.25, 0.15]
     rng = np.random.default_rng(seed)
     for b, size in enumerate([1, 7, 64, 500, 4000, 33, 2]):
@@ -122,6 +123,26 @@ def test_random_batches_all_sizes(dg, seed, undirected):
         check_queries(g, o, ep, rng.integers(0, n, 3), dg, bc=(b % 3 == 2))
     nv, na = g.stats()
     assert (nv, na) == o.counts()
+
+
+def test_first_batches_of_fresh_graphs(dg):
+    """A graph's first batch of host ops, smaller than the batch scratch's
+    minimum size, is staged after that scratch is sized: fresh graphs
+    created and destroyed in turn (so device blocks are recycled) all apply
+    their first batch exactly."""
+    for it in range(40):
+        n = [9, 300, 700, 1000][it % 4]
+        o = Oracle(n, w_max=50)
+        g = dg.Graph(n, w_max=50)
+        load = make_ops([ADDV] * n, np.arange(n), np.zeros(n), np.zeros(n))
+        _, r_o = o.apply(load)
+        res, _ = g.apply(load)
+        assert np.array_equal(res, r_o), (it, np.nonzero(res != r_o)[0][:10])
+        ops = synth.random_ops(n, 200, 500 + it, w_max=50)
+        _, r_o = o.apply(ops)
+        res, _ = g.apply(ops)
+        assert np.array_equal(res, r_o), (it, np.nonzero(res != r_o)[0][:10])
+        del g
 
 
 def test_device_resident_ops_and_results(dg):
