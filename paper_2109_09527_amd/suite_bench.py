@@ -25,6 +25,10 @@
       are compared with it.  The No-Sync (barrier-free) form runs on e1 too,
       compared with the synchronous ranks.
 
+  python -m paper_2109_09527_amd.suite_bench scc [--scale 20]
+      The same graph and batch; strongly connected components of the latest
+      snapshot, timed, against the oracle's Tarjan on the host.
+
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
 vertices reached) / wall time.  Kernel figures come from the library's
@@ -188,6 +192,61 @@ def bc(args):
     print(json.dumps(out), flush=True)
 
 
+# SCC: algorithmic bytes of one colouring or collecting pass, per visible arc
+# (other endpoint 4 + its colour 4) and per vertex (colour, flags: 8)
+SCC_BYTES_PER_ARC, SCC_BYTES_PER_VERTEX = 8, 8
+
+
+def scc(args):
+    import torch
+    from oracle import Oracle
+    from paper_2109_09527_amd import dg, synth
+    wl = synth.update_batches(scale=args.scale, n_batches=1, seed=0)
+    gr = wl.graph
+    g = dg.Graph(gr.n, w_max=255, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    g.apply(dg.ops_to_device(wl.batches[0]), torch.empty(len(wl.batches[0]), dtype=torch.uint8, device="cuda"))
+    nv, na = g.stats()
+    g.scc()   # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for rep in range(args.reps):
+        g.profile(True)
+        g.profile_read(reset=True)
+        t = time.perf_counter()
+        comp, nc = g.scc()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        prof = g.profile_read(reset=True).get("scc", {})
+        g.profile(False)
+    t_med = sorted(times)[len(times) // 2]
+    passes = prof.get("launches", 0)
+    pass_ms = prof.get("total_ms", 0.0) / max(1, passes)
+    algo = SCC_BYTES_PER_ARC * na + SCC_BYTES_PER_VERTEX * nv
+    gbs = algo / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else 0.0
+    comp = comp.cpu().numpy()
+    sizes = np.bincount(comp[comp >= 0])
+    out = {"workload": f"R-MAT scale {args.scale} directed, {gr.m} loaded edges, then one batch of "
+                       f"{len(wl.batches[0])} ops; strongly connected components of the latest snapshot",
+           "live_vertices": nv, "arcs": na, "components": nc, "largest": int(sizes.max()),
+           "seconds": round(t_med, 5), "passes": passes, "pass_ms": round(pass_ms, 4),
+           "roofline": {"bound": "hbm", "kernel": "k_scc_forward / k_scc_collect pass", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "bytes_per_pass": algo}}
+    if args.cpu:
+        o = Oracle(gr.n, w_max=255)
+        o.apply(load)
+        o.apply(wl.batches[0])
+        t = time.perf_counter()
+        _, want = o.scc()
+        t_cpu = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(t_cpu, 4), "unit": "s per query", "cores": 1, "kind": "oracle",
+                               "sample": "the whole query (Tarjan) on the same snapshot"}
+        out["equal_to_oracle"] = bool(np.array_equal(comp, want))
+    print(json.dumps(out), flush=True)
+
+
 # PageRank: algorithmic bytes of one iteration, per visible in-arc (source
 # id 4 + its contribution 8) and per live vertex (rank read and write 16,
 # contribution write 8, out-degree 4, CSR offset 4)
@@ -304,11 +363,15 @@ def main():
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--cpu-iters", type=int, default=20, help="oracle iterations timed on the host (0: none)")
     c.add_argument("--copy-mib", type=int, default=0, help="one plain device copy of this many MiB at the end")
+    d = sub.add_parser("scc")
+    d.add_argument("--scale", type=int, default=20)
+    d.add_argument("--reps", type=int, default=3)
+    d.add_argument("--cpu", type=int, default=1, help="1: time the oracle on the same snapshot and compare")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    {"batched": batched, "bc": bc, "pagerank": pagerank}[args.what](args)
+    {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc}[args.what](args)
 
 
 if __name__ == "__main__":
