@@ -271,7 +271,8 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_pull(PrIter a, uint32_t it) {
     const uint32_t p = p0 + (threadIdx.x >> 4);   // group-uniform
     double s = 0.0;
     const uint32_t u = p < a.P ? a.piece_v[p] : 0;
-    if (p < a.P && !a.frozen[u]) {
+    // the frozen flags are read only with perforation on (uniform test)
+    if (p < a.P && !(a.freeze_below > 0.0 && a.frozen[u])) {
       const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
       const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
       // four arcs per lane in flight: indices first, then their contributions
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_apply(PrIter a, uint32_t it) 
   __shared__ double wmax[PR_THREADS / 64];
   double ch = 0.0;
   for (uint32_t u = blockIdx.x * PR_THREADS + threadIdx.x; u < a.V; u += gridDim.x * PR_THREADS) {
-    if (!a.live[u] || a.frozen[u]) continue;
+    if (!a.live[u] || (a.freeze_below > 0.0 && a.frozen[u])) continue;
     double s = 0.0;
     for (uint32_t k = a.pfirst[u]; k < a.pfirst[u + 1]; k++) s += a.part[k];
     const double x = a.base + a.d * s;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_nosync(PrAsync a) {
     // the workgroup's pieces (16-lane groups, group-uniform loop)
     for (uint32_t p = p0 + grp; p < p1; p += PR_THREADS / 16) {
       const uint32_t u = a.piece_v[p];
-      if (a.frozen[u]) continue;   // group-uniform
+      if (a.freeze_below > 0.0 && a.frozen[u]) continue;   // group-uniform
       const uint32_t b = a.off[u] + (p - a.pfirst[u]) * PR_PIECE;
       const uint32_t end = min(b + PR_PIECE, a.off[u + 1]);
       double s = 0.0;
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_nosync(PrAsync a) {
     // the workgroup's vertices, from the latest sums of their pieces
     double ch = 0.0;
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += PR_THREADS) {
-      if (!a.live[r] || a.frozen[r]) continue;
+      if (!a.live[r] || (a.freeze_below > 0.0 && a.frozen[r])) continue;
       double s = 0.0;
       for (uint32_t k = a.pfirst[r]; k < a.pfirst[r + 1]; k++) s += pr_ld(&a.part[k]);
       const double x = a.base + a.d * s;
