@@ -68,6 +68,8 @@ def _load():
     lib.orc_pagerank.argtypes = [P, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     lib.orc_scc.restype = ctypes.c_int
     lib.orc_scc.argtypes = [P, P]
+    lib.orc_diameter.restype = ctypes.c_int
+    lib.orc_diameter.argtypes = [P, P]
     lib.orc_pagerank_perforated.restype = ctypes.c_int
     lib.orc_pagerank_perforated.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
@@ -147,6 +149,13 @@ class Oracle:
         out = np.empty(self.n, dtype=np.int32)
         rc = self.lib.orc_scc(self.h, _ptr(out))
         return rc, out
+
+    def diameter(self):
+        """(status, largest hop distance between live vertices u, v with v
+        reachable from u)."""
+        d = ctypes.c_uint32()
+        rc = self.lib.orc_diameter(self.h, ctypes.byref(d))
+        return rc, d.value
 
     def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000, freeze_below=None):
         """(status, pr[n] float64, iterations, last iteration's largest change);

@@ -647,3 +647,44 @@ int orc_scc(const orc_graph* g, int32_t* comp) {
   free(index); free(low); free(on); free(st); free(cs_v); free(cs_j);
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------- diameter */
+
+/* Diameter of the current state (the GD query named in the preamble;
+ * textbook semantics): the largest hop distance d(u, v) over ordered pairs
+ * of live vertices with v reachable from u, 0 when no arc exists.  One FIFO
+ * BFS from every live vertex. */
+int orc_diameter(const orc_graph* g, uint32_t* diameter) {
+  const uint32_t n = g->n;
+  int32_t* dist = (int32_t*)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+  uint32_t* q = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+  if (!dist || !q) {
+    free(dist);
+    free(q);
+    return ORC_E_OOM;
+  }
+  uint32_t best = 0;
+  for (uint32_t s = 0; s < n; s++) {
+    if (!g->alive[s]) continue;
+    for (uint32_t i = 0; i < n; i++) dist[i] = -1;
+    uint32_t head = 0, tail = 0;
+    dist[s] = 0;
+    q[tail++] = s;
+    while (head < tail) {
+      const uint32_t x = q[head++];
+      if ((uint32_t)dist[x] > best) best = (uint32_t)dist[x];
+      const arc_list* l = &g->out[x];
+      for (uint32_t j = 0; j < l->n; j++) {
+        const uint32_t y = l->a[j].v;
+        if (dist[y] < 0) {
+          dist[y] = dist[x] + 1;
+          q[tail++] = y;
+        }
+      }
+    }
+  }
+  free(dist);
+  free(q);
+  *diameter = best;
+  return ORC_OK;
+}

@@ -16,7 +16,8 @@
  *   - PageRank of the current state, Eq. (1) iterated as the synchronous
  *     Barrier baseline (Alg. 1) in FP64, optionally with the loop
  *     perforation of Alg. 5;
- *   - strongly connected components (GetSCC in the preamble), by Tarjan.
+ *   - strongly connected components (GetSCC in the preamble), by Tarjan;
+ *   - the diameter (GD in the preamble), by a BFS from every vertex.
  *
  * Error codes are the integer values of the C boundary's call status.
  */
@@ -70,6 +71,9 @@ int        orc_pagerank(const orc_graph* g, double damping, double threshold, ui
 /* Strongly connected components (Tarjan): comp[v] = smallest id in v's
  * component for live v, -1 otherwise. */
 int        orc_scc(const orc_graph* g, int32_t* comp);
+/* Diameter: largest hop distance over ordered pairs (u, v) of live vertices
+ * with v reachable from u (0 without arcs); one BFS per live vertex. */
+int        orc_diameter(const orc_graph* g, uint32_t* diameter);
 int        orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
                                    uint32_t max_iters, double* pr, uint32_t* iters, double* last_change);
 

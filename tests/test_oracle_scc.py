@@ -107,3 +107,49 @@ def test_rmat_invariants():
     # the graph has one large component besides many singletons
     sizes = np.bincount(lab)
     assert sizes.max() > gr.n // 4
+
+
+# ------------------------------------------------------------ diameter (GD)
+
+def brute_diameter(o):
+    """Largest finite hop distance from Floyd-Warshall on the arc matrix."""
+    n = o.n
+    live = np.array([o.alive(v) for v in range(n)])
+    INF = 10 ** 9
+    D = np.full((n, n), INF, dtype=np.int64)
+    np.fill_diagonal(D, 0)
+    us, vs, _ = o.edges()
+    D[us, vs] = np.minimum(D[us, vs], 1)
+    if o.undirected:
+        D[vs, us] = np.minimum(D[vs, us], 1)
+    for k in range(n):
+        D = np.minimum(D, D[:, k:k + 1] + D[k:k + 1, :])
+    D = D[np.ix_(live, live)]
+    fin = D[D < INF]
+    return int(fin.max()) if fin.size else 0
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_diameter_matches_floyd_warshall(seed, undirected):
+    rng = synth.rng_for(seed, 94)
+    n = 40
+    m = 50 if undirected else 80
+    us = rng.integers(0, n, m)
+    vs = rng.integers(0, n, m)
+    keep = us != vs
+    o = load(n, us[keep], vs[keep], undirected)
+    dead = rng.choice(n, 3, replace=False)
+    o.apply(make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead))))
+    rc, d = o.diameter()
+    assert rc == OK and d == brute_diameter(o)
+
+
+def test_diameter_closed_forms():
+    n = 20
+    assert load(n, np.arange(n - 1), np.arange(1, n)).diameter()[1] == n - 1          # path
+    assert load(n, np.arange(n), (np.arange(n) + 1) % n).diameter()[1] == n - 1       # directed cycle
+    assert load(n, np.arange(n), (np.arange(n) + 1) % n, undirected=True).diameter()[1] == n // 2
+    assert load(n, np.zeros(n - 1), np.arange(1, n)).diameter()[1] == 1               # out-star
+    assert load(n, np.zeros(n - 1), np.arange(1, n), undirected=True).diameter()[1] == 2
+    assert Oracle(5).diameter()[1] == 0
