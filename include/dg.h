@@ -138,6 +138,16 @@ dg_status dg_bc(dg_graph* g, dg_epoch e, const uint32_t* srcs, uint32_t k, doubl
 dg_status dg_scc(dg_graph* g, dg_epoch e, int32_t* comp, uint32_t* n_components, void* stream);
 
 /*
+ * Diameter of the snapshot at epoch e (the GD query named in the preamble of
+ * arXiv 2109.09527; textbook semantics): the largest number of arcs on a
+ * shortest path from u to v, over ordered pairs of vertices live at e with v
+ * reachable from u; 0 when no arc is visible.  Exact (a BFS from every live
+ * vertex, 256 at a time, bit-parallel).  diameter: host.  The call returns
+ * when the value is known.
+ */
+dg_status dg_diameter(dg_graph* g, dg_epoch e, uint32_t* diameter, void* stream);
+
+/*
  * Snapshot PageRank on epoch e: Eq. (1) of arXiv 2109.09527, iterated as its
  * synchronous Barrier baseline (Alg. 1), in FP64.  With n the live vertices
  * at e and q(v) the visible out-degree, every live vertex starts at 1/n, and

@@ -408,6 +408,7 @@ dg_status dg_destroy(dg_graph* g) {
   free_query_scratch(g->qs);
   free_pr_scratch(g->pr);
   free_scc_scratch(g->scc);
+  free_diam_scratch(g->diam);
   free_batch_state(g);
   for (auto& r : g->prof.pending) {
     hipEventDestroy(r.a);
@@ -631,6 +632,15 @@ dg_status dg_scc(dg_graph* g, dg_epoch want, int32_t* comp, uint32_t* n_componen
   return note_query(g, scc_dev(g, e, comp, n_components, nullptr, static_cast<hipStream_t>(stream)), stream);
 }
 
+dg_status dg_diameter(dg_graph* g, dg_epoch want, uint32_t* diameter, void* stream) {
+  if (!g || !diameter) return DG_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g->mu);
+  uint32_t e;
+  dg_status st = resolve_epoch(g, want, &e);
+  if (st != DG_OK) return st;
+  return note_query(g, diameter_dev(g, e, diameter, static_cast<hipStream_t>(stream)), stream);
+}
+
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
@@ -662,7 +672,8 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
 dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32_t* n_out, int reset) {
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
-                                         "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc"};
+                                         "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
+                                         "diameter"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

@@ -98,6 +98,13 @@ struct SccScratch {
   void* host = nullptr;   // pinned: counters read back
 };
 
+// Diameter: the in-arc snapshot CSR, its pieces, and the bit-parallel BFS
+// words (reached, frontier, next: 4 x 64 bits per vertex each).
+struct DiamScratch {
+  DevBuf off, csr, pf, pv, vis, fr, nx, src, flag, scan;
+  void* host = nullptr;
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -113,6 +120,7 @@ enum KernelId {
   KID_PAGERANK,     // one PageRank iteration (pull and apply)
   KID_PAGERANK_NOSYNC,  // one No-Sync PageRank launch
   KID_SCC,          // one colouring or collecting pass of the SCC query
+  KID_DIAMETER,     // one level of a bit-parallel BFS sweep (diameter)
   KID_COUNT
 };
 struct Prof {
@@ -158,6 +166,7 @@ struct dg_graph {
   dg::QueryScratch qs;
   dg::PrScratch pr;
   dg::SccScratch scc;
+  dg::DiamScratch diam;
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
@@ -214,6 +223,9 @@ hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t s);
 // scc.hip
 dg_status scc_dev(dg_graph* g, uint32_t e, int32_t* comp, uint32_t* n_comp, uint32_t* rounds, hipStream_t s);
 void free_scc_scratch(SccScratch& s);
+// diameter.hip
+dg_status diameter_dev(dg_graph* g, uint32_t e, uint32_t* diameter, hipStream_t s);
+void free_diam_scratch(DiamScratch& s);
 hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
                         DevBuf& off, DevBuf& csr, uint32_t* m, hipStream_t s);
 

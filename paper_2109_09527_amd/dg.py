@@ -84,6 +84,7 @@ for _n in ("dg_pagerank", "dg_pagerank_nosync"):
 
 
 _sig("dg_scc", _i32, _P, _u32, _P, ctypes.POINTER(_u32), _P)
+_sig("dg_diameter", _i32, _P, _u32, ctypes.POINTER(_u32), _P)
 
 
 class PageRankOpts(ctypes.Structure):
@@ -269,6 +270,12 @@ class Graph:
         rc, out, nc = self.try_scc(epoch, out)
         self._check(rc)
         return out, nc
+
+    def diameter(self, epoch=EPOCH_LATEST) -> int:
+        """Largest hop distance over reachable ordered pairs of live vertices."""
+        d = _u32()
+        self._check(lib.dg_diameter(self.h, epoch, ctypes.byref(d), _stream()))
+        return int(d.value)
 
     def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
                      nosync=False, freeze_below=None):

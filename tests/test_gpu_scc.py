@@ -108,3 +108,58 @@ def test_rmat_snapshots(dg, undirected):
     say("rmat14 earlier", undirected)
     check(g, o, epoch=e1, want=want1)
     g.release(e1)
+
+
+# ------------------------------------------------------------ diameter (GD)
+
+def test_diameter_closed_forms(dg):
+    n = 20
+    say("diameter closed forms")
+    cases = [
+        ((np.arange(n - 1), np.arange(1, n)), False, n - 1),            # path
+        ((np.arange(n), (np.arange(n) + 1) % n), False, n - 1),         # directed cycle
+        ((np.arange(n), (np.arange(n) + 1) % n), True, n // 2),         # undirected cycle
+        ((np.zeros(n - 1), np.arange(1, n)), False, 1),                 # out-star
+        ((np.zeros(n - 1), np.arange(1, n)), True, 2),                  # undirected star
+    ]
+    for (us, vs), und, want in cases:
+        g, o = build(dg, n, us, vs, und)
+        assert g.diameter() == want == o.diameter()[1], (und, want)
+    assert dg.Graph(8, w_max=255).diameter() == 0
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_diameter_random_and_rmat(dg, undirected):
+    """Random graphs past one 256-source sweep, with dead vertices, and
+    R-MAT 12 before and after edge removals (the earlier epoch read
+    afterwards): equal to the oracle's BFS from every vertex."""
+    for seed in range(3):
+        rng = synth.rng_for(seed, 95)
+        n = 700
+        m = 900 if undirected else 1800
+        us = rng.integers(0, n, m)
+        vs = rng.integers(0, n, m)
+        keep = us != vs
+        say("diameter random", undirected, seed)
+        g, o = build(dg, n, us[keep], vs[keep], undirected)
+        dead = rng.choice(n, 30, replace=False)
+        ops = make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead)))
+        o.apply(ops)
+        g.apply(ops)
+        assert g.diameter() == o.diameter()[1]
+    gr = synth.rmat_graph(12, 8, 255, seed=29, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    e1 = g.acquire()
+    want1 = o.diameter()[1]
+    rng = synth.rng_for(29, 5)
+    pick = rng.choice(gr.m, gr.m // 3, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    say("diameter rmat12", undirected)
+    assert g.diameter() == o.diameter()[1]
+    assert g.diameter(e1) == want1
+    g.release(e1)
