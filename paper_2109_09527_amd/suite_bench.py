@@ -29,6 +29,10 @@
       The same graph and batch; strongly connected components of the latest
       snapshot, timed, against the oracle's Tarjan on the host.
 
+  python -m paper_2109_09527_amd.suite_bench diameter [--scale 16]
+      Exact diameter of a loaded R-MAT graph (a BFS from every vertex, 256
+      per bit-parallel sweep); the oracle is timed on a scale-14 graph.
+
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
 vertices reached) / wall time.  Kernel figures come from the library's
@@ -247,6 +251,57 @@ def scc(args):
     print(json.dumps(out), flush=True)
 
 
+# Diameter: algorithmic bytes of one bit-parallel BFS level, per visible arc
+# (source id 4 + its 32-byte frontier words) and per vertex (reached, next
+# and frontier words: 3 x 32 read, 3 x 32 written)
+DIAM_BYTES_PER_ARC, DIAM_BYTES_PER_VERTEX = 36, 192
+
+
+def diameter(args):
+    import torch
+    from oracle import Oracle
+    from paper_2109_09527_amd import dg, synth
+    gr = synth.rmat_graph(args.scale, 16, 255, seed=0)
+    g = dg.Graph(gr.n, w_max=255, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    nv, na = g.stats()
+    g.diameter()   # warm-up
+    torch.cuda.synchronize()
+    g.profile(True)
+    g.profile_read(reset=True)
+    t = time.perf_counter()
+    d = g.diameter()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    prof = g.profile_read(reset=True).get("diameter", {})
+    g.profile(False)
+    levels = prof.get("launches", 0)
+    lv_ms = prof.get("total_ms", 0.0) / max(1, levels)
+    algo = DIAM_BYTES_PER_ARC * na + DIAM_BYTES_PER_VERTEX * nv
+    gbs = algo / (lv_ms / 1e3) / 1e9 if lv_ms > 0 else 0.0
+    out = {"workload": f"R-MAT scale {args.scale} directed ({gr.m} edges): exact diameter by a BFS from every "
+                       f"vertex, 256 per bit-parallel sweep",
+           "vertices": nv, "arcs": na, "diameter": d, "seconds": round(dt, 4), "levels": levels,
+           "level_ms": round(lv_ms, 4),
+           "roofline": {"bound": "hbm", "kernel": "k_dm_level", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_level": algo}}
+    if args.cpu_scale > 0:
+        # the oracle's BFS from every vertex grows as V * (V + m): timed on a smaller graph
+        gs = synth.rmat_graph(args.cpu_scale, 16, 255, seed=0)
+        o = Oracle(gs.n, w_max=255)
+        o.apply(synth.load_ops(gs))
+        t = time.perf_counter()
+        _, do = o.diameter()
+        t_cpu = time.perf_counter() - t
+        g2 = dg.Graph(gs.n, w_max=255)
+        g2.apply(synth.load_ops(gs))
+        out["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s per query", "cores": 1, "kind": "oracle",
+                               "sample": f"R-MAT scale {args.cpu_scale}, the whole query"}
+        out["small_graph"] = {"scale": args.cpu_scale, "gpu": g2.diameter(), "oracle": do}
+    print(json.dumps(out), flush=True)
+
+
 # PageRank: algorithmic bytes of one iteration, per visible in-arc (source
 # id 4 + its contribution 8) and per live vertex (rank read and write 16,
 # contribution write 8, out-degree 4, CSR offset 4)
@@ -367,11 +422,14 @@ def main():
     d.add_argument("--scale", type=int, default=20)
     d.add_argument("--reps", type=int, default=3)
     d.add_argument("--cpu", type=int, default=1, help="1: time the oracle on the same snapshot and compare")
+    f = sub.add_parser("diameter")
+    f.add_argument("--scale", type=int, default=16)
+    f.add_argument("--cpu-scale", type=int, default=14, help="graph the oracle is timed on (0: none)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc}[args.what](args)
+    {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc, "diameter": diameter}[args.what](args)
 
 
 if __name__ == "__main__":
