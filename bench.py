@@ -94,7 +94,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(this path is single-GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the store and its queries run on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
