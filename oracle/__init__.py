@@ -70,6 +70,8 @@ def _load():
     lib.orc_scc.argtypes = [P, P]
     lib.orc_diameter.restype = ctypes.c_int
     lib.orc_diameter.argtypes = [P, P]
+    lib.orc_maxflow.restype = ctypes.c_int
+    lib.orc_maxflow.argtypes = [P, u32, u32, P]
     lib.orc_pagerank_perforated.restype = ctypes.c_int
     lib.orc_pagerank_perforated.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
@@ -156,6 +158,12 @@ class Oracle:
         d = ctypes.c_uint32()
         rc = self.lib.orc_diameter(self.h, ctypes.byref(d))
         return rc, d.value
+
+    def maxflow(self, s: int, t: int):
+        """(status, maximum s-t flow with arc weights as capacities)."""
+        f = ctypes.c_int64()
+        rc = self.lib.orc_maxflow(self.h, int(s), int(t), ctypes.byref(f))
+        return rc, f.value
 
     def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000, freeze_below=None):
         """(status, pr[n] float64, iterations, last iteration's largest change);

@@ -688,3 +688,80 @@ int orc_diameter(const orc_graph* g, uint32_t* diameter) {
   *diameter = best;
   return ORC_OK;
 }
+
+/* --------------------------------------------------------- network flow */
+
+/* Maximum flow from s to t of the current state (the GetNF query named in
+ * the preamble; textbook semantics): arc weights are capacities (an
+ * undirected edge carries its weight each way).  Edmonds-Karp (1972):
+ * shortest augmenting paths by BFS over the residual arcs, each arc paired
+ * with a reverse of capacity 0, until t is unreachable.  ORC_E_SOURCE_ABSENT
+ * when s or t is not live, ORC_E_INVALID_ARG when s == t. */
+int orc_maxflow(const orc_graph* g, uint32_t s, uint32_t t, int64_t* flow) {
+  if (s >= g->n || t >= g->n) return ORC_E_VERTEX_RANGE;
+  if (!g->alive[s] || !g->alive[t]) return ORC_E_SOURCE_ABSENT;
+  if (s == t) return ORC_E_INVALID_ARG;
+  const uint32_t n = g->n;
+  uint64_t m = 0;
+  for (uint32_t u = 0; u < n; u++) m += g->out[u].n;
+  /* residual arc 2i: arc i forward; 2i + 1: its reverse */
+  uint32_t* head = (uint32_t*)malloc((size_t)(2 * m + 1) * sizeof(uint32_t));
+  int64_t* cap = (int64_t*)malloc((size_t)(2 * m + 1) * sizeof(int64_t));
+  uint64_t* start = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+  uint64_t* adj = (uint64_t*)malloc((size_t)(2 * m + 1) * sizeof(uint64_t));
+  uint64_t* fill = (uint64_t*)malloc((size_t)(n + 1) * sizeof(uint64_t));
+  int64_t* par = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+  uint32_t* q = (uint32_t*)malloc((size_t)(n + 1) * sizeof(uint32_t));
+  if (!head || !cap || !start || !adj || !fill || !par || !q) {
+    free(head); free(cap); free(start); free(adj); free(fill); free(par); free(q);
+    return ORC_E_OOM;
+  }
+  uint64_t i = 0;
+  for (uint32_t u = 0; u < n; u++)
+    for (uint32_t j = 0; j < g->out[u].n; j++, i++) {
+      const uint32_t v = g->out[u].a[j].v;
+      head[2 * i] = v;       /* u -> v */
+      cap[2 * i] = g->out[u].a[j].w;
+      head[2 * i + 1] = u;   /* v -> u */
+      cap[2 * i + 1] = 0;
+      start[u + 1]++;
+      start[v + 1]++;
+    }
+  for (uint32_t u = 0; u < n; u++) start[u + 1] += start[u];
+  for (uint32_t u = 0; u <= n; u++) fill[u] = start[u];
+  i = 0;
+  for (uint32_t u = 0; u < n; u++)
+    for (uint32_t j = 0; j < g->out[u].n; j++, i++) {
+      adj[fill[u]++] = 2 * i;
+      adj[fill[head[2 * i]]++] = 2 * i + 1;
+    }
+  int64_t total = 0;
+  for (;;) {
+    for (uint32_t u = 0; u < n; u++) par[u] = -1;
+    par[s] = -2;
+    uint32_t hd = 0, tl = 0;
+    q[tl++] = s;
+    while (hd < tl && par[t] == -1) {
+      const uint32_t x = q[hd++];
+      for (uint64_t k = start[x]; k < start[x + 1]; k++) {
+        const uint64_t a = adj[k];
+        const uint32_t y = head[a];
+        if (cap[a] > 0 && par[y] == -1) {
+          par[y] = (int64_t)a;
+          q[tl++] = y;
+        }
+      }
+    }
+    if (par[t] == -1) break;
+    int64_t b = INT64_MAX;
+    for (uint32_t y = t; y != s; y = head[par[y] ^ 1]) if (cap[par[y]] < b) b = cap[par[y]];
+    for (uint32_t y = t; y != s; y = head[par[y] ^ 1]) {
+      cap[par[y]] -= b;
+      cap[par[y] ^ 1] += b;
+    }
+    total += b;
+  }
+  free(head); free(cap); free(start); free(adj); free(fill); free(par); free(q);
+  *flow = total;
+  return ORC_OK;
+}

@@ -17,7 +17,8 @@
  *     Barrier baseline (Alg. 1) in FP64, optionally with the loop
  *     perforation of Alg. 5;
  *   - strongly connected components (GetSCC in the preamble), by Tarjan;
- *   - the diameter (GD in the preamble), by a BFS from every vertex.
+ *   - the diameter (GD in the preamble), by a BFS from every vertex;
+ *   - the maximum s-t flow (GetNF in the preamble), by Edmonds-Karp.
  *
  * Error codes are the integer values of the C boundary's call status.
  */
@@ -74,6 +75,8 @@ int        orc_scc(const orc_graph* g, int32_t* comp);
 /* Diameter: largest hop distance over ordered pairs (u, v) of live vertices
  * with v reachable from u (0 without arcs); one BFS per live vertex. */
 int        orc_diameter(const orc_graph* g, uint32_t* diameter);
+/* Maximum s-t flow with arc weights as capacities (Edmonds-Karp). */
+int        orc_maxflow(const orc_graph* g, uint32_t s, uint32_t t, int64_t* flow);
 int        orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
                                    uint32_t max_iters, double* pr, uint32_t* iters, double* last_change);
 

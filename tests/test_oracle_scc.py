@@ -10,7 +10,7 @@ vertex, and the condensation has no cycle.
 import numpy as np
 import pytest
 
-from oracle import Oracle, OK
+from oracle import Oracle, OK, E_INVALID_ARG
 from paper_2109_09527_amd import synth
 from paper_2109_09527_amd.synth import REMV, make_ops
 from tests.brute import warshall
@@ -153,3 +153,59 @@ def test_diameter_closed_forms():
     assert load(n, np.zeros(n - 1), np.arange(1, n)).diameter()[1] == 1               # out-star
     assert load(n, np.zeros(n - 1), np.arange(1, n), undirected=True).diameter()[1] == 2
     assert Oracle(5).diameter()[1] == 0
+
+
+# ------------------------------------------------------ network flow (GetNF)
+
+def load_w(n, us, vs, ws, undirected=False):
+    o = Oracle(n, undirected=undirected, w_max=255)
+    g = synth.Graph(n, np.asarray(us, np.uint32), np.asarray(vs, np.uint32), np.asarray(ws, np.int32), undirected)
+    rc, _ = o.apply(synth.load_ops(g))
+    assert rc == OK
+    return o
+
+
+def brute_min_cut(o, s, t):
+    """Max-flow min-cut: the least total weight of arcs leaving a vertex set
+    that holds s and not t, over all such sets."""
+    n = o.n
+    us, vs, ws = o.edges()
+    arcs = list(zip(us.tolist(), vs.tolist(), ws.tolist()))
+    if o.undirected:
+        arcs += [(b, a, w) for a, b, w in arcs if a != b]
+    others = [v for v in range(n) if v not in (s, t)]
+    best = None
+    for mask in range(1 << len(others)):
+        S = {s} | {others[i] for i in range(len(others)) if mask >> i & 1}
+        cut = sum(w for a, b, w in arcs if a in S and b not in S)
+        best = cut if best is None else min(best, cut)
+    return best
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_maxflow_equals_min_cut(seed, undirected):
+    rng = synth.rng_for(seed, 96)
+    n = 11
+    m = 20 if undirected else 35
+    us = rng.integers(0, n, m)
+    vs = rng.integers(0, n, m)
+    keep = us != vs
+    ws = rng.integers(1, 20, m)
+    o = load_w(n, us[keep], vs[keep], ws[keep], undirected)
+    for s, t in ((0, n - 1), (3, 5), (n - 1, 0)):
+        rc, f = o.maxflow(s, t)
+        assert rc == OK and f == brute_min_cut(o, s, t), (s, t)
+
+
+def test_maxflow_closed_forms():
+    # a path: its lightest arc; two disjoint paths: the sum; no path: 0
+    path = load_w(4, [0, 1, 2], [1, 2, 3], [7, 3, 9])
+    assert path.maxflow(0, 3) == (OK, 3)
+    assert path.maxflow(3, 0) == (OK, 0)
+    two = load_w(4, [0, 1, 0, 2], [1, 3, 2, 3], [5, 4, 6, 8])
+    assert two.maxflow(0, 3) == (OK, 10)
+    # a flow that must use a reverse residual arc (the classic crossing)
+    x = load_w(4, [0, 0, 1, 1, 2], [1, 2, 2, 3, 3], [1, 1, 1, 1, 1])
+    assert x.maxflow(0, 3) == (OK, 2)
+    assert path.maxflow(1, 1)[0] == E_INVALID_ARG
