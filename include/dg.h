@@ -148,6 +148,16 @@ dg_status dg_scc(dg_graph* g, dg_epoch e, int32_t* comp, uint32_t* n_components,
 dg_status dg_diameter(dg_graph* g, dg_epoch e, uint32_t* diameter, void* stream);
 
 /*
+ * Maximum s-t flow of the snapshot at epoch e (the GetNF query named in the
+ * preamble of arXiv 2109.09527; textbook semantics): arc weights are
+ * capacities, an undirected edge carrying its weight in each direction.
+ * flow (host) receives the value.  DG_E_VERTEX_RANGE / DG_E_SOURCE_ABSENT when
+ * s or t is out of range or not live at e, DG_E_INVALID_ARG when s == t.
+ * The call returns when the value is known.
+ */
+dg_status dg_maxflow(dg_graph* g, dg_epoch e, uint32_t s, uint32_t t, int64_t* flow, void* stream);
+
+/*
  * Snapshot PageRank on epoch e: Eq. (1) of arXiv 2109.09527, iterated as its
  * synchronous Barrier baseline (Alg. 1), in FP64.  With n the live vertices
  * at e and q(v) the visible out-degree, every live vertex starts at 1/n, and

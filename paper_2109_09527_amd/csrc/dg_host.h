@@ -105,6 +105,13 @@ struct DiamScratch {
   void* host = nullptr;
 };
 
+// Maximum flow: the out-arc snapshot with capacities, the arcs by target,
+// flows, and the BFS state of one augmenting search.
+struct FlowScratch {
+  DevBuf off, csr, cap, esrc, keys0, keys1, vals0, vals1, inoff, flow, parent, level, sort, scan, ctl;
+  void* host = nullptr;
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -121,6 +128,7 @@ enum KernelId {
   KID_PAGERANK_NOSYNC,  // one No-Sync PageRank launch
   KID_SCC,          // one colouring or collecting pass of the SCC query
   KID_DIAMETER,     // one level of a bit-parallel BFS sweep (diameter)
+  KID_MAXFLOW,      // one level of an augmenting-path search (maximum flow)
   KID_COUNT
 };
 struct Prof {
@@ -167,6 +175,7 @@ struct dg_graph {
   dg::PrScratch pr;
   dg::SccScratch scc;
   dg::DiamScratch diam;
+  dg::FlowScratch flow;
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
@@ -218,16 +227,20 @@ void free_pr_scratch(PrScratch& s);
 // Snapshot helpers shared by the whole-graph queries (they use the PageRank
 // build scratch): liveness at e as a device byte mask, and the visible arcs
 // at e of the live vertices' slabs in `pool` as a CSR (off: V + 1 entries;
-// csr: the other endpoint of each arc, in slab order); m = arcs.
+// csr: the other endpoint of each arc, in slab order); m = arcs.  With wts,
+// also each arc's weight (forward pool only).
 hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t s);
+hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
+                        DevBuf& off, DevBuf& csr, uint32_t* m, hipStream_t s, DevBuf* wts = nullptr);
 // scc.hip
 dg_status scc_dev(dg_graph* g, uint32_t e, int32_t* comp, uint32_t* n_comp, uint32_t* rounds, hipStream_t s);
 void free_scc_scratch(SccScratch& s);
 // diameter.hip
 dg_status diameter_dev(dg_graph* g, uint32_t e, uint32_t* diameter, hipStream_t s);
 void free_diam_scratch(DiamScratch& s);
-hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
-                        DevBuf& off, DevBuf& csr, uint32_t* m, hipStream_t s);
+// flow.hip
+dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64_t* flow, hipStream_t s);
+void free_flow_scratch(FlowScratch& s);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

@@ -149,6 +149,33 @@ __global__ __launch_bounds__(PR_THREADS) void k_pr_fill(Pool p, const uint64_t* 
   }
 }
 
+// The same as k_pr_fill, with each arc's weight (forward pool) beside it.
+__global__ __launch_bounds__(PR_THREADS) void k_pr_fill_w(Pool p, const uint64_t* desc, const uint32_t* tfirst,
+                                                          const uint32_t* tile_v, uint32_t T, uint32_t e,
+                                                          const uint32_t* toff, uint32_t* csr, uint32_t* wts) {
+  const uint32_t nw = gridDim.x * (PR_THREADS / 64);
+  const uint32_t lane = pr_lane();
+  for (uint32_t t = blockIdx.x * (PR_THREADS / 64) + (threadIdx.x >> 6); t < T; t += nw) {
+    const uint32_t u = tile_v[t];
+    const Slab s = slab_of(p, desc[u]);
+    const uint32_t b = (t - tfirst[u]) * PR_TILE + (lane >> 4);
+    const int j = (int)(lane & 15);
+    uint32_t dst = EMPTY, w = 0;
+    if (b < s.nb) {
+      uint32_t* bp = bucket_ptr(s, b);
+      dst = bp[j];
+      if (dst != EMPTY && visible(*slot_stamp(bp, j, s.words), e)) w = bp[16 + j];
+      else dst = EMPTY;
+    }
+    const unsigned long long m = __ballot(dst != EMPTY);
+    const uint32_t pos = toff[t] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (dst != EMPTY && pos < toff[t + 1]) {
+      csr[pos] = dst;
+      wts[pos] = w;
+    }
+  }
+}
+
 // CSR start of each vertex (id order).
 __global__ void k_pr_offsets(const uint32_t* tfirst, const uint32_t* toff, uint32_t V, uint32_t* off) {
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= V; u += gridDim.x * blockDim.x)
@@ -512,7 +539,7 @@ hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t st) 
 }
 
 hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_t* desc, const uint8_t* live,
-                        DevBuf& off_buf, DevBuf& csr_buf, uint32_t* m_out, hipStream_t st) {
+                        DevBuf& off_buf, DevBuf& csr_buf, uint32_t* m_out, hipStream_t st, DevBuf* wts) {
   PrScratch& s = g->pr;
   const uint32_t V = g->cfg.v_capacity;
   hipError_t he;
@@ -545,7 +572,12 @@ hipError_t snapshot_csr(dg_graph* g, uint32_t e, const Pool& pool, const uint64_
   uint32_t m;
   std::memcpy(&m, s.host, 4);
   if ((he = ensure(csr_buf, (uint64_t)m * 4 + 64)) != hipSuccess) return he;
-  if (T)
+  if (wts && (he = ensure(*wts, (uint64_t)m * 4 + 64)) != hipSuccess) return he;
+  if (T && wts)
+    k_pr_fill_w<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T,
+                                                                    e, tc, csr_buf.as<uint32_t>(),
+                                                                    wts->as<uint32_t>());
+  else if (T)
     k_pr_fill<<<pr_grid(T, PR_THREADS / 64), PR_THREADS, 0, st>>>(pool, desc, tfirst, s.tile_v.as<uint32_t>(), T, e,
                                                                   tc, csr_buf.as<uint32_t>());
   k_pr_offsets<<<pr_grid(V + 1ull, 256), 256, 0, st>>>(tfirst, tc, V, off_buf.as<uint32_t>());

@@ -85,6 +85,7 @@ for _n in ("dg_pagerank", "dg_pagerank_nosync"):
 
 _sig("dg_scc", _i32, _P, _u32, _P, ctypes.POINTER(_u32), _P)
 _sig("dg_diameter", _i32, _P, _u32, ctypes.POINTER(_u32), _P)
+_sig("dg_maxflow", _i32, _P, _u32, _u32, _u32, ctypes.POINTER(ctypes.c_int64), _P)
 
 
 class PageRankOpts(ctypes.Structure):
@@ -276,6 +277,17 @@ class Graph:
         d = _u32()
         self._check(lib.dg_diameter(self.h, epoch, ctypes.byref(d), _stream()))
         return int(d.value)
+
+    def try_maxflow(self, s, t, epoch=EPOCH_LATEST):
+        """(status, maximum s-t flow with arc weights as capacities)."""
+        f = ctypes.c_int64()
+        rc = lib.dg_maxflow(self.h, epoch, int(s), int(t), ctypes.byref(f), _stream())
+        return rc, int(f.value)
+
+    def maxflow(self, s, t, epoch=EPOCH_LATEST) -> int:
+        rc, f = self.try_maxflow(s, t, epoch)
+        self._check(rc)
+        return f
 
     def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
                      nosync=False, freeze_below=None):

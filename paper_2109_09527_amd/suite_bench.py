@@ -33,6 +33,10 @@
       Exact diameter of a loaded R-MAT graph (a BFS from every vertex, 256
       per bit-parallel sweep); the oracle is timed on a scale-14 graph.
 
+  python -m paper_2109_09527_amd.suite_bench maxflow [--scale 16]
+      Maximum s-t flow (weights as capacities) for a few source-sink pairs
+      of a loaded R-MAT graph, each against the oracle's Edmonds-Karp.
+
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
 vertices reached) / wall time.  Kernel figures come from the library's
@@ -302,6 +306,40 @@ def diameter(args):
     print(json.dumps(out), flush=True)
 
 
+def maxflow(args):
+    import torch
+    from oracle import Oracle
+    from paper_2109_09527_amd import dg, synth
+    gr = synth.rmat_graph(args.scale, 16, 255, seed=0)
+    g = dg.Graph(gr.n, w_max=255, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    o = Oracle(gr.n, w_max=255)
+    o.apply(load)
+    src = synth.out_degree_sources(gr, 2 * args.pairs, synth.rng_for(0, 7))
+    runs = []
+    for i in range(0, 2 * args.pairs, 2):
+        s, t = int(src[i]), int(src[i + 1])
+        g.maxflow(s, t)   # warm-up
+        g.profile(True)
+        g.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = g.maxflow(s, t)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        levels = g.profile_read(reset=True).get("maxflow", {}).get("launches", 0)
+        g.profile(False)
+        t0 = time.perf_counter()
+        _, fo = o.maxflow(s, t)
+        t_cpu = time.perf_counter() - t0
+        runs.append({"s": s, "t": t, "flow": f, "equal_to_oracle": f == fo, "seconds": round(dt, 4),
+                     "search_levels": levels, "oracle_seconds": round(t_cpu, 4)})
+    print(json.dumps({"workload": f"R-MAT scale {args.scale} directed ({gr.m} edges), weights 1..255 as "
+                                  f"capacities: maximum s-t flow for {args.pairs} source-sink pairs",
+                      "runs": runs}), flush=True)
+
+
 # PageRank: algorithmic bytes of one iteration, per visible in-arc (source
 # id 4 + its contribution 8) and per live vertex (rank read and write 16,
 # contribution write 8, out-degree 4, CSR offset 4)
@@ -425,11 +463,15 @@ def main():
     f = sub.add_parser("diameter")
     f.add_argument("--scale", type=int, default=16)
     f.add_argument("--cpu-scale", type=int, default=14, help="graph the oracle is timed on (0: none)")
+    h = sub.add_parser("maxflow")
+    h.add_argument("--scale", type=int, default=16)
+    h.add_argument("--pairs", type=int, default=4)
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc, "diameter": diameter}[args.what](args)
+    {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc, "diameter": diameter,
+     "maxflow": maxflow}[args.what](args)
 
 
 if __name__ == "__main__":

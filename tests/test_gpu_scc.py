@@ -163,3 +163,68 @@ def test_diameter_random_and_rmat(dg, undirected):
     assert g.diameter() == o.diameter()[1]
     assert g.diameter(e1) == want1
     g.release(e1)
+
+
+# ------------------------------------------------------ network flow (GetNF)
+
+def build_w(dg, n, us, vs, ws, undirected=False):
+    gr = synth.Graph(n, np.asarray(us, np.uint32), np.asarray(vs, np.uint32), np.asarray(ws, np.int32), undirected)
+    o = Oracle(n, undirected=undirected, w_max=255)
+    g = dg.Graph(n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    return g, o
+
+
+def test_maxflow_closed_forms_and_errors(dg):
+    say("maxflow closed forms")
+    g, o = build_w(dg, 4, [0, 1, 2], [1, 2, 3], [7, 3, 9])
+    assert g.maxflow(0, 3) == 3 and g.maxflow(3, 0) == 0
+    g, o = build_w(dg, 4, [0, 1, 0, 2], [1, 3, 2, 3], [5, 4, 6, 8])
+    assert g.maxflow(0, 3) == 10
+    # needs a reverse residual arc
+    g, o = build_w(dg, 4, [0, 0, 1, 1, 2], [1, 2, 2, 3, 3], [1, 1, 1, 1, 1])
+    assert g.maxflow(0, 3) == 2
+    assert g.try_maxflow(1, 1)[0] == dg.E_INVALID_ARG
+    assert g.try_maxflow(0, 99)[0] == dg.E_VERTEX_RANGE
+    g.remove_vertex(2)
+    assert g.try_maxflow(0, 2)[0] == dg.E_SOURCE_ABSENT
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_maxflow_random_and_rmat(dg, undirected):
+    """Random weighted graphs and R-MAT 10 (weights 1..255), several
+    source-sink pairs, before and after removals (the earlier epoch read
+    afterwards): equal to the oracle's Edmonds-Karp."""
+    for seed in range(3):
+        rng = synth.rng_for(seed, 97)
+        n = 60
+        m = 150 if undirected else 300
+        us = rng.integers(0, n, m)
+        vs = rng.integers(0, n, m)
+        keep = us != vs
+        ws = rng.integers(1, 50, m)
+        say("maxflow random", undirected, seed)
+        g, o = build_w(dg, n, us[keep], vs[keep], ws[keep], undirected)
+        for s, t in rng.integers(0, n, (6, 2)):
+            if s != t:
+                assert g.maxflow(int(s), int(t)) == o.maxflow(int(s), int(t))[1], (seed, s, t)
+    gr = synth.rmat_graph(10, 8, 255, seed=31, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    rng = synth.rng_for(31, 6)
+    srcs = synth.out_degree_sources(gr, 6, rng)
+    pairs = [(int(srcs[i]), int(srcs[i + 1])) for i in range(0, 6, 2)]
+    e1 = g.acquire()
+    want1 = [o.maxflow(s, t)[1] for s, t in pairs]
+    pick = rng.choice(gr.m, gr.m // 4, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    say("maxflow rmat10", undirected)
+    for (s, t), w1 in zip(pairs, want1):
+        assert g.maxflow(s, t) == o.maxflow(s, t)[1]
+        assert g.maxflow(s, t, e1) == w1
+    g.release(e1)
