@@ -108,7 +108,7 @@ struct DiamScratch {
 // Maximum flow: the out-arc snapshot with capacities, the arcs by target,
 // flows, and the BFS state of one augmenting search.
 struct FlowScratch {
-  DevBuf off, csr, cap, esrc, keys0, keys1, vals0, vals1, inoff, flow, parent, level, sort, scan, ctl;
+  DevBuf off, csr, cap, esrc, keys0, keys1, vals0, vals1, inoff, flow, parent, queue, sort, scan, ctl;
   void* host = nullptr;
 };
 

@@ -10,17 +10,22 @@
 // target.
 //
 // One augmentation:
-//   search    level-synchronous BFS from s: k_nf_level takes the vertices of
-//             level L and claims, with atomicCAS on parent[], every vertex
-//             that a residual arc reaches for the first time (the parent
-//             word holds the arc id and its direction); the host reads one
-//             flag and parent[t] after each level
+//   search    level-synchronous BFS from s over compact frontier queues:
+//             k_nf_level gives each vertex of level L one wave, whose lanes
+//             sweep its forward arcs with room and its in-arcs carrying
+//             flow, and claim with atomicCAS on parent[] every vertex that
+//             a residual arc reaches first (the parent word holds the arc id
+//             and its direction); the wave appends its claims to the next
+//             queue with one atomicAdd
 //   augment   one thread walks the parents back from t, takes the smallest
 //             residual and moves that much flow along the path (the walk is
 //             bounded by V steps)
-// The flow value is exact; which maximum flow the arcs carry can differ
-// between runs (any BFS tree gives a shortest path), so only the value is
-// returned.
+// The host enqueues the levels of a search in batches and reads back two
+// flags per batch (t reached, frontier empty); a level launched after
+// either is set returns at once, so a search of up to a batch's depth costs
+// one read-back.  The flow value is exact; which maximum flow the arcs carry
+// can differ between runs (any BFS tree gives a shortest path), so only the
+// value is returned.
 #include <algorithm>
 #include <cstring>
 
@@ -59,11 +64,24 @@ __global__ void k_nf_arcs(const uint32_t* off, const uint32_t* csr, uint32_t V, 
   }
 }
 
-// Start of a search: no parents, s at level 0.
-__global__ void k_nf_reset(uint32_t* parent, int32_t* level, uint32_t V, uint32_t s) {
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
+// Control words: [0] t reached, [1] frontier empty, [2..3] flow total,
+// [4] a walk or a queue went wrong, and three queue lengths, each on a
+// 128-byte line of its own, rotating by level: level L reads length L mod 3,
+// appends to (L+1) mod 3 and clears (L+2) mod 3, the one level L+1 appends to.
+constexpr uint32_t NF_REACHED = 0, NF_EMPTY = 1, NF_TOTAL = 2, NF_BAD = 4, NF_LINE = 32, NF_WORDS = 4 * NF_LINE;
+__device__ inline uint32_t* nf_count(uint32_t* ctl, uint32_t r) { return ctl + NF_LINE * (1 + r); }
+
+// Start of a search: no parents, the queue of level 0 holds s alone.
+__global__ void k_nf_reset(uint32_t* parent, uint32_t* q0, uint32_t* ctl, uint32_t V, uint32_t s) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
     parent[v] = v == s ? NF_ROOT : NF_NONE;
-    level[v] = v == s ? 0 : -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    q0[0] = s;
+    ctl[NF_REACHED] = 0;
+    ctl[NF_EMPTY] = 0;
+    *nf_count(ctl, 0) = 1;
+    *nf_count(ctl, 1) = 0;
+    *nf_count(ctl, 2) = 0;
   }
 }
 
@@ -76,30 +94,63 @@ struct NfArgs {
   const uint32_t* ine;    // arc ids grouped by target
   const uint32_t* flow;
   uint32_t* parent;
-  int32_t* level;
-  uint32_t* grew;
-  uint32_t V;
+  uint32_t* q[2];         // frontier queues, V entries each
+  uint32_t* ctl;
+  uint32_t V, t;
 };
 
-__device__ inline void nf_claim(const NfArgs& a, uint32_t y, uint32_t word, int32_t L) {
-  if (__hip_atomic_load(&a.parent[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != NF_NONE) return;
-  if (atomicCAS(&a.parent[y], NF_NONE, word) == NF_NONE) {
-    a.level[y] = L + 1;
-    if (__hip_atomic_load(a.grew, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-      __hip_atomic_store(a.grew, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Claims y for the lane when it is still unreached; the wave then appends
+// its claims to `out` (one atomicAdd per wave) and flags t.
+__device__ inline void nf_push(const NfArgs& a, bool want, uint32_t y, uint32_t word, uint32_t* out,
+                               uint32_t* count) {
+  bool mine = false;
+  if (want && __hip_atomic_load(&a.parent[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == NF_NONE)
+    mine = atomicCAS(&a.parent[y], NF_NONE, word) == NF_NONE;
+  const unsigned long long bal = __ballot(mine);
+  if (bal == 0) return;
+  const uint32_t lane = __lane_id();
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(count, (uint32_t)__popcll(bal));
+  base = __shfl(base, 0);
+  if (mine) {
+    const uint32_t at = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (at < a.V) out[at] = y;
+    else a.ctl[NF_BAD] = 1u;
+    if (y == a.t) __hip_atomic_store(&a.ctl[NF_REACHED], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// One thread per vertex of level L: forward arcs with room, then reverse
-// arcs (in-arcs carrying flow).
-__global__ __launch_bounds__(NF_THREADS) void k_nf_level(NfArgs a, int32_t L) {
-  for (uint32_t x = blockIdx.x * NF_THREADS + threadIdx.x; x < a.V; x += gridDim.x * NF_THREADS) {
-    if (a.level[x] != L) continue;
-    for (uint32_t k = a.off[x]; k < a.off[x + 1]; k++)
-      if (a.cap[k] > a.flow[k]) nf_claim(a, a.csr[k], k << 1, L);
-    for (uint32_t i = a.inoff[x]; i < a.inoff[x + 1]; i++) {
-      const uint32_t k = a.ine[i];
-      if (a.flow[k] > 0) nf_claim(a, a.esrc[k], (k << 1) | 1u, L);
+__global__ __launch_bounds__(NF_THREADS) void k_nf_level(NfArgs a, uint32_t L) {
+  uint32_t* ctl = a.ctl;
+  if (ctl[NF_REACHED] || ctl[NF_EMPTY]) return;
+  const uint32_t n = *nf_count(ctl, L % 3);
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[NF_EMPTY] = 1u;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nf_count(ctl, (L + 2) % 3) = 0;
+  const uint32_t* in = a.q[L & 1];
+  uint32_t* out = a.q[(L + 1) & 1];
+  uint32_t* count = nf_count(ctl, (L + 1) % 3);
+  const uint32_t lane = __lane_id();
+  const uint32_t nw = gridDim.x * (NF_THREADS / 64);
+  for (uint32_t i = blockIdx.x * (NF_THREADS / 64) + threadIdx.x / 64; i < n; i += nw) {   // wave-uniform
+    if (__builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&ctl[NF_REACHED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      break;
+    const uint32_t x = in[i];
+    const uint32_t ob = a.off[x], oe = a.off[x + 1];
+    for (uint32_t k0 = ob; k0 < oe; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      const bool want = k < oe && a.cap[k] > a.flow[k];
+      nf_push(a, want, want ? a.csr[k] : 0u, k << 1, out, count);
+    }
+    const uint32_t ib = a.inoff[x], ie = a.inoff[x + 1];
+    for (uint32_t i0 = ib; i0 < ie; i0 += 64) {
+      const uint32_t j = i0 + lane;
+      const uint32_t k = j < ie ? a.ine[j] : 0u;
+      const bool want = j < ie && a.flow[k] > 0;
+      nf_push(a, want, want ? a.esrc[k] : 0u, (k << 1) | 1u, out, count);
     }
   }
 }
@@ -148,7 +199,7 @@ __global__ void k_nf_augment(const uint32_t* parent, const uint32_t* csr, const 
 
 void free_flow_scratch(FlowScratch& s) {
   release(s.off); release(s.csr); release(s.cap); release(s.esrc); release(s.keys0); release(s.keys1);
-  release(s.vals0); release(s.vals1); release(s.inoff); release(s.flow); release(s.parent); release(s.level);
+  release(s.vals0); release(s.vals1); release(s.inoff); release(s.flow); release(s.parent); release(s.queue);
   release(s.sort); release(s.scan); release(s.ctl);
   if (s.host) (void)hipHostFree(s.host);
   s.host = nullptr;
@@ -180,9 +231,9 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
       (he = ensure(s.keys1, m * 8ull)) != hipSuccess || (he = ensure(s.vals0, m * 4ull)) != hipSuccess ||
       (he = ensure(s.vals1, m * 4ull)) != hipSuccess || (he = ensure(s.inoff, (V + 1ull) * 4)) != hipSuccess ||
       (he = ensure(s.flow, m * 4ull)) != hipSuccess || (he = ensure(s.parent, V * 4ull)) != hipSuccess ||
-      (he = ensure(s.level, V * 4ull)) != hipSuccess || (he = ensure(s.sort, sort_scratch_words(m) * 4 + 64)) != hipSuccess ||
+      (he = ensure(s.queue, V * 8ull)) != hipSuccess || (he = ensure(s.sort, sort_scratch_words(m) * 4 + 64)) != hipSuccess ||
       (he = ensure(s.scan, scan_scratch_words(V + 1ull) * 4 + 64)) != hipSuccess ||
-      (he = ensure(s.ctl, 64)) != hipSuccess)
+      (he = ensure(s.ctl, NF_WORDS * 4)) != hipSuccess)
     return fail_hip(he, "alloc");
   uint32_t* inoff = s.inoff.as<uint32_t>();
   k_nf_fill<<<nf_grid(V + 1ull, 256), 256, 0, st>>>(inoff, V + 1ull, 0u);
@@ -195,47 +246,53 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
                                     s.vals1.as<uint32_t>(), m, bits, s.sort.as<uint32_t>(), st);
   const uint32_t* ine = alt ? s.vals1.as<uint32_t>() : s.vals0.as<uint32_t>();
   k_nf_fill<<<nf_grid(m, 256), 256, 0, st>>>(s.flow.as<uint32_t>(), m, 0u);
-  uint32_t* ctl = s.ctl.as<uint32_t>();   // [0] grew, [2..3] total, [4] bad
-  k_nf_fill<<<1, 64, 0, st>>>(ctl, 16, 0u);
-  auto* total = reinterpret_cast<unsigned long long*>(ctl + 2);
+  uint32_t* ctl = s.ctl.as<uint32_t>();
+  k_nf_fill<<<1, 64, 0, st>>>(ctl, NF_WORDS, 0u);
+  auto* total = reinterpret_cast<unsigned long long*>(ctl + NF_TOTAL);
+  uint32_t* q0 = s.queue.as<uint32_t>();
   NfArgs a{s.off.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(), s.esrc.as<uint32_t>(), inoff, ine,
-           s.flow.as<uint32_t>(), s.parent.as<uint32_t>(), s.level.as<int32_t>(), ctl, V};
-  const uint32_t g_v = nf_grid(V, NF_THREADS, 4096);
+           s.flow.as<uint32_t>(), s.parent.as<uint32_t>(), {q0, q0 + V}, ctl, V, dst};
+  const uint32_t g_lv = nf_grid(V, NF_THREADS / 64, 1024), g_v = nf_grid(V, 256);
   uint32_t* hw = static_cast<uint32_t*>(s.host);
-  // every augmentation moves at least one unit, and the flow cannot pass the
-  // capacity out of s: the loop ends; the cap only guards against a fault
-  for (uint64_t aug = 0; aug < (1ull << 32); aug++) {
-    k_nf_reset<<<nf_grid(V, 256), 256, 0, st>>>(s.parent.as<uint32_t>(), s.level.as<int32_t>(), V, src);
-    bool reached = false;
-    for (int32_t L = 0; L <= (int32_t)V; L++) {
-      k_nf_fill<<<1, 64, 0, st>>>(ctl, 1, 0u);
-      {
-        ProfScope ps(g, KID_MAXFLOW, st);
-        k_nf_level<<<g_v, NF_THREADS, 0, st>>>(a, L);
-      }
-      if ((he = hipMemcpyAsync(hw, ctl, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-          (he = hipMemcpyAsync(hw + 1, s.parent.as<uint32_t>() + dst, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-          (he = hipStreamSynchronize(st)) != hipSuccess)
-        return fail_hip(he, "search");
-      if (hw[1] != NF_NONE) {
-        reached = true;
-        break;
-      }
-      if (!hw[0]) break;
+  // Every augmentation moves at least one unit, and the flow cannot pass the
+  // capacity out of s, so the loop ends; a search has at most V + 1 levels
+  // (each level but the last claims a vertex).
+  uint32_t batch = 8;
+  k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, V, src);
+  for (uint32_t L = 0;;) {
+    const uint32_t first = L;
+    for (uint32_t j = 0; j < batch; j++, L++) {
+      ProfScope ps(g, KID_MAXFLOW, st);
+      k_nf_level<<<g_lv, NF_THREADS, 0, st>>>(a, L);
     }
-    if (!reached) break;
-    k_nf_augment<<<1, 64, 0, st>>>(s.parent.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(),
-                                   s.esrc.as<uint32_t>(), s.flow.as<uint32_t>(), V, src, dst, total, ctl + 4);
+    if ((he = hipMemcpyAsync(hw, ctl, 32, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (he = hipStreamSynchronize(st)) != hipSuccess)
+      return fail_hip(he, "search");
+    if (hw[NF_BAD]) break;   // reported below
+    if (hw[NF_REACHED]) {
+      k_nf_augment<<<1, 64, 0, st>>>(s.parent.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(),
+                                     s.esrc.as<uint32_t>(), s.flow.as<uint32_t>(), V, src, dst, total, ctl + NF_BAD);
+      k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, V, src);
+      // a search that needed more than one batch doubles the batch
+      if (first > 0) batch = std::min<uint32_t>(batch * 2, 64);
+      L = 0;
+      continue;
+    }
+    if (hw[NF_EMPTY]) break;
+    if (L > V + 1) {
+      g->err = "maxflow: a search ran past V + 1 levels";
+      return DG_E_HIP;
+    }
   }
   if ((he = hipMemcpyAsync(hw, ctl, 32, hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (he = hipStreamSynchronize(st)) != hipSuccess)
     return fail_hip(he, "read back");
-  if (hw[4]) {
-    g->err = "maxflow: an augmenting path did not lead back to the source";
+  if (hw[NF_BAD]) {
+    g->err = "maxflow: an augmenting path did not lead back to the source, or a queue overflowed";
     return DG_E_HIP;
   }
   unsigned long long tot;
-  std::memcpy(&tot, hw + 2, 8);
+  std::memcpy(&tot, hw + NF_TOTAL, 8);
   *flow_out = (int64_t)tot;
   prof_arcs(g, KID_MAXFLOW, m);
   return DG_OK;

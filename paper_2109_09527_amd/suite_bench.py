@@ -33,7 +33,7 @@
       Exact diameter of a loaded R-MAT graph (a BFS from every vertex, 256
       per bit-parallel sweep); the oracle is timed on a scale-14 graph.
 
-  python -m paper_2109_09527_amd.suite_bench maxflow [--scale 16]
+  python -m paper_2109_09527_amd.suite_bench maxflow [--scale 18]
       Maximum s-t flow (weights as capacities) for a few source-sink pairs
       of a loaded R-MAT graph, each against the oracle's Edmonds-Karp.
 
@@ -464,8 +464,8 @@ def main():
     f.add_argument("--scale", type=int, default=16)
     f.add_argument("--cpu-scale", type=int, default=14, help="graph the oracle is timed on (0: none)")
     h = sub.add_parser("maxflow")
-    h.add_argument("--scale", type=int, default=16)
-    h.add_argument("--pairs", type=int, default=4)
+    h.add_argument("--scale", type=int, default=18)
+    h.add_argument("--pairs", type=int, default=3)
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
