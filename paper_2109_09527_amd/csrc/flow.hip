@@ -10,13 +10,15 @@
 // target.
 //
 // One augmentation:
-//   search    level-synchronous BFS from s over compact frontier queues:
-//             k_nf_level gives each vertex of level L one wave, whose lanes
-//             sweep its forward arcs with room and its in-arcs carrying
-//             flow, and claim with atomicCAS on parent[] every vertex that
-//             a residual arc reaches first (the parent word holds the arc id
-//             and its direction); the wave appends its claims to the next
-//             queue with one atomicAdd
+//   search    level-synchronous BFS from s over compact frontier queues
+//             whose entries are (vertex, piece): a vertex's out-arcs and
+//             then its in-arcs, cut into pieces of NF_PIECE, so a hub's arcs
+//             spread over many waves.  k_nf_level gives each entry one wave,
+//             whose lanes take the forward arcs with room and the in-arcs
+//             carrying flow, and claim with atomicCAS on parent[] every
+//             vertex that a residual arc reaches first (the parent word
+//             holds the arc id and its direction); the wave appends the
+//             pieces of its claims to the next queue with one atomicAdd
 //   augment   one thread walks the parents back from t, takes the smallest
 //             residual and moves that much flow along the path (the walk is
 //             bounded by V steps)
@@ -34,6 +36,7 @@
 namespace dg {
 
 constexpr uint32_t NF_THREADS = 256;
+constexpr uint32_t NF_PIECE = 256;   // arcs per queue entry
 constexpr uint32_t NF_NONE = 0xFFFFFFFFu;
 constexpr uint32_t NF_ROOT = 0xFFFFFFFEu;
 
@@ -71,15 +74,23 @@ __global__ void k_nf_arcs(const uint32_t* off, const uint32_t* csr, uint32_t V, 
 constexpr uint32_t NF_REACHED = 0, NF_EMPTY = 1, NF_TOTAL = 2, NF_BAD = 4, NF_LINE = 32, NF_WORDS = 4 * NF_LINE;
 __device__ inline uint32_t* nf_count(uint32_t* ctl, uint32_t r) { return ctl + NF_LINE * (1 + r); }
 
-// Start of a search: no parents, the queue of level 0 holds s alone.
-__global__ void k_nf_reset(uint32_t* parent, uint32_t* q0, uint32_t* ctl, uint32_t V, uint32_t s) {
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x)
+// Pieces of vertex v: its out- and in-arcs together, NF_PIECE at a time.
+__device__ inline uint32_t nf_pieces(const uint32_t* off, const uint32_t* inoff, uint32_t v) {
+  return (off[v + 1] - off[v] + inoff[v + 1] - inoff[v] + NF_PIECE - 1) / NF_PIECE;
+}
+
+// Start of a search: no parents, the queue of level 0 holds the pieces of s.
+__global__ void k_nf_reset(uint32_t* parent, uint2* q0, uint32_t* ctl, const uint32_t* off, const uint32_t* inoff,
+                           uint32_t V, uint32_t s) {
+  const uint32_t np = nf_pieces(off, inoff, s);
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
     parent[v] = v == s ? NF_ROOT : NF_NONE;
+    if (v < np) q0[v] = make_uint2(s, v);   // np <= V: s has at most 2V arcs
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    q0[0] = s;
     ctl[NF_REACHED] = 0;
     ctl[NF_EMPTY] = 0;
-    *nf_count(ctl, 0) = 1;
+    *nf_count(ctl, 0) = np;
     *nf_count(ctl, 1) = 0;
     *nf_count(ctl, 2) = 0;
   }
@@ -94,28 +105,37 @@ struct NfArgs {
   const uint32_t* ine;    // arc ids grouped by target
   const uint32_t* flow;
   uint32_t* parent;
-  uint32_t* q[2];         // frontier queues, V entries each
+  uint2* q[2];            // frontier queues of (vertex, piece), qcap entries each
   uint32_t* ctl;
-  uint32_t V, t;
+  uint32_t V, t, qcap;
 };
 
 // Claims y for the lane when it is still unreached; the wave then appends
-// its claims to `out` (one atomicAdd per wave) and flags t.
-__device__ inline void nf_push(const NfArgs& a, bool want, uint32_t y, uint32_t word, uint32_t* out,
-                               uint32_t* count) {
+// the pieces of its claims to `out` (one atomicAdd per wave) and flags t.
+__device__ inline void nf_push(const NfArgs& a, bool want, uint32_t y, uint32_t word, uint2* out, uint32_t* count) {
   bool mine = false;
   if (want && __hip_atomic_load(&a.parent[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == NF_NONE)
     mine = atomicCAS(&a.parent[y], NF_NONE, word) == NF_NONE;
-  const unsigned long long bal = __ballot(mine);
-  if (bal == 0) return;
+  if (__ballot(mine) == 0) return;
   const uint32_t lane = __lane_id();
+  const uint32_t np = mine ? nf_pieces(a.off, a.inoff, y) : 0u;
+  uint32_t incl = np;   // inclusive prefix sum over the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t x = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += x;
+  }
+  const uint32_t tot = __shfl(incl, 63, 64);
   uint32_t base = 0;
-  if (lane == 0) base = atomicAdd(count, (uint32_t)__popcll(bal));
-  base = __shfl(base, 0);
+  if (lane == 0 && tot) base = atomicAdd(count, tot);
+  base = __shfl(base, 0, 64);
   if (mine) {
-    const uint32_t at = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1));
-    if (at < a.V) out[at] = y;
-    else a.ctl[NF_BAD] = 1u;
+    const uint32_t at = base + incl - np;
+    if (at + np <= a.qcap) {
+      for (uint32_t p = 0; p < np; p++) out[at + p] = make_uint2(y, p);
+    } else {
+      a.ctl[NF_BAD] = 1u;
+    }
     if (y == a.t) __hip_atomic_store(&a.ctl[NF_REACHED], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -129,8 +149,8 @@ __global__ __launch_bounds__(NF_THREADS) void k_nf_level(NfArgs a, uint32_t L) {
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *nf_count(ctl, (L + 2) % 3) = 0;
-  const uint32_t* in = a.q[L & 1];
-  uint32_t* out = a.q[(L + 1) & 1];
+  const uint2* in = a.q[L & 1];
+  uint2* out = a.q[(L + 1) & 1];
   uint32_t* count = nf_count(ctl, (L + 1) % 3);
   const uint32_t lane = __lane_id();
   const uint32_t nw = gridDim.x * (NF_THREADS / 64);
@@ -138,19 +158,31 @@ __global__ __launch_bounds__(NF_THREADS) void k_nf_level(NfArgs a, uint32_t L) {
     if (__builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctl[NF_REACHED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
       break;
-    const uint32_t x = in[i];
-    const uint32_t ob = a.off[x], oe = a.off[x + 1];
-    for (uint32_t k0 = ob; k0 < oe; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      const bool want = k < oe && a.cap[k] > a.flow[k];
-      nf_push(a, want, want ? a.csr[k] : 0u, k << 1, out, count);
-    }
-    const uint32_t ib = a.inoff[x], ie = a.inoff[x + 1];
-    for (uint32_t i0 = ib; i0 < ie; i0 += 64) {
-      const uint32_t j = i0 + lane;
-      const uint32_t k = j < ie ? a.ine[j] : 0u;
-      const bool want = j < ie && a.flow[k] > 0;
-      nf_push(a, want, want ? a.esrc[k] : 0u, (k << 1) | 1u, out, count);
+    const uint2 en = in[i];
+    const uint32_t x = en.x;
+    const uint32_t ob = a.off[x], dout = a.off[x + 1] - ob;
+    const uint32_t ib = a.inoff[x], dtot = dout + a.inoff[x + 1] - ib;
+    const uint32_t j1 = min(dtot, (en.y + 1) * NF_PIECE);
+    for (uint32_t j0 = en.y * NF_PIECE; j0 < j1; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      bool want = false;
+      uint32_t y = 0, word = 0;
+      if (j < dout) {
+        const uint32_t k = ob + j;
+        if (a.cap[k] > a.flow[k]) {
+          want = true;
+          y = a.csr[k];
+          word = k << 1;
+        }
+      } else if (j < j1) {
+        const uint32_t k = a.ine[ib + (j - dout)];
+        if (a.flow[k] > 0) {
+          want = true;
+          y = a.esrc[k];
+          word = (k << 1) | 1u;
+        }
+      }
+      nf_push(a, want, y, word, out, count);
     }
   }
 }
@@ -227,11 +259,18 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
     g->err = "maxflow: too many arcs for 31-bit arc ids";
     return DG_E_INVALID_ARG;
   }
+  // a level's entries: at most one piece per vertex plus one per NF_PIECE
+  // of the arcs seen from both ends
+  const uint64_t qcap = (uint64_t)V + (2ull * m) / NF_PIECE + 64;
+  if (qcap > 0xFFFFFFFFull) {
+    g->err = "maxflow: the frontier queues would pass 2^32 entries";
+    return DG_E_INVALID_ARG;
+  }
   if ((he = ensure(s.esrc, m * 4ull)) != hipSuccess || (he = ensure(s.keys0, m * 8ull)) != hipSuccess ||
       (he = ensure(s.keys1, m * 8ull)) != hipSuccess || (he = ensure(s.vals0, m * 4ull)) != hipSuccess ||
       (he = ensure(s.vals1, m * 4ull)) != hipSuccess || (he = ensure(s.inoff, (V + 1ull) * 4)) != hipSuccess ||
       (he = ensure(s.flow, m * 4ull)) != hipSuccess || (he = ensure(s.parent, V * 4ull)) != hipSuccess ||
-      (he = ensure(s.queue, V * 8ull)) != hipSuccess || (he = ensure(s.sort, sort_scratch_words(m) * 4 + 64)) != hipSuccess ||
+      (he = ensure(s.queue, qcap * 16ull)) != hipSuccess || (he = ensure(s.sort, sort_scratch_words(m) * 4 + 64)) != hipSuccess ||
       (he = ensure(s.scan, scan_scratch_words(V + 1ull) * 4 + 64)) != hipSuccess ||
       (he = ensure(s.ctl, NF_WORDS * 4)) != hipSuccess)
     return fail_hip(he, "alloc");
@@ -249,16 +288,16 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
   uint32_t* ctl = s.ctl.as<uint32_t>();
   k_nf_fill<<<1, 64, 0, st>>>(ctl, NF_WORDS, 0u);
   auto* total = reinterpret_cast<unsigned long long*>(ctl + NF_TOTAL);
-  uint32_t* q0 = s.queue.as<uint32_t>();
+  uint2* q0 = s.queue.as<uint2>();
   NfArgs a{s.off.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(), s.esrc.as<uint32_t>(), inoff, ine,
-           s.flow.as<uint32_t>(), s.parent.as<uint32_t>(), {q0, q0 + V}, ctl, V, dst};
-  const uint32_t g_lv = nf_grid(V, NF_THREADS / 64, 1024), g_v = nf_grid(V, 256);
+           s.flow.as<uint32_t>(), s.parent.as<uint32_t>(), {q0, q0 + qcap}, ctl, V, dst, (uint32_t)qcap};
+  const uint32_t g_lv = nf_grid(qcap, NF_THREADS / 64, 1024), g_v = nf_grid(V, 256);
   uint32_t* hw = static_cast<uint32_t*>(s.host);
   // Every augmentation moves at least one unit, and the flow cannot pass the
   // capacity out of s, so the loop ends; a search has at most V + 1 levels
   // (each level but the last claims a vertex).
   uint32_t batch = 8;
-  k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, V, src);
+  k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, s.off.as<uint32_t>(), inoff, V, src);
   for (uint32_t L = 0;;) {
     const uint32_t first = L;
     for (uint32_t j = 0; j < batch; j++, L++) {
@@ -272,7 +311,7 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
     if (hw[NF_REACHED]) {
       k_nf_augment<<<1, 64, 0, st>>>(s.parent.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(),
                                      s.esrc.as<uint32_t>(), s.flow.as<uint32_t>(), V, src, dst, total, ctl + NF_BAD);
-      k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, V, src);
+      k_nf_reset<<<g_v, 256, 0, st>>>(s.parent.as<uint32_t>(), q0, ctl, s.off.as<uint32_t>(), inoff, V, src);
       // a search that needed more than one batch doubles the batch
       if (first > 0) batch = std::min<uint32_t>(batch * 2, 64);
       L = 0;
