@@ -72,6 +72,8 @@ def _load():
     lib.orc_diameter.argtypes = [P, P]
     lib.orc_maxflow.restype = ctypes.c_int
     lib.orc_maxflow.argtypes = [P, u32, u32, P]
+    lib.orc_dfs.restype = ctypes.c_int
+    lib.orc_dfs.argtypes = [P, u32, P, P]
     lib.orc_pagerank_perforated.restype = ctypes.c_int
     lib.orc_pagerank_perforated.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, u32, P, P, P]
     _lib = lib
@@ -164,6 +166,15 @@ class Oracle:
         f = ctypes.c_int64()
         rc = self.lib.orc_maxflow(self.h, int(s), int(t), ctypes.byref(f))
         return rc, f.value
+
+    def dfs(self, s: int):
+        """(status, disc[n] int32, parent[n] int32): depth-first search from s
+        taking out-neighbours in ascending id order; disc = preorder position,
+        parent = discovering vertex, -1 where not reached (and parent[s])."""
+        disc = np.empty(self.n, dtype=np.int32)
+        par = np.empty(self.n, dtype=np.int32)
+        rc = self.lib.orc_dfs(self.h, int(s), _ptr(disc), _ptr(par))
+        return rc, disc, par
 
     def pagerank(self, damping=0.85, threshold=1e-16, max_iters=10000, freeze_below=None):
         """(status, pr[n] float64, iterations, last iteration's largest change);

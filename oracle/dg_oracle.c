@@ -765,3 +765,61 @@ int orc_maxflow(const orc_graph* g, uint32_t s, uint32_t t, int64_t* flow) {
   *flow = total;
   return ORC_OK;
 }
+
+static int cmp_u32(const void* a, const void* b) {
+  const uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* DFS collect (the GetDFS query named in the preamble; textbook semantics):
+ * depth-first search from s over the visible arcs, each vertex taking its
+ * out-neighbours in ascending id order (recursive DFS, run here with an
+ * explicit stack of vertices and a next-neighbour cursor per vertex).
+ * disc[v] = v's position in the discovery order (preorder), parent[v] = the
+ * vertex whose arc discovered v; both -1 where v is not reached, and
+ * parent[s] = -1. */
+int orc_dfs(const orc_graph* g, uint32_t s, int32_t* disc, int32_t* parent) {
+  int rc = check_source(g, s);
+  if (rc) return rc;
+  const uint32_t n = g->n;
+  uint64_t m = 0;
+  for (uint32_t u = 0; u < n; u++) m += g->out[u].n;
+  uint64_t* start = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+  uint32_t* nb = (uint32_t*)malloc((size_t)(m + 1) * sizeof(uint32_t));
+  uint64_t* cur = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+  uint32_t* stk = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+  if (!start || !nb || !cur || !stk) {
+    free(start); free(nb); free(cur); free(stk);
+    return ORC_E_OOM;
+  }
+  for (uint32_t u = 0; u < n; u++) {
+    start[u + 1] = start[u] + g->out[u].n;
+    for (uint32_t j = 0; j < g->out[u].n; j++) nb[start[u] + j] = g->out[u].a[j].v;
+    qsort(nb + start[u], g->out[u].n, sizeof(uint32_t), cmp_u32);
+  }
+  for (uint32_t v = 0; v < n; v++) {
+    disc[v] = -1;
+    parent[v] = -1;
+  }
+  int32_t t = 0;
+  uint32_t sp = 0;
+  disc[s] = t++;
+  cur[s] = start[s];
+  stk[sp++] = s;
+  while (sp > 0) {
+    const uint32_t x = stk[sp - 1];
+    if (cur[x] == start[x + 1]) {   /* every neighbour of x is done */
+      sp--;
+      continue;
+    }
+    const uint32_t y = nb[cur[x]++];
+    if (disc[y] < 0) {
+      disc[y] = t++;
+      parent[y] = (int32_t)x;
+      cur[y] = start[y];
+      stk[sp++] = y;
+    }
+  }
+  free(start); free(nb); free(cur); free(stk);
+  return ORC_OK;
+}

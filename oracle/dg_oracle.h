@@ -77,6 +77,10 @@ int        orc_scc(const orc_graph* g, int32_t* comp);
 int        orc_diameter(const orc_graph* g, uint32_t* diameter);
 /* Maximum s-t flow with arc weights as capacities (Edmonds-Karp). */
 int        orc_maxflow(const orc_graph* g, uint32_t s, uint32_t t, int64_t* flow);
+/* DFS collect: depth-first search from s taking out-neighbours in ascending
+ * id order; disc[v] = preorder position, parent[v] = discovering vertex (-1
+ * where not reached, and for s). */
+int        orc_dfs(const orc_graph* g, uint32_t s, int32_t* disc, int32_t* parent);
 int        orc_pagerank_perforated(const orc_graph* g, double damping, double threshold, double freeze_below,
                                    uint32_t max_iters, double* pr, uint32_t* iters, double* last_change);
 

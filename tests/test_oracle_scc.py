@@ -209,3 +209,125 @@ def test_maxflow_closed_forms():
     x = load_w(4, [0, 0, 1, 1, 2], [1, 2, 2, 3, 3], [1, 1, 1, 1, 1])
     assert x.maxflow(0, 3) == (OK, 2)
     assert path.maxflow(1, 1)[0] == E_INVALID_ARG
+
+
+# ----------------------------------------------------- DFS collect (GetDFS)
+
+def recursive_dfs(o, s):
+    """Textbook recursive DFS, neighbours in ascending id order."""
+    import sys
+    n = o.n
+    us, vs, _ = o.edges()
+    adj = [[] for _ in range(n)]
+    for a, b in zip(us.tolist(), vs.tolist()):
+        adj[a].append(b)
+        if o.undirected and a != b:
+            adj[b].append(a)
+    disc = [-1] * n
+    par = [-1] * n
+    clock = [0]
+
+    def visit(x):
+        disc[x] = clock[0]
+        clock[0] += 1
+        for y in sorted(adj[x]):
+            if disc[y] < 0:
+                par[y] = x
+                visit(y)
+
+    old = sys.getrecursionlimit()
+    sys.setrecursionlimit(max(old, 4 * n + 100))
+    try:
+        visit(s)
+    finally:
+        sys.setrecursionlimit(old)
+    return np.array(disc, np.int32), np.array(par, np.int32)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_dfs_matches_recursive_definition(seed, undirected):
+    rng = synth.rng_for(seed, 98)
+    n = 40
+    m = 60 if undirected else 100
+    us = rng.integers(0, n, m)
+    vs = rng.integers(0, n, m)
+    keep = us != vs
+    o = load(n, us[keep], vs[keep], undirected)
+    dead = rng.choice(n, 3, replace=False)
+    o.apply(make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead))))
+    for s in range(n):
+        if not o.alive(s):
+            continue
+        rc, disc, par = o.dfs(s)
+        assert rc == OK
+        want_d, want_p = recursive_dfs(o, s)
+        assert np.array_equal(disc, want_d) and np.array_equal(par, want_p), s
+
+
+def test_dfs_closed_forms():
+    n = 12
+    path = load(n, np.arange(n - 1), np.arange(1, n))
+    rc, disc, par = path.dfs(0)
+    assert rc == OK and np.array_equal(disc, np.arange(n)) and par.tolist() == [-1] + list(range(n - 1))
+    # preorder, not postorder: from the middle only the tail is reached
+    rc, disc, par = path.dfs(5)
+    assert disc.tolist() == [-1] * 5 + list(range(n - 5))
+    # an out-star inserted in descending order is still visited ascending
+    star = load(n, np.zeros(n - 1), np.arange(n - 1, 0, -1))
+    rc, disc, par = star.dfs(0)
+    assert np.array_equal(disc, np.arange(n)) and par.tolist() == [-1] + [0] * (n - 1)
+    # 0 -> 2, 0 -> 1, 1 -> 2: 2 is found through 1
+    tri = load(3, [0, 0, 1], [2, 1, 2])
+    assert [a.tolist() for a in tri.dfs(0)[1:]] == [[0, 1, 2], [-1, 0, 1]]
+    # a reverse path from its top
+    rev = load(n, np.arange(1, n), np.arange(n - 1))
+    rc, disc, par = rev.dfs(n - 1)
+    assert np.array_equal(disc, np.arange(n - 1, -1, -1))
+    assert path.dfs(n + 3)[0] != OK
+    path.apply(make_ops(np.array([REMV]), np.array([3]), np.zeros(1)))
+    assert path.dfs(3)[0] != OK
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_dfs_rmat_invariants(undirected):
+    """Properties that fix a DFS in ascending neighbour order: the reached set
+    is BFS's; the tree arcs are arcs; every arc from an earlier-discovered
+    vertex leads into its subtree (white-path theorem); and a parent's
+    smaller neighbours were all discovered before its child."""
+    gr = synth.rmat_graph(11, 8, 255, seed=8, undirected=undirected)
+    o = load(gr.n, gr.u, gr.v, undirected)
+    s = int(synth.out_degree_sources(gr, 1, synth.rng_for(8, 1))[0])
+    rc, disc, par = o.dfs(s)
+    assert rc == OK
+    reached = disc >= 0
+    assert np.array_equal(reached, o.bfs(s)[1] >= 0)
+    r = int(reached.sum())
+    assert sorted(disc[reached].tolist()) == list(range(r))
+    us, vs, _ = o.edges()
+    if undirected:
+        us, vs = np.concatenate([us, vs]), np.concatenate([vs, us])
+    arcs = set(zip(us.tolist(), vs.tolist()))
+    kids = [[] for _ in range(o.n)]
+    for v in np.nonzero(reached)[0].tolist():
+        p = int(par[v])
+        if v == s:
+            assert p == -1
+            continue
+        assert (p, v) in arcs and disc[p] < disc[v]
+        kids[p].append(v)
+    size = np.zeros(o.n, np.int64)
+    for v in sorted(np.nonzero(reached)[0].tolist(), key=lambda x: -disc[x]):
+        size[v] = 1 + sum(size[c] for c in kids[v])
+    nbrs = [[] for _ in range(o.n)]
+    for a, b in arcs:
+        nbrs[a].append(b)
+    for a, b in arcs:
+        if reached[a]:
+            assert reached[b]
+            if disc[a] < disc[b]:
+                assert disc[b] < disc[a] + size[a], (a, b)
+    for v in np.nonzero(reached)[0].tolist():
+        if v != s:
+            p = int(par[v])
+            assert all(disc[y] < disc[v] for y in nbrs[p] if y < v), v
