@@ -158,6 +158,24 @@ dg_status dg_diameter(dg_graph* g, dg_epoch e, uint32_t* diameter, void* stream)
 dg_status dg_maxflow(dg_graph* g, dg_epoch e, uint32_t s, uint32_t t, int64_t* flow, void* stream);
 
 /*
+ * DFS collect from s on the snapshot at epoch e (the GetDFS query named in
+ * the preamble of arXiv 2109.09527; textbook semantics): a depth-first search
+ * over the arcs visible at e, each vertex taking its out-neighbours (for an
+ * undirected graph, its neighbours) in ascending id order.
+ * disc: device array of v_capacity int32, disc[v] = v's position in the
+ *   discovery order (s is 0), -1 where v is not reached.
+ * parent (device, optional): v_capacity int32, the vertex whose arc
+ *   discovered v; -1 for s and for vertices not reached.
+ * n_reached (host, optional): the number of vertices reached.
+ * DG_E_VERTEX_RANGE / DG_E_SOURCE_ABSENT when s is out of range or not live
+ * at e; DG_E_INVALID_ARG when disc or parent is not device memory.  The visit
+ * order is sequential by nature, so the walk runs on one wave.  The call
+ * returns when the walk has ended; the arrays are then complete.
+ */
+dg_status dg_dfs(dg_graph* g, dg_epoch e, uint32_t s, int32_t* disc, int32_t* parent, uint32_t* n_reached,
+                 void* stream);
+
+/*
  * Snapshot PageRank on epoch e: Eq. (1) of arXiv 2109.09527, iterated as its
  * synchronous Barrier baseline (Alg. 1), in FP64.  With n the live vertices
  * at e and q(v) the visible out-degree, every live vertex starts at 1/n, and

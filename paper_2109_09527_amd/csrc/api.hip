@@ -410,6 +410,7 @@ dg_status dg_destroy(dg_graph* g) {
   free_scc_scratch(g->scc);
   free_diam_scratch(g->diam);
   free_flow_scratch(g->flow);
+  free_dfs_scratch(g->dfs);
   free_batch_state(g);
   for (auto& r : g->prof.pending) {
     hipEventDestroy(r.a);
@@ -653,6 +654,19 @@ dg_status dg_maxflow(dg_graph* g, dg_epoch want, uint32_t s, uint32_t t, int64_t
   return note_query(g, maxflow_dev(g, e, s, t, flow, static_cast<hipStream_t>(stream)), stream);
 }
 
+dg_status dg_dfs(dg_graph* g, dg_epoch want, uint32_t s, int32_t* disc, int32_t* parent, uint32_t* n_reached,
+                 void* stream) {
+  if (!g || !disc) return DG_E_INVALID_ARG;
+  if (!is_device_ptr(disc) || (parent && !is_device_ptr(parent)))
+    return fail(g, DG_E_INVALID_ARG, "disc and parent must be device memory");
+  std::lock_guard<std::mutex> lk(g->mu);
+  uint32_t e;
+  dg_status st = resolve_epoch(g, want, &e);
+  if (st != DG_OK) return st;
+  if ((st = check_source(g, e, s)) != DG_OK) return st;
+  return note_query(g, dfs_dev(g, e, s, disc, parent, n_reached, static_cast<hipStream_t>(stream)), stream);
+}
+
 dg_status dg_stats(dg_graph* g, dg_epoch want, uint64_t* n_vertices, uint64_t* n_arcs, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
@@ -685,7 +699,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
                                          "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
-                                         "diameter",     "maxflow"};
+                                         "diameter",     "maxflow",      "dfs"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

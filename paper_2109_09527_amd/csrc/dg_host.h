@@ -112,6 +112,11 @@ struct FlowScratch {
   void* host = nullptr;
 };
 
+struct DfsScratch {
+  DevBuf off, csr, keys0, keys1, vals0, vals1, par, stk, sort, ctl;
+  void* host = nullptr;
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -129,6 +134,7 @@ enum KernelId {
   KID_SCC,          // one colouring or collecting pass of the SCC query
   KID_DIAMETER,     // one level of a bit-parallel BFS sweep (diameter)
   KID_MAXFLOW,      // one level of an augmenting-path search (maximum flow)
+  KID_DFS,          // the one-wave depth-first walk
   KID_COUNT
 };
 struct Prof {
@@ -176,6 +182,7 @@ struct dg_graph {
   dg::SccScratch scc;
   dg::DiamScratch diam;
   dg::FlowScratch flow;
+  dg::DfsScratch dfs;
   dg::Tuning tune;
   dg::Prof prof;
   int concurrent_writers = 0;   // >0 while the serving loop may update under running queries
@@ -241,6 +248,9 @@ void free_diam_scratch(DiamScratch& s);
 // flow.hip
 dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64_t* flow, hipStream_t s);
 void free_flow_scratch(FlowScratch& s);
+dg_status dfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* disc, int32_t* parent, uint32_t* n_reached,
+                  hipStream_t s);
+void free_dfs_scratch(DfsScratch& s);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

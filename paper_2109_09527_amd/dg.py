@@ -86,6 +86,7 @@ for _n in ("dg_pagerank", "dg_pagerank_nosync"):
 _sig("dg_scc", _i32, _P, _u32, _P, ctypes.POINTER(_u32), _P)
 _sig("dg_diameter", _i32, _P, _u32, ctypes.POINTER(_u32), _P)
 _sig("dg_maxflow", _i32, _P, _u32, _u32, _u32, ctypes.POINTER(ctypes.c_int64), _P)
+_sig("dg_dfs", _i32, _P, _u32, _u32, _P, _P, ctypes.POINTER(_u32), _P)
 
 
 class PageRankOpts(ctypes.Structure):
@@ -288,6 +289,21 @@ class Graph:
         rc, f = self.try_maxflow(s, t, epoch)
         self._check(rc)
         return f
+
+    def try_dfs(self, s, epoch=EPOCH_LATEST, disc=None, parent=None):
+        """(status, disc tensor int32, parent tensor int32, vertices reached):
+        depth-first search from s taking neighbours in ascending id order."""
+        disc = torch.empty(self.n, dtype=torch.int32, device="cuda") if disc is None else disc
+        parent = torch.empty(self.n, dtype=torch.int32, device="cuda") if parent is None else parent
+        nr = _u32()
+        rc = lib.dg_dfs(self.h, epoch, int(s), _ptr(disc), _ptr(parent), ctypes.byref(nr), _stream())
+        return rc, disc, parent, int(nr.value)
+
+    def dfs(self, s, epoch=EPOCH_LATEST, disc=None, parent=None):
+        """(disc, parent, vertices reached); raises on a failed call."""
+        rc, disc, parent, nr = self.try_dfs(s, epoch, disc, parent)
+        self._check(rc)
+        return disc, parent, nr
 
     def try_pagerank(self, epoch=EPOCH_LATEST, damping=0.85, threshold=1e-16, max_iters=10000, out=None,
                      nosync=False, freeze_below=None):

@@ -37,6 +37,10 @@
       Maximum s-t flow (weights as capacities) for a few source-sink pairs
       of a loaded R-MAT graph, each against the oracle's Edmonds-Karp.
 
+  python -m paper_2109_09527_amd.suite_bench dfs [--scale 16]
+      DFS collect from one source of a loaded R-MAT graph, against the
+      oracle's preorder and parents.
+
 Each prints one JSON line.  GTEPS = sum over queries (over sources for BC)
 of the edges in the traversed component (visible out-degree summed over the
 vertices reached) / wall time.  Kernel figures come from the library's
@@ -340,6 +344,40 @@ def maxflow(args):
                       "runs": runs}), flush=True)
 
 
+def dfs(args):
+    import numpy as np
+    import torch
+    from oracle import Oracle
+    from paper_2109_09527_amd import dg, synth
+    gr = synth.rmat_graph(args.scale, 16, 255, seed=0)
+    g = dg.Graph(gr.n, w_max=255, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    o = Oracle(gr.n, w_max=255)
+    o.apply(load)
+    s = int(synth.out_degree_sources(gr, 1, synth.rng_for(0, 7))[0])
+    g.dfs(s)   # warm-up
+    g.profile(True)
+    g.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    disc, par, nr = g.dfs(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    walk = g.profile_read(reset=True).get("dfs", {})
+    g.profile(False)
+    t0 = time.perf_counter()
+    _, wd, wp = o.dfs(s)
+    t_cpu = time.perf_counter() - t0
+    equal = bool(np.array_equal(disc.cpu().numpy(), wd) and np.array_equal(par.cpu().numpy(), wp))
+    print(json.dumps({"workload": f"R-MAT scale {args.scale} directed ({gr.m} edges): DFS collect from the "
+                                  f"source {s} (ascending neighbour order)",
+                      "reached": nr, "equal_to_oracle": equal, "seconds": round(dt, 4),
+                      "walk_ms": round(walk.get("total_ms", 0.0), 3),
+                      "us_per_vertex": round(walk.get("total_ms", 0.0) * 1e3 / max(nr, 1), 3),
+                      "oracle_seconds": round(t_cpu, 4)}), flush=True)
+
+
 # PageRank: algorithmic bytes of one iteration, per visible in-arc (source
 # id 4 + its contribution 8) and per live vertex (rank read and write 16,
 # contribution write 8, out-degree 4, CSR offset 4)
@@ -466,12 +504,14 @@ def main():
     h = sub.add_parser("maxflow")
     h.add_argument("--scale", type=int, default=18)
     h.add_argument("--pairs", type=int, default=3)
+    h = sub.add_parser("dfs")
+    h.add_argument("--scale", type=int, default=16)
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
     {"batched": batched, "bc": bc, "pagerank": pagerank, "scc": scc, "diameter": diameter,
-     "maxflow": maxflow}[args.what](args)
+     "maxflow": maxflow, "dfs": dfs}[args.what](args)
 
 
 if __name__ == "__main__":

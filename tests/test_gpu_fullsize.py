@@ -109,6 +109,14 @@ def test_rmat21_eight_epochs_batched_equals_plain(dg):
     for kind, ep, s, out in sample:
         want = (o.bfs if kind == dg.Q_BFS else o.sssp)(s)[1]
         assert np.array_equal(out.cpu().numpy(), want)
+    # DFS collect at the last epoch: 2^21 vertices take the walk whose
+    # discovered set is the disc array (the LDS bitmap would need 256 KB)
+    s = sample[0][2]
+    say("rmat21 dfs from", s)
+    disc, par, nr = g.dfs(s, epochs[-1])
+    _, wd, wp = o.dfs(s)
+    assert np.array_equal(disc.cpu().numpy(), wd) and np.array_equal(par.cpu().numpy(), wp)
+    assert nr == int((wd >= 0).sum())
 
 
 @pytest.mark.timeout(600)

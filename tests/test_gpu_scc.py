@@ -1,6 +1,8 @@
-"""Parity of the snapshot SCC query (dg_scc) with the oracle's Tarjan:
-component labels (smallest member, -1 for vertices not live) must match
-bit for bit, and so must the number of components."""
+"""Parity of the snapshot traversals with the oracle: SCC labels (dg_scc,
+smallest member, -1 for vertices not live) and component counts bit for bit;
+the diameter (dg_diameter); the maximum flow value (dg_maxflow); and the DFS
+preorder and tree parents (dg_dfs), which are unique for ascending neighbour
+order, bit for bit."""
 import numpy as np
 import pytest
 
@@ -227,4 +229,86 @@ def test_maxflow_random_and_rmat(dg, undirected):
     for (s, t), w1 in zip(pairs, want1):
         assert g.maxflow(s, t) == o.maxflow(s, t)[1]
         assert g.maxflow(s, t, e1) == w1
+    g.release(e1)
+
+
+# ----------------------------------------------------- DFS collect (dg_dfs)
+
+def dfs_equal(g, o, s, epoch=None, want=None):
+    if want is None:
+        rc, wd, wp = o.dfs(s)
+        assert rc == 0
+    else:
+        wd, wp = want
+    kw = {} if epoch is None else {"epoch": epoch}
+    disc, par, nr = g.dfs(s, **kw)
+    assert np.array_equal(disc.cpu().numpy(), wd), s
+    assert np.array_equal(par.cpu().numpy(), wp), s
+    assert nr == int((wd >= 0).sum())
+
+
+def test_dfs_closed_forms_and_errors(dg):
+    say("dfs closed forms")
+    n = 300
+    g, o = build(dg, n, np.arange(n - 1), np.arange(1, n))   # a path deeper than a wave
+    disc, par, nr = g.dfs(0)
+    assert np.array_equal(disc.cpu().numpy(), np.arange(n)) and nr == n
+    dfs_equal(g, o, 150)
+    # an out-star of 299 leaves, inserted in descending order (rows of several
+    # 64-arc chunks)
+    g, o = build(dg, n, np.zeros(n - 1), np.arange(n - 1, 0, -1))
+    disc, par, nr = g.dfs(0)
+    assert np.array_equal(disc.cpu().numpy(), np.arange(n))
+    assert par.cpu().numpy().tolist() == [-1] + [0] * (n - 1)
+    g, o = build(dg, 3, [0, 0, 1], [2, 1, 2])
+    disc, par, _ = g.dfs(0)
+    assert disc.cpu().tolist() == [0, 1, 2] and par.cpu().tolist() == [-1, 0, 1]
+    # a hub whose row is scanned again, over several chunks, after a path
+    # through its first neighbour has found every other one
+    us = list(range(1, 200)) + [0] * 199
+    vs = list(range(2, 201)) + list(range(1, 200))
+    g, o = build(dg, 201, us, vs)
+    dfs_equal(g, o, 0)
+    assert g.try_dfs(10 ** 6)[0] == dg.E_VERTEX_RANGE
+    g.remove_vertex(5)
+    o.apply(make_ops(np.array([REMV]), np.array([5]), np.zeros(1)))
+    assert g.try_dfs(5)[0] == dg.E_SOURCE_ABSENT
+    dfs_equal(g, o, 0)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_dfs_random_and_rmat(dg, undirected):
+    """Random graphs with dead vertices and R-MAT 12 before and after removing
+    a quarter of its edges (the earlier epoch read afterwards): preorder and
+    parents equal to the oracle's for several sources."""
+    for seed in range(3):
+        rng = synth.rng_for(seed, 99)
+        n = 500
+        m = 900 if undirected else 1600
+        us = rng.integers(0, n, m)
+        vs = rng.integers(0, n, m)
+        keep = us != vs
+        say("dfs random", undirected, seed)
+        g, o = build(dg, n, us[keep], vs[keep], undirected)
+        dead = rng.choice(n, 10, replace=False)
+        ops = make_ops(np.full(len(dead), REMV), dead, np.zeros(len(dead)))
+        o.apply(ops)
+        g.apply(ops)
+        for s in rng.integers(0, n, 6).tolist():
+            if o.alive(s):
+                dfs_equal(g, o, s)
+    gr = synth.rmat_graph(12, 16, 255, seed=41, undirected=undirected)
+    g, o = build(dg, gr.n, gr.u, gr.v, undirected)
+    rng = synth.rng_for(41, 3)
+    srcs = [int(x) for x in synth.out_degree_sources(gr, 3, rng)]
+    e1 = g.acquire()
+    want1 = {s: o.dfs(s)[1:] for s in srcs}
+    pick = rng.choice(gr.m, gr.m // 4, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    say("dfs rmat12", undirected)
+    for s in srcs:
+        dfs_equal(g, o, s)
+        dfs_equal(g, o, s, epoch=e1, want=want1[s])
     g.release(e1)
