@@ -877,7 +877,60 @@ struct BatchState {
   DevBuf gang_scratch, gq, gsrc, gsync, gctrl, gstatus;
   int gang_cap = 0;              // resident workgroups of the gang kernel
   DevBuf bc_part;                // per-source dependency arrays of split BC queries
+  uint32_t* hflag = nullptr;     // completion sequence number (coherent pinned memory)
+  uint32_t seq = 0;
+  void* hres = nullptr;          // pinned landing area of per-query statuses and control records
+  size_t hres_bytes = 0;
 };
+
+// Completion of everything enqueued on s so far, seen by polling: a one-wave
+// kernel stores a sequence number to coherent pinned memory (system scope)
+// and the host spins on it, so the wait does not depend on how the runtime
+// blocks inside a stream synchronisation.  Not seen within two seconds, the
+// wait falls back to synchronising the stream, which reports any device
+// error.
+__global__ void k_batch_signal(uint32_t* flag, uint32_t seq) {
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+static hipError_t host_area(BatchState* bs, size_t bytes) {
+  hipError_t e;
+  if (!bs->hflag) {
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&bs->hflag), 64, hipHostMallocCoherent)) != hipSuccess) {
+      bs->hflag = nullptr;
+      return e;
+    }
+    *bs->hflag = 0;
+    bs->seq = 0;
+  }
+  if (bs->hres_bytes < bytes) {
+    if (bs->hres) (void)hipHostFree(bs->hres);
+    bs->hres = nullptr;
+    bs->hres_bytes = 0;
+    if ((e = hipHostMalloc(&bs->hres, bytes, hipHostMallocDefault)) != hipSuccess) {
+      bs->hres = nullptr;
+      return e;
+    }
+    bs->hres_bytes = bytes;
+  }
+  return hipSuccess;
+}
+
+static hipError_t wait_polled(BatchState* bs, hipStream_t s) {
+  const uint32_t seq = ++bs->seq;
+  k_batch_signal<<<1, 64, 0, s>>>(bs->hflag, seq);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 1; __atomic_load_n(bs->hflag, __ATOMIC_ACQUIRE) != seq; spin++) {
+    if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (__atomic_load_n(bs->hflag, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
+      break;
+    }
+  }
+  return hipSuccess;
+}
 
 static std::mutex g_engine_mu;   // one engine launch enqueued per process at a time
 // Engine state per (graph, lane): each lane owns its buffers, so launches of
@@ -904,6 +957,8 @@ void free_batch_state(dg_graph* g) {
                       &b->live, &b->ctrl, &b->gang_scratch, &b->gq, &b->gsrc, &b->gsync, &b->gctrl, &b->gstatus,
                       &b->bc_part})
       release(*d);
+    if (b->hflag) (void)hipHostFree(b->hflag);
+    if (b->hres) (void)hipHostFree(b->hres);
     delete b;
     it = g_states.erase(it);
   }
@@ -1062,10 +1117,15 @@ static dg_status run_sssp_gangs(dg_graph* g, BatchState* bs, const Store& st_, c
     if ((e = hipGetLastError()) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("gang launch: ") + hipGetErrorString(e));
     Ctrl cres;
-    if ((e = hipMemcpyAsync(gst.data(), bs->gstatus.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&cres, bs->gctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
+    const size_t st_bytes = align256(n * 4ull);
+    if ((e = host_area(bs, st_bytes + sizeof(Ctrl))) != hipSuccess ||
+        (e = hipMemcpyAsync(bs->hres, bs->gstatus.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(static_cast<char*>(bs->hres) + st_bytes, bs->gctrl.p, sizeof(cres),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = wait_polled(bs, s)) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("gang: ") + hipGetErrorString(e));
+    std::memcpy(gst.data(), bs->hres, n * 4);
+    std::memcpy(&cres, static_cast<char*>(bs->hres) + st_bytes, sizeof(cres));
     if (cres.abort) return bfail(g, DG_E_HIP, "gang engine: a barrier timed out");
     if (cres.done != n) return bfail(g, DG_E_HIP, "gang engine: the gang could not assemble");
     prof_arcs(g, KID_BATCH_SSSP, cres.arcs);
@@ -1328,10 +1388,15 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
         return bfail(g, DG_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
     }
     Ctrl cres[3];
-    if ((e = hipMemcpyAsync(st.data(), bs->status.p, nj * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(cres, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
+    const size_t st_bytes = align256(nj * 4ull);
+    if ((e = host_area(bs, st_bytes + sizeof(cres))) != hipSuccess ||
+        (e = hipMemcpyAsync(bs->hres, bs->status.p, nj * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(static_cast<char*>(bs->hres) + st_bytes, bs->ctrl.p, sizeof(cres), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = wait_polled(bs, s)) != hipSuccess)
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+    std::memcpy(st.data(), bs->hres, nj * 4);
+    std::memcpy(cres, static_cast<char*>(bs->hres) + st_bytes, sizeof(cres));
     if (!by_kind[DG_Q_SSSP].empty()) {
       dg_status r = run_sssp_gangs(g, bs, st_, tune, fast, share, qd, by_kind[DG_Q_SSSP], st, budget, s);
       if (r != DG_OK) return r;
