@@ -362,9 +362,9 @@ class Graph:
 
     def profile_read(self, reset: bool = True) -> dict:
         """{family: {"launches", "total_ms", "arcs"}} for kernel families with launches."""
-        arr = (KernelStat * 16)()
+        arr = (KernelStat * 32)()
         n = _u32()
-        self._check(lib.dg_profile_read(self.h, arr, 16, ctypes.byref(n), 1 if reset else 0))
+        self._check(lib.dg_profile_read(self.h, arr, 32, ctypes.byref(n), 1 if reset else 0))
         out = {}
         for i in range(n.value):
             k = arr[i]
