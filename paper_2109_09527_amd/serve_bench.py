@@ -18,6 +18,7 @@ Usage: python -m paper_2109_09527_amd.serve_bench [--scale 22] [--rate 2000] [--
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import sys
 import time
@@ -35,6 +36,10 @@ def main():
     ap.add_argument("--lanes", default="1", help="query lanes (engine launches in flight); a comma-separated list runs each")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
+    # the drivers are short-lived and make few reference cycles: no collector
+    # pause of this interpreter lands inside a timed region
+    gc.collect()
+    gc.disable()
 
     import torch
     from paper_2109_09527_amd import dg, synth

@@ -49,6 +49,7 @@ HIP-event profile on the stream the kernels run on.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import sys
 import time
@@ -507,6 +508,10 @@ def main():
     h = sub.add_parser("dfs")
     h.add_argument("--scale", type=int, default=16)
     args = ap.parse_args()
+    # the drivers are short-lived and make few reference cycles: no collector
+    # pause of this interpreter lands inside a timed region
+    gc.collect()
+    gc.disable()
     import torch
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
