@@ -110,6 +110,8 @@ struct DiamScratch {
 struct FlowScratch {
   DevBuf off, csr, cap, esrc, keys0, keys1, vals0, vals1, inoff, flow, parent, queue, sort, scan, ctl;
   void* host = nullptr;
+  void* pub = nullptr;   // coherent pinned: polled control words and their sequence number
+  uint32_t seq = 0;
 };
 
 struct DfsScratch {

@@ -29,6 +29,7 @@
 // can differ between runs (any BFS tree gives a shortest path), so only the
 // value is returned.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "dg_host.h"
@@ -229,12 +230,23 @@ __global__ void k_nf_augment(const uint32_t* parent, const uint32_t* csr, const 
   *total += b;
 }
 
+// The first eight control words to coherent pinned memory, then the
+// sequence number (system scope): the host polls it instead of
+// synchronising the stream after every batch of levels.
+__global__ void k_nf_publish(const uint32_t* ctl, uint32_t* host, uint32_t seq) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < 8; i++) host[i] = ctl[i];
+  __hip_atomic_store(&host[8], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 void free_flow_scratch(FlowScratch& s) {
   release(s.off); release(s.csr); release(s.cap); release(s.esrc); release(s.keys0); release(s.keys1);
   release(s.vals0); release(s.vals1); release(s.inoff); release(s.flow); release(s.parent); release(s.queue);
   release(s.sort); release(s.scan); release(s.ctl);
   if (s.host) (void)hipHostFree(s.host);
   s.host = nullptr;
+  if (s.pub) (void)hipHostFree(s.pub);
+  s.pub = nullptr;
 }
 
 dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64_t* flow_out, hipStream_t st) {
@@ -248,6 +260,13 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
   hipError_t he;
   if (!s.host && (he = hipHostMalloc(&s.host, 64, hipHostMallocDefault)) != hipSuccess)
     return fail_hip(he, "host buffer");
+  if (!s.pub) {
+    if ((he = hipHostMalloc(&s.pub, 64, hipHostMallocCoherent)) != hipSuccess) {
+      s.pub = nullptr;
+      return fail_hip(he, "host buffer");
+    }
+    std::memset(s.pub, 0, 64);
+  }
   DevBuf& live = g->pr.live;
   if ((he = snapshot_live(g, e, live, st)) != hipSuccess) return fail_hip(he, "liveness");
   uint32_t m = 0;
@@ -304,9 +323,21 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
       ProfScope ps(g, KID_MAXFLOW, st);
       k_nf_level<<<g_lv, NF_THREADS, 0, st>>>(a, L);
     }
-    if ((he = hipMemcpyAsync(hw, ctl, 32, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (he = hipStreamSynchronize(st)) != hipSuccess)
-      return fail_hip(he, "search");
+    {
+      uint32_t* pub = static_cast<uint32_t*>(s.pub);
+      const uint32_t seq = ++s.seq;
+      k_nf_publish<<<1, 64, 0, st>>>(ctl, pub, seq);
+      if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "search");
+      const auto t0 = std::chrono::steady_clock::now();
+      for (uint32_t spin = 1; __atomic_load_n(&pub[8], __ATOMIC_ACQUIRE) != seq; spin++) {
+        if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+          if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "search");
+          if (__atomic_load_n(&pub[8], __ATOMIC_ACQUIRE) != seq) return fail_hip(hipErrorUnknown, "search");
+          break;
+        }
+      }
+      std::memcpy(hw, pub, 32);
+    }
     if (hw[NF_BAD]) break;   // reported below
     if (hw[NF_REACHED]) {
       k_nf_augment<<<1, 64, 0, st>>>(s.parent.as<uint32_t>(), s.csr.as<uint32_t>(), s.cap.as<uint32_t>(),
