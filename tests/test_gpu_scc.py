@@ -312,3 +312,24 @@ def test_dfs_random_and_rmat(dg, undirected):
         dfs_equal(g, o, s)
         dfs_equal(g, o, s, epoch=e1, want=want1[s])
     g.release(e1)
+
+
+def test_dfs_abi_optional_outputs(dg):
+    """dg_dfs through the C ABI with the optional parent array and reached
+    count left null: disc alone, equal to the oracle's; a host disc array is
+    rejected."""
+    say("dfs abi optional outputs")
+    rng = synth.rng_for(5, 99)
+    n = 300
+    us = rng.integers(0, n, 900)
+    vs = rng.integers(0, n, 900)
+    keep = us != vs
+    g, o = build(dg, n, us[keep], vs[keep])
+    disc = torch.empty(n, dtype=torch.int32, device="cuda")
+    for s in (0, 17, 123):
+        rc = dg.lib.dg_dfs(g.h, dg.EPOCH_LATEST, s, dg._ptr(disc), None, None, dg._stream())
+        assert rc == 0
+        assert np.array_equal(disc.cpu().numpy(), o.dfs(s)[1]), s
+    host = np.zeros(n, dtype=np.int32)
+    rc = dg.lib.dg_dfs(g.h, dg.EPOCH_LATEST, 0, host.ctypes.data, None, None, dg._stream())
+    assert rc == dg.E_INVALID_ARG
