@@ -127,6 +127,25 @@ dg_status dg_sssp(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* st
 dg_status dg_bc(dg_graph* g, dg_epoch e, const uint32_t* srcs, uint32_t k, double* bc, void* stream);
 
 /*
+ * dg_bfs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and result as dg_bfs; dist must be device memory.  Every
+ * scratch buffer of the search (frontier queues and their chunk maps,
+ * bitmaps, counters) is carved from one fixed device area of
+ * DG_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first use on
+ * that GPU until the process ends; the call makes no device or pinned-host
+ * allocation, and waits for its stream between levels instead of polling
+ * pinned memory.  A graph whose search needs more than the area
+ * (about 48 B per vertex of capacity plus 2.5 B per bucket of the slab
+ * pools; R-MAT scale 20 fits) is rejected with DG_E_OUT_OF_MEMORY and a
+ * message giving both sizes, before any work is enqueued.  All calls on one
+ * GPU share its area: calls that overlap on one GPU (from two threads, or on
+ * two streams with work in flight) race and must not be issued.
+ */
+#define DG_NOALLOC_SCRATCH_BYTES (96ull << 20)
+dg_status dg_bfs_noalloc(dg_graph* g, dg_epoch e, uint32_t src, int32_t* dist, void* stream);
+
+/*
  * Strongly connected components of the snapshot at epoch e (the GetSCC query
  * named in the preamble of arXiv 2109.09527; textbook semantics): u and v
  * share a component iff each reaches the other.  comp: device array of

@@ -390,6 +390,14 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   st.cursor = g->cursor.as<unsigned long long>();
   st.alive = g->alive.as<uint8_t>();
   g->vfirst.assign(V, 0);
+  // set-up that later calls must not repeat: the event updates wait on, and
+  // the address of this device's fixed area for the allocation-free calls
+  if ((e = hipEventCreateWithFlags(&g->last_query, hipEventDisableTiming)) != hipSuccess ||
+      (e = noalloc_setup(g->device)) != hipSuccess) {
+    std::string msg = std::string("set-up: ") + hipGetErrorString(e);
+    dg_destroy(g);
+    return fail(nullptr, DG_E_HIP, msg);
+  }
   *out = g;
   return DG_OK;
 }
@@ -532,10 +540,6 @@ dg_status dg_compact(dg_graph* g, void* stream) {
 
 static dg_status note_query(dg_graph* g, dg_status st, void* stream) {
   if (st != DG_OK) return st;
-  if (!g->last_query && hipEventCreateWithFlags(&g->last_query, hipEventDisableTiming) != hipSuccess) {
-    g->last_query = nullptr;
-    return fail(g, DG_E_HIP, "event creation");
-  }
   if (hipEventRecord(g->last_query, static_cast<hipStream_t>(stream)) != hipSuccess)
     return fail(g, DG_E_HIP, "event record");
   return DG_OK;
@@ -556,6 +560,26 @@ dg_status dg_bfs(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void* 
   if (st == DG_OK) st = check_source(g, e, src);
   if (st != DG_OK) return st;
   return note_query(g, bfs_dev(g, e, src, dist, static_cast<hipStream_t>(stream), g->qs), stream);
+}
+
+dg_status dg_bfs_noalloc(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void* stream) {
+  if (!g || !dist) return DG_E_INVALID_ARG;
+  if (!is_device_ptr(dist)) return fail(g, DG_E_INVALID_ARG, "dist must be device memory");
+  std::lock_guard<std::mutex> lk(g->mu);
+  uint32_t e;
+  dg_status st = resolve_epoch(g, want, &e);
+  if (st == DG_OK) st = check_source(g, e, src);
+  if (st != DG_OK) return st;
+  const uint64_t need = bfs_fixed_layout(g, nullptr, nullptr);
+  if (need > DG_NOALLOC_SCRATCH_BYTES)
+    return fail(g, DG_E_OUT_OF_MEMORY,
+                "dg_bfs_noalloc: this graph's search needs " + std::to_string(need) +
+                    " bytes of scratch; the fixed area holds " + std::to_string(DG_NOALLOC_SCRATCH_BYTES));
+  char* area = static_cast<char*>(noalloc_area(g->device));
+  if (!area) return fail(g, DG_E_HIP, "dg_bfs_noalloc: fixed area not set up on this device");
+  QueryScratch q;
+  bfs_fixed_layout(g, area, &q);
+  return note_query(g, bfs_dev(g, e, src, dist, static_cast<hipStream_t>(stream), q), stream);
 }
 
 dg_status dg_sssp(dg_graph* g, dg_epoch want, uint32_t src, int32_t* dist, void* stream) {

@@ -78,6 +78,11 @@ struct QueryScratch {
   void* host_counters = nullptr;
   void* host_pub = nullptr;     // coherent pinned block the device publishes counters into
   uint32_t pub_seq = 0;         // sequence number of the last publication
+  // fixed: the buffers are carved from a device area that is neither grown
+  // nor freed, and counters are published into dev_pub (device memory,
+  // copied back) instead of host_pub
+  bool fixed = false;
+  void* dev_pub = nullptr;
   uint64_t items_cap = 0, chunks_cap = 0;
   uint32_t lch = 6;             // log2 of the chunk size in buckets
 };
@@ -226,6 +231,13 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
 dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, double* bc, hipStream_t s,
                  QueryScratch& q);
 dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hipStream_t s);
+// Lays a BFS's buffers out from base into q (marked fixed) and returns the
+// bytes they take; with q null only the size.
+uint64_t bfs_fixed_layout(const dg_graph* g, char* base, QueryScratch* q);
+// noalloc.hip: finds the device address of the fixed area on `device`
+// (which must be current) once; noalloc_area returns it (null before set-up).
+hipError_t noalloc_setup(int device);
+void* noalloc_area(int device);
 void free_query_scratch(QueryScratch& q);
 
 // pagerank.hip

@@ -203,22 +203,91 @@ __global__ void k_publish(const QCounters* cnt, const CountStripe* st, int slot,
   __hip_atomic_store(&h->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
-  hipError_t e;
+// Bytes of each plain-query buffer for this graph (0 = not needed by the
+// query kinds asked for).
+struct QuerySizes {
+  uint64_t items, chunks;
+  uint64_t qa, qb, cmap_a, cmap_b, bm0, bm1, counters, fb, stamp, flag8, rlist, rstamp, fa, sigma, delta, level;
+};
+
+static QuerySizes query_sizes(const dg_graph* g, bool sssp, bool bc) {
+  QuerySizes z{};
   const uint64_t V = g->cfg.v_capacity;
-  uint64_t items = items_capacity(g);
-  if ((e = ensure(q.qa, items * sizeof(Item))) != hipSuccess) return e;
-  if ((e = ensure(q.qb, items * sizeof(Item))) != hipSuccess) return e;
-  q.items_cap = items;
-  const uint64_t chunks = chunks_capacity(g);
-  if ((e = ensure(q.cmap_a, chunks * 4)) != hipSuccess) return e;
-  if ((e = ensure(q.cmap_b, chunks * 4)) != hipSuccess) return e;
-  q.chunks_cap = chunks;
+  z.items = items_capacity(g);
+  z.chunks = chunks_capacity(g);
+  z.qa = z.qb = z.items * sizeof(Item);
+  z.cmap_a = z.cmap_b = z.chunks * 4;
+  z.bm0 = z.bm1 = ((V + 31) / 32 + 1) * 4;
+  z.counters = COUNTERS_BYTES;
+  // bottom-up chunk items of long in-slabs
+  if (!sssp && !bc) z.fb = (V + std::max(g->st.fp.cap, g->st.rp.cap) / BU_CHUNK + 1024) * sizeof(Item);
+  if (sssp) z.stamp = z.flag8 = z.rlist = z.rstamp = V * 4 + 64;
+  if (bc) {
+    z.fa = V * 4 + 64;
+    z.sigma = z.delta = V * 8 + 64;
+    z.level = V * 4 + 64;
+  }
+  return z;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// A BFS's buffers laid out one after another from base (each 256-byte
+// aligned), followed by the block its counters are published into;
+// returns the bytes used.  With q null only the size is computed.
+uint64_t bfs_fixed_layout(const dg_graph* g, char* base, QueryScratch* q) {
+  const QuerySizes z = query_sizes(g, false, false);
+  uint64_t off = 0;
+  auto carve = [&](DevBuf* b, uint64_t bytes) {
+    if (q) {
+      b->p = base + off;
+      b->bytes = bytes;
+    }
+    off += align256(bytes);
+  };
+  QueryScratch dummy;
+  QueryScratch& t = q ? *q : dummy;
+  carve(&t.qa, z.qa);
+  carve(&t.qb, z.qb);
+  carve(&t.cmap_a, z.cmap_a);
+  carve(&t.cmap_b, z.cmap_b);
+  carve(&t.bm0, z.bm0);
+  carve(&t.bm1, z.bm1);
+  carve(&t.counters, z.counters);
+  carve(&t.fb, z.fb);
+  DevBuf pub;
+  carve(&pub, sizeof(HostCounters));
+  if (q) {
+    q->fixed = true;
+    q->dev_pub = pub.p;
+  }
+  return off;
+}
+
+static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, bool bc) {
+  const QuerySizes z = query_sizes(g, sssp, bc);
+  q.items_cap = z.items;
+  q.chunks_cap = z.chunks;
   q.lch = log2_of(g->tune.chunk_buckets);
-  uint64_t bmw = (V + 31) / 32 + 1;
-  if ((e = ensure(q.bm0, bmw * 4)) != hipSuccess) return e;
-  if ((e = ensure(q.bm1, bmw * 4)) != hipSuccess) return e;
-  if ((e = ensure(q.counters, COUNTERS_BYTES)) != hipSuccess) return e;
+  if (q.fixed) {
+    // a fixed area is never grown: its layout was computed from the same sizes
+    const std::pair<const DevBuf*, uint64_t> need[] = {
+        {&q.qa, z.qa},       {&q.qb, z.qb},       {&q.cmap_a, z.cmap_a}, {&q.cmap_b, z.cmap_b},
+        {&q.bm0, z.bm0},     {&q.bm1, z.bm1},     {&q.counters, z.counters}, {&q.fb, z.fb},
+        {&q.stamp, z.stamp}, {&q.flag8, z.flag8}, {&q.rlist, z.rlist},   {&q.rstamp, z.rstamp},
+        {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level}};
+    for (const auto& n : need)
+      if (n.second && (!n.first->p || n.first->bytes < n.second)) return hipErrorInvalidValue;
+    return q.dev_pub ? hipSuccess : hipErrorInvalidValue;
+  }
+  hipError_t e;
+  const std::pair<DevBuf*, uint64_t> need[] = {
+      {&q.qa, z.qa},       {&q.qb, z.qb},       {&q.cmap_a, z.cmap_a}, {&q.cmap_b, z.cmap_b},
+      {&q.bm0, z.bm0},     {&q.bm1, z.bm1},     {&q.counters, z.counters}, {&q.fb, z.fb},
+      {&q.stamp, z.stamp}, {&q.flag8, z.flag8}, {&q.rlist, z.rlist},   {&q.rstamp, z.rstamp},
+      {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level}};
+  for (const auto& n : need)
+    if (n.second && (e = ensure(*n.first, n.second)) != hipSuccess) return e;
   if (!q.host_pub) {
     if ((e = hipHostMalloc(&q.host_pub, sizeof(HostCounters), hipHostMallocCoherent)) != hipSuccess) return e;
     std::memset(q.host_pub, 0, sizeof(HostCounters));
@@ -226,23 +295,6 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
   }
   if (!q.host_counters) {
     if ((e = hipHostMalloc(&q.host_counters, COUNTERS_BYTES, hipHostMallocDefault)) != hipSuccess) return e;
-  }
-  if (!sssp && !bc) {
-    // bottom-up chunk items of long in-slabs
-    uint64_t big = V + std::max(g->st.fp.cap, g->st.rp.cap) / BU_CHUNK + 1024;
-    if ((e = ensure(q.fb, big * sizeof(Item))) != hipSuccess) return e;
-  }
-  if (sssp) {
-    if ((e = ensure(q.stamp, V * 4 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.flag8, V * 4 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.rlist, V * 4 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.rstamp, V * 4 + 64)) != hipSuccess) return e;
-  }
-  if (bc) {
-    if ((e = ensure(q.fa, V * 4 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.sigma, V * 8 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.delta, V * 8 + 64)) != hipSuccess) return e;
-    if ((e = ensure(q.level, V * 4 + 64)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -269,10 +321,25 @@ static CountStripe* stripes_of(QueryScratch& q, int slot) {
 // short).  A publication not seen within two seconds falls back to
 // synchronising the stream, which reports any device error.
 static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
-  HostCounters* h = static_cast<HostCounters*>(q.host_pub);
   const uint32_t seq = ++q.pub_seq;
+  hipError_t e;
+  if (q.fixed) {
+    // a fixed area has no pinned host block: publish on the device, copy
+    // back and wait for the stream
+    HostCounters* d = static_cast<HostCounters*>(q.dev_pub);
+    k_publish<<<1, 64, 0, s>>>(q.counters.as<QCounters>(), stripes_of(q, 0), slot, d, seq);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    HostCounters hc;
+    if ((e = hipMemcpyAsync(&hc, d, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (hc.seq != seq) return hipErrorUnknown;
+    *out = hc.c;
+    *rc = hc.rc;
+    return hipSuccess;
+  }
+  HostCounters* h = static_cast<HostCounters*>(q.host_pub);
   k_publish<<<1, 64, 0, s>>>(q.counters.as<QCounters>(), stripes_of(q, 0), slot, h, seq);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 1; __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq; spin++) {

@@ -76,6 +76,8 @@ _sig("dg_snapshot_acquire", _i32, _P, _u32, ctypes.POINTER(_u32))
 _sig("dg_snapshot_release", _i32, _P, _u32)
 _sig("dg_compact", _i32, _P, _P)
 _sig("dg_bfs", _i32, _P, _u32, _u32, _P, _P)
+_sig("dg_bfs_noalloc", _i32, _P, _u32, _u32, _P, _P)
+NOALLOC_SCRATCH_BYTES = 96 << 20   # DG_NOALLOC_SCRATCH_BYTES
 _sig("dg_sssp", _i32, _P, _u32, _u32, _P, _P)
 _sig("dg_bc", _i32, _P, _u32, _P, _u32, _P, _P)
 for _n in ("dg_pagerank", "dg_pagerank_nosync"):
@@ -238,6 +240,15 @@ class Graph:
 
     def bfs(self, src, epoch=EPOCH_LATEST, out=None) -> torch.Tensor:
         rc, out = self.try_bfs(src, epoch, out)
+        self._check(rc)
+        return out
+
+    def try_bfs_noalloc(self, src, epoch=EPOCH_LATEST, out=None):
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda") if out is None else out
+        return lib.dg_bfs_noalloc(self.h, epoch, src, _ptr(out), _stream()), out
+
+    def bfs_noalloc(self, src, epoch=EPOCH_LATEST, out=None) -> torch.Tensor:
+        rc, out = self.try_bfs_noalloc(src, epoch, out)
         self._check(rc)
         return out
 
