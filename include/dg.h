@@ -286,7 +286,9 @@ dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, void* strea
  * by HIP events on the stream it runs on, and the visible arcs each launch
  * examined are counted on the device.  dg_profile_read waits for the
  * recorded events and reports, per family: launches, summed duration and
- * summed arcs.  Names are static strings owned by the library.
+ * summed arcs.  Names are static strings owned by the library.  The entry
+ * "pool_growth" counts reallocations of the slab pools instead (host clock,
+ * including the wait for running engine launches to finish).
  */
 typedef struct {
   const char* name;
@@ -325,6 +327,7 @@ typedef struct {
   uint32_t max_inflight;   /* queries admitted and not yet finished, over all lanes; 0 = 1024 */
   uint32_t max_batch;      /* queries fused into one launch; 0 = 64 */
   uint32_t query_lanes;    /* engine launches in flight at once, 1..4; 0 = 1 */
+  uint32_t log_ops;        /* 1 = keep every update's ops for dg_server_log (16 B per op until stop) */
 } dg_server_config;
 typedef struct {
   uint64_t completed, updates, queries, ops_applied;
@@ -338,6 +341,36 @@ dg_status dg_server_stop(dg_server* s);
 dg_status dg_server_submit_update(dg_server* s, const dg_op* ops, uint64_t n, uint64_t* ticket);
 dg_status dg_server_submit_query(dg_server* s, uint32_t kind, const uint32_t* srcs, uint32_t k,
                                  uint64_t* ticket);
+/*
+ * The server's log: one record per finished request, in linearization
+ * order.  An update that published epoch e comes before every query bound
+ * to e, and those queries follow it in ticket order; a rejected update
+ * (status < 0, no epoch published) stands, in ticket order, among the
+ * queries bound to the epoch that was latest when it was applied.
+ * Replaying the updates in this order on an empty graph that first receives
+ * the graph's state at the server's start reproduces every epoch, and each
+ * query's result is the plain query's on its epoch.
+ *   recs (host, optional): the records; ops (host, optional): the op records
+ *   of every update, concatenated, which are kept only when the server was
+ *   started with log_ops = 1 (otherwise an update's ops_off is UINT64_MAX);
+ *   srcs (host, optional): every query's sources, concatenated.
+ * Each array receives at most its capacity; *n_recs / *n_ops / *n_srcs
+ * (optional) receive the full counts, so a call with null arrays sizes
+ * them.  Records stay until dg_server_stop; dg_server_take does not remove
+ * them.
+ */
+typedef struct {
+  uint64_t ticket;
+  int32_t kind;        /* -1 update batch, else DG_Q_BFS / DG_Q_SSSP / DG_Q_BC */
+  dg_status status;    /* the request's call status */
+  dg_epoch epoch;      /* update: the epoch it published (rejected: the latest then); query: its bound epoch */
+  uint32_t n;          /* update: ops in the batch; query: sources */
+  uint64_t off;        /* index of its first op in ops[] (updates) or source in srcs[] (queries) */
+  double t_arrive_ms;  /* submission, ms after dg_server_start */
+  double t_done_ms;    /* completion, same clock */
+} dg_log_record;
+dg_status dg_server_log(dg_server* s, dg_log_record* recs, uint64_t rec_cap, uint64_t* n_recs, dg_op* ops,
+                        uint64_t ops_cap, uint64_t* n_ops, uint32_t* srcs, uint64_t srcs_cap, uint64_t* n_srcs);
 /* done = 1 when finished; status/epoch/latency_ms valid then. */
 dg_status dg_server_poll(dg_server* s, uint64_t ticket, int* done, dg_status* status,
                          dg_epoch* epoch, double* latency_ms);

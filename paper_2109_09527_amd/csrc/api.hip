@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <chrono>
+
 #include "dg_host.h"
 
 namespace dg {
@@ -141,8 +143,45 @@ static hipError_t realloc_pool(DevBuf& buf, DevBuf& sbuf, Pool& p, uint64_t new_
 // Enlarge the bucket pools so that `need` more buckets fit.  Every queued
 // kernel on every stream finishes first: offsets stay valid (the contents
 // are copied to the same offsets), only the base addresses change.
-hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r) {
+void pool_read_begin(dg_graph* g, std::unique_lock<std::mutex>& lk) {
+  g->pool_cv.wait(lk, [g] { return g->pool_writers == 0; });
+  g->pool_readers++;
+}
+
+void pool_read_end(dg_graph* g) {
   std::lock_guard<std::mutex> lk(g->mu);
+  g->pool_readers--;
+  g->pool_cv.notify_all();
+}
+
+// Holds off new pool readers and waits for running ones, with g->mu held in
+// lk; the destructor lets readers in again.
+struct PoolWrite {
+  dg_graph* g;
+  PoolWrite(dg_graph* g_, std::unique_lock<std::mutex>& lk) : g(g_) {
+    g->pool_writers++;
+    g->pool_cv.wait(lk, [this] { return g->pool_readers == 0; });
+  }
+  ~PoolWrite() {
+    g->pool_writers--;
+    g->pool_cv.notify_all();
+  }
+};
+
+hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_lock<std::mutex> lk(g->mu);
+  PoolWrite pw(g, lk);
+  struct Clock {
+    dg_graph* g;
+    std::chrono::steady_clock::time_point t0;
+    ~Clock() {
+      if (!g->prof.on) return;
+      g->prof.launches[KID_POOL_GROW]++;
+      g->prof.ms[KID_POOL_GROW] +=
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  } clock{g, t0};
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return e;
   unsigned long long cur[2];
@@ -530,7 +569,8 @@ dg_status dg_snapshot_release(dg_graph* g, dg_epoch e) {
 dg_status dg_compact(dg_graph* g, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lku(g->upd_mu);
-  std::lock_guard<std::mutex> lk(g->mu);
+  std::unique_lock<std::mutex> lk(g->mu);
+  PoolWrite pw(g, lk);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipDeviceSynchronize() != hipSuccess) return fail(g, DG_E_HIP, "compaction: device sync");
   dg_status st = compact_pool(g, true, s);
@@ -723,7 +763,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
                                          "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
-                                         "diameter",     "maxflow",      "dfs"};
+                                         "diameter",     "maxflow",      "dfs",          "pool_growth"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

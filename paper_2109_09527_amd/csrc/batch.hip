@@ -923,6 +923,7 @@ static hipError_t wait_polled(BatchState* bs, hipStream_t s) {
   if (e != hipSuccess) return e;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 1; __atomic_load_n(bs->hflag, __ATOMIC_ACQUIRE) != seq; spin++) {
+    host_pause(spin);
     if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
       if (__atomic_load_n(bs->hflag, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
@@ -1155,8 +1156,19 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   std::vector<uint64_t> src_off(nq, 0);
   std::vector<uint32_t> by_kind[3];
   std::vector<uint32_t> pinned;
+  // the copied descriptors hold the pools' base addresses: pool
+  // reallocation waits until this call's last launch has finished
+  struct PoolRead {
+    dg_graph* g;
+    bool on = false;
+    ~PoolRead() {
+      if (on) pool_read_end(g);
+    }
+  } pool_read{g};
   {
-    std::lock_guard<std::mutex> lk(g->mu);
+    std::unique_lock<std::mutex> lk(g->mu);
+    pool_read_begin(g, lk);
+    pool_read.on = true;
     st_ = g->st;
     tune = g->tune;
     arcs = g->arcs_by_epoch;

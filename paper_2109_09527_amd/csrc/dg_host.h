@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -20,6 +22,15 @@ void exclusive_scan_u32(uint32_t* data, uint64_t n, uint32_t* scratch, hipStream
 uint64_t sort_scratch_words(uint32_t n);
 bool radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint32_t n, int bits,
                       uint32_t* scratch, hipStream_t s);
+
+// One turn of a host thread's wait for a word the device publishes into
+// pinned memory: a pause instruction for the first few thousand turns
+// (about the length of a short kernel), then a yield of the core, so that
+// long waits do not hold a core that other host threads need.
+inline void host_pause(uint32_t turn) {
+  if (turn < 4096) __builtin_ia32_pause();
+  else std::this_thread::yield();
+}
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -142,6 +153,7 @@ enum KernelId {
   KID_DIAMETER,     // one level of a bit-parallel BFS sweep (diameter)
   KID_MAXFLOW,      // one level of an augmenting-path search (maximum flow)
   KID_DFS,          // the one-wave depth-first walk
+  KID_POOL_GROW,    // one reallocation of the bucket pools (host clock, waits included)
   KID_COUNT
 };
 struct Prof {
@@ -198,11 +210,23 @@ struct dg_graph {
   hipEvent_t last_query = nullptr;  // end of the last plain query's work; updates wait for it
   std::string err;
   std::mutex mu;                // host state: epoch, pins, history, store descriptors
+  // Engine launches copy the store descriptors (pool base addresses) under
+  // mu and then run without it; a pool reallocation or compaction, which
+  // frees the old pools, waits until none of them is running
+  // (pool_readers), and new readers wait while one is pending.
+  std::condition_variable pool_cv;
+  int pool_readers = 0;
+  int pool_writers = 0;
   std::mutex upd_mu;            // one update batch (or compaction) at a time
 };
 
 namespace dg {
 // graph-level helpers (api.cpp)
+// With g->mu held in lk: wait until no pool reallocation is pending, then
+// count the caller as a reader of the store descriptors it copies next.
+void pool_read_begin(dg_graph* g, std::unique_lock<std::mutex>& lk);
+// Ends a read begun by pool_read_begin (takes g->mu).
+void pool_read_end(dg_graph* g);
 uint32_t gc_floor(const dg_graph* g);
 bool alive_at(const dg_graph* g, uint32_t v, uint32_t e);
 bool is_device_ptr(const void* p);

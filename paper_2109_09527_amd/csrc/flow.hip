@@ -330,6 +330,7 @@ dg_status maxflow_dev(dg_graph* g, uint32_t e, uint32_t src, uint32_t dst, int64
       if ((he = hipGetLastError()) != hipSuccess) return fail_hip(he, "search");
       const auto t0 = std::chrono::steady_clock::now();
       for (uint32_t spin = 1; __atomic_load_n(&pub[8], __ATOMIC_ACQUIRE) != seq; spin++) {
+        host_pause(spin);
         if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
           if ((he = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(he, "search");
           if (__atomic_load_n(&pub[8], __ATOMIC_ACQUIRE) != seq) return fail_hip(hipErrorUnknown, "search");

@@ -343,6 +343,7 @@ static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, ui
   if (e != hipSuccess) return e;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 1; __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq; spin++) {
+    host_pause(spin);
     if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
       if (__atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;

@@ -76,6 +76,15 @@ struct dg_server {
   std::vector<double> lat_all, lat_q, lat_u;
   uint64_t ops_applied = 0, arcs = 0, n_upd = 0, n_qry = 0;
   double t_first = -1, t_last = 0;
+  // the log: finished requests in completion order (sorted into
+  // linearization order when read), with their ops (if kept) and sources
+  struct LogRec {
+    dg_log_record r;
+    int cls;   // 0: an update that published r.epoch; 1: a query or a rejected update
+  };
+  std::vector<LogRec> log;
+  std::vector<dg_op> log_ops;
+  std::vector<uint32_t> log_srcs;
 
   double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
@@ -99,6 +108,27 @@ struct dg_server {
     } else {
       n_qry++;
     }
+    LogRec lr{};
+    lr.r.ticket = r->ticket;
+    lr.r.kind = r->kind;
+    lr.r.status = st;
+    lr.r.epoch = ep;
+    lr.r.t_arrive_ms = r->t_arrive * 1e3;
+    lr.r.t_done_ms = r->t_done * 1e3;
+    lr.cls = (r->kind < 0 && st == DG_OK) ? 0 : 1;
+    if (r->kind < 0) {
+      lr.r.n = (uint32_t)r->ops.size();
+      lr.r.off = UINT64_MAX;
+      if (cfg.log_ops) {
+        lr.r.off = log_ops.size();
+        log_ops.insert(log_ops.end(), r->ops.begin(), r->ops.end());
+      }
+    } else {
+      lr.r.n = (uint32_t)r->srcs.size();
+      lr.r.off = log_srcs.size();
+      log_srcs.insert(log_srcs.end(), r->srcs.begin(), r->srcs.end());
+    }
+    log.push_back(lr);
     t_last = std::max(t_last, r->t_done);
     mem_used -= r->reserve;
     r->reserve = 0;
@@ -122,6 +152,9 @@ struct dg_server {
       r->results.assign(r->ops.size(), 0);
       dg_epoch ep = 0;
       dg_status st = dg_apply_batch(g, r->ops.data(), r->ops.size(), r->results.data(), &ep, su);
+      // a rejected batch publishes nothing: it stands at the epoch that is
+      // latest (only this thread publishes, so that is still the one it saw)
+      if (st != DG_OK) ep = dg_latest_epoch(g);
       finish(r, st, ep);
     }
   }
@@ -334,6 +367,30 @@ dg_status dg_server_take(dg_server* s, uint64_t ticket, void* host_out, uint64_t
   uint64_t have = r->kind < 0 ? r->results.size() : r->out.size();
   if (host_out && bytes) std::memcpy(host_out, src, std::min(bytes, have));
   s->reqs.erase(it);
+  return DG_OK;
+}
+
+dg_status dg_server_log(dg_server* s, dg_log_record* recs, uint64_t rec_cap, uint64_t* n_recs, dg_op* ops,
+                        uint64_t ops_cap, uint64_t* n_ops, uint32_t* srcs, uint64_t srcs_cap, uint64_t* n_srcs) {
+  if (!s) return DG_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->m);
+  if (recs && rec_cap) {
+    std::vector<const dg_server::LogRec*> order;
+    order.reserve(s->log.size());
+    for (const auto& x : s->log) order.push_back(&x);
+    std::sort(order.begin(), order.end(), [](const dg_server::LogRec* a, const dg_server::LogRec* b) {
+      if (a->r.epoch != b->r.epoch) return a->r.epoch < b->r.epoch;
+      if (a->cls != b->cls) return a->cls < b->cls;
+      return a->r.ticket < b->r.ticket;
+    });
+    for (uint64_t i = 0; i < order.size() && i < rec_cap; i++) recs[i] = order[i]->r;
+  }
+  if (ops && ops_cap) std::memcpy(ops, s->log_ops.data(), std::min<uint64_t>(ops_cap, s->log_ops.size()) * sizeof(dg_op));
+  if (srcs && srcs_cap)
+    std::memcpy(srcs, s->log_srcs.data(), std::min<uint64_t>(srcs_cap, s->log_srcs.size()) * sizeof(uint32_t));
+  if (n_recs) *n_recs = s->log.size();
+  if (n_ops) *n_ops = s->log_ops.size();
+  if (n_srcs) *n_srcs = s->log_srcs.size();
   return DG_OK;
 }
 

@@ -586,6 +586,7 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 1; __atomic_load_n(seqw, __ATOMIC_ACQUIRE) != seq; spin++) {
+    host_pause(spin);
     if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
       if (__atomic_load_n(seqw, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;

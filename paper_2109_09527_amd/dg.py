@@ -44,7 +44,13 @@ class Query(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32), ("query_lanes", _u32)]
+    _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32), ("query_lanes", _u32),
+                ("log_ops", _u32)]
+
+
+class LogRecord(ctypes.Structure):
+    _fields_ = [("ticket", _u64), ("kind", _i32), ("status", _i32), ("epoch", _u32), ("n", _u32), ("off", _u64),
+                ("t_arrive_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -118,6 +124,8 @@ _sig("dg_server_poll", _i32, _P, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POIN
      ctypes.POINTER(ctypes.c_double))
 _sig("dg_server_take", _i32, _P, _u64, _P, _u64)
 _sig("dg_server_drain", _i32, _P)
+_sig("dg_server_log", _i32, _P, _P, _u64, ctypes.POINTER(_u64), _P, _u64, ctypes.POINTER(_u64), _P, _u64,
+     ctypes.POINTER(_u64))
 _sig("dg_server_get_stats", _i32, _P, ctypes.POINTER(ServerStats))
 
 EXPORTED = [n for n in dir(lib) if n.startswith("dg_")]
@@ -404,8 +412,9 @@ class Graph:
 class Server:
     """Serving loop over a Graph (dg_server_*)."""
 
-    def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32, query_lanes=1):
-        cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes)
+    def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32, query_lanes=1,
+                 log_ops=False):
+        cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes, 1 if log_ops else 0)
         h = _P()
         rc = lib.dg_server_start(graph.h, ctypes.byref(cfg), ctypes.byref(h))
         if rc != OK:
@@ -437,6 +446,31 @@ class Server:
 
     def drain(self):
         self.g._check(lib.dg_server_drain(self.h))
+
+    def log(self):
+        """The library's log in linearization order: a list of dicts with
+        ticket, kind ("update" / "bfs" / "sssp" / "bc"), status, epoch and
+        ops (updates, when kept) or srcs (queries)."""
+        nr, no, ns = _u64(), _u64(), _u64()
+        self.g._check(lib.dg_server_log(self.h, None, 0, ctypes.byref(nr), None, 0, ctypes.byref(no), None, 0,
+                                        ctypes.byref(ns)))
+        recs = (LogRecord * max(1, nr.value))()
+        ops = np.zeros(max(1, no.value), dtype=OP_DTYPE)
+        srcs = np.zeros(max(1, ns.value), dtype=np.uint32)
+        self.g._check(lib.dg_server_log(self.h, recs, nr.value, ctypes.byref(nr), _ptr(ops), no.value,
+                                        ctypes.byref(no), _ptr(srcs), ns.value, ctypes.byref(ns)))
+        names = {-1: "update", Q_BFS: "bfs", Q_SSSP: "sssp", Q_BC: "bc"}
+        out = []
+        for i in range(nr.value):
+            r = recs[i]
+            d = {"ticket": int(r.ticket), "kind": names[r.kind], "status": int(r.status), "epoch": int(r.epoch),
+                 "t_arrive_ms": r.t_arrive_ms, "t_done_ms": r.t_done_ms}
+            if r.kind < 0:
+                d["ops"] = None if r.off == 0xFFFFFFFFFFFFFFFF else ops[r.off:r.off + r.n].copy()
+            else:
+                d["srcs"] = [int(x) for x in srcs[r.off:r.off + r.n]]
+            out.append(d)
+        return out
 
     def stats(self) -> dict:
         s = ServerStats()

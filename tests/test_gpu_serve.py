@@ -1,6 +1,8 @@
 """The serving loop: interleaved update batches and queries submitted over
-time, checked against the oracle replaying the updates in arrival order;
-every query's result equals the same query run alone on its bound epoch."""
+time.  The oracle replays the server's own log (dg_server_log, in
+linearization order): each update's result bytes and published epoch, and
+each query's result on its bound epoch, must match; every query's result
+also equals the same query run alone on that epoch."""
 import time
 
 import numpy as np
@@ -27,105 +29,119 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
+def collect(srv, submitted, n):
+    """Drain, take every result by ticket, and read the library's log."""
+    srv.drain()
+    stats = srv.stats()
+    taken = {}
+    for t, (kind, payload) in submitted.items():
+        done, st, ep, lat = srv.poll(t)
+        assert done
+        if kind == "update":
+            buf = np.zeros(len(payload), np.uint8)
+        elif kind == "bc":
+            buf = np.zeros(n, np.float64)
+        else:
+            buf = np.zeros(n, np.int32)
+        srv.take(t, buf)
+        taken[t] = (st, ep, buf)
+    log = srv.log()
+    srv.stop()
+    return log, taken, stats
+
+
+def replay_log(dg, g, o, e_start, log, submitted, taken):
+    """Replays the library-written log through the oracle, which starts at
+    the graph's state at the server's start (epoch e_start)."""
+    assert o.epoch == e_start
+    assert sorted(r["ticket"] for r in log) == sorted(submitted), "log misses or repeats a request"
+    n_checked = 0
+    for r in log:
+        t = r["ticket"]
+        kind, payload = submitted[t]
+        st, ep, buf = taken[t]
+        assert r["kind"] == kind and r["status"] == st and r["epoch"] == ep, (r, st, ep)
+        if kind == "update":
+            assert r["ops"] is not None and np.array_equal(r["ops"], payload), ("logged ops", t)
+            rc, want = o.apply(r["ops"])
+            assert rc == st == 0, (t, rc, st)
+            assert ep == o.epoch, ("update epoch out of linearization order", t, ep, o.epoch)
+            assert np.array_equal(buf, want), ("update results", ep)
+            continue
+        # a query stands after the update that published its epoch
+        assert ep == o.epoch, ("query epoch out of linearization order", t, ep, o.epoch)
+        srcs = r["srcs"]
+        assert srcs == list(payload), ("logged sources", t)
+        if kind == "bfs":
+            rc, want = o.bfs(srcs[0])
+        elif kind == "sssp":
+            rc, want = o.sssp(srcs[0])
+        else:
+            rc, want = o.bc(srcs)
+        assert st == rc, (kind, srcs, ep, st, rc)
+        if rc:
+            continue
+        if kind == "bc":
+            assert not (np.abs(buf - want) > BC_RTOL * np.abs(want)).any(), ("bc", ep)
+        else:
+            assert np.array_equal(buf, want), (kind, srcs, ep)
+        # the same query alone, on its bound epoch
+        if kind == "bfs":
+            alone = g.bfs(srcs[0], ep).cpu().numpy()
+        elif kind == "sssp":
+            alone = g.sssp(srcs[0], ep).cpu().numpy()
+        else:
+            alone = g.bc(srcs, ep).cpu().numpy()
+        if kind == "bc":
+            assert not (np.abs(buf - alone) > BC_RTOL * np.abs(alone)).any()
+        else:
+            assert np.array_equal(buf, alone)
+        n_checked += 1
+    return n_checked
+
+
 def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2):
     gr = synth.rmat_graph(11, 8, 50, seed=seed)
     g = dg.Graph(gr.n, w_max=50, max_resident_epochs=128)
-    g.apply(synth.load_ops(gr))
-    e_load = g.epoch
+    load = synth.load_ops(gr)
+    g.apply(load)
     wl = synth.update_batches(graph=gr, n_batches=n_req, n_edge_ops=400, w_max=50, seed=seed)
     srcs = synth.out_degree_sources(gr, 16, synth.rng_for(seed, 4))
     rng = np.random.default_rng(seed)
-    srv = dg.Server(g, mem_budget=mem_budget, max_inflight=64, max_batch=max_batch, query_lanes=query_lanes)
-    log = []   # (ticket, kind, payload)
+    srv = dg.Server(g, mem_budget=mem_budget, max_inflight=64, max_batch=max_batch, query_lanes=query_lanes,
+                    log_ops=True)
+    submitted = {}
     nu = 0
     for i in range(n_req):
         r = rng.random()
         if r < 0.3:
-            t = srv.submit_update(wl.batches[nu])
-            log.append((t, "update", nu))
+            submitted[srv.submit_update(wl.batches[nu])] = ("update", wl.batches[nu])
             nu += 1
         elif r < 0.6:
             s = int(srcs[rng.integers(len(srcs))])
-            log.append((srv.submit_query(dg.Q_BFS, [s]), "bfs", s))
+            submitted[srv.submit_query(dg.Q_BFS, [s])] = ("bfs", [s])
         elif r < 0.9:
             s = int(srcs[rng.integers(len(srcs))])
-            log.append((srv.submit_query(dg.Q_SSSP, [s]), "sssp", s))
+            submitted[srv.submit_query(dg.Q_SSSP, [s])] = ("sssp", [s])
         else:
             S = [int(x) for x in rng.choice(srcs, 3, replace=False)]
-            log.append((srv.submit_query(dg.Q_BC, S), "bc", tuple(S)))
+            submitted[srv.submit_query(dg.Q_BC, S)] = ("bc", S)
         time.sleep(float(rng.exponential(0.002)))
-    srv.drain()
-    stats = srv.stats()
-    out = []
-    for t, kind, payload in log:
-        done, st, ep, lat = srv.poll(t)
-        assert done
-        if kind == "update":
-            buf = np.zeros(len(wl.batches[payload]), np.uint8)
-        elif kind == "bc":
-            buf = np.zeros(gr.n, np.float64)
-        else:
-            buf = np.zeros(gr.n, np.int32)
-        srv.take(t, buf)
-        out.append((kind, payload, st, ep, lat, buf))
-    srv.stop()
-    return gr, g, e_load, wl, out, stats
-
-
-def check_against_oracle(dg, gr, g, e_load, wl, out):
+    log, taken, stats = collect(srv, submitted, gr.n)
     o = Oracle(gr.n, w_max=50)
-    o.apply(synth.load_ops(gr))
-    assert o.epoch == e_load
-    updates = [(p, st, ep, buf) for kind, p, st, ep, lat, buf in out if kind == "update"]
-    queries = [(kind, p, st, ep, buf) for kind, p, st, ep, lat, buf in out if kind != "update"]
-    # updates commit in arrival order, one epoch each
-    for j, (p, st, ep, buf) in enumerate(updates):
-        assert st == 0 and ep == e_load + 1 + j
-    by_epoch = {}
-    for q in queries:
-        by_epoch.setdefault(q[3], []).append(q)
-    for ep in range(e_load, e_load + len(updates) + 1):
-        if ep > e_load:
-            p, st, uep, buf = updates[ep - e_load - 1]
-            rc, want = o.apply(wl.batches[p])
-            assert np.array_equal(buf, want), ("update results", ep)
-        for kind, p, st, qep, buf in by_epoch.get(ep, []):
-            if kind == "bfs":
-                rc, want = o.bfs(p)
-            elif kind == "sssp":
-                rc, want = o.sssp(p)
-            else:
-                rc, want = o.bc(list(p))
-            assert st == rc, (kind, p, ep, st, rc)
-            if rc:
-                continue
-            if kind == "bc":
-                assert not (np.abs(buf - want) > BC_RTOL * np.abs(want)).any(), ("bc", ep)
-            else:
-                assert np.array_equal(buf, want), (kind, p, ep)
-            # the same query alone, on its bound epoch
-            if kind == "bfs":
-                alone = g.bfs(p, ep).cpu().numpy()
-            elif kind == "sssp":
-                alone = g.sssp(p, ep).cpu().numpy()
-            else:
-                alone = g.bc(list(p), ep).cpu().numpy()
-            if kind == "bc":
-                assert not (np.abs(buf - alone) > BC_RTOL * np.abs(alone)).any()
-            else:
-                assert np.array_equal(buf, alone)
-    assert sum(1 for ep in by_epoch if ep < e_load) == 0
+    o.apply(load)
+    return g, o, log, submitted, taken, stats
 
 
 @pytest.mark.parametrize("lanes", [1, 3])
 def test_serving_mix_matches_oracle_and_alone(dg, lanes):
     """With one lane, and with three lanes whose launches overlap."""
     say("serving mix, lanes", lanes)
-    gr, g, e_load, wl, out, stats = run_mix(dg, mem_budget=1 << 30, max_batch=8, query_lanes=lanes)
-    check_against_oracle(dg, gr, g, e_load, wl, out)
-    assert stats["completed"] == len(out)
+    g, o, log, submitted, taken, stats = run_mix(dg, mem_budget=1 << 30, max_batch=8, query_lanes=lanes)
+    assert replay_log(dg, g, o, o.epoch, log, submitted, taken) > 0
+    assert stats["completed"] == len(submitted)
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
-    assert stats["queries"] + stats["updates"] == len(out)
+    assert stats["queries"] + stats["updates"] == len(submitted)
 
 
 def test_serving_admission_under_tiny_budget(dg):
@@ -133,9 +149,9 @@ def test_serving_admission_under_tiny_budget(dg):
     with correct results; a BC output larger than the budget is refused."""
     say("serving tiny budget")
     V = 1 << 11
-    gr, g, e_load, wl, out, stats = run_mix(dg, mem_budget=2 * 4 * V, max_batch=4, n_req=30, seed=5)
-    # BC needs 8V bytes: larger than... exactly the budget, so it is admitted alone
-    check_against_oracle(dg, gr, g, e_load, wl, out)
+    g, o, log, submitted, taken, stats = run_mix(dg, mem_budget=2 * 4 * V, max_batch=4, n_req=30, seed=5)
+    # BC needs 8V bytes: exactly the budget, so it is admitted alone
+    replay_log(dg, g, o, o.epoch, log, submitted, taken)
     g2 = dg.Graph(V, w_max=50)
     srv = dg.Server(g2, mem_budget=4 * V, max_inflight=4, max_batch=4)
     with pytest.raises(dg.DGError) as ei:
@@ -145,3 +161,79 @@ def test_serving_admission_under_tiny_budget(dg):
     with pytest.raises(dg.DGError) as ei:
         dg.Server(g2, query_lanes=5)
     assert ei.value.status == dg.E_INVALID_ARG
+
+
+def test_server_log_without_ops(dg):
+    """Without log_ops the log still holds every request, in linearization
+    order, with an update's op count but not its ops."""
+    say("server log without ops")
+    gr = synth.rmat_graph(9, 8, 50, seed=11)
+    g = dg.Graph(gr.n, w_max=50)
+    g.apply(synth.load_ops(gr))
+    wl = synth.update_batches(graph=gr, n_batches=3, n_edge_ops=200, w_max=50, seed=11)
+    s = int(synth.out_degree_sources(gr, 1, synth.rng_for(11, 4))[0])
+    srv = dg.Server(g, query_lanes=1)
+    ts = [srv.submit_update(wl.batches[0]), srv.submit_query(dg.Q_BFS, [s]), srv.submit_update(wl.batches[1])]
+    bad = wl.batches[2].copy()
+    bad["u"][0] = gr.n + 5                      # out of range: the whole batch is rejected
+    ts.append(srv.submit_update(bad))
+    srv.drain()
+    log = srv.log()
+    srv.stop()
+    assert sorted(r["ticket"] for r in log) == sorted(ts)
+    eps = [r["epoch"] for r in log]
+    assert eps == sorted(eps)
+    for r in log:
+        if r["kind"] == "update":
+            assert r["ops"] is None
+    rej = [r for r in log if r["ticket"] == ts[3]][0]
+    assert rej["status"] == dg.E_VERTEX_RANGE and rej["epoch"] == g.epoch
+
+
+def c5_mix(dg, lanes, scale=16, rate=400.0, duration=0.12, seed=7):
+    """The C5 serving mix at R-MAT 16: BFS 40 % / SSSP 40 % / BC with 16
+    sources 20 % of queries, 30 % update batches of log-uniform [1,024,
+    262,144] edge ops.  The graph starts with all vertices and a quarter of
+    its edges in pools sized for the vertices alone, so the mix's updates
+    (up to a quarter of the graph each) reallocate the pools while queries
+    run."""
+    gr = synth.rmat_graph(scale, 16, 255, seed=seed)
+    g = dg.Graph(gr.n, w_max=255, max_resident_epochs=256)
+    load = synth.load_ops(gr)[: gr.n + gr.m // 4]
+    g.apply(load)
+    reqs = synth.serving_requests(gr, rate=rate, duration=duration, seed=seed, bc_sources=16)
+    kinds = [r.kind for r in reqs]
+    assert "update" in kinds and "bc" in kinds, kinds
+    g.profile(True)
+    g.profile_read(reset=True)
+    srv = dg.Server(g, mem_budget=1 << 30, max_inflight=64, max_batch=16, query_lanes=lanes, log_ops=True)
+    submitted = {}
+    t0 = time.perf_counter()
+    for r in reqs:
+        wait = r.t - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        if r.kind == "update":
+            submitted[srv.submit_update(r.ops)] = ("update", r.ops)
+        elif r.kind == "bc":
+            S = [int(x) for x in r.srcs]
+            submitted[srv.submit_query(dg.Q_BC, S)] = ("bc", S)
+        else:
+            kind = dg.Q_BFS if r.kind == "bfs" else dg.Q_SSSP
+            submitted[srv.submit_query(kind, [r.src])] = (r.kind, [r.src])
+    log, taken, stats = collect(srv, submitted, gr.n)
+    growths = g.profile_read(reset=True).get("pool_growth", {}).get("launches", 0)
+    o = Oracle(gr.n, w_max=255)
+    o.apply(load)
+    return g, o, log, submitted, taken, stats, growths
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_c5_mix_rmat16_matches_oracle_and_alone(dg, lanes):
+    say("C5 mix at R-MAT 16, lanes", lanes)
+    g, o, log, submitted, taken, stats, growths = c5_mix(dg, lanes)
+    say("requests", len(submitted), "pool growths while serving", growths)
+    assert growths >= 1, "the mix did not reallocate the pools"
+    n = replay_log(dg, g, o, o.epoch, log, submitted, taken)
+    assert n > 0
+    assert stats["completed"] == len(submitted)
