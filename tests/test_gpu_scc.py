@@ -232,6 +232,35 @@ def test_maxflow_random_and_rmat(dg, undirected):
     g.release(e1)
 
 
+@pytest.mark.parametrize("undirected", [False, True])
+def test_maxflow_rmat14(dg, undirected):
+    """R-MAT scale 14 (weights 1..255 as capacities), four source-sink pairs
+    with out-arcs, before and after removing an eighth of the edges (the
+    earlier epoch read afterwards): flow values equal to the oracle's."""
+    gr = synth.rmat_graph(14, 16, 255, seed=41, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    rng = synth.rng_for(41, 6)
+    srcs = synth.out_degree_sources(gr, 8, rng)
+    pairs = [(int(srcs[i]), int(srcs[i + 1])) for i in range(0, 8, 2)]
+    e1 = g.acquire()
+    want1 = [o.maxflow(s, t)[1] for s, t in pairs]
+    say("maxflow rmat14", undirected, want1)
+    for (s, t), w1 in zip(pairs, want1):
+        assert g.maxflow(s, t) == w1, (s, t)
+    pick = rng.choice(gr.m, gr.m // 8, replace=False)
+    ops = make_ops(np.full(len(pick), REME), gr.u[pick], gr.v[pick])
+    o.apply(ops)
+    g.apply(ops)
+    say("maxflow rmat14 after removals", undirected)
+    for (s, t), w1 in zip(pairs, want1):
+        assert g.maxflow(s, t) == o.maxflow(s, t)[1], (s, t)
+        assert g.maxflow(s, t, e1) == w1
+    g.release(e1)
+
+
 # ----------------------------------------------------- DFS collect (dg_dfs)
 
 def dfs_equal(g, o, s, epoch=None, want=None):
