@@ -631,23 +631,40 @@ __device__ __forceinline__ void td_step(const LevelArgs& a, unsigned long long n
     const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
     for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
       Pairs4 s4 = load_pairs<false>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+      // each stage issues its loads or atomics for all four arcs before any
+      // result is used, so their round trips overlap
+      int32_t cur[4];
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        bool found = false;
-        uint32_t d = s4.d[k];
-        if (s4.vis[k]) {
-          lc.arcs++;
-          if (a.dist[d] < 0 && atomicCAS(&a.dist[d], -1, a.next_level) == -1) found = true;
+        cur[k] = s4.vis[k] ? a.dist[s4.d[k]] : 0;
+        lc.arcs += s4.vis[k] ? 1 : 0;
+      }
+      int32_t prev[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        prev[k] = 0;
+        if (s4.vis[k] && cur[k] < 0) prev[k] = atomicCAS(&a.dist[s4.d[k]], -1, a.next_level);
+      }
+      bool found[4];
+      uint64_t yd[4];
+      uint32_t used[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        found[k] = s4.vis[k] && cur[k] < 0 && prev[k] == -1;
+        yd[k] = 0;
+        used[k] = 0;
+        if (found[k]) {
+          yd[k] = a.st.fdesc[s4.d[k]];
+          used[k] = a.st.fused[s4.d[k]];
+          bm_set(a.bm_next, s4.d[k]);
         }
-        uint64_t yd = 0;
-        if (found) {
-          yd = a.st.fdesc[d];
-          bm_set(a.bm_next, d);
-          lc.verts++;
-          lc.m += a.st.fused[d];
-        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        lc.verts += found[k] ? 1 : 0;
+        lc.m += used[k];
         room_front(qn, 64, a.fout, a.cnt_out);
-        push_item(qn, found, d, yd);
+        push_item(qn, found[k], s4.d[k], yd[k]);
       }
     }
   }
@@ -846,42 +863,58 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
   }
   for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
     Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
-    // the four targets' distances are read up front, so the loads overlap
-    // instead of each waiting behind the previous target's atomics;
-    // distances only fall, so an early read is an upper bound and the
-    // atomicMin below decides
-    int32_t cur[4];
+    // Each stage below issues its loads or atomics for all four arcs before
+    // any result is used, so their round trips overlap.  The targets'
+    // distances are read first; distances only fall, so an early read is
+    // an upper bound and the atomicMin decides.
+    bool take[4];
+    int32_t nd[4], cur[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
-      cur[k] = s4.vis[k] && take ? a.dist[s4.d[k]] : 0;
+      take[k] = s4.vis[k] && (a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light)));
+      cur[k] = take[k] ? a.dist[s4.d[k]] : 0;
+      nd[k] = __shfl(du_l, (int)s4.item[k], 64) + s4.w[k];
+      lc.arcs += take[k] ? 1 : 0;
+    }
+    int32_t old[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      old[k] = DIST_INF;
+      if (take[k] && nd[k] < cur[k]) old[k] = atomicMin(&a.dist[s4.d[k]], nd[k]);
+    }
+    // an improvement below the threshold claims the target's place in the
+    // next near frontier (once per pass); one at or above it raises the
+    // target's far flag
+    uint32_t prev[4], fl[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      prev[k] = 0u;
+      fl[k] = 0u;
+      if (take[k] && nd[k] < cur[k] && nd[k] < old[k]) {
+        if (nd[k] < a.thr) {
+          prev[k] = atomicExch(&a.stamp[s4.d[k]], a.it1);
+          fl[k] = a.infar[s4.d[k]];
+        } else {
+          prev[k] = atomicExch(&a.infar[s4.d[k]], 1u);
+        }
+      }
+    }
+    bool to_near[4];
+    uint64_t yd[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool imp = take[k] && nd[k] < cur[k] && nd[k] < old[k];
+      to_near[k] = imp && nd[k] < a.thr && prev[k] != a.it1;
+      // settled in this bucket: no later split needs to move it again
+      if (imp && nd[k] < a.thr && fl[k]) a.infar[s4.d[k]] = 0u;
+      if (imp && nd[k] >= a.thr && prev[k] == 0u) lc.far++;
+      yd[k] = to_near[k] ? a.st.fdesc[s4.d[k]] : 0;
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const int32_t du = __shfl(du_l, (int)s4.item[k], 64);
-      bool to_near = false;
-      uint32_t d = s4.d[k];
-      bool take = a.mode == 0 || ((a.mode == 1) == (s4.w[k] <= a.light));
-      if (s4.vis[k] && take) {
-        lc.arcs++;
-        int32_t nd = du + s4.w[k];
-        if (nd < cur[k]) {
-          int32_t old = atomicMin(&a.dist[d], nd);
-          if (nd < old) {
-            if (nd < a.thr) {
-              to_near = atomicExch(&a.stamp[d], a.it1) != a.it1;
-              // settled in this bucket: no later split needs to move it again
-              if (a.infar[d]) a.infar[d] = 0u;
-            } else if (atomicExch(&a.infar[d], 1u) == 0u) {
-              lc.far++;
-            }
-          }
-        }
-      }
-      uint64_t yd = to_near ? a.st.fdesc[d] : 0;
-      lc.verts += to_near ? 1 : 0;
+      lc.verts += to_near[k] ? 1 : 0;
       room_front(qn, 64, a.fout, a.cnt_out);
-      push_item(qn, to_near, d, yd);
+      push_item(qn, to_near[k], s4.d[k], yd[k]);
     }
   }
 }
@@ -1067,22 +1100,39 @@ __device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_
   const unsigned long long f_l = touches(cv) ? a.fr[cv.v] : 0ull;
   for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
     Pairs4 s4 = load_pairs<false>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+    // each stage issues its loads or atomics for all four arcs before any
+    // result is used, so their round trips overlap
+    unsigned long long want[4], have[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const unsigned long long fm = __shfl(f_l, (int)s4.item[k], 64);
-      const uint32_t d = s4.d[k];
-      bool first = false;
+      const unsigned long long fm = __shfl(f_l, (int)s4.item[k], 64);   // all lanes take part
+      want[k] = 0ull;
+      have[k] = 0ull;
       if (s4.vis[k]) {
-        lc.arcs++;
-        const unsigned long long m = fm & ~a.vis[d];
-        if (m && (m & ~__hip_atomic_load(&a.nxt[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-          first = atomicOr(&a.nxt[d], m) == 0ull;
+        want[k] = fm & ~a.vis[s4.d[k]];
+        have[k] = __hip_atomic_load(&a.nxt[s4.d[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      const uint64_t yd = first ? a.st.fdesc[d] : 0;
+      lc.arcs += s4.vis[k] ? 1 : 0;
+    }
+    unsigned long long before[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      before[k] = 1ull;
+      if (want[k] & ~have[k]) before[k] = atomicOr(&a.nxt[s4.d[k]], want[k]);
+    }
+    bool first[4];
+    uint64_t yd[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      first[k] = before[k] == 0ull;
+      yd[k] = first[k] ? a.st.fdesc[s4.d[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
       room_front(qn, 64, a.fout, a.cnt_out);
-      push_item(qn, first, d, yd);
+      push_item(qn, first[k], s4.d[k], yd[k]);
       room_u32(qt, 64, a.touched, &a.cnt_out->n_far);
-      push_u32(qt, first, d);
+      push_u32(qt, first[k], s4.d[k]);
     }
   }
 }
