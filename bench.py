@@ -10,6 +10,13 @@ Workload (one "step" = one pass of the hot path over one batch):
   snapshot BFS and one delta-stepping SSSP from sources drawn among vertices
   with an initial out-arc, on that epoch.
 
+Batched leg (the batched configuration as stated): R-MAT scale 21 (2.1M
+vertices, 33.5M sampled edges), loaded as the first snapshot, then 7
+batches of log-uniform [65,536, 1,048,576] edge ops (half AddEdge, half
+RemoveEdge), one snapshot each; 512 BFS/SSSP queries (query i a BFS when i
+is even, bound to snapshot i mod 8) run as one dg_query_batch call against
+512 plain calls, outputs compared element by element.
+
 Reported value: snapshot-query GTEPS of the whole job = sum over the
 queries of the edges in the traversed component (visible out-degree summed
 over reached vertices) / wall time of all timed steps (updates included).
@@ -41,6 +48,12 @@ HBM_PEAK_GBS = 8000.0
 #   bfs_top_down  dst 4 + stamp 8 + dist 4
 #   bfs_bottom_up src 4 + stamp 8 (frontier bit test stays in L2)
 BYTES_PER_ARC = {"sssp_relax": 20, "bfs_top_down": 16, "bfs_bottom_up": 12}
+# The engine's multi-source BFS (same-snapshot BFS queries share one scan,
+# one bit per query): per visible arc dst 4 + stamp 8 + the target's visited
+# mask 8 + its next-level mask 8 (read, then atomicOr when it gains bits).
+# Its SSSP gangs relax as the plain path does.
+BATCH_BYTES_PER_ARC = {"batch_bfs": 28, "batch_sssp": 20}
+ORACLE_WORKERS_MAX = 16   # the host cores one GPU's share of the box offers
 METRIC = "snapshot-query GTEPS + updates/s; p50/p99 query latency, batched vs plain"
 # HBM bytes per launch measured with rocprofv3 counters, valid only while the
 # kernel's sources are unchanged (their digest is stored beside the figure).
@@ -90,9 +103,16 @@ def main():
     ap.add_argument("--tuning-file", default=None,
                     help="JSON tuning: loaded (and the autotuner skipped) if the file exists, else written "
                          "after autotuning, so a profiled run can replay the tuned configuration")
-    ap.add_argument("--batch-queries", type=int, default=128,
+    ap.add_argument("--batch-queries", type=int, default=512,
                     help="queries of the batched-vs-plain comparison (0 = skip)")
+    ap.add_argument("--batch-scale", type=int, default=21, help="R-MAT scale of the batched comparison")
+    ap.add_argument("--c3-oracle", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.c3_oracle:
+        # the oracle leg of the batched configuration, in a process of its
+        # own that never touches the GPU (its workers are forked from it)
+        c3_oracle_child(args.c3_oracle)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the store and its queries run on a single GPU)", file=sys.stderr)
@@ -204,13 +224,19 @@ def main():
                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kp["launches"],
                     "bytes_per_launch": int(bytes_per_launch)}
 
-    batched = None
-    if args.batch_queries > 0:
-        batched = batched_vs_plain(g, wl, epochs, args.batch_queries)
-
     cpu = None
     if args.cpu_steps > 0:
         cpu = cpu_baseline(wl, W, min(args.cpu_steps, K), m_bfs, m_sssp, dist_b, dist_s)
+
+    # the batched configuration runs on a graph of its own
+    g.close()
+    del dbatches, dresults, dist_b, dist_s
+    torch.cuda.empty_cache()
+    batched = None
+    if args.batch_queries > 0:
+        batched, c3_cpu = batched_vs_plain(args)
+        if cpu is not None and c3_cpu is not None:
+            cpu["batched_config"] = c3_cpu
 
     out = {
         "metric": METRIC,
@@ -265,17 +291,35 @@ def kernel_roof(prof, name, bytes_per_arc):
             "bytes_per_launch": int(kp["arcs"] * bytes_per_arc / kp["launches"])}
 
 
-def batched_vs_plain(g, wl, epochs, nq):
-    """nq BFS/SSSP queries (alternating) over the last 8 retained epochs:
-    one dg_query_batch launch versus one plain call per query.  Outputs of
-    the two forms are compared element by element."""
+def batched_vs_plain(args):
+    """The batched configuration: R-MAT scale 21 loaded as the first of 8
+    snapshots, 7 batches of log-uniform [64k, 1M] edge ops, 512 BFS/SSSP
+    queries as one dg_query_batch call against one plain call per query.
+    Outputs of the two forms are compared element by element; the oracle is
+    then timed on a sample of the same queries, single-threaded and on the
+    host's cores."""
+    import hashlib
+
     import torch
-    from paper_2109_09527_amd import dg
-    n = g.n
-    eps = epochs[-8:]
-    srcs = np.concatenate([wl.bfs_src, wl.sssp_src])
-    qs = [(dg.Q_BFS if i % 2 == 0 else dg.Q_SSSP, eps[i % len(eps)], int(srcs[(i * 7) % len(srcs)]))
-          for i in range(nq)]
+    from paper_2109_09527_amd import dg, synth
+    t0 = time.time()
+    eq = synth.epoch_queries(scale=args.batch_scale, n_queries=args.batch_queries, seed=0)
+    gr = eq.graph
+    g = dg.Graph(gr.n, w_max=255, max_resident_epochs=8, edge_capacity=2 * gr.m)
+    load = synth.load_ops(gr)
+    g.apply(dg.ops_to_device(load), torch.empty(len(load), dtype=torch.uint8, device="cuda"))
+    epochs = [g.epoch]
+    for b in eq.batches:
+        _, ep = g.apply(dg.ops_to_device(b), torch.empty(len(b), dtype=torch.uint8, device="cuda"))
+        epochs.append(ep)
+    torch.cuda.synchronize()
+    print(f"[bench] batched configuration: R-MAT {args.batch_scale}, m={gr.m}, batches "
+          f"{[len(b) for b in eq.batches]}, ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    tuning = g.autotune(seed=0)
+    print(f"[bench] batched configuration tuning {tuning}", file=sys.stderr, flush=True)
+    n = gr.n
+    nq = len(eq.kinds)
+    qs = [(dg.Q_BFS if eq.kinds[i] == 0 else dg.Q_SSSP, epochs[eq.epoch_slot[i]], int(eq.src[i])) for i in range(nq)]
     plain = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
     batch = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in qs]
     # warm-up of both forms; the engine's warm-up runs the whole batch, so
@@ -308,19 +352,153 @@ def batched_vs_plain(g, wl, epochs, nq):
     prof = g.profile_read(reset=True)
     g.profile(False)
     same = all(x == 0 for x in st) and all(torch.equal(a, b) for a, b in zip(plain, batch))
-    degs = {e: g.out_degrees(e).to(torch.int64) for e in set(eps)}
-    m = sum(int(degs[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, batch))
-    roof = {k: kernel_roof(prof, f"batch_{k}", BYTES_PER_ARC["sssp_relax" if k == "sssp" else "bfs_top_down"])
-            for k in ("bfs", "sssp")}
-    return {"queries": nq, "epochs": len(set(eps)), "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
-            "plain_gteps": round(m / t_plain / 1e9, 4), "batched_gteps": round(m / t_batch / 1e9, 4),
-            "speedup": round(t_plain / t_batch, 2),
-            "plain_latency_ms": {"p50": round(pct(plain_ms, 50), 3), "p99": round(pct(plain_ms, 99), 3)},
-            "batched_latency_ms": {"p50": round(t_batch * 1e3, 3), "p99": round(t_batch * 1e3, 3)},
-            "outputs_equal": same,
-            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3), "arcs": v["arcs"]}
-                        for k, v in prof.items()},
-            "roofline": roof}
+    degs = {e: g.out_degrees(e).to(torch.int64) for e in set(epochs)}
+    ms = [int(degs[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, batch)]
+    m = sum(ms)
+    roof = {k: kernel_roof(prof, k, BATCH_BYTES_PER_ARC[k]) for k in BATCH_BYTES_PER_ARC}
+    out = {"config": {"workload": f"R-MAT scale {args.batch_scale}: {nq} snapshot BFS/SSSP queries (50/50) over "
+                                  f"{len(epochs)} epochs (load + batches of log-uniform 64k-1M edge ops), one "
+                                  f"persistent batched call vs {nq} plain calls",
+                      "vertices": n, "loaded_edges": gr.m, "batch_ops": [len(b) for b in eq.batches],
+                      "tuning": tuning},
+           "queries": nq, "epochs": len(set(epochs)), "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+           "plain_gteps": round(m / t_plain / 1e9, 4), "batched_gteps": round(m / t_batch / 1e9, 4),
+           "speedup": round(t_plain / t_batch, 2),
+           "plain_latency_ms": {"p50": round(pct(plain_ms, 50), 3), "p99": round(pct(plain_ms, 99), 3)},
+           "batched_latency_ms": {"p50": round(t_batch * 1e3, 3), "p99": round(t_batch * 1e3, 3)},
+           "outputs_equal": same,
+           "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3), "arcs": v["arcs"]}
+                       for k, v in prof.items()},
+           "roofline": roof}
+    cpu = None
+    if args.cpu_steps > 0:
+        # the oracle sample: the first 2 queries of each epoch single-threaded,
+        # the first 16 of each epoch on the host's cores
+        by_epoch = {}
+        for i in range(nq):
+            by_epoch.setdefault(int(eq.epoch_slot[i]), []).append(i)
+        single = [i for k in sorted(by_epoch) for i in by_epoch[k][:2]]
+        par = [i for k in sorted(by_epoch) for i in by_epoch[k][:16]]
+        want = {i: hashlib.sha256(batch[i].cpu().numpy().tobytes()).hexdigest() for i in set(single) | set(par)}
+        g.close()
+        del plain, batch
+        torch.cuda.empty_cache()
+        cpu = c3_oracle_leg(args, single, par, ms, want)
+    return out, cpu
+
+
+def cpu_info():
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def c3_oracle_leg(args, single, par, ms, want):
+    """Runs the oracle on the batched configuration's sample in a child
+    process (it never initialises the GPU, so it may fork workers)."""
+    import subprocess
+    import tempfile
+    job = {"scale": args.batch_scale, "n_queries": args.batch_queries, "single": single, "parallel": par,
+           "m": {str(i): ms[i] for i in set(single) | set(par)}}
+    with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+        json.dump(job, f)
+        path = f.name
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--c3-oracle", path], capture_output=True,
+                           text=True, timeout=600)
+    finally:
+        os.unlink(path)
+    sys.stderr.write(r.stderr)
+    if r.returncode != 0:
+        return {"error": f"oracle leg exited with {r.returncode}"}
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    hashes = res.pop("hashes")
+    res["matches_gpu"] = all(hashes.get(str(i)) == want[i] for i in want)
+    return res
+
+
+def _c3_worker(args):
+    """A forked worker: one query on the oracle state inherited at fork."""
+    import hashlib
+    kind, s = args
+    t = time.perf_counter()
+    _, d = (_ORC.bfs if kind == 0 else _ORC.sssp)(s)
+    return time.perf_counter() - t, hashlib.sha256(d.tobytes()).hexdigest()
+
+
+_ORC = None
+
+
+def c3_oracle_child(path):
+    """Oracle timing of the batched configuration: the oracle replays the
+    load and the batches in order; at each epoch it runs that epoch's
+    single-threaded sample one query after another on one core, then its
+    parallel sample on up to 16 forked workers.  GTEPS use the GPU's TEPS
+    numerators (passed in), which the output hashes tie to these runs."""
+    global _ORC
+    import multiprocessing as mp
+
+    from oracle import Oracle
+    from paper_2109_09527_amd import synth
+    with open(path) as f:
+        job = json.load(f)
+    t0 = time.time()
+    eq = synth.epoch_queries(scale=job["scale"], n_queries=job["n_queries"], seed=0)
+    gr = eq.graph
+    o = Oracle(gr.n, w_max=255)
+    o.apply(synth.load_ops(gr))
+    print(f"[bench] oracle load of R-MAT {job['scale']} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    single, par = set(job["single"]), set(job["parallel"])
+    cpus = sorted(os.sched_getaffinity(0))
+    workers = max(1, min(ORACLE_WORKERS_MAX, len(cpus)))
+    t_single = 0.0
+    m_single = 0
+    t_par = 0.0
+    m_par = 0
+    hashes = {}
+    _ORC = o
+    ctx = mp.get_context("fork")
+    for k in range(len(eq.batches) + 1):
+        if k > 0:
+            o.apply(eq.batches[k - 1])
+        idx = [i for i in range(job["n_queries"]) if int(eq.epoch_slot[i]) == k]
+        mine = [i for i in idx if i in single]
+        os.sched_setaffinity(0, {cpus[0]})
+        for i in mine:
+            dt, h = _c3_worker((int(eq.kinds[i]), int(eq.src[i])))
+            t_single += dt
+            m_single += job["m"][str(i)]
+            hashes[str(i)] = h
+        os.sched_setaffinity(0, set(cpus))
+        mine = [i for i in idx if i in par]
+        if mine:
+            t = time.perf_counter()
+            with ctx.Pool(workers) as pool:
+                res = pool.map(_c3_worker, [(int(eq.kinds[i]), int(eq.src[i])) for i in mine], chunksize=1)
+            t_par += time.perf_counter() - t
+            for i, (_, h) in zip(mine, res):
+                m_par += job["m"][str(i)]
+                if hashes.setdefault(str(i), h) != h:
+                    hashes[str(i)] = "mismatch"
+    model, nproc, affinity = cpu_info()
+    print(json.dumps({
+        "single_thread": {"value": round(m_single / t_single / 1e9, 5), "unit": "GTEPS", "cores": 1,
+                          "queries": len(single), "seconds": round(t_single, 2)},
+        "parallel": {"value": round(m_par / t_par / 1e9, 5), "unit": "GTEPS", "cores": workers,
+                     "queries": len(par), "seconds": round(t_par, 2),
+                     "how": "independent queries on forked worker processes, each the plain sequential oracle; "
+                            "wall time per epoch includes forking the pool"},
+        "sample": "the batched configuration's queries: the first 2 of each epoch single-threaded (pinned to one "
+                  "core), the first 16 of each epoch on the parallel workers",
+        "cpu_model": model, "nproc": nproc, "affinity_cpus": affinity,
+        "hashes": hashes}), flush=True)
 
 
 def cpu_baseline(wl, W, S, m_bfs, m_sssp, dist_b, dist_s):
@@ -337,6 +515,8 @@ def cpu_baseline(wl, W, S, m_bfs, m_sssp, dist_b, dist_s):
     print(f"[bench] oracle setup {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     same = True
     t = 0.0
+    cpus = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {cpus[0]})   # single-threaded on one core
     for j in range(S):
         i = W + j
         t1 = time.perf_counter()
@@ -345,11 +525,14 @@ def cpu_baseline(wl, W, S, m_bfs, m_sssp, dist_b, dist_s):
         _, ds = o.sssp(int(wl.sssp_src[i]))
         t += time.perf_counter() - t1
         same &= bool(np.array_equal(db, dist_b[i].cpu().numpy()) and np.array_equal(ds, dist_s[i].cpu().numpy()))
+    os.sched_setaffinity(0, set(cpus))
     m = sum(m_bfs[:S]) + sum(m_sssp[:S])
+    model, nproc, affinity = cpu_info()
     return {"value": round(m / t / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"{S} steps (batch + BFS + SSSP) of the same workload after the bulk load and warm-up "
-                      f"batches; single-threaded C on {platform.processor() or platform.machine()}",
-            "seconds": round(t, 2), "matches_gpu": same}
+                      f"batches; the sequential C oracle pinned to one core",
+            "seconds": round(t, 2), "matches_gpu": same,
+            "cpu_model": model, "nproc": nproc, "affinity_cpus": affinity}
 
 
 def synth_load(gr):
