@@ -881,6 +881,7 @@ struct BatchState {
   uint32_t seq = 0;
   void* hres = nullptr;          // pinned landing area of per-query statuses and control records
   size_t hres_bytes = 0;
+  MsScratch ms;                  // multi-source SSSP groups
 };
 
 // Completion of everything enqueued on s so far, seen by polling: a one-wave
@@ -960,6 +961,7 @@ void free_batch_state(dg_graph* g) {
       release(*d);
     if (b->hflag) (void)hipHostFree(b->hflag);
     if (b->hres) (void)hipHostFree(b->hres);
+    free_ms_scratch(b->ms);
     delete b;
     it = g_states.erase(it);
   }
@@ -1256,6 +1258,26 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
     }
     by_kind[DG_Q_BFS] = jobs;
   }
+  // SSSP queries on one snapshot run in groups of up to ms_sssp_width() as
+  // one multi-source search each (a shared frontier, the group's distances
+  // of a vertex in one line); fewer than MS_MIN stay single and run in the
+  // lockstep gangs
+  std::vector<std::vector<uint32_t>> sgroups;
+  {
+    std::map<uint32_t, std::vector<uint32_t>> by_ep;
+    for (uint32_t i : by_kind[DG_Q_SSSP]) by_ep[qd[i].epoch].push_back(i);
+    std::vector<uint32_t> single;
+    const size_t W = ms_sssp_width();
+    for (auto& kv : by_ep) {
+      const std::vector<uint32_t>& v = kv.second;
+      for (size_t o = 0; o < v.size(); o += W) {
+        const size_t n = std::min<size_t>(W, v.size() - o);
+        if (n < MS_MIN) single.insert(single.end(), v.begin() + o, v.begin() + o + n);
+        else sgroups.emplace_back(v.begin() + o, v.begin() + o + n);
+      }
+    }
+    by_kind[DG_Q_SSSP] = single;
+  }
   // A BC query of k > 1 sources runs as k one-source jobs, each writing its
   // own dependency array, when those fit the engine's memory budget; a
   // reduction then adds the k arrays in source order.  A single
@@ -1409,6 +1431,21 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
     std::memcpy(st.data(), bs->hres, nj * 4);
     std::memcpy(cres, static_cast<char*>(bs->hres) + st_bytes, sizeof(cres));
+    for (const std::vector<uint32_t>& grp : sgroups) {
+      std::vector<uint32_t> srcs;
+      std::vector<void*> outs;
+      for (uint32_t i : grp) {
+        srcs.push_back(qd[i].src);
+        outs.push_back(qd[i].out);
+      }
+      uint64_t ga = 0;
+      dg_status r = ms_sssp_dev(g, st_, qd[grp[0]].epoch, fast, srcs.data(), (uint32_t)grp.size(), outs.data(),
+                                (int32_t)std::max<uint32_t>(1, tune.batch_delta), tune.chunk_buckets, bs->ms, s, &ga);
+      if (r != DG_OK) return r;
+      for (uint32_t i : grp) st[i] = DG_OK;
+      prof_arcs(g, KID_BATCH_SSSP, ga);
+      g->engine_arcs += ga;
+    }
     if (!by_kind[DG_Q_SSSP].empty()) {
       dg_status r = run_sssp_gangs(g, bs, st_, tune, fast, share, qd, by_kind[DG_Q_SSSP], st, budget, s);
       if (r != DG_OK) return r;

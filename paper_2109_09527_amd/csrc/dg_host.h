@@ -135,6 +135,15 @@ struct DfsScratch {
   void* host = nullptr;
 };
 
+// Multi-source SSSP (msssp.hip): one group search's buffers, carved from
+// one area, and the pinned block its counters are published into.
+struct MsScratch {
+  DevBuf area;
+  void* host = nullptr;
+  uint32_t seq = 0;
+  uint32_t relax_grid = 0, split_grid = 0;   // resident workgroups of its kernels
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -289,6 +298,15 @@ void free_flow_scratch(FlowScratch& s);
 dg_status dfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* disc, int32_t* parent, uint32_t* n_reached,
                   hipStream_t s);
 void free_dfs_scratch(DfsScratch& s);
+
+// msssp.hip: up to ms_sssp_width() SSSP queries of one snapshot e (sources
+// srcs[0..k), device outputs outs[0..k), host arrays) as one delta-stepping
+// search over a shared frontier; adds the relaxations to *arcs_out.
+uint32_t ms_sssp_width();
+dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const uint32_t* srcs, uint32_t k,
+                      void* const* outs, int32_t delta, uint32_t chunk_buckets, MsScratch& ms, hipStream_t s,
+                      uint64_t* arcs_out);
+void free_ms_scratch(MsScratch& ms);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

@@ -159,3 +159,42 @@ def test_autotune_keeps_results(dg):
         s = int(s)
         assert np.array_equal(g.bfs(s).cpu().numpy(), o.bfs(s)[1])
         assert np.array_equal(g.sssp(s).cpu().numpy(), o.sssp(s)[1])
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_multi_source_sssp_groups(dg, undirected):
+    """SSSP queries of one snapshot run as multi-source searches of up to 16
+    (one shared frontier, a vertex's distances for the group in one line).
+    21 queries on the latest epoch (a group of 16, then one of 5) including
+    a repeated source and a source without out-arcs, plus 6 on an earlier
+    epoch read after a batch, at bucket widths from 1 to far above w_max:
+    every output equals the oracle's Dijkstra."""
+    gr = synth.rmat_graph(12, 16, 255, seed=23, undirected=undirected)
+    o = Oracle(gr.n, undirected=undirected, w_max=255)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=255, max_resident_epochs=4)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    e0 = g.epoch
+    srcs0 = [int(s) for s in synth.out_degree_sources(gr, 6, synth.rng_for(23, 4))]
+    want0 = {s: o.sssp(s)[1] for s in srcs0}
+    wl = synth.update_batches(graph=gr, n_batches=1, n_edge_ops=3000, w_max=255, seed=23)
+    batch = wl.batches[0]
+    batch = batch[(batch["type"] == synth.ADDE) | (batch["type"] == synth.REME)]   # every source stays live
+    o.apply(batch)
+    g.apply(batch)
+    deg = np.bincount(np.concatenate([gr.u, gr.v]) if undirected else gr.u, minlength=gr.n)
+    lone = [v for v in np.nonzero(deg == 0)[0][:50] if o.alive(int(v))][:1]
+    srcs = [int(s) for s in synth.out_degree_sources(gr, 19, synth.rng_for(23, 5))]
+    srcs = srcs[:10] + [srcs[0]] + [int(x) for x in lone] + srcs[10:]
+    srcs = srcs[:21]
+    want = {s: o.sssp(s)[1] for s in set(srcs)}
+    for delta in (1, 7, 64, 255, 512, 100000):
+        say("multi-source sssp delta", delta, "undirected", undirected)
+        g.set_tuning(batch_delta=delta)
+        q = [(dg.Q_SSSP, g.epoch, s, torch.empty(gr.n, dtype=torch.int32, device="cuda")) for s in srcs]
+        q += [(dg.Q_SSSP, e0, s, torch.empty(gr.n, dtype=torch.int32, device="cuda")) for s in srcs0]
+        st = g.query_batch(q)
+        assert st == [0] * len(q)
+        for i, (_, ep, s, out) in enumerate(q):
+            ref = want[s] if ep != e0 else want0[s]
+            assert np.array_equal(out.cpu().numpy(), ref), (delta, i, s, ep)
