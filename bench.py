@@ -51,8 +51,11 @@ BYTES_PER_ARC = {"sssp_relax": 20, "bfs_top_down": 16, "bfs_bottom_up": 12}
 # The engine's multi-source BFS (same-snapshot BFS queries share one scan,
 # one bit per query): per visible arc dst 4 + stamp 8 + the target's visited
 # mask 8 + its next-level mask 8 (read, then atomicOr when it gains bits).
-# Its SSSP gangs relax as the plain path does.
-BATCH_BYTES_PER_ARC = {"batch_bfs": 28, "batch_sssp": 20}
+# Its multi-source SSSP (up to 16 same-snapshot queries share one scan, a
+# vertex's 16 distances in one line): per arc scanned dst 4 + weight 4 +
+# stamp 8, plus per relaxation (arc, query) the target's distance 4.
+BATCH_BYTES_PER_ARC = {"batch_bfs": 28}
+MS_SSSP_BYTES = {"per_scan": 16, "per_relaxation": 4}
 ORACLE_WORKERS_MAX = 16   # the host cores one GPU's share of the box offers
 METRIC = "snapshot-query GTEPS + updates/s; p50/p99 query latency, batched vs plain"
 # HBM bytes per launch measured with rocprofv3 counters, valid only while the
@@ -356,6 +359,16 @@ def batched_vs_plain(args):
     ms = [int(degs[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, batch)]
     m = sum(ms)
     roof = {k: kernel_roof(prof, k, BATCH_BYTES_PER_ARC[k]) for k in BATCH_BYTES_PER_ARC}
+    kp, sc = prof.get("batch_sssp"), prof.get("batch_sssp_scan")
+    if kp and sc and kp["launches"] and kp["total_ms"] > 0:
+        nbytes = MS_SSSP_BYTES["per_scan"] * sc["arcs"] + MS_SSSP_BYTES["per_relaxation"] * kp["arcs"]
+        achieved = nbytes / (kp["total_ms"] / 1e3) / 1e9
+        roof["batch_sssp"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_ms_relax",
+                              "avg_launch_us": round(kp["total_ms"] / kp["launches"] * 1e3, 2),
+                              "launches": kp["launches"], "bytes_per_launch": int(nbytes / kp["launches"]),
+                              "arcs_scanned": sc["arcs"], "relaxations": kp["arcs"],
+                              "queries_per_scan": round(kp["arcs"] / max(1, sc["arcs"]), 2)}
     out = {"config": {"workload": f"R-MAT scale {args.batch_scale}: {nq} snapshot BFS/SSSP queries (50/50) over "
                                   f"{len(epochs)} epochs (load + batches of log-uniform 64k-1M edge ops), one "
                                   f"persistent batched call vs {nq} plain calls",

@@ -288,7 +288,10 @@ dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, void* strea
  * recorded events and reports, per family: launches, summed duration and
  * summed arcs.  Names are static strings owned by the library.  The entry
  * "pool_growth" counts reallocations of the slab pools instead (host clock,
- * including the wait for running engine launches to finish).
+ * including the wait for running engine launches to finish), and
+ * "batch_sssp_scan" counts the batched engine's multi-source SSSP searches
+ * with the arcs they scanned (each scan serves every query of its group;
+ * "batch_sssp" counts their relaxations, one per arc and query).
  */
 typedef struct {
   const char* name;

@@ -76,6 +76,12 @@ void prof_arcs(dg_graph* g, int kid, uint64_t arcs) {
   if (g->prof.on) g->prof.arcs[kid] += arcs;
 }
 
+void prof_scans(dg_graph* g, int kid, uint64_t arcs) {
+  if (!g->prof.on) return;
+  g->prof.launches[kid]++;
+  g->prof.arcs[kid] += arcs;
+}
+
 static void prof_collect(Prof& p) {
   for (auto& r : p.pending) {
     float ms = 0.f;
@@ -763,7 +769,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
                                          "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
-                                         "diameter",     "maxflow",      "dfs",          "pool_growth"};
+                                         "diameter",     "maxflow",      "dfs",          "pool_growth",  "batch_sssp_scan"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

@@ -163,6 +163,7 @@ enum KernelId {
   KID_MAXFLOW,      // one level of an augmenting-path search (maximum flow)
   KID_DFS,          // the one-wave depth-first walk
   KID_POOL_GROW,    // one reallocation of the bucket pools (host clock, waits included)
+  KID_BATCH_SSSP_SCAN,  // multi-source SSSP searches: arcs scanned once for a whole group
   KID_COUNT
 };
 struct Prof {
@@ -251,6 +252,8 @@ struct ProfScope {
   ~ProfScope();
 };
 void prof_arcs(dg_graph* g, int kid, uint64_t arcs);
+// Counts one search of a family that is not timed by itself, with `arcs`.
+void prof_scans(dg_graph* g, int kid, uint64_t arcs);
 
 // update.hip: sizes the batch scratch (us.*) for n ops; callers that stage
 // ops into us.ops do so after this, since growing it replaces the buffer.

@@ -1,12 +1,12 @@
 // Multi-source SSSP: up to MSQ single-source SSSP queries on one snapshot
 // run as one delta-stepping search over a shared vertex frontier.
 //
-// Each vertex holds the MSQ queries' tentative distances in one 64-byte
-// record, D[v * MSQ + q].  A frontier item is a vertex with a mask of the
-// queries for which it was improved below the current threshold; scanning
-// its arcs once serves every query in the mask: for arc (u, w, d), lane q of
-// a 16-lane group reads D[d * MSQ + q] (one line for the group), and
-// relaxes query q when u is in q's mask.  Improvements below the threshold
+// Each vertex holds the MSQ = 32 queries' tentative distances in one
+// 128-byte record (one cache line), D[v * MSQ + q].  A frontier item is a
+// vertex with a mask of the queries for which it was improved below the
+// current threshold; scanning its arcs once serves every query in the mask:
+// for arc (u, w, d), lane q of a 32-lane half-wave reads D[d * MSQ + q] (one
+// line for the half), and relaxes query q when u is in q's mask.  Improvements below the threshold
 // OR the query's bit into d's mask for the next pass (the first bit set
 // enqueues d); improvements at or above it OR the bit into d's far mask
 // (the first bit set puts d on the far pile).  When the near frontier is
@@ -14,8 +14,8 @@
 // distance) and the pile is split: bits whose distance fell below the
 // threshold move into the near masks, the rest stay.
 //
-// Near masks carry the pass that wrote them in their upper 16 bits
-// (tag << 16 | bits) and alternate between two arrays, so a pass reads the
+// Near masks carry the pass that wrote them in their upper 32 bits
+// (tag << 32 | bits) and alternate between two arrays, so a pass reads the
 // masks the previous pass wrote while it writes the next ones, and no
 // array ever needs clearing.  Far masks are rewritten only by the split,
 // which owns each piled vertex exactly once.
@@ -32,8 +32,9 @@
 
 namespace dg {
 
-constexpr uint32_t MSQ = 16;
-constexpr uint32_t MS_TAG_MAX = 0xFFFFu;
+constexpr uint32_t MSQ = 32;
+constexpr uint32_t MS_TAG_MAX = 0xFFFFFFF0u;
+typedef unsigned long long u64;
 
 struct MsPass {
   Store st;
@@ -41,8 +42,8 @@ struct MsPass {
   int fast;
   Front fin, fout;
   int32_t* D;              // V * MSQ distances
-  const uint32_t* nm_in;   // masks of fin's vertices (tag_in)
-  uint32_t* nm_out;        // masks of fout's vertices (tag_out)
+  const u64* nm_in;        // masks of fin's vertices (tag_in)
+  u64* nm_out;             // masks of fout's vertices (tag_out)
   uint32_t* fm;            // far masks
   uint32_t* pile;          // far pile entries appended by this pass
   uint32_t tag_in, tag_out;
@@ -58,16 +59,21 @@ __device__ inline void ms_reset(QCounters* c) {
 
 // ORs bits into v's mask for tag (a mask of an older tag is replaced);
 // returns true for the caller that set the first bit of this tag.
-__device__ inline bool ms_mark(uint32_t* nm, uint32_t v, uint32_t tag, uint32_t bits) {
-  uint32_t old = __hip_atomic_load(&nm[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline bool ms_mark(u64* nm, uint32_t v, uint32_t tag, uint32_t bits) {
+  u64 old = __hip_atomic_load(&nm[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    const bool same = (old >> 16) == tag;
-    const uint32_t nw = same ? (old | bits) : ((tag << 16) | bits);
+    const bool same = (uint32_t)(old >> 32) == tag;
+    const u64 nw = same ? (old | bits) : (((u64)tag << 32) | bits);
     if (nw == old) return false;
-    const uint32_t prev = atomicCAS(&nm[v], old, nw);
+    const u64 prev = atomicCAS(&nm[v], old, nw);
     if (prev == old) return !same;
     old = prev;
   }
+}
+
+// 32-bit mask of the lanes of this lane's half-wave for which pred holds.
+__device__ inline uint32_t half_ballot(bool pred) {
+  return (uint32_t)(__ballot(pred) >> (threadIdx.x & 32));
 }
 
 // x[k] for a wave-uniform k, without indexing a register array.
@@ -76,48 +82,62 @@ __device__ inline T pick4(const T (&x)[4], int k) {
   return k == 0 ? x[0] : (k == 1 ? x[1] : (k == 2 ? x[2] : x[3]));
 }
 
-// One chunk of the near frontier.  Group grp (16 lanes) takes buckets
-// f0 + 4 grp + k; for each bucket, lane q relaxes query q over the bucket's
-// 16 slots, one slot after another, and lane s then publishes slot s's mask
-// bits.
+// One chunk of the near frontier.  load_pairs gives each 16-lane group the
+// 16 slots of buckets f0 + 4 grp + k; half-wave h (lanes 32 h .. 32 h + 31)
+// holds the buckets of groups 2h and 2h + 1, 32 arcs per k.  Lane q of the
+// half relaxes query q over those 32 arcs, one after another (two owners:
+// arcs 0..15 belong to the first bucket, 16..31 to the second), and lane s
+// then publishes arc s's mask bits.
 __device__ __forceinline__ void ms_relax_chunk(const MsPass& a, uint32_t c, uint32_t nitems, uint32_t nb, ItemQ& qn,
                                                U32Q& qp, LaneCounts& lc) {
-  const uint32_t j = threadIdx.x & 15, gb = threadIdx.x & 48, grp = (threadIdx.x >> 4) & 3;
+  const uint32_t j = threadIdx.x & 31, hb = threadIdx.x & 32, grp = (threadIdx.x >> 4) & 3;
   const ChunkView cv = chunk_view(a.fin, c, nitems, nb);
   uint32_t mk_l = 0;
   if (touches(cv)) {
-    const uint32_t t = a.nm_in[cv.v];
-    mk_l = (t >> 16) == a.tag_in ? (t & 0xFFFFu) : 0u;
+    const u64 t = a.nm_in[cv.v];
+    mk_l = (uint32_t)(t >> 32) == a.tag_in ? (uint32_t)t : 0u;
   }
   for (uint32_t f0 = cv.lo; f0 < cv.hi; f0 += 16) {
-    Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, j, a.e, a.fast);
+    Pairs4 s4 = load_pairs<true>(a.st.fp, cv, f0, grp, threadIdx.x & 15, a.e, a.fast);
 #pragma unroll 1
     for (int k = 0; k < 4; k++) {
       const uint32_t it_k = pick4(s4.item, k), d_k = pick4(s4.d, k);
       const int32_t w_k = pick4(s4.w, k);
       const int vis_k = pick4(s4.vis, k) ? 1 : 0;
-      // the bucket's owner, its mask and this lane's query's distance
-      const uint32_t u = __shfl(cv.v, (int)it_k, 64);
-      const uint32_t mk = __shfl(mk_l, (int)it_k, 64);
-      const bool mine = j < a.nq && ((mk >> j) & 1u);
-      const int32_t du = mine ? a.D[(uint64_t)u * MSQ + j] : 0;
-      // the bucket's 16 slots in two halves of 8 (registers), each half's
-      // reads and atomics issued together
+      // the two buckets' owners, their masks and this lane's query's distances
+      uint32_t own[2];
+      int32_t du[2];
+      bool mine[2];
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        const int src_lane = (int)(hb + 16 * b);
+        const uint32_t itb = __shfl(it_k, src_lane, 64);
+        own[b] = __shfl(cv.v, (int)itb, 64);
+        const uint32_t mk = __shfl(mk_l, (int)itb, 64);
+        mine[b] = j < a.nq && ((mk >> j) & 1u);
+        du[b] = mine[b] ? a.D[(uint64_t)own[b] * MSQ + j] : 0;
+      }
+      // the 32 arcs in four quarters of 8 (registers), each quarter's reads
+      // and atomics issued together
       uint32_t my_near = 0, my_far = 0;
 #pragma unroll 1
-      for (int h = 0; h < 16; h += 8) {
+      for (int h = 0; h < 32; h += 8) {
+        const int b = h >> 4;   // which bucket (owner) these arcs belong to
+        const bool mb = b ? mine[1] : mine[0];
+        const int32_t dub = b ? du[1] : du[0];
         uint32_t dd[8];
         int32_t nd[8], cur[8];
         bool act[8];
 #pragma unroll
         for (int t = 0; t < 8; t++) {
-          dd[t] = __shfl(d_k, (int)(gb + h + t), 64);
-          const int32_t w = __shfl(w_k, (int)(gb + h + t), 64);
-          const bool vis = __shfl(vis_k, (int)(gb + h + t), 64) != 0;
-          act[t] = vis && mine;
-          nd[t] = du + w;
+          dd[t] = __shfl(d_k, (int)(hb + h + t), 64);
+          const int32_t w = __shfl(w_k, (int)(hb + h + t), 64);
+          const bool vis = __shfl(vis_k, (int)(hb + h + t), 64) != 0;
+          act[t] = vis && mb;
+          nd[t] = dub + w;
           cur[t] = act[t] ? a.D[(uint64_t)dd[t] * MSQ + j] : 0;
-          lc.arcs += act[t] ? 1 : 0;
+          lc.arcs += act[t] ? 1 : 0;          // relaxations (arc, query)
+          lc.m += (j == 0 && vis) ? 1 : 0;    // arcs scanned, once for the half
         }
         int32_t old[8];
 #pragma unroll
@@ -125,12 +145,12 @@ __device__ __forceinline__ void ms_relax_chunk(const MsPass& a, uint32_t c, uint
           old[t] = DIST_INF;
           if (act[t] && nd[t] < cur[t]) old[t] = atomicMin(&a.D[(uint64_t)dd[t] * MSQ + j], nd[t]);
         }
-        // lane s collects slot s's improved queries: near bits and far bits
+        // lane s collects arc s's improved queries: near bits and far bits
 #pragma unroll
         for (int t = 0; t < 8; t++) {
           const bool imp = act[t] && nd[t] < cur[t] && nd[t] < old[t];
-          const uint32_t nbits = group16_ballot(imp && nd[t] < a.thr);
-          const uint32_t fbits = group16_ballot(imp && nd[t] >= a.thr);
+          const uint32_t nbits = half_ballot(imp && nd[t] < a.thr);
+          const uint32_t fbits = half_ballot(imp && nd[t] >= a.thr);
           if (j == (uint32_t)(h + t)) {
             my_near = nbits;
             my_far = fbits;
@@ -169,7 +189,7 @@ struct MsSplit {
   Store st;
   Front fout;
   int32_t* D;
-  uint32_t* nm_out;
+  u64* nm_out;
   uint32_t* fm;
   const uint32_t* pile_in;
   uint32_t n_in;
@@ -204,7 +224,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_ms_split(MsSplit a) {
       }
       keep = f & ~near;
       a.fm[v] = keep;
-      if (near) a.nm_out[v] = (a.tag_out << 16) | near;
+      if (near) a.nm_out[v] = ((u64)a.tag_out << 32) | near;
     }
     const uint64_t vd = near ? a.st.fdesc[v] : 0;
     room_front(qn, 64, a.fout, a.cnt_out);
@@ -217,19 +237,19 @@ __global__ __launch_bounds__(Q_THREADS) void k_ms_split(MsSplit a) {
   commit_far_min(mn, a.cnt_out);
 }
 
-__global__ void k_ms_init(int32_t* D, uint32_t* nm0, uint32_t* nm1, uint32_t* fm, uint64_t V) {
+__global__ void k_ms_init(int32_t* D, u64* nm0, u64* nm1, uint32_t* fm, uint64_t V) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V * MSQ; i += (uint64_t)gridDim.x * blockDim.x)
     D[i] = DIST_INF;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += (uint64_t)gridDim.x * blockDim.x) {
-    nm0[i] = 0u;
-    nm1[i] = 0u;
+    nm0[i] = 0ull;
+    nm1[i] = 0ull;
     fm[i] = 0u;
   }
 }
 
 // The seed frontier: each distinct source with the mask of its queries
 // (tag 1), at distance 0 for them.  One wave.
-__global__ void k_ms_seed(Store st, const uint32_t* src, const uint32_t* mask, uint32_t n, int32_t* D, uint32_t* nm,
+__global__ void k_ms_seed(Store st, const uint32_t* src, const uint32_t* mask, uint32_t n, int32_t* D, u64* nm,
                           Front f, QCounters* cnt, QCounters* other) {
   __shared__ Shared sh;
   if (threadIdx.x == 0) {
@@ -244,7 +264,7 @@ __global__ void k_ms_seed(Store st, const uint32_t* src, const uint32_t* mask, u
     uint64_t vd = 0;
     if (i < n) {
       v = src[i];
-      nm[v] = (1u << 16) | mask[i];
+      nm[v] = (1ull << 32) | mask[i];
       for (uint32_t b = mask[i]; b; b &= b - 1) D[(uint64_t)v * MSQ + (__ffs(b) - 1)] = 0;
       vd = st.fdesc[v];
     }
@@ -283,7 +303,8 @@ static uint64_t al256(uint64_t x) { return (x + 255) & ~255ull; }
 // Buffers of one group search, carved from ms.area.
 struct MsLayout {
   int32_t* D;
-  uint32_t *nm[2], *fm, *pile[2];
+  u64* nm[2];
+  uint32_t *fm, *pile[2];
   Item* q[2];
   uint32_t* cmap[2];
   QCounters* cnt;        // two slots
@@ -303,7 +324,7 @@ static uint64_t ms_layout(const Store& st, char* base, MsLayout* L) {
   };
   char* p;
   p = take(V * MSQ * 4); if (L) L->D = reinterpret_cast<int32_t*>(p);
-  for (int i = 0; i < 2; i++) { p = take(V * 4 + 64); if (L) L->nm[i] = reinterpret_cast<uint32_t*>(p); }
+  for (int i = 0; i < 2; i++) { p = take(V * 8 + 64); if (L) L->nm[i] = reinterpret_cast<u64*>(p); }
   p = take(V * 4 + 64); if (L) L->fm = reinterpret_cast<uint32_t*>(p);
   for (int i = 0; i < 2; i++) { p = take(V * 4 + 64); if (L) L->pile[i] = reinterpret_cast<uint32_t*>(p); }
   for (int i = 0; i < 2; i++) { p = take(items * sizeof(Item)); if (L) L->q[i] = reinterpret_cast<Item*>(p); }
@@ -341,7 +362,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
     return code;
   };
   if (k == 0) return DG_OK;
-  if (k > MSQ) return fail(DG_E_INVALID_ARG, "more than 16 queries in a group");
+  if (k > MSQ) return fail(DG_E_INVALID_ARG, "more than 32 queries in a group");
   hipError_t he;
   const uint64_t need = ms_layout(st, nullptr, nullptr);
   if ((he = ensure(ms.area, need)) != hipSuccess) return fail(DG_E_OUT_OF_MEMORY, "scratch allocation");
@@ -405,7 +426,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
   int slot = 0, qi = 0, pi = 0;
   uint32_t tag = 1, n_pile = 0;
   int32_t thr = std::max<int32_t>(1, delta);
-  uint64_t arcs = 0;
+  uint64_t arcs = 0, scanned = 0;
   for (;;) {
     if (tag >= MS_TAG_MAX) return fail(DG_E_HIP, "pass count exceeds the mask tag range");
     if (near) {
@@ -422,6 +443,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
         return fail(DG_E_HIP, std::string("relax: ") + hipGetErrorString(he));
       if (hc.overflow & OVF_QUEUE) return fail(DG_E_OUT_OF_MEMORY, "frontier queue capacity exceeded");
       arcs += hc.arcs;
+      scanned += hc.m_next;
       near = hc.fq;
       n_pile += hc.n_order;
       slot = nxt;
@@ -457,6 +479,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
   k_ms_extract<<<grid, 256, 0, s>>>(L.D, V, L.outs);
   if ((he = hipGetLastError()) != hipSuccess) return fail(DG_E_HIP, std::string("extract: ") + hipGetErrorString(he));
   if (arcs_out) *arcs_out += arcs;
+  prof_scans(g, KID_BATCH_SSSP_SCAN, scanned);
   return DG_OK;
 }
 
