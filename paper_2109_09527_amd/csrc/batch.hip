@@ -882,6 +882,7 @@ struct BatchState {
   void* hres = nullptr;          // pinned landing area of per-query statuses and control records
   size_t hres_bytes = 0;
   MsScratch ms;                  // multi-source SSSP groups
+  MbScratch mb;                  // multi-source BC groups
 };
 
 // Completion of everything enqueued on s so far, seen by polling: a one-wave
@@ -962,6 +963,7 @@ void free_batch_state(dg_graph* g) {
     if (b->hflag) (void)hipHostFree(b->hflag);
     if (b->hres) (void)hipHostFree(b->hres);
     free_ms_scratch(b->ms);
+    free_mb_scratch(b->mb);
     delete b;
     it = g_states.erase(it);
   }
@@ -1278,6 +1280,15 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
     }
     by_kind[DG_Q_SSSP] = single;
   }
+  // A BC query of at least MS_MIN sources runs as multi-source searches of
+  // up to ms_bc_width() sources each (after the engine launch), adding its
+  // sources' dependencies in order, bit for bit as the plain call does.
+  std::vector<uint32_t> mbq;
+  {
+    std::vector<uint32_t> rest;
+    for (uint32_t i : by_kind[DG_Q_BC]) (qd[i].k >= MS_MIN ? mbq : rest).push_back(i);
+    by_kind[DG_Q_BC] = rest;
+  }
   // A BC query of k > 1 sources runs as k one-source jobs, each writing its
   // own dependency array, when those fit the engine's memory budget; a
   // reduction then adds the k arrays in source order.  A single
@@ -1431,6 +1442,21 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       return bfail(g, DG_E_HIP, std::string("batch: ") + hipGetErrorString(e));
     std::memcpy(st.data(), bs->hres, nj * 4);
     std::memcpy(cres, static_cast<char*>(bs->hres) + st_bytes, sizeof(cres));
+    for (uint32_t i : mbq) {
+      const uint32_t* S = all_srcs.data() + src_off[i];
+      double* out = static_cast<double*>(qd[i].out);
+      if ((e = hipMemsetAsync(out, 0, st_.V * sizeof(double), s)) != hipSuccess)
+        return bfail(g, DG_E_HIP, std::string("batch BC clear: ") + hipGetErrorString(e));
+      uint64_t ga = 0;
+      dg_status r = DG_OK;
+      for (uint32_t o = 0; o < qd[i].k && r == DG_OK; o += ms_bc_width())
+        r = ms_bc_dev(g, st_, qd[i].epoch, fast, S + o, std::min(ms_bc_width(), qd[i].k - o), out, tune.chunk_buckets,
+                      bs->mb, s, &ga);
+      if (r != DG_OK && r != DG_E_OVERFLOW) return r;
+      st[i] = r;
+      prof_arcs(g, KID_BATCH_BC, ga);
+      g->engine_arcs += ga;
+    }
     for (const std::vector<uint32_t>& grp : sgroups) {
       std::vector<uint32_t> srcs;
       std::vector<void*> outs;

@@ -144,6 +144,15 @@ struct MsScratch {
   uint32_t relax_grid = 0, split_grid = 0;   // resident workgroups of its kernels
 };
 
+// Multi-source BC (msbc.hip): one group search's buffers and its pinned
+// counter block.
+struct MbScratch {
+  DevBuf area;
+  void* host = nullptr;
+  uint32_t seq = 0;
+  uint32_t fwd_grid = 0, bwd_grid = 0;
+};
+
 // Per-kernel-family event timing (dg_profile_*).
 enum KernelId {
   KID_UPDATE = 0,   // the whole update pipeline of one batch
@@ -310,6 +319,15 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
                       void* const* outs, int32_t delta, uint32_t chunk_buckets, MsScratch& ms, hipStream_t s,
                       uint64_t* arcs_out);
 void free_ms_scratch(MsScratch& ms);
+// msbc.hip: up to ms_bc_width() distinct sources srcs[0..k) (host) of one BC
+// query on snapshot e as one search; adds their dependencies to the device
+// array bc in source order (bc must hold the sums of earlier sources, or
+// zeros); adds the arcs examined to *arcs_out.  DG_E_OVERFLOW when a path
+// count exceeds int64.
+uint32_t ms_bc_width();
+dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const uint32_t* srcs, uint32_t k, double* bc,
+                    uint32_t chunk_buckets, MbScratch& mb, hipStream_t s, uint64_t* arcs_out);
+void free_mb_scratch(MbScratch& mb);
 
 // batch.hip
 // lane: engine instance (its own buffers); lanes may run at once on

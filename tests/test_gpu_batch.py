@@ -198,3 +198,59 @@ def test_multi_source_sssp_groups(dg, undirected):
         for i, (_, ep, s, out) in enumerate(q):
             ref = want[s] if ep != e0 else want0[s]
             assert np.array_equal(out.cpu().numpy(), ref), (delta, i, s, ep)
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_multi_source_bc_groups(dg, undirected):
+    """BC queries of at least 4 sources run as multi-source searches of up
+    to 16 sources (one shared frontier per level, a vertex's per-source
+    state in one line per field).  Queries of 4, 16 and 21 sources (two
+    groups) on the latest epoch and one of 7 on an earlier epoch read after
+    a batch: every output equals the plain call bit for bit (same per-source
+    summation order) and the oracle within 1e-9."""
+    gr = synth.rmat_graph(11, 8, 1, seed=29, undirected=undirected, unweighted=True)
+    o = Oracle(gr.n, undirected=undirected, w_max=1)
+    g = dg.Graph(gr.n, undirected=undirected, w_max=1, max_resident_epochs=4)
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    e0 = g.epoch
+    S0 = [int(s) for s in synth.out_degree_sources(gr, 7, synth.rng_for(29, 4))]
+    want0 = o.bc(S0)[1]
+    rng = np.random.default_rng(29)
+    pick = rng.choice(gr.m, size=gr.m // 10, replace=False)
+    dels = synth.make_ops(np.full(len(pick), synth.REME), gr.u[pick], gr.v[pick])
+    o.apply(dels)
+    g.apply(dels)
+    S = [int(s) for s in synth.out_degree_sources(gr, 21, synth.rng_for(29, 5))]
+    cases = [(g.epoch, S[:4]), (g.epoch, S[:16]), (g.epoch, S), (e0, S0)]
+    say("multi-source bc, undirected", undirected)
+    outs = [torch.empty(gr.n, dtype=torch.float64, device="cuda") for _ in cases]
+    st = g.query_batch([(dg.Q_BC, ep, srcs, out) for (ep, srcs), out in zip(cases, outs)])
+    assert st == [0] * len(cases)
+    for (ep, srcs), out in zip(cases, outs):
+        got = out.cpu().numpy()
+        plain = g.bc(srcs, ep).cpu().numpy()
+        assert np.array_equal(got, plain), ("multi-source bc differs from plain", ep, len(srcs))
+        want = want0 if ep == e0 else o.bc(srcs)[1]
+        assert not (np.abs(got - want) > BC_RTOL * np.abs(want)).any(), ("bc vs oracle", ep, len(srcs))
+
+
+def test_multi_source_bc_overflow(dg):
+    """A chain of 63 diamonds has 2^63 shortest paths from its first vertex:
+    a batched BC query of 4 sources that include it reports the overflow;
+    one whose sources avoid it does not."""
+    k = 63
+    us, vs = [], []
+    for i in range(k):
+        a, b, c, d = 3 * i, 3 * i + 1, 3 * i + 2, 3 * i + 3
+        us += [a, a, b, c]
+        vs += [b, c, d, d]
+    n = 3 * k + 1
+    g = dg.Graph(n, w_max=1)
+    g.apply(synth.make_ops([synth.ADDV] * n + [synth.ADDE] * len(us), list(range(n)) + us, [0] * n + vs,
+                           [0] * n + [1] * len(us)))
+    o1 = torch.empty(n, dtype=torch.float64, device="cuda")
+    o2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = g.query_batch([(dg.Q_BC, g.epoch, [0, 3, 6, 9], o1), (dg.Q_BC, g.epoch, [3, 6, 9, 12], o2)])
+    assert st[0] == dg.E_OVERFLOW
+    assert st[1] == g.try_bc([3, 6, 9, 12])[0]
