@@ -195,13 +195,18 @@ struct MsSplit {
   uint32_t n_in;
   uint32_t* pile_out;
   uint32_t tag_out;
+  int32_t thr_old;      // the threshold of the bucket just settled
   int32_t thr;
   QCounters* cnt_out;   // fq, n_order = entries kept, far_min = least kept distance
   QCounters* reset;
 };
 
-// One lane per pile entry: the far bits whose distance fell below the
-// threshold become the vertex's near mask, the rest stay on the pile.
+// One lane per pile entry: the far bits whose distance now lies in
+// [thr_old, thr) become the vertex's near mask, those at or above thr stay
+// on the pile, and those below thr_old are dropped: such a distance was
+// reached below the threshold then in force, so it went through the near
+// frontier and its arcs were relaxed from it (relaxations do not clear far
+// bits).
 __global__ __launch_bounds__(Q_THREADS) void k_ms_split(MsSplit a) {
   __shared__ Shared sh;
   ms_reset(a.reset);
@@ -219,10 +224,13 @@ __global__ __launch_bounds__(Q_THREADS) void k_ms_split(MsSplit a) {
       for (uint32_t b = f; b; b &= b - 1) {
         const uint32_t q = __ffs(b) - 1;
         const int32_t dq = a.D[(uint64_t)v * MSQ + q];
-        if (dq < a.thr) near |= 1u << q;
-        else mn = min(mn, dq);
+        if (dq >= a.thr) {
+          keep |= 1u << q;
+          mn = min(mn, dq);
+        } else if (dq >= a.thr_old) {
+          near |= 1u << q;
+        }
       }
-      keep = f & ~near;
       a.fm[v] = keep;
       if (near) a.nm_out[v] = ((u64)a.tag_out << 32) | near;
     }
@@ -456,12 +464,13 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
     int32_t far_min = DIST_INF;
     do {
       if (tag >= MS_TAG_MAX) return fail(DG_E_HIP, "pass count exceeds the mask tag range");
+      const int32_t thr_old = thr;
       thr = far_min == DIST_INF ? (int32_t)std::min<int64_t>(DIST_INF, (int64_t)thr + delta)
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       const int nxt = slot ^ 1;
       // the split's near masks carry the tag the next pass reads
-      MsSplit a{st,          fr[qi], L.D,   L.nm[(tag - 1) & 1], L.fm, L.pile[pi], n_pile, L.pile[pi ^ 1],
-                tag,         thr,    &L.cnt[nxt], &L.cnt[slot]};
+      MsSplit a{st,  fr[qi],  L.D, L.nm[(tag - 1) & 1], L.fm,        L.pile[pi], n_pile, L.pile[pi ^ 1],
+                tag, thr_old, thr, &L.cnt[nxt],         &L.cnt[slot]};
       const uint32_t grid =
           std::max<uint32_t>(1, std::min<uint32_t>((n_pile + Q_THREADS - 1) / Q_THREADS, ms.split_grid));
       k_ms_split<<<grid, Q_THREADS, 0, s>>>(a);
