@@ -169,7 +169,7 @@ __device__ __forceinline__ void ms_relax_chunk(const MsPass& a, uint32_t c, uint
   }
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_ms_relax(MsPass a, unsigned long long nfq) {
+__global__ __launch_bounds__(Q_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_ms_relax(MsPass a, unsigned long long nfq) {
   __shared__ Shared sh;
   ms_reset(a.reset);
   const uint32_t wave = threadIdx.x >> 6;
