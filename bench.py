@@ -58,28 +58,34 @@ BATCH_BYTES_PER_ARC = {"batch_bfs": 28}
 MS_SSSP_BYTES = {"per_scan": 16, "per_relaxation": 4}
 ORACLE_WORKERS_MAX = 16   # the host cores one GPU's share of the box offers
 METRIC = "snapshot-query GTEPS + updates/s; p50/p99 query latency, batched vs plain"
-# HBM bytes per launch measured with rocprofv3 counters, valid only while the
-# kernel's sources are unchanged (their digest is stored beside the figure).
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sssp_relax_rmat20_traffic.txt")
+# HBM bytes per launch measured with rocprofv3 counters (profiles/*_traffic.txt),
+# valid only while the kernel's sources are unchanged (their digest is stored
+# beside the figure).
+PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic(kernel):
-    """Per-launch HBM bytes of `kernel` from the committed counter summary,
-    or None when there is none or the kernel's sources changed since."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            rec = next(json.loads(line[5:]) for line in f if line.startswith("json:"))
-    except (OSError, StopIteration, ValueError):
-        return None
-    if rec.get("kernel") != kernel or "sources" not in rec:
-        return None
+def measured_traffic(kernel, workload):
+    """Per-launch HBM bytes of `kernel` on `workload` (a file name part, e.g.
+    "rmat20") from the committed counter summaries, or None when there is
+    none or the kernel's sources changed since."""
+    import glob
     from paper_2109_09527_amd.rocprof_summary import sources_digest
-    try:
-        if sources_digest([os.path.join(ROOT, p) for p in rec["sources"]]) != rec.get("sources_sha256"):
-            return None
-    except OSError:
-        return None
-    return rec["bytes_per_dispatch"]
+    for path in sorted(glob.glob(os.path.join(PROFILES, f"*_{workload}_traffic.txt"))):
+        try:
+            with open(path) as f:
+                recs = [json.loads(line[5:]) for line in f if line.startswith("json:")]
+        except (OSError, ValueError):
+            continue
+        for rec in recs:
+            if rec.get("kernel") != kernel or "sources" not in rec:
+                continue
+            try:
+                if sources_digest([os.path.join(ROOT, p) for p in rec["sources"]]) != rec.get("sources_sha256"):
+                    return None
+            except OSError:
+                return None
+            return rec["bytes_per_dispatch"]
+    return None
 
 
 def pct(xs, p):
@@ -109,6 +115,8 @@ def main():
     ap.add_argument("--batch-queries", type=int, default=512,
                     help="queries of the batched-vs-plain comparison (0 = skip)")
     ap.add_argument("--batch-scale", type=int, default=21, help="R-MAT scale of the batched comparison")
+    ap.add_argument("--batch-tuning-file", default=None,
+                    help="as --tuning-file, for the batched comparison's graph")
     ap.add_argument("--c3-oracle", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.c3_oracle:
@@ -221,7 +229,7 @@ def main():
             avg_ms = kp["total_ms"] / kp["launches"]
             bytes_per_launch = kp["arcs"] * BYTES_PER_ARC[kname] / kp["launches"]
             achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-            traffic = measured_traffic("k_" + kname)
+            traffic = measured_traffic("k_" + kname, "rmat20")
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                     "avg_launch_us": round(avg_ms * 1e3, 2), "launches": kp["launches"],
@@ -318,7 +326,16 @@ def batched_vs_plain(args):
     torch.cuda.synchronize()
     print(f"[bench] batched configuration: R-MAT {args.batch_scale}, m={gr.m}, batches "
           f"{[len(b) for b in eq.batches]}, ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    tuning = g.autotune(seed=0)
+    tf = args.batch_tuning_file
+    if tf and os.path.exists(tf):
+        with open(tf) as f:
+            g.set_tuning(**json.load(f))
+        tuning = g.get_tuning()
+    else:
+        tuning = g.autotune(seed=0)
+        if tf:
+            with open(tf, "w") as f:
+                json.dump(tuning, f)
     print(f"[bench] batched configuration tuning {tuning}", file=sys.stderr, flush=True)
     n = gr.n
     nq = len(eq.kinds)
@@ -359,12 +376,16 @@ def batched_vs_plain(args):
     ms = [int(degs[e][o >= 0].sum().item()) for (k, e, s), o in zip(qs, batch)]
     m = sum(ms)
     roof = {k: kernel_roof(prof, k, BATCH_BYTES_PER_ARC[k]) for k in BATCH_BYTES_PER_ARC}
+    if roof.get("batch_bfs"):
+        # one launch holds the whole multi-source BFS engine run
+        roof["batch_bfs"]["traffic"] = measured_traffic("k_team", f"rmat{args.batch_scale}")
     kp, sc = prof.get("batch_sssp"), prof.get("batch_sssp_scan")
     if kp and sc and kp["launches"] and kp["total_ms"] > 0:
         nbytes = MS_SSSP_BYTES["per_scan"] * sc["arcs"] + MS_SSSP_BYTES["per_relaxation"] * kp["arcs"]
         achieved = nbytes / (kp["total_ms"] / 1e3) / 1e9
         roof["batch_sssp"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_ms_relax",
+                              "frac": round(achieved / HBM_PEAK_GBS, 4),
+                              "traffic": measured_traffic("k_ms_relax", f"rmat{args.batch_scale}"), "kernel": "k_ms_relax",
                               "avg_launch_us": round(kp["total_ms"] / kp["launches"] * 1e3, 2),
                               "launches": kp["launches"], "bytes_per_launch": int(nbytes / kp["launches"]),
                               "arcs_scanned": sc["arcs"], "relaxations": kp["arcs"],
