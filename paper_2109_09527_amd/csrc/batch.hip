@@ -347,18 +347,17 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
 }
 
 // A group of qd.k BFS queries on one snapshot (multi-source BFS, top-down
-// only).  vis and nxt reuse the BC arrays sigma and delta; the touched list
-// lives in fa.
+// only).  The per-vertex {visited, next} mask records use the bottom-up
+// chunk buffer (qbig: at least V + 1024 items of 16 bytes), which a
+// multi-source job never needs; the touched list lives in fa.
 __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
                                           uint32_t S, BarrierPos& bp, Shared& sh, int32_t* status) {
   const uint32_t V = a.st.V, k = qd.k;
   int32_t* const* outs = static_cast<int32_t* const*>(qd.out);
-  unsigned long long* vis = ts.sigma;
-  unsigned long long* nxt = reinterpret_cast<unsigned long long*>(ts.delta);
+  unsigned long long* vn = reinterpret_cast<unsigned long long*>(ts.qbig);
   unsigned long long* fr = ts.msf;
   const uint32_t wave = threadIdx.x >> 6, gw = w * Q_WAVES + wave, nw = S * Q_WAVES;
-  team_fill<unsigned long long>(vis, V, 0ull, w, S);
-  team_fill<unsigned long long>(nxt, V, 0ull, w, S);
+  team_fill<unsigned long long>(vn, 2ull * V, 0ull, w, S);
   team_fill<unsigned long long>(fr, V, 0ull, w, S);
   for (uint32_t q = 0; q < k; q++) team_fill<int32_t>(uni(outs[q]), V, -1, w, S);
   if (w == 0 && threadIdx.x == 0)
@@ -371,7 +370,7 @@ __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, c
     bool first = false;
     if (q < k) {
       const unsigned long long bit = 1ull << q;
-      first = atomicOr(&vis[v], bit) == 0ull;
+      first = atomicOr(&vn[2 * (uint64_t)v], bit) == 0ull;
       atomicOr(&fr[v], bit);
       outs[q][v] = 0;
     }
@@ -386,7 +385,7 @@ __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, c
     QCounters* cout = &ts.cnt[(lvl + 1) % 3];
     if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(lvl + 2) % 3]);
     const MsArgs ma{a.st, qd.epoch, a.fast, team_front(ts, lvl & 1), team_front(ts, (lvl + 1) & 1),
-                    fr,   vis,      nxt,    ts.fa,                   cout};
+                    fr,   vn,       ts.fa,  cout};
     {
       ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
       U32Q qt = u32_q(sh.ws[wave]);
@@ -402,7 +401,7 @@ __device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, c
     QUEUE_CHECK(cout);
     const uint32_t nt = uni(ld_relaxed(&cout->n_far));
     for (uint32_t base = gw * 64; base < nt; base += nw * 64)
-      msbfs_final_block(ts.fa, nt, base, fr, vis, nxt, outs, (int32_t)lvl);
+      msbfs_final_block(ts.fa, nt, base, fr, vn, outs, (int32_t)lvl);
     BARRIER();
   }
   return true;

@@ -1087,8 +1087,9 @@ struct MsArgs {
   Front fin;                      // vertices with a nonzero frontier mask
   Front fout;                     // touched vertices that have an out-slab
   const unsigned long long* fr;
-  const unsigned long long* vis;
-  unsigned long long* nxt;
+  // per vertex one 16-byte record {visited mask, next-level mask}, so an
+  // arc's target costs one line
+  unsigned long long* vn;
   uint32_t* touched;              // all touched vertices (count in cnt_out->n_far)
   QCounters* cnt_out;
 };
@@ -1109,8 +1110,11 @@ __device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_
       want[k] = 0ull;
       have[k] = 0ull;
       if (s4.vis[k]) {
-        want[k] = fm & ~a.vis[s4.d[k]];
-        have[k] = __hip_atomic_load(&a.nxt[s4.d[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // next-level masks only gain bits within a level, so a stale copy
+        // is a subset and at most costs an atomicOr that adds nothing
+        const ulonglong2 r = *reinterpret_cast<const ulonglong2*>(&a.vn[2 * (uint64_t)s4.d[k]]);
+        want[k] = fm & ~r.x;
+        have[k] = r.y;
       }
       lc.arcs += s4.vis[k] ? 1 : 0;
     }
@@ -1118,7 +1122,7 @@ __device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       before[k] = 1ull;
-      if (want[k] & ~have[k]) before[k] = atomicOr(&a.nxt[s4.d[k]], want[k]);
+      if (want[k] & ~have[k]) before[k] = atomicOr(&a.vn[2 * (uint64_t)s4.d[k] + 1], want[k]);
     }
     bool first[4];
     uint64_t yd[4];
@@ -1140,15 +1144,18 @@ __device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_
 // Touched vertices touched[base .. base + 64) of level `lvl` (the levels
 // reached are lvl + 1); outs[q] is query q's distance array.
 __device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint32_t n, uint32_t base,
-                                                  unsigned long long* fr, unsigned long long* vis,
-                                                  unsigned long long* nxt, int32_t* const* outs, int32_t lvl) {
+                                                  unsigned long long* fr, unsigned long long* vn,
+                                                  int32_t* const* outs, int32_t lvl) {
   const uint32_t i = base + lane_id();
   if (i >= n) return;
   const uint32_t v = touched[i];
-  unsigned long long nw = nxt[v] & ~vis[v];
-  vis[v] |= nw;
+  ulonglong2* rec = reinterpret_cast<ulonglong2*>(&vn[2 * (uint64_t)v]);
+  ulonglong2 r = *rec;
+  unsigned long long nw = r.y & ~r.x;
+  r.x |= nw;
+  r.y = 0ull;
+  *rec = r;
   fr[v] = nw;
-  nxt[v] = 0ull;
   while (nw) {
     const int b = __ffsll((long long)nw) - 1;
     nw &= nw - 1;
