@@ -447,6 +447,14 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
       if (w == 0 && threadIdx.x == 0) ts.off[nlev + 1] = ts.off[nlev] + found;
       nlev++;
     }
+    // the backward's tile lists live in the bottom-up chunk buffer, which
+    // a BC job does not otherwise use; the counts start at zero
+    const BwdTiles bt = bwd_tiles_at(reinterpret_cast<char*>(ts.qbig), a.st.fp.cap, 1);
+    if (w == 0 && threadIdx.x == 0) {
+      bt.head->verts[0] = bt.head->verts[1] = 0;
+      bt.head->tiles[0] = bt.head->tiles[1] = 0;
+      bt.head->ovf = 0;
+    }
     BARRIER();
     if (ld_relaxed(&ts.cnt[3].overflow) & OVF_SIGMA) {
       if (w == 0 && threadIdx.x == 0) *status = DG_E_OVERFLOW;
@@ -454,9 +462,20 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
     }
     for (int L = (int)nlev - 1; L >= 0; L--) {
       uint32_t o0 = uni(ld_relaxed(&ts.off[L])), o1 = uni(ld_relaxed(&ts.off[L + 1]));
-      bcbwd_step(a.st, qd.epoch, a.fast != 0, ts.fa + o0, o1 - o0, src, ts.level, L, ts.sigma, ts.delta, bc, w,
+      bcbwd_step(a.st, qd.epoch, a.fast != 0, ts.fa + o0, o1 - o0, src, ts.level, L, ts.sigma, ts.delta, bc, bt, w,
                  S);
       BARRIER();
+      const uint32_t nt = uni(ld_relaxed(&bt.head->tiles[L & 1]));
+      if (nt) {
+        bcbwd_tiles(a.st, qd.epoch, a.fast != 0, ts.level, L, ts.sigma, ts.delta, bt, nt, w, S);
+        BARRIER();
+        bcbwd_combine(bt, uni(ld_relaxed(&bt.head->verts[L & 1])), src, ts.delta, bc, w, S);
+        BARRIER();
+      }
+    }
+    if (ld_relaxed(&bt.head->ovf)) {
+      if (w == 0 && threadIdx.x == 0) *status = DG_E_OUT_OF_MEMORY;
+      return true;
     }
   }
   return true;
@@ -993,7 +1012,8 @@ static uint64_t team_layout(const Store& st, uint32_t chunk_buckets, char* base,
     ts->ccap = (uint32_t)std::min<uint64_t>(chunks, 0xFFFFFFFFu);
     ts->lch = 31 - __builtin_clz(chunk_buckets);
   }
-  p = take(big * sizeof(Item)); if (ts) ts->qbig = reinterpret_cast<Item*>(p);
+  // a BC job keeps its backward tile lists here
+  p = take(std::max<uint64_t>(big * sizeof(Item), bwd_tiles_bytes(st.fp.cap, 1))); if (ts) ts->qbig = reinterpret_cast<Item*>(p);
   p = take(bmw * 4); if (ts) ts->bm0 = reinterpret_cast<uint32_t*>(p);
   p = take(bmw * 4); if (ts) ts->bm1 = reinterpret_cast<uint32_t*>(p);
   p = take(bmw * 4); if (ts) ts->bm2 = reinterpret_cast<uint32_t*>(p);

@@ -84,6 +84,7 @@ struct QueryScratch {
   DevBuf bm0, bm1;              // frontier bitmaps
   DevBuf stamp, flag8;          // SSSP dedup state
   DevBuf sigma, delta, level;   // BC
+  DevBuf bt;                    // BC: backward tile lists and sums
   DevBuf rlist, rstamp;         // SSSP: vertices of the current bucket
   DevBuf counters;
   void* host_counters = nullptr;
@@ -150,7 +151,7 @@ struct MbScratch {
   DevBuf area;
   void* host = nullptr;
   uint32_t seq = 0;
-  uint32_t fwd_grid = 0, bwd_grid = 0;
+  uint32_t fwd_grid = 0, bwd_grid = 0, tiles_grid = 0;
 };
 
 // Per-kernel-family event timing (dg_profile_*).

@@ -1006,6 +1006,12 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, 
 
 // ------------------------------------------------------------------- BC
 
+// The BC backward sums a slab of more than BWD_TILE buckets as tiles (see
+// bcbwd_step below); the forward counts such vertices per level.
+constexpr uint32_t BWD_TILE = 32;        // buckets per tile (slabs hold 2^k buckets)
+constexpr uint32_t BWD_TILE_LOG = 5;
+__host__ __device__ inline bool bwd_is_big(uint64_t desc) { return desc != 0 && (desc & 63) > BWD_TILE_LOG; }
+
 struct BcFwdArgs {
   Store st;
   uint32_t e;
@@ -1056,6 +1062,7 @@ __device__ __forceinline__ void bcfwd_step(const BcFwdArgs& a, unsigned long lon
         }
         uint64_t yd = found ? a.st.fdesc[d] : 0;
         lc.verts += found ? 1 : 0;
+        lc.far += bwd_is_big(yd) ? 1 : 0;   // slabs the backward splits into tiles
         room_front(qn, 64, a.fout, a.cnt_out);
         push_item(qn, found, d, yd);
         room_u32(qo, 64, a.order, &a.cnt_total->n_order);
@@ -1163,35 +1170,163 @@ __device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint3
   }
 }
 
-// One wave per vertex of level L: delta[v] = sum over visible arcs v->w
-// with level[w] = L+1 of sigma[v]/sigma[w] * (1 + delta[w]); lane l reads
-// slot l%16 of bucket l/16 of each group of four buckets; the 64 partial
-// sums combine by a fixed butterfly, so the result is deterministic for a
-// given slab layout.
+// ------------------------------------------------- BC backward tiles
+//
+// The dependency of v at level L (Brandes' backward recurrence):
+//   delta[v] = sum over visible arcs v->w with level[w] = L+1 of
+//              sigma[v]/sigma[w] * (1 + delta[w]).
+// Its summation order is fixed by the slab layout alone: the slab is cut
+// into tiles of BWD_TILE buckets; in tile t, lane l adds the matching slots
+// l % 16 of buckets t BWD_TILE + l / 16 + 4i in increasing i, the 64 lane
+// sums combine by a fixed butterfly, and the tile sums add in tile order.
+// A slab of at most BWD_TILE buckets is one tile, summed by the wave that
+// takes the vertex; a longer one (a hub) is listed for a tile pass, one
+// wave per tile, and a combine pass adds its tile sums.  The plain, team
+// and multi-source searches all follow this order, so their dependencies
+// agree bit for bit.
+
+struct BigVert {
+  uint32_t v, base, n, pad;   // vertex v owns tiles [base, base + n)
+};
+// Counts of the listed vertices and their tiles, by level parity (a level
+// fills one parity while its pass zeroes the other's), and an overflow flag.
+struct BwdHead {
+  uint32_t verts[2], tiles[2];
+  uint32_t ovf, pad[3];
+};
+struct BwdTiles {
+  BwdHead* head;
+  BigVert* big;
+  uint32_t* tmap;     // tile -> index into big
+  double* part;       // tile sums (per tile: `per` doubles)
+  uint32_t cap_verts, cap_tiles;
+};
+
+
+// Capacities from the pool's bucket count: a listed slab holds at least
+// 2 BWD_TILE buckets, and the slabs of one level are distinct, so one
+// level lists at most cap / BWD_TILE tiles and cap / (2 BWD_TILE) vertices.
+__host__ __device__ inline uint64_t bwd_cap_tiles(uint64_t pool_buckets) { return pool_buckets / BWD_TILE + 1; }
+__host__ __device__ inline uint64_t bwd_cap_verts(uint64_t pool_buckets) { return pool_buckets / (2 * BWD_TILE) + 1; }
+__host__ __device__ inline uint64_t bwd_al(uint64_t x) { return (x + 255) & ~255ull; }
+__host__ __device__ inline uint64_t bwd_tiles_bytes(uint64_t pool_buckets, uint32_t per) {
+  return bwd_al(sizeof(BwdHead)) + bwd_al(bwd_cap_verts(pool_buckets) * sizeof(BigVert)) +
+         bwd_al(bwd_cap_tiles(pool_buckets) * 4) + bwd_al(bwd_cap_tiles(pool_buckets) * 8 * (uint64_t)per);
+}
+__host__ __device__ inline BwdTiles bwd_tiles_at(char* p, uint64_t pool_buckets, uint32_t per) {
+  BwdTiles t;
+  const uint64_t cv = bwd_cap_verts(pool_buckets), ct = bwd_cap_tiles(pool_buckets);
+  t.head = reinterpret_cast<BwdHead*>(p);
+  p += bwd_al(sizeof(BwdHead));
+  t.big = reinterpret_cast<BigVert*>(p);
+  p += bwd_al(cv * sizeof(BigVert));
+  t.tmap = reinterpret_cast<uint32_t*>(p);
+  p += bwd_al(ct * 4);
+  t.part = reinterpret_cast<double*>(p);
+  t.cap_verts = (uint32_t)(cv < 0xFFFFFFFFull ? cv : 0xFFFFFFFFull);
+  t.cap_tiles = (uint32_t)(ct < 0xFFFFFFFFull ? ct : 0xFFFFFFFFull);
+  return t;
+}
+
+// Wave-uniform: list vertex v (slab of nb > BWD_TILE buckets) for the tile
+// pass of its level (parity par); a full list raises the overflow flag.
+__device__ inline void bwd_list(const BwdTiles& t, uint32_t par, uint32_t v, uint32_t nb) {
+  const uint32_t n = nb >> BWD_TILE_LOG;
+  uint32_t idx = 0, base = 0;
+  if (lane_id() == 0) {
+    idx = atomicAdd(&t.head->verts[par], 1u);
+    base = atomicAdd(&t.head->tiles[par], n);
+  }
+  idx = uni(idx);
+  base = uni(base);
+  if (idx >= t.cap_verts || base >= t.cap_tiles || n > t.cap_tiles - base) {
+    if (lane_id() == 0) atomicOr(&t.head->ovf, 1u);
+    return;
+  }
+  if (lane_id() == 0) t.big[idx] = BigVert{v, base, n, 0};
+  for (uint32_t i = lane_id(); i < n; i += 64) t.tmap[base + i] = idx;
+}
+
+// The wave's sum over tile [b0, b1) of v's slab (combined over lanes).
+__device__ __forceinline__ double bwd_tile_sum(const Slab& s, uint32_t b0, uint32_t b1, uint32_t e, bool fast,
+                                               double sv, const int32_t* level, int32_t L,
+                                               const unsigned long long* sigma, const double* delta) {
+  const uint32_t lane = lane_id(), j = lane & 15;
+  double acc = 0.0;
+  for (uint32_t b = b0 + (lane >> 4); b < b1; b += 4) {
+    uint32_t* bp = bucket_ptr(s, b);
+    uint32_t w = bp[j];
+    if (w != EMPTY && slot_visible(s, bp, b, j, e, fast) && level[w] == L + 1)
+      acc += sv / (double)sigma[w] * (1.0 + delta[w]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  return acc;
+}
+
+// One wave per vertex of level L's list verts[0..nv): slabs of one tile
+// are summed here; longer slabs are listed for bcbwd_tiles.  Worker 0
+// zeroes the other parity's counts for the next level.
 __device__ __forceinline__ void bcbwd_step(const Store& st, uint32_t e, bool fast, const uint32_t* verts, uint32_t nv,
-                                  uint32_t src, const int32_t* level, int32_t L, const unsigned long long* sigma,
-                                  double* delta, double* bc, uint32_t worker, uint32_t nworkers) {
+                                           uint32_t src, const int32_t* level, int32_t L,
+                                           const unsigned long long* sigma, double* delta, double* bc,
+                                           const BwdTiles& bt, uint32_t worker, uint32_t nworkers) {
   const uint32_t lane = lane_id();
+  const uint32_t par = (uint32_t)L & 1u;
+  if (worker == 0 && threadIdx.x == 0) {
+    bt.head->verts[par ^ 1] = 0;
+    bt.head->tiles[par ^ 1] = 0;
+  }
   const uint32_t gwave = worker * Q_WAVES + (threadIdx.x >> 6);
   const uint32_t nwaves = nworkers * Q_WAVES;
   for (uint32_t k = gwave; k < nv; k += nwaves) {
-    uint32_t v = verts[k];
-    Slab s = slab_of(st.fp, st.fdesc[v]);
-    double sv = (double)sigma[v];
-    double acc = 0.0;
-    const uint32_t j = lane & 15;
-    for (uint32_t b = lane >> 4; b < s.nb; b += 4) {
-      uint32_t* bp = bucket_ptr(s, b);
-      uint32_t w = bp[j];
-      if (w != EMPTY && slot_visible(s, bp, b, j, e, fast) && level[w] == L + 1)
-        acc += sv / (double)sigma[w] * (1.0 + delta[w]);
+    const uint32_t v = verts[k];
+    const uint64_t desc = st.fdesc[v];
+    const Slab s = slab_of(st.fp, desc);
+    if (bwd_is_big(desc)) {
+      bwd_list(bt, par, v, s.nb);
+      continue;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    const double acc = bwd_tile_sum(s, 0, s.nb, e, fast, (double)sigma[v], level, L, sigma, delta);
     if (lane == 0) {
       delta[v] = acc;
       if (v != src) bc[v] += acc;
     }
+  }
+}
+
+// One wave per listed tile of level L: its sum into part[tile].
+__device__ __forceinline__ void bcbwd_tiles(const Store& st, uint32_t e, bool fast, const int32_t* level, int32_t L,
+                                            const unsigned long long* sigma, const double* delta, const BwdTiles& bt,
+                                            uint32_t nt, uint32_t worker, uint32_t nworkers) {
+  const uint32_t gwave = worker * Q_WAVES + (threadIdx.x >> 6);
+  const uint32_t nwaves = nworkers * Q_WAVES;
+  nt = min(nt, bt.cap_tiles);
+  for (uint32_t t = gwave; t < nt; t += nwaves) {
+    const uint32_t i = bt.tmap[t];
+    if (i >= bt.cap_verts) continue;
+    const BigVert bv = bt.big[i];
+    if (t < bv.base || t - bv.base >= bv.n) continue;
+    const Slab s = slab_of(st.fp, st.fdesc[bv.v]);
+    const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
+    if (b0 >= s.nb) continue;
+    const double acc =
+        bwd_tile_sum(s, b0, min(s.nb, b0 + BWD_TILE), e, fast, (double)sigma[bv.v], level, L, sigma, delta);
+    if (lane_id() == 0) bt.part[t] = acc;
+  }
+}
+
+// One lane per listed vertex of level L: its tile sums added in tile order.
+__device__ __forceinline__ void bcbwd_combine(const BwdTiles& bt, uint32_t nbig, uint32_t src, double* delta,
+                                              double* bc, uint32_t worker, uint32_t nworkers) {
+  nbig = min(nbig, bt.cap_verts);
+  for (uint32_t i = worker * Q_THREADS + threadIdx.x; i < nbig; i += nworkers * Q_THREADS) {
+    const BigVert bv = bt.big[i];
+    if (bv.n == 0 || bv.base >= bt.cap_tiles || bv.n > bt.cap_tiles - bv.base) continue;
+    double acc = bt.part[bv.base];
+    for (uint32_t t = 1; t < bv.n; t++) acc += bt.part[bv.base + t];
+    delta[bv.v] = acc;
+    if (bv.v != src) bc[bv.v] += acc;
   }
 }
 

@@ -130,6 +130,7 @@ __device__ __forceinline__ void mb_fwd_chunk(const MbFwd& a, uint32_t c, uint32_
       }
       const bool first = my_new && mb_mark(a.nm_out, d_k, a.tag_out, my_new);
       const uint64_t yd = first ? a.st.fdesc[d_k] : 0;
+      lc.far += bwd_is_big(yd) ? 1 : 0;   // slabs the backward splits into tiles
       room_front(qn, 64, a.fout, a.cnt_out);
       push_item(qn, first, d_k, yd);
       room_u32(qo, 64, a.order, &a.cnt_out->n_order);
@@ -155,34 +156,74 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_fwd(MbFwd a, unsigned long lon
   lc.commit(a.cnt_out, sh);
 }
 
-// Backward pass of level lvl over its vertex list verts[0..nv).
+// Per-lane sums over tile [b0, b1) of v's slab for the sources in m (the
+// plain path's terms and order, one accumulator per source).
+__device__ __forceinline__ void mb_tile_lanes(const Slab& sl, uint32_t b0, uint32_t b1, uint32_t e, bool fast,
+                                              uint32_t m, const double (&sv)[MBQ], int32_t lvl, const int32_t* L,
+                                              const unsigned long long* SG, const double* DL, double (&acc)[MBQ]) {
+  const uint32_t j = lane_id() & 15;
+  for (uint32_t b = b0 + (lane_id() >> 4); b < b1; b += 4) {
+    uint32_t* bp = bucket_ptr(sl, b);
+    const uint32_t w = bp[j];
+    if (w == EMPTY || !slot_visible(sl, bp, b, j, e, fast)) continue;
+    // the 16 levels of w: one 64-byte record, four 16-byte loads
+    const int4* lw = reinterpret_cast<const int4*>(&L[(uint64_t)w * MBQ]);
+    int32_t lv[MBQ];
+#pragma unroll
+    for (int q = 0; q < (int)(MBQ / 4); q++) {
+      const int4 x = lw[q];
+      lv[4 * q] = x.x;
+      lv[4 * q + 1] = x.y;
+      lv[4 * q + 2] = x.z;
+      lv[4 * q + 3] = x.w;
+    }
+#pragma unroll
+    for (int s = 0; s < (int)MBQ; s++) {
+      if (((m >> s) & 1u) && lv[s] == lvl + 1)
+        acc[s] += sv[s] / (double)SG[(uint64_t)w * MBQ + s] * (1.0 + DL[(uint64_t)w * MBQ + s]);
+    }
+  }
+}
+
+// The group's sources at level lvl for vertex v (wave-uniform), and their
+// path counts at v.
+__device__ __forceinline__ uint32_t mb_at_level(uint32_t v, int32_t lvl, uint32_t nq, const int32_t* L,
+                                                const unsigned long long* SG, double (&sv)[MBQ]) {
+  const uint32_t lane = lane_id(), j = lane & 15;
+  const bool at = j < nq && L[(uint64_t)v * MBQ + j] == lvl;
+  const uint32_t m = (uint32_t)(__ballot(at && lane < 16) & 0xFFFFull);
+#pragma unroll
+  for (int s = 0; s < (int)MBQ; s++) sv[s] = ((m >> s) & 1u) ? (double)SG[(uint64_t)v * MBQ + s] : 0.0;
+  return m;
+}
+
+// Backward pass of level lvl over its vertex list verts[0..nv): one wave
+// per vertex; slabs of more than BWD_TILE buckets are listed for the tile
+// pass (k_mb_tiles, k_mb_combine).  Workgroup 0 zeroes the other parity's
+// tile counts.
 __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int fast, const uint32_t* verts,
                                                       uint32_t nv, int32_t lvl, uint32_t nq, const int32_t* L,
-                                                      const unsigned long long* SG, double* DL) {
-  const uint32_t lane = lane_id(), j = lane & 15;
+                                                      const unsigned long long* SG, double* DL, BwdTiles bt) {
+  const uint32_t lane = lane_id();
+  const uint32_t par = (uint32_t)lvl & 1u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bt.head->verts[par ^ 1] = 0;
+    bt.head->tiles[par ^ 1] = 0;
+  }
   const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6), nwaves = gridDim.x * Q_WAVES;
   for (uint32_t k = gwave; k < nv; k += nwaves) {
     const uint32_t v = verts[k];
-    // the group's sources at this level, and their path counts at v
-    const bool at = j < nq && L[(uint64_t)v * MBQ + j] == lvl;
-    const uint32_t m = (uint32_t)(__ballot(at && lane < 16) & 0xFFFFull);
+    const uint64_t desc = st.fdesc[v];
+    const Slab sl = slab_of(st.fp, desc);
+    if (bwd_is_big(desc)) {
+      bwd_list(bt, par, v, sl.nb);
+      continue;
+    }
     double sv[MBQ], acc[MBQ];
+    const uint32_t m = mb_at_level(v, lvl, nq, L, SG, sv);
 #pragma unroll
-    for (int s = 0; s < (int)MBQ; s++) {
-      sv[s] = ((m >> s) & 1u) ? (double)SG[(uint64_t)v * MBQ + s] : 0.0;
-      acc[s] = 0.0;
-    }
-    const Slab sl = slab_of(st.fp, st.fdesc[v]);
-    for (uint32_t b = lane >> 4; b < sl.nb; b += 4) {
-      uint32_t* bp = bucket_ptr(sl, b);
-      const uint32_t w = bp[j];
-      if (w == EMPTY || !slot_visible(sl, bp, b, j, e, fast != 0)) continue;
-#pragma unroll
-      for (int s = 0; s < (int)MBQ; s++) {
-        if (((m >> s) & 1u) && L[(uint64_t)w * MBQ + s] == lvl + 1)
-          acc[s] += sv[s] / (double)SG[(uint64_t)w * MBQ + s] * (1.0 + DL[(uint64_t)w * MBQ + s]);
-      }
-    }
+    for (int s = 0; s < (int)MBQ; s++) acc[s] = 0.0;
+    mb_tile_lanes(sl, 0, sl.nb, e, fast != 0, m, sv, lvl, L, SG, DL, acc);
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) {
       if (!((m >> s) & 1u)) continue;   // wave-uniform
@@ -191,6 +232,54 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int 
       for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
       if (lane == 0) DL[(uint64_t)v * MBQ + s] = x;
     }
+  }
+}
+
+// One wave per listed tile of level lvl: its sums into part[tile * MBQ + s].
+__global__ __launch_bounds__(Q_THREADS) void k_mb_tiles(Store st, uint32_t e, int fast, int32_t lvl, uint32_t nq,
+                                                        const int32_t* L, const unsigned long long* SG,
+                                                        const double* DL, BwdTiles bt) {
+  const uint32_t lane = lane_id();
+  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6), nwaves = gridDim.x * Q_WAVES;
+  const uint32_t nt = min(bt.head->tiles[lvl & 1], bt.cap_tiles);
+  for (uint32_t t = gwave; t < nt; t += nwaves) {
+    const uint32_t i = bt.tmap[t];
+    if (i >= bt.cap_verts) continue;
+    const BigVert bv = bt.big[i];
+    if (t < bv.base || t - bv.base >= bv.n) continue;
+    const Slab sl = slab_of(st.fp, st.fdesc[bv.v]);
+    const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
+    if (b0 >= sl.nb) continue;
+    double sv[MBQ], acc[MBQ];
+    const uint32_t m = mb_at_level(bv.v, lvl, nq, L, SG, sv);
+#pragma unroll
+    for (int s = 0; s < (int)MBQ; s++) acc[s] = 0.0;
+    mb_tile_lanes(sl, b0, min(sl.nb, b0 + BWD_TILE), e, fast != 0, m, sv, lvl, L, SG, DL, acc);
+#pragma unroll
+    for (int s = 0; s < (int)MBQ; s++) {
+      if (!((m >> s) & 1u)) continue;   // wave-uniform
+      double x = acc[s];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) bt.part[(uint64_t)t * MBQ + s] = x;
+    }
+  }
+}
+
+// One lane per (listed vertex, source at level lvl): the tile sums added in
+// tile order.
+__global__ __launch_bounds__(Q_THREADS) void k_mb_combine(int32_t lvl, uint32_t nq, const int32_t* L, double* DL,
+                                                          BwdTiles bt) {
+  const uint32_t nbig = min(bt.head->verts[lvl & 1], bt.cap_verts);
+  for (uint64_t x = (uint64_t)blockIdx.x * Q_THREADS + threadIdx.x; x < (uint64_t)nbig * MBQ;
+       x += (uint64_t)gridDim.x * Q_THREADS) {
+    const uint32_t i = (uint32_t)(x / MBQ), s = (uint32_t)(x % MBQ);
+    const BigVert bv = bt.big[i];
+    if (s >= nq || L[(uint64_t)bv.v * MBQ + s] != lvl) continue;
+    if (bv.n == 0 || bv.base >= bt.cap_tiles || bv.n > bt.cap_tiles - bv.base) continue;
+    double acc = bt.part[(uint64_t)bv.base * MBQ + s];
+    for (uint32_t t = 1; t < bv.n; t++) acc += bt.part[(uint64_t)(bv.base + t) * MBQ + s];
+    DL[(uint64_t)bv.v * MBQ + s] = acc;
   }
 }
 
@@ -206,7 +295,9 @@ __global__ void k_mb_accum(const int32_t* L, const double* DL, const uint32_t* s
   }
 }
 
-__global__ void k_mb_init(int32_t* L, unsigned long long* SG, uint32_t* nm0, uint32_t* nm1, uint64_t V) {
+__global__ void k_mb_init(int32_t* L, unsigned long long* SG, uint32_t* nm0, uint32_t* nm1, uint64_t V,
+                          BwdHead* head) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *head = BwdHead{};
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V * MBQ; i += (uint64_t)gridDim.x * blockDim.x) {
     L[i] = -1;
     SG[i] = 0ull;
@@ -250,6 +341,10 @@ struct MbHost {
   uint32_t seq;
 };
 
+__global__ void k_mb_tile_flag(const BwdHead* head, QCounters* c) {
+  if (threadIdx.x == 0) c->overflow = head->ovf;
+}
+
 __global__ void k_mb_publish(const QCounters* c, MbHost* h, uint32_t seq) {
   if (threadIdx.x != 0) return;
   h->c = *c;
@@ -269,6 +364,7 @@ struct MbLayout {
   uint32_t* cmap[2];
   QCounters* cnt;
   uint32_t* src;
+  BwdTiles bt;
 };
 
 static uint64_t mb_layout(const Store& st, char* base, MbLayout* P) {
@@ -293,6 +389,7 @@ static uint64_t mb_layout(const Store& st, char* base, MbLayout* P) {
   for (int i = 0; i < 2; i++) { p = take(chunks * 4); if (P) P->cmap[i] = reinterpret_cast<uint32_t*>(p); }
   p = take(2 * sizeof(QCounters)); if (P) P->cnt = reinterpret_cast<QCounters*>(p);
   p = take(MBQ * 4); if (P) P->src = reinterpret_cast<uint32_t*>(p);
+  p = take(bwd_tiles_bytes(st.fp.cap, MBQ)); if (P) P->bt = bwd_tiles_at(p, st.fp.cap, MBQ);
   return o;
 }
 
@@ -335,6 +432,7 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
   if (!mb.fwd_grid) {
     mb.fwd_grid = mb_resident((const void*)k_mb_fwd);
     mb.bwd_grid = mb_resident((const void*)k_mb_bwd);
+    mb.tiles_grid = mb_resident((const void*)k_mb_tiles);
   }
   MbLayout P;
   mb_layout(st, mb.area.as<char>(), &P);
@@ -343,7 +441,7 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
   const uint32_t ccap = (uint32_t)std::min<uint64_t>(st.fp.cap / CH_MIN + 2, 0xFFFFFFFFu);
   Front fr[2] = {Front{P.q[0], P.cmap[0], qcap, ccap, lch}, Front{P.q[1], P.cmap[1], qcap, ccap, lch}};
   const uint64_t V = st.V;
-  k_mb_init<<<(uint32_t)std::min<uint64_t>((V * MBQ + 255) / 256, 8192), 256, 0, s>>>(P.L, P.SG, P.nm[0], P.nm[1], V);
+  k_mb_init<<<(uint32_t)std::min<uint64_t>((V * MBQ + 255) / 256, 8192), 256, 0, s>>>(P.L, P.SG, P.nm[0], P.nm[1], V, P.bt.head);
   if ((he = hipMemcpyAsync(P.src, srcs, k * 4, hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail(DG_E_HIP, std::string("upload: ") + hipGetErrorString(he));
   k_mb_seed<<<1, 64, 0, s>>>(st, P.src, k, P.L, P.SG, P.nm[0], P.order, fr[0], &P.cnt[0], &P.cnt[1]);
@@ -369,6 +467,7 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
   if ((he = read(0, &hc)) != hipSuccess) return fail(DG_E_HIP, std::string("seed: ") + hipGetErrorString(he));
   // off[l] .. off[l + 1]: the vertex list of level l in order[]
   std::vector<uint64_t> off{0, k};
+  std::vector<uint32_t> nbig{1};   // listed (long-slab) vertices per level; the sources are not counted
   unsigned long long near = hc.fq;
   int slot = 0, qi = 0;
   uint32_t tag = 1;
@@ -395,24 +494,38 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
     }
     if (used + hc.n_order > P.order_cap) return fail(DG_E_OUT_OF_MEMORY, "level list capacity exceeded");
     arcs += hc.arcs;
-    if (hc.n_order) off.push_back(used + hc.n_order);
+    if (hc.n_order) {
+      off.push_back(used + hc.n_order);
+      nbig.push_back(hc.n_far);
+    }
     near = hc.fq;
     slot = nxt;
     qi ^= 1;
     tag++;
     if (!hc.n_order) break;
   }
-  // levels in decreasing order
+  // levels in decreasing order (k_mb_init zeroed the tile counts)
   ProfScope ps(g, KID_BATCH_BC, s);
   for (int32_t lvl = (int32_t)off.size() - 2; lvl >= 0; lvl--) {
     const uint64_t o0 = off[lvl], n = off[lvl + 1] - off[lvl];
     if (!n) continue;
     const uint32_t grid =
         std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)((n + Q_WAVES - 1) / Q_WAVES), mb.bwd_grid));
-    k_mb_bwd<<<grid, Q_THREADS, 0, s>>>(st, e, fast, P.order + o0, (uint32_t)n, lvl, k, P.L, P.SG, P.DL);
+    k_mb_bwd<<<grid, Q_THREADS, 0, s>>>(st, e, fast, P.order + o0, (uint32_t)n, lvl, k, P.L, P.SG, P.DL, P.bt);
+    if (nbig[lvl]) {
+      k_mb_tiles<<<mb.tiles_grid, Q_THREADS, 0, s>>>(st, e, fast, lvl, k, P.L, P.SG, P.DL, P.bt);
+      const uint64_t lanes = (uint64_t)nbig[lvl] * MBQ;
+      k_mb_combine<<<(uint32_t)std::min<uint64_t>((lanes + Q_THREADS - 1) / Q_THREADS, 4096), Q_THREADS, 0, s>>>(
+          lvl, k, P.L, P.DL, P.bt);
+    }
   }
   k_mb_accum<<<(uint32_t)std::min<uint64_t>((V + 255) / 256, 4096), 256, 0, s>>>(P.L, P.DL, P.src, k, V, bc);
   if ((he = hipGetLastError()) != hipSuccess) return fail(DG_E_HIP, std::string("backward: ") + hipGetErrorString(he));
+  // the tile lists' overflow flag (their capacity covers every level)
+  k_mb_tile_flag<<<1, 64, 0, s>>>(P.bt.head, &P.cnt[0]);
+  if ((he = hipGetLastError()) != hipSuccess || (he = read(0, &hc)) != hipSuccess)
+    return fail(DG_E_HIP, std::string("backward: ") + hipGetErrorString(he));
+  if (hc.overflow) return fail(DG_E_OUT_OF_MEMORY, "backward tile list capacity exceeded");
   if (arcs_out) *arcs_out += arcs;
   return DG_OK;
 }

@@ -136,8 +136,20 @@ __global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, unsigned long
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_bwd(Store st, uint32_t e, int fast, const uint32_t* verts,
                                                       uint32_t nv, uint32_t src, const int32_t* level, int32_t L,
-                                                      const unsigned long long* sigma, double* delta, double* bc) {
-  bcbwd_step(st, e, fast != 0, verts, nv, src, level, L, sigma, delta, bc, blockIdx.x, gridDim.x);
+                                                      const unsigned long long* sigma, double* delta, double* bc,
+                                                      BwdTiles bt) {
+  bcbwd_step(st, e, fast != 0, verts, nv, src, level, L, sigma, delta, bc, bt, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bc_tiles(Store st, uint32_t e, int fast, const int32_t* level, int32_t L,
+                                                        const unsigned long long* sigma, const double* delta,
+                                                        BwdTiles bt) {
+  bcbwd_tiles(st, e, fast != 0, level, L, sigma, delta, bt, bt.head->tiles[L & 1], blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(Q_THREADS) void k_bc_combine(BwdTiles bt, int32_t L, uint32_t src, double* delta,
+                                                          double* bc) {
+  bcbwd_combine(bt, bt.head->verts[L & 1], src, delta, bc, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_inf_to_minus1(int32_t* d, uint32_t n) {
@@ -207,7 +219,7 @@ __global__ void k_publish(const QCounters* cnt, const CountStripe* st, int slot,
 // query kinds asked for).
 struct QuerySizes {
   uint64_t items, chunks;
-  uint64_t qa, qb, cmap_a, cmap_b, bm0, bm1, counters, fb, stamp, flag8, rlist, rstamp, fa, sigma, delta, level;
+  uint64_t qa, qb, cmap_a, cmap_b, bm0, bm1, counters, fb, stamp, flag8, rlist, rstamp, fa, sigma, delta, level, bt;
 };
 
 static QuerySizes query_sizes(const dg_graph* g, bool sssp, bool bc) {
@@ -226,6 +238,7 @@ static QuerySizes query_sizes(const dg_graph* g, bool sssp, bool bc) {
     z.fa = V * 4 + 64;
     z.sigma = z.delta = V * 8 + 64;
     z.level = V * 4 + 64;
+    z.bt = bwd_tiles_bytes(g->st.fp.cap, 1);
   }
   return z;
 }
@@ -275,7 +288,8 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
         {&q.qa, z.qa},       {&q.qb, z.qb},       {&q.cmap_a, z.cmap_a}, {&q.cmap_b, z.cmap_b},
         {&q.bm0, z.bm0},     {&q.bm1, z.bm1},     {&q.counters, z.counters}, {&q.fb, z.fb},
         {&q.stamp, z.stamp}, {&q.flag8, z.flag8}, {&q.rlist, z.rlist},   {&q.rstamp, z.rstamp},
-        {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level}};
+        {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level},
+        {&q.bt, z.bt}};
     for (const auto& n : need)
       if (n.second && (!n.first->p || n.first->bytes < n.second)) return hipErrorInvalidValue;
     return q.dev_pub ? hipSuccess : hipErrorInvalidValue;
@@ -285,7 +299,8 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
       {&q.qa, z.qa},       {&q.qb, z.qb},       {&q.cmap_a, z.cmap_a}, {&q.cmap_b, z.cmap_b},
       {&q.bm0, z.bm0},     {&q.bm1, z.bm1},     {&q.counters, z.counters}, {&q.fb, z.fb},
       {&q.stamp, z.stamp}, {&q.flag8, z.flag8}, {&q.rlist, z.rlist},   {&q.rstamp, z.rstamp},
-      {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level}};
+      {&q.fa, z.fa},       {&q.sigma, z.sigma}, {&q.delta, z.delta},   {&q.level, z.level},
+        {&q.bt, z.bt}};
   for (const auto& n : need)
     if (n.second && (e = ensure(*n.first, n.second)) != hipSuccess) return e;
   if (!q.host_pub) {
@@ -302,7 +317,7 @@ static hipError_t ensure_query_scratch(dg_graph* g, QueryScratch& q, bool sssp, 
 void free_query_scratch(QueryScratch& q) {
   release(q.qa); release(q.qb); release(q.cmap_a); release(q.cmap_b); release(q.fa); release(q.fb); release(q.bm0); release(q.bm1);
   release(q.stamp); release(q.flag8); release(q.sigma); release(q.delta); release(q.level);
-  release(q.rlist); release(q.rstamp);
+  release(q.rlist); release(q.rstamp); release(q.bt);
   release(q.counters);
   if (q.host_counters) hipHostFree(q.host_counters);
   q.host_counters = nullptr;
@@ -595,9 +610,11 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
   // cnt[0..1] alternate per level; cnt[2] holds the running order total
   // and the overflow flag of the current source
   QCounters* tot = cnt + 2;
+  const BwdTiles bt = bwd_tiles_at(q.bt.as<char>(), g->st.fp.cap, 1);
   fill<double>(bc, V, 0.0, s);
   fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
-  std::vector<uint32_t> off;
+  fill<uint32_t>(reinterpret_cast<uint32_t*>(bt.head), sizeof(BwdHead) / 4, 0u, s);
+  std::vector<uint32_t> off, nbig;
   for (uint32_t si = 0; si < k; si++) {
     uint32_t src = srcs[si];
     fill<int32_t>(level, V, -1, s);
@@ -610,6 +627,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
     if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "bc seed");
     off.assign(1, 0);
     off.push_back(1);
+    nbig.assign(1, 1);   // the source's slab is not counted: assume it is long
     unsigned long long fq = hc.fq;
     int lvl = 0;
     while (true) {
@@ -627,6 +645,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
       prof_arcs(g, KID_BC_FWD, hc.arcs);
       if (hc.n_verts == 0) break;
       off.push_back(off.back() + hc.n_verts);
+      nbig.push_back(hc.n_far);
       fq = hc.fq;
       lvl++;
     }
@@ -640,13 +659,31 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
         return DG_E_OVERFLOW;
       }
     }
+    // both parities' tile counts start at zero
+    fill<uint32_t>(reinterpret_cast<uint32_t*>(bt.head), 4, 0u, s);
     for (int L = (int)off.size() - 2; L >= 0; L--) {
       uint32_t nv = off[L + 1] - off[L];
       ProfScope ps(g, KID_BC_BWD, s);
       k_bc_bwd<<<grid_for(nv, Q_WAVES), Q_THREADS, 0, s>>>(g->st, e, fast, order + off[L], nv, src, level, L,
-                                                           sigma, delta, bc);
+                                                           sigma, delta, bc, bt);
+      if (nbig[L]) {
+        k_bc_tiles<<<resident((const void*)k_bc_tiles), Q_THREADS, 0, s>>>(g->st, e, fast, level, L, sigma, delta,
+                                                                          bt);
+        k_bc_combine<<<grid_for(nbig[L], Q_THREADS), Q_THREADS, 0, s>>>(bt, L, src, delta, bc);
+      }
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc bwd launch");
+  }
+  {
+    uint32_t ovf = 0;
+    if ((he = hipMemcpyAsync(q.host_counters, &bt.head->ovf, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (he = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(g, he, "bc tiles");
+    std::memcpy(&ovf, q.host_counters, 4);
+    if (ovf) {
+      g->err = "backward tile list capacity exceeded";
+      return DG_E_OUT_OF_MEMORY;
+    }
   }
   return DG_OK;
 }
