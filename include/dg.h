@@ -309,16 +309,20 @@ dg_status dg_out_degrees(dg_graph* g, dg_epoch e, uint32_t* deg, void* stream);
 
 /*
  * Serving loop: requests are admitted in arrival order.  Update batches run
- * on an update stream (each publishes the next epoch).  Queries run on
- * query_lanes lanes, each a host thread with a stream and an engine instance
- * of its own: a free lane takes the queries at the head of the queue (up to
- * max_batch, within max_inflight queries admitted across lanes) and runs
- * them in one engine launch, binding each to the latest epoch published when
- * it is admitted (its linearization point).  Queries that arrive while a
- * lane is busy go to the next lane to come free, so launches overlap on the
- * device with each other and with update batches.  Admission reserves
- * device memory for a query's output from mem_budget; queries wait while the
- * budget is exhausted.
+ * on an update stream (each publishes the next epoch).  BFS queries join a
+ * running multi-source search of 64 slots (the BFS executor): before each
+ * of its passes, waiting BFS queries take the free slots, each bound to the
+ * latest epoch published at that moment (its linearization point), and a
+ * slot frees up as soon as its query's search is complete.  SSSP and BC
+ * queries run on query_lanes lanes, each a host thread with a stream and an
+ * engine instance of its own: a free lane takes the queries at the head of
+ * its queue (up to max_batch, within max_inflight queries admitted in all)
+ * and runs them in one engine call, binding each to the latest epoch
+ * published when it is admitted.  Queries that arrive while a lane is busy
+ * go to the next lane to come free, so the executor's passes, the lanes'
+ * launches and the update batches overlap on the device.  Admission
+ * reserves device memory for a query's output from mem_budget; queries wait
+ * while the budget is exhausted.
  * dg_server_submit_* copy their inputs and return a ticket immediately;
  * dg_server_poll reports whether a ticket finished, its status, bound epoch
  * and latency; dg_server_take copies a finished query's output to a host
@@ -331,6 +335,7 @@ typedef struct {
   uint32_t max_batch;      /* queries fused into one launch; 0 = 64 */
   uint32_t query_lanes;    /* engine launches in flight at once, 1..4; 0 = 1 */
   uint32_t log_ops;        /* 1 = keep every update's ops for dg_server_log (16 B per op until stop) */
+  uint32_t bfs_rounds;     /* 1 = BFS queries run in the lanes' rounds; 0 = in the continuous BFS executor */
 } dg_server_config;
 typedef struct {
   uint64_t completed, updates, queries, ops_applied;
@@ -338,6 +343,7 @@ typedef struct {
   double p50_query_ms, p99_query_ms, p50_update_ms, p99_update_ms;
   double wall_s;                     /* first arrival -> last completion */
   uint64_t edges_traversed;          /* sum of TEPS numerators of finished queries */
+  uint64_t joined_running;           /* BFS queries admitted into a search other queries were running in */
 } dg_server_stats;
 dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** out);
 dg_status dg_server_stop(dg_server* s);

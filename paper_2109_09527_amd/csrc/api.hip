@@ -576,6 +576,16 @@ dg_status dg_compact(dg_graph* g, void* stream) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lku(g->upd_mu);
   std::unique_lock<std::mutex> lk(g->mu);
+  // running multi-pass searches hold slab descriptors between passes
+  struct Waiting {
+    dg_graph* g;
+    ~Waiting() {
+      g->compact_waiting--;
+      g->pool_cv.notify_all();
+    }
+  } waiting{g};
+  g->compact_waiting++;
+  g->pool_cv.wait(lk, [g] { return g->search_holds == 0; });
   PoolWrite pw(g, lk);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipDeviceSynchronize() != hipSuccess) return fail(g, DG_E_HIP, "compaction: device sync");
@@ -769,7 +779,8 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
   static const char* names[KID_COUNT] = {"update_batch", "bfs_top_down", "bfs_bottom_up", "sssp_relax",
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
                                          "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
-                                         "diameter",     "maxflow",      "dfs",          "pool_growth",  "batch_sssp_scan"};
+                                         "diameter",     "maxflow",      "dfs",          "pool_growth",  "batch_sssp_scan",
+                                         "serve_bfs"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

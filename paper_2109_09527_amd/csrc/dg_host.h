@@ -174,6 +174,7 @@ enum KernelId {
   KID_DFS,          // the one-wave depth-first walk
   KID_POOL_GROW,    // one reallocation of the bucket pools (host clock, waits included)
   KID_BATCH_SSSP_SCAN,  // multi-source SSSP searches: arcs scanned once for a whole group
+  KID_SERVE_BFS,    // one expansion pass of the serving loop's BFS executor
   KID_COUNT
 };
 struct Prof {
@@ -237,6 +238,12 @@ struct dg_graph {
   std::condition_variable pool_cv;
   int pool_readers = 0;
   int pool_writers = 0;
+  // A search that spans many passes (the serving loop's BFS executor) keeps
+  // slab descriptors in its frontier between passes: compaction, which
+  // moves slabs, waits until no such search runs (search_holds), and
+  // searches admit no new queries while a compaction waits.
+  int search_holds = 0;
+  std::atomic<int> compact_waiting{0};
   std::mutex upd_mu;            // one update batch (or compaction) at a time
 };
 

@@ -3,16 +3,24 @@
 //
 //   update thread  applies update requests in arrival order on its own
 //                  stream; each publishes the next epoch.
+//   BFS executor   one multi-source BFS search of 64 slots that runs pass
+//                  after pass on its own stream while any slot is active;
+//                  before every pass, waiting BFS queries take the free
+//                  slots, each bound to the latest published epoch at that
+//                  moment (its linearization point), and join the running
+//                  search.  A finished slot's output is copied to the host
+//                  by a copy thread, after which the slot is reused.
 //   query lanes    (query_lanes threads, each with a stream and an engine
 //                  instance of its own) each take, whenever it is free, the
-//                  waiting queries at the head of the queue in arrival order
-//                  while their output memory fits the budget and the
-//                  in-flight cap allows (up to max_batch at once), bind them
-//                  to the latest published epoch (their linearization point)
-//                  and run them in one persistent engine launch.  A query
-//                  arriving while a lane is busy is taken by the next lane to
-//                  come free, so the launches of different lanes overlap on
-//                  the device with each other and with the update stream.
+//                  waiting SSSP and BC queries at the head of the queue in
+//                  arrival order while their output memory fits the budget
+//                  and the in-flight cap allows (up to max_batch at once),
+//                  bind them to the latest published epoch and run them in
+//                  one engine call.  A query arriving while a lane is busy
+//                  is taken by the next lane to come free, so the launches
+//                  of the lanes, the executor and the update stream overlap
+//                  on the device.  (With bfs_rounds set, BFS queries also go
+//                  to the lanes.)
 // While a server runs, scans read per-slot stamps (no summary fast path),
 // since update kernels may write slabs under running queries, and the
 // engine launches share part of the device's resident-workgroup capacity
@@ -28,6 +36,7 @@
 #include <vector>
 
 #include "dg_host.h"
+#include "xbfs.h"
 
 namespace {
 
@@ -62,6 +71,7 @@ struct dg_server {
   std::mutex m;
   std::condition_variable cv, cv_done;
   std::deque<Req*> uq, qq;
+  std::deque<Req*> bq;           // BFS queries waiting for a slot of the BFS executor
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next = 1;
   bool stop = false;
@@ -72,6 +82,21 @@ struct dg_server {
   std::vector<std::thread> tq;   // one per query lane
   hipStream_t su = nullptr;
   std::vector<hipStream_t> sq;   // one per query lane
+  // the continuous BFS executor: its thread and stream, and a thread that
+  // copies finished outputs to the host so that passes keep running
+  std::thread tb, tc;
+  hipStream_t sb = nullptr, sc = nullptr;
+  struct Done {
+    Req* r;
+    uint32_t slot;
+    const void* dev;
+    uint32_t epoch;
+  };
+  std::deque<Done> copies;
+  std::condition_variable cv_copy;
+  bool copy_stop = false;
+  unsigned long long xb_draining = 0;   // slots whose output is being copied
+  uint64_t joined_running = 0;          // BFS queries admitted while others of the search were running
   clk::time_point t0;
   std::vector<double> lat_all, lat_q, lat_u;
   uint64_t ops_applied = 0, arcs = 0, n_upd = 0, n_qry = 0;
@@ -239,6 +264,226 @@ struct dg_server {
       if (pinned) dg_snapshot_release(g, e_bind);
     }
   }
+
+  // ---- continuous BFS executor
+  //
+  // One multi-source search of up to 64 slots runs pass after pass while
+  // any slot is active.  Before each pass, waiting BFS queries take free
+  // slots (arrival order, within the memory budget and the in-flight cap),
+  // each bound to the latest published epoch at that moment; their sources
+  // join the pass.  A slot that reached no new vertex in a pass is finished:
+  // its output goes to the copy thread, and its slot is reused once the copy
+  // is done (its visited bits are cleared when the next query takes it).
+  struct XSlot {
+    Req* r = nullptr;
+    uint32_t epoch = 0;
+    bool pinned = false;
+    dg::DevBuf out;
+    int32_t start = 0;
+  };
+
+  void bfs_loop() {
+    dg::XbState* x = dg::xb_create();
+    std::vector<XSlot> slot(dg::XB_SLOTS);
+    unsigned long long active = 0, dirty = 0;
+    int32_t pass = 0;
+    const uint64_t V = g->cfg.v_capacity;
+    const uint32_t share = std::max<uint32_t>(1, g->engine_share_pct);
+    bool held = false;   // this executor's search hold (compaction waits while it is held)
+    auto hold = [&](bool on) {
+      std::unique_lock<std::mutex> lk(g->mu);
+      if (on) {
+        g->pool_cv.wait(lk, [&] { return g->compact_waiting.load() == 0; });
+        g->search_holds++;
+      } else {
+        g->search_holds--;
+        g->pool_cv.notify_all();
+      }
+      held = on;
+    };
+    for (;;) {
+      std::vector<uint32_t> joined;
+      if (!active) {
+        if (held) hold(false);
+        pass = 0;   // levels count from each slot's start, so the pass number may restart
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] {
+          return (stop && bq.empty() && !xb_draining) ||
+                 (!bq.empty() && (~xb_draining) != 0 && q_running < cfg.max_inflight &&
+                  mem_used + out_bytes(bq.front()) <= cfg.mem_budget);
+        });
+        if (bq.empty() && stop && !xb_draining) break;
+      }
+      if (!held) hold(true);
+      {
+        std::unique_lock<std::mutex> lk(m);
+        // no admission while a compaction waits: the search drains first
+        auto admissible = [&] {
+          return !bq.empty() && (~(active | xb_draining)) != 0 && q_running < cfg.max_inflight &&
+                 mem_used + out_bytes(bq.front()) <= cfg.mem_budget && g->compact_waiting.load() == 0;
+        };
+        const bool others = active != 0;
+        while (admissible()) {
+          Req* r = bq.front();
+          const uint64_t need = out_bytes(r);
+          bq.pop_front();
+          mem_used += need;
+          r->reserve = need;
+          busy++;
+          q_running++;
+          const uint32_t b = (uint32_t)__builtin_ctzll(~(active | xb_draining));
+          slot[b].r = r;
+          active |= 1ull << b;
+          joined.push_back(b);
+          if (others) joined_running++;
+        }
+      }
+      dg::XbSeeds seeds{};
+      unsigned long long clear = 0;
+      for (uint32_t b : joined) {
+        XSlot& sl = slot[b];
+        dg_epoch e = 0;
+        sl.pinned = dg_snapshot_acquire(g, DG_EPOCH_LATEST, &e) == DG_OK;
+        sl.epoch = e;
+        const uint32_t src = sl.r->srcs[0];
+        dg_status st = DG_OK;
+        if (src >= V) {
+          st = DG_E_VERTEX_RANGE;
+        } else {
+          std::lock_guard<std::mutex> lk(g->mu);
+          if (!dg::alive_at(g, src, e)) st = DG_E_SOURCE_ABSENT;
+        }
+        if (st == DG_OK && dg::ensure(sl.out, V * 4) != hipSuccess) st = DG_E_OUT_OF_MEMORY;
+        if (st == DG_OK && dg::fill_i32(sl.out.as<int32_t>(), V, -1, sb) != hipSuccess) st = DG_E_HIP;
+        if (st != DG_OK) {
+          if (sl.pinned) dg_snapshot_release(g, e);
+          sl.pinned = false;
+          active &= ~(1ull << b);
+          Req* r = sl.r;
+          sl.r = nullptr;
+          finish(r, st, e);
+          continue;
+        }
+        sl.start = pass;
+        seeds.slot[seeds.n] = b;
+        seeds.src[seeds.n] = src;
+        seeds.n++;
+        if (dirty >> b & 1ull) clear |= 1ull << b;
+      }
+      dirty &= ~clear;
+      if (!active) continue;
+      // the active slots' epochs, ascending, with their cumulative masks
+      dg::XbEpochs ep{};
+      dg::XbOuts outs{};
+      {
+        std::vector<std::pair<uint32_t, uint32_t>> es;
+        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+          if (active >> b & 1ull) {
+            es.push_back({slot[b].epoch, b});
+            outs.out[b] = slot[b].out.as<int32_t>();
+            outs.start[b] = slot[b].start;
+          }
+        std::sort(es.begin(), es.end());
+        unsigned long long cum = 0;
+        for (size_t i = 0; i < es.size(); i++) {
+          if (i == 0 || es[i].first != es[i - 1].first) {
+            ep.cm[ep.ne] = cum;
+            ep.ue[ep.ne++] = es[i].first;
+          }
+          cum |= 1ull << es[i].second;
+        }
+        ep.cm[ep.ne] = cum;
+        for (uint32_t i = ep.ne; i < dg::XB_SLOTS; i++) {
+          ep.ue[i] = 0xFFFFFFFFu;
+          ep.cm[i + 1] = cum;
+        }
+      }
+      dg::Store st;
+      {
+        std::unique_lock<std::mutex> lk(g->mu);
+        dg::pool_read_begin(g, lk);
+        st = g->st;
+      }
+      dg::XbResult res{};
+      hipError_t he = dg::xb_pass(x, g, st, sb, share, pass, ep, outs, seeds, clear, &res);
+      dg::pool_read_end(g);
+      pass++;
+      if (he != hipSuccess || res.overflow) {
+        // the search state is lost: fail its queries and start afresh
+        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+          if (active >> b & 1ull) {
+            if (slot[b].pinned) dg_snapshot_release(g, slot[b].epoch);
+            slot[b].pinned = false;
+            Req* r = slot[b].r;
+            slot[b].r = nullptr;
+            finish(r, he != hipSuccess ? DG_E_HIP : DG_E_OUT_OF_MEMORY, slot[b].epoch);
+          }
+        active = 0;
+        dirty = 0;
+        (void)hipStreamSynchronize(sb);
+        dg::xb_destroy(x);
+        x = dg::xb_create();
+        continue;
+      }
+      {
+        std::lock_guard<std::mutex> lk(m);
+        arcs += res.arcs;
+      }
+      const unsigned long long done = active & ~res.progress;
+      if (done) {
+        std::lock_guard<std::mutex> lk(m);
+        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+          if (done >> b & 1ull) {
+            if (slot[b].pinned) dg_snapshot_release(g, slot[b].epoch);
+            slot[b].pinned = false;
+            copies.push_back(Done{slot[b].r, b, slot[b].out.p, slot[b].epoch});
+            slot[b].r = nullptr;
+          }
+        active &= ~done;
+        dirty |= done;
+        xb_draining |= done;
+        cv_copy.notify_all();
+      }
+    }
+    if (held) hold(false);
+    for (auto& sl : slot) dg::release(sl.out);
+    dg::xb_destroy(x);
+  }
+
+  // Copies finished executor outputs to the host, then frees their slots.
+  // Each output goes by DMA into pinned staging, then into the request.
+  void copy_loop() {
+    const uint64_t bytes = g->cfg.v_capacity * 4;
+    void* stage = nullptr;
+    if (hipHostMalloc(&stage, bytes, hipHostMallocDefault) != hipSuccess) stage = nullptr;
+    for (;;) {
+      Done d;
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv_copy.wait(lk, [&] { return copy_stop || !copies.empty(); });
+        if (copies.empty()) {
+          if (stage) hipHostFree(stage);
+          return;
+        }
+        d = copies.front();
+        copies.pop_front();
+      }
+      dg_status st = DG_OK;
+      d.r->out.resize(bytes);
+      void* dst = stage ? stage : (void*)d.r->out.data();
+      if (hipMemcpyAsync(dst, d.dev, bytes, hipMemcpyDeviceToHost, sc) != hipSuccess ||
+          hipStreamSynchronize(sc) != hipSuccess)
+        st = DG_E_HIP;
+      else if (stage)
+        std::memcpy(d.r->out.data(), stage, bytes);
+      finish(d.r, st, d.epoch);
+      {
+        std::lock_guard<std::mutex> lk(m);
+        xb_draining &= ~(1ull << d.slot);
+      }
+      cv.notify_all();
+    }
+  }
 };
 
 extern "C" {
@@ -259,7 +504,9 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
     g->err = "query_lanes must be at most 4";
     return DG_E_INVALID_ARG;
   }
-  bool ok = hipStreamCreateWithFlags(&s->su, hipStreamNonBlocking) == hipSuccess;
+  bool ok = hipStreamCreateWithFlags(&s->su, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&s->sb, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&s->sc, hipStreamNonBlocking) == hipSuccess;
   for (uint32_t i = 0; ok && i < s->cfg.query_lanes; i++) {
     hipStream_t x = nullptr;
     ok = hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
@@ -267,6 +514,8 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   }
   if (!ok) {
     if (s->su) hipStreamDestroy(s->su);
+    if (s->sb) hipStreamDestroy(s->sb);
+    if (s->sc) hipStreamDestroy(s->sc);
     for (hipStream_t x : s->sq) hipStreamDestroy(x);
     delete s;
     g->err = "server stream creation";
@@ -281,6 +530,10 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   s->t0 = clk::now();
   s->tu = std::thread([s] { s->update_loop(); });
   for (uint32_t i = 0; i < s->cfg.query_lanes; i++) s->tq.emplace_back([s, i] { s->query_loop(i); });
+  if (!s->cfg.bfs_rounds) {
+    s->tb = std::thread([s] { s->bfs_loop(); });
+    s->tc = std::thread([s] { s->copy_loop(); });
+  }
   *out = s;
   return DG_OK;
 }
@@ -294,6 +547,17 @@ dg_status dg_server_stop(dg_server* s) {
   s->cv.notify_all();
   s->tu.join();
   for (auto& t : s->tq) t.join();
+  if (s->tb.joinable()) s->tb.join();
+  {
+    std::lock_guard<std::mutex> lk(s->m);
+    s->copy_stop = true;
+  }
+  s->cv_copy.notify_all();
+  if (s->tc.joinable()) s->tc.join();
+  for (hipStream_t x : {s->sb, s->sc}) {
+    hipStreamSynchronize(x);
+    hipStreamDestroy(x);
+  }
   hipStreamSynchronize(s->su);
   hipStreamDestroy(s->su);
   for (hipStream_t x : s->sq) {
@@ -317,7 +581,9 @@ static dg_status submit(dg_server* s, std::unique_ptr<Req> r, uint64_t* ticket) 
   if (s->t_first < 0) s->t_first = r->t_arrive;
   Req* raw = r.get();
   s->reqs[raw->ticket] = std::move(r);
-  (raw->kind < 0 ? s->uq : s->qq).push_back(raw);
+  if (raw->kind < 0) s->uq.push_back(raw);
+  else if (raw->kind == DG_Q_BFS && !s->cfg.bfs_rounds) s->bq.push_back(raw);
+  else s->qq.push_back(raw);
   if (ticket) *ticket = raw->ticket;
   s->cv.notify_all();
   return DG_OK;
@@ -397,7 +663,7 @@ dg_status dg_server_log(dg_server* s, dg_log_record* recs, uint64_t rec_cap, uin
 dg_status dg_server_drain(dg_server* s) {
   if (!s) return DG_E_INVALID_ARG;
   std::unique_lock<std::mutex> lk(s->m);
-  s->cv_done.wait(lk, [&] { return s->uq.empty() && s->qq.empty() && s->busy == 0; });
+  s->cv_done.wait(lk, [&] { return s->uq.empty() && s->qq.empty() && s->bq.empty() && s->busy == 0; });
   return DG_OK;
 }
 
@@ -416,6 +682,7 @@ dg_status dg_server_get_stats(dg_server* s, dg_server_stats* st) {
   st->p99_update_ms = pct(s->lat_u, 99);
   st->wall_s = s->t_first < 0 ? 0.0 : s->t_last - s->t_first;
   st->edges_traversed = s->arcs;
+  st->joined_running = s->joined_running;
   return DG_OK;
 }
 

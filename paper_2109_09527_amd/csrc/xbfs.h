@@ -1,0 +1,65 @@
+// Continuous multi-source BFS: the serving loop's resident BFS executor.
+//
+// Up to XB_SLOTS BFS queries share one level-synchronous multi-source
+// search, each bound to its own snapshot epoch.  A query is admitted at any
+// pass boundary into a free slot: its source joins the next frontier, and
+// its levels count from the pass it joined, so its hop distances are those
+// of a search of its own.  An arc is followed for the slots whose epoch
+// lies in the arc's lifetime [birth, death), so each query sees exactly its
+// snapshot.  A slot whose search added no vertex in a pass is complete and
+// its output is final.
+#pragma once
+
+#include <string>
+
+#include "dg_host.h"
+
+namespace dg {
+
+constexpr uint32_t XB_SLOTS = 64;
+
+// The active slots' epochs: distinct values ascending (padded with
+// 0xFFFFFFFF) and cm[i] = the slots bound to one of the i smallest, so the
+// slots with epoch below x are cm[#{ue < x}].
+struct XbEpochs {
+  uint32_t ne;
+  uint32_t ue[XB_SLOTS];
+  unsigned long long cm[XB_SLOTS + 1];
+};
+
+// Per slot: its output (distance array) and the pass its source joined.
+struct XbOuts {
+  int32_t* out[XB_SLOTS];
+  int32_t start[XB_SLOTS];
+};
+
+struct XbSeeds {
+  uint32_t n;
+  uint32_t slot[XB_SLOTS];
+  uint32_t src[XB_SLOTS];
+};
+
+struct XbResult {
+  unsigned long long progress;   // slots that reached a new vertex in the pass
+  unsigned long long arcs;       // arcs followed for at least one slot
+  uint32_t n_touched;
+  uint32_t overflow;
+  unsigned long long fq;         // the next frontier (items | buckets)
+};
+
+// p[0 .. n) = v on stream s.
+hipError_t fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t s);
+
+struct XbState;
+XbState* xb_create();
+void xb_destroy(XbState* x);
+// One pass on stream s: clears the visited bits of the slots in
+// clear_mask, expands the frontier for the slots in `ep`, joins the seeds,
+// finalises the pass's new vertices (level = pass - start of their slot)
+// and waits for its counters.  grid_pct bounds the expansion's workgroups
+// as a share of those resident.
+hipError_t xb_pass(XbState* x, dg_graph* g, const Store& st, hipStream_t s, uint32_t grid_pct, int32_t pass,
+                   const XbEpochs& ep, const XbOuts& outs, const XbSeeds& seeds, unsigned long long clear_mask,
+                   XbResult* r);
+
+}  // namespace dg

@@ -45,7 +45,7 @@ class Query(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32), ("query_lanes", _u32),
-                ("log_ops", _u32)]
+                ("log_ops", _u32), ("bfs_rounds", _u32)]
 
 
 class LogRecord(ctypes.Structure):
@@ -58,7 +58,7 @@ class ServerStats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("p50_query_ms", ctypes.c_double), ("p99_query_ms", ctypes.c_double),
                 ("p50_update_ms", ctypes.c_double), ("p99_update_ms", ctypes.c_double),
-                ("wall_s", ctypes.c_double), ("edges_traversed", _u64)]
+                ("wall_s", ctypes.c_double), ("edges_traversed", _u64), ("joined_running", _u64)]
 
 
 def _sig(name, res, *args):
@@ -413,8 +413,9 @@ class Server:
     """Serving loop over a Graph (dg_server_*)."""
 
     def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32, query_lanes=1,
-                 log_ops=False):
-        cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes, 1 if log_ops else 0)
+                 log_ops=False, bfs_rounds=False):
+        cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes, 1 if log_ops else 0,
+                           1 if bfs_rounds else 0)
         h = _P()
         rc = lib.dg_server_start(graph.h, ctypes.byref(cfg), ctypes.byref(h))
         if rc != OK:
