@@ -309,12 +309,13 @@ dg_status dg_out_degrees(dg_graph* g, dg_epoch e, uint32_t* deg, void* stream);
 
 /*
  * Serving loop: requests are admitted in arrival order.  Update batches run
- * on an update stream (each publishes the next epoch).  BFS queries join a
- * running multi-source search of 64 slots (the BFS executor): before each
- * of its passes, waiting BFS queries take the free slots, each bound to the
- * latest epoch published at that moment (its linearization point), and a
- * slot frees up as soon as its query's search is complete.  SSSP and BC
- * queries run on query_lanes lanes, each a host thread with a stream and an
+ * on an update stream (each publishes the next epoch).  BFS and SSSP queries
+ * join a running multi-source search of their kind (an executor: 64 slots
+ * for BFS, 32 for SSSP): before each of its passes, waiting queries take the
+ * free slots, each bound to the latest epoch published at that moment (its
+ * linearization point), and a slot frees up as soon as its query's search
+ * is complete.  BC queries (and, with bfs_rounds or sssp_rounds, those
+ * kinds too) run on query_lanes lanes, each a host thread with a stream and an
  * engine instance of its own: a free lane takes the queries at the head of
  * its queue (up to max_batch, within max_inflight queries admitted in all)
  * and runs them in one engine call, binding each to the latest epoch
@@ -336,6 +337,7 @@ typedef struct {
   uint32_t query_lanes;    /* engine launches in flight at once, 1..4; 0 = 1 */
   uint32_t log_ops;        /* 1 = keep every update's ops for dg_server_log (16 B per op until stop) */
   uint32_t bfs_rounds;     /* 1 = BFS queries run in the lanes' rounds; 0 = in the continuous BFS executor */
+  uint32_t sssp_rounds;    /* 1 = SSSP queries run in the lanes' rounds; 0 = in the continuous SSSP executor */
 } dg_server_config;
 typedef struct {
   uint64_t completed, updates, queries, ops_applied;
@@ -343,7 +345,7 @@ typedef struct {
   double p50_query_ms, p99_query_ms, p50_update_ms, p99_update_ms;
   double wall_s;                     /* first arrival -> last completion */
   uint64_t edges_traversed;          /* sum of TEPS numerators of finished queries */
-  uint64_t joined_running;           /* BFS queries admitted into a search other queries were running in */
+  uint64_t joined_running;           /* queries admitted into an executor's search while others ran in it */
 } dg_server_stats;
 dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** out);
 dg_status dg_server_stop(dg_server* s);

@@ -780,7 +780,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
                                          "sssp_split",   "bc_forward",   "bc_backward",   "batch_bfs",
                                          "batch_sssp",   "batch_bc",     "pagerank",     "pagerank_nosync", "scc",
                                          "diameter",     "maxflow",      "dfs",          "pool_growth",  "batch_sssp_scan",
-                                         "serve_bfs"};
+                                         "serve_bfs",    "serve_sssp"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
   prof_collect(g->prof);

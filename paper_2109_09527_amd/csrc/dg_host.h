@@ -175,6 +175,7 @@ enum KernelId {
   KID_POOL_GROW,    // one reallocation of the bucket pools (host clock, waits included)
   KID_BATCH_SSSP_SCAN,  // multi-source SSSP searches: arcs scanned once for a whole group
   KID_SERVE_BFS,    // one expansion pass of the serving loop's BFS executor
+  KID_SERVE_SSSP,   // one relaxation pass of the serving loop's SSSP executor
   KID_COUNT
 };
 struct Prof {

@@ -3,30 +3,32 @@
 //
 //   update thread  applies update requests in arrival order on its own
 //                  stream; each publishes the next epoch.
-//   BFS executor   one multi-source BFS search of 64 slots that runs pass
-//                  after pass on its own stream while any slot is active;
-//                  before every pass, waiting BFS queries take the free
-//                  slots, each bound to the latest published epoch at that
-//                  moment (its linearization point), and join the running
-//                  search.  A finished slot's output is copied to the host
-//                  by a copy thread, after which the slot is reused.
+//   executors      one for BFS (64 slots) and one for SSSP (32 slots), each
+//                  a multi-source search that runs pass after pass on its
+//                  own stream while any slot is active; before every pass,
+//                  waiting queries of its kind take the free slots, each
+//                  bound to the latest published epoch at that moment (its
+//                  linearization point), and join the running search.  A
+//                  finished slot's output is copied to the host by a copy
+//                  thread, after which the slot is reused.
 //   query lanes    (query_lanes threads, each with a stream and an engine
 //                  instance of its own) each take, whenever it is free, the
-//                  waiting SSSP and BC queries at the head of the queue in
-//                  arrival order while their output memory fits the budget
-//                  and the in-flight cap allows (up to max_batch at once),
-//                  bind them to the latest published epoch and run them in
-//                  one engine call.  A query arriving while a lane is busy
-//                  is taken by the next lane to come free, so the launches
-//                  of the lanes, the executor and the update stream overlap
-//                  on the device.  (With bfs_rounds set, BFS queries also go
-//                  to the lanes.)
+//                  waiting BC queries at the head of the queue in arrival
+//                  order while their output memory fits the budget and the
+//                  in-flight cap allows (up to max_batch at once), bind them
+//                  to the latest published epoch and run them in one engine
+//                  call.  A query arriving while a lane is busy is taken by
+//                  the next lane to come free, so the launches of the lanes,
+//                  the executors and the update stream overlap on the
+//                  device.  (With bfs_rounds or sssp_rounds set, queries of
+//                  that kind go to the lanes too.)
 // While a server runs, scans read per-slot stamps (no summary fast path),
 // since update kernels may write slabs under running queries, and the
 // engine launches share part of the device's resident-workgroup capacity
 // (the rest stays free for the update kernels).  Latency = completion -
 // submission, host clock.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -36,7 +38,7 @@
 #include <vector>
 
 #include "dg_host.h"
-#include "xbfs.h"
+#include "xexec.h"
 
 namespace {
 
@@ -71,7 +73,19 @@ struct dg_server {
   std::mutex m;
   std::condition_variable cv, cv_done;
   std::deque<Req*> uq, qq;
-  std::deque<Req*> bq;           // BFS queries waiting for a slot of the BFS executor
+  // the continuous executors (BFS and SSSP): waiting queries, slots whose
+  // output is being copied, and each one's thread, stream and event
+  struct ExecQ {
+    int kind;
+    uint32_t nslots;
+    std::deque<Req*> q;
+    unsigned long long draining = 0;
+    hipStream_t s = nullptr;
+    hipEvent_t out_ready = nullptr;   // SSSP: outputs extracted up to here
+    std::thread t;
+    uint64_t joined_running = 0;      // admitted while others of the search were running
+  };
+  ExecQ xb{DG_Q_BFS, dg::XB_SLOTS}, xs{DG_Q_SSSP, dg::XS_SLOTS};
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next = 1;
   bool stop = false;
@@ -82,21 +96,24 @@ struct dg_server {
   std::vector<std::thread> tq;   // one per query lane
   hipStream_t su = nullptr;
   std::vector<hipStream_t> sq;   // one per query lane
-  // the continuous BFS executor: its thread and stream, and a thread that
-  // copies finished outputs to the host so that passes keep running
-  std::thread tb, tc;
-  hipStream_t sb = nullptr, sc = nullptr;
+  // a thread that copies finished executor outputs to the host, so that
+  // the executors' passes keep running
+  std::thread tc;
+  hipStream_t sc = nullptr;
   struct Done {
     Req* r;
+    ExecQ* x;
     uint32_t slot;
     const void* dev;
     uint32_t epoch;
+    hipEvent_t ready;   // the output is final once this event completes (null: already)
   };
   std::deque<Done> copies;
   std::condition_variable cv_copy;
   bool copy_stop = false;
-  unsigned long long xb_draining = 0;   // slots whose output is being copied
-  uint64_t joined_running = 0;          // BFS queries admitted while others of the search were running
+  // an update batch is being applied: the executors hold their next pass
+  // back for a while, so the batch's short kernels find free compute units
+  std::atomic<int> updating{0};
   clk::time_point t0;
   std::vector<double> lat_all, lat_q, lat_u;
   uint64_t ops_applied = 0, arcs = 0, n_upd = 0, n_qry = 0;
@@ -176,7 +193,9 @@ struct dg_server {
       }
       r->results.assign(r->ops.size(), 0);
       dg_epoch ep = 0;
+      updating.store(1);
       dg_status st = dg_apply_batch(g, r->ops.data(), r->ops.size(), r->results.data(), &ep, su);
+      updating.store(0);
       // a rejected batch publishes nothing: it stands at the epoch that is
       // latest (only this thread publishes, so that is still the one it saw)
       if (st != DG_OK) ep = dg_latest_epoch(g);
@@ -265,15 +284,16 @@ struct dg_server {
     }
   }
 
-  // ---- continuous BFS executor
+  // ---- continuous executors (BFS, SSSP)
   //
-  // One multi-source search of up to 64 slots runs pass after pass while
-  // any slot is active.  Before each pass, waiting BFS queries take free
-  // slots (arrival order, within the memory budget and the in-flight cap),
-  // each bound to the latest published epoch at that moment; their sources
-  // join the pass.  A slot that reached no new vertex in a pass is finished:
-  // its output goes to the copy thread, and its slot is reused once the copy
-  // is done (its visited bits are cleared when the next query takes it).
+  // One multi-source search of up to 64 (BFS) or 32 (SSSP) slots runs pass
+  // after pass while any slot is active.  Before each pass, waiting queries
+  // of the executor's kind take free slots (arrival order, within the memory
+  // budget and the in-flight cap), each bound to the latest published epoch
+  // at that moment; their sources join the pass.  A slot that made no
+  // progress in a pass is finished: its output goes to the copy thread, and
+  // its slot is reused once the copy is done (its state is reset when the
+  // next query takes it).
   struct XSlot {
     Req* r = nullptr;
     uint32_t epoch = 0;
@@ -282,14 +302,17 @@ struct dg_server {
     int32_t start = 0;
   };
 
-  void bfs_loop() {
-    dg::XbState* x = dg::xb_create();
-    std::vector<XSlot> slot(dg::XB_SLOTS);
+  void exec_loop(ExecQ& X) {
+    const bool bfs = X.kind == DG_Q_BFS;
+    dg::XbState* xbs = bfs ? dg::xb_create() : nullptr;
+    dg::XsState* xss = bfs ? nullptr : dg::xs_create();
+    const unsigned long long all_slots = X.nslots >= 64 ? ~0ull : ((1ull << X.nslots) - 1);
+    std::vector<XSlot> slot(X.nslots);
     unsigned long long active = 0, dirty = 0;
     int32_t pass = 0;
     const uint64_t V = g->cfg.v_capacity;
     const uint32_t share = std::max<uint32_t>(1, g->engine_share_pct);
-    bool held = false;   // this executor's search hold (compaction waits while it is held)
+    bool held = false;   // this search's hold (compaction waits while it is held)
     auto hold = [&](bool on) {
       std::unique_lock<std::mutex> lk(g->mu);
       if (on) {
@@ -301,41 +324,42 @@ struct dg_server {
       }
       held = on;
     };
+    auto free_slots = [&] { return all_slots & ~(active | X.draining); };
     for (;;) {
       std::vector<uint32_t> joined;
       if (!active) {
         if (held) hold(false);
-        pass = 0;   // levels count from each slot's start, so the pass number may restart
+        pass = 0;   // BFS levels count from each slot's start, so the pass number may restart
         std::unique_lock<std::mutex> lk(m);
         cv.wait(lk, [&] {
-          return (stop && bq.empty() && !xb_draining) ||
-                 (!bq.empty() && (~xb_draining) != 0 && q_running < cfg.max_inflight &&
-                  mem_used + out_bytes(bq.front()) <= cfg.mem_budget);
+          return (stop && X.q.empty() && !X.draining) ||
+                 (!X.q.empty() && free_slots() != 0 && q_running < cfg.max_inflight &&
+                  mem_used + out_bytes(X.q.front()) <= cfg.mem_budget);
         });
-        if (bq.empty() && stop && !xb_draining) break;
+        if (X.q.empty() && stop && !X.draining) break;
       }
       if (!held) hold(true);
       {
         std::unique_lock<std::mutex> lk(m);
         // no admission while a compaction waits: the search drains first
         auto admissible = [&] {
-          return !bq.empty() && (~(active | xb_draining)) != 0 && q_running < cfg.max_inflight &&
-                 mem_used + out_bytes(bq.front()) <= cfg.mem_budget && g->compact_waiting.load() == 0;
+          return !X.q.empty() && free_slots() != 0 && q_running < cfg.max_inflight &&
+                 mem_used + out_bytes(X.q.front()) <= cfg.mem_budget && g->compact_waiting.load() == 0;
         };
         const bool others = active != 0;
         while (admissible()) {
-          Req* r = bq.front();
+          Req* r = X.q.front();
           const uint64_t need = out_bytes(r);
-          bq.pop_front();
+          X.q.pop_front();
           mem_used += need;
           r->reserve = need;
           busy++;
           q_running++;
-          const uint32_t b = (uint32_t)__builtin_ctzll(~(active | xb_draining));
+          const uint32_t b = (uint32_t)__builtin_ctzll(free_slots());
           slot[b].r = r;
           active |= 1ull << b;
           joined.push_back(b);
-          if (others) joined_running++;
+          if (others) X.joined_running++;
         }
       }
       dg::XbSeeds seeds{};
@@ -354,7 +378,8 @@ struct dg_server {
           if (!dg::alive_at(g, src, e)) st = DG_E_SOURCE_ABSENT;
         }
         if (st == DG_OK && dg::ensure(sl.out, V * 4) != hipSuccess) st = DG_E_OUT_OF_MEMORY;
-        if (st == DG_OK && dg::fill_i32(sl.out.as<int32_t>(), V, -1, sb) != hipSuccess) st = DG_E_HIP;
+        // a BFS writes levels as it goes; an SSSP output is written whole at the end
+        if (st == DG_OK && bfs && dg::fill_i32(sl.out.as<int32_t>(), V, -1, X.s) != hipSuccess) st = DG_E_HIP;
         if (st != DG_OK) {
           if (sl.pinned) dg_snapshot_release(g, e);
           sl.pinned = false;
@@ -377,7 +402,7 @@ struct dg_server {
       dg::XbOuts outs{};
       {
         std::vector<std::pair<uint32_t, uint32_t>> es;
-        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+        for (uint32_t b = 0; b < X.nslots; b++)
           if (active >> b & 1ull) {
             es.push_back({slot[b].epoch, b});
             outs.out[b] = slot[b].out.as<int32_t>();
@@ -398,6 +423,9 @@ struct dg_server {
           ep.cm[i + 1] = cum;
         }
       }
+      // updates go first: wait (up to a few ms) for a running batch
+      for (auto t0 = clk::now(); updating.load() && clk::now() - t0 < std::chrono::milliseconds(4);)
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
       dg::Store st;
       {
         std::unique_lock<std::mutex> lk(g->mu);
@@ -405,12 +433,19 @@ struct dg_server {
         st = g->st;
       }
       dg::XbResult res{};
-      hipError_t he = dg::xb_pass(x, g, st, sb, share, pass, ep, outs, seeds, clear, &res);
+      hipError_t he = bfs ? dg::xb_pass(xbs, g, st, X.s, share, pass, ep, outs, seeds, clear, &res)
+                          : dg::xs_pass(xss, g, st, X.s, share, ep, seeds, clear, &res);
       dg::pool_read_end(g);
       pass++;
+      const unsigned long long done = he == hipSuccess && !res.overflow ? active & ~res.progress : 0ull;
+      hipEvent_t ready = nullptr;
+      if (done && !bfs) {
+        he = dg::xs_extract(xss, outs, done, X.s, X.out_ready);
+        ready = X.out_ready;
+      }
       if (he != hipSuccess || res.overflow) {
         // the search state is lost: fail its queries and start afresh
-        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+        for (uint32_t b = 0; b < X.nslots; b++)
           if (active >> b & 1ull) {
             if (slot[b].pinned) dg_snapshot_release(g, slot[b].epoch);
             slot[b].pinned = false;
@@ -420,34 +455,39 @@ struct dg_server {
           }
         active = 0;
         dirty = 0;
-        (void)hipStreamSynchronize(sb);
-        dg::xb_destroy(x);
-        x = dg::xb_create();
+        (void)hipStreamSynchronize(X.s);
+        if (bfs) {
+          dg::xb_destroy(xbs);
+          xbs = dg::xb_create();
+        } else {
+          dg::xs_destroy(xss);
+          xss = dg::xs_create();
+        }
         continue;
       }
       {
         std::lock_guard<std::mutex> lk(m);
         arcs += res.arcs;
       }
-      const unsigned long long done = active & ~res.progress;
       if (done) {
         std::lock_guard<std::mutex> lk(m);
-        for (uint32_t b = 0; b < dg::XB_SLOTS; b++)
+        for (uint32_t b = 0; b < X.nslots; b++)
           if (done >> b & 1ull) {
             if (slot[b].pinned) dg_snapshot_release(g, slot[b].epoch);
             slot[b].pinned = false;
-            copies.push_back(Done{slot[b].r, b, slot[b].out.p, slot[b].epoch});
+            copies.push_back(Done{slot[b].r, &X, b, slot[b].out.p, slot[b].epoch, ready});
             slot[b].r = nullptr;
           }
         active &= ~done;
         dirty |= done;
-        xb_draining |= done;
+        X.draining |= done;
         cv_copy.notify_all();
       }
     }
     if (held) hold(false);
     for (auto& sl : slot) dg::release(sl.out);
-    dg::xb_destroy(x);
+    if (xbs) dg::xb_destroy(xbs);
+    if (xss) dg::xs_destroy(xss);
   }
 
   // Copies finished executor outputs to the host, then frees their slots.
@@ -471,7 +511,8 @@ struct dg_server {
       dg_status st = DG_OK;
       d.r->out.resize(bytes);
       void* dst = stage ? stage : (void*)d.r->out.data();
-      if (hipMemcpyAsync(dst, d.dev, bytes, hipMemcpyDeviceToHost, sc) != hipSuccess ||
+      if ((d.ready && hipStreamWaitEvent(sc, d.ready, 0) != hipSuccess) ||
+          hipMemcpyAsync(dst, d.dev, bytes, hipMemcpyDeviceToHost, sc) != hipSuccess ||
           hipStreamSynchronize(sc) != hipSuccess)
         st = DG_E_HIP;
       else if (stage)
@@ -479,7 +520,7 @@ struct dg_server {
       finish(d.r, st, d.epoch);
       {
         std::lock_guard<std::mutex> lk(m);
-        xb_draining &= ~(1ull << d.slot);
+        d.x->draining &= ~(1ull << d.slot);
       }
       cv.notify_all();
     }
@@ -505,8 +546,13 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
     return DG_E_INVALID_ARG;
   }
   bool ok = hipStreamCreateWithFlags(&s->su, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&s->sb, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->sc, hipStreamNonBlocking) == hipSuccess;
+  for (dg_server::ExecQ* x : {&s->xb, &s->xs}) {
+    const bool on = x->kind == DG_Q_BFS ? !s->cfg.bfs_rounds : !s->cfg.sssp_rounds;
+    if (ok && on)
+      ok = hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&x->out_ready, hipEventDisableTiming) == hipSuccess;
+  }
   for (uint32_t i = 0; ok && i < s->cfg.query_lanes; i++) {
     hipStream_t x = nullptr;
     ok = hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
@@ -514,8 +560,11 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   }
   if (!ok) {
     if (s->su) hipStreamDestroy(s->su);
-    if (s->sb) hipStreamDestroy(s->sb);
     if (s->sc) hipStreamDestroy(s->sc);
+    for (dg_server::ExecQ* x : {&s->xb, &s->xs}) {
+      if (x->s) hipStreamDestroy(x->s);
+      if (x->out_ready) hipEventDestroy(x->out_ready);
+    }
     for (hipStream_t x : s->sq) hipStreamDestroy(x);
     delete s;
     g->err = "server stream creation";
@@ -530,10 +579,9 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
   s->t0 = clk::now();
   s->tu = std::thread([s] { s->update_loop(); });
   for (uint32_t i = 0; i < s->cfg.query_lanes; i++) s->tq.emplace_back([s, i] { s->query_loop(i); });
-  if (!s->cfg.bfs_rounds) {
-    s->tb = std::thread([s] { s->bfs_loop(); });
-    s->tc = std::thread([s] { s->copy_loop(); });
-  }
+  for (dg_server::ExecQ* x : {&s->xb, &s->xs})
+    if (x->s) x->t = std::thread([s, x] { s->exec_loop(*x); });
+  if (s->xb.s || s->xs.s) s->tc = std::thread([s] { s->copy_loop(); });
   *out = s;
   return DG_OK;
 }
@@ -547,16 +595,22 @@ dg_status dg_server_stop(dg_server* s) {
   s->cv.notify_all();
   s->tu.join();
   for (auto& t : s->tq) t.join();
-  if (s->tb.joinable()) s->tb.join();
+  for (dg_server::ExecQ* x : {&s->xb, &s->xs})
+    if (x->t.joinable()) x->t.join();
   {
     std::lock_guard<std::mutex> lk(s->m);
     s->copy_stop = true;
   }
   s->cv_copy.notify_all();
   if (s->tc.joinable()) s->tc.join();
-  for (hipStream_t x : {s->sb, s->sc}) {
-    hipStreamSynchronize(x);
-    hipStreamDestroy(x);
+  hipStreamSynchronize(s->sc);
+  hipStreamDestroy(s->sc);
+  for (dg_server::ExecQ* x : {&s->xb, &s->xs}) {
+    if (x->s) {
+      hipStreamSynchronize(x->s);
+      hipStreamDestroy(x->s);
+    }
+    if (x->out_ready) hipEventDestroy(x->out_ready);
   }
   hipStreamSynchronize(s->su);
   hipStreamDestroy(s->su);
@@ -582,7 +636,8 @@ static dg_status submit(dg_server* s, std::unique_ptr<Req> r, uint64_t* ticket) 
   Req* raw = r.get();
   s->reqs[raw->ticket] = std::move(r);
   if (raw->kind < 0) s->uq.push_back(raw);
-  else if (raw->kind == DG_Q_BFS && !s->cfg.bfs_rounds) s->bq.push_back(raw);
+  else if (raw->kind == DG_Q_BFS && s->xb.s) s->xb.q.push_back(raw);
+  else if (raw->kind == DG_Q_SSSP && s->xs.s) s->xs.q.push_back(raw);
   else s->qq.push_back(raw);
   if (ticket) *ticket = raw->ticket;
   s->cv.notify_all();
@@ -663,7 +718,7 @@ dg_status dg_server_log(dg_server* s, dg_log_record* recs, uint64_t rec_cap, uin
 dg_status dg_server_drain(dg_server* s) {
   if (!s) return DG_E_INVALID_ARG;
   std::unique_lock<std::mutex> lk(s->m);
-  s->cv_done.wait(lk, [&] { return s->uq.empty() && s->qq.empty() && s->bq.empty() && s->busy == 0; });
+  s->cv_done.wait(lk, [&] { return s->uq.empty() && s->qq.empty() && s->xb.q.empty() && s->xs.q.empty() && s->busy == 0; });
   return DG_OK;
 }
 
@@ -682,7 +737,7 @@ dg_status dg_server_get_stats(dg_server* s, dg_server_stats* st) {
   st->p99_update_ms = pct(s->lat_u, 99);
   st->wall_s = s->t_first < 0 ? 0.0 : s->t_last - s->t_first;
   st->edges_traversed = s->arcs;
-  st->joined_running = s->joined_running;
+  st->joined_running = s->xb.joined_running + s->xs.joined_running;
   return DG_OK;
 }
 

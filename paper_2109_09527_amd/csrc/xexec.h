@@ -1,6 +1,6 @@
-// Continuous multi-source BFS: the serving loop's resident BFS executor.
+// The serving loop's executors: continuous multi-source BFS and SSSP.
 //
-// Up to XB_SLOTS BFS queries share one level-synchronous multi-source
+// BFS: up to XB_SLOTS BFS queries share one level-synchronous multi-source
 // search, each bound to its own snapshot epoch.  A query is admitted at any
 // pass boundary into a free slot: its source joins the next frontier, and
 // its levels count from the pass it joined, so its hop distances are those
@@ -8,6 +8,14 @@
 // lies in the arc's lifetime [birth, death), so each query sees exactly its
 // snapshot.  A slot whose search added no vertex in a pass is complete and
 // its output is final.
+//
+// SSSP: up to XS_SLOTS SSSP queries share one label-correcting search (a
+// frontier of vertices whose distance improved in the last pass, for a mask
+// of slots; Bellman-Ford order, one bucket of unbounded width).  A query
+// joins at any pass boundary with its source at distance 0; a slot whose
+// distances did not change in a pass has converged to the exact
+// shortest-path distances.  Relaxations are integer atomicMin, so the
+// result does not depend on the order of work or on the other slots.
 #pragma once
 
 #include <string>
@@ -17,6 +25,7 @@
 namespace dg {
 
 constexpr uint32_t XB_SLOTS = 64;
+constexpr uint32_t XS_SLOTS = 32;
 
 // The active slots' epochs: distinct values ascending (padded with
 // 0xFFFFFFFF) and cm[i] = the slots bound to one of the i smallest, so the
@@ -61,5 +70,18 @@ void xb_destroy(XbState* x);
 hipError_t xb_pass(XbState* x, dg_graph* g, const Store& st, hipStream_t s, uint32_t grid_pct, int32_t pass,
                    const XbEpochs& ep, const XbOuts& outs, const XbSeeds& seeds, unsigned long long clear_mask,
                    XbResult* r);
+
+struct XsState;
+XsState* xs_create();
+void xs_destroy(XsState* x);
+// One SSSP pass on stream s: resets the distances of the slots in
+// clear_mask, relaxes the frontier for the slots in `ep` (slots below
+// XS_SLOTS), joins the seeds and waits for its counters; r->progress holds
+// the slots whose distances changed.
+hipError_t xs_pass(XsState* x, dg_graph* g, const Store& st, hipStream_t s, uint32_t grid_pct, const XbEpochs& ep,
+                   const XbSeeds& seeds, unsigned long long clear_mask, XbResult* r);
+// Writes the distances of the slots in mask into outs.out[slot] (-1 where
+// unreached) on stream s, then records `done` on s.
+hipError_t xs_extract(XsState* x, const XbOuts& outs, unsigned long long mask, hipStream_t s, hipEvent_t done);
 
 }  // namespace dg

@@ -45,7 +45,7 @@ class Query(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_budget", _u64), ("max_inflight", _u32), ("max_batch", _u32), ("query_lanes", _u32),
-                ("log_ops", _u32), ("bfs_rounds", _u32)]
+                ("log_ops", _u32), ("bfs_rounds", _u32), ("sssp_rounds", _u32)]
 
 
 class LogRecord(ctypes.Structure):
@@ -413,9 +413,9 @@ class Server:
     """Serving loop over a Graph (dg_server_*)."""
 
     def __init__(self, graph: Graph, mem_budget=8 << 30, max_inflight=64, max_batch=32, query_lanes=1,
-                 log_ops=False, bfs_rounds=False):
+                 log_ops=False, bfs_rounds=False, sssp_rounds=False):
         cfg = ServerConfig(mem_budget, max_inflight, max_batch, query_lanes, 1 if log_ops else 0,
-                           1 if bfs_rounds else 0)
+                           1 if bfs_rounds else 0, 1 if sssp_rounds else 0)
         h = _P()
         rc = lib.dg_server_start(graph.h, ctypes.byref(cfg), ctypes.byref(h))
         if rc != OK:

@@ -35,8 +35,8 @@ def main():
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--lanes", default="1", help="query lanes (engine launches in flight); a comma-separated list runs each")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--bfs-rounds", action="store_true",
-                    help="BFS queries in the lanes' rounds instead of the continuous BFS executor")
+    ap.add_argument("--rounds", action="store_true",
+                    help="BFS and SSSP queries in the lanes' rounds instead of the continuous executors")
     args = ap.parse_args()
     # the drivers are short-lived and make few reference cycles: no collector
     # pause of this interpreter lands inside a timed region
@@ -65,7 +65,7 @@ def run_rate(args, g, gr, rate, seed, lanes):
     print(f"[serve] rate {rate:g}/s, {lanes} lanes: {len(reqs)} requests", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     srv = dg.Server(g, mem_budget=int(args.mem_gb * (1 << 30)), max_inflight=1024, max_batch=args.max_batch,
-                    query_lanes=lanes, bfs_rounds=args.bfs_rounds)
+                    query_lanes=lanes, bfs_rounds=args.rounds, sssp_rounds=args.rounds)
     tickets = []
     start = time.perf_counter()
     for r in reqs:
@@ -101,8 +101,8 @@ def run_rate(args, g, gr, rate, seed, lanes):
         "workload": f"R-MAT scale {args.scale} serving: Poisson {rate:g}/s for {args.duration:g}s, 30% updates "
                     "(log-uniform 1k-256k edge ops), 70% queries (BFS 40%, SSSP 40%, BC-16 20%)",
         "query_lanes": lanes, "max_batch": args.max_batch,
-        "bfs": "lanes' rounds" if args.bfs_rounds else "continuous executor",
-        "bfs_joined_running": st["joined_running"],
+        "bfs_sssp": "lanes' rounds" if args.rounds else "continuous executors",
+        "joined_running": st["joined_running"],
         "requests": len(tickets), "offered_rps": rate, "achieved_rps": round(achieved, 1) if achieved else None,
         "sustained": bool(achieved and achieved >= 0.95 * rate),
         "wall_s": round(st["wall_s"], 3), "drain_s": round(t_all - t_submit, 3),

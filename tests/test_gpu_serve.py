@@ -100,7 +100,7 @@ def replay_log(dg, g, o, e_start, log, submitted, taken):
     return n_checked
 
 
-def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2, bfs_rounds=False):
+def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2, rounds=False):
     gr = synth.rmat_graph(11, 8, 50, seed=seed)
     g = dg.Graph(gr.n, w_max=50, max_resident_epochs=128)
     load = synth.load_ops(gr)
@@ -109,7 +109,7 @@ def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2, bfs_roun
     srcs = synth.out_degree_sources(gr, 16, synth.rng_for(seed, 4))
     rng = np.random.default_rng(seed)
     srv = dg.Server(g, mem_budget=mem_budget, max_inflight=64, max_batch=max_batch, query_lanes=query_lanes,
-                    log_ops=True, bfs_rounds=bfs_rounds)
+                    log_ops=True, bfs_rounds=rounds, sssp_rounds=rounds)
     submitted = {}
     nu = 0
     for i in range(n_req):
@@ -133,13 +133,13 @@ def run_mix(dg, mem_budget, max_batch, n_req=60, seed=3, query_lanes=2, bfs_roun
     return g, o, log, submitted, taken, stats
 
 
-@pytest.mark.parametrize("lanes,bfs_rounds", [(1, False), (3, False), (1, True)])
-def test_serving_mix_matches_oracle_and_alone(dg, lanes, bfs_rounds):
-    """With one lane, and with three lanes whose launches overlap; BFS
-    queries in the continuous executor, or in the lanes' rounds."""
-    say("serving mix, lanes", lanes, "bfs in rounds", bfs_rounds)
+@pytest.mark.parametrize("lanes,rounds", [(1, False), (3, False), (1, True)])
+def test_serving_mix_matches_oracle_and_alone(dg, lanes, rounds):
+    """With one lane, and with three lanes whose launches overlap; BFS and
+    SSSP queries in the continuous executors, or in the lanes' rounds."""
+    say("serving mix, lanes", lanes, "bfs and sssp in rounds", rounds)
     g, o, log, submitted, taken, stats = run_mix(dg, mem_budget=1 << 30, max_batch=8, query_lanes=lanes,
-                                                 bfs_rounds=bfs_rounds)
+                                                 rounds=rounds)
     assert replay_log(dg, g, o, o.epoch, log, submitted, taken) > 0
     assert stats["completed"] == len(submitted)
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
@@ -241,13 +241,14 @@ def test_c5_mix_rmat16_matches_oracle_and_alone(dg, lanes):
     assert stats["completed"] == len(submitted)
 
 
-def test_bfs_executor_admits_into_running_searches(dg):
-    """BFS queries submitted back to back, with update batches between them,
+@pytest.mark.parametrize("kind", ["bfs", "sssp"])
+def test_executor_admits_into_running_searches(dg, kind):
+    """Queries submitted back to back, with update batches between them,
     join the executor's running search at pass boundaries, each bound to the
     epoch latest at its admission: some are admitted while others run, and
     queries bound to different epochs run at the same time.  Every result
     matches the oracle on its epoch and the same query run alone."""
-    say("BFS executor: admission into running searches")
+    say(kind, "executor: admission into running searches")
     seed = 21
     gr = synth.rmat_graph(14, 16, 50, seed=seed)
     g = dg.Graph(gr.n, w_max=50, max_resident_epochs=256)
@@ -263,7 +264,7 @@ def test_bfs_executor_admits_into_running_searches(dg):
             submitted[srv.submit_update(wl.batches[nu])] = ("update", wl.batches[nu])
             nu += 1
         s = int(srcs[i % len(srcs)])
-        submitted[srv.submit_query(dg.Q_BFS, [s])] = ("bfs", [s])
+        submitted[srv.submit_query(dg.Q_BFS if kind == "bfs" else dg.Q_SSSP, [s])] = (kind, [s])
     log, taken, stats = collect(srv, submitted, gr.n)
     o = Oracle(gr.n, w_max=50)
     o.apply(load)
@@ -271,9 +272,9 @@ def test_bfs_executor_admits_into_running_searches(dg):
     say("checked", n, "joined running searches", stats["joined_running"])
     assert n == 160
     assert stats["joined_running"] > 0
-    bfs = [r for r in log if r["kind"] == "bfs"]
+    qs = [r for r in log if r["kind"] == kind]
     overlap_mixed = sum(
-        1 for a in bfs for b in bfs
+        1 for a in qs for b in qs
         if a["epoch"] < b["epoch"] and a["t_arrive_ms"] < b["t_done_ms"] and b["t_arrive_ms"] < a["t_done_ms"])
     say("overlapping pairs on different epochs", overlap_mixed)
     assert overlap_mixed > 0
