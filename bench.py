@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--batch-scale", type=int, default=21, help="R-MAT scale of the batched comparison")
     ap.add_argument("--batch-tuning-file", default=None,
                     help="as --tuning-file, for the batched comparison's graph")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON tuning given inline (the autotuner is skipped), e.g. for a profiled run")
+    ap.add_argument("--batch-tuning", default=None, help="as --tuning, for the batched comparison's graph")
     ap.add_argument("--c3-oracle", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.c3_oracle:
@@ -172,13 +175,15 @@ def main():
         e3.record()
         return ep, (e0, e1, e2, e3)
 
-    if args.tuning_file and os.path.exists(args.tuning_file):
+    fixed_tuning = bool(args.tuning or (args.tuning_file and os.path.exists(args.tuning_file)))
+    if args.tuning:
+        g.set_tuning(**json.loads(args.tuning))
+    elif fixed_tuning:
         with open(args.tuning_file) as f:
             g.set_tuning(**json.load(f))
     for i in range(W):
         step(i)
     torch.cuda.synchronize()
-    fixed_tuning = bool(args.tuning_file and os.path.exists(args.tuning_file))
     if fixed_tuning:
         tuning = g.get_tuning()
     else:
@@ -327,7 +332,10 @@ def batched_vs_plain(args):
     print(f"[bench] batched configuration: R-MAT {args.batch_scale}, m={gr.m}, batches "
           f"{[len(b) for b in eq.batches]}, ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     tf = args.batch_tuning_file
-    if tf and os.path.exists(tf):
+    if args.batch_tuning:
+        g.set_tuning(**json.loads(args.batch_tuning))
+        tuning = g.get_tuning()
+    elif tf and os.path.exists(tf):
         with open(tf) as f:
             g.set_tuning(**json.load(f))
         tuning = g.get_tuning()

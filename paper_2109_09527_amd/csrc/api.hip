@@ -47,6 +47,7 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice;
 }
 
+// With p.mu held.
 static hipEvent_t prof_event(Prof& p) {
   if (!p.pool.empty()) {
     hipEvent_t e = p.pool.back();
@@ -59,29 +60,43 @@ static hipEvent_t prof_event(Prof& p) {
 }
 
 ProfScope::ProfScope(dg_graph* g_, int kid_, hipStream_t s_) : g(g_), kid(kid_), s(s_) {
-  if (!g->prof.on) return;
-  a = prof_event(g->prof);
+  {
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    if (!g->prof.on) return;
+    a = prof_event(g->prof);
+  }
   if (a) (void)hipEventRecord(a, s);
 }
 
 ProfScope::~ProfScope() {
   if (!a) return;
-  hipEvent_t b = prof_event(g->prof);
-  if (!b) return;
+  hipEvent_t b;
+  {
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    b = prof_event(g->prof);
+    if (!b) {
+      g->prof.pool.push_back(a);
+      return;
+    }
+  }
   (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g->prof.mu);
   g->prof.pending.push_back(Prof::Rec{kid, a, b});
 }
 
 void prof_arcs(dg_graph* g, int kid, uint64_t arcs) {
+  std::lock_guard<std::mutex> lk(g->prof.mu);
   if (g->prof.on) g->prof.arcs[kid] += arcs;
 }
 
 void prof_scans(dg_graph* g, int kid, uint64_t arcs) {
+  std::lock_guard<std::mutex> lk(g->prof.mu);
   if (!g->prof.on) return;
   g->prof.launches[kid]++;
   g->prof.arcs[kid] += arcs;
 }
 
+// With p.mu held.
 static void prof_collect(Prof& p) {
   for (auto& r : p.pending) {
     float ms = 0.f;
@@ -182,6 +197,7 @@ hipError_t grow_pools(dg_graph* g, uint64_t need_f, uint64_t need_r) {
     dg_graph* g;
     std::chrono::steady_clock::time_point t0;
     ~Clock() {
+      std::lock_guard<std::mutex> lk(g->prof.mu);
       if (!g->prof.on) return;
       g->prof.launches[KID_POOL_GROW]++;
       g->prof.ms[KID_POOL_GROW] +=
@@ -771,6 +787,7 @@ dg_status dg_out_degrees(dg_graph* g, dg_epoch want, uint32_t* deg, void* stream
 dg_status dg_profile_enable(dg_graph* g, int on) {
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
+  std::lock_guard<std::mutex> lp(g->prof.mu);
   g->prof.on = on != 0;
   return DG_OK;
 }
@@ -783,6 +800,7 @@ dg_status dg_profile_read(dg_graph* g, dg_kernel_stat* out, uint32_t cap, uint32
                                          "serve_bfs",    "serve_sssp"};
   if (!g) return DG_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g->mu);
+  std::lock_guard<std::mutex> lp(g->prof.mu);
   prof_collect(g->prof);
   uint32_t n = 0;
   for (int k = 0; k < KID_COUNT && n < cap; k++) {

@@ -178,7 +178,12 @@ enum KernelId {
   KID_SERVE_SSSP,   // one relaxation pass of the serving loop's SSSP executor
   KID_COUNT
 };
+// Kernel timing state.  Several host threads time kernels at once (the
+// serving loop's update thread, lanes and executors), so every access to the
+// event pool, the pending records and the totals holds mu (a leaf lock:
+// nothing else is taken while it is held).
 struct Prof {
+  std::mutex mu;
   bool on = false;
   struct Rec {
     int kid;

@@ -1185,8 +1185,12 @@ __device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint3
 // and multi-source searches all follow this order, so their dependencies
 // agree bit for bit.
 
+// Vertex v owns tiles [base, base + n) of the slab desc it was listed with
+// (tiles read that slab even if an update has since moved v's arcs to a
+// larger one: slabs are never reused while a search can hold them).
 struct BigVert {
-  uint32_t v, base, n, pad;   // vertex v owns tiles [base, base + n)
+  uint64_t desc;
+  uint32_t v, base, n, pad;
 };
 // Counts of the listed vertices and their tiles, by level parity (a level
 // fills one parity while its pass zeroes the other's), and an overflow flag.
@@ -1228,10 +1232,11 @@ __host__ __device__ inline BwdTiles bwd_tiles_at(char* p, uint64_t pool_buckets,
   return t;
 }
 
-// Wave-uniform: list vertex v (slab of nb > BWD_TILE buckets) for the tile
-// pass of its level (parity par); a full list raises the overflow flag.
-__device__ inline void bwd_list(const BwdTiles& t, uint32_t par, uint32_t v, uint32_t nb) {
-  const uint32_t n = nb >> BWD_TILE_LOG;
+// Wave-uniform: list vertex v (slab desc of more than BWD_TILE buckets) for
+// the tile pass of its level (parity par); a full list raises the overflow
+// flag.
+__device__ inline void bwd_list(const BwdTiles& t, uint32_t par, uint32_t v, uint64_t desc) {
+  const uint32_t n = (1u << (desc & 63)) >> BWD_TILE_LOG;
   uint32_t idx = 0, base = 0;
   if (lane_id() == 0) {
     idx = atomicAdd(&t.head->verts[par], 1u);
@@ -1243,7 +1248,7 @@ __device__ inline void bwd_list(const BwdTiles& t, uint32_t par, uint32_t v, uin
     if (lane_id() == 0) atomicOr(&t.head->ovf, 1u);
     return;
   }
-  if (lane_id() == 0) t.big[idx] = BigVert{v, base, n, 0};
+  if (lane_id() == 0) t.big[idx] = BigVert{desc, v, base, n, 0};
   for (uint32_t i = lane_id(); i < n; i += 64) t.tmap[base + i] = idx;
 }
 
@@ -1284,7 +1289,7 @@ __device__ __forceinline__ void bcbwd_step(const Store& st, uint32_t e, bool fas
     const uint64_t desc = st.fdesc[v];
     const Slab s = slab_of(st.fp, desc);
     if (bwd_is_big(desc)) {
-      bwd_list(bt, par, v, s.nb);
+      bwd_list(bt, par, v, desc);
       continue;
     }
     const double acc = bwd_tile_sum(s, 0, s.nb, e, fast, (double)sigma[v], level, L, sigma, delta);
@@ -1307,7 +1312,7 @@ __device__ __forceinline__ void bcbwd_tiles(const Store& st, uint32_t e, bool fa
     if (i >= bt.cap_verts) continue;
     const BigVert bv = bt.big[i];
     if (t < bv.base || t - bv.base >= bv.n) continue;
-    const Slab s = slab_of(st.fp, st.fdesc[bv.v]);
+    const Slab s = slab_of(st.fp, bv.desc);
     const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
     if (b0 >= s.nb) continue;
     const double acc =

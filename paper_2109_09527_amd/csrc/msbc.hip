@@ -216,7 +216,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int 
     const uint64_t desc = st.fdesc[v];
     const Slab sl = slab_of(st.fp, desc);
     if (bwd_is_big(desc)) {
-      bwd_list(bt, par, v, sl.nb);
+      bwd_list(bt, par, v, desc);
       continue;
     }
     double sv[MBQ], acc[MBQ];
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_tiles(Store st, uint32_t e, in
     if (i >= bt.cap_verts) continue;
     const BigVert bv = bt.big[i];
     if (t < bv.base || t - bv.base >= bv.n) continue;
-    const Slab sl = slab_of(st.fp, st.fdesc[bv.v]);
+    const Slab sl = slab_of(st.fp, bv.desc);
     const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
     if (b0 >= sl.nb) continue;
     double sv[MBQ], acc[MBQ];
@@ -512,9 +512,11 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
     const uint32_t grid =
         std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)((n + Q_WAVES - 1) / Q_WAVES), mb.bwd_grid));
     k_mb_bwd<<<grid, Q_THREADS, 0, s>>>(st, e, fast, P.order + o0, (uint32_t)n, lvl, k, P.L, P.SG, P.DL, P.bt);
-    if (nbig[lvl]) {
+    // the forward's count of long slabs is exact only while no update can
+    // move a slab in between
+    if (nbig[lvl] || !fast) {
       k_mb_tiles<<<mb.tiles_grid, Q_THREADS, 0, s>>>(st, e, fast, lvl, k, P.L, P.SG, P.DL, P.bt);
-      const uint64_t lanes = (uint64_t)nbig[lvl] * MBQ;
+      const uint64_t lanes = (uint64_t)std::max<uint32_t>(nbig[lvl], fast ? 0u : 4096u) * MBQ;
       k_mb_combine<<<(uint32_t)std::min<uint64_t>((lanes + Q_THREADS - 1) / Q_THREADS, 4096), Q_THREADS, 0, s>>>(
           lvl, k, P.L, P.DL, P.bt);
     }

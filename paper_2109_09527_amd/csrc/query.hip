@@ -666,10 +666,13 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
       ProfScope ps(g, KID_BC_BWD, s);
       k_bc_bwd<<<grid_for(nv, Q_WAVES), Q_THREADS, 0, s>>>(g->st, e, fast, order + off[L], nv, src, level, L,
                                                            sigma, delta, bc, bt);
-      if (nbig[L]) {
+      // the forward's count of long slabs is exact only while no update can
+      // move a slab in between
+      if (nbig[L] || !fast) {
         k_bc_tiles<<<resident((const void*)k_bc_tiles), Q_THREADS, 0, s>>>(g->st, e, fast, level, L, sigma, delta,
                                                                           bt);
-        k_bc_combine<<<grid_for(nbig[L], Q_THREADS), Q_THREADS, 0, s>>>(bt, L, src, delta, bc);
+        k_bc_combine<<<grid_for(fast ? nbig[L] : 4096u * Q_THREADS, Q_THREADS), Q_THREADS, 0, s>>>(bt, L, src, delta,
+                                                                                                    bc);
       }
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc bwd launch");
@@ -690,23 +693,62 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
 
 // ---------------------------------------------------------------- stats
 
-__global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, uint32_t* deg,
-                                                       unsigned long long* total) {
+// Visible slots of buckets [b0, b1) of a slab, summed over the wave.
+__device__ inline uint32_t visible_in(const Slab& s, uint32_t b0, uint32_t b1, uint32_t e) {
+  const uint32_t lane = lane_id(), j = lane & 15;
+  uint32_t c = 0;
+  for (uint32_t b = b0 + (lane >> 4); b < b1; b += 4) {
+    uint32_t* bp = bucket_ptr(s, b);
+    if (bp[j] != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), e)) c++;
+  }
+  return wave_sum_u32(c);
+}
+
+// One wave per vertex: slabs of one backward tile (BWD_TILE buckets) are
+// counted here; longer ones are listed, with their tiles, for k_degree_tiles
+// (parity 0), so a hub does not hold one wave for its whole slab.
+__global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, uint32_t* deg, unsigned long long* total,
+                                                       BwdTiles bt) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
   const uint32_t nwaves = gridDim.x * Q_WAVES;
   unsigned long long sum = 0;
   for (uint32_t v = gwave; v < st.V; v += nwaves) {
-    Slab s = slab_of(st.fp, st.fdesc[v]);
-    uint32_t c = 0;
-    for (uint32_t b = lane >> 4; b < s.nb; b += 4) {
-      uint32_t* bp = bucket_ptr(s, b);
-      uint32_t j = lane & 15;
-      if (bp[j] != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), e)) c++;
+    const uint64_t desc = st.fdesc[v];
+    const Slab s = slab_of(st.fp, desc);
+    if (bwd_is_big(desc)) {
+      if (deg && lane == 0) deg[v] = 0;
+      bwd_list(bt, 0, v, desc);
+      continue;
     }
-    c = wave_sum_u32(c);
+    const uint32_t c = visible_in(s, 0, s.nb, e);
     if (lane == 0) {
       if (deg) deg[v] = c;
+      sum += c;
+    }
+  }
+  if (lane == 0 && sum) atomicAdd(total, sum);
+}
+
+// One wave per listed tile: its count added to the vertex's degree.
+__global__ __launch_bounds__(Q_THREADS) void k_degree_tiles(Store st, uint32_t e, uint32_t* deg,
+                                                            unsigned long long* total, BwdTiles bt) {
+  const uint32_t lane = lane_id();
+  const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
+  const uint32_t nwaves = gridDim.x * Q_WAVES;
+  const uint32_t nt = min(bt.head->tiles[0], bt.cap_tiles);
+  unsigned long long sum = 0;
+  for (uint32_t t = gwave; t < nt; t += nwaves) {
+    const uint32_t i = bt.tmap[t];
+    if (i >= bt.cap_verts) continue;
+    const BigVert bv = bt.big[i];
+    if (t < bv.base || t - bv.base >= bv.n) continue;
+    const Slab s = slab_of(st.fp, bv.desc);
+    const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
+    if (b0 >= s.nb) continue;
+    const uint32_t c = visible_in(s, b0, min(s.nb, b0 + BWD_TILE), e);
+    if (lane == 0 && c) {
+      if (deg) atomicAdd(&deg[bv.v], c);
       sum += c;
     }
   }
@@ -716,9 +758,13 @@ __global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, uin
 dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hipStream_t s) {
   hipError_t he = ensure_query_scratch(g, g->qs, false, false);
   if (he != hipSuccess) return hip_fail(g, he, "stats scratch");
+  if ((he = ensure(g->qs.bt, bwd_tiles_bytes(g->st.fp.cap, 1))) != hipSuccess) return hip_fail(g, he, "stats scratch");
+  const BwdTiles bt = bwd_tiles_at(g->qs.bt.as<char>(), g->st.fp.cap, 1);
   unsigned long long* tot = reinterpret_cast<unsigned long long*>(g->qs.counters.as<QCounters>() + 3);
   fill<unsigned long long>(tot, 1, 0ull, s);
-  k_degrees<<<grid_for(g->cfg.v_capacity, Q_WAVES, 8192), Q_THREADS, 0, s>>>(g->st, e, deg, tot);
+  fill<uint32_t>(reinterpret_cast<uint32_t*>(bt.head), sizeof(BwdHead) / 4, 0u, s);
+  k_degrees<<<grid_for(g->cfg.v_capacity, Q_WAVES, 8192), Q_THREADS, 0, s>>>(g->st, e, deg, tot, bt);
+  k_degree_tiles<<<resident((const void*)k_degree_tiles), Q_THREADS, 0, s>>>(g->st, e, deg, tot, bt);
   if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "stats launch");
   if (n_arcs) {
     if ((he = hipMemcpyAsync(g->qs.host_counters, tot, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)

@@ -81,7 +81,9 @@ struct dg_server {
     std::deque<Req*> q;
     unsigned long long draining = 0;
     hipStream_t s = nullptr;
-    hipEvent_t out_ready = nullptr;   // SSSP: outputs extracted up to here
+    // SSSP: per slot, its output extracted up to here (one event per slot, so
+    // no event is recorded again while the copy thread may wait on it)
+    std::vector<hipEvent_t> ready;
     std::thread t;
     uint64_t joined_running = 0;      // admitted while others of the search were running
   };
@@ -438,10 +440,10 @@ struct dg_server {
       dg::pool_read_end(g);
       pass++;
       const unsigned long long done = he == hipSuccess && !res.overflow ? active & ~res.progress : 0ull;
-      hipEvent_t ready = nullptr;
       if (done && !bfs) {
-        he = dg::xs_extract(xss, outs, done, X.s, X.out_ready);
-        ready = X.out_ready;
+        he = dg::xs_extract(xss, outs, done, X.s, nullptr);
+        for (uint32_t b = 0; he == hipSuccess && b < X.nslots; b++)
+          if (done >> b & 1ull) he = hipEventRecord(X.ready[b], X.s);
       }
       if (he != hipSuccess || res.overflow) {
         // the search state is lost: fail its queries and start afresh
@@ -475,7 +477,7 @@ struct dg_server {
           if (done >> b & 1ull) {
             if (slot[b].pinned) dg_snapshot_release(g, slot[b].epoch);
             slot[b].pinned = false;
-            copies.push_back(Done{slot[b].r, &X, b, slot[b].out.p, slot[b].epoch, ready});
+            copies.push_back(Done{slot[b].r, &X, b, slot[b].out.p, slot[b].epoch, bfs ? nullptr : X.ready[b]});
             slot[b].r = nullptr;
           }
         active &= ~done;
@@ -549,9 +551,12 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
             hipStreamCreateWithFlags(&s->sc, hipStreamNonBlocking) == hipSuccess;
   for (dg_server::ExecQ* x : {&s->xb, &s->xs}) {
     const bool on = x->kind == DG_Q_BFS ? !s->cfg.bfs_rounds : !s->cfg.sssp_rounds;
-    if (ok && on)
-      ok = hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&x->out_ready, hipEventDisableTiming) == hipSuccess;
+    if (ok && on) ok = hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking) == hipSuccess;
+    if (ok && on && x->kind == DG_Q_SSSP) {
+      x->ready.assign(x->nslots, nullptr);
+      for (hipEvent_t& ev : x->ready)
+        if (ok) ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    }
   }
   for (uint32_t i = 0; ok && i < s->cfg.query_lanes; i++) {
     hipStream_t x = nullptr;
@@ -563,7 +568,8 @@ dg_status dg_server_start(dg_graph* g, const dg_server_config* cfg, dg_server** 
     if (s->sc) hipStreamDestroy(s->sc);
     for (dg_server::ExecQ* x : {&s->xb, &s->xs}) {
       if (x->s) hipStreamDestroy(x->s);
-      if (x->out_ready) hipEventDestroy(x->out_ready);
+      for (hipEvent_t ev : x->ready)
+        if (ev) hipEventDestroy(ev);
     }
     for (hipStream_t x : s->sq) hipStreamDestroy(x);
     delete s;
@@ -610,7 +616,8 @@ dg_status dg_server_stop(dg_server* s) {
       hipStreamSynchronize(x->s);
       hipStreamDestroy(x->s);
     }
-    if (x->out_ready) hipEventDestroy(x->out_ready);
+    for (hipEvent_t ev : x->ready)
+      if (ev) hipEventDestroy(ev);
   }
   hipStreamSynchronize(s->su);
   hipStreamDestroy(s->su);

@@ -81,7 +81,7 @@ void xs_destroy(XsState* x);
 hipError_t xs_pass(XsState* x, dg_graph* g, const Store& st, hipStream_t s, uint32_t grid_pct, const XbEpochs& ep,
                    const XbSeeds& seeds, unsigned long long clear_mask, XbResult* r);
 // Writes the distances of the slots in mask into outs.out[slot] (-1 where
-// unreached) on stream s, then records `done` on s.
+// unreached) on stream s, then records `done` on s unless it is null.
 hipError_t xs_extract(XsState* x, const XbOuts& outs, unsigned long long mask, hipStream_t s, hipEvent_t done);
 
 }  // namespace dg

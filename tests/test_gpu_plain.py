@@ -268,6 +268,10 @@ def test_bulk_load_spans_many_tiles(dg):
         assert np.array_equal(res, r_o)
         src = synth.out_degree_sources(gr, 4, synth.rng_for(2, 3))
         check_queries(g, o, g.epoch, src, dg, bc=True)
+        # out-degrees, hubs counted tile by tile
+        want = np.array([o.out_degree(v) for v in range(gr.n)], np.int64)
+        assert want.max() > 32 * 16, "no slab longer than one tile"
+        assert np.array_equal(g.out_degrees().cpu().numpy().astype(np.int64), want)
         for T in (16, 32, 64):
             g.set_tuning(chunk_buckets=T, sssp_delta=17 * T)
             check_queries(g, o, g.epoch, src[:1], dg)
