@@ -169,6 +169,12 @@ void pool_read_begin(dg_graph* g, std::unique_lock<std::mutex>& lk) {
   g->pool_readers++;
 }
 
+void yield_to_updates(dg_graph* g) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (g->update_running.load() && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(4))
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+}
+
 void pool_read_end(dg_graph* g) {
   std::lock_guard<std::mutex> lk(g->mu);
   g->pool_readers--;

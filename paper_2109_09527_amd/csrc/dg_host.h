@@ -250,6 +250,10 @@ struct dg_graph {
   // searches admit no new queries while a compaction waits.
   int search_holds = 0;
   std::atomic<int> compact_waiting{0};
+  // Set by the serving loop while it applies an update batch: multi-pass
+  // searches hold their next pass back for a while (yield_to_updates), so
+  // the batch's short dependent kernels find free compute units.
+  std::atomic<int> update_running{0};
   std::mutex upd_mu;            // one update batch (or compaction) at a time
 };
 
@@ -260,6 +264,8 @@ namespace dg {
 void pool_read_begin(dg_graph* g, std::unique_lock<std::mutex>& lk);
 // Ends a read begun by pool_read_begin (takes g->mu).
 void pool_read_end(dg_graph* g);
+// Waits (up to 4 ms) while the serving loop applies an update batch.
+void yield_to_updates(dg_graph* g);
 uint32_t gc_floor(const dg_graph* g);
 bool alive_at(const dg_graph* g, uint32_t v, uint32_t e);
 bool is_device_ptr(const void* p);

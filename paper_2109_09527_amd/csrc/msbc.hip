@@ -473,6 +473,7 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
   uint32_t tag = 1;
   uint64_t arcs = 0;
   for (int32_t lvl = 0; near; lvl++) {
+    yield_to_updates(g);
     if (tag >= MB_TAG_MAX) return fail(DG_E_HIP, "level count exceeds the mask tag range");
     const int nxt = slot ^ 1;
     const uint64_t used = off.back();
@@ -507,6 +508,7 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
   // levels in decreasing order (k_mb_init zeroed the tile counts)
   ProfScope ps(g, KID_BATCH_BC, s);
   for (int32_t lvl = (int32_t)off.size() - 2; lvl >= 0; lvl--) {
+    yield_to_updates(g);
     const uint64_t o0 = off[lvl], n = off[lvl + 1] - off[lvl];
     if (!n) continue;
     const uint32_t grid =

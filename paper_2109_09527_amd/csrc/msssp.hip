@@ -437,6 +437,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
   uint64_t arcs = 0, scanned = 0;
   for (;;) {
     if (tag >= MS_TAG_MAX) return fail(DG_E_HIP, "pass count exceeds the mask tag range");
+    yield_to_updates(g);
     if (near) {
       const int nxt = slot ^ 1;
       MsPass a{st,        e,         fast,        fr[qi],  fr[qi ^ 1], L.D,           L.nm[(tag - 1) & 1],

@@ -113,9 +113,6 @@ struct dg_server {
   std::deque<Done> copies;
   std::condition_variable cv_copy;
   bool copy_stop = false;
-  // an update batch is being applied: the executors hold their next pass
-  // back for a while, so the batch's short kernels find free compute units
-  std::atomic<int> updating{0};
   clk::time_point t0;
   std::vector<double> lat_all, lat_q, lat_u;
   uint64_t ops_applied = 0, arcs = 0, n_upd = 0, n_qry = 0;
@@ -195,9 +192,9 @@ struct dg_server {
       }
       r->results.assign(r->ops.size(), 0);
       dg_epoch ep = 0;
-      updating.store(1);
+      g->update_running.store(1);
       dg_status st = dg_apply_batch(g, r->ops.data(), r->ops.size(), r->results.data(), &ep, su);
-      updating.store(0);
+      g->update_running.store(0);
       // a rejected batch publishes nothing: it stands at the epoch that is
       // latest (only this thread publishes, so that is still the one it saw)
       if (st != DG_OK) ep = dg_latest_epoch(g);
@@ -426,8 +423,7 @@ struct dg_server {
         }
       }
       // updates go first: wait (up to a few ms) for a running batch
-      for (auto t0 = clk::now(); updating.load() && clk::now() - t0 < std::chrono::milliseconds(4);)
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      dg::yield_to_updates(g);
       dg::Store st;
       {
         std::unique_lock<std::mutex> lk(g->mu);

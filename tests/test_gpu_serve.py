@@ -278,3 +278,36 @@ def test_executor_admits_into_running_searches(dg, kind):
         if a["epoch"] < b["epoch"] and a["t_arrive_ms"] < b["t_done_ms"] and b["t_arrive_ms"] < a["t_done_ms"])
     say("overlapping pairs on different epochs", overlap_mixed)
     assert overlap_mixed > 0
+
+
+def test_compaction_while_serving(dg):
+    """dg_compact called while the executors run searches: compaction moves
+    slabs, so it waits until no running search holds slab descriptors (the
+    executors admit nothing meanwhile), then serving resumes.  Every result
+    still matches the oracle on its epoch and the same query alone."""
+    say("compaction while serving")
+    seed = 31
+    gr = synth.rmat_graph(13, 16, 50, seed=seed)
+    g = dg.Graph(gr.n, w_max=50, max_resident_epochs=256)
+    load = synth.load_ops(gr)
+    g.apply(load)
+    wl = synth.update_batches(graph=gr, n_batches=20, n_edge_ops=1500, w_max=50, seed=seed)
+    srcs = synth.out_degree_sources(gr, 32, synth.rng_for(seed, 4))
+    srv = dg.Server(g, mem_budget=1 << 30, max_inflight=128, max_batch=16, log_ops=True)
+    submitted = {}
+    nu = 0
+    for i in range(150):
+        if i % 7 == 6 and nu < len(wl.batches):
+            submitted[srv.submit_update(wl.batches[nu])] = ("update", wl.batches[nu])
+            nu += 1
+        s = int(srcs[i % len(srcs)])
+        kind = "bfs" if i % 2 == 0 else "sssp"
+        submitted[srv.submit_query(dg.Q_BFS if kind == "bfs" else dg.Q_SSSP, [s])] = (kind, [s])
+        if i in (50, 100):
+            g.compact()
+    log, taken, stats = collect(srv, submitted, gr.n)
+    o = Oracle(gr.n, w_max=50)
+    o.apply(load)
+    n = replay_log(dg, g, o, o.epoch, log, submitted, taken)
+    say("checked", n)
+    assert n == 150
