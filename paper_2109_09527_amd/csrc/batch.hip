@@ -106,7 +106,7 @@ struct TeamScratch {
   uint32_t* stamp;
   uint32_t* infar;
   unsigned long long* sigma;
-  double* delta;
+  double* delta;          // BC: (1 + dependency) / path count of each finished vertex
   int32_t* level;
   uint32_t* off;          // BC: start of each level in the discovery order
   uint32_t* rlist;        // SSSP bucket record list (aliases sigma)
@@ -467,9 +467,9 @@ __device__ __forceinline__ bool run_bc(const BatchArgs& a, const QDesc& qd, cons
       BARRIER();
       const uint32_t nt = uni(ld_relaxed(&bt.head->tiles[L & 1]));
       if (nt) {
-        bcbwd_tiles(a.st, qd.epoch, a.fast != 0, ts.level, L, ts.sigma, ts.delta, bt, nt, w, S);
+        bcbwd_tiles(a.st, qd.epoch, a.fast != 0, ts.level, L, ts.delta, bt, nt, w, S);
         BARRIER();
-        bcbwd_combine(bt, uni(ld_relaxed(&bt.head->verts[L & 1])), src, ts.delta, bc, w, S);
+        bcbwd_combine(bt, uni(ld_relaxed(&bt.head->verts[L & 1])), src, ts.sigma, ts.delta, bc, w, S);
         BARRIER();
       }
     }

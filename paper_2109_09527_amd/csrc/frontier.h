@@ -1174,8 +1174,11 @@ __device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint3
 //
 // The dependency of v at level L (Brandes' backward recurrence):
 //   delta[v] = sum over visible arcs v->w with level[w] = L+1 of
-//              sigma[v]/sigma[w] * (1 + delta[w]).
-// Its summation order is fixed by the slab layout alone: the slab is cut
+//              sigma[v]/sigma[w] * (1 + delta[w])
+//            = sigma[v] * (sum of coef[w]),  coef[w] = (1 + delta[w]) / sigma[w].
+// A finished vertex stores coef (one division per vertex, not per arc), so
+// a pull reads one value per arc.  The sum's order is fixed by the slab
+// layout alone: the slab is cut
 // into tiles of BWD_TILE buckets; in tile t, lane l adds the matching slots
 // l % 16 of buckets t BWD_TILE + l / 16 + 4i in increasing i, the 64 lane
 // sums combine by a fixed butterfly, and the tile sums add in tile order.
@@ -1252,21 +1255,33 @@ __device__ inline void bwd_list(const BwdTiles& t, uint32_t par, uint32_t v, uin
   for (uint32_t i = lane_id(); i < n; i += 64) t.tmap[base + i] = idx;
 }
 
-// The wave's sum over tile [b0, b1) of v's slab (combined over lanes).
+// The wave's sum of coef[w] over tile [b0, b1) of v's slab (combined over
+// lanes).
 __device__ __forceinline__ double bwd_tile_sum(const Slab& s, uint32_t b0, uint32_t b1, uint32_t e, bool fast,
-                                               double sv, const int32_t* level, int32_t L,
-                                               const unsigned long long* sigma, const double* delta) {
+                                               const int32_t* level, int32_t L, const double* coef) {
   const uint32_t lane = lane_id(), j = lane & 15;
   double acc = 0.0;
   for (uint32_t b = b0 + (lane >> 4); b < b1; b += 4) {
     uint32_t* bp = bucket_ptr(s, b);
     uint32_t w = bp[j];
-    if (w != EMPTY && slot_visible(s, bp, b, j, e, fast) && level[w] == L + 1)
-      acc += sv / (double)sigma[w] * (1.0 + delta[w]);
+    if (w != EMPTY && slot_visible(s, bp, b, j, e, fast) && level[w] == L + 1) acc += coef[w];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   return acc;
+}
+
+// v's dependency from its sum of coefficients: added to bc (v not the
+// source), and v's own coefficient stored for the level above.  Every
+// operation rounds on its own (no fused multiply-add), as in the
+// multi-source form, which stores the dependency before adding it.
+__device__ inline void bwd_finish(uint32_t v, double sum, uint32_t src, const unsigned long long* sigma, double* coef,
+                                  double* bc) {
+#pragma clang fp contract(off)
+  const double sv = (double)sigma[v];
+  const double d = sv * sum;
+  if (v != src) bc[v] += d;
+  coef[v] = (1.0 + d) / sv;
 }
 
 // One wave per vertex of level L's list verts[0..nv): slabs of one tile
@@ -1274,7 +1289,7 @@ __device__ __forceinline__ double bwd_tile_sum(const Slab& s, uint32_t b0, uint3
 // zeroes the other parity's counts for the next level.
 __device__ __forceinline__ void bcbwd_step(const Store& st, uint32_t e, bool fast, const uint32_t* verts, uint32_t nv,
                                            uint32_t src, const int32_t* level, int32_t L,
-                                           const unsigned long long* sigma, double* delta, double* bc,
+                                           const unsigned long long* sigma, double* coef, double* bc,
                                            const BwdTiles& bt, uint32_t worker, uint32_t nworkers) {
   const uint32_t lane = lane_id();
   const uint32_t par = (uint32_t)L & 1u;
@@ -1292,18 +1307,15 @@ __device__ __forceinline__ void bcbwd_step(const Store& st, uint32_t e, bool fas
       bwd_list(bt, par, v, desc);
       continue;
     }
-    const double acc = bwd_tile_sum(s, 0, s.nb, e, fast, (double)sigma[v], level, L, sigma, delta);
-    if (lane == 0) {
-      delta[v] = acc;
-      if (v != src) bc[v] += acc;
-    }
+    const double acc = bwd_tile_sum(s, 0, s.nb, e, fast, level, L, coef);
+    if (lane == 0) bwd_finish(v, acc, src, sigma, coef, bc);
   }
 }
 
 // One wave per listed tile of level L: its sum into part[tile].
 __device__ __forceinline__ void bcbwd_tiles(const Store& st, uint32_t e, bool fast, const int32_t* level, int32_t L,
-                                            const unsigned long long* sigma, const double* delta, const BwdTiles& bt,
-                                            uint32_t nt, uint32_t worker, uint32_t nworkers) {
+                                            const double* coef, const BwdTiles& bt, uint32_t nt, uint32_t worker,
+                                            uint32_t nworkers) {
   const uint32_t gwave = worker * Q_WAVES + (threadIdx.x >> 6);
   const uint32_t nwaves = nworkers * Q_WAVES;
   nt = min(nt, bt.cap_tiles);
@@ -1315,23 +1327,22 @@ __device__ __forceinline__ void bcbwd_tiles(const Store& st, uint32_t e, bool fa
     const Slab s = slab_of(st.fp, bv.desc);
     const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
     if (b0 >= s.nb) continue;
-    const double acc =
-        bwd_tile_sum(s, b0, min(s.nb, b0 + BWD_TILE), e, fast, (double)sigma[bv.v], level, L, sigma, delta);
+    const double acc = bwd_tile_sum(s, b0, min(s.nb, b0 + BWD_TILE), e, fast, level, L, coef);
     if (lane_id() == 0) bt.part[t] = acc;
   }
 }
 
 // One lane per listed vertex of level L: its tile sums added in tile order.
-__device__ __forceinline__ void bcbwd_combine(const BwdTiles& bt, uint32_t nbig, uint32_t src, double* delta,
-                                              double* bc, uint32_t worker, uint32_t nworkers) {
+__device__ __forceinline__ void bcbwd_combine(const BwdTiles& bt, uint32_t nbig, uint32_t src,
+                                              const unsigned long long* sigma, double* coef, double* bc,
+                                              uint32_t worker, uint32_t nworkers) {
   nbig = min(nbig, bt.cap_verts);
   for (uint32_t i = worker * Q_THREADS + threadIdx.x; i < nbig; i += nworkers * Q_THREADS) {
     const BigVert bv = bt.big[i];
     if (bv.n == 0 || bv.base >= bt.cap_tiles || bv.n > bt.cap_tiles - bv.base) continue;
     double acc = bt.part[bv.base];
     for (uint32_t t = 1; t < bv.n; t++) acc += bt.part[bv.base + t];
-    delta[bv.v] = acc;
-    if (bv.v != src) bc[bv.v] += acc;
+    bwd_finish(bv.v, acc, src, sigma, coef, bc);
   }
 }
 

@@ -15,10 +15,11 @@
 // Backward pass at level l, one wave per vertex v of the level's list, for
 // each source s with L[v][s] = l:
 //   DL[v][s] = sum over visible arcs v -> w with L[w][s] = l + 1 of
-//              SG[v][s] / SG[w][s] * (1 + DL[w][s]),
-// each lane summing its slots bucket after bucket and the 64 partial sums
-// combining by a fixed butterfly, which is the plain path's order for one
-// source, so every dependency equals the plain path's bit for bit.  Then
+//              SG[v][s] / SG[w][s] * (1 + DL[w][s])
+//            = SG[v][s] * (sum of CL[w][s]),  CL = (1 + DL) / SG,
+// each lane summing its slots bucket after bucket (a long slab tile by
+// tile) and the partial sums combining in the plain path's fixed order,
+// so every dependency equals the plain path's bit for bit.  Then
 // bc[v] += DL[v][s] for the group's sources in their order (v != s, v
 // reached), which continues the plain path's sequence of additions.
 #include <algorithm>
@@ -156,11 +157,12 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_fwd(MbFwd a, unsigned long lon
   lc.commit(a.cnt_out, sh);
 }
 
-// Per-lane sums over tile [b0, b1) of v's slab for the sources in m (the
-// plain path's terms and order, one accumulator per source).
+// Per-lane sums of CL[w][s] = (1 + DL[w][s]) / SG[w][s] over tile
+// [b0, b1) of v's slab for the sources in m (the plain path's terms and
+// order, one accumulator per source).
 __device__ __forceinline__ void mb_tile_lanes(const Slab& sl, uint32_t b0, uint32_t b1, uint32_t e, bool fast,
-                                              uint32_t m, const double (&sv)[MBQ], int32_t lvl, const int32_t* L,
-                                              const unsigned long long* SG, const double* DL, double (&acc)[MBQ]) {
+                                              uint32_t m, int32_t lvl, const int32_t* L, const double* CL,
+                                              double (&acc)[MBQ]) {
   const uint32_t j = lane_id() & 15;
   for (uint32_t b = b0 + (lane_id() >> 4); b < b1; b += 4) {
     uint32_t* bp = bucket_ptr(sl, b);
@@ -179,10 +181,19 @@ __device__ __forceinline__ void mb_tile_lanes(const Slab& sl, uint32_t b0, uint3
     }
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) {
-      if (((m >> s) & 1u) && lv[s] == lvl + 1)
-        acc[s] += sv[s] / (double)SG[(uint64_t)w * MBQ + s] * (1.0 + DL[(uint64_t)w * MBQ + s]);
+      if (((m >> s) & 1u) && lv[s] == lvl + 1) acc[s] += CL[(uint64_t)w * MBQ + s];
     }
   }
+}
+
+// A (vertex, source)'s dependency from its path count and sum of
+// coefficients, and its own coefficient.  Every operation rounds on its own
+// (no fused multiply-add), as in the plain path.
+__device__ inline void mb_finish(double sv, double sum, double* dl, double* cl) {
+#pragma clang fp contract(off)
+  const double d = sv * sum;
+  *dl = d;
+  *cl = (1.0 + d) / sv;
 }
 
 // The group's sources at level lvl for vertex v (wave-uniform), and their
@@ -203,7 +214,8 @@ __device__ __forceinline__ uint32_t mb_at_level(uint32_t v, int32_t lvl, uint32_
 // tile counts.
 __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int fast, const uint32_t* verts,
                                                       uint32_t nv, int32_t lvl, uint32_t nq, const int32_t* L,
-                                                      const unsigned long long* SG, double* DL, BwdTiles bt) {
+                                                      const unsigned long long* SG, double* DL, double* CL,
+                                                      BwdTiles bt) {
   const uint32_t lane = lane_id();
   const uint32_t par = (uint32_t)lvl & 1u;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -223,14 +235,14 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int 
     const uint32_t m = mb_at_level(v, lvl, nq, L, SG, sv);
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) acc[s] = 0.0;
-    mb_tile_lanes(sl, 0, sl.nb, e, fast != 0, m, sv, lvl, L, SG, DL, acc);
+    mb_tile_lanes(sl, 0, sl.nb, e, fast != 0, m, lvl, L, CL, acc);
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) {
       if (!((m >> s) & 1u)) continue;   // wave-uniform
       double x = acc[s];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-      if (lane == 0) DL[(uint64_t)v * MBQ + s] = x;
+      if (lane == 0) mb_finish(sv[s], x, &DL[(uint64_t)v * MBQ + s], &CL[(uint64_t)v * MBQ + s]);
     }
   }
 }
@@ -238,7 +250,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_bwd(Store st, uint32_t e, int 
 // One wave per listed tile of level lvl: its sums into part[tile * MBQ + s].
 __global__ __launch_bounds__(Q_THREADS) void k_mb_tiles(Store st, uint32_t e, int fast, int32_t lvl, uint32_t nq,
                                                         const int32_t* L, const unsigned long long* SG,
-                                                        const double* DL, BwdTiles bt) {
+                                                        const double* CL, BwdTiles bt) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6), nwaves = gridDim.x * Q_WAVES;
   const uint32_t nt = min(bt.head->tiles[lvl & 1], bt.cap_tiles);
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_tiles(Store st, uint32_t e, in
     const uint32_t m = mb_at_level(bv.v, lvl, nq, L, SG, sv);
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) acc[s] = 0.0;
-    mb_tile_lanes(sl, b0, min(sl.nb, b0 + BWD_TILE), e, fast != 0, m, sv, lvl, L, SG, DL, acc);
+    mb_tile_lanes(sl, b0, min(sl.nb, b0 + BWD_TILE), e, fast != 0, m, lvl, L, CL, acc);
 #pragma unroll
     for (int s = 0; s < (int)MBQ; s++) {
       if (!((m >> s) & 1u)) continue;   // wave-uniform
@@ -268,7 +280,8 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_tiles(Store st, uint32_t e, in
 
 // One lane per (listed vertex, source at level lvl): the tile sums added in
 // tile order.
-__global__ __launch_bounds__(Q_THREADS) void k_mb_combine(int32_t lvl, uint32_t nq, const int32_t* L, double* DL,
+__global__ __launch_bounds__(Q_THREADS) void k_mb_combine(int32_t lvl, uint32_t nq, const int32_t* L,
+                                                          const unsigned long long* SG, double* DL, double* CL,
                                                           BwdTiles bt) {
   const uint32_t nbig = min(bt.head->verts[lvl & 1], bt.cap_verts);
   for (uint64_t x = (uint64_t)blockIdx.x * Q_THREADS + threadIdx.x; x < (uint64_t)nbig * MBQ;
@@ -279,7 +292,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_mb_combine(int32_t lvl, uint32_t 
     if (bv.n == 0 || bv.base >= bt.cap_tiles || bv.n > bt.cap_tiles - bv.base) continue;
     double acc = bt.part[(uint64_t)bv.base * MBQ + s];
     for (uint32_t t = 1; t < bv.n; t++) acc += bt.part[(uint64_t)(bv.base + t) * MBQ + s];
-    DL[(uint64_t)bv.v * MBQ + s] = acc;
+    mb_finish((double)SG[(uint64_t)bv.v * MBQ + s], acc, &DL[(uint64_t)bv.v * MBQ + s], &CL[(uint64_t)bv.v * MBQ + s]);
   }
 }
 
@@ -358,6 +371,7 @@ struct MbLayout {
   int32_t* L;
   unsigned long long* SG;
   double* DL;
+  double* CL;   // (1 + DL) / SG of each finished (vertex, source)
   uint32_t *nm[2], *order;
   uint64_t order_cap;
   Item* q[2];
@@ -383,6 +397,7 @@ static uint64_t mb_layout(const Store& st, char* base, MbLayout* P) {
   p = take(V * MBQ * 4); if (P) P->L = reinterpret_cast<int32_t*>(p);
   p = take(V * MBQ * 8); if (P) P->SG = reinterpret_cast<unsigned long long*>(p);
   p = take(V * MBQ * 8); if (P) P->DL = reinterpret_cast<double*>(p);
+  p = take(V * MBQ * 8); if (P) P->CL = reinterpret_cast<double*>(p);
   for (int i = 0; i < 2; i++) { p = take(V * 4 + 64); if (P) P->nm[i] = reinterpret_cast<uint32_t*>(p); }
   p = take(order_cap * 4); if (P) { P->order = reinterpret_cast<uint32_t*>(p); P->order_cap = order_cap; }
   for (int i = 0; i < 2; i++) { p = take(items * sizeof(Item)); if (P) P->q[i] = reinterpret_cast<Item*>(p); }
@@ -513,14 +528,14 @@ dg_status ms_bc_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const ui
     if (!n) continue;
     const uint32_t grid =
         std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)((n + Q_WAVES - 1) / Q_WAVES), mb.bwd_grid));
-    k_mb_bwd<<<grid, Q_THREADS, 0, s>>>(st, e, fast, P.order + o0, (uint32_t)n, lvl, k, P.L, P.SG, P.DL, P.bt);
+    k_mb_bwd<<<grid, Q_THREADS, 0, s>>>(st, e, fast, P.order + o0, (uint32_t)n, lvl, k, P.L, P.SG, P.DL, P.CL, P.bt);
     // the forward's count of long slabs is exact only while no update can
     // move a slab in between
     if (nbig[lvl] || !fast) {
-      k_mb_tiles<<<mb.tiles_grid, Q_THREADS, 0, s>>>(st, e, fast, lvl, k, P.L, P.SG, P.DL, P.bt);
+      k_mb_tiles<<<mb.tiles_grid, Q_THREADS, 0, s>>>(st, e, fast, lvl, k, P.L, P.SG, P.CL, P.bt);
       const uint64_t lanes = (uint64_t)std::max<uint32_t>(nbig[lvl], fast ? 0u : 4096u) * MBQ;
       k_mb_combine<<<(uint32_t)std::min<uint64_t>((lanes + Q_THREADS - 1) / Q_THREADS, 4096), Q_THREADS, 0, s>>>(
-          lvl, k, P.L, P.DL, P.bt);
+          lvl, k, P.L, P.SG, P.DL, P.CL, P.bt);
     }
   }
   k_mb_accum<<<(uint32_t)std::min<uint64_t>((V + 255) / 256, 4096), 256, 0, s>>>(P.L, P.DL, P.src, k, V, bc);

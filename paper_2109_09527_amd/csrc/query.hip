@@ -142,14 +142,13 @@ __global__ __launch_bounds__(Q_THREADS) void k_bc_bwd(Store st, uint32_t e, int 
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_tiles(Store st, uint32_t e, int fast, const int32_t* level, int32_t L,
-                                                        const unsigned long long* sigma, const double* delta,
-                                                        BwdTiles bt) {
-  bcbwd_tiles(st, e, fast != 0, level, L, sigma, delta, bt, bt.head->tiles[L & 1], blockIdx.x, gridDim.x);
+                                                        const double* coef, BwdTiles bt) {
+  bcbwd_tiles(st, e, fast != 0, level, L, coef, bt, bt.head->tiles[L & 1], blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bc_combine(BwdTiles bt, int32_t L, uint32_t src, double* delta,
-                                                          double* bc) {
-  bcbwd_combine(bt, bt.head->verts[L & 1], src, delta, bc, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(Q_THREADS) void k_bc_combine(BwdTiles bt, int32_t L, uint32_t src,
+                                                          const unsigned long long* sigma, double* coef, double* bc) {
+  bcbwd_combine(bt, bt.head->verts[L & 1], src, sigma, coef, bc, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_inf_to_minus1(int32_t* d, uint32_t n) {
@@ -605,7 +604,7 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
   uint32_t* order = q.fa.as<uint32_t>();
   int32_t* level = q.level.as<int32_t>();
   unsigned long long* sigma = q.sigma.as<unsigned long long>();
-  double* delta = q.delta.as<double>();
+  double* delta = q.delta.as<double>();   // per vertex (1 + dependency) / path count, once finished
   QCounters* cnt = q.counters.as<QCounters>();
   // cnt[0..1] alternate per level; cnt[2] holds the running order total
   // and the overflow flag of the current source
@@ -669,10 +668,9 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
       // the forward's count of long slabs is exact only while no update can
       // move a slab in between
       if (nbig[L] || !fast) {
-        k_bc_tiles<<<resident((const void*)k_bc_tiles), Q_THREADS, 0, s>>>(g->st, e, fast, level, L, sigma, delta,
-                                                                          bt);
-        k_bc_combine<<<grid_for(fast ? nbig[L] : 4096u * Q_THREADS, Q_THREADS), Q_THREADS, 0, s>>>(bt, L, src, delta,
-                                                                                                    bc);
+        k_bc_tiles<<<resident((const void*)k_bc_tiles), Q_THREADS, 0, s>>>(g->st, e, fast, level, L, delta, bt);
+        k_bc_combine<<<grid_for(fast ? nbig[L] : 4096u * Q_THREADS, Q_THREADS), Q_THREADS, 0, s>>>(bt, L, src, sigma,
+                                                                                                    delta, bc);
       }
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bc bwd launch");

@@ -57,8 +57,9 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-# BC: the forward arc count stands for both passes (forward 16 B + backward pull 32 B per arc)
-BYTES_PER_ARC = {"batch_bfs": 16, "batch_sssp": 20, "batch_bc": 48, "bc_forward": 48, "sssp_relax": 20,
+# BC: the forward arc count stands for both passes (forward 16 B + backward pull 24 B per arc:
+# dst 4, stamp 8, the target's level 4 and coefficient (1 + dependency) / path count 8)
+BYTES_PER_ARC = {"batch_bfs": 16, "batch_sssp": 20, "batch_bc": 40, "bc_forward": 40, "sssp_relax": 20,
                  "bfs_top_down": 16, "bfs_bottom_up": 12}
 
 
