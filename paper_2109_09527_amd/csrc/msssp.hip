@@ -282,13 +282,24 @@ __global__ void k_ms_seed(Store st, const uint32_t* src, const uint32_t* mask, u
   flush_front(qn, f, cnt);
 }
 
-// Query q's distances into its output, -1 where unreached (grid y: query).
-__global__ void k_ms_extract(const int32_t* D, uint64_t V, int32_t* const* outs) {
-  const uint32_t q = blockIdx.y;
-  int32_t* out = outs[q];
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
-    const int32_t x = D[v * MSQ + q];
-    out[v] = x == DIST_INF ? -1 : x;
+// Each query's distances into its output, -1 where unreached: a block
+// reads 64 vertices' records in order (8 KiB) into LDS and writes each
+// query's 64 distances as one run, so D is read once and every store is
+// coalesced.
+__global__ __launch_bounds__(256) void k_ms_extract(const int32_t* D, uint64_t V, int32_t* const* outs, uint32_t k) {
+  __shared__ int32_t t[64][MSQ + 1];
+  for (uint64_t v0 = (uint64_t)blockIdx.x * 64; v0 < V; v0 += (uint64_t)gridDim.x * 64) {
+    for (uint32_t i = threadIdx.x; i < 64 * MSQ; i += 256)
+      t[i / MSQ][i % MSQ] = v0 + i / MSQ < V ? D[v0 * MSQ + i] : DIST_INF;
+    __syncthreads();
+    const uint32_t r = threadIdx.x & 63;
+    for (uint32_t q = threadIdx.x >> 6; q < k; q += 4) {
+      if (v0 + r < V) {
+        const int32_t x = t[r][q];
+        outs[q][v0 + r] = x == DIST_INF ? -1 : x;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -485,8 +496,7 @@ dg_status ms_sssp_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const 
       far_min = hc.far_min;
     } while (!near && n_pile > 0);
   }
-  dim3 grid((uint32_t)std::min<uint64_t>((V + 255) / 256, 1024), k);
-  k_ms_extract<<<grid, 256, 0, s>>>(L.D, V, L.outs);
+  k_ms_extract<<<(uint32_t)std::min<uint64_t>((V + 63) / 64, 8192), 256, 0, s>>>(L.D, V, L.outs, k);
   if ((he = hipGetLastError()) != hipSuccess) return fail(DG_E_HIP, std::string("extract: ") + hipGetErrorString(he));
   if (arcs_out) *arcs_out += arcs;
   prof_scans(g, KID_BATCH_SSSP_SCAN, scanned);

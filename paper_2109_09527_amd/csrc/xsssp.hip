@@ -238,17 +238,27 @@ __global__ void k_xs_clear(int32_t* D, uint64_t V, uint32_t mask) {
     if ((mask >> (i % XSQ)) & 1u) D[i] = DIST_INF;
 }
 
-// Slot list[blockIdx.y]'s distances into its output (-1 where unreached).
+// The listed slots' distances into their outputs (-1 where unreached).
 struct XsOutList {
   int32_t* out[XSQ];
   uint32_t slot[XSQ];
 };
-__global__ void k_xs_extract(const int32_t* D, uint64_t V, XsOutList l) {
-  const uint32_t q = l.slot[blockIdx.y];
-  int32_t* out = l.out[blockIdx.y];
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x) {
-    const int32_t x = D[v * XSQ + q];
-    out[v] = x == DIST_INF ? -1 : x;
+// A block reads 64 vertices' records in order into LDS and writes each of
+// the n listed slots' 64 distances as one run.
+__global__ __launch_bounds__(256) void k_xs_extract(const int32_t* D, uint64_t V, XsOutList l, uint32_t n) {
+  __shared__ int32_t t[64][XSQ + 1];
+  for (uint64_t v0 = (uint64_t)blockIdx.x * 64; v0 < V; v0 += (uint64_t)gridDim.x * 64) {
+    for (uint32_t i = threadIdx.x; i < 64 * XSQ; i += 256)
+      t[i / XSQ][i % XSQ] = v0 + i / XSQ < V ? D[v0 * XSQ + i] : DIST_INF;
+    __syncthreads();
+    const uint32_t r = threadIdx.x & 63;
+    for (uint32_t i = threadIdx.x >> 6; i < n; i += 4) {
+      if (v0 + r < V) {
+        const int32_t x = t[r][l.slot[i] % XSQ];
+        l.out[i][v0 + r] = x == DIST_INF ? -1 : x;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -402,10 +412,7 @@ hipError_t xs_extract(XsState* x, const XbOuts& outs, unsigned long long mask, h
       l.slot[n] = q;
       n++;
     }
-  if (n) {
-    dim3 grid((uint32_t)std::min<uint64_t>((x->V + 255) / 256, 1024), n);
-    k_xs_extract<<<grid, 256, 0, s>>>(x->D.as<int32_t>(), x->V, l);
-  }
+  if (n) k_xs_extract<<<(uint32_t)std::min<uint64_t>((x->V + 63) / 64, 8192), 256, 0, s>>>(x->D.as<int32_t>(), x->V, l, n);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && done) e = hipEventRecord(done, s);
   return e;
