@@ -179,7 +179,13 @@ def test_server_log_without_ops(dg):
     bad = wl.batches[2].copy()
     bad["u"][0] = gr.n + 5                      # out of range: the whole batch is rejected
     ts.append(srv.submit_update(bad))
+    # sources out of range, taken by the executors and refused at admission
+    ts_bad = [srv.submit_query(dg.Q_BFS, [gr.n + 3]), srv.submit_query(dg.Q_SSSP, [gr.n + 7])]
+    ts += ts_bad
     srv.drain()
+    for t in ts_bad:
+        done, st, ep, lat = srv.poll(t)
+        assert done and st == dg.E_VERTEX_RANGE, (t, st)
     log = srv.log()
     srv.stop()
     assert sorted(r["ticket"] for r in log) == sorted(ts)
