@@ -385,8 +385,9 @@ def batched_vs_plain(args):
     m = sum(ms)
     roof = {k: kernel_roof(prof, k, BATCH_BYTES_PER_ARC[k]) for k in BATCH_BYTES_PER_ARC}
     if roof.get("batch_bfs"):
-        # one launch holds the whole multi-source BFS engine run
-        roof["batch_bfs"]["traffic"] = measured_traffic("k_team", f"rmat{args.batch_scale}")
+        # one launch is one level's expansion of a multi-source BFS group
+        roof["batch_bfs"]["kernel"] = "k_mf_pass"
+        roof["batch_bfs"]["traffic"] = measured_traffic("k_mf_pass", f"rmat{args.batch_scale}")
     kp, sc = prof.get("batch_sssp"), prof.get("batch_sssp_scan")
     if kp and sc and kp["launches"] and kp["total_ms"] > 0:
         nbytes = MS_SSSP_BYTES["per_scan"] * sc["arcs"] + MS_SSSP_BYTES["per_relaxation"] * kp["arcs"]

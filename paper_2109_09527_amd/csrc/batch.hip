@@ -1,5 +1,9 @@
-// Persistent multi-query engine: many BFS / SSSP / BC queries, on any mix
-// of retained epochs, one launch per query kind.
+// Batched queries: many BFS / SSSP / BC queries, on any mix of retained
+// epochs, in one call.  Queries of one kind on one snapshot share adjacency
+// scans: BFS groups of up to 64 (msbfs.hip), SSSP groups of up to 32
+// (msssp.hip) and BC queries of 4 or more sources (msbc.hip) run as
+// multi-source searches driven level by level from the host.  The rest runs
+// in a persistent engine, one launch per query kind:
 //
 // BFS and BC run in teams.  The grid holds at most 90% of the workgroups
 // that can be resident at once (from the occupancy API).  Workgroups join
@@ -79,12 +83,10 @@ __device__ inline void add_step_arcs(Ctrl* c, const QCounters* step, uint32_t w)
   }
 }
 
-// One engine job: a query, or (BFS with k > 0) a group of k <= 64 BFS
-// queries on one snapshot, run as one multi-source BFS; then srcs holds
-// their sources and out points at a device array of their k outputs.
+// One engine job: a query (for BC, k sources in srcs).
 struct QDesc {
   uint32_t kind, src, epoch, k;
-  const uint32_t* srcs;   // device copy of BC / group sources
+  const uint32_t* srcs;   // device copy of BC sources
   void* out;
 };
 
@@ -111,12 +113,11 @@ struct TeamScratch {
   uint32_t* off;          // BC: start of each level in the discovery order
   uint32_t* rlist;        // SSSP bucket record list (aliases sigma)
   uint32_t* rstamp;       // SSSP bucket record stamps (aliases delta)
-  unsigned long long* msf;   // multi-source BFS frontier masks
   TeamSync* sync;
 };
 
 // uni_scratch copies every field; a new field must be added there too.
-static_assert(sizeof(TeamScratch) == 4 * 8 + 4 * 4 + 17 * 8, "TeamScratch layout changed: update uni_scratch");
+static_assert(sizeof(TeamScratch) == 4 * 8 + 4 * 4 + 16 * 8, "TeamScratch layout changed: update uni_scratch");
 
 struct BatchArgs {
   Store st;
@@ -249,7 +250,6 @@ __device__ inline TeamScratch uni_scratch(const TeamScratch& x) {
   r.off = uni(x.off);
   r.rlist = uni(x.rlist);
   r.rstamp = uni(x.rstamp);
-  r.msf = uni(x.msf);
   r.sync = uni(x.sync);
   return r;
 }
@@ -342,67 +342,6 @@ __device__ __forceinline__ bool run_bfs(const BatchArgs& a, const QDesc& qd, con
     BARRIER();
     add_step_arcs(a.ctrl, cout, w);
     QUEUE_CHECK(cout);
-  }
-  return true;
-}
-
-// A group of qd.k BFS queries on one snapshot (multi-source BFS, top-down
-// only).  The per-vertex {visited, next} mask records use the bottom-up
-// chunk buffer (qbig: at least V + 1024 items of 16 bytes), which a
-// multi-source job never needs; the touched list lives in fa.
-__device__ __forceinline__ bool run_msbfs(const BatchArgs& a, const QDesc& qd, const TeamScratch& ts, uint32_t w,
-                                          uint32_t S, BarrierPos& bp, Shared& sh, int32_t* status) {
-  const uint32_t V = a.st.V, k = qd.k;
-  int32_t* const* outs = static_cast<int32_t* const*>(qd.out);
-  unsigned long long* vn = reinterpret_cast<unsigned long long*>(ts.qbig);
-  unsigned long long* fr = ts.msf;
-  const uint32_t wave = threadIdx.x >> 6, gw = w * Q_WAVES + wave, nw = S * Q_WAVES;
-  team_fill<unsigned long long>(vn, 2ull * V, 0ull, w, S);
-  team_fill<unsigned long long>(fr, V, 0ull, w, S);
-  for (uint32_t q = 0; q < k; q++) team_fill<int32_t>(uni(outs[q]), V, -1, w, S);
-  if (w == 0 && threadIdx.x == 0)
-    for (int i = 0; i < 3; i++) zero_counters(&ts.cnt[i]);
-  BARRIER();
-  if (w == 0 && wave == 0) {
-    // query q's bit at its source; one frontier item per distinct source
-    const uint32_t q = lane_id();
-    const uint32_t v = q < k ? qd.srcs[q] : 0;
-    bool first = false;
-    if (q < k) {
-      const unsigned long long bit = 1ull << q;
-      first = atomicOr(&vn[2 * (uint64_t)v], bit) == 0ull;
-      atomicOr(&fr[v], bit);
-      outs[q][v] = 0;
-    }
-    ItemQ qn = item_q(sh.ws[0], 0, WSTAGE);
-    push_item(qn, first, v, first ? a.st.fdesc[v] : 0);
-    flush_front(qn, team_front(ts, 0), &ts.cnt[0]);
-  }
-  BARRIER();
-  for (uint32_t lvl = 0;; lvl++) {
-    const QCounters c = read_cnt(&ts.cnt[lvl % 3]);
-    if (c.fq == 0) break;   // no frontier vertex has an out-slab
-    QCounters* cout = &ts.cnt[(lvl + 1) % 3];
-    if (w == 0 && threadIdx.x == 0) zero_counters(&ts.cnt[(lvl + 2) % 3]);
-    const MsArgs ma{a.st, qd.epoch, a.fast, team_front(ts, lvl & 1), team_front(ts, (lvl + 1) & 1),
-                    fr,   vn,       ts.fa,  cout};
-    {
-      ItemQ qn = item_q(sh.ws[wave], 0, WSTAGE);
-      U32Q qt = u32_q(sh.ws[wave]);
-      LaneCounts lc;
-      const uint32_t nitems = front_items(ma.fin, c.fq), nb = fq_buckets(c.fq), nc = front_chunks(ma.fin, c.fq);
-      for (uint32_t cc = gw; cc < nc; cc += nw) msbfs_chunk(ma, cc, nitems, nb, qn, qt, lc);
-      flush_front(qn, ma.fout, cout);
-      flush_u32_q(qt, ts.fa, &cout->n_far);
-      lc.commit(cout, sh);
-    }
-    BARRIER();
-    add_step_arcs(a.ctrl, cout, w);
-    QUEUE_CHECK(cout);
-    const uint32_t nt = uni(ld_relaxed(&cout->n_far));
-    for (uint32_t base = gw * 64; base < nt; base += nw * 64)
-      msbfs_final_block(ts.fa, nt, base, fr, vn, outs, (int32_t)lvl);
-    BARRIER();
   }
   return true;
 }
@@ -544,8 +483,7 @@ __global__ __launch_bounds__(Q_THREADS, 4) void k_team(BatchArgs a) {
     const QDesc qd = uni_desc(a.q[qi]);
     bool ok = true;
     if (a.status[qi] == DG_OK) {
-      if (KIND == DG_Q_BFS) ok = qd.k ? run_msbfs(a, qd, ts, w, S, bp, sh, &a.status[qi])
-                                      : run_bfs(a, qd, ts, w, S, bp, sh, &a.status[qi]);
+      if (KIND == DG_Q_BFS) ok = run_bfs(a, qd, ts, w, S, bp, sh, &a.status[qi]);
       else ok = run_bc(a, qd, ts, w, S, bp, sh, &a.status[qi]);
     }
     if (!ok || !team_barrier(ts.sync, S, bp, a.ctrl, sh, a.spin_ticks)) return;
@@ -899,6 +837,7 @@ struct BatchState {
   uint32_t seq = 0;
   void* hres = nullptr;          // pinned landing area of per-query statuses and control records
   size_t hres_bytes = 0;
+  MfScratch mf;                  // multi-source BFS groups
   MsScratch ms;                  // multi-source SSSP groups
   MbScratch mb;                  // multi-source BC groups
 };
@@ -980,6 +919,7 @@ void free_batch_state(dg_graph* g) {
       release(*d);
     if (b->hflag) (void)hipHostFree(b->hflag);
     if (b->hres) (void)hipHostFree(b->hres);
+    free_mf_scratch(b->mf);
     free_ms_scratch(b->ms);
     free_mb_scratch(b->mb);
     delete b;
@@ -1028,7 +968,6 @@ static uint64_t team_layout(const Store& st, uint32_t chunk_buckets, char* base,
   if (ts) ts->rstamp = reinterpret_cast<uint32_t*>(p);
   p = take(V * 4 + 64); if (ts) ts->level = reinterpret_cast<int32_t*>(p);
   p = take((V + 2) * 4 + 64); if (ts) ts->off = reinterpret_cast<uint32_t*>(p);
-  p = take(V * 8 + 64); if (ts) ts->msf = reinterpret_cast<unsigned long long*>(p);
   p = take(sizeof(TeamSync)); if (ts) ts->sync = reinterpret_cast<TeamSync*>(p);
   return o;
 }
@@ -1242,42 +1181,25 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       }
     }
   } unpin{g, pinned};
-  // BFS queries on one snapshot run in groups of up to 64 as one
-  // multi-source BFS job each (appended to qd); fewer than MS_MIN stay single
+  // BFS queries on one snapshot run in groups of up to ms_bfs_width() as
+  // one multi-source BFS each (host-driven levels, a kernel boundary per
+  // level); fewer than MS_MIN stay single and run in the engine's teams
   constexpr size_t MS_MIN = 4;
-  std::vector<std::vector<uint32_t>> groups;   // member queries of each group job
-  std::vector<uint32_t> group_job;
-  std::vector<void*> all_outs;
-  std::vector<uint64_t> out_off;
+  std::vector<std::vector<uint32_t>> bgroups;
   {
     std::map<uint32_t, std::vector<uint32_t>> by_ep;
     for (uint32_t i : by_kind[DG_Q_BFS]) by_ep[qd[i].epoch].push_back(i);
-    std::vector<uint32_t> jobs;
+    std::vector<uint32_t> single;
+    const size_t W = ms_bfs_width();
     for (auto& kv : by_ep) {
       const std::vector<uint32_t>& v = kv.second;
-      for (size_t o = 0; o < v.size(); o += 64) {
-        const size_t n = std::min<size_t>(64, v.size() - o);
-        if (n < MS_MIN) {
-          jobs.insert(jobs.end(), v.begin() + o, v.begin() + o + n);
-          continue;
-        }
-        std::vector<uint32_t> mem(v.begin() + o, v.begin() + o + n);
-        const uint32_t j = (uint32_t)qd.size();
-        const uint32_t src0 = qd[mem[0]].src;
-        src_off.push_back(all_srcs.size());
-        out_off.push_back(all_outs.size());
-        for (uint32_t u : mem) {
-          all_srcs.push_back(qd[u].src);
-          all_outs.push_back(qd[u].out);
-        }
-        qd.push_back(QDesc{DG_Q_BFS, src0, kv.first, (uint32_t)n, nullptr, nullptr});
-        st.push_back(DG_OK);
-        groups.push_back(std::move(mem));
-        group_job.push_back(j);
-        jobs.push_back(j);
+      for (size_t o = 0; o < v.size(); o += W) {
+        const size_t n = std::min<size_t>(W, v.size() - o);
+        if (n < MS_MIN) single.insert(single.end(), v.begin() + o, v.begin() + o + n);
+        else bgroups.emplace_back(v.begin() + o, v.begin() + o + n);
       }
     }
-    by_kind[DG_Q_BFS] = jobs;
+    by_kind[DG_Q_BFS] = single;
   }
   // SSSP queries on one snapshot run in groups of up to ms_sssp_width() as
   // one multi-source search each (a shared frontier, the group's distances
@@ -1384,7 +1306,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   if ((e = ensure(bs->teams, most * sizeof(TeamScratch))) != hipSuccess ||
       (e = ensure(bs->qdesc, nj * sizeof(QDesc))) != hipSuccess || (e = ensure(bs->qidx, nj * 4)) != hipSuccess ||
       (e = ensure(bs->srcs, std::max<size_t>(1, all_srcs.size()) * 4)) != hipSuccess ||
-      (e = ensure(bs->outs, std::max<size_t>(1, all_outs.size()) * sizeof(void*))) != hipSuccess ||
       (e = ensure(bs->status, nj * 4)) != hipSuccess || (e = ensure(bs->arcs, e_cnt * 8)) != hipSuccess ||
       (e = ensure(bs->live, e_cnt * 8)) != hipSuccess || (e = ensure(bs->ctrl, 3 * sizeof(Ctrl))) != hipSuccess ||
       (part_words && (e = ensure(bs->bc_part, part_words * 8)) != hipSuccess))
@@ -1397,11 +1318,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       d.srcs = bs->srcs.as<uint32_t>() + src_off[sp.j0 + t];
       d.out = bs->bc_part.as<double>() + sp.off + (uint64_t)t * st_.V;
     }
-  for (size_t gi = 0; gi < group_job.size(); gi++) {
-    QDesc& d = qd[group_job[gi]];
-    d.srcs = bs->srcs.as<uint32_t>() + src_off[group_job[gi]];
-    d.out = bs->outs.as<void*>() + out_off[gi];
-  }
   std::vector<uint32_t> qidx;
   uint32_t koff[3] = {0, 0, 0};
   for (int k = 0; k < 3; k++) {
@@ -1411,8 +1327,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
   Ctrl c0[3] = {};
   if ((e = hipMemcpyAsync(bs->teams.p, tsv.data(), most * sizeof(TeamScratch), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(bs->qdesc.p, qd.data(), nj * sizeof(QDesc), hipMemcpyHostToDevice, s)) ||
-      (all_outs.size() &&
-       (e = hipMemcpyAsync(bs->outs.p, all_outs.data(), all_outs.size() * sizeof(void*), hipMemcpyHostToDevice, s))) ||
       (qidx.size() && (e = hipMemcpyAsync(bs->qidx.p, qidx.data(), qidx.size() * 4, hipMemcpyHostToDevice, s))) ||
       (all_srcs.size() &&
        (e = hipMemcpyAsync(bs->srcs.p, all_srcs.data(), all_srcs.size() * 4, hipMemcpyHostToDevice, s))) ||
@@ -1476,6 +1390,21 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       prof_arcs(g, KID_BATCH_BC, ga);
       g->engine_arcs += ga;
     }
+    for (const std::vector<uint32_t>& grp : bgroups) {
+      std::vector<uint32_t> srcs;
+      std::vector<void*> outs;
+      for (uint32_t i : grp) {
+        srcs.push_back(qd[i].src);
+        outs.push_back(qd[i].out);
+      }
+      uint64_t ga = 0;
+      dg_status r = ms_bfs_dev(g, st_, qd[grp[0]].epoch, fast, srcs.data(), (uint32_t)grp.size(), outs.data(),
+                               tune.chunk_buckets, bs->mf, s, &ga);
+      if (r != DG_OK) return r;
+      for (uint32_t i : grp) st[i] = DG_OK;
+      prof_arcs(g, KID_BATCH_BFS, ga);
+      g->engine_arcs += ga;
+    }
     for (const std::vector<uint32_t>& grp : sgroups) {
       std::vector<uint32_t> srcs;
       std::vector<void*> outs;
@@ -1506,8 +1435,6 @@ dg_status query_batch_dev(dg_graph* g, const dg_query* q, uint32_t nq, dg_status
       }
     }
   }
-  for (size_t gi = 0; gi < groups.size(); gi++)
-    for (uint32_t u : groups[gi]) st[u] = st[group_job[gi]];
   if (!splits.empty()) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((st_.V + 255) / 256, 4096);
     for (const BcSplit& sp : splits) {

@@ -145,6 +145,15 @@ struct MsScratch {
   uint32_t relax_grid = 0, split_grid = 0;   // resident workgroups of its kernels
 };
 
+// Multi-source BFS (msbfs.hip): one group search's buffers and its pinned
+// counter block.
+struct MfScratch {
+  DevBuf area;
+  void* host = nullptr;
+  uint32_t seq = 0;
+  uint32_t pass_grid = 0, final_grid = 0;   // resident workgroups of its kernels
+};
+
 // Multi-source BC (msbc.hip): one group search's buffers and its pinned
 // counter block.
 struct MbScratch {
@@ -330,6 +339,14 @@ void free_flow_scratch(FlowScratch& s);
 dg_status dfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* disc, int32_t* parent, uint32_t* n_reached,
                   hipStream_t s);
 void free_dfs_scratch(DfsScratch& s);
+
+// msbfs.hip: up to ms_bfs_width() BFS queries of one snapshot e (sources
+// srcs, outputs outs[i], int32 hop distances, -1 unreached) as one
+// multi-source BFS on stream s; adds the visible arcs examined to *arcs_out.
+uint32_t ms_bfs_width();
+dg_status ms_bfs_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const uint32_t* srcs, uint32_t k,
+                     void* const* outs, uint32_t chunk_buckets, MfScratch& mf, hipStream_t s, uint64_t* arcs_out);
+void free_mf_scratch(MfScratch& mf);
 
 // msssp.hip: up to ms_sssp_width() SSSP queries of one snapshot e (sources
 // srcs[0..k), device outputs outs[0..k), host arrays) as one delta-stepping
