@@ -1506,6 +1506,13 @@ extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, 
   uint64_t rs = 0x243f6a8885a308d3ull ^ seed;
   std::vector<uint32_t> src(4);
   for (auto& x : src) x = cand[pick_u32(rs) % cand.size()];
+  // the batched call's sample: 64 distinct sources, each a BFS and an SSSP
+  // query, so the searches have the widths they have in real batches
+  std::vector<uint32_t> bsrc;
+  for (uint32_t t = 0; t < 4 * 64 && bsrc.size() < std::min<size_t>(64, cand.size()); t++) {
+    const uint32_t x = cand[pick_u32(rs) % cand.size()];
+    if (std::find(bsrc.begin(), bsrc.end(), x) == bsrc.end()) bsrc.push_back(x);
+  }
   auto time_queries = [&](int kind) -> double {
     auto t0 = std::chrono::steady_clock::now();
     for (uint32_t x : src) {
@@ -1515,12 +1522,12 @@ extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, 
     hipStreamSynchronize(s);
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
-  std::vector<DevBuf> outs(32);
+  std::vector<DevBuf> outs(2 * bsrc.size());
   auto time_batch = [&]() -> double {
     std::vector<dg_query> qs;
-    for (uint32_t i = 0; i < 32; i++) {
+    for (uint32_t i = 0; i < outs.size(); i++) {
       if (ensure(outs[i], V * 4ull) != hipSuccess) return 1e30;
-      qs.push_back(dg_query{i % 2 ? (uint32_t)DG_Q_SSSP : (uint32_t)DG_Q_BFS, src[i % src.size()], e, 0, nullptr,
+      qs.push_back(dg_query{i % 2 ? (uint32_t)DG_Q_SSSP : (uint32_t)DG_Q_BFS, bsrc[i / 2], e, 0, nullptr,
                             outs[i].p});
     }
     std::vector<dg_status> qst(qs.size());
@@ -1553,7 +1560,7 @@ extern "C" dg_status dg_autotune(dg_graph* g, uint32_t seed, dg_tuning* chosen, 
   try_field(&dg_tuning::alpha, {4, 14, 40, 1000000}, 0);
   try_field(&dg_tuning::beta, {8, 24, 64}, 0);
   try_field(&dg_tuning::sssp_delta, {16, 32, 64, 128, 256, 512}, 1);
-  try_field(&dg_tuning::batch_delta, {8, 16, 32, 64, 128, 256, 512, 1024}, 2);
+  try_field(&dg_tuning::batch_delta, {64, 128, 256, 512, 1024, 2048}, 2);
   try_field(&dg_tuning::batch_groups, {0, 4, 8, 16, 32}, 2);
   release(deg);
   release(d0);

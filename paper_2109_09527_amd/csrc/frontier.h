@@ -1148,28 +1148,6 @@ __device__ __forceinline__ void msbfs_chunk(const MsArgs& a, uint32_t c, uint32_
   }
 }
 
-// Touched vertices touched[base .. base + 64) of level `lvl` (the levels
-// reached are lvl + 1); outs[q] is query q's distance array.
-__device__ __forceinline__ void msbfs_final_block(const uint32_t* touched, uint32_t n, uint32_t base,
-                                                  unsigned long long* fr, unsigned long long* vn,
-                                                  int32_t* const* outs, int32_t lvl) {
-  const uint32_t i = base + lane_id();
-  if (i >= n) return;
-  const uint32_t v = touched[i];
-  ulonglong2* rec = reinterpret_cast<ulonglong2*>(&vn[2 * (uint64_t)v]);
-  ulonglong2 r = *rec;
-  unsigned long long nw = r.y & ~r.x;
-  r.x |= nw;
-  r.y = 0ull;
-  *rec = r;
-  fr[v] = nw;
-  while (nw) {
-    const int b = __ffsll((long long)nw) - 1;
-    nw &= nw - 1;
-    outs[b][v] = lvl + 1;
-  }
-}
-
 // ------------------------------------------------- BC backward tiles
 //
 // The dependency of v at level L (Brandes' backward recurrence):

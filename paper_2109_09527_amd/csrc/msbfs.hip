@@ -8,9 +8,13 @@
 // arc (u, v) it ORs fr[u] & ~visited[v] into v's next mask, and the first
 // bit set lists v as touched and queues its slab for the next level.  The
 // level's finish (`k_mf_final`) moves each touched vertex's new bits into
-// its visited mask and frontier mask and writes the level into each new
-// query's distance array.  Query q's distance at v is the first level at
-// which q's bit reaches v, which is its BFS hop distance.
+// its visited mask and frontier mask and records the level of each new
+// query in the vertex's 64-byte level record (one line per vertex, one byte
+// per query); `k_mf_extract` then writes every query's distance array in
+// coalesced runs.  Query q's distance at v is the first level at which q's
+// bit reaches v, which is its BFS hop distance.  Levels from MF_DIRECT on
+// do not fit a byte: they go straight to the output, and the record marks
+// the entry as written.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -23,30 +27,28 @@ namespace dg {
 namespace {
 
 constexpr uint32_t MFQ = 64;
+constexpr uint8_t MF_UNREACHED = 0xFF;
+constexpr uint8_t MF_WRITTEN = 0xFE;   // the level went to the output directly
+constexpr int32_t MF_DIRECT = 0xFE;    // levels >= this are written directly
 
 struct MfHost {
   QCounters c;
   uint32_t seq;
 };
 
-__global__ void k_mf_init(unsigned long long* vn, unsigned long long* fr, uint64_t V, QCounters* cnt) {
+__global__ void k_mf_init(unsigned long long* vn, unsigned long long* fr, uint4* lev, uint64_t V, QCounters* cnt) {
+  const uint4 un = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += (uint64_t)gridDim.x * blockDim.x) {
     reinterpret_cast<ulonglong2*>(vn)[i] = make_ulonglong2(0ull, 0ull);
     fr[i] = 0ull;
+    for (int k = 0; k < 4; k++) lev[4 * i + k] = un;
   }
   if (blockIdx.x == 0 && threadIdx.x < 3) zero_counters(&cnt[threadIdx.x]);
 }
 
-// outs[blockIdx.y][v] = -1 (unreached until a level reaches it).
-__global__ void k_mf_fill(int32_t* const* outs, uint64_t V) {
-  int32_t* o = outs[blockIdx.y];
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (uint64_t)gridDim.x * blockDim.x)
-    o[v] = -1;
-}
-
 // Level 0: query q's bit at its source, distance 0; one frontier item per
 // distinct source (one wave).
-__global__ void k_mf_seed(MsArgs a, unsigned long long* frm, const uint32_t* srcs, uint32_t k, int32_t* const* outs) {
+__global__ void k_mf_seed(MsArgs a, unsigned long long* frm, const uint32_t* srcs, uint32_t k, uint8_t* lev) {
   __shared__ Shared sh;
   const uint32_t q = lane_id();
   bool first = false;
@@ -56,7 +58,7 @@ __global__ void k_mf_seed(MsArgs a, unsigned long long* frm, const uint32_t* src
     const unsigned long long bit = 1ull << q;
     first = atomicOr(&a.vn[2 * (uint64_t)v], bit) == 0ull;
     atomicOr(&frm[v], bit);
-    outs[q][v] = 0;
+    lev[(uint64_t)v * MFQ + q] = 0;
   }
   ItemQ qn = item_q(sh.ws[0], 0, WSTAGE);
   push_item(qn, first, v, first ? a.st.fdesc[v] : 0);
@@ -80,13 +82,55 @@ __global__ __launch_bounds__(Q_THREADS) void k_mf_pass(MsArgs a, unsigned long l
   lc.commit(a.cnt_out, sh);
 }
 
-// The level's touched vertices (64 per wave round), levels written as lvl + 1.
-__global__ __launch_bounds__(Q_THREADS) void k_mf_final(MsArgs a, unsigned long long* frm, int32_t* const* outs,
-                                                        int32_t lvl, uint32_t touched_cap) {
+// One lane per touched vertex of the level: its new bits move into its
+// visited mask and become its frontier mask, and each new query's level
+// (lvl + 1) goes into the vertex's level record.
+__global__ __launch_bounds__(Q_THREADS) void k_mf_final(MsArgs a, unsigned long long* frm, uint8_t* lev,
+                                                        int32_t* const* outs, int32_t lvl, uint32_t touched_cap) {
   const uint32_t n = min(a.cnt_out->n_far, touched_cap);
-  const uint32_t stride = gridDim.x * Q_THREADS;
-  for (uint32_t base = blockIdx.x * Q_THREADS + (threadIdx.x & ~63u); base < n; base += stride)
-    msbfs_final_block(a.touched, n, base, frm, a.vn, outs, lvl);
+  const int32_t L = lvl + 1;
+  for (uint32_t i = blockIdx.x * Q_THREADS + threadIdx.x; i < n; i += gridDim.x * Q_THREADS) {
+    const uint32_t v = a.touched[i];
+    ulonglong2* rec = reinterpret_cast<ulonglong2*>(&a.vn[2 * (uint64_t)v]);
+    ulonglong2 r = *rec;
+    unsigned long long nw = r.y & ~r.x;
+    r.x |= nw;
+    r.y = 0ull;
+    *rec = r;
+    frm[v] = nw;
+    while (nw) {
+      const int b = __ffsll((long long)nw) - 1;
+      nw &= nw - 1;
+      if (L < MF_DIRECT) {
+        lev[(uint64_t)v * MFQ + b] = (uint8_t)L;
+      } else {
+        outs[b][v] = L;
+        lev[(uint64_t)v * MFQ + b] = MF_WRITTEN;
+      }
+    }
+  }
+}
+
+// Every query's distances from the level records: a block reads 64
+// vertices' records in order (4 KiB) into LDS and writes each query's 64
+// distances as one coalesced run (-1 unreached; entries already written
+// directly are left alone).
+__global__ __launch_bounds__(256) void k_mf_extract(const uint8_t* lev, uint64_t V, int32_t* const* outs, uint32_t k) {
+  __shared__ uint8_t t[64][MFQ + 4];
+  for (uint64_t v0 = (uint64_t)blockIdx.x * 64; v0 < V; v0 += (uint64_t)gridDim.x * 64) {
+    for (uint32_t i = threadIdx.x; i < 64 * MFQ / 4; i += 256) {
+      const uint32_t r = i / (MFQ / 4), c = i % (MFQ / 4);
+      const uint32_t x = v0 + r < V ? reinterpret_cast<const uint32_t*>(lev)[(v0 + r) * (MFQ / 4) + c] : 0xFFFFFFFFu;
+      *reinterpret_cast<uint32_t*>(&t[r][4 * c]) = x;
+    }
+    __syncthreads();
+    const uint32_t r = threadIdx.x & 63;
+    for (uint32_t q = threadIdx.x >> 6; q < k; q += 4) {
+      const uint8_t x = t[r][q];
+      if (v0 + r < V && x != MF_WRITTEN) outs[q][v0 + r] = x == MF_UNREACHED ? -1 : (int32_t)x;
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void k_mf_publish(const QCounters* c, MfHost* h, uint32_t seq) {
@@ -100,6 +144,7 @@ uint64_t mf_al(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct MfLayout {
   unsigned long long *vn, *fr;
+  uint8_t* lev;             // per vertex one level byte per query
   uint32_t* touched;
   uint32_t touched_cap;
   Item* q[2];
@@ -123,6 +168,7 @@ uint64_t mf_layout(const Store& st, char* base, MfLayout* P) {
   char* p;
   p = take(V * 16); if (P) P->vn = reinterpret_cast<unsigned long long*>(p);
   p = take(V * 8); if (P) P->fr = reinterpret_cast<unsigned long long*>(p);
+  p = take(V * MFQ); if (P) P->lev = reinterpret_cast<uint8_t*>(p);
   p = take(items * 4); if (P) { P->touched = reinterpret_cast<uint32_t*>(p); P->touched_cap = (uint32_t)std::min<uint64_t>(items, 0xFFFFFFFFu); }
   for (int i = 0; i < 2; i++) { p = take(items * sizeof(Item)); if (P) P->q[i] = reinterpret_cast<Item*>(p); }
   for (int i = 0; i < 2; i++) { p = take(chunks * 4); if (P) P->cmap[i] = reinterpret_cast<uint32_t*>(p); }
@@ -188,10 +234,10 @@ dg_status ms_bfs_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const u
   if ((he = hipMemcpyAsync(P.srcs, srcs, k * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (he = hipMemcpyAsync(P.outs, outs, k * sizeof(void*), hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail(DG_E_HIP, std::string("upload: ") + hipGetErrorString(he));
-  k_mf_init<<<(uint32_t)std::min<uint64_t>((V + 255) / 256, 4096), 256, 0, s>>>(P.vn, P.fr, V, P.cnt);
-  k_mf_fill<<<dim3((uint32_t)std::min<uint64_t>((V + 255) / 256, 1024), k), 256, 0, s>>>(P.outs, V);
+  k_mf_init<<<(uint32_t)std::min<uint64_t>((V + 255) / 256, 4096), 256, 0, s>>>(P.vn, P.fr,
+                                                                               reinterpret_cast<uint4*>(P.lev), V, P.cnt);
   MsArgs a0{st, e, fast, fr[1], fr[0], P.fr, P.vn, P.touched, &P.cnt[0]};
-  k_mf_seed<<<1, 64, 0, s>>>(a0, P.fr, P.srcs, k, P.outs);
+  k_mf_seed<<<1, 64, 0, s>>>(a0, P.fr, P.srcs, k, P.lev);
   MfHost* h = static_cast<MfHost*>(mf.host);
   auto read = [&](QCounters* c, QCounters* out) -> hipError_t {
     const uint32_t seq = ++mf.seq;
@@ -226,13 +272,15 @@ dg_status ms_bfs_dev(dg_graph* g, const Store& st, uint32_t e, int fast, const u
       ProfScope ps(g, KID_BATCH_BFS, s);
       k_mf_pass<<<grid, Q_THREADS, 0, s>>>(a, fq, &P.cnt[cur]);
     }
-    k_mf_final<<<mf.final_grid, Q_THREADS, 0, s>>>(a, P.fr, P.outs, lvl, P.touched_cap);
+    k_mf_final<<<mf.final_grid, Q_THREADS, 0, s>>>(a, P.fr, P.lev, P.outs, lvl, P.touched_cap);
     if ((he = hipGetLastError()) != hipSuccess || (he = read(&P.cnt[nxt], &hc)) != hipSuccess)
       return fail(DG_E_HIP, std::string("level: ") + hipGetErrorString(he));
     if (hc.overflow & OVF_QUEUE) return fail(DG_E_OUT_OF_MEMORY, "frontier queue capacity exceeded");
     arcs += hc.arcs;
     fq = hc.fq;
   }
+  k_mf_extract<<<(uint32_t)std::min<uint64_t>((V + 63) / 64, 8192), 256, 0, s>>>(P.lev, V, P.outs, k);
+  if ((he = hipGetLastError()) != hipSuccess) return fail(DG_E_HIP, std::string("extract: ") + hipGetErrorString(he));
   if (arcs_out) *arcs_out += arcs;
   return DG_OK;
 }

@@ -254,3 +254,32 @@ def test_multi_source_bc_overflow(dg):
     st = g.query_batch([(dg.Q_BC, g.epoch, [0, 3, 6, 9], o1), (dg.Q_BC, g.epoch, [3, 6, 9, 12], o2)])
     assert st[0] == dg.E_OVERFLOW
     assert st[1] == g.try_bc([3, 6, 9, 12])[0]
+
+
+def test_multi_source_bfs_deep_levels(dg):
+    """A directed path of 700 vertices plus a few shortcuts: a group of 6
+    BFS queries reaches levels above 253, which no longer fit the group's
+    one-byte level records and go to the outputs directly.  Every output
+    equals the plain call and the oracle."""
+    n = 700
+    us = list(range(n - 1)) + [10, 300, 50]
+    vs = list(range(1, n)) + [20, 320, 400]
+    ops = synth.make_ops(np.array([synth.ADDV] * n + [synth.ADDE] * len(us), np.uint32),
+                         np.array(list(range(n)) + us, np.uint32), np.array([0] * n + vs, np.uint32),
+                         np.array([0] * n + [1] * len(us), np.int32))
+    o = Oracle(n, w_max=1)
+    g = dg.Graph(n, w_max=1)
+    o.apply(ops)
+    g.apply(ops)
+    srcs = [0, 1, 2, 5, 30, 400]
+    outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in srcs]
+    st = g.query_batch([(dg.Q_BFS, g.epoch, s, out) for s, out in zip(srcs, outs)])
+    assert st == [0] * len(srcs)
+    deepest = 0
+    for s, out in zip(srcs, outs):
+        got = out.cpu().numpy()
+        want = o.bfs(s)[1]
+        assert np.array_equal(got, want), s
+        assert np.array_equal(got, g.bfs(s).cpu().numpy()), s
+        deepest = max(deepest, int(got.max()))
+    assert deepest > 300, deepest
