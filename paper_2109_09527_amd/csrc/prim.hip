@@ -4,6 +4,7 @@
 // Radix sort, per digit pass (Satish, Harris & Garland, IPDPS 2009 layout):
 //   k_rs_hist    per 2048-key tile, digit histogram -> hist[digit][tile]
 //   scan         exclusive scan of hist in digit-major order -> global offsets
+//                (up to 64 tiles, the scatter sums its own offsets instead)
 //   k_rs_scatter per tile, stable rank of each key among equal digits of the
 //                tile (wave ballots on the 8 digit bits give the lanes sharing
 //                a digit; per-wave counts combine in wave order through LDS),
@@ -141,14 +142,36 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* keys, ui
   hist[(uint64_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
 }
 
+// Up to this many tiles, the scatter computes its tile's offsets from the
+// histograms itself (a row of at most RS_FUSED_TILES counts per digit, then
+// a workgroup scan of the digit totals) and the pass needs no scan launch.
+constexpr uint32_t RS_FUSED_TILES = 64;
+
+// offs: the scanned histograms, or, when `scanned` is false, the histograms
+// themselves (ntile <= RS_FUSED_TILES).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
                                                            uint64_t* kout, uint32_t* vout, uint32_t n,
-                                                           int shift, const uint32_t* offs, uint32_t ntile) {
+                                                           int shift, const uint32_t* offs, uint32_t ntile,
+                                                           int scanned) {
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[RS_WAVES][256];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  gbase[tid] = offs[(uint64_t)tid * ntile + blockIdx.x];
+  if (scanned) {
+    gbase[tid] = offs[(uint64_t)tid * ntile + blockIdx.x];
+  } else {
+    // digit tid: its count in the tiles before this one and in all tiles
+    const uint32_t* row = offs + (uint64_t)tid * ntile;
+    uint32_t before = 0, total = 0;
+#pragma unroll 8
+    for (uint32_t t = 0; t < ntile; t++) {
+      const uint32_t h = row[t];
+      before += t < blockIdx.x ? h : 0u;
+      total += h;
+    }
+    uint32_t all;
+    gbase[tid] = block_exclusive_scan(total, &all) + before;
+  }
   run[tid] = 0;
   const unsigned long long lt = (1ull << lane) - 1ull;
   uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
@@ -208,8 +231,9 @@ bool radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, ui
     uint64_t* ko = alt ? k0 : k1;
     uint32_t* vo = alt ? v0 : v1;
     k_rs_hist<<<ntile, RS_THREADS, 0, s>>>(ki, n, shift, hist, ntile);
-    exclusive_scan_u32(hist, 256ull * ntile, scan_tmp, s);
-    k_rs_scatter<<<ntile, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, ntile);
+    const bool fused = ntile <= RS_FUSED_TILES;
+    if (!fused) exclusive_scan_u32(hist, 256ull * ntile, scan_tmp, s);
+    k_rs_scatter<<<ntile, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, ntile, fused ? 0 : 1);
     alt = !alt;
   }
   return alt;

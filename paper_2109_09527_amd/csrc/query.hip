@@ -36,6 +36,109 @@ constexpr uint32_t BIG_GRID = 2048;
 
 // --------------------------------------------------------------- fills
 
+// Layout of q.counters: four counter slots, the finished-workgroup count of
+// the running step (DONE_OFF), then (from STRIPE_OFF) the N_STRIPES count
+// stripes of each slot.
+constexpr size_t DONE_OFF = 192;
+constexpr size_t STRIPE_OFF = 256;
+constexpr size_t COUNTERS_BYTES = STRIPE_OFF + 4 * N_STRIPES * sizeof(CountStripe);
+static_assert(4 * sizeof(QCounters) <= DONE_OFF, "counter slots overlap the done count");
+
+// What the device publishes to the host after a step: one slot's counters
+// with its stripes added in, the running bucket record count, and the
+// sequence number that marks the publication complete.
+struct HostCounters {
+  QCounters c;
+  uint32_t rc;
+  uint32_t seq;
+};
+
+// One publication: the counters of `slot` go to h with sequence number seq.
+// A step kernel given a PubArgs with h set publishes from its last
+// workgroup to finish; h null: the step publishes nothing.
+struct PubArgs {
+  const QCounters* cnt;
+  const CountStripe* st;   // the stripes of all four slots, slot-major
+  uint32_t* done;          // zero between steps
+  HostCounters* h;
+  int slot;
+  uint32_t seq;
+};
+
+// One lane: writes the counters r and the running record count rc, then the
+// sequence number with a system-scope release, which makes the two writes
+// before it visible first.
+__device__ inline void publish_write(const PubArgs& p, const QCounters& r, uint32_t rc) {
+  p.h->c = r;
+  p.h->rc = rc;
+  __hip_atomic_store(&p.h->seq, p.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// A counter word as the device-scope atomics left it (a plain load could
+// hit a line this workgroup's cache still holds from earlier in the step).
+template <class T>
+__device__ inline T ld_coherent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave (lanes 0..63): sums the slot's stripes into its counters and
+// writes the result to h, the sequence number last (system scope), so the
+// host can wait by polling instead of synchronising the stream.
+__device__ inline void publish_wave(const PubArgs& p) {
+  const uint32_t lane = threadIdx.x;
+  unsigned long long m = 0, arcs = 0;
+  uint32_t verts = 0, far = 0;
+  if (lane < N_STRIPES) {
+    const CountStripe* x = p.st + (size_t)p.slot * N_STRIPES + lane;
+    m = ld_coherent(&x->m);
+    arcs = ld_coherent(&x->arcs);
+    verts = ld_coherent(&x->verts);
+    far = ld_coherent(&x->far);
+  }
+  m = wave_sum_u64(m);
+  arcs = wave_sum_u64(arcs);
+  verts = wave_sum_u32(verts);
+  far = wave_sum_u32(far);
+  if (lane != 0) return;
+  const QCounters* c = p.cnt + p.slot;
+  QCounters r;
+  r.fq = ld_coherent(&c->fq);
+  r.n_verts = ld_coherent(&c->n_verts) + verts;
+  r.n_far = ld_coherent(&c->n_far) + far;
+  r.m_next = ld_coherent(&c->m_next) + m;
+  r.far_min = ld_coherent(&c->far_min);
+  r.overflow = ld_coherent(&c->overflow);
+  r.n_order = ld_coherent(&c->n_order);
+  r.n_big = ld_coherent(&c->n_big);
+  r.arcs = ld_coherent(&c->arcs) + arcs;
+  publish_write(p, r, ld_coherent(&p.cnt[3].n_order));
+}
+
+// End of a step kernel (workgroup-uniform call): every workgroup counts
+// itself done once its waves' memory operations have completed, and the
+// last one publishes.  The step's counters change only through device-scope
+// atomics, which are performed at the device's coherent level, so waiting
+// for completion (no cache write-back or invalidation, which an agent-scope
+// fence would cost every workgroup) orders them before the count.  No
+// workgroup waits for another, and the last clears the count for the next
+// step.  A separate publishing launch per step had cost its own dispatch on
+// every level's host round trip.
+__device__ inline void publish_if_last(const PubArgs& p) {
+  if (!p.h) return;
+  __shared__ uint32_t last;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);   // vmcnt, expcnt and lgkmcnt all zero
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(p.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x * gridDim.y;
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  publish_wave(p);
+  if (threadIdx.x == 0) __hip_atomic_store(p.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_publish(PubArgs p) { publish_wave(p); }
+
 template <class T>
 __global__ void k_fill(T* p, uint64_t n, T v) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -53,7 +156,7 @@ static void fill(T* p, uint64_t n, T v, hipStream_t s) {
 // bitmap bit; counters slot 0 describes the seed frontier, slot 1 is
 // cleared.  One wave.
 __global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Front f, uint32_t* bm, QCounters* cnt,
-                       uint32_t* order) {
+                       uint32_t* order, PubArgs pub) {
   const uint64_t desc = st.fdesc[src];
   const uint32_t nb = desc ? 1u << (desc & 63) : 0;
   const uint32_t nc = (nb + (1u << f.lch) - 1) >> f.lch;
@@ -71,6 +174,8 @@ __global__ void k_seed(Store st, uint32_t src, int32_t* dist, int32_t d0, Front 
   c0.far_min = DIST_INF;
   cnt[0] = c0;
   zero_counters(&cnt[1]);
+  // the seed frontier's counts are c0 (slot 0's stripes are clear)
+  if (pub.h) publish_write(pub, c0, cnt[3].n_order);
 }
 
 __device__ inline void reset_other(QCounters* c) {
@@ -90,10 +195,11 @@ __device__ inline void reset_other(QCounters* c, CountStripe* st) {
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_td(LevelArgs a, unsigned long long nfq, QCounters* reset,
-                                                       CountStripe* reset_st) {
+                                                       CountStripe* reset_st, PubArgs pub) {
   __shared__ Shared sh;
   reset_other(reset, reset_st);
   td_step(a, nfq, blockIdx.x, gridDim.x, sh);
+  publish_if_last(pub);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* reset, CountStripe* reset_st) {
@@ -102,30 +208,35 @@ __global__ __launch_bounds__(Q_THREADS) void k_bfs_bu(LevelArgs a, QCounters* re
   bu_step(a, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a) {
+__global__ __launch_bounds__(Q_THREADS) void k_bfs_bu_big(LevelArgs a, PubArgs pub) {
   __shared__ Shared sh;
   bu_big_step(a, a.cnt_out->n_big, blockIdx.x, gridDim.x, sh);
+  publish_if_last(pub);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_relax(RelaxArgs a, unsigned long long nfq, QCounters* reset,
-                                                           CountStripe* reset_st) {
+                                                           CountStripe* reset_st, PubArgs pub) {
   __shared__ Shared sh;
   reset_other(reset, reset_st);
   relax_step(a, nfq, blockIdx.x, gridDim.x, sh);
+  publish_if_last(pub);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_sssp_expand(Store st, const uint32_t* list, uint32_t n, Front fout,
                                                             QCounters* cnt_out, QCounters* reset,
-                                                            CountStripe* reset_st) {
+                                                            CountStripe* reset_st, PubArgs pub) {
   __shared__ Shared sh;
   reset_other(reset, reset_st);
   expand_step(st, list, n, fout, cnt_out, blockIdx.x, gridDim.x, sh);
+  publish_if_last(pub);
 }
 
-__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, QCounters* reset, CountStripe* reset_st) {
+__global__ __launch_bounds__(Q_THREADS) void k_sssp_split(SplitArgs a, QCounters* reset, CountStripe* reset_st,
+                                                           PubArgs pub) {
   __shared__ Shared sh;
   reset_other(reset, reset_st);
   split_step(a, blockIdx.x, gridDim.x, sh);
+  publish_if_last(pub);
 }
 
 __global__ __launch_bounds__(Q_THREADS) void k_bc_fwd(BcFwdArgs a, unsigned long long nfq, QCounters* reset) {
@@ -167,51 +278,6 @@ static Front front_of(const QueryScratch& q, int which) {
   const DevBuf& cmap = which ? q.cmap_b : q.cmap_a;
   return Front{items.as<Item>(), cmap.as<uint32_t>(), (uint32_t)std::min<uint64_t>(q.items_cap, 0xFFFFFFFFu),
                (uint32_t)std::min<uint64_t>(q.chunks_cap, 0xFFFFFFFFu), q.lch};
-}
-
-// Layout of q.counters: four counter slots, then (from STRIPE_OFF) the
-// N_STRIPES count stripes of each slot.
-constexpr size_t STRIPE_OFF = 256;
-constexpr size_t COUNTERS_BYTES = STRIPE_OFF + 4 * N_STRIPES * sizeof(CountStripe);
-static_assert(4 * sizeof(QCounters) <= STRIPE_OFF, "counter slots overlap their stripes");
-
-// What the device publishes to the host after a step: one slot's counters
-// with its stripes added in, the running bucket record count, and the
-// sequence number that marks the publication complete.
-struct HostCounters {
-  QCounters c;
-  uint32_t rc;
-  uint32_t seq;
-};
-
-// One wave: sums slot's stripes into its counters and writes the result to
-// pinned host memory, the sequence number last (system scope), so the host
-// can wait by polling instead of synchronising the stream.
-__global__ void k_publish(const QCounters* cnt, const CountStripe* st, int slot, HostCounters* h, uint32_t seq) {
-  const uint32_t lane = threadIdx.x;
-  unsigned long long m = 0, arcs = 0;
-  uint32_t verts = 0, far = 0;
-  if (lane < N_STRIPES) {
-    const CountStripe* x = st + (size_t)slot * N_STRIPES + lane;
-    m = x->m;
-    arcs = x->arcs;
-    verts = x->verts;
-    far = x->far;
-  }
-  m = wave_sum_u64(m);
-  arcs = wave_sum_u64(arcs);
-  verts = wave_sum_u32(verts);
-  far = wave_sum_u32(far);
-  if (lane != 0) return;
-  QCounters r = cnt[slot];
-  r.m_next += m;
-  r.arcs += arcs;
-  r.n_verts += verts;
-  r.n_far += far;
-  h->c = r;
-  h->rc = cnt[3].n_order;
-  __threadfence_system();
-  __hip_atomic_store(&h->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Bytes of each plain-query buffer for this graph (0 = not needed by the
@@ -328,45 +394,65 @@ static CountStripe* stripes_of(QueryScratch& q, int slot) {
   return reinterpret_cast<CountStripe*>(q.counters.as<char>() + STRIPE_OFF) + (size_t)slot * N_STRIPES;
 }
 
-// Counters of one slot with its stripes added in, plus the running bucket
-// record count (slot 3): a one-wave kernel publishes them to pinned host
-// memory, and the host polls for its sequence number (a stream
+static uint32_t* done_of(QueryScratch& q) { return reinterpret_cast<uint32_t*>(q.counters.as<char>() + DONE_OFF); }
+
+// Zero the step's done count and every slot's stripes (one fill).
+static void clear_counts(QueryScratch& q, hipStream_t s) {
+  fill<uint32_t>(done_of(q), (COUNTERS_BYTES - DONE_OFF) / 4, 0u, s);
+}
+
+// The next publication of slot's counters (with its stripes added in, plus
+// the running bucket record count of slot 3): to pinned host memory, or,
+// for a fixed area, which has no pinned block, to its device word.
+static PubArgs pub_args(QueryScratch& q, int slot) {
+  HostCounters* h = static_cast<HostCounters*>(q.fixed ? q.dev_pub : q.host_pub);
+  return PubArgs{q.counters.as<QCounters>(), stripes_of(q, 0), done_of(q), h, slot, ++q.pub_seq};
+}
+
+// Wait for publication p: the host polls its sequence number (a stream
 // synchronisation costs more than the step it follows when steps are
-// short).  A publication not seen within two seconds falls back to
-// synchronising the stream, which reports any device error.
-static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
-  const uint32_t seq = ++q.pub_seq;
+// short); one not seen within two seconds falls back to synchronising the
+// stream, which reports any device error.  A fixed area's publication is
+// copied back after the stream has drained.
+static hipError_t await_counters(QueryScratch& q, const PubArgs& p, QCounters* out, uint32_t* rc, hipStream_t s) {
   hipError_t e;
   if (q.fixed) {
-    // a fixed area has no pinned host block: publish on the device, copy
-    // back and wait for the stream
-    HostCounters* d = static_cast<HostCounters*>(q.dev_pub);
-    k_publish<<<1, 64, 0, s>>>(q.counters.as<QCounters>(), stripes_of(q, 0), slot, d, seq);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     HostCounters hc;
-    if ((e = hipMemcpyAsync(&hc, d, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&hc, p.h, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    if (hc.seq != seq) return hipErrorUnknown;
+    if (hc.seq != p.seq) return hipErrorUnknown;
     *out = hc.c;
     *rc = hc.rc;
     return hipSuccess;
   }
-  HostCounters* h = static_cast<HostCounters*>(q.host_pub);
-  k_publish<<<1, 64, 0, s>>>(q.counters.as<QCounters>(), stripes_of(q, 0), slot, h, seq);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const HostCounters* h = p.h;
   const auto t0 = std::chrono::steady_clock::now();
-  for (uint32_t spin = 1; __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq; spin++) {
+  for (uint32_t spin = 1; __atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != p.seq; spin++) {
     host_pause(spin);
     if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-      if (__atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
+      if (__atomic_load_n(&h->seq, __ATOMIC_ACQUIRE) != p.seq) return hipErrorUnknown;
       break;
     }
   }
   std::memcpy(out, &h->c, sizeof(QCounters));
   *rc = h->rc;
   return hipSuccess;
+}
+
+// The counters of a slot filled by steps that do not publish themselves:
+// a one-wave kernel publishes them.
+static hipError_t read_counters_rc(QueryScratch& q, int slot, QCounters* out, uint32_t* rc, hipStream_t s) {
+  const PubArgs p = pub_args(q, slot);
+  k_publish<<<1, 64, 0, s>>>(p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return await_counters(q, p, out, rc, s);
+}
+
+static hipError_t await_counters(QueryScratch& q, const PubArgs& p, QCounters* out, hipStream_t s) {
+  uint32_t rc;
+  return await_counters(q, p, out, &rc, s);
 }
 
 static hipError_t read_counters(QueryScratch& q, int slot, QCounters* out, hipStream_t s) {
@@ -432,11 +518,12 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
   uint32_t* bm[2] = {q.bm0.as<uint32_t>(), q.bm1.as<uint32_t>()};
   QCounters* cnt = q.counters.as<QCounters>();
   fill<int32_t>(dist, V, -1, s);
-  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
+  clear_counts(q, s);
   fill<uint32_t>(bm[0], bmw, 0u, s);
-  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], bm[0], cnt, nullptr);
+  PubArgs pub = pub_args(q, 0);
+  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], bm[0], cnt, nullptr, pub);
   QCounters hc;
-  if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs seed");
+  if ((he = await_counters(q, pub, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs seed");
   int64_t m_u = (int64_t)arcs_at(g, e);
   const uint64_t n_live = std::max<uint64_t>(1, live_at(g, e));
   bool bu = false;
@@ -452,6 +539,7 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
     fill<uint32_t>(bm[nxt], bmw, 0u, s);
     LevelArgs a{g->st, e, fast, fr[cur], fr[nxt], qbig, bm[cur], bm[nxt], dist, level + 1, cnt + nxt,
                 stripes_of(q, nxt)};
+    pub = pub_args(q, nxt);
     if (bu) {
       ProfScope ps(g, KID_BFS_BU, s);
       // half the resident workgroups: each workgroup's final counter commit
@@ -460,14 +548,14 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
       // half: 53 us; a quarter: 59; an eighth: 72)
       k_bfs_bu<<<grid_for(V, Q_THREADS, std::max<uint32_t>(1, resident((const void*)k_bfs_bu) / 2)), Q_THREADS, 0, s>>>(
           a, cnt + cur, stripes_of(q, cur));
-      k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a);
+      k_bfs_bu_big<<<std::min(BIG_GRID, resident((const void*)k_bfs_bu_big)), Q_THREADS, 0, s>>>(a, pub);
     } else {
       ProfScope ps(g, KID_BFS_TD, s);
       k_bfs_td<<<chunks_grid((const void*)k_bfs_td, fq, q.lch), Q_THREADS, 0, s>>>(a, fq, cnt + cur,
-                                                                                    stripes_of(q, cur));
+                                                                                    stripes_of(q, cur), pub);
     }
     if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "bfs level launch");
-    if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
+    if ((he = await_counters(q, pub, &hc, s)) != hipSuccess) return hip_fail(g, he, "bfs level");
     if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
     prof_arcs(g, bu ? KID_BFS_BU : KID_BFS_TD, hc.arcs);
     fq = hc.fq;
@@ -497,16 +585,17 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   QCounters* cnt = q.counters.as<QCounters>();
   uint32_t* rcount = &cnt[3].n_order;
   fill<int32_t>(dist, V, DIST_INF, s);
-  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
+  clear_counts(q, s);
   fill<uint32_t>(stamp, V, 0u, s);
   fill<uint32_t>(infar, V, 0u, s);
   if (split_lh) {
     fill<uint32_t>(rstamp, V, 0u, s);
     fill<uint32_t>(rcount, 1, 0u, s);
   }
-  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], nullptr, cnt, nullptr);
+  PubArgs pub = pub_args(q, 0);
+  k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], nullptr, cnt, nullptr, pub);
   QCounters hc;
-  if ((he = read_counters(q, 0, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp seed");
+  if ((he = await_counters(q, pub, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp seed");
   unsigned long long near = hc.fq;
   uint32_t n_far = 0;
   int32_t thr = delta;
@@ -520,14 +609,15 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
     // far entries found by this pass are appended after the current far list
     RelaxArgs a{g->st, e,     fast,  fr[qi], fr[qi ^ 1], dist,  stamp,  infar, thr,
                 it,    cnt + nxt, mode, delta,  rlist,      rcount, rstamp, phase, stripes_of(q, nxt)};
+    const PubArgs p = pub_args(q, nxt);
     {
       ProfScope ps(g, KID_SSSP_RELAX, s);
       k_sssp_relax<<<chunks_grid((const void*)k_sssp_relax, nfq, q.lch), Q_THREADS, 0, s>>>(a, nfq, cnt + slot,
-                                                                                            stripes_of(q, slot));
+                                                                                            stripes_of(q, slot), p);
     }
     hipError_t r = hipGetLastError();
     if (r != hipSuccess) return r;
-    if ((r = read_counters_rc(q, nxt, &hc, &n_rec, s)) != hipSuccess) return r;
+    if ((r = await_counters(q, p, &hc, &n_rec, s)) != hipSuccess) return r;
     ovf |= (hc.overflow & OVF_QUEUE) != 0;
     prof_arcs(g, KID_SSSP_RELAX, hc.arcs);
     near = hc.fq;
@@ -550,9 +640,10 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
         fill<uint32_t>(rcount, 1, 0u, s);
         n_rec = 0;
         int nxt = slot ^ 1;
+        pub = pub_args(q, nxt);
         k_sssp_expand<<<lanes_grid((const void*)k_sssp_expand, n_r), Q_THREADS, 0, s>>>(
-            g->st, rlist, n_r, fr[qi], cnt + nxt, cnt + slot, stripes_of(q, slot));
-        if ((he = hipGetLastError()) != hipSuccess || (he = read_counters(q, nxt, &hc, s)) != hipSuccess)
+            g->st, rlist, n_r, fr[qi], cnt + nxt, cnt + slot, stripes_of(q, slot), pub);
+        if ((he = hipGetLastError()) != hipSuccess || (he = await_counters(q, pub, &hc, s)) != hipSuccess)
           return hip_fail(g, he, "sssp expand");
         if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
         slot = nxt;
@@ -572,13 +663,14 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
                                 : (int32_t)std::min<int64_t>(DIST_INF, ((int64_t)far_min / delta + 1) * delta);
       int nxt = slot ^ 1;
       SplitArgs a{g->st, fr[qi], dist, stamp, infar, thr, it, cnt + nxt, stripes_of(q, nxt)};
+      pub = pub_args(q, nxt);
       {
         ProfScope ps(g, KID_SSSP_SPLIT, s);
         k_sssp_split<<<lanes_grid((const void*)k_sssp_split, V), Q_THREADS, 0, s>>>(a, cnt + slot,
-                                                                                    stripes_of(q, slot));
+                                                                                    stripes_of(q, slot), pub);
       }
       if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "sssp split launch");
-      if ((he = read_counters(q, nxt, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
+      if ((he = await_counters(q, pub, &hc, s)) != hipSuccess) return hip_fail(g, he, "sssp split");
       if (hc.overflow & OVF_QUEUE) return queue_overflow(g);
       slot = nxt;
       n_far = hc.n_far;
@@ -611,14 +703,14 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
   QCounters* tot = cnt + 2;
   const BwdTiles bt = bwd_tiles_at(q.bt.as<char>(), g->st.fp.cap, 1);
   fill<double>(bc, V, 0.0, s);
-  fill<uint32_t>(reinterpret_cast<uint32_t*>(stripes_of(q, 0)), 4 * N_STRIPES * sizeof(CountStripe) / 4, 0u, s);
+  clear_counts(q, s);
   fill<uint32_t>(reinterpret_cast<uint32_t*>(bt.head), sizeof(BwdHead) / 4, 0u, s);
   std::vector<uint32_t> off, nbig;
   for (uint32_t si = 0; si < k; si++) {
     uint32_t src = srcs[si];
     fill<int32_t>(level, V, -1, s);
     fill<unsigned long long>(sigma, V, 0ull, s);
-    k_seed<<<1, 64, 0, s>>>(g->st, src, level, 0, fr[0], nullptr, cnt, order);
+    k_seed<<<1, 64, 0, s>>>(g->st, src, level, 0, fr[0], nullptr, cnt, order, PubArgs{});
     fill<unsigned long long>(reinterpret_cast<unsigned long long*>(tot), sizeof(QCounters) / 8, 0ull, s);
     fill<unsigned long long>(sigma + src, 1, 1ull, s);
     fill<uint32_t>(&tot->n_order, 1, 1u, s);

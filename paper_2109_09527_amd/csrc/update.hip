@@ -88,10 +88,25 @@ struct VState {
   uint32_t lastrem;   // index of the last successful RemoveVertex, or NONE
 };
 
+// Filter of the vertices that have ops in the batch: one bit per hash of a
+// vertex in LDS, so an edge op on a vertex without vertex ops (nearly all of
+// them) takes its liveness from the store instead of a binary search of the
+// vertex ops, whose ten or more dependent loads dominated edge resolution.
+constexpr uint32_t VF_WORDS = 2048;          // 64 Kbit
+constexpr uint32_t VF_MAX_VERTS = 16384;     // larger vertex parts search every time
+__device__ inline uint32_t vf_hash(uint32_t x) { return (x * 0x9E3779B1u) >> 16; }
+__device__ inline bool vf_maybe(const uint32_t* vf, uint32_t x) {
+  if (!vf) return true;
+  const uint32_t h = vf_hash(x);
+  return (vf[h >> 5] >> (h & 31)) & 1u;
+}
+
 // State of vertex x just before op index i: the last vertex op on x with a
 // smaller index (sorted part [0, nv) is ordered by (vertex, index)).
 __device__ inline VState vstate(const uint64_t* keys, const uint32_t* vals, uint32_t nv, uint32_t L, uint32_t x,
-                                uint32_t i, const uint8_t* alive, const uint8_t* vafter, const uint32_t* vlastrem) {
+                                uint32_t i, const uint8_t* alive, const uint8_t* vafter, const uint32_t* vlastrem,
+                                const uint32_t* vf) {
+  if (!vf_maybe(vf, x)) return VState{alive[x], NONE};
   uint32_t lo = 0, hi = nv;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
@@ -156,7 +171,20 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
     uint8_t* results, const uint8_t* vafter, const uint32_t* vlastrem, uint8_t* recflags, int32_t* recw,
     uint32_t* touch_f, uint32_t* touch_r, uint32_t* insf, uint32_t* insr, UpdCounters* c) {
   if (c->flags) return;
-  uint32_t nv = c->nv;
+  const uint32_t nv = c->nv;
+  if (nv + blockIdx.x * UPD_THREADS >= n) return;   // workgroup-uniform
+  __shared__ uint32_t vf_lds[VF_WORDS];
+  const uint32_t* vf = nullptr;
+  if (nv <= VF_MAX_VERTS) {
+    for (uint32_t w = threadIdx.x; w < VF_WORDS; w += UPD_THREADS) vf_lds[w] = 0u;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nv; j += UPD_THREADS) {
+      const uint32_t h = vf_hash((uint32_t)(keys[j] >> L));
+      atomicOr(&vf_lds[h >> 5], 1u << (h & 31));
+    }
+    __syncthreads();
+    vf = vf_lds;
+  }
   uint32_t k = nv + blockIdx.x * UPD_THREADS + threadIdx.x;
   if (k >= n) return;
   uint64_t key = keys[k];
@@ -176,8 +204,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   for (uint32_t j = k; j < n && keys[j] == key; j++) {
     uint32_t i = vals[j];
     dg_op op = ops[i];
-    VState sa_ = vstate(keys, vals, nv, L, a, i, st.alive, vafter, vlastrem);
-    VState sb_ = vstate(keys, vals, nv, L, b, i, st.alive, vafter, vlastrem);
+    VState sa_ = vstate(keys, vals, nv, L, a, i, st.alive, vafter, vlastrem, vf);
+    VState sb_ = vstate(keys, vals, nv, L, b, i, st.alive, vafter, vlastrem, vf);
     int64_t tc = -1;
     if (sa_.lastrem != NONE) tc = sa_.lastrem;
     if (sb_.lastrem != NONE && (int64_t)sb_.lastrem > tc) tc = sb_.lastrem;
@@ -201,8 +229,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
     results[i] = r;
     last_pt = i;
   }
-  VState ea = vstate(keys, vals, nv, L, a, n, st.alive, vafter, vlastrem);
-  VState eb = vstate(keys, vals, nv, L, b, n, st.alive, vafter, vlastrem);
+  VState ea = vstate(keys, vals, nv, L, a, n, st.alive, vafter, vlastrem, vf);
+  VState eb = vstate(keys, vals, nv, L, b, n, st.alive, vafter, vlastrem, vf);
   int64_t tce = -1;
   if (ea.lastrem != NONE) tce = ea.lastrem;
   if (eb.lastrem != NONE && (int64_t)eb.lastrem > tce) tce = eb.lastrem;

@@ -153,7 +153,7 @@ def test_autotune_keeps_results(dg):
     t = g.autotune(seed=1)
     assert t["chunk_buckets"] in (16, 32, 64)
     assert t["sssp_delta"] in (16, 32, 64, 128, 256, 512)
-    assert t["batch_delta"] in (8, 16, 32, 64, 128, 256, 512, 1024)
+    assert t["batch_delta"] in (64, 128, 256, 512, 1024, 2048)
     assert g.get_tuning() == t
     for s in synth.out_degree_sources(gr, 3, synth.rng_for(21, 2)):
         s = int(s)
