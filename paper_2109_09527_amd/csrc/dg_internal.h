@@ -145,6 +145,35 @@ struct SlotRef {
   uint32_t b;
 };
 
+// The 16 destination words of a bucket, read as one line (four 16-byte
+// loads issued together).  Slots are claimed in order and never released
+// while a slab is live, so the used slots always form a prefix of the
+// bucket; a copy read while other threads claim slots can only show EMPTY
+// for a slot claimed since, never a destination for an empty slot.
+__device__ inline void load_dsts(const uint32_t* bp, uint32_t d[BSLOTS]) {
+  const uint4* p = reinterpret_cast<const uint4*>(bp);
+#pragma unroll
+  for (int q = 0; q < BSLOTS / 4; q++) {
+    const uint4 v = p[q];
+    d[4 * q] = v.x;
+    d[4 * q + 1] = v.y;
+    d[4 * q + 2] = v.z;
+    d[4 * q + 3] = v.w;
+  }
+}
+
+// First EMPTY slot of a bucket copy (BSLOTS: none).
+__device__ inline int first_empty(const uint32_t d[BSLOTS]) {
+  int j0 = BSLOTS;
+#pragma unroll
+  for (int j = BSLOTS - 1; j >= 0; j--)
+    if (d[j] == EMPTY) j0 = j;
+  return j0;
+}
+
+// Every version of x already stored lies inside the prefix, so a copy that
+// misses slots claimed since it was read loses none of them; the death of
+// a matching slot is read fresh.
 __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
   SlotRef r{nullptr, -1, 0};
   if (s.nb == 0) return r;
@@ -152,16 +181,18 @@ __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
   uint32_t b = hmix(x) & mask;
   for (uint32_t probe = 0; probe < s.nb; probe++) {
     uint32_t* bp = bucket_ptr(s, b);
-    bool full = true;
-    for (int j = 0; j < BSLOTS; j++) {
-      uint32_t d = ld_relaxed(slot_dst(bp, j));
-      if (d == EMPTY) { full = false; break; }
-      if (d == x) {
-        uint32_t death = ld_relaxed(slot_death(bp, j, s.words));
-        if (death == INF_EPOCH) { r.bp = bp; r.j = j; r.b = b; return r; }
+    uint32_t d[BSLOTS];
+    load_dsts(bp, d);
+    const int used = first_empty(d);
+    for (int j = 0; j < used; j++) {
+      if (d[j] == x && ld_relaxed(slot_death(bp, j, s.words)) == INF_EPOCH) {
+        r.bp = bp;
+        r.j = j;
+        r.b = b;
+        return r;
       }
     }
-    if (!full) return r;
+    if (used < BSLOTS) return r;
     b = (b + 1) & mask;
   }
   return r;
@@ -170,22 +201,26 @@ __device__ inline SlotRef find_current(const Slab& s, uint32_t x) {
 // Claim a free slot for key x whose version is born at `birth` (capacity
 // is guaranteed by the growth step) and raise the bucket's largest-birth
 // summary.  Readers that trust the summary never run beside a writer, so
-// the two updates need no ordering between them.
+// the two updates need no ordering between them.  Slots before the first
+// EMPTY of a bucket copy are taken for good; from there each slot is tried
+// with a compare-and-swap, which fails on a slot claimed since the copy.
 __device__ inline SlotRef claim_slot(const Slab& s, uint32_t x, uint32_t birth) {
   SlotRef r{nullptr, -1, 0};
   uint32_t mask = s.nb - 1;
   uint32_t b = hmix(x) & mask;
   for (uint32_t probe = 0; probe < s.nb; probe++) {
     uint32_t* bp = bucket_ptr(s, b);
-    bool raised = false;
-    for (int j = 0; j < BSLOTS; j++) {
-      uint32_t* pd = slot_dst(bp, j);
-      if (ld_relaxed(pd) != EMPTY) continue;
-      if (!raised) {
-        atomicMax(&s.sum[SUM_WORDS * b], birth);
-        raised = true;
+    uint32_t d[BSLOTS];
+    load_dsts(bp, d);
+    const int j0 = first_empty(d);
+    if (j0 < BSLOTS) atomicMax(&s.sum[SUM_WORDS * b], birth);
+    for (int j = j0; j < BSLOTS; j++) {
+      if (atomicCAS(slot_dst(bp, j), EMPTY, x) == EMPTY) {
+        r.bp = bp;
+        r.j = j;
+        r.b = b;
+        return r;
       }
-      if (atomicCAS(pd, EMPTY, x) == EMPTY) { r.bp = bp; r.j = j; r.b = b; return r; }
     }
     b = (b + 1) & mask;
   }

@@ -103,10 +103,11 @@ __device__ inline bool vf_maybe(const uint32_t* vf, uint32_t x) {
 
 // State of vertex x just before op index i: the last vertex op on x with a
 // smaller index (sorted part [0, nv) is ordered by (vertex, index)).
+// alive_x: x's liveness at e (st.alive[x], loaded by the caller).
 __device__ inline VState vstate(const uint64_t* keys, const uint32_t* vals, uint32_t nv, uint32_t L, uint32_t x,
-                                uint32_t i, const uint8_t* alive, const uint8_t* vafter, const uint32_t* vlastrem,
+                                uint32_t i, uint8_t alive_x, const uint8_t* vafter, const uint32_t* vlastrem,
                                 const uint32_t* vf) {
-  if (!vf_maybe(vf, x)) return VState{alive[x], NONE};
+  if (!vf_maybe(vf, x)) return VState{alive_x, NONE};
   uint32_t lo = 0, hi = nv;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
@@ -115,7 +116,7 @@ __device__ inline VState vstate(const uint64_t* keys, const uint32_t* vals, uint
     else hi = mid;
   }
   if (lo > 0 && (uint32_t)(keys[lo - 1] >> L) == x) return VState{vafter[lo - 1], vlastrem[lo - 1]};
-  return VState{alive[x], NONE};
+  return VState{alive_x, NONE};
 }
 
 __global__ __launch_bounds__(UPD_THREADS) void k_resolve_vertex(const uint64_t* keys, const uint32_t* vals,
@@ -194,6 +195,9 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   }
   const uint64_t mask = (1ull << L) - 1;
   uint32_t a = (uint32_t)((key >> L) & mask), b = (uint32_t)(key & mask);
+  // loads that do not depend on the store probe go out first
+  const dg_op op0 = ops[vals[k]];
+  const uint8_t alive_a = st.alive[a], alive_b = st.alive[b];
   Slab sa = slab_of(st.fp, st.fdesc[a]);
   SlotRef ref = find_current(sa, b);
   bool present0 = ref.bp != nullptr;
@@ -203,9 +207,9 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   int64_t last_pt = -1;
   for (uint32_t j = k; j < n && keys[j] == key; j++) {
     uint32_t i = vals[j];
-    dg_op op = ops[i];
-    VState sa_ = vstate(keys, vals, nv, L, a, i, st.alive, vafter, vlastrem, vf);
-    VState sb_ = vstate(keys, vals, nv, L, b, i, st.alive, vafter, vlastrem, vf);
+    dg_op op = j == k ? op0 : ops[i];
+    VState sa_ = vstate(keys, vals, nv, L, a, i, alive_a, vafter, vlastrem, vf);
+    VState sb_ = vstate(keys, vals, nv, L, b, i, alive_b, vafter, vlastrem, vf);
     int64_t tc = -1;
     if (sa_.lastrem != NONE) tc = sa_.lastrem;
     if (sb_.lastrem != NONE && (int64_t)sb_.lastrem > tc) tc = sb_.lastrem;
@@ -229,8 +233,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
     results[i] = r;
     last_pt = i;
   }
-  VState ea = vstate(keys, vals, nv, L, a, n, st.alive, vafter, vlastrem, vf);
-  VState eb = vstate(keys, vals, nv, L, b, n, st.alive, vafter, vlastrem, vf);
+  VState ea = vstate(keys, vals, nv, L, a, n, alive_a, vafter, vlastrem, vf);
+  VState eb = vstate(keys, vals, nv, L, b, n, alive_b, vafter, vlastrem, vf);
   int64_t tce = -1;
   if (ea.lastrem != NONE) tce = ea.lastrem;
   if (eb.lastrem != NONE && (int64_t)eb.lastrem > tce) tce = eb.lastrem;
@@ -255,44 +259,53 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   }
 }
 
-// One wave per touched vertex: decide whether its slab must grow.
-// plan[k] = log2(new buckets) + 1, or 0 when the slab keeps its size.
+// One lane per touched vertex: decide whether its slab must grow.
+// plan[k] = log2(new buckets) + 1, or 0 when the slab keeps its size.  The
+// versions a growing slab keeps are counted by its whole wave, one growing
+// slab after another (growth is rare, so most waves count none); a wave per
+// touched vertex had left 63 lanes idle on nearly every vertex.
 __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint32_t* touch_f,
                                                             const uint32_t* touch_r, uint32_t* plan,
                                                             uint32_t* plan_ins, uint32_t* glist, uint32_t* insf,
                                                             uint32_t* insr, uint32_t floor_e,
                                                             UpdCounters* c) {
   if (c->flags) return;
-  const uint32_t nf = c->n_touch_f, nr = c->n_touch_r;
+  const uint32_t nf = c->n_touch_f, nt = nf + c->n_touch_r;
   const uint32_t lane = lane_id();
-  const uint32_t waves = gridDim.x * (UPD_THREADS / 64);
-  for (uint32_t k = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6); k < nf + nr; k += waves) {
-    bool fwd = k < nf;
-    uint32_t x = fwd ? touch_f[k] : touch_r[k - nf];
-    uint32_t* insa = fwd ? insf : insr;
-    uint32_t* useda = fwd ? st.fused : st.rused;
-    const Pool& p = fwd ? st.fp : st.rp;
-    uint32_t ins = insa[x];
-    uint32_t used = useda[x];
-    Slab s = slab_of(p, fwd ? st.fdesc[x] : st.rdesc[x]);
-    bool grow = (uint64_t)used + ins > 12ull * s.nb;
-    uint32_t kept = 0;
-    if (grow) {
-      for (uint32_t t = lane; t < s.nb * BSLOTS; t += 64) {
-        uint32_t* bp = bucket_ptr(s, t / BSLOTS);
-        uint32_t j = t % BSLOTS;
-        uint32_t d = *slot_dst(bp, j);
-        if (d != EMPTY && *slot_death(bp, j, s.words) > floor_e) kept++;
-      }
-      kept = wave_sum_u32(kept);
-    }
-    if (lane == 0) {
+  const uint32_t gw = (blockIdx.x * UPD_THREADS + threadIdx.x) >> 6, nw = (gridDim.x * UPD_THREADS) >> 6;
+  for (uint32_t base = gw * 64; base < nt; base += nw * 64) {   // wave-uniform
+    const uint32_t k = base + lane;
+    const bool act = k < nt, fwd = k < nf;
+    uint32_t ins = 0;
+    Slab sl{nullptr, nullptr, 0, 0};
+    bool grow = false;
+    if (act) {
+      const uint32_t x = fwd ? touch_f[k] : touch_r[k - nf];
+      uint32_t* insa = fwd ? insf : insr;
+      uint32_t* useda = fwd ? st.fused : st.rused;
+      ins = insa[x];
+      const uint32_t used = useda[x];
+      sl = slab_of(fwd ? st.fp : st.rp, fwd ? st.fdesc[x] : st.rdesc[x]);
+      grow = (uint64_t)used + ins > 12ull * sl.nb;
       insa[x] = 0;
       if (!grow) {
         useda[x] = used + ins;
         plan[k] = 0;
-      } else {
-        uint64_t target = (uint64_t)kept + ins;
+      }
+    }
+    for (unsigned long long gm = __ballot(grow); gm; gm &= gm - 1) {
+      const int l = __ffsll((long long)gm) - 1;
+      uint32_t* sb = reinterpret_cast<uint32_t*>(__shfl(reinterpret_cast<unsigned long long>(sl.base), l, 64));
+      const uint32_t snb = __shfl(sl.nb, l, 64), sw = __shfl(sl.words, l, 64);
+      uint32_t kept = 0;
+      for (uint32_t t = lane; t < snb * BSLOTS; t += 64) {
+        uint32_t* bp = sb + (uint64_t)(t / BSLOTS) * sw;
+        const uint32_t j = t % BSLOTS;
+        if (*slot_dst(bp, j) != EMPTY && *slot_death(bp, j, sw) > floor_e) kept++;
+      }
+      kept = wave_sum_u32(kept);
+      if ((int)lane == l) {
+        const uint64_t target = (uint64_t)kept + ins;
         uint32_t lg = 0;
         while ((8ull << lg) < target) lg++;
         plan[k] = lg + 1;
@@ -319,7 +332,18 @@ __device__ inline GrowRef grow_ref(uint32_t i, const uint32_t* glist, const uint
   return r;
 }
 
-// Reserve each growing slab's new space (or flag the batch out of memory).
+__device__ inline unsigned long long wave_incl_sum64(unsigned long long x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  return x;
+}
+
+// Reserve each growing slab's new space (or flag the batch out of memory):
+// a wave takes its slabs' space with one atomic per pool cursor.
 __global__ __launch_bounds__(UPD_THREADS) void k_grow_alloc(Store st, const uint32_t* glist, const uint32_t* plan,
                                                              unsigned long long* goff, uint32_t* gkept,
                                                              UpdCounters* c) {
@@ -329,11 +353,28 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_alloc(Store st, const uint
     return;
   }
   const uint32_t ng = c->n_grow, nf = c->n_touch_f;
-  for (uint32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < ng; i += gridDim.x * UPD_THREADS) {
-    const uint32_t k = glist[i];
-    const bool fwd = k < nf;
-    goff[i] = atomicAdd(&st.cursor[fwd ? 0 : 1], 1ull << (plan[k] - 1));
-    gkept[i] = 0;
+  const uint32_t lane = lane_id();
+  const uint32_t gw = (blockIdx.x * UPD_THREADS + threadIdx.x) >> 6, nw = (gridDim.x * UPD_THREADS) >> 6;
+  for (uint32_t base = gw * 64; base < ng; base += nw * 64) {   // wave-uniform
+    const uint32_t i = base + lane;
+    const bool act = i < ng;
+    const uint32_t k = act ? glist[i] : 0u;
+    const bool fwd = act && k < nf;
+    const unsigned long long sz = act ? 1ull << (plan[k] - 1) : 0ull;
+    const unsigned long long szf = fwd ? sz : 0ull, szr = fwd ? 0ull : sz;
+    const unsigned long long xf = wave_incl_sum64(szf), xr = wave_incl_sum64(szr);
+    const unsigned long long tf = __shfl(xf, 63, 64), tr = __shfl(xr, 63, 64);
+    unsigned long long bf = 0, br = 0;
+    if (lane == 0) {
+      if (tf) bf = atomicAdd(&st.cursor[0], tf);
+      if (tr) br = atomicAdd(&st.cursor[1], tr);
+    }
+    bf = __shfl(bf, 0, 64);
+    br = __shfl(br, 0, 64);
+    if (act) {
+      goff[i] = fwd ? bf + xf - szf : br + xr - szr;
+      gkept[i] = 0;
+    }
   }
 }
 
@@ -590,7 +631,7 @@ static hipError_t run_pipeline(dg_graph* g, const dg_op* dops, uint32_t n, uint8
                                             u.vlastrem.as<uint32_t>(), u.recflags.as<uint8_t>(),
                                             u.recw.as<int32_t>(), touch_f, touch_r, g->insf.as<uint32_t>(),
                                             g->insr.as<uint32_t>(), c);
-  k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS / 64, 4096), UPD_THREADS, 0, s>>>(
+  k_grow_plan<<<blocks_for(3ull * n, UPD_THREADS, 4096), UPD_THREADS, 0, s>>>(
       st, touch_f, touch_r, plan, plan_ins, glist, g->insf.as<uint32_t>(), g->insr.as<uint32_t>(), fl, c);
   const uint32_t gx = blocks_for(3ull * n, 1, 512);
   k_grow_alloc<<<blocks_for(3ull * n, UPD_THREADS, 64), UPD_THREADS, 0, s>>>(st, glist, plan, goff, gkept, c);
