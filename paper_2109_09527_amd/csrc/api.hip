@@ -121,10 +121,8 @@ bool alive_at(const dg_graph* g, uint32_t v, uint32_t e) {
   uint32_t t0 = g->vfirst[v];
   if (t0 == 0 || t0 > e) return false;
   uint32_t toggles = 1;
-  auto it = g->vmore.find(v);
-  if (it != g->vmore.end())
-    for (uint32_t t : it->second)
-      if (t <= e) toggles++;
+  for (uint32_t i = g->vhead[v]; i != VLOG_NONE; i = g->vlog[i].second)
+    if (g->vlog[i].first <= e) toggles++;
   return toggles & 1;
 }
 
@@ -457,6 +455,7 @@ dg_status dg_create(const dg_config* cfg, dg_graph** out) {
   st.cursor = g->cursor.as<unsigned long long>();
   st.alive = g->alive.as<uint8_t>();
   g->vfirst.assign(V, 0);
+  g->vhead.assign(V, VLOG_NONE);
   // set-up that later calls must not repeat: the event updates wait on, and
   // the address of this device's fixed area for the allocation-free calls
   if ((e = hipEventCreateWithFlags(&g->last_query, hipEventDisableTiming)) != hipSuccess ||
@@ -795,6 +794,14 @@ dg_status dg_profile_enable(dg_graph* g, int on) {
   std::lock_guard<std::mutex> lk(g->mu);
   std::lock_guard<std::mutex> lp(g->prof.mu);
   g->prof.on = on != 0;
+  // events for a few thousand timed launches, so that timing them creates
+  // no event inside the region being timed
+  constexpr size_t PROF_POOL = 4096;
+  while (g->prof.on && g->prof.pool.size() + g->prof.pending.size() * 2 < PROF_POOL) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    g->prof.pool.push_back(e);
+  }
   return DG_OK;
 }
 

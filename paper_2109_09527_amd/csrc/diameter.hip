@@ -141,7 +141,7 @@ dg_status diameter_dev(dg_graph* g, uint32_t e, uint32_t* diameter, hipStream_t 
   // the live vertices at e, from the host's history, are the sources
   std::vector<uint32_t> srcs;
   for (uint32_t v = 0; v < V; v++)
-    if (g->vfirst[v] != 0 && g->vfirst[v] <= e && (g->vmore.count(v) == 0 || alive_at(g, v, e))) srcs.push_back(v);
+    if (g->vfirst[v] != 0 && g->vfirst[v] <= e && (g->vhead[v] == VLOG_NONE || alive_at(g, v, e))) srcs.push_back(v);
   if (srcs.empty()) return DG_OK;
   DevBuf& live = g->pr.live;
   if ((he = snapshot_live(g, e, live, st)) != hipSuccess) return fail_hip(he, "liveness");

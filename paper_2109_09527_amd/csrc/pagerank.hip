@@ -533,7 +533,7 @@ hipError_t snapshot_live(dg_graph* g, uint32_t e, DevBuf& live, hipStream_t st) 
   if ((he = hipStreamSynchronize(st)) != hipSuccess) return he;
   uint8_t* hl = static_cast<uint8_t*>(s.host);
   for (uint32_t v = 0; v < V; v++) hl[v] = g->vfirst[v] != 0 && g->vfirst[v] <= e;
-  for (const auto& kv : g->vmore) hl[kv.first] = alive_at(g, kv.first, e) ? 1 : 0;
+  for (const uint32_t v : g->vtoggled) hl[v] = alive_at(g, v, e) ? 1 : 0;
   if ((he = ensure(live, V + 64)) != hipSuccess) return he;
   return hipMemcpyAsync(live.p, hl, V, hipMemcpyHostToDevice, st);
 }

@@ -152,6 +152,26 @@ static void fill(T* p, uint64_t n, T v, hipStream_t s) {
   k_fill<T><<<(uint32_t)b, 256, 0, s>>>(p, n, v);
 }
 
+// Up to four 32-bit fills in one launch (a query's start-up clears), so a
+// search does not pay a launch per array before its seed.
+struct Fills {
+  uint32_t* p[4];
+  uint64_t n[4];
+  uint32_t v[4];
+};
+__global__ void k_fills(Fills f) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.n[k]; i += stride) f.p[k][i] = f.v[k];
+}
+static void fills(const Fills& f, hipStream_t s) {
+  uint64_t n = 0;
+  for (int k = 0; k < 4; k++) n = std::max(n, f.n[k]);
+  if (!n) return;
+  k_fills<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(f);
+}
+
 // Seed a query at src: dist/level d0, the item of src and its chunk map,
 // bitmap bit; counters slot 0 describes the seed frontier, slot 1 is
 // cleared.  One wave.
@@ -517,9 +537,10 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
   Item* qbig = q.fb.as<Item>();
   uint32_t* bm[2] = {q.bm0.as<uint32_t>(), q.bm1.as<uint32_t>()};
   QCounters* cnt = q.counters.as<QCounters>();
-  fill<int32_t>(dist, V, -1, s);
-  clear_counts(q, s);
-  fill<uint32_t>(bm[0], bmw, 0u, s);
+  fills(Fills{{reinterpret_cast<uint32_t*>(dist), done_of(q), bm[0], nullptr},
+               {V, (COUNTERS_BYTES - DONE_OFF) / 4, bmw, 0},
+               {0xFFFFFFFFu, 0u, 0u, 0u}},
+        s);
   PubArgs pub = pub_args(q, 0);
   k_seed<<<1, 64, 0, s>>>(g->st, src, dist, 0, fr[0], bm[0], cnt, nullptr, pub);
   QCounters hc;
@@ -584,10 +605,10 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   uint32_t* rstamp = q.rstamp.as<uint32_t>();
   QCounters* cnt = q.counters.as<QCounters>();
   uint32_t* rcount = &cnt[3].n_order;
-  fill<int32_t>(dist, V, DIST_INF, s);
-  clear_counts(q, s);
-  fill<uint32_t>(stamp, V, 0u, s);
-  fill<uint32_t>(infar, V, 0u, s);
+  fills(Fills{{reinterpret_cast<uint32_t*>(dist), done_of(q), stamp, infar},
+               {V, (COUNTERS_BYTES - DONE_OFF) / 4, V, V},
+               {(uint32_t)DIST_INF, 0u, 0u, 0u}},
+        s);
   if (split_lh) {
     fill<uint32_t>(rstamp, V, 0u, s);
     fill<uint32_t>(rcount, 1, 0u, s);

@@ -670,8 +670,13 @@ static void record_vertex_changes(dg_graph* g, const uint32_t* list, uint32_t cn
   for (uint32_t k = 0; k < cnt; k++) {
     uint32_t x = list[k] & 0x7FFFFFFFu;
     bool now = (list[k] >> 31) != 0;
-    if (g->vfirst[x] == 0) g->vfirst[x] = E;
-    else g->vmore[x].push_back(E);
+    if (g->vfirst[x] == 0) {
+      g->vfirst[x] = E;
+    } else {
+      if (g->vhead[x] == VLOG_NONE) g->vtoggled.push_back(x);
+      g->vlog.emplace_back(E, g->vhead[x]);
+      g->vhead[x] = (uint32_t)(g->vlog.size() - 1);
+    }
     g->n_live += now ? 1 : -1;
   }
 }
