@@ -693,31 +693,32 @@ __device__ __forceinline__ void bu_step(const LevelArgs& a, uint32_t worker, uin
     Slab s = slab_of(ip, ydesc_in);
     bool found = false;
     if (act && s.nb == 1) {
-      const uint4* src4 = reinterpret_cast<const uint4*>(s.base);
       const uint4 sm = a.fast ? *reinterpret_cast<const uint4*>(s.sum)
                               : make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
-      bool more = true;   // no empty slot seen yet (used slots are a prefix)
-      // four slots per 16-byte load; each slot is tested in turn until a
-      // parent is found or an empty slot ends the bucket
-      auto slot = [&](uint32_t x, int j) {
-        if (!more || found) return;
-        if (x == EMPTY) {
-          more = false;
-          return;
-        }
-        bool vis = visible_by_summary(sm, a.fast, j, a.e, slot_stamp(s.base, j, s.words));
-        if (vis) {
-          lc.arcs++;
-          found = bm_test(a.bm_cur, x);
-        }
-      };
+      uint32_t x[BSLOTS];
+      load_dsts(s.base, x);
+      const int used = first_empty(x);   // used slots are a prefix
+      // the frontier bits of eight slots are fetched together, and a second
+      // eight only when the first hold no parent; arcs examined are counted
+      // in slot order up to the first parent, as a scan that stops there
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        uint4 v = src4[q];
-        slot(v.x, 4 * q);
-        slot(v.y, 4 * q + 1);
-        slot(v.z, 4 * q + 2);
-        slot(v.w, 4 * q + 3);
+      for (int h = 0; h < BSLOTS; h += 8) {
+        if (h >= used || found) break;
+        bool vis[8];
+        uint32_t w[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          const int j = h + i;
+          vis[i] = j < used && visible_by_summary(sm, a.fast, j, a.e, slot_stamp(s.base, j, s.words));
+          w[i] = vis[i] ? a.bm_cur[x[j] >> 5] : 0u;
+        }
+        int first = 8;
+#pragma unroll
+        for (int i = 7; i >= 0; i--)
+          if (vis[i] && ((w[i] >> (x[h + i] & 31)) & 1u)) first = i;
+#pragma unroll
+        for (int i = 0; i < 8; i++) lc.arcs += vis[i] && i <= first ? 1 : 0;
+        found = first < 8;
       }
     }
     uint64_t yd = 0;
