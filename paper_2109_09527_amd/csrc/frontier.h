@@ -818,12 +818,15 @@ __device__ __forceinline__ void bu_big_step(const LevelArgs& a, uint32_t nbig, u
 
 // ----------------------------------------------------------------- SSSP
 
-// The far set of delta-stepping is the flag array infar (no list): a relax
-// that improves a vertex to a distance at or above the threshold flags it,
-// and a split scans all vertices densely (flags and distances are read in
-// order), moving flagged vertices below the new threshold into the near
-// frontier.  A split then costs one streaming pass over V, whatever the
-// number of far vertices, instead of a random read per far entry.
+// The far set of delta-stepping is the bitmap infar, one bit per vertex (no
+// list): a relax that improves a vertex to a distance at or above the
+// threshold sets its bit, and a split scans the bitmap densely, reading the
+// distances of flagged vertices only and moving those below the new
+// threshold into the near frontier.  A split then costs one streaming pass
+// over V / 8 bytes, whatever the number of far vertices, instead of a
+// random read per far entry; a flag word per vertex had cost 4 bytes per
+// vertex in every split and a line per flag test in the relax.
+__device__ inline uint32_t far_bit(uint32_t v) { return 1u << (v & 31); }
 struct RelaxArgs {
   Store st;
   uint32_t e;
@@ -832,7 +835,7 @@ struct RelaxArgs {
   Front fout;
   int32_t* dist;
   uint32_t* stamp;     // iteration stamp of the last push into the near queue
-  uint32_t* infar;     // far flags (new flags are counted in cnt_out->n_far)
+  uint32_t* infar;     // far bitmap (new flags are counted in cnt_out->n_far)
   int32_t thr;
   uint32_t it1;        // stamp value of the queue being filled
   QCounters* cnt_out;
@@ -894,9 +897,9 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
       if (take[k] && nd[k] < cur[k] && nd[k] < old[k]) {
         if (nd[k] < a.thr) {
           prev[k] = atomicExch(&a.stamp[s4.d[k]], a.it1);
-          fl[k] = a.infar[s4.d[k]];
+          fl[k] = a.infar[s4.d[k] >> 5] & far_bit(s4.d[k]);
         } else {
-          prev[k] = atomicExch(&a.infar[s4.d[k]], 1u);
+          prev[k] = atomicOr(&a.infar[s4.d[k] >> 5], far_bit(s4.d[k])) & far_bit(s4.d[k]);
         }
       }
     }
@@ -907,7 +910,7 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
       const bool imp = take[k] && nd[k] < cur[k] && nd[k] < old[k];
       to_near[k] = imp && nd[k] < a.thr && prev[k] != a.it1;
       // settled in this bucket: no later split needs to move it again
-      if (imp && nd[k] < a.thr && fl[k]) a.infar[s4.d[k]] = 0u;
+      if (imp && nd[k] < a.thr && fl[k]) atomicAnd(&a.infar[s4.d[k] >> 5], ~far_bit(s4.d[k]));
       if (imp && nd[k] >= a.thr && prev[k] == 0u) lc.far++;
       yd[k] = to_near[k] ? a.st.fdesc[s4.d[k]] : 0;
     }
@@ -969,12 +972,19 @@ struct SplitArgs {
 // near queue; the rest stay flagged, counted, with their minimum distance.
 __device__ __forceinline__ void split_block(const SplitArgs& a, uint32_t base, ItemQ& qn, LaneCounts& lc,
                                             int32_t& mn) {
+  // base is a multiple of 64: lanes 0-31 and 32-63 share one flag word
+  // each, and no other wave touches either (no relax runs beside a split)
   const uint32_t v = base + lane_id();
-  const bool flagged = v < a.st.V && a.infar[v] != 0u;
+  const uint32_t w = v < a.st.V ? a.infar[v >> 5] : 0u;
+  const bool flagged = (w & far_bit(v)) != 0u;
   const int32_t dv = flagged ? a.dist[v] : DIST_INF;
   bool near = flagged && dv < a.thr;
+  const unsigned long long moved = __ballot(near);
+  if ((lane_id() & 31) == 0 && v < a.st.V) {
+    const uint32_t m = (uint32_t)(moved >> (lane_id() & 32));
+    if (m) a.infar[v >> 5] = w & ~m;
+  }
   if (near) {
-    a.infar[v] = 0u;
     near = atomicExch(&a.stamp[v], a.it1) != a.it1;
   } else if (flagged) {
     mn = min(mn, dv);

@@ -606,7 +606,7 @@ dg_status sssp_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStre
   QCounters* cnt = q.counters.as<QCounters>();
   uint32_t* rcount = &cnt[3].n_order;
   fills(Fills{{reinterpret_cast<uint32_t*>(dist), done_of(q), stamp, infar},
-               {V, (COUNTERS_BYTES - DONE_OFF) / 4, V, V},
+               {V, (COUNTERS_BYTES - DONE_OFF) / 4, V, (V + 31) / 32 + 1},
                {(uint32_t)DIST_INF, 0u, 0u, 0u}},
         s);
   if (split_lh) {
