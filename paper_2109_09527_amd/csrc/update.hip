@@ -167,34 +167,19 @@ __device__ inline void wave_append(uint32_t* list, uint32_t* count, bool want, u
   if (want) list[base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull))] = x;
 }
 
-__global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
-    const uint64_t* keys, const uint32_t* vals, const dg_op* ops, uint32_t n, uint32_t L, Store st,
-    uint8_t* results, const uint8_t* vafter, const uint32_t* vlastrem, uint8_t* recflags, int32_t* recw,
-    uint32_t* touch_f, uint32_t* touch_r, uint32_t* insf, uint32_t* insr, UpdCounters* c) {
-  if (c->flags) return;
-  const uint32_t nv = c->nv;
-  if (nv + blockIdx.x * UPD_THREADS >= n) return;   // workgroup-uniform
-  __shared__ uint32_t vf_lds[VF_WORDS];
-  const uint32_t* vf = nullptr;
-  if (nv <= VF_MAX_VERTS) {
-    for (uint32_t w = threadIdx.x; w < VF_WORDS; w += UPD_THREADS) vf_lds[w] = 0u;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < nv; j += UPD_THREADS) {
-      const uint32_t h = vf_hash((uint32_t)(keys[j] >> L));
-      atomicOr(&vf_lds[h >> 5], 1u << (h & 31));
-    }
-    __syncthreads();
-    vf = vf_lds;
-  }
-  uint32_t k = nv + blockIdx.x * UPD_THREADS + threadIdx.x;
-  if (k >= n) return;
-  uint64_t key = keys[k];
-  if (k > nv && keys[k - 1] == key) {
-    recflags[k] = 0;
-    return;
-  }
+// One edge-key segment starting at k: each op's result in index order, and
+// the net effect on the store recorded for the commit (recflags: 1 =
+// tombstone the version present at e, 2 = insert a new one; recw: its
+// weight).  Returns whether the key inserts.
+__device__ __forceinline__ bool resolve_key(const uint64_t* keys, const uint32_t* vals, const dg_op* ops, uint32_t n,
+                                            uint32_t nv, uint32_t L, const Store& st, uint8_t* results,
+                                            const uint8_t* vafter, const uint32_t* vlastrem, const uint32_t* vf,
+                                            uint32_t k, uint64_t key, uint8_t* recflags, int32_t* recw,
+                                            uint32_t* a_out, uint32_t* b_out) {
   const uint64_t mask = (1ull << L) - 1;
-  uint32_t a = (uint32_t)((key >> L) & mask), b = (uint32_t)(key & mask);
+  const uint32_t a = (uint32_t)((key >> L) & mask), b = (uint32_t)(key & mask);
+  *a_out = a;
+  *b_out = b;
   // loads that do not depend on the store probe go out first
   const dg_op op0 = ops[vals[k]];
   const uint8_t alive_a = st.alive[a], alive_b = st.alive[b];
@@ -246,24 +231,71 @@ __global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
   bool ins = present && (!present0 || cleared || w != w0);
   recflags[k] = (uint8_t)((tomb ? 1 : 0) | (ins ? 2 : 0));
   recw[k] = w;
+  return ins;
+}
+
+// Wave-uniform call: adds each inserting lane's insert to cnt[x] and tells
+// the lane that made the count leave zero.  Keys are sorted by source, so a
+// vertex's inserts often sit on consecutive lanes; such a run adds its
+// length with one atomic from its first lane (a hub's inserts had queued
+// one atomic per key on one word).
+__device__ inline bool count_inserts(uint32_t* cnt, bool ins, uint32_t x) {
+  const uint32_t lane = lane_id();
+  const uint32_t xp = __shfl_up(x, 1, 64);
+  const bool insp = __shfl_up(ins ? 1 : 0, 1, 64) != 0;
+  const bool cont = ins && lane > 0 && insp && xp == x;
+  const unsigned long long mc = __ballot(cont);
+  if (!ins || cont) return false;
+  const unsigned long long after = lane == 63 ? 0ull : mc >> (lane + 1);
+  const uint32_t len = 1u + (uint32_t)__builtin_ctzll(~after);
+  return atomicAdd(&cnt[x], len) == 0;
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_resolve_edge(
+    const uint64_t* keys, const uint32_t* vals, const dg_op* ops, uint32_t n, uint32_t L, Store st,
+    uint8_t* results, const uint8_t* vafter, const uint32_t* vlastrem, uint8_t* recflags, int32_t* recw,
+    uint32_t* touch_f, uint32_t* touch_r, uint32_t* insf, uint32_t* insr, UpdCounters* c) {
+  if (c->flags) return;
+  const uint32_t nv = c->nv;
+  if (nv + blockIdx.x * UPD_THREADS >= n) return;   // workgroup-uniform
+  __shared__ uint32_t vf_lds[VF_WORDS];
+  const uint32_t* vf = nullptr;
+  if (nv <= VF_MAX_VERTS) {
+    for (uint32_t w = threadIdx.x; w < VF_WORDS; w += UPD_THREADS) vf_lds[w] = 0u;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nv; j += UPD_THREADS) {
+      const uint32_t h = vf_hash((uint32_t)(keys[j] >> L));
+      atomicOr(&vf_lds[h >> 5], 1u << (h & 31));
+    }
+    __syncthreads();
+    vf = vf_lds;
+  }
+  const uint32_t k = nv + blockIdx.x * UPD_THREADS + threadIdx.x;
+  bool ins = false;
+  uint32_t a = 0, b = 0;
+  if (k < n) {
+    const uint64_t key = keys[k];
+    if (k > nv && keys[k - 1] == key) recflags[k] = 0;
+    else ins = resolve_key(keys, vals, ops, n, nv, L, st, results, vafter, vlastrem, vf, k, key, recflags, recw, &a, &b);
+  }
   // count the insert at each endpoint; the first insert at a vertex lists
   // it as touched (one list reservation per wave, not per lane)
-  const bool fa = ins && atomicAdd(&insf[a], 1u) == 0;
+  const bool fa = count_inserts(insf, ins, a);
   wave_append(touch_f, &c->n_touch_f, fa, a);
   if (!st.undirected) {
-    const bool fb = ins && atomicAdd(&insr[b], 1u) == 0;
+    const bool fb = count_inserts(insr, ins, b);
     wave_append(touch_r, &c->n_touch_r, fb, b);
   } else {
-    const bool fb = ins && a != b && atomicAdd(&insf[b], 1u) == 0;
+    const bool fb = count_inserts(insf, ins && a != b, b);
     wave_append(touch_f, &c->n_touch_f, fb, b);
   }
 }
 
 // One lane per touched vertex: decide whether its slab must grow.
 // plan[k] = log2(new buckets) + 1, or 0 when the slab keeps its size.  The
-// versions a growing slab keeps are counted by its whole wave, one growing
-// slab after another (growth is rare, so most waves count none); a wave per
-// touched vertex had left 63 lanes idle on nearly every vertex.
+// versions a growing slab keeps are counted by its own lane when the slab
+// is small, else by its whole wave, one such slab after another; a wave
+// per touched vertex had left 63 lanes idle on nearly every vertex.
 __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint32_t* touch_f,
                                                             const uint32_t* touch_r, uint32_t* plan,
                                                             uint32_t* plan_ins, uint32_t* glist, uint32_t* insf,
@@ -293,7 +325,20 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint3
         plan[k] = 0;
       }
     }
-    for (unsigned long long gm = __ballot(grow); gm; gm &= gm - 1) {
+    // a slab of at most SMALL_GROW buckets is counted by its own lane
+    constexpr uint32_t SMALL_GROW = 2;
+    uint32_t kept_own = 0;
+    if (grow && sl.nb <= SMALL_GROW) {
+      for (uint32_t bk = 0; bk < sl.nb; bk++) {
+        uint32_t* bp = bucket_ptr(sl, bk);
+        uint32_t d[BSLOTS];
+        load_dsts(bp, d);
+#pragma unroll
+        for (int j = 0; j < BSLOTS; j++)
+          kept_own += d[j] != EMPTY && *slot_death(bp, j, sl.words) > floor_e ? 1u : 0u;
+      }
+    }
+    for (unsigned long long gm = __ballot(grow && sl.nb > SMALL_GROW); gm; gm &= gm - 1) {
       const int l = __ffsll((long long)gm) - 1;
       uint32_t* sb = reinterpret_cast<uint32_t*>(__shfl(reinterpret_cast<unsigned long long>(sl.base), l, 64));
       const uint32_t snb = __shfl(sl.nb, l, 64), sw = __shfl(sl.words, l, 64);
@@ -304,15 +349,16 @@ __global__ __launch_bounds__(UPD_THREADS) void k_grow_plan(Store st, const uint3
         if (*slot_dst(bp, j) != EMPTY && *slot_death(bp, j, sw) > floor_e) kept++;
       }
       kept = wave_sum_u32(kept);
-      if ((int)lane == l) {
-        const uint64_t target = (uint64_t)kept + ins;
-        uint32_t lg = 0;
-        while ((8ull << lg) < target) lg++;
-        plan[k] = lg + 1;
-        plan_ins[k] = ins;
-        atomicAdd(fwd ? &c->demand_f : &c->demand_r, 1ull << lg);
-        glist[atomicAdd(&c->n_grow, 1u)] = k;
-      }
+      if ((int)lane == l) kept_own = kept;
+    }
+    if (grow) {
+      const uint64_t target = (uint64_t)kept_own + ins;
+      uint32_t lg = 0;
+      while ((8ull << lg) < target) lg++;
+      plan[k] = lg + 1;
+      plan_ins[k] = ins;
+      atomicAdd(fwd ? &c->demand_f : &c->demand_r, 1ull << lg);
+      glist[atomicAdd(&c->n_grow, 1u)] = k;
     }
   }
 }
