@@ -804,45 +804,79 @@ dg_status bc_dev(dg_graph* g, uint32_t e, const uint32_t* srcs, uint32_t k, doub
 
 // ---------------------------------------------------------------- stats
 
-// Visible slots of buckets [b0, b1) of a slab, summed over the wave.
-__device__ inline uint32_t visible_in(const Slab& s, uint32_t b0, uint32_t b1, uint32_t e) {
+// Visible slots of buckets [b0, b1) of a slab, summed over the wave.  With
+// trusted summaries (fast), a bucket whose versions were all born by e
+// decides most slots from its summary, and a slot's stamp is read only
+// where the summary cannot tell.
+__device__ inline uint32_t visible_in(const Slab& s, uint32_t b0, uint32_t b1, uint32_t e, bool fast) {
   const uint32_t lane = lane_id(), j = lane & 15;
   uint32_t c = 0;
   for (uint32_t b = b0 + (lane >> 4); b < b1; b += 4) {
     uint32_t* bp = bucket_ptr(s, b);
-    if (bp[j] != EMPTY && visible(*slot_stamp(bp, j, FWD_WORDS), e)) c++;
+    const uint4 sm = fast ? *reinterpret_cast<const uint4*>(&s.sum[SUM_WORDS * b])
+                          : make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
+    if (bp[j] != EMPTY && visible_by_summary(sm, fast, j, e, slot_stamp(bp, j, FWD_WORDS))) c++;
   }
   return wave_sum_u32(c);
 }
 
-// One wave per vertex: slabs of one backward tile (BWD_TILE buckets) are
-// counted here; longer ones are listed, with their tiles, for k_degree_tiles
-// (parity 0), so a hub does not hold one wave for its whole slab.
-__global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, uint32_t* deg, unsigned long long* total,
-                                                       BwdTiles bt) {
+// One lane per vertex for slabs of at most DEG_OWN buckets (nearly all
+// vertices), each bucket read as lines; the wave takes the longer slabs of
+// its 64 vertices one after another, and lists those longer than one
+// backward tile (BWD_TILE buckets), with their tiles, for k_degree_tiles
+// (parity 0), so a hub does not hold one wave for its whole slab.  A wave
+// per vertex had left most lanes idle on one-bucket slabs.
+constexpr uint32_t DEG_OWN = 2;
+__global__ __launch_bounds__(Q_THREADS) void k_degrees(Store st, uint32_t e, int fast, uint32_t* deg,
+                                                       unsigned long long* total, BwdTiles bt) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
   const uint32_t nwaves = gridDim.x * Q_WAVES;
   unsigned long long sum = 0;
-  for (uint32_t v = gwave; v < st.V; v += nwaves) {
-    const uint64_t desc = st.fdesc[v];
+  for (uint32_t base = gwave * 64; base < st.V; base += nwaves * 64) {   // wave-uniform
+    const uint32_t v = base + lane;
+    const bool act = v < st.V;
+    const uint64_t desc = act ? st.fdesc[v] : 0;
     const Slab s = slab_of(st.fp, desc);
-    if (bwd_is_big(desc)) {
-      if (deg && lane == 0) deg[v] = 0;
-      bwd_list(bt, 0, v, desc);
-      continue;
-    }
-    const uint32_t c = visible_in(s, 0, s.nb, e);
-    if (lane == 0) {
+    const bool own = act && s.nb <= DEG_OWN;
+    if (own) {
+      uint32_t c = 0;
+      for (uint32_t b = 0; b < s.nb; b++) {
+        uint32_t* bp = bucket_ptr(s, b);
+        uint32_t d[BSLOTS];
+        load_dsts(bp, d);
+        const uint4 sm = fast ? *reinterpret_cast<const uint4*>(&s.sum[SUM_WORDS * b])
+                              : make_uint4(0xFFFFFFFFu, 0xFFFFu, 0xFFFFFFFFu, 0u);
+#pragma unroll
+        for (int j = 0; j < BSLOTS; j++)
+          c += d[j] != EMPTY && visible_by_summary(sm, fast != 0, j, e, slot_stamp(bp, j, FWD_WORDS)) ? 1u : 0u;
+      }
       if (deg) deg[v] = c;
       sum += c;
     }
+    for (unsigned long long m = __ballot(act && !own); m; m &= m - 1) {
+      const int l = __ffsll((long long)m) - 1;
+      const uint32_t vv = __shfl(v, l, 64);
+      const uint64_t dv = __shfl((unsigned long long)desc, l, 64);
+      if (bwd_is_big(dv)) {
+        if (deg && lane == 0) deg[vv] = 0;
+        bwd_list(bt, 0, vv, dv);
+        continue;
+      }
+      const Slab sv = slab_of(st.fp, dv);
+      const uint32_t c = visible_in(sv, 0, sv.nb, e, fast != 0);
+      if (lane == 0) {
+        if (deg) deg[vv] = c;
+        sum += c;
+      }
+    }
   }
+  sum = wave_sum_u64(sum);
   if (lane == 0 && sum) atomicAdd(total, sum);
 }
 
 // One wave per listed tile: its count added to the vertex's degree.
-__global__ __launch_bounds__(Q_THREADS) void k_degree_tiles(Store st, uint32_t e, uint32_t* deg,
+__global__ __launch_bounds__(Q_THREADS) void k_degree_tiles(Store st, uint32_t e, int fast, uint32_t* deg,
                                                             unsigned long long* total, BwdTiles bt) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * Q_WAVES + (threadIdx.x >> 6);
@@ -857,7 +891,7 @@ __global__ __launch_bounds__(Q_THREADS) void k_degree_tiles(Store st, uint32_t e
     const Slab s = slab_of(st.fp, bv.desc);
     const uint32_t b0 = (t - bv.base) << BWD_TILE_LOG;
     if (b0 >= s.nb) continue;
-    const uint32_t c = visible_in(s, b0, min(s.nb, b0 + BWD_TILE), e);
+    const uint32_t c = visible_in(s, b0, min(s.nb, b0 + BWD_TILE), e, fast != 0);
     if (lane == 0 && c) {
       if (deg) atomicAdd(&deg[bv.v], c);
       sum += c;
@@ -874,8 +908,9 @@ dg_status stats_dev(dg_graph* g, uint32_t e, uint64_t* n_arcs, uint32_t* deg, hi
   unsigned long long* tot = reinterpret_cast<unsigned long long*>(g->qs.counters.as<QCounters>() + 3);
   fill<unsigned long long>(tot, 1, 0ull, s);
   fill<uint32_t>(reinterpret_cast<uint32_t*>(bt.head), sizeof(BwdHead) / 4, 0u, s);
-  k_degrees<<<grid_for(g->cfg.v_capacity, Q_WAVES, 8192), Q_THREADS, 0, s>>>(g->st, e, deg, tot, bt);
-  k_degree_tiles<<<resident((const void*)k_degree_tiles), Q_THREADS, 0, s>>>(g->st, e, deg, tot, bt);
+  const int fast = g->concurrent_writers ? 0 : 1;
+  k_degrees<<<grid_for(g->cfg.v_capacity, Q_THREADS, 8192), Q_THREADS, 0, s>>>(g->st, e, fast, deg, tot, bt);
+  k_degree_tiles<<<resident((const void*)k_degree_tiles), Q_THREADS, 0, s>>>(g->st, e, fast, deg, tot, bt);
   if ((he = hipGetLastError()) != hipSuccess) return hip_fail(g, he, "stats launch");
   if (n_arcs) {
     if ((he = hipMemcpyAsync(g->qs.host_counters, tot, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)

@@ -206,9 +206,10 @@ def test_source_absent_and_retired_epochs(dg):
 
 
 def test_snapshots_of_many_epochs_match_oracle_history(dg):
-    """Queries on every retained epoch after later batches changed the graph
-    (versions born and tombstoned since), compared with the oracle's answer
-    recorded when it was at that epoch; then after compaction."""
+    """Queries and out-degrees on every retained epoch after later batches
+    changed the graph (versions born and tombstoned since), compared with the
+    oracle's answer recorded when it was at that epoch; then after
+    compaction."""
     gr = synth.rmat_graph(12, 8, 30, seed=4)
     o = Oracle(gr.n, w_max=30)
     g = dg.Graph(gr.n, w_max=30, max_resident_epochs=6)
@@ -217,16 +218,18 @@ def test_snapshots_of_many_epochs_match_oracle_history(dg):
     g.apply(synth.load_ops(gr))
     wl = synth.update_batches(graph=gr, n_batches=5, n_edge_ops=3000, w_max=30, seed=4)
     srcs = wl.bfs_src[:3]
-    hist = {}
+    hist, degs = {}, {}
     for b in wl.batches:
         rc, r_o = o.apply(b)
         res, ep = g.apply(b)
         assert np.array_equal(res, r_o)
         hist[ep] = {int(s): (o.bfs(int(s))[1], o.sssp(int(s))[1]) for s in srcs}
+        degs[ep] = np.array([o.out_degree(v) for v in range(gr.n)], np.int64)
     for compacted in (False, True):
         if compacted:
             g.compact()
         for ep, ans in hist.items():
+            assert np.array_equal(g.out_degrees(ep).cpu().numpy().astype(np.int64), degs[ep]), (ep, compacted)
             for s, (bd, sd) in ans.items():
                 assert np.array_equal(g.bfs(s, ep).cpu().numpy(), bd), (ep, s, compacted)
                 assert np.array_equal(g.sssp(s, ep).cpu().numpy(), sd), (ep, s, compacted)
