@@ -554,8 +554,13 @@ dg_status bfs_dev(dg_graph* g, uint32_t e, uint32_t src, int32_t* dist, hipStrea
   int level = 0;
   while (n_verts > 0) {
     int cur = level & 1, nxt = cur ^ 1;
-    if (!bu && (int64_t)m_f * (int64_t)g->tune.alpha > m_u) bu = true;
-    else if (bu && (uint64_t)n_verts * g->tune.beta < n_live) bu = false;
+    // Beamer's switches, with one change: a bottom-up level scans every
+    // vertex, so a frontier below the switch-back size stays top-down even
+    // when few unexplored arcs remain (the last levels of a search had
+    // flipped to bottom-up and back)
+    const bool small = (uint64_t)n_verts * g->tune.beta < n_live;
+    if (!bu && (int64_t)m_f * (int64_t)g->tune.alpha > m_u && !small) bu = true;
+    else if (bu && small) bu = false;
     m_u -= (int64_t)m_f;
     fill<uint32_t>(bm[nxt], bmw, 0u, s);
     LevelArgs a{g->st, e, fast, fr[cur], fr[nxt], qbig, bm[cur], bm[nxt], dist, level + 1, cnt + nxt,
