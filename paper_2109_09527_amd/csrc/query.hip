@@ -34,7 +34,7 @@ namespace dg {
 
 constexpr uint32_t BIG_GRID = 2048;
 
-// --------------------------------------------------------------- fills
+// ---------------------------------------------------- counter publication
 
 // Layout of q.counters: four counter slots, the finished-workgroup count of
 // the running step (DONE_OFF), then (from STRIPE_OFF) the N_STRIPES count
@@ -138,6 +138,8 @@ __device__ inline void publish_if_last(const PubArgs& p) {
 }
 
 __global__ void k_publish(PubArgs p) { publish_wave(p); }
+
+// --------------------------------------------------------------- fills
 
 template <class T>
 __global__ void k_fill(T* p, uint64_t n, T v) {
