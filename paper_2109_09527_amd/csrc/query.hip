@@ -36,11 +36,14 @@ constexpr uint32_t BIG_GRID = 2048;
 
 // ---------------------------------------------------- counter publication
 
-// Layout of q.counters: four counter slots, the finished-workgroup count of
-// the running step (DONE_OFF), then (from STRIPE_OFF) the N_STRIPES count
+// Layout of q.counters: four counter slots, the finished-workgroup counts
+// of the running step (DONE_OFF: DONE_GROUPS group counts and the total,
+// each on its own 64-byte line), then (from STRIPE_OFF) the N_STRIPES count
 // stripes of each slot.
+constexpr uint32_t DONE_GROUPS = 16;
+constexpr uint32_t DONE_STRIDE = 16;   // words between two done counts
 constexpr size_t DONE_OFF = 192;
-constexpr size_t STRIPE_OFF = 256;
+constexpr size_t STRIPE_OFF = DONE_OFF + (DONE_GROUPS + 1) * DONE_STRIDE * 4;
 constexpr size_t COUNTERS_BYTES = STRIPE_OFF + 4 * N_STRIPES * sizeof(CountStripe);
 static_assert(4 * sizeof(QCounters) <= DONE_OFF, "counter slots overlap the done count");
 
@@ -59,7 +62,7 @@ struct HostCounters {
 struct PubArgs {
   const QCounters* cnt;
   const CountStripe* st;   // the stripes of all four slots, slot-major
-  uint32_t* done;          // zero between steps
+  uint32_t* done;          // the done counts, zero between steps
   HostCounters* h;
   int slot;
   uint32_t seq;
@@ -119,22 +122,38 @@ __device__ inline void publish_wave(const PubArgs& p) {
 // last one publishes.  The step's counters change only through device-scope
 // atomics, which are performed at the device's coherent level, so waiting
 // for completion (no cache write-back or invalidation, which an agent-scope
-// fence would cost every workgroup) orders them before the count.  No
-// workgroup waits for another, and the last clears the count for the next
-// step.  A separate publishing launch per step had cost its own dispatch on
-// every level's host round trip.
+// fence would cost every workgroup) orders them before the count.  A
+// workgroup counts itself in group b mod DONE_GROUPS; the one that
+// completes its group counts the group in the total, and the one that
+// completes the total is last (a grid of a thousand workgroups then puts
+// at most a few dozen atomics on any one word).  No workgroup waits for
+// another, and the last clears the counts for the next step.  A separate
+// publishing launch per step had cost its own dispatch on every level's
+// host round trip.
 __device__ inline void publish_if_last(const PubArgs& p) {
   if (!p.h) return;
   __shared__ uint32_t last;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);   // vmcnt, expcnt and lgkmcnt all zero
   __syncthreads();
-  if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(p.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    const uint32_t nwg = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t grp = b % DONE_GROUPS;
+    const uint32_t in_grp = (nwg - grp + DONE_GROUPS - 1) / DONE_GROUPS;   // workgroups of group grp
+    bool l = false;
+    if (__hip_atomic_fetch_add(&p.done[grp * DONE_STRIDE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u ==
+        in_grp) {
+      const uint32_t groups = min(nwg, DONE_GROUPS);
+      l = __hip_atomic_fetch_add(&p.done[DONE_GROUPS * DONE_STRIDE], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) + 1u == groups;
+    }
+    last = l;
+  }
   __syncthreads();
   if (!last || threadIdx.x >= 64) return;
   publish_wave(p);
-  if (threadIdx.x == 0) __hip_atomic_store(p.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x <= DONE_GROUPS)
+    __hip_atomic_store(&p.done[threadIdx.x * DONE_STRIDE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_publish(PubArgs p) { publish_wave(p); }
