@@ -417,7 +417,8 @@ constexpr uint32_t N_STRIPES = 16;
 struct alignas(128) CountStripe {
   unsigned long long m, arcs;
   uint32_t verts, far;
-  uint32_t pad[26];
+  uint32_t far_inv;   // DIST_INF - least far distance (0: none), raised by atomicMax
+  uint32_t pad[25];
 };
 
 // Register counters, summed per workgroup and added with one atomic per
@@ -1003,6 +1004,23 @@ __device__ inline void commit_far_min(int32_t mn, QCounters* c) {
   if (lane_id() == 0 && mn < DIST_INF) atomicMin(&c->far_min, mn);
 }
 
+// The far minimum of a workgroup (workgroup-uniform call, one barrier)
+// reaches its count stripe with one atomic: a split's waves had each put an
+// atomicMin on the one far_min word, about ten thousand at R-MAT 20.
+__device__ inline void commit_far_min_striped(int32_t mn, CountStripe* st) {
+  __shared__ int32_t wmin[Q_WAVES];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = min(mn, (int32_t)__shfl_xor(mn, o, 64));
+  if (lane_id() == 0) wmin[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = DIST_INF;
+#pragma unroll
+    for (int w = 0; w < Q_WAVES; w++) m = min(m, wmin[w]);
+    if (m < DIST_INF) atomicMax(&st[blockIdx.x % N_STRIPES].far_inv, (uint32_t)(DIST_INF - m));
+  }
+}
+
 __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, uint32_t nworkers, Shared& sh) {
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t gw = worker * Q_WAVES + wave, nw = nworkers * Q_WAVES;
@@ -1011,7 +1029,8 @@ __device__ __forceinline__ void split_step(const SplitArgs& a, uint32_t worker, 
   int32_t mn = DIST_INF;
   for (uint32_t base = gw * 64; base < a.st.V; base += nw * 64) split_block(a, base, qn, lc, mn);
   flush_front_wg(qn, a.fout, a.cnt_out, sh);
-  commit_far_min(mn, a.cnt_out);
+  if (a.stripes) commit_far_min_striped(mn, a.stripes);
+  else commit_far_min(mn, a.cnt_out);
   lc.commit(a.cnt_out, sh, a.stripes);
 }
 

@@ -90,18 +90,20 @@ __device__ inline T ld_coherent(const T* p) {
 __device__ inline void publish_wave(const PubArgs& p) {
   const uint32_t lane = threadIdx.x;
   unsigned long long m = 0, arcs = 0;
-  uint32_t verts = 0, far = 0;
+  uint32_t verts = 0, far = 0, far_inv = 0;
   if (lane < N_STRIPES) {
     const CountStripe* x = p.st + (size_t)p.slot * N_STRIPES + lane;
     m = ld_coherent(&x->m);
     arcs = ld_coherent(&x->arcs);
     verts = ld_coherent(&x->verts);
     far = ld_coherent(&x->far);
+    far_inv = ld_coherent(&x->far_inv);
   }
   m = wave_sum_u64(m);
   arcs = wave_sum_u64(arcs);
   verts = wave_sum_u32(verts);
   far = wave_sum_u32(far);
+  far_inv = wave_max_u32(far_inv);
   if (lane != 0) return;
   const QCounters* c = p.cnt + p.slot;
   QCounters r;
@@ -109,7 +111,7 @@ __device__ inline void publish_wave(const PubArgs& p) {
   r.n_verts = ld_coherent(&c->n_verts) + verts;
   r.n_far = ld_coherent(&c->n_far) + far;
   r.m_next = ld_coherent(&c->m_next) + m;
-  r.far_min = ld_coherent(&c->far_min);
+  r.far_min = min(ld_coherent(&c->far_min), (int32_t)(DIST_INF - far_inv));
   r.overflow = ld_coherent(&c->overflow);
   r.n_order = ld_coherent(&c->n_order);
   r.n_big = ld_coherent(&c->n_big);
@@ -232,6 +234,7 @@ __device__ inline void reset_other(QCounters* c, CountStripe* st) {
     x->arcs = 0;
     x->verts = 0;
     x->far = 0;
+    x->far_inv = 0;
   }
 }
 
