@@ -125,6 +125,26 @@ def test_random_batches_all_sizes(dg, seed, undirected):
     assert (nv, na) == o.counts()
 
 
+def test_batches_at_the_sort_path_boundary(dg):
+    """Batches of 131,072 and 131,073 ops (64 and 65 sort tiles of 2,048
+    keys): the first sort sums its offsets inside the scatter, the second
+    takes the separate scan; op results and queries equal the oracle's."""
+    gr = synth.rmat_graph(13, 8, 50, seed=9)
+    o = Oracle(gr.n, w_max=50)
+    g = dg.Graph(gr.n, w_max=50)
+    say("sort path boundary")
+    o.apply(synth.load_ops(gr))
+    g.apply(synth.load_ops(gr))
+    mix = [0.02, 0.01, 0.02, 0.45, 0.35, 0.15]
+    for b, size in enumerate([131_072, 131_073]):
+        ops = synth.random_ops(gr.n, size, 700 + b, w_max=50, mix=mix)
+        rc_o, r_o = o.apply(ops)
+        res, ep = g.apply(ops)
+        assert np.array_equal(res, r_o), ("batch", size, np.nonzero(res != r_o)[0][:10])
+        check_queries(g, o, ep, synth.out_degree_sources(gr, 2, synth.rng_for(9, b)), dg)
+    assert g.stats() == o.counts()
+
+
 def test_first_batches_of_fresh_graphs(dg):
     """A graph's first batch of host ops, smaller than the batch scratch's
     minimum size, is staged after that scratch is sized: fresh graphs
