@@ -300,6 +300,31 @@ def test_bulk_load_spans_many_tiles(dg):
             check_queries(g, o, g.epoch, src[:1], dg)
 
 
+def test_bfs_direction_thresholds_sweep(dg):
+    """BFS levels do not depend on the direction switches: all top-down
+    (every frontier counted small), bottom-up from the first large frontier,
+    and the defaults, on a directed and an undirected R-MAT graph, before and
+    after a batch of deletions, all equal the oracle's."""
+    for und in (False, True):
+        gr = synth.rmat_graph(12, 16, 20, seed=13, undirected=und)
+        o = Oracle(gr.n, undirected=und, w_max=20)
+        g = dg.Graph(gr.n, undirected=und, w_max=20)
+        o.apply(synth.load_ops(gr))
+        g.apply(synth.load_ops(gr))
+        src = [int(s) for s in synth.out_degree_sources(gr, 3, synth.rng_for(13, 1))]
+        wl = synth.update_batches(graph=gr, n_batches=1, n_edge_ops=4000, w_max=20, seed=13)
+        for phase in range(2):
+            if phase:
+                o.apply(wl.batches[0])
+                g.apply(wl.batches[0])
+            want = {s: o.bfs(s)[1] for s in src}
+            for alpha, beta in ((4, 24), (1000000, 1), (1, 1000000), (1000000, 1000000)):
+                say("bfs thresholds", und, phase, alpha, beta)
+                g.set_tuning(alpha=alpha, beta=beta)
+                for s in src:
+                    assert np.array_equal(g.bfs(s, g.epoch).cpu().numpy(), want[s]), (und, phase, alpha, beta, s)
+
+
 def test_sssp_bucket_width_sweep(dg):
     """Delta-stepping with bucket widths from 1 (Dijkstra-like, every arc
     heavy but weight-1 ones) through w_max (no heavy arcs) to far above it:
