@@ -881,12 +881,16 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
       nd[k] = __shfl(du_l, (int)s4.item[k], 64) + s4.w[k];
       lc.arcs += take[k] ? 1 : 0;
     }
-    int32_t old[4];
+    // The atomicMin's result is not waited for: an arc whose tentative
+    // distance beats the read value counts as an improvement even when a
+    // racing arc lowered the target further in between.  That arc pushes or
+    // flags the target too, so the push below at worst repeats one the
+    // target needs anyway (the stamp keeps one queue entry per pass) or
+    // raises a far flag that a later split finds already below its
+    // threshold.  Distances only fall, so every result stays exact.
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-      old[k] = DIST_INF;
-      if (take[k] && nd[k] < cur[k]) old[k] = atomicMin(&a.dist[s4.d[k]], nd[k]);
-    }
+    for (int k = 0; k < 4; k++)
+      if (take[k] && nd[k] < cur[k]) atomicMin(&a.dist[s4.d[k]], nd[k]);
     // an improvement below the threshold claims the target's place in the
     // next near frontier (once per pass); one at or above it raises the
     // target's far flag
@@ -895,7 +899,7 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
     for (int k = 0; k < 4; k++) {
       prev[k] = 0u;
       fl[k] = 0u;
-      if (take[k] && nd[k] < cur[k] && nd[k] < old[k]) {
+      if (take[k] && nd[k] < cur[k]) {
         if (nd[k] < a.thr) {
           prev[k] = atomicExch(&a.stamp[s4.d[k]], a.it1);
           fl[k] = a.infar[s4.d[k] >> 5] & far_bit(s4.d[k]);
@@ -908,7 +912,7 @@ __device__ __forceinline__ void relax_chunk(const RelaxArgs& a, uint32_t c, uint
     uint64_t yd[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      const bool imp = take[k] && nd[k] < cur[k] && nd[k] < old[k];
+      const bool imp = take[k] && nd[k] < cur[k];
       to_near[k] = imp && nd[k] < a.thr && prev[k] != a.it1;
       // settled in this bucket: no later split needs to move it again
       if (imp && nd[k] < a.thr && fl[k]) atomicAnd(&a.infar[s4.d[k] >> 5], ~far_bit(s4.d[k]));
