@@ -139,16 +139,18 @@ __device__ __forceinline__ void ms_relax_chunk(const MsPass& a, uint32_t c, uint
           lc.arcs += act[t] ? 1 : 0;          // relaxations (arc, query)
           lc.m += (j == 0 && vis) ? 1 : 0;    // arcs scanned, once for the half
         }
-        int32_t old[8];
+        // the atomicMin's result is not waited for: a tentative distance
+        // that beats the read value counts as an improvement even when a
+        // racing arc lowered the target further, which at worst sets a near
+        // or far bit that the racing arc sets too (bits, so no duplicate
+        // queue entry); distances only fall, so every result stays exact
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-          old[t] = DIST_INF;
-          if (act[t] && nd[t] < cur[t]) old[t] = atomicMin(&a.D[(uint64_t)dd[t] * MSQ + j], nd[t]);
-        }
+        for (int t = 0; t < 8; t++)
+          if (act[t] && nd[t] < cur[t]) atomicMin(&a.D[(uint64_t)dd[t] * MSQ + j], nd[t]);
         // lane s collects arc s's improved queries: near bits and far bits
 #pragma unroll
         for (int t = 0; t < 8; t++) {
-          const bool imp = act[t] && nd[t] < cur[t] && nd[t] < old[t];
+          const bool imp = act[t] && nd[t] < cur[t];
           const uint32_t nbits = half_ballot(imp && nd[t] < a.thr);
           const uint32_t fbits = half_ballot(imp && nd[t] >= a.thr);
           if (j == (uint32_t)(h + t)) {
